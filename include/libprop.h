@@ -1,0 +1,206 @@
+/*
+ * libprop -- scalar and vectorial light propagation with exact adjoints on
+ * one MI355X (gfx950) GPU.
+ *
+ * What is computed (paper: Methods, "Features and performance"; Software
+ * section).  The simulator propagates complex fields between planes by two
+ * methods, each scalar and vectorial: the FFT-based numerical integration of
+ * the Rayleigh-Sommerfeld (RS) diffraction integral, and the chirped
+ * z-transform (CZT), which samples an arbitrary output region.  A high-NA
+ * objective is evaluated with CZT methods.  Gradients with respect to the
+ * optical parameters (SLM phases, wave-plate retardance and angle) come from
+ * the adjoint of every linear operator (the paper uses reverse-mode
+ * autodiff, of which the adjoint method is a special case).
+ *
+ * Conventions (the paper states none; readings of this library):
+ *  - grid: row-major [ny][nx], x fastest; sample (i, j) sits at
+ *    (cx + (j - nx/2) dx, cy + (i - ny/2) dy) (integer division); metres.
+ *  - time dependence exp(-i w t): outgoing waves exp(+i k r), k = 2 pi / lambda.
+ *  - fields are interleaved complex: PROP_C64 = float (re, im) pairs
+ *    (torch.complex64), PROP_C128 = double pairs (torch.complex128); real
+ *    parameter arrays (phases, phase gradients) are float resp. double.
+ *  - batch: `batch` independent fields stored back to back; every field
+ *    pointer addresses batch * ny * nx contiguous elements.
+ *  - adjoints: each *_adjoint applies the exact adjoint A^H of its forward
+ *    operator A; with the gradient convention g = dL/dRe + i dL/dIm this
+ *    maps output gradients to input gradients.
+ *
+ * Memory: every field pointer is DEVICE memory owned by the caller (e.g. a
+ * torch tensor); the library neither retains nor frees it.  Inputs and
+ * outputs must not overlap (PROP_EALIAS).  All calls are asynchronous on
+ * `stream` (a hipStream_t; NULL = the legacy default stream).  Kernel
+ * spectra, chirp vectors and twiddle tables are computed on first use and
+ * cached per geometry (that first call synchronises its stream); workspace
+ * is cached per stream.  Calls on one stream are ordered; calls on
+ * different streams may run concurrently.
+ *
+ * Status: 0 on success, > 0 success with a warning, < 0 error (nothing was
+ * launched; outputs untouched).  Device-side numeric problems are not
+ * checked: NaN/Inf in the input propagate to the output.
+ */
+#ifndef LIBPROP_H
+#define LIBPROP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PROP_OK = 0,
+  PROP_WUNDERSAMPLED = 1, /* RS/VRS: exp(ikr) under-sampled at the largest offset (result still computed) */
+  PROP_ENULL = -1,        /* a required pointer is NULL */
+  PROP_ESHAPE = -2,       /* n < 1, batch < 0, or a transform length above 8192 */
+  PROP_EPARAM = -3,       /* bad dtype, lambda <= 0, z <= 0, pitch <= 0, NA not in (0,1), f <= 0, non-finite */
+  PROP_EALIAS = -4,       /* an output overlaps an input */
+  PROP_ENOMEM = -5,       /* device allocation failed */
+  PROP_EDEVICE = -6       /* a HIP call failed; prop_last_device_error() has the code */
+};
+
+typedef enum { PROP_C64 = 0, PROP_C128 = 1 } prop_dtype;
+
+/* Sampling grid: nx, ny samples with pitch dx, dy, centred at (cx, cy). */
+typedef struct {
+  int32_t nx, ny;
+  double dx, dy;
+  double cx, cy;
+} prop_grid;
+
+/* Aplanatic objective for the focusing mode of VCZT. */
+typedef struct {
+  double na; /* numerical aperture, 0 < na < 1 */
+  double f;  /* focal length (m); the pupil is the input grid, aperture radius f*na */
+} prop_lens;
+
+/* ---------------------------------------------------------------- RS --
+ * Scalar Rayleigh-Sommerfeld (first kind) propagation over distance z > 0
+ * onto the input grid (paper: Methods, RS propagation; Software section,
+ * "a general FFT-based light propagation algorithm"):
+ *   U(x_m, y_l) = dx dy sum_{i,j} U0(x_j, y_i) H(x_m - x_j, y_l - y_i; z),
+ *   H = (1/2pi)(z/r^2)(1/r - i k) exp(i k r),  r = sqrt(X^2 + Y^2 + z^2),
+ * evaluated exactly (up to rounding) as a zero-padded FFT convolution of
+ * length M >= 2n - 1 per axis (M = 2n for n = 2^a 3^b).  Requires
+ * M <= 8192, i.e. nx, ny <= 4096.  u_in/u_out: [batch][ny][nx].
+ * Returns PROP_WUNDERSAMPLED when, along some axis with 2 d > lambda,
+ * z < sqrt((2 L d / lambda)^2 - L^2) (L = n d), after launching.
+ */
+int rs_propagate(prop_dtype t, const void* u_in, void* u_out, const prop_grid* g, double wavelength,
+                 double z, int32_t batch, void* stream);
+/* g_in = A^H g_out for A = rs_propagate (same geometry and layout). */
+int rs_adjoint(prop_dtype t, const void* g_out, void* g_in, const prop_grid* g, double wavelength,
+               double z, int32_t batch, void* stream);
+
+/* --------------------------------------------------------------- CZT --
+ * Fresnel propagation over z > 0 onto an arbitrary output window `win`
+ * (position and pitch free; paper: Methods, "CZT ... allows arbitrary
+ * selection and sampling of the region of interest"):
+ *   U(X_p, Y_q) = K P(X_p, Y_q) sum_{i,j} U0(x_j, y_i) Q(x_j, y_i)
+ *                 exp(-i 2pi (X_p x_j + Y_q y_i) / (lambda z)),
+ *   K = exp(ikz) dx dy / (i lambda z), Q = exp(ik(x^2+y^2)/2z),
+ *   P = exp(ik(X^2+Y^2)/2z),
+ * evaluated by separable Bluestein transforms of length
+ * L >= n_in + n_out - 1 (2^a 3^b, L <= 8192 per axis).
+ * u_in: [batch][g_in.ny][g_in.nx]; u_out: [batch][win.ny][win.nx].
+ */
+int czt_propagate(prop_dtype t, const void* u_in, void* u_out, const prop_grid* g_in,
+                  const prop_grid* win, double wavelength, double z, int32_t batch, void* stream);
+/* g_in = A^H g_out for A = czt_propagate (window -> input grid). */
+int czt_adjoint(prop_dtype t, const void* g_out, void* g_in, const prop_grid* g_in_grid,
+                const prop_grid* win, double wavelength, double z, int32_t batch, void* stream);
+
+/* --------------------------------------------------------------- VRS --
+ * Vectorial RS (paper: Methods, vectorial RS): E_x, E_y propagate as scalar
+ * RS; E_z follows from div E = 0:
+ *   E_z = -dx dy sum [E_x0 (x - x')/z + E_y0 (y - y')/z] H.
+ * ex, ey, ox, oy, oz: [batch][ny][nx].  Same limits and warning as RS.
+ */
+int vrs_propagate(prop_dtype t, const void* ex, const void* ey, void* ox, void* oy, void* oz,
+                  const prop_grid* g, double wavelength, double z, int32_t batch, void* stream);
+/* (g_ex, g_ey) = A^H (g_x, g_y, g_z) for A = vrs_propagate. */
+int vrs_adjoint(prop_dtype t, const void* gx, const void* gy, const void* gz, void* gex, void* gey,
+                const prop_grid* g, double wavelength, double z, int32_t batch, void* stream);
+
+/* -------------------------------------------------------------- VCZT --
+ * Vectorial CZT (paper: Methods, vectorial CZT; high-NA objective "with CZT
+ * methods").  lens == NULL: free space over z > 0 with C the CZT operator,
+ *   E_x = C[E_x0], E_y = C[E_y0],
+ *   E_z = -(1/z) (X C[E_x0] + Y C[E_y0] - C[x E_x0 + y E_y0]).
+ * lens != NULL: focal field of an aplanatic objective (Richards-Wolf/Debye
+ * integral; z is ignored but must be finite):
+ *   E(X,Y) = (i k f e^{-ikf} / 2pi) (dx dy / f^2)
+ *            sum_pupil (E_inf / s_z) exp(i k (s_x X + s_y Y)),
+ *   s_perp = (x, y)/f, s_z = sqrt(1 - |s_perp|^2), aperture x^2+y^2 <= (f na)^2,
+ *   E_inf = sqrt(s_z) [(E0.n_phi) n_phi + (E0.n_rho) n_theta].
+ * ex, ey: [batch][g_in.ny][g_in.nx]; ox, oy, oz: [batch][win.ny][win.nx].
+ */
+int vczt_propagate(prop_dtype t, const void* ex, const void* ey, void* ox, void* oy, void* oz,
+                   const prop_grid* g_in, const prop_grid* win, double wavelength, double z,
+                   const prop_lens* lens, int32_t batch, void* stream);
+/* (g_ex, g_ey) = A^H (g_x, g_y, g_z) for A = vczt_propagate. */
+int vczt_adjoint(prop_dtype t, const void* gx, const void* gy, const void* gz, void* gex, void* gey,
+                 const prop_grid* g_in, const prop_grid* win, double wavelength, double z,
+                 const prop_lens* lens, int32_t batch, void* stream);
+
+/* ------------------------------------------------- sources and elements --
+ * Gaussian source (paper: Methods, light sources of any wavelength and
+ * power): out = amplitude exp(-r^2/w0^2) [exp(-i k r^2 / 2 lens_f) if
+ * lens_f > 0], r measured from the origin; phases in FP64.  out:
+ * [batch][ny][nx], every batch item identical.
+ */
+int prop_source_gaussian(prop_dtype t, void* out, const prop_grid* g, double w0, double amplitude,
+                         double lens_f, double wavelength, int32_t batch, void* stream);
+/* Radially polarised source: (E_x, E_y) = (x, y) exp(-r^2/w0^2) /
+ * (w0 exp(-1/2) / sqrt 2), so that max |E_perp| = 1. */
+int prop_source_radial(prop_dtype t, void* ex, void* ey, const prop_grid* g, double w0, int32_t batch,
+                       void* stream);
+/* SLM (paper: Methods, one free phase per pixel): u_out = u_in exp(i phase).
+ * phase: real [phase_batch][npix] with phase_batch = batch or 1 (shared). */
+int prop_modulate(prop_dtype t, const void* u_in, const void* phase, void* u_out, int64_t npix,
+                  int32_t batch, int32_t phase_batch, void* stream);
+/* SLM gradient: grad = Im(g_u conj(u)) (u = the modulated field), real
+ * [batch][npix]; accumulate != 0 adds to grad. */
+int prop_phase_grad(prop_dtype t, const void* g_u, const void* u, void* grad, int64_t npix,
+                    int32_t batch, int32_t accumulate, void* stream);
+/* Wave plate / variable retarder (paper: Methods, variable retarders with
+ * retardance eta and angle theta): (ox, oy) = J (ex, ey),
+ * J = R(-theta) diag(1, e^{i eta}) R(theta). */
+int prop_waveplate(prop_dtype t, const void* ex, const void* ey, void* ox, void* oy, double eta,
+                   double theta, int64_t npix, int32_t batch, void* stream);
+/* Adjoint: (g_ex, g_ey) = J^H (g_x, g_y); dparams (device double
+ * [batch][2]) receives dL/deta, dL/dtheta per batch item (deterministic
+ * fixed-order reduction). ex, ey: the wave plate's inputs. */
+int prop_waveplate_adjoint(prop_dtype t, const void* gx, const void* gy, const void* ex,
+                           const void* ey, void* gex, void* gey, double eta, double theta,
+                           double* dparams, int64_t npix, int32_t batch, void* stream);
+
+/* -------------------------------------------------------------- losses --
+ * Detector loss on window `win`: I = |E_x|^2 + |E_y|^2 + |E_z|^2,
+ * sigma^2 = sum I |X - Xbar|^2 / P about the intensity centroid,
+ * F_z = sum |E_z|^2 / P, loss = sigma^2 / lambda^2 + w_fz F_z.
+ * ez may be NULL (two components).  result: device double [batch][8] =
+ * (loss, sigma^2, F_z, P, Xbar - cx, Ybar - cy, 0, 0).  If gx and gy are
+ * non-NULL the gradient seeds g_c = 2 E_c dL/dI_c are written (gz too when
+ * ez and gz are non-NULL).  Reductions use FP64 in a fixed order.
+ */
+int prop_spot_loss(prop_dtype t, const void* ex, const void* ey, const void* ez, const prop_grid* win,
+                   double wavelength, double w_fz, double* result, void* gx, void* gy, void* gz,
+                   int32_t batch, void* stream);
+
+/* ------------------------------------------------------------- utility -- */
+/* Host-only sampling check of RS/VRS: PROP_OK or PROP_WUNDERSAMPLED. */
+int prop_sampling_check(const prop_grid* g, double wavelength, double z);
+/* Smallest supported transform length (2^a 3^b) >= n, or -1 above 8192. */
+int32_t prop_fft_length(int32_t n);
+/* Free cached spectra, chirps, twiddles and workspaces (synchronises the device). */
+void prop_cache_clear(void);
+/* Text for a status code. */
+const char* prop_status_string(int status);
+/* hipError_t of the last PROP_EDEVICE on this thread (0 if none). */
+int prop_last_device_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBPROP_H */

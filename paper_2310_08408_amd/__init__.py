@@ -1,0 +1,305 @@
+"""libprop Python binding: RS / CZT / VRS / VCZT light propagation and exact
+adjoints on one MI355X, behind the C ABI of include/libprop.h.
+
+Every function here marshals torch tensors (device memory, current stream)
+into one libprop call; all arithmetic runs in the library's HIP kernels.
+Fields are complex64 or complex128 CUDA(HIP) tensors shaped [..., ny, nx];
+leading dimensions form the batch.  Real parameter tensors (phases) use the
+matching real dtype.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import torch
+
+from . import _lib
+from ._lib import PropError, PropWarning  # noqa: F401
+
+__all__ = [
+    "rs_propagate", "rs_adjoint", "czt_propagate", "czt_adjoint", "vrs_propagate", "vrs_adjoint",
+    "vczt_propagate", "vczt_adjoint", "prop_source_gaussian", "prop_source_radial", "prop_modulate",
+    "prop_phase_grad", "prop_waveplate", "prop_waveplate_adjoint", "prop_spot_loss", "prop_sampling_check",
+    "prop_fft_length", "prop_cache_clear", "PropError", "PropWarning", "library",
+]
+
+
+def library():
+    return _lib.load()
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.complex64:
+        return _lib.PROP_C64
+    if t.dtype == torch.complex128:
+        return _lib.PROP_C128
+    raise TypeError(f"expected complex64/complex128, got {t.dtype}")
+
+
+def _real_dtype(t: torch.Tensor):
+    return torch.float32 if t.dtype == torch.complex64 else torch.float64
+
+
+def _dev(t: torch.Tensor):
+    if not t.is_cuda:
+        raise ValueError("libprop operates on GPU tensors")
+    if not t.is_contiguous():
+        raise ValueError("libprop needs contiguous tensors")
+    return t
+
+
+def _stream(t: torch.Tensor):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _batch(t: torch.Tensor, g) -> int:
+    n = int(g.nx) * int(g.ny)
+    if t.dim() < 2 or t.shape[-1] != int(g.nx) or t.shape[-2] != int(g.ny):
+        raise ValueError(f"tensor shape {tuple(t.shape)} does not end in (ny, nx) = ({g.ny}, {g.nx})")
+    return t.numel() // n
+
+
+def _like(t: torch.Tensor, g, out):
+    shape = tuple(t.shape[:-2]) + (int(g.ny), int(g.nx))
+    if out is None:
+        return torch.empty(shape, dtype=t.dtype, device=t.device)
+    _dev(out)
+    if tuple(out.shape) != shape or out.dtype != t.dtype:
+        raise ValueError("out has the wrong shape or dtype")
+    return out
+
+
+# ------------------------------------------------------------------ RS / CZT --
+
+def rs_propagate(u, grid, wavelength, z, out=None):
+    """Scalar RS over z onto the input grid (see include/libprop.h)."""
+    lib = library()
+    _dev(u)
+    out = _like(u, grid, out)
+    with torch.cuda.device(u.device):
+        st = lib.rs_propagate(_dtype_code(u), _ptr(u), _ptr(out), ctypes.byref(_lib.grid(grid)), float(wavelength),
+                              float(z), _batch(u, grid), _stream(u))
+    _lib.check("rs_propagate", st)
+    return out
+
+
+def rs_adjoint(g_out, grid, wavelength, z, out=None):
+    lib = library()
+    _dev(g_out)
+    out = _like(g_out, grid, out)
+    with torch.cuda.device(g_out.device):
+        st = lib.rs_adjoint(_dtype_code(g_out), _ptr(g_out), _ptr(out), ctypes.byref(_lib.grid(grid)),
+                            float(wavelength), float(z), _batch(g_out, grid), _stream(g_out))
+    _lib.check("rs_adjoint", st)
+    return out
+
+
+def czt_propagate(u, grid_in, window, wavelength, z, out=None):
+    """Fresnel/CZT propagation over z onto ``window``."""
+    lib = library()
+    _dev(u)
+    b = _batch(u, grid_in)
+    out = _like(u, window, out)
+    with torch.cuda.device(u.device):
+        st = lib.czt_propagate(_dtype_code(u), _ptr(u), _ptr(out), ctypes.byref(_lib.grid(grid_in)),
+                               ctypes.byref(_lib.grid(window)), float(wavelength), float(z), b, _stream(u))
+    _lib.check("czt_propagate", st)
+    return out
+
+
+def czt_adjoint(g_out, grid_in, window, wavelength, z, out=None):
+    lib = library()
+    _dev(g_out)
+    b = _batch(g_out, window)
+    out = _like(g_out, grid_in, out)
+    with torch.cuda.device(g_out.device):
+        st = lib.czt_adjoint(_dtype_code(g_out), _ptr(g_out), _ptr(out), ctypes.byref(_lib.grid(grid_in)),
+                             ctypes.byref(_lib.grid(window)), float(wavelength), float(z), b, _stream(g_out))
+    _lib.check("czt_adjoint", st)
+    return out
+
+
+# --------------------------------------------------------------- VRS / VCZT --
+
+def vrs_propagate(ex, ey, grid, wavelength, z):
+    lib = library()
+    _dev(ex), _dev(ey)
+    b = _batch(ex, grid)
+    ox, oy, oz = (torch.empty_like(ex) for _ in range(3))
+    with torch.cuda.device(ex.device):
+        st = lib.vrs_propagate(_dtype_code(ex), _ptr(ex), _ptr(ey), _ptr(ox), _ptr(oy), _ptr(oz),
+                               ctypes.byref(_lib.grid(grid)), float(wavelength), float(z), b, _stream(ex))
+    _lib.check("vrs_propagate", st)
+    return ox, oy, oz
+
+
+def vrs_adjoint(gx, gy, gz, grid, wavelength, z):
+    lib = library()
+    for t in (gx, gy, gz):
+        _dev(t)
+    b = _batch(gx, grid)
+    gex, gey = torch.empty_like(gx), torch.empty_like(gx)
+    with torch.cuda.device(gx.device):
+        st = lib.vrs_adjoint(_dtype_code(gx), _ptr(gx), _ptr(gy), _ptr(gz), _ptr(gex), _ptr(gey),
+                             ctypes.byref(_lib.grid(grid)), float(wavelength), float(z), b, _stream(gx))
+    _lib.check("vrs_adjoint", st)
+    return gex, gey
+
+
+def _lens(lens):
+    if lens is None:
+        return None
+    na, f = (lens.na, lens.f) if hasattr(lens, "na") else lens
+    return ctypes.byref(_lib.prop_lens(float(na), float(f)))
+
+
+def vczt_propagate(ex, ey, grid_in, window, wavelength, z=0.0, lens=None):
+    """Vectorial CZT; ``lens=(na, f)`` selects the focusing (objective) mode."""
+    lib = library()
+    _dev(ex), _dev(ey)
+    b = _batch(ex, grid_in)
+    ox, oy, oz = (_like(ex, window, None) for _ in range(3))
+    with torch.cuda.device(ex.device):
+        st = lib.vczt_propagate(_dtype_code(ex), _ptr(ex), _ptr(ey), _ptr(ox), _ptr(oy), _ptr(oz),
+                                ctypes.byref(_lib.grid(grid_in)), ctypes.byref(_lib.grid(window)), float(wavelength),
+                                float(z), _lens(lens), b, _stream(ex))
+    _lib.check("vczt_propagate", st)
+    return ox, oy, oz
+
+
+def vczt_adjoint(gx, gy, gz, grid_in, window, wavelength, z=0.0, lens=None):
+    lib = library()
+    for t in (gx, gy, gz):
+        _dev(t)
+    b = _batch(gx, window)
+    gex, gey = _like(gx, grid_in, None), _like(gx, grid_in, None)
+    with torch.cuda.device(gx.device):
+        st = lib.vczt_adjoint(_dtype_code(gx), _ptr(gx), _ptr(gy), _ptr(gz), _ptr(gex), _ptr(gey),
+                              ctypes.byref(_lib.grid(grid_in)), ctypes.byref(_lib.grid(window)), float(wavelength),
+                              float(z), _lens(lens), b, _stream(gx))
+    _lib.check("vczt_adjoint", st)
+    return gex, gey
+
+
+# ---------------------------------------------------------- sources, elements --
+
+def prop_source_gaussian(grid, w0, wavelength, amplitude=1.0, lens_f=0.0, batch=1, dtype=torch.complex64,
+                         device="cuda"):
+    lib = library()
+    out = torch.empty((batch, int(grid.ny), int(grid.nx)), dtype=dtype, device=device)
+    with torch.cuda.device(out.device):
+        st = lib.prop_source_gaussian(_dtype_code(out), _ptr(out), ctypes.byref(_lib.grid(grid)), float(w0),
+                                      float(amplitude), float(lens_f), float(wavelength), batch, _stream(out))
+    _lib.check("prop_source_gaussian", st)
+    return out
+
+
+def prop_source_radial(grid, w0, batch=1, dtype=torch.complex64, device="cuda"):
+    lib = library()
+    ex = torch.empty((batch, int(grid.ny), int(grid.nx)), dtype=dtype, device=device)
+    ey = torch.empty_like(ex)
+    with torch.cuda.device(ex.device):
+        st = lib.prop_source_radial(_dtype_code(ex), _ptr(ex), _ptr(ey), ctypes.byref(_lib.grid(grid)), float(w0),
+                                    batch, _stream(ex))
+    _lib.check("prop_source_radial", st)
+    return ex, ey
+
+
+def prop_modulate(u, phase, out=None):
+    """u * exp(i phase); phase [..., ny, nx] (real) broadcast over the batch if it has one item."""
+    lib = library()
+    _dev(u), _dev(phase)
+    if phase.dtype != _real_dtype(u):
+        raise TypeError("phase dtype must match the field precision")
+    npix = u.shape[-1] * u.shape[-2]
+    batch = u.numel() // npix
+    pb = phase.numel() // npix
+    out = torch.empty_like(u) if out is None else out
+    with torch.cuda.device(u.device):
+        st = lib.prop_modulate(_dtype_code(u), _ptr(u), _ptr(phase), _ptr(out), npix, batch, pb, _stream(u))
+    _lib.check("prop_modulate", st)
+    return out
+
+
+def prop_phase_grad(g_u, u, grad=None, accumulate=False):
+    """Im(g_u conj(u)) (real, same shape as u)."""
+    lib = library()
+    _dev(g_u), _dev(u)
+    npix = u.shape[-1] * u.shape[-2]
+    batch = u.numel() // npix
+    if grad is None:
+        grad = torch.empty(u.shape, dtype=_real_dtype(u), device=u.device)
+    with torch.cuda.device(u.device):
+        st = lib.prop_phase_grad(_dtype_code(u), _ptr(g_u), _ptr(u), _ptr(grad), npix, batch, int(accumulate),
+                                 _stream(u))
+    _lib.check("prop_phase_grad", st)
+    return grad
+
+
+def prop_waveplate(ex, ey, eta, theta):
+    lib = library()
+    _dev(ex), _dev(ey)
+    npix = ex.shape[-1] * ex.shape[-2]
+    batch = ex.numel() // npix
+    ox, oy = torch.empty_like(ex), torch.empty_like(ey)
+    with torch.cuda.device(ex.device):
+        st = lib.prop_waveplate(_dtype_code(ex), _ptr(ex), _ptr(ey), _ptr(ox), _ptr(oy), float(eta), float(theta),
+                                npix, batch, _stream(ex))
+    _lib.check("prop_waveplate", st)
+    return ox, oy
+
+
+def prop_waveplate_adjoint(gx, gy, ex, ey, eta, theta):
+    """Returns (g_ex, g_ey, dparams[batch, 2] = (dL/deta, dL/dtheta))."""
+    lib = library()
+    for t in (gx, gy, ex, ey):
+        _dev(t)
+    npix = ex.shape[-1] * ex.shape[-2]
+    batch = ex.numel() // npix
+    gex, gey = torch.empty_like(gx), torch.empty_like(gy)
+    dp = torch.empty((batch, 2), dtype=torch.float64, device=ex.device)
+    with torch.cuda.device(ex.device):
+        st = lib.prop_waveplate_adjoint(_dtype_code(ex), _ptr(gx), _ptr(gy), _ptr(ex), _ptr(ey), _ptr(gex),
+                                        _ptr(gey), float(eta), float(theta), _ptr(dp), npix, batch, _stream(ex))
+    _lib.check("prop_waveplate_adjoint", st)
+    return gex, gey, dp
+
+
+def prop_spot_loss(ex, ey, ez, window, wavelength, w_fz=0.0, seeds=True):
+    """Returns (result[batch, 8] float64, (g_x, g_y, g_z) or None).
+
+    result columns: loss, sigma^2, F_z, P, Xbar - cx, Ybar - cy, 0, 0.
+    """
+    lib = library()
+    _dev(ex), _dev(ey)
+    if ez is not None:
+        _dev(ez)
+    b = _batch(ex, window)
+    res = torch.empty((b, 8), dtype=torch.float64, device=ex.device)
+    gx = gy = gz = None
+    if seeds:
+        gx, gy = torch.empty_like(ex), torch.empty_like(ey)
+        gz = torch.empty_like(ez) if ez is not None else None
+    with torch.cuda.device(ex.device):
+        st = lib.prop_spot_loss(_dtype_code(ex), _ptr(ex), _ptr(ey), _ptr(ez), ctypes.byref(_lib.grid(window)),
+                                float(wavelength), float(w_fz), _ptr(res), _ptr(gx), _ptr(gy), _ptr(gz), b,
+                                _stream(ex))
+    _lib.check("prop_spot_loss", st)
+    return res, ((gx, gy, gz) if seeds else None)
+
+
+def prop_sampling_check(grid, wavelength, z) -> int:
+    return library().prop_sampling_check(ctypes.byref(_lib.grid(grid)), float(wavelength), float(z))
+
+
+def prop_fft_length(n: int) -> int:
+    return library().prop_fft_length(int(n))
+
+
+def prop_cache_clear() -> None:
+    library().prop_cache_clear()

@@ -1,0 +1,131 @@
+"""torch.autograd.Function wrappers: forward calls a libprop propagator,
+backward calls its hand-written adjoint (the paper obtains these gradients
+by reverse-mode autodiff; for a linear operator A the backward is A^H).
+
+With torch's complex gradient convention (g = dL/dRe + i dL/dIm) the
+gradient of an input x of y = A x is A^H g_y; for U = V exp(i phi) it is
+dL/dphi = Im(g_U conj(U)) and g_V = g_U exp(-i phi).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import (czt_adjoint, czt_propagate, prop_modulate, prop_phase_grad, prop_spot_loss, prop_waveplate,
+               prop_waveplate_adjoint, rs_adjoint, rs_propagate, vczt_adjoint, vczt_propagate, vrs_adjoint,
+               vrs_propagate)
+
+
+class RS(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, u, grid, wavelength, z):
+        ctx.args = (grid, wavelength, z)
+        return rs_propagate(u.contiguous(), grid, wavelength, z)
+
+    @staticmethod
+    def backward(ctx, g):
+        grid, wl, z = ctx.args
+        return rs_adjoint(g.contiguous(), grid, wl, z), None, None, None
+
+
+class CZT(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, u, grid_in, window, wavelength, z):
+        ctx.args = (grid_in, window, wavelength, z)
+        return czt_propagate(u.contiguous(), grid_in, window, wavelength, z)
+
+    @staticmethod
+    def backward(ctx, g):
+        gi, win, wl, z = ctx.args
+        return czt_adjoint(g.contiguous(), gi, win, wl, z), None, None, None, None
+
+
+class VRS(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, ex, ey, grid, wavelength, z):
+        ctx.args = (grid, wavelength, z)
+        return vrs_propagate(ex.contiguous(), ey.contiguous(), grid, wavelength, z)
+
+    @staticmethod
+    def backward(ctx, gx, gy, gz):
+        grid, wl, z = ctx.args
+        ref = next(t for t in (gx, gy, gz) if t is not None)
+        gx, gy, gz = (torch.zeros_like(ref) if t is None else t.contiguous() for t in (gx, gy, gz))
+        gex, gey = vrs_adjoint(gx, gy, gz, grid, wl, z)
+        return gex, gey, None, None, None
+
+
+class VCZT(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, ex, ey, grid_in, window, wavelength, z, lens):
+        ctx.args = (grid_in, window, wavelength, z, lens)
+        return vczt_propagate(ex.contiguous(), ey.contiguous(), grid_in, window, wavelength, z, lens)
+
+    @staticmethod
+    def backward(ctx, gx, gy, gz):
+        gi, win, wl, z, lens = ctx.args
+        ref = next(t for t in (gx, gy, gz) if t is not None)
+        gx, gy, gz = (torch.zeros_like(ref) if t is None else t.contiguous() for t in (gx, gy, gz))
+        gex, gey = vczt_adjoint(gx, gy, gz, gi, win, wl, z, lens)
+        return gex, gey, None, None, None, None, None
+
+
+class Modulate(torch.autograd.Function):
+    """SLM: U = V exp(i phi) (phi real, broadcast over the batch if shared)."""
+
+    @staticmethod
+    def forward(ctx, v, phase):
+        v, phase = v.contiguous(), phase.contiguous()
+        u = prop_modulate(v, phase)
+        ctx.save_for_backward(u, phase)
+        ctx.shared = phase.numel() != v.numel()
+        return u
+
+    @staticmethod
+    def backward(ctx, g):
+        u, phase = ctx.saved_tensors
+        g = g.contiguous()
+        g_v = prop_modulate(g, -phase) if ctx.needs_input_grad[0] else None
+        g_phi = None
+        if ctx.needs_input_grad[1]:
+            g_phi = prop_phase_grad(g, u)
+            if ctx.shared:
+                g_phi = g_phi.reshape((-1,) + tuple(phase.shape[-2:])).sum(0).reshape(phase.shape)
+        return g_v, g_phi
+
+
+class WavePlate(torch.autograd.Function):
+    """Jones retarder J(eta, theta) on (E_x, E_y); eta, theta are 0-d tensors."""
+
+    @staticmethod
+    def forward(ctx, ex, ey, eta, theta):
+        ex, ey = ex.contiguous(), ey.contiguous()
+        ctx.save_for_backward(ex, ey, eta, theta)
+        return prop_waveplate(ex, ey, float(eta), float(theta))
+
+    @staticmethod
+    def backward(ctx, gx, gy):
+        ex, ey, eta, theta = ctx.saved_tensors
+        gx = torch.zeros_like(ex) if gx is None else gx.contiguous()
+        gy = torch.zeros_like(ey) if gy is None else gy.contiguous()
+        gex, gey, dp = prop_waveplate_adjoint(gx, gy, ex, ey, float(eta), float(theta))
+        tot = dp.sum(0)
+        return gex, gey, tot[0].to(eta.dtype).reshape(eta.shape), tot[1].to(theta.dtype).reshape(theta.shape)
+
+
+class SpotLoss(torch.autograd.Function):
+    """Per-field loss sigma^2/lambda^2 + w_fz F_z on ``window`` (shape [batch])."""
+
+    @staticmethod
+    def forward(ctx, ex, ey, ez, window, wavelength, w_fz):
+        res, seeds = prop_spot_loss(ex.contiguous(), ey.contiguous(), None if ez is None else ez.contiguous(),
+                                    window, wavelength, w_fz, seeds=True)
+        ctx.seeds = seeds
+        ctx.has_ez = ez is not None
+        return res[:, 0].clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        gx, gy, gz = ctx.seeds
+        shape = (-1,) + (1,) * (gx.dim() - 1)
+        w = g.to(gx.real.dtype).reshape(shape)
+        return gx * w, gy * w, (gz * w if ctx.has_ez else None), None, None, None

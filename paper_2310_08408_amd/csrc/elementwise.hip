@@ -1,0 +1,600 @@
+// Setup generators (RS kernel spectra, chirp vectors) in FP64 and the
+// elementwise / reduction kernels of libprop (sources, SLM phase and its
+// gradient, Jones matrices, the focusing pupil map, detector losses).
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <algorithm>
+
+#include "kernels.hpp"
+
+namespace lp {
+
+template <typename T> __device__ __forceinline__ cx<T> zero() { return mk<T>(T(0), T(0)); }
+
+// --------------------------------------------------- FP64 generators --
+static constexpr double kTwoPi = 6.283185307179586476925286766559;
+static constexpr double kPi = 3.1415926535897932384626433832795;
+
+__global__ void k_rs_kernel_wrapped(cx<double>* out, int Mx, int My, int nx, int ny, double dx, double dy,
+                                    double k, double z, int kind) {
+  const int64_t total = (int64_t)Mx * My;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(t / Mx), bcol = (int)(t - (int64_t)a * Mx);
+    int oy, ox;
+    bool ok = true;
+    if (a <= ny - 1) oy = a; else if (a >= My - (ny - 1)) oy = a - My; else { oy = 0; ok = false; }
+    if (bcol <= nx - 1) ox = bcol; else if (bcol >= Mx - (nx - 1)) ox = bcol - Mx; else { ox = 0; ok = false; }
+    cx<double> h = mk<double>(0.0, 0.0);
+    if (ok) {
+      const double X = ox * dx, Y = oy * dy;
+      const double r2 = X * X + Y * Y + z * z;
+      const double r = sqrt(r2);
+      double sn, cs;
+      sincos(k * r, &sn, &cs);
+      const double pre = z / (kTwoPi * r2);
+      // (1/r - i k) e^{ikr}
+      double re = (cs / r + k * sn) * pre;
+      double im = (sn / r - k * cs) * pre;
+      if (kind == 1) { re *= X / z; im *= X / z; }
+      if (kind == 2) { re *= Y / z; im *= Y / z; }
+      h = mk<double>(re, im);
+    }
+    out[t] = h;
+  }
+}
+
+hipError_t launch_rs_kernel_wrapped(cx<double>* out, int Mx, int My, int nx, int ny, double dx, double dy,
+                                    double k, double z, int kind, hipStream_t s) {
+  const int64_t total = (int64_t)Mx * My;
+  const int blocks = (int)std::min<int64_t>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_rs_kernel_wrapped, dim3(blocks), dim3(256), 0, s, out, Mx, My, nx, ny, dx, dy, k, z, kind);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_extract_quarter(const cx<double>* full, cx<T>* q, int Mx, int My) {
+  const int qw = Mx / 2 + 1, qh = My / 2 + 1;
+  const int64_t total = (int64_t)qw * qh;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int a = (int)(t / qw), bcol = (int)(t - (int64_t)a * qw);
+    const cx<double> v = full[(int64_t)a * Mx + bcol];
+    q[t] = mk<T>(T(v.x), T(v.y));
+  }
+}
+
+template <typename T>
+hipError_t launch_extract_quarter(const cx<double>* full, cx<T>* q, int Mx, int My, hipStream_t s) {
+  const int64_t total = (int64_t)(Mx / 2 + 1) * (My / 2 + 1);
+  const int blocks = (int)std::min<int64_t>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL((k_extract_quarter<T>), dim3(blocks), dim3(256), 0, s, full, q, Mx, My);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_zoom_vectors(ZoomSpec zs, cx<T>* pre, cx<T>* post, cx<double>* chirp) {
+  const double alpha = zs.beta * zs.dx * zs.dX;
+  const double sg = (double)zs.sigma;
+  const int top = max(max(zs.n_in, zs.n_out), zs.L);
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < top; t += gridDim.x * blockDim.x) {
+    if (t < zs.n_in) {
+      const double j = (double)t;
+      const double xj = zs.x0 + j * zs.dx;
+      const double ph = sg * kTwoPi * zs.beta * zs.X0 * zs.dx * j + sg * kPi * alpha * (j * j) + zs.qin * xj * xj;
+      double sn, cs;
+      sincos(ph, &sn, &cs);
+      pre[t] = mk<T>(T(cs), T(sn));
+    }
+    if (t < zs.n_out) {
+      const double p = (double)t;
+      const double Xp = zs.X0 + p * zs.dX;
+      const double ph = sg * kTwoPi * zs.beta * (zs.X0 * zs.x0 + zs.x0 * zs.dX * p) + sg * kPi * alpha * (p * p) +
+                        zs.qout * Xp * Xp;
+      double sn, cs;
+      sincos(ph, &sn, &cs);
+      const double kr = zs.Kre / zs.L, ki = zs.Kim / zs.L;
+      post[t] = mk<T>(T(kr * cs - ki * sn), T(kr * sn + ki * cs));
+    }
+    if (t < zs.L) {
+      double m = 0.0;
+      bool ok = true;
+      if (t <= zs.n_out - 1) m = (double)t;
+      else if (t >= zs.L - (zs.n_in - 1)) m = (double)(t - zs.L);
+      else ok = false;
+      cx<double> v = mk<double>(0.0, 0.0);
+      if (ok) {
+        double sn, cs;
+        sincos(-sg * kPi * alpha * (m * m), &sn, &cs);
+        v = mk<double>(cs, sn);
+      }
+      chirp[t] = v;
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_zoom_vectors(const ZoomSpec& zs, cx<T>* pre, cx<T>* post, cx<double>* chirp, hipStream_t s) {
+  const int top = std::max(std::max(zs.n_in, zs.n_out), zs.L);
+  hipLaunchKernelGGL((k_zoom_vectors<T>), dim3((top + 255) / 256), dim3(256), 0, s, zs, pre, post, chirp);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_convert(const cx<double>* in, cx<T>* out, int64_t n) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    out[t] = mk<T>(T(in[t].x), T(in[t].y));
+}
+
+template <typename T>
+hipError_t launch_convert(const cx<double>* in, cx<T>* out, int64_t n, hipStream_t s) {
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL((k_convert<T>), dim3(std::max(blocks, 1)), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- elementwise --
+static int ew_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
+
+template <typename T> __device__ __forceinline__ void sc(T x, T* s, T* c);
+template <> __device__ __forceinline__ void sc<float>(float x, float* s, float* c) { sincosf(x, s, c); }
+template <> __device__ __forceinline__ void sc<double>(double x, double* s, double* c) { sincos(x, s, c); }
+
+template <typename T>
+__global__ void k_modulate(const cx<T>* in, const T* phase, cx<T>* out, int64_t npix, int batch, int64_t pbs) {
+  const int64_t total = npix * batch;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = t / npix, i = t - b * npix;
+    T sn, cs;
+    sc<T>(phase[b * pbs + i], &sn, &cs);
+    out[t] = cmul(in[t], mk<T>(cs, sn));
+  }
+}
+template <typename T>
+hipError_t launch_modulate(const cx<T>* in, const T* phase, cx<T>* out, int64_t npix, int batch, int64_t pbs,
+                           hipStream_t s) {
+  hipLaunchKernelGGL((k_modulate<T>), dim3(ew_blocks(npix * batch)), dim3(256), 0, s, in, phase, out, npix, batch, pbs);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_phase_grad(const cx<T>* g, const cx<T>* u, T* grad, int64_t total, int accumulate) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const cx<T> a = g[t], v = u[t];
+    const T val = a.y * v.x - a.x * v.y;
+    grad[t] = accumulate ? grad[t] + val : val;
+  }
+}
+template <typename T>
+hipError_t launch_phase_grad(const cx<T>* g, const cx<T>* u, T* grad, int64_t npix, int batch, int accumulate,
+                             hipStream_t s) {
+  hipLaunchKernelGGL((k_phase_grad<T>), dim3(ew_blocks(npix * batch)), dim3(256), 0, s, g, u, grad, npix * batch,
+                     accumulate);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_source_gaussian(cx<T>* out, int nx, int ny, double dx, double dy, double cx0, double cy0,
+                                  double w0, double amp, double f, double k, int batch) {
+  const int64_t npix = (int64_t)nx * ny, total = npix * batch;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = t % npix;
+    const int row = (int)(i / nx), col = (int)(i - (int64_t)row * nx);
+    const double x = cx0 + (double)(col - nx / 2) * dx, y = cy0 + (double)(row - ny / 2) * dy;
+    const double r2 = x * x + y * y;
+    const double a = amp * exp(-r2 / (w0 * w0));
+    double re = a, im = 0.0;
+    if (f > 0.0) {
+      double sn, cs;
+      sincos(-k * r2 / (2.0 * f), &sn, &cs);
+      re = a * cs;
+      im = a * sn;
+    }
+    out[t] = mk<T>(T(re), T(im));
+  }
+}
+template <typename T>
+hipError_t launch_source_gaussian(cx<T>* out, int nx, int ny, double dx, double dy, double cx0, double cy0,
+                                  double w0, double amp, double f, double k, int batch, hipStream_t s) {
+  hipLaunchKernelGGL((k_source_gaussian<T>), dim3(ew_blocks((int64_t)nx * ny * batch)), dim3(256), 0, s, out, nx,
+                     ny, dx, dy, cx0, cy0, w0, amp, f, k, batch);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_source_radial(cx<T>* ex, cx<T>* ey, int nx, int ny, double dx, double dy, double cx0,
+                                double cy0, double w0, int batch) {
+  const int64_t npix = (int64_t)nx * ny, total = npix * batch;
+  const double norm = 1.0 / (w0 * exp(-0.5) / sqrt(2.0));
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = t % npix;
+    const int row = (int)(i / nx), col = (int)(i - (int64_t)row * nx);
+    const double x = cx0 + (double)(col - nx / 2) * dx, y = cy0 + (double)(row - ny / 2) * dy;
+    const double g = exp(-(x * x + y * y) / (w0 * w0)) * norm;
+    ex[t] = mk<T>(T(x * g), T(0));
+    ey[t] = mk<T>(T(y * g), T(0));
+  }
+}
+template <typename T>
+hipError_t launch_source_radial(cx<T>* ex, cx<T>* ey, int nx, int ny, double dx, double dy, double cx0,
+                                double cy0, double w0, int batch, hipStream_t s) {
+  hipLaunchKernelGGL((k_source_radial<T>), dim3(ew_blocks((int64_t)nx * ny * batch)), dim3(256), 0, s, ex, ey, nx,
+                     ny, dx, dy, cx0, cy0, w0, batch);
+  return hipGetLastError();
+}
+
+struct J4 { double v[8]; };
+
+template <typename T>
+__global__ void k_jones(const cx<T>* ex, const cx<T>* ey, cx<T>* ox, cx<T>* oy, J4 J, int64_t total) {
+  const cx<T> a = mk<T>(T(J.v[0]), T(J.v[1])), b = mk<T>(T(J.v[2]), T(J.v[3]));
+  const cx<T> c = mk<T>(T(J.v[4]), T(J.v[5])), d = mk<T>(T(J.v[6]), T(J.v[7]));
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const cx<T> x = ex[t], y = ey[t];
+    ox[t] = cadd(cmul(a, x), cmul(b, y));
+    oy[t] = cadd(cmul(c, x), cmul(d, y));
+  }
+}
+template <typename T>
+hipError_t launch_jones(const cx<T>* ex, const cx<T>* ey, cx<T>* ox, cx<T>* oy, const double* J, int64_t npix,
+                        int batch, hipStream_t s) {
+  J4 j4;
+  for (int i = 0; i < 8; ++i) j4.v[i] = J[i];
+  hipLaunchKernelGGL((k_jones<T>), dim3(ew_blocks(npix * batch)), dim3(256), 0, s, ex, ey, ox, oy, j4, npix * batch);
+  return hipGetLastError();
+}
+
+// fixed-order block reduction of NV doubles
+template <int NV>
+__device__ __forceinline__ void block_reduce(double (&v)[NV], double* sh /* NV * 256 */) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int m = 0; m < NV; ++m) sh[m * 256 + t] = v[m];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+#pragma unroll
+      for (int m = 0; m < NV; ++m) sh[m * 256 + t] += sh[m * 256 + t + w];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int m = 0; m < NV; ++m) v[m] = sh[m * 256];
+}
+
+struct J8 { double v[16]; };
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_jones_grad_partial(const cx<T>* gx, const cx<T>* gy, const cx<T>* ex,
+                                                            const cx<T>* ey, J8 dJ, double* partial, int nblk,
+                                                            int64_t npix) {
+  __shared__ double sh[2 * 256];
+  const int b = blockIdx.y;
+  double acc[2] = {0.0, 0.0};
+  const int64_t off = (int64_t)b * npix;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < npix; i += (int64_t)nblk * 256) {
+    const cx<T> x = ex[off + i], y = ey[off + i], g0 = gx[off + i], g1 = gy[off + i];
+    const double X[2] = {x.x, x.y}, Y[2] = {y.x, y.y}, G0[2] = {g0.x, g0.y}, G1[2] = {g1.x, g1.y};
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const double* d = dJ.v + 8 * m;
+      const double o0r = d[0] * X[0] - d[1] * X[1] + d[2] * Y[0] - d[3] * Y[1];
+      const double o0i = d[0] * X[1] + d[1] * X[0] + d[2] * Y[1] + d[3] * Y[0];
+      const double o1r = d[4] * X[0] - d[5] * X[1] + d[6] * Y[0] - d[7] * Y[1];
+      const double o1i = d[4] * X[1] + d[5] * X[0] + d[6] * Y[1] + d[7] * Y[0];
+      acc[m] += G0[0] * o0r + G0[1] * o0i + G1[0] * o1r + G1[1] * o1i;
+    }
+  }
+  block_reduce<2>(acc, sh);
+  if (threadIdx.x == 0) {
+    partial[((int64_t)b * nblk + blockIdx.x) * 2 + 0] = acc[0];
+    partial[((int64_t)b * nblk + blockIdx.x) * 2 + 1] = acc[1];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials2(const double* partial, int nblk, double* out) {
+  __shared__ double sh[2 * 256];
+  const int b = blockIdx.x;
+  double acc[2] = {0.0, 0.0};
+  for (int i = threadIdx.x; i < nblk; i += 256) {
+    acc[0] += partial[((int64_t)b * nblk + i) * 2 + 0];
+    acc[1] += partial[((int64_t)b * nblk + i) * 2 + 1];
+  }
+  block_reduce<2>(acc, sh);
+  if (threadIdx.x == 0) { out[b * 2 + 0] = acc[0]; out[b * 2 + 1] = acc[1]; }
+}
+
+template <typename T>
+hipError_t launch_jones_grad(const cx<T>* gx, const cx<T>* gy, const cx<T>* ex, const cx<T>* ey, const double* dJ,
+                             double* out, double* partial, int nblk, int64_t npix, int batch, hipStream_t s) {
+  J8 j8;
+  for (int i = 0; i < 16; ++i) j8.v[i] = dJ[i];
+  hipLaunchKernelGGL((k_jones_grad_partial<T>), dim3(nblk, batch), dim3(256), 0, s, gx, gy, ex, ey, j8, partial, nblk,
+                     npix);
+  hipLaunchKernelGGL(k_sum_partials2, dim3(batch), dim3(256), 0, s, partial, nblk, out);
+  return hipGetLastError();
+}
+
+// focusing pupil map
+__device__ __forceinline__ bool pupil_coeffs(double x, double y, double f, double na, double m[6]) {
+  const double X2 = x * x + y * y;
+  const double rmax = f * na;
+  if (!(X2 <= rmax * rmax * (1.0 + 1e-9))) {
+    for (int i = 0; i < 6; ++i) m[i] = 0.0;
+    return false;
+  }
+  const double sx = x / f, sy = y / f;
+  const double sz = sqrt(fmax(1.0 - X2 / (f * f), 0.0));
+  const double w = 1.0 / sqrt(sz);
+  const double a = 1.0 / (1.0 + sz);
+  m[0] = w * (1.0 - sx * sx * a);
+  m[1] = w * (-sx * sy * a);
+  m[2] = w * (-sx * sy * a);
+  m[3] = w * (1.0 - sy * sy * a);
+  m[4] = w * (-sx);
+  m[5] = w * (-sy);
+  return true;
+}
+
+template <typename T>
+__global__ void k_pupil_fwd(const cx<T>* ex, const cx<T>* ey, cx<T>* o0, cx<T>* o1, cx<T>* o2, int nx, int ny,
+                            double dx, double dy, double cx0, double cy0, double f, double na, int batch,
+                            int64_t obs) {
+  const int64_t npix = (int64_t)nx * ny, total = npix * batch;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = t / npix, i = t - b * npix;
+    const int row = (int)(i / nx), col = (int)(i - (int64_t)row * nx);
+    const double x = cx0 + (double)(col - nx / 2) * dx, y = cy0 + (double)(row - ny / 2) * dy;
+    double m[6];
+    pupil_coeffs(x, y, f, na, m);
+    const cx<T> a = ex[t], c = ey[t];
+    const int64_t o = b * obs + i;
+    o0[o] = mk<T>(T(m[0]) * a.x + T(m[1]) * c.x, T(m[0]) * a.y + T(m[1]) * c.y);
+    o1[o] = mk<T>(T(m[2]) * a.x + T(m[3]) * c.x, T(m[2]) * a.y + T(m[3]) * c.y);
+    o2[o] = mk<T>(T(m[4]) * a.x + T(m[5]) * c.x, T(m[4]) * a.y + T(m[5]) * c.y);
+  }
+}
+
+template <typename T>
+__global__ void k_pupil_adj(cx<T>* gex, cx<T>* gey, const cx<T>* g0, const cx<T>* g1, const cx<T>* g2, int nx,
+                            int ny, double dx, double dy, double cx0, double cy0, double f, double na, int batch,
+                            int64_t ibs) {
+  const int64_t npix = (int64_t)nx * ny, total = npix * batch;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = t / npix, i = t - b * npix;
+    const int row = (int)(i / nx), col = (int)(i - (int64_t)row * nx);
+    const double x = cx0 + (double)(col - nx / 2) * dx, y = cy0 + (double)(row - ny / 2) * dy;
+    double m[6];
+    pupil_coeffs(x, y, f, na, m);
+    const int64_t o = b * ibs + i;
+    const cx<T> a = g0[o], c = g1[o], d = g2[o];
+    gex[t] = mk<T>(T(m[0]) * a.x + T(m[2]) * c.x + T(m[4]) * d.x, T(m[0]) * a.y + T(m[2]) * c.y + T(m[4]) * d.y);
+    gey[t] = mk<T>(T(m[1]) * a.x + T(m[3]) * c.x + T(m[5]) * d.x, T(m[1]) * a.y + T(m[3]) * c.y + T(m[5]) * d.y);
+  }
+}
+
+template <typename T>
+hipError_t launch_pupil(const cx<T>* ex, const cx<T>* ey, cx<T>* o0, cx<T>* o1, cx<T>* o2, int nx, int ny,
+                        double dx, double dy, double cx0, double cy0, double f, double na, int batch,
+                        int64_t out_bstride, bool adjoint, hipStream_t s) {
+  const int blocks = ew_blocks((int64_t)nx * ny * batch);
+  if (!adjoint)
+    hipLaunchKernelGGL((k_pupil_fwd<T>), dim3(blocks), dim3(256), 0, s, ex, ey, o0, o1, o2, nx, ny, dx, dy, cx0, cy0,
+                       f, na, batch, out_bstride);
+  else  // here ex/ey are the outputs and o0..o2 the inputs
+    hipLaunchKernelGGL((k_pupil_adj<T>), dim3(blocks), dim3(256), 0, s, const_cast<cx<T>*>(ex),
+                       const_cast<cx<T>*>(ey), o0, o1, o2, nx, ny, dx, dy, cx0, cy0, f, na, batch, out_bstride);
+  return hipGetLastError();
+}
+
+// free-space VCZT helpers
+template <typename T>
+__global__ void k_vczt_prep(const cx<T>* ex, const cx<T>* ey, cx<T>* o, int nx, int ny, double dx, double dy,
+                            double cx0, double cy0, int batch) {
+  const int64_t npix = (int64_t)nx * ny, total = npix * batch;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = t % npix;
+    const int row = (int)(i / nx), col = (int)(i - (int64_t)row * nx);
+    const T x = T(cx0 + (double)(col - nx / 2) * dx), y = T(cy0 + (double)(row - ny / 2) * dy);
+    const cx<T> a = ex[t], c = ey[t];
+    o[t] = mk<T>(x * a.x + y * c.x, x * a.y + y * c.y);
+  }
+}
+template <typename T>
+hipError_t launch_vczt_prep(const cx<T>* ex, const cx<T>* ey, cx<T>* o, int nx, int ny, double dx, double dy,
+                            double cx0, double cy0, int batch, hipStream_t s) {
+  hipLaunchKernelGGL((k_vczt_prep<T>), dim3(ew_blocks((int64_t)nx * ny * batch)), dim3(256), 0, s, ex, ey, o, nx, ny,
+                     dx, dy, cx0, cy0, batch);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_vczt_combine(const cx<T>* cxp, const cx<T>* cyp, const cx<T>* c2, cx<T>* ez, int nx, int ny,
+                               double dx, double dy, double cx0, double cy0, double z, int batch) {
+  const int64_t npix = (int64_t)nx * ny, total = npix * batch;
+  const T iz = T(1.0 / z);
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = t % npix;
+    const int row = (int)(i / nx), col = (int)(i - (int64_t)row * nx);
+    const T X = T(cx0 + (double)(col - nx / 2) * dx), Y = T(cy0 + (double)(row - ny / 2) * dy);
+    const cx<T> a = cxp[t], b = cyp[t], c = c2[t];
+    ez[t] = mk<T>(-(X * a.x + Y * b.x - c.x) * iz, -(X * a.y + Y * b.y - c.y) * iz);
+  }
+}
+template <typename T>
+hipError_t launch_vczt_combine(const cx<T>* cxp, const cx<T>* cyp, const cx<T>* c2, cx<T>* ez, int nx, int ny,
+                               double dx, double dy, double cx0, double cy0, double z, int batch, hipStream_t s) {
+  hipLaunchKernelGGL((k_vczt_combine<T>), dim3(ew_blocks((int64_t)nx * ny * batch)), dim3(256), 0, s, cxp, cyp, c2, ez,
+                     nx, ny, dx, dy, cx0, cy0, z, batch);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_vczt_adj_prep(const cx<T>* gz, cx<T>* xg, cx<T>* yg, int nx, int ny, double dx, double dy,
+                                double cx0, double cy0, double z, int batch) {
+  const int64_t npix = (int64_t)nx * ny, total = npix * batch;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = t % npix;
+    const int row = (int)(i / nx), col = (int)(i - (int64_t)row * nx);
+    const T X = T(cx0 + (double)(col - nx / 2) * dx), Y = T(cy0 + (double)(row - ny / 2) * dy);
+    const cx<T> g = gz[t];
+    xg[t] = mk<T>(X * g.x, X * g.y);
+    yg[t] = mk<T>(Y * g.x, Y * g.y);
+  }
+}
+template <typename T>
+hipError_t launch_vczt_adj_prep(const cx<T>* gz, cx<T>* xg, cx<T>* yg, int nx, int ny, double dx, double dy,
+                                double cx0, double cy0, double z, int batch, hipStream_t s) {
+  hipLaunchKernelGGL((k_vczt_adj_prep<T>), dim3(ew_blocks((int64_t)nx * ny * batch)), dim3(256), 0, s, gz, xg, yg, nx,
+                     ny, dx, dy, cx0, cy0, z, batch);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_vczt_adj_combine(cx<T>* gex, cx<T>* gey, const cx<T>* cxg, const cx<T>* cyg, const cx<T>* cz,
+                                   int nx, int ny, double dx, double dy, double cx0, double cy0, double z, int batch) {
+  const int64_t npix = (int64_t)nx * ny, total = npix * batch;
+  const T iz = T(1.0 / z);
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = t % npix;
+    const int row = (int)(i / nx), col = (int)(i - (int64_t)row * nx);
+    const T x = T(cx0 + (double)(col - nx / 2) * dx), y = T(cy0 + (double)(row - ny / 2) * dy);
+    const cx<T> a = cxg[t], b = cyg[t], c = cz[t], ge = gex[t], gf = gey[t];
+    gex[t] = mk<T>(ge.x - (a.x - x * c.x) * iz, ge.y - (a.y - x * c.y) * iz);
+    gey[t] = mk<T>(gf.x - (b.x - y * c.x) * iz, gf.y - (b.y - y * c.y) * iz);
+  }
+}
+template <typename T>
+hipError_t launch_vczt_adj_combine(cx<T>* gex, cx<T>* gey, const cx<T>* cxg, const cx<T>* cyg, const cx<T>* cz,
+                                   int nx, int ny, double dx, double dy, double cx0, double cy0, double z, int batch,
+                                   hipStream_t s) {
+  hipLaunchKernelGGL((k_vczt_adj_combine<T>), dim3(ew_blocks((int64_t)nx * ny * batch)), dim3(256), 0, s, gex, gey,
+                     cxg, cyg, cz, nx, ny, dx, dy, cx0, cy0, z, batch);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------- spot loss --
+template <typename T>
+__global__ __launch_bounds__(256) void k_spot_partial(const cx<T>* ex, const cx<T>* ey, const cx<T>* ez, int nx,
+                                                      int ny, double dx, double dy, double* partial, int nblk) {
+  __shared__ double sh[5 * 256];
+  const int b = blockIdx.y;
+  const int64_t npix = (int64_t)nx * ny, off = (int64_t)b * npix;
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < npix; i += (int64_t)nblk * 256) {
+    const int row = (int)(i / nx), col = (int)(i - (int64_t)row * nx);
+    const double X = (double)(col - nx / 2) * dx, Y = (double)(row - ny / 2) * dy;
+    const cx<T> a = ex[off + i], c = ey[off + i];
+    double Iz = 0.0;
+    if (ez) { const cx<T> e = ez[off + i]; Iz = (double)e.x * e.x + (double)e.y * e.y; }
+    const double I = (double)a.x * a.x + (double)a.y * a.y + (double)c.x * c.x + (double)c.y * c.y + Iz;
+    acc[0] += I;
+    acc[1] += I * X;
+    acc[2] += I * Y;
+    acc[3] += I * (X * X + Y * Y);
+    acc[4] += Iz;
+  }
+  block_reduce<5>(acc, sh);
+  if (threadIdx.x == 0)
+    for (int m = 0; m < 5; ++m) partial[((int64_t)b * nblk + blockIdx.x) * 5 + m] = acc[m];
+}
+
+__global__ __launch_bounds__(256) void k_spot_final(const double* partial, int nblk, double wavelength, double w_fz,
+                                                    double* res) {
+  __shared__ double sh[5 * 256];
+  const int b = blockIdx.x;
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int i = threadIdx.x; i < nblk; i += 256)
+    for (int m = 0; m < 5; ++m) acc[m] += partial[((int64_t)b * nblk + i) * 5 + m];
+  block_reduce<5>(acc, sh);
+  if (threadIdx.x == 0) {
+    const double P = acc[0];
+    const double xb = acc[1] / P, yb = acc[2] / P;
+    const double s2 = acc[3] / P - xb * xb - yb * yb;
+    const double fz = acc[4] / P;
+    double* r = res + 8 * b;
+    r[0] = s2 / (wavelength * wavelength) + w_fz * fz;
+    r[1] = s2;
+    r[2] = fz;
+    r[3] = P;
+    r[4] = xb;
+    r[5] = yb;
+    r[6] = 0.0;
+    r[7] = 0.0;
+  }
+}
+
+template <typename T>
+__global__ void k_spot_seed(const cx<T>* ex, const cx<T>* ey, const cx<T>* ez, cx<T>* gx, cx<T>* gy, cx<T>* gz,
+                            int nx, int ny, double dx, double dy, double wavelength, double w_fz, const double* res,
+                            int batch) {
+  const int64_t npix = (int64_t)nx * ny, total = npix * batch;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = t / npix, i = t - b * npix;
+    const double* r = res + 8 * b;
+    const double P = r[3], s2 = r[1], fz = r[2], xb = r[4], yb = r[5];
+    const int row = (int)(i / nx), col = (int)(i - (int64_t)row * nx);
+    const double X = (double)(col - nx / 2) * dx - xb, Y = (double)(row - ny / 2) * dy - yb;
+    const double dI = (X * X + Y * Y - s2) / (P * wavelength * wavelength);
+    const double dxy = 2.0 * (dI - w_fz * fz / P);
+    const T ct = T(dxy);
+    const cx<T> a = ex[t], c = ey[t];
+    gx[t] = mk<T>(ct * a.x, ct * a.y);
+    gy[t] = mk<T>(ct * c.x, ct * c.y);
+    if (ez && gz) {
+      const T cz = T(2.0 * (dI + w_fz * (1.0 - fz) / P));
+      const cx<T> e = ez[t];
+      gz[t] = mk<T>(cz * e.x, cz * e.y);
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_spot_loss(const cx<T>* ex, const cx<T>* ey, const cx<T>* ez, int nx, int ny, double dx, double dy,
+                            double cx0, double cy0, double wavelength, double w_fz, double* res, double* partial,
+                            int nblk, cx<T>* gx, cx<T>* gy, cx<T>* gz, int batch, hipStream_t s) {
+  (void)cx0;
+  (void)cy0;  // moments are taken relative to the window centre
+  hipLaunchKernelGGL((k_spot_partial<T>), dim3(nblk, batch), dim3(256), 0, s, ex, ey, ez, nx, ny, dx, dy, partial,
+                     nblk);
+  hipLaunchKernelGGL(k_spot_final, dim3(batch), dim3(256), 0, s, partial, nblk, wavelength, w_fz, res);
+  if (gx && gy)
+    hipLaunchKernelGGL((k_spot_seed<T>), dim3(ew_blocks((int64_t)nx * ny * batch)), dim3(256), 0, s, ex, ey, ez, gx,
+                       gy, gz, nx, ny, dx, dy, wavelength, w_fz, res, batch);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ instantiations --
+#define LP_INST(T)                                                                                                  \
+  template hipError_t launch_extract_quarter<T>(const cx<double>*, cx<T>*, int, int, hipStream_t);                  \
+  template hipError_t launch_zoom_vectors<T>(const ZoomSpec&, cx<T>*, cx<T>*, cx<double>*, hipStream_t);            \
+  template hipError_t launch_convert<T>(const cx<double>*, cx<T>*, int64_t, hipStream_t);                           \
+  template hipError_t launch_modulate<T>(const cx<T>*, const T*, cx<T>*, int64_t, int, int64_t, hipStream_t);      \
+  template hipError_t launch_phase_grad<T>(const cx<T>*, const cx<T>*, T*, int64_t, int, int, hipStream_t);         \
+  template hipError_t launch_source_gaussian<T>(cx<T>*, int, int, double, double, double, double, double, double,  \
+                                                double, double, int, hipStream_t);                                  \
+  template hipError_t launch_source_radial<T>(cx<T>*, cx<T>*, int, int, double, double, double, double, double,    \
+                                              int, hipStream_t);                                                    \
+  template hipError_t launch_jones<T>(const cx<T>*, const cx<T>*, cx<T>*, cx<T>*, const double*, int64_t, int,     \
+                                      hipStream_t);                                                                 \
+  template hipError_t launch_jones_grad<T>(const cx<T>*, const cx<T>*, const cx<T>*, const cx<T>*, const double*, \
+                                           double*, double*, int, int64_t, int, hipStream_t);                       \
+  template hipError_t launch_pupil<T>(const cx<T>*, const cx<T>*, cx<T>*, cx<T>*, cx<T>*, int, int, double,       \
+                                      double, double, double, double, double, int, int64_t, bool, hipStream_t);     \
+  template hipError_t launch_vczt_prep<T>(const cx<T>*, const cx<T>*, cx<T>*, int, int, double, double, double,    \
+                                          double, int, hipStream_t);                                                \
+  template hipError_t launch_vczt_combine<T>(const cx<T>*, const cx<T>*, const cx<T>*, cx<T>*, int, int, double,   \
+                                             double, double, double, double, int, hipStream_t);                     \
+  template hipError_t launch_vczt_adj_prep<T>(const cx<T>*, cx<T>*, cx<T>*, int, int, double, double, double,      \
+                                              double, double, int, hipStream_t);                                    \
+  template hipError_t launch_vczt_adj_combine<T>(cx<T>*, cx<T>*, const cx<T>*, const cx<T>*, const cx<T>*, int,    \
+                                                 int, double, double, double, double, double, int, hipStream_t);    \
+  template hipError_t launch_spot_loss<T>(const cx<T>*, const cx<T>*, const cx<T>*, int, int, double, double,       \
+                                          double, double, double, double, double*, double*, int, cx<T>*, cx<T>*,    \
+                                          cx<T>*, int, hipStream_t);
+
+LP_INST(float)
+LP_INST(double)
+
+}  // namespace lp

@@ -1,0 +1,319 @@
+// Device-side mixed-radix (2/3) FFT engine for CDNA4 (gfx950).
+//
+// A "line" is one 1-D transform of length n = 2^a 3^b <= 8192 handled by T
+// threads of a workgroup.  The transform is a Stockham autosort sequence of
+// stages with radices R_s (prod R_s = n).  In stage s every active thread
+// owns one radix-R_s butterfly: it reads R values at stride n/R_s, applies
+// the stage twiddles, runs an in-register DFT_R and writes R values.  The
+// first stage reads through a caller-supplied load functor (global memory,
+// zero padding and pre-multiplication fused in), intermediate stages go
+// through LDS, and the last stage hands natural-order outputs to a store
+// functor (global memory with cropping/post-multiplication, or LDS for a
+// following transform).  The twiddle table holds, for stage s, the values
+// W_{Ns R}^{r k} (r = 1..R-1, k = 0..Ns-1) at tw[off_s + (r-1) Ns + k], so
+// lanes with consecutive k read consecutive entries.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <utility>
+
+namespace lp {
+
+// ---------------------------------------------------------------- complex --
+// Interleaved (re, im) pair: the layout of torch.complex64 / complex128.
+template <typename T> struct alignas(2 * sizeof(T)) cx { T x, y; };
+
+template <typename T> __device__ __forceinline__ cx<T> mk(T a, T b) { cx<T> r; r.x = a; r.y = b; return r; }
+template <typename V> __device__ __forceinline__ V cadd(V a, V b) { V r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+template <typename V> __device__ __forceinline__ V csub(V a, V b) { V r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
+  V r; r.x = a.x * b.x - a.y * b.y; r.y = a.x * b.y + a.y * b.x; return r;
+}
+// a * conj(b)
+template <typename V> __device__ __forceinline__ V cmulc(V a, V b) {
+  V r; r.x = a.x * b.x + a.y * b.y; r.y = a.y * b.x - a.x * b.y; return r;
+}
+template <typename V> __device__ __forceinline__ V cconj(V a) { a.y = -a.y; return a; }
+template <typename V, typename S> __device__ __forceinline__ V cscale(V a, S s) { a.x *= s; a.y *= s; return a; }
+// multiply by -i (DIR<0) or +i (DIR>0)
+template <int DIR, typename V> __device__ __forceinline__ V mul_i(V a) {
+  V r;
+  if (DIR < 0) { r.x = a.y; r.y = -a.x; } else { r.x = -a.y; r.y = a.x; }
+  return r;
+}
+
+// ------------------------------------------- compile-time sin/cos of 2 pi p/q
+struct CS { double c, s; };
+constexpr double taylor_sin(double x) {
+  double t = x, s = x;
+  for (int n = 1; n < 14; ++n) { t *= -x * x / double((2 * n) * (2 * n + 1)); s += t; }
+  return s;
+}
+constexpr double taylor_cos(double x) {
+  double t = 1.0, s = 1.0;
+  for (int n = 1; n < 14; ++n) { t *= -x * x / double((2 * n - 1) * (2 * n)); s += t; }
+  return s;
+}
+// exact octant reduction in integers, Taylor on [0, pi/4]
+constexpr CS sincos2pi(long p, long q) {
+  p %= q;
+  if (p < 0) p += q;
+  const long quad = (4 * p) / q;
+  long rem = 4 * p - quad * q;  // angle within quadrant = (pi/2) rem / q
+  bool swap = false;
+  if (2 * rem > q) { rem = q - rem; swap = true; }
+  const double x = 1.5707963267948966192313216916398 * double(rem) / double(q);
+  double c = taylor_cos(x), s = taylor_sin(x);
+  if (swap) { double t = c; c = s; s = t; }
+  double rc = c, rs = s;
+  if (quad == 1) { rc = -s; rs = c; }
+  else if (quad == 2) { rc = -c; rs = -s; }
+  else if (quad == 3) { rc = s; rs = -c; }
+  return CS{rc, rs};
+}
+
+// multiply by the constant W_R^M in direction DIR (exp(DIR * 2 pi i M / R));
+// M is a template parameter so that every constant folds at compile time
+template <int R, int DIR, int M, typename T>
+__device__ __forceinline__ cx<T> mul_const(cx<T> a) {
+  using V = cx<T>;
+  constexpr int mm = ((M % R) + R) % R;
+  constexpr CS w = sincos2pi(mm, R);
+  constexpr double c = w.c;
+  constexpr double s = DIR * w.s;
+  if constexpr (mm == 0) {
+    return a;
+  } else if constexpr (4 * mm == R) {
+    return mul_i<DIR>(a);
+  } else if constexpr (2 * mm == R) {
+    a.x = -a.x;
+    a.y = -a.y;
+    return a;
+  } else if constexpr (4 * mm == 3 * R) {
+    return mul_i<-DIR>(a);
+  } else if constexpr (8 * mm == R || 8 * mm == 3 * R || 8 * mm == 5 * R || 8 * mm == 7 * R) {
+    // |c| == |s| == 1/sqrt 2
+    constexpr T h = T(c > 0 ? c : -c);
+    constexpr T sc = T(c > 0 ? 1 : -1), ss = T(s > 0 ? 1 : -1);
+    V r;
+    const T re = sc * a.x - ss * a.y;
+    const T im = ss * a.x + sc * a.y;
+    r.x = re * h;
+    r.y = im * h;
+    return r;
+  } else {
+    constexpr T cc = T(c), sv = T(s);
+    V r;
+    r.x = a.x * cc - a.y * sv;
+    r.y = a.x * sv + a.y * cc;
+    return r;
+  }
+}
+
+// ------------------------------------------------------- in-register DFTs --
+// Dft<R, DIR>: v[k] <- sum_r v[r] exp(DIR 2 pi i r k / R), natural order.
+template <int R, int DIR> struct Dft;
+
+template <int DIR> struct Dft<1, DIR> {
+  template <typename T> __device__ __forceinline__ static void run(cx<T>*) {}
+};
+template <int DIR> struct Dft<2, DIR> {
+  template <typename T> __device__ __forceinline__ static void run(cx<T>* v) {
+    using V = cx<T>;
+    V a = v[0], b = v[1];
+    v[0] = cadd(a, b); v[1] = csub(a, b);
+  }
+};
+template <int DIR> struct Dft<3, DIR> {
+  template <typename T> __device__ __forceinline__ static void run(cx<T>* v) {
+    using V = cx<T>;
+    const T h = T(0.86602540378443864676372317075294);  // sqrt(3)/2
+    V t = cadd(v[1], v[2]);
+    V d = csub(v[1], v[2]);
+    V m; m.x = v[0].x - T(0.5) * t.x; m.y = v[0].y - T(0.5) * t.y;
+    v[0] = cadd(v[0], t);
+    // DIR * i * (sqrt3/2) * d
+    V s = mul_i<DIR>(d); s.x *= h; s.y *= h;
+    v[1] = cadd(m, s);
+    v[2] = csub(m, s);
+  }
+};
+template <int DIR> struct Dft<4, DIR> {
+  template <typename T> __device__ __forceinline__ static void run(cx<T>* v) {
+    using V = cx<T>;
+    V t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    V t2 = cadd(v[1], v[3]), t3 = mul_i<DIR>(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2); v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3); v[3] = csub(t1, t3);
+  }
+};
+
+template <int R> struct FirstFactor {
+  static constexpr int value = (R % 4 == 0 && R != 4) ? 4 : (R % 3 == 0 && R != 3) ? 3 : (R % 2 == 0 && R != 2) ? 2 : R;
+};
+
+// y[I] *= W_R^{(I / B) (I % B)} for all I < R
+template <int R, int B, int DIR, typename T, int... I>
+__device__ __forceinline__ void twiddle_block(cx<T>* y, std::integer_sequence<int, I...>) {
+  ((y[I] = mul_const<R, DIR, (I / B) * (I % B), T>(y[I])), ...);
+}
+
+// Composite R = A B: r = r1 + A r2, k = k2 + B k1.
+template <int R, int DIR> struct Dft {
+  static constexpr int A = FirstFactor<R>::value;
+  static constexpr int B = R / A;
+  template <typename T> __device__ __forceinline__ static void run(cx<T>* v) {
+    using V = cx<T>;
+    V y[R];
+#pragma unroll
+    for (int r1 = 0; r1 < A; ++r1) {
+      V t[B];
+#pragma unroll
+      for (int r2 = 0; r2 < B; ++r2) t[r2] = v[r1 + A * r2];
+      Dft<B, DIR>::template run<T>(t);
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) y[r1 * B + k2] = t[k2];
+    }
+    twiddle_block<R, B, DIR, T>(y, std::make_integer_sequence<int, R>{});
+#pragma unroll
+    for (int k2 = 0; k2 < B; ++k2) {
+      V t[A];
+#pragma unroll
+      for (int r1 = 0; r1 < A; ++r1) t[r1] = y[r1 * B + k2];
+      Dft<A, DIR>::template run<T>(t);
+#pragma unroll
+      for (int k1 = 0; k1 < A; ++k1) v[k2 + B * k1] = t[k1];
+    }
+  }
+};
+
+// ------------------------------------------------------- radix schedules --
+// Every transform length the library uses, with its compile-time radix
+// schedule (largest radix first).  Requested sizes are rounded up to the
+// next length in this list, which is exact for zero-padded convolution and
+// for Bluestein.  X(n, radices...)
+#define LP_LENGTHS(X)                                                                            \
+  X(1, 1) X(2, 2) X(4, 4) X(8, 8) X(16, 16) X(32, 8, 4) X(64, 8, 8) X(96, 12, 8) X(128, 16, 8)  \
+  X(192, 16, 12) X(256, 16, 16) X(384, 8, 8, 6) X(512, 8, 8, 8) X(768, 12, 8, 8)                \
+  X(1024, 16, 8, 8) X(1536, 16, 12, 8) X(2048, 16, 16, 8) X(3072, 16, 16, 12)                   \
+  X(4096, 16, 16, 16) X(6144, 32, 16, 12) X(8192, 32, 16, 16)
+
+constexpr int kMaxLen = 8192;
+constexpr int kMaxStages = 4;
+
+template <int... Rs> struct Sched {
+  static constexpr int nst = sizeof...(Rs);
+  static constexpr int rad[nst] = {Rs...};
+  static constexpr int n = (1 * ... * Rs);
+  static constexpr int rmin() {
+    int m = rad[0];
+    for (int i = 1; i < nst; ++i) m = rad[i] < m ? rad[i] : m;
+    return m;
+  }
+  static constexpr int threads = n / rmin();
+  static constexpr int ns(int s) {
+    int p = 1;
+    for (int i = 0; i < s; ++i) p *= rad[i];
+    return p;
+  }
+  // offset of stage s in the twiddle table: stage s >= 1 holds
+  // W_{Ns R}^{r k} at off + (r-1) Ns + k, r = 1..R-1, k = 0..Ns-1
+  static constexpr int twoff(int s) {
+    int off = 0;
+    for (int i = 1; i < s; ++i) off += (rad[i] - 1) * ns(i);
+    return off;
+  }
+  static constexpr int twsize() { return nst > 1 ? twoff(nst) : 1; }
+};
+
+__host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 5); }
+__host__ __device__ constexpr int lds_line_elems(int n) { return n + (n >> 5) + 1; }
+
+template <typename T, int DIR, class S, int s, class Load, class Store>
+__device__ __forceinline__ void ct_stage(cx<T>* __restrict__ lds, const cx<T>* __restrict__ tw, int j,
+                                         bool sync_first, Load& load, Store& store) {
+  using V = cx<T>;
+  constexpr int R = S::rad[s];
+  constexpr int nr = S::n / R;
+  constexpr int Ns = S::ns(s);
+  constexpr bool first = s == 0, last = s == S::nst - 1;
+  const bool act = j < nr;
+  V v[R];
+  if (act) {
+    if constexpr (first) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = load(j + r * nr);
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = lds[lds_pad(j + r * nr)];
+    }
+  }
+  if (!first || sync_first) __syncthreads();
+  if (act) {
+    const int k = j % Ns;
+    const int q = j / Ns;
+    if constexpr (!first) {
+      const V* t = tw + S::twoff(s) + k;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const V w = t[(r - 1) * Ns];
+        v[r] = DIR < 0 ? cmul(v[r], w) : cmulc(v[r], w);
+      }
+    }
+    Dft<R, DIR>::template run<T>(v);
+    if constexpr (last) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) store(j + r * nr, v[r]);
+    } else {
+      const int base = q * Ns * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[lds_pad(base + r * Ns)] = v[r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int DIR, class S, class Load, class Store, int... I>
+__device__ __forceinline__ void ct_line_impl(cx<T>* lds, const cx<T>* tw, int j, bool sync_first, Load& load,
+                                             Store& store, std::integer_sequence<int, I...>) {
+  (ct_stage<T, DIR, S, I>(lds, tw, j, sync_first, load, store), ...);
+}
+
+// One transform of one line of length S::n by threads j = 0..S::threads-1.
+// Every thread of the workgroup must call this (barriers inside).
+// DIR = -1: forward (exp(-2 pi i jk/n)); DIR = +1: inverse, unnormalised.
+// load_reads_lds: the load functor reads this workgroup's LDS, so the first
+// stage waits for every read before writing.
+template <typename T, int DIR, class S, class Load, class Store>
+__device__ __forceinline__ void fft_line(cx<T>* lds, const cx<T>* tw, int j, Load load, Store store,
+                                         bool load_reads_lds = false) {
+  ct_line_impl<T, DIR, S>(lds, tw, j, load_reads_lds, load, store, std::make_integer_sequence<int, S::nst>{});
+}
+
+// Host-side description of a length's schedule (for twiddle tables).
+struct SchedInfo {
+  int n, nst, threads;
+  int rad[kMaxStages];
+};
+
+inline bool sched_info(int n, SchedInfo* out) {
+  switch (n) {
+#define LP_SCHED_CASE(N, ...)                                      \
+  case N: {                                                        \
+    using S = Sched<__VA_ARGS__>;                                  \
+    out->n = N;                                                    \
+    out->nst = S::nst;                                             \
+    out->threads = S::threads;                                     \
+    for (int i = 0; i < S::nst; ++i) out->rad[i] = S::rad[i];      \
+    return true;                                                   \
+  }
+    LP_LENGTHS(LP_SCHED_CASE)
+#undef LP_SCHED_CASE
+    default:
+      return false;
+  }
+}
+
+}  // namespace lp

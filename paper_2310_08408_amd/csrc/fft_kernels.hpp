@@ -1,0 +1,337 @@
+// Transform kernels (templated on element type, radix schedule and lines per
+// workgroup) and their host launchers, which switch over the supported
+// lengths.  Included by the per-type instantiation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "kernels.hpp"
+
+namespace lp {
+
+constexpr int kLdsBytes = 160 * 1024;  // LDS per CU (and per workgroup) on gfx950
+constexpr int kColThreads = 1024;      // thread cap of column-pass workgroups
+
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+// Lines per workgroup.  Column passes pack adjacent columns (wide coalesced
+// segments) up to the LDS and thread limits; row passes aim at >= 256
+// threads with at most half the LDS (two workgroups per CU).
+template <typename T, class S, bool COL, int LINES_PER_ITEM = 1, int COL_THREADS = kColThreads>
+struct Cfg {
+  static constexpr int line_bytes = lds_line_elems(S::n) * (int)sizeof(cx<T>) * LINES_PER_ITEM;
+  static constexpr int max_threads = COL ? COL_THREADS : 1024;
+  static constexpr int c_col = cmax(1, cmin(cmin(16, max_threads / (S::threads * LINES_PER_ITEM)), kLdsBytes / line_bytes));
+  static constexpr int c_row =
+      cmax(1, cmin(cmin(cmax(1, 256 / (S::threads * LINES_PER_ITEM)), (kLdsBytes / 2) / line_bytes),
+                   max_threads / (S::threads * LINES_PER_ITEM)));
+  static constexpr int C = COL ? c_col : c_row;
+  static constexpr int threads = C * S::threads * LINES_PER_ITEM;
+  static constexpr bool fits = line_bytes <= kLdsBytes && S::threads * LINES_PER_ITEM <= 1024;
+};
+
+// Workgroup i is dispatched to XCD i % 8; give each XCD a contiguous range
+// of tiles so that neighbouring lines (adjacent columns) share one L2.
+__device__ __forceinline__ int xcd_remap(int i, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = i & 7;
+  return x * q + min(x, r) + (i >> 3);
+}
+
+template <typename T> __device__ __forceinline__ cx<T> czero() { return mk<T>(T(0), T(0)); }
+
+// address of element i of line l of batch item b
+template <bool COL>
+__device__ __forceinline__ int64_t line_off(const Lines& L, int b, int l, int i) {
+  return COL ? (int64_t)b * L.bstride + (int64_t)i * L.pitch + l : (int64_t)b * L.bstride + (int64_t)l * L.pitch + i;
+}
+
+// ------------------------------------------------------------ FFT lines --
+template <typename T, int DIR, bool COL, class S, int C>
+__global__ __launch_bounds__(C * S::threads) void k_fft_lines(const cx<T>* in, cx<T>* out, Lines li, Lines lo,
+                                                              int nlines, int n_in, int n_out, T scale, int tiles,
+                                                              const cx<T>* __restrict__ tw) {
+  __shared__ cx<T> smem[C * lds_line_elems(S::n)];
+  const int id = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = id / tiles, tile = id - b * tiles;
+  const int c = COL ? (int)(threadIdx.x % C) : (int)(threadIdx.x / S::threads);
+  const int j = COL ? (int)(threadIdx.x / C) : (int)(threadIdx.x % S::threads);
+  const int l = tile * C + c;
+  const bool valid = l < nlines;
+  cx<T>* lds = smem + c * lds_line_elems(S::n);
+  auto load = [&](int i) -> cx<T> {
+    cx<T> v = czero<T>();
+    if (valid && i < n_in) v = in[line_off<COL>(li, b, l, i)];
+    return v;
+  };
+  auto store = [&](int i, cx<T> v) {
+    if (valid && i < n_out) out[line_off<COL>(lo, b, l, i)] = cscale(v, scale);
+  };
+  fft_line<T, DIR, S>(lds, tw, j, load, store);
+}
+
+template <typename T, int DIR, bool COL, class S>
+hipError_t launch_fft_lines_s(const cx<T>* in, cx<T>* out, Lines li, Lines lo, int nlines, int n_in, int n_out,
+                              T scale, int batch, const cx<T>* tw, hipStream_t s) {
+  using CF = Cfg<T, S, COL>;
+  if constexpr (!CF::fits) {
+    return hipErrorInvalidValue;
+  } else {
+    const int tiles = (nlines + CF::C - 1) / CF::C;
+    hipLaunchKernelGGL((k_fft_lines<T, DIR, COL, S, CF::C>), dim3(tiles * batch), dim3(CF::threads), 0, s, in, out,
+                       li, lo, nlines, n_in, n_out, scale, tiles, tw);
+    return hipGetLastError();
+  }
+}
+
+template <typename T, int DIR>
+hipError_t launch_fft_lines(int n, bool col, const cx<T>* in, cx<T>* out, Lines li, Lines lo, int nlines, int n_in,
+                            int n_out, T scale, int batch, const cx<T>* tw, hipStream_t s) {
+  if (nlines <= 0 || batch <= 0) return hipSuccess;
+  switch (n) {
+#define LP_CASE(N, ...)                                                                                          \
+  case N:                                                                                                        \
+    return col ? launch_fft_lines_s<T, DIR, true, Sched<__VA_ARGS__>>(in, out, li, lo, nlines, n_in, n_out, scale, \
+                                                                     batch, tw, s)                               \
+               : launch_fft_lines_s<T, DIR, false, Sched<__VA_ARGS__>>(in, out, li, lo, nlines, n_in, n_out,     \
+                                                                      scale, batch, tw, s);
+    LP_LENGTHS(LP_CASE)
+#undef LP_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+// ------------------------------------------------- kernel-spectrum access --
+// Quarter table Sq[(M_y/2+1)][(M_x/2+1)] of an RS-type kernel spectrum with
+// parity: kind 0 even/even, 1 odd in kx, 2 odd in ky.
+template <typename T>
+__device__ __forceinline__ cx<T> spec_at(const cx<T>* __restrict__ Sq, int kind, int kx, int ky, int Mx, int My) {
+  const int qx = min(kx, Mx - kx), qy = min(ky, My - ky);
+  cx<T> h = Sq[(int64_t)qy * (Mx / 2 + 1) + qx];
+  if ((kind == 1 && kx > Mx / 2) || (kind == 2 && ky > My / 2)) { h.x = -h.x; h.y = -h.y; }
+  return h;
+}
+
+// ------------------------------------------------------ RS column pass --
+// In place on columns kx of W: forward transform of the zero-padded column,
+// multiply by the kernel spectrum (conjugated for the adjoint), inverse
+// transform, keep the first n_valid rows.
+template <typename T, class S, int C>
+__global__ __launch_bounds__(C * S::threads) void k_rs_cols(cx<T>* W, int64_t bstride, int64_t pitch, int ncols,
+                                                            int n_valid, const cx<T>* __restrict__ Sq, int Mx,
+                                                            int conj_spec, int tiles, const cx<T>* __restrict__ tw) {
+  __shared__ cx<T> smem[C * lds_line_elems(S::n)];
+  constexpr int My = S::n;
+  const int id = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = id / tiles, tile = id - b * tiles;
+  const int c = threadIdx.x % C, j = threadIdx.x / C;
+  const int kx = tile * C + c;
+  const bool valid = kx < ncols;
+  cx<T>* lds = smem + c * lds_line_elems(S::n);
+  cx<T>* col = W + b * bstride + kx;
+  const cx<T>* sq = Sq + (valid ? min(kx, Mx - kx) : 0);
+  const int qw = Mx / 2 + 1;
+  auto load = [&](int i) -> cx<T> {
+    cx<T> v = czero<T>();
+    if (valid && i < n_valid) v = col[(int64_t)i * pitch];
+    return v;
+  };
+  auto mid = [&](int i, cx<T> v) {
+    cx<T> h = czero<T>();
+    if (valid) h = sq[(int64_t)min(i, My - i) * qw];
+    lds[lds_pad(i)] = conj_spec ? cmulc(v, h) : cmul(v, h);
+  };
+  fft_line<T, -1, S>(lds, tw, j, load, mid);
+  auto load2 = [&](int i) -> cx<T> { return lds[lds_pad(i)]; };
+  auto store = [&](int i, cx<T> v) {
+    if (valid && i < n_valid) col[(int64_t)i * pitch] = v;
+  };
+  fft_line<T, 1, S>(lds, tw, j, load2, store, true);
+}
+
+template <typename T, class S>
+hipError_t launch_rs_cols_s(cx<T>* W, int64_t bstride, int64_t pitch, int ncols, int n_valid, const cx<T>* Sq, int Mx,
+                            bool conj_spec, int batch, const cx<T>* tw, hipStream_t s) {
+  using CF = Cfg<T, S, true>;
+  if constexpr (!CF::fits) {
+    return hipErrorInvalidValue;
+  } else {
+    const int tiles = (ncols + CF::C - 1) / CF::C;
+    hipLaunchKernelGGL((k_rs_cols<T, S, CF::C>), dim3(tiles * batch), dim3(CF::threads), 0, s, W, bstride, pitch,
+                       ncols, n_valid, Sq, Mx, conj_spec ? 1 : 0, tiles, tw);
+    return hipGetLastError();
+  }
+}
+
+template <typename T>
+hipError_t launch_rs_cols(int My, cx<T>* W, int64_t bstride, int64_t pitch, int ncols, int n_valid, const cx<T>* Sq,
+                          int Mx, bool conj_spec, int batch, const cx<T>* tw, hipStream_t s) {
+  if (batch <= 0 || ncols <= 0) return hipSuccess;
+  switch (My) {
+#define LP_CASE(N, ...) \
+  case N: return launch_rs_cols_s<T, Sched<__VA_ARGS__>>(W, bstride, pitch, ncols, n_valid, Sq, Mx, conj_spec, batch, tw, s);
+    LP_LENGTHS(LP_CASE)
+#undef LP_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+// --------------------------------------------------- two-input mixing --
+// out column = IFFT( ca Sa .* FFT(a) + cb Sb .* FFT(b) ) for the vectorial
+// RS passes; Sa/Sb are quarter-stored kernel spectra of the given parity
+// kinds, ca/cb in {-1, +1}, optionally conjugated (adjoint).  `out` may be
+// the same plane as `a` (in place per column).
+template <typename T, class S, int C>
+__global__ __launch_bounds__(2 * C * S::threads) void k_mix2_cols(
+    const cx<T>* a, const cx<T>* bsrc, cx<T>* out, int64_t bstride, int64_t pitch, int ncols, int n_valid,
+    const cx<T>* __restrict__ Sa, int kind_a, T ca, const cx<T>* __restrict__ Sb, int kind_b, T cb, int conj_spec,
+    int Mx, int tiles, const cx<T>* __restrict__ tw) {
+  __shared__ cx<T> smem[2 * C * lds_line_elems(S::n)];
+  constexpr int My = S::n;
+  constexpr int LE = lds_line_elems(S::n);
+  const int id = xcd_remap(blockIdx.x, gridDim.x);
+  const int bt = id / tiles, tile = id - bt * tiles;
+  // thread -> (input slot, column c, butterfly j)
+  const int slot = threadIdx.x / (C * S::threads);
+  const int t = threadIdx.x - slot * (C * S::threads);
+  const int c = t % C, j = t / C;
+  const int kx = tile * C + c;
+  const bool valid = kx < ncols;
+  cx<T>* lds = smem + (slot * C + c) * LE;
+  const cx<T>* src = (slot == 0 ? a : bsrc) + bt * bstride + kx;
+  auto load = [&](int i) -> cx<T> {
+    cx<T> v = czero<T>();
+    if (valid && i < n_valid) v = src[(int64_t)i * pitch];
+    return v;
+  };
+  auto st = [&](int i, cx<T> v) { lds[lds_pad(i)] = v; };
+  fft_line<T, -1, S>(lds, tw, j, load, st);
+  // combine into slot 0 (each (c, k) owned by one thread)
+  for (int e = threadIdx.x; e < C * My; e += 2 * C * S::threads) {
+    const int cc = e % C, k = e / C;
+    const int kxx = tile * C + cc;
+    if (kxx >= ncols) continue;
+    cx<T> ha = spec_at(Sa, kind_a, kxx, k, Mx, My);
+    cx<T> hb = spec_at(Sb, kind_b, kxx, k, Mx, My);
+    if (conj_spec) { ha.y = -ha.y; hb.y = -hb.y; }
+    const int p = lds_pad(k);
+    const cx<T> va = smem[cc * LE + p], vb = smem[(C + cc) * LE + p];
+    const cx<T> r = cadd(cscale(cmul(va, ha), ca), cscale(cmul(vb, hb), cb));
+    smem[cc * LE + p] = r;
+  }
+  __syncthreads();
+  // inverse transform of slot 0 by the slot-0 threads; slot-1 threads pass
+  // an out-of-range butterfly index and only meet the barriers
+  cx<T>* dst = out + bt * bstride + kx;
+  cx<T>* lds0 = smem + c * LE;
+  auto load2 = [&](int i) -> cx<T> { return lds0[lds_pad(i)]; };
+  auto store = [&](int i, cx<T> v) {
+    if (valid && i < n_valid) dst[(int64_t)i * pitch] = v;
+  };
+  fft_line<T, 1, S>(lds0, tw, slot == 0 ? j : S::threads, load2, store, true);
+}
+
+template <typename T, class S>
+hipError_t launch_mix2_cols_s(const cx<T>* a, const cx<T>* b, cx<T>* out, int64_t bstride, int64_t pitch, int ncols,
+                              int n_valid, const cx<T>* Sa, int kind_a, T ca, const cx<T>* Sb, int kind_b, T cb,
+                              bool conj_spec, int Mx, int batch, const cx<T>* tw, hipStream_t s) {
+  using CF = Cfg<T, S, true, 2>;
+  if constexpr (!CF::fits) {
+    return hipErrorInvalidValue;
+  } else {
+    const int tiles = (ncols + CF::C - 1) / CF::C;
+    hipLaunchKernelGGL((k_mix2_cols<T, S, CF::C>), dim3(tiles * batch), dim3(CF::threads), 0, s, a, b, out, bstride,
+                       pitch, ncols, n_valid, Sa, kind_a, ca, Sb, kind_b, cb, conj_spec ? 1 : 0, Mx, tiles, tw);
+    return hipGetLastError();
+  }
+}
+
+template <typename T>
+hipError_t launch_mix2_cols(int My, const cx<T>* a, const cx<T>* b, cx<T>* out, int64_t bstride, int64_t pitch,
+                            int ncols, int n_valid, const cx<T>* Sa, int kind_a, T ca, const cx<T>* Sb, int kind_b,
+                            T cb, bool conj_spec, int Mx, int batch, const cx<T>* tw, hipStream_t s) {
+  if (batch <= 0 || ncols <= 0) return hipSuccess;
+  switch (My) {
+#define LP_CASE(N, ...)                                                                                             \
+  case N:                                                                                                           \
+    return launch_mix2_cols_s<T, Sched<__VA_ARGS__>>(a, b, out, bstride, pitch, ncols, n_valid, Sa, kind_a, ca, Sb, \
+                                                     kind_b, cb, conj_spec, Mx, batch, tw, s);
+    LP_LENGTHS(LP_CASE)
+#undef LP_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+// ----------------------------------------------------------- Bluestein --
+// out[p] = post[p] * IFFT_L( FFT_L(pad(pre .* in)) .* chat )[p], p < n_out.
+template <typename T, bool COL, class S, int C>
+__global__ __launch_bounds__(C * S::threads) void k_bluestein(const cx<T>* in, cx<T>* out, Lines li, Lines lo,
+                                                              int nlines, int n_in, int n_out,
+                                                              const cx<T>* __restrict__ pre,
+                                                              const cx<T>* __restrict__ chat,
+                                                              const cx<T>* __restrict__ post, int tiles,
+                                                              const cx<T>* __restrict__ tw) {
+  __shared__ cx<T> smem[C * lds_line_elems(S::n)];
+  const int id = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = id / tiles, tile = id - b * tiles;
+  const int c = COL ? (int)(threadIdx.x % C) : (int)(threadIdx.x / S::threads);
+  const int j = COL ? (int)(threadIdx.x / C) : (int)(threadIdx.x % S::threads);
+  const int l = tile * C + c;
+  const bool valid = l < nlines;
+  cx<T>* lds = smem + c * lds_line_elems(S::n);
+  auto load = [&](int i) -> cx<T> {
+    cx<T> v = czero<T>();
+    if (valid && i < n_in) v = cmul(in[line_off<COL>(li, b, l, i)], pre[i]);
+    return v;
+  };
+  auto mid = [&](int i, cx<T> v) { lds[lds_pad(i)] = cmul(v, chat[i]); };
+  fft_line<T, -1, S>(lds, tw, j, load, mid);
+  auto load2 = [&](int i) -> cx<T> { return lds[lds_pad(i)]; };
+  auto store = [&](int i, cx<T> v) {
+    if (valid && i < n_out) out[line_off<COL>(lo, b, l, i)] = cmul(v, post[i]);
+  };
+  fft_line<T, 1, S>(lds, tw, j, load2, store, true);
+}
+
+template <typename T, bool COL, class S>
+hipError_t launch_bluestein_s(const cx<T>* in, cx<T>* out, Lines li, Lines lo, int nlines, int n_in, int n_out,
+                              const cx<T>* pre, const cx<T>* chat, const cx<T>* post, int batch, const cx<T>* tw,
+                              hipStream_t s) {
+  // two transforms plus the chirp multiplies per line: 512 threads keep the
+  // radix-16 stages free of register spills
+  using CF = Cfg<T, S, COL, 1, 512>;
+  if constexpr (!CF::fits) {
+    return hipErrorInvalidValue;
+  } else {
+    const int tiles = (nlines + CF::C - 1) / CF::C;
+    hipLaunchKernelGGL((k_bluestein<T, COL, S, CF::C>), dim3(tiles * batch), dim3(CF::threads), 0, s, in, out, li, lo,
+                       nlines, n_in, n_out, pre, chat, post, tiles, tw);
+    return hipGetLastError();
+  }
+}
+
+template <typename T>
+hipError_t launch_bluestein(int L, bool col, const cx<T>* in, cx<T>* out, Lines li, Lines lo, int nlines, int n_in,
+                            int n_out, const cx<T>* pre, const cx<T>* chat, const cx<T>* post, int batch,
+                            const cx<T>* tw, hipStream_t s) {
+  if (nlines <= 0 || batch <= 0) return hipSuccess;
+  switch (L) {
+#define LP_CASE(N, ...)                                                                                             \
+  case N:                                                                                                           \
+    return col ? launch_bluestein_s<T, true, Sched<__VA_ARGS__>>(in, out, li, lo, nlines, n_in, n_out, pre, chat,   \
+                                                                 post, batch, tw, s)                                \
+               : launch_bluestein_s<T, false, Sched<__VA_ARGS__>>(in, out, li, lo, nlines, n_in, n_out, pre, chat, \
+                                                                  post, batch, tw, s);
+    LP_LENGTHS(LP_CASE)
+#undef LP_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace lp

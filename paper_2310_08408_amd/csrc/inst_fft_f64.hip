@@ -1,0 +1,9 @@
+// Plain transform kernels for element type double, all supported lengths.
+#include "fft_kernels.hpp"
+
+namespace lp {
+template hipError_t launch_fft_lines<double, -1>(int, bool, const cx<double>*, cx<double>*, Lines, Lines, int, int, int, double,
+                                             int, const cx<double>*, hipStream_t);
+template hipError_t launch_fft_lines<double, 1>(int, bool, const cx<double>*, cx<double>*, Lines, Lines, int, int, int, double,
+                                            int, const cx<double>*, hipStream_t);
+}  // namespace lp

@@ -1,0 +1,133 @@
+// Host-side launch interface of the libprop HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft_engine.hpp"
+
+namespace lp {
+
+// Lines of a batch of 2-D arrays.  Row mode: line l of batch item b starts
+// at b*bstride + l*pitch and its elements are contiguous.  Column mode: line
+// l is column l, element i at b*bstride + i*pitch + l.  (complex elements)
+struct Lines {
+  int64_t bstride, pitch;
+};
+
+// Plain transform of length n (a supported length) of nlines lines: inputs
+// beyond n_in are zero, the first n_out outputs are kept and scaled.  In
+// place is allowed.
+template <typename T, int DIR>
+hipError_t launch_fft_lines(int n, bool col, const cx<T>* in, cx<T>* out, Lines li, Lines lo, int nlines, int n_in,
+                            int n_out, T scale, int batch, const cx<T>* tw, hipStream_t s);
+
+// RS middle pass, in place on columns kx < ncols of W[b][0..n_valid)[kx]
+// (row pitch `pitch`): transform of length My of the zero-padded column,
+// multiply by the even/even kernel spectrum Sq (quarter table, conjugated
+// for the adjoint), inverse transform, keep the first n_valid rows.
+template <typename T>
+hipError_t launch_rs_cols(int My, cx<T>* W, int64_t bstride, int64_t pitch, int ncols, int n_valid, const cx<T>* Sq,
+                          int Mx, bool conj_spec, int batch, const cx<T>* tw, hipStream_t s);
+
+// Vectorial RS middle pass: out column = IFFT(ca Sa FFT(a) + cb Sb FFT(b))
+// with quarter-stored spectra of parity kind 0 (even/even), 1 (odd in kx)
+// or 2 (odd in ky); conj_spec conjugates both spectra.  out may equal a.
+template <typename T>
+hipError_t launch_mix2_cols(int My, const cx<T>* a, const cx<T>* b, cx<T>* out, int64_t bstride, int64_t pitch,
+                            int ncols, int n_valid, const cx<T>* Sa, int kind_a, T ca, const cx<T>* Sb, int kind_b,
+                            T cb, bool conj_spec, int Mx, int batch, const cx<T>* tw, hipStream_t s);
+
+// Bluestein zoom transform of each line: out[p] = post[p] *
+// IFFT_L(FFT_L(pad(pre .* in)) .* chat)[p], p < n_out.
+template <typename T>
+hipError_t launch_bluestein(int L, bool col, const cx<T>* in, cx<T>* out, Lines li, Lines lo, int nlines, int n_in,
+                            int n_out, const cx<T>* pre, const cx<T>* chat, const cx<T>* post, int batch,
+                            const cx<T>* tw, hipStream_t s);
+
+// ---- FP64 generators (setup work) ----
+// Wrapped RS kernel on an My x Mx grid (complex128), kind 0: H, 1: (X/z) H,
+// 2: (Y/z) H.  Offsets d in [-(n-1), n-1] sit at index d mod M, the rest 0.
+hipError_t launch_rs_kernel_wrapped(cx<double>* out, int Mx, int My, int nx, int ny, double dx,
+                                    double dy, double k, double z, int kind, hipStream_t s);
+// Quarter extraction [0..My/2] x [0..Mx/2] with conversion.
+template <typename T>
+hipError_t launch_extract_quarter(const cx<double>* full, cx<T>* q, int Mx, int My, hipStream_t s);
+
+// 1-D zoom-DFT vectors: sum_j a_j exp(i sigma 2 pi beta X_p x_j) with
+// x_j = x0 + j dx (n_in), X_p = X0 + p dX (n_out):
+//   pre[j]  = exp(i (sigma 2pi beta X0 dx j + sigma pi alpha j^2 + qin x_j^2))
+//   post[p] = K/L exp(i (sigma 2pi beta (X0 x0 + x0 dX p) + sigma pi alpha p^2 + qout X_p^2))
+//   chirp[m mod L] = exp(-i sigma pi alpha m^2), m in [-(n_in-1), n_out-1]
+// with alpha = beta dx dX.  chirp is written in complex128 (to be
+// transformed in FP64), pre/post in T.
+struct ZoomSpec {
+  int sigma;
+  double beta, x0, dx, X0, dX, qin, qout;
+  double Kre, Kim;
+  int n_in, n_out, L;
+};
+template <typename T>
+hipError_t launch_zoom_vectors(const ZoomSpec& zs, cx<T>* pre, cx<T>* post, cx<double>* chirp,
+                               hipStream_t s);
+template <typename T>
+hipError_t launch_convert(const cx<double>* in, cx<T>* out, int64_t n, hipStream_t s);
+
+// ---- elementwise ----
+template <typename T>
+hipError_t launch_modulate(const cx<T>* in, const T* phase, cx<T>* out, int64_t npix, int batch,
+                           int64_t phase_bstride, hipStream_t s);
+template <typename T>
+hipError_t launch_phase_grad(const cx<T>* g, const cx<T>* u, T* grad, int64_t npix, int batch,
+                             int accumulate, hipStream_t s);
+template <typename T>
+hipError_t launch_source_gaussian(cx<T>* out, int nx, int ny, double dx, double dy, double cx0,
+                                  double cy0, double w0, double amp, double f, double k, int batch,
+                                  hipStream_t s);
+template <typename T>
+hipError_t launch_source_radial(cx<T>* ex, cx<T>* ey, int nx, int ny, double dx, double dy,
+                                double cx0, double cy0, double w0, int batch, hipStream_t s);
+// out_c = sum_d J[c][d] in_d (J: 2x2 complex, row-major, as complex128)
+template <typename T>
+hipError_t launch_jones(const cx<T>* ex, const cx<T>* ey, cx<T>* ox, cx<T>* oy, const double* J,
+                        int64_t npix, int batch, hipStream_t s);
+// Deterministic per-batch sums of Re(conj(gx) (A ex + B ey) + conj(gy)(C ex + D ey))
+// for two 2x2 matrices (dJ/deta, dJ/dtheta): out[b*2 + m] (double, device).
+template <typename T>
+hipError_t launch_jones_grad(const cx<T>* gx, const cx<T>* gy, const cx<T>* ex, const cx<T>* ey,
+                             const double* dJ /* 2 x 4 complex */, double* out, double* partial,
+                             int nblk, int64_t npix, int batch, hipStream_t s);
+
+// focusing pupil map (real 3x2 per sample, 1/sqrt(sz) apodisation folded in)
+template <typename T>
+hipError_t launch_pupil(const cx<T>* ex, const cx<T>* ey, cx<T>* o0, cx<T>* o1, cx<T>* o2,
+                        int nx, int ny, double dx, double dy, double cx0, double cy0, double f,
+                        double na, int batch, int64_t out_bstride, bool adjoint, hipStream_t s);
+
+// free-space VCZT helpers
+template <typename T>
+hipError_t launch_vczt_prep(const cx<T>* ex, const cx<T>* ey, cx<T>* o, int nx, int ny, double dx,
+                            double dy, double cx0, double cy0, int batch, hipStream_t s);
+template <typename T>
+hipError_t launch_vczt_combine(const cx<T>* cxp, const cx<T>* cyp, const cx<T>* c2, cx<T>* ez,
+                               int nx, int ny, double dx, double dy, double cx0, double cy0,
+                               double z, int batch, hipStream_t s);
+// adjoint helpers: gz -> (X gz, Y gz) and final combination
+template <typename T>
+hipError_t launch_vczt_adj_prep(const cx<T>* gz, cx<T>* xg, cx<T>* yg, int nx, int ny, double dx,
+                                double dy, double cx0, double cy0, double z, int batch,
+                                hipStream_t s);
+template <typename T>
+hipError_t launch_vczt_adj_combine(cx<T>* gex, cx<T>* gey, const cx<T>* cxg, const cx<T>* cyg,
+                                   const cx<T>* cz, int nx, int ny, double dx, double dy,
+                                   double cx0, double cy0, double z, int batch, hipStream_t s);
+
+// spot-size / E_z-fraction loss: per batch item res[b*4 + {0..3}] =
+// (loss, sigma2, fz, P); seeds g_c = 2 E_c dL/dI_c (optional).
+template <typename T>
+hipError_t launch_spot_loss(const cx<T>* ex, const cx<T>* ey, const cx<T>* ez, int nx, int ny,
+                            double dx, double dy, double cx0, double cy0, double wavelength,
+                            double w_fz, double* res, double* partial, int nblk, cx<T>* gx,
+                            cx<T>* gy, cx<T>* gz, int batch, hipStream_t s);
+
+}  // namespace lp

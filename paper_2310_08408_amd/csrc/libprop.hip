@@ -1,0 +1,996 @@
+// libprop C ABI: argument validation, transform planning, cached kernel
+// spectra / chirp vectors / twiddle tables, per-stream workspace, and the
+// pass sequences of every propagator and its adjoint.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "libprop.h"
+#include "kernels.hpp"
+
+namespace lp {
+
+static thread_local int g_last_hip = 0;
+
+static int dev_err(hipError_t e) {
+  g_last_hip = (int)e;
+  return e == hipErrorOutOfMemory ? PROP_ENOMEM : PROP_EDEVICE;
+}
+#define LP_TRY(expr)                       \
+  do {                                     \
+    hipError_t e_ = (expr);                \
+    if (e_ != hipSuccess) return dev_err(e_); \
+  } while (0)
+#define LP_RET(expr)          \
+  do {                        \
+    int r_ = (expr);          \
+    if (r_ < 0) return r_;    \
+  } while (0)
+
+static const double kPi = 3.14159265358979323846;
+
+// ------------------------------------------------------------- lengths --
+static const int kLengths[] = {
+#define LP_LEN(N, ...) N,
+    LP_LENGTHS(LP_LEN)
+#undef LP_LEN
+};
+
+// Smallest supported transform length >= n, or -1.
+int fft_len(int n) {
+  if (n < 1) return -1;
+  int best = -1;
+  for (int v : kLengths)
+    if (v >= n && (best < 0 || v < best)) best = v;
+  return best;
+}
+
+// Twiddle table of a length's schedule: stage s >= 1 holds W_{Ns R}^{r k}
+// at off_s + (r-1) Ns + k (forward sign), computed in long double.
+static bool make_twiddles(int n, std::vector<long double>& twr, std::vector<long double>& twi) {
+  SchedInfo si;
+  if (!sched_info(n, &si)) return false;
+  twr.clear();
+  twi.clear();
+  long ns = 1;
+  for (int s = 0; s < si.nst; ++s) {
+    const int R = si.rad[s];
+    if (s > 0) {
+      const long span = ns * R;
+      for (int r = 1; r < R; ++r)
+        for (long k = 0; k < ns; ++k) {
+          const long m = (r * k) % span;
+          const long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)span;
+          twr.push_back(cosl(ang));
+          twi.push_back(sinl(ang));
+        }
+    }
+    ns *= R;
+  }
+  if (twr.empty()) {
+    twr.push_back(1.0L);
+    twi.push_back(0.0L);
+  }
+  return true;
+}
+
+// --------------------------------------------------------------- context --
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct PlanEntry {
+  void* tw = nullptr;
+};
+
+struct SpecEntry {
+  void* q[3] = {nullptr, nullptr, nullptr};
+  int Mx = 0, My = 0;
+};
+
+struct ZoomEntry {
+  void* pre = nullptr;
+  void* post = nullptr;
+  void* chat = nullptr;
+};
+
+using SpecKey = std::tuple<int, int, int, int, double, double, double, double, int>;
+using ZoomKey = std::tuple<int, int, int, double, double, double, double, double, double, double, double, double,
+                           int, int, int>;
+
+struct Ctx {
+  std::mutex mu;
+  std::map<std::tuple<int, int, int>, PlanEntry> plans;  // (dev, is_double, n)
+  std::map<SpecKey, SpecEntry> specs;
+  std::map<ZoomKey, ZoomEntry> zooms;
+  std::map<std::pair<int, hipStream_t>, Buf> work;
+  std::map<int, Buf> scratch;  // complex128 setup scratch per device
+};
+
+static Ctx& ctx() {
+  static Ctx* c = new Ctx();
+  return *c;
+}
+
+static int cur_device(int* dev) {
+  LP_TRY(hipGetDevice(dev));
+  return PROP_OK;
+}
+
+static int ensure_buf(Buf& b, size_t bytes, hipStream_t s) {
+  if (b.bytes >= bytes && b.p) return PROP_OK;
+  if (b.p) {
+    LP_TRY(hipStreamSynchronize(s));
+    LP_TRY(hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  size_t want = std::max<size_t>(bytes, 1 << 20);
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    return dev_err(e);
+  }
+  b.bytes = want;
+  return PROP_OK;
+}
+
+template <typename T>
+static int get_tw(int dev, int n, const cx<T>** tw) {
+  Ctx& C = ctx();
+  const auto key = std::make_tuple(dev, (int)sizeof(T), n);
+  auto it = C.plans.find(key);
+  if (it == C.plans.end()) {
+    PlanEntry e;
+    std::vector<long double> wr, wi;
+    if (!make_twiddles(n, wr, wi)) return PROP_ESHAPE;
+    std::vector<cx<T>> h(wr.size());
+    for (size_t i = 0; i < wr.size(); ++i) {
+      h[i].x = (T)wr[i];
+      h[i].y = (T)wi[i];
+    }
+    hipError_t er = hipMalloc(&e.tw, h.size() * sizeof(cx<T>));
+    if (er != hipSuccess) return dev_err(er);
+    LP_TRY(hipMemcpy(e.tw, h.data(), h.size() * sizeof(cx<T>), hipMemcpyHostToDevice));
+    it = C.plans.emplace(key, e).first;
+  }
+  *tw = (const cx<T>*)it->second.tw;
+  return PROP_OK;
+}
+
+// ----------------------------------------------------- RS kernel spectra --
+template <typename T>
+static int get_rs_spectra(int dev, const prop_grid* g, double wl, double z, bool vec, hipStream_t s,
+                          const cx<T>* q[3], int* Mx_out, int* My_out) {
+  Ctx& C = ctx();
+  const int Mx = fft_len(2 * g->nx - 1), My = fft_len(2 * g->ny - 1);
+  *Mx_out = Mx;
+  *My_out = My;
+  const SpecKey key{dev, (int)sizeof(T), g->nx, g->ny, g->dx, g->dy, wl, z, 0};
+  SpecEntry& e = C.specs[key];
+  e.Mx = Mx;
+  e.My = My;
+  const int nk = vec ? 3 : 1;
+  bool need = false;
+  for (int k = 0; k < nk; ++k) need |= (e.q[k] == nullptr);
+  if (need) {
+    const cx<double> *twx, *twy;
+    LP_RET(get_tw<double>(dev, Mx, &twx));
+    LP_RET(get_tw<double>(dev, My, &twy));
+    Buf& sb = C.scratch[dev];
+    LP_RET(ensure_buf(sb, (size_t)Mx * My * sizeof(cx<double>), s));
+    cx<double>* full = (cx<double>*)sb.p;
+    const size_t qbytes = (size_t)(Mx / 2 + 1) * (My / 2 + 1) * sizeof(cx<T>);
+    const double k = 2.0 * kPi / wl;
+    for (int kind = 0; kind < nk; ++kind) {
+      if (e.q[kind]) continue;
+      void* qp = nullptr;
+      hipError_t er = hipMalloc(&qp, qbytes);
+      if (er != hipSuccess) return dev_err(er);
+      LP_TRY(launch_rs_kernel_wrapped(full, Mx, My, g->nx, g->ny, g->dx, g->dy, k, z, kind, s));
+      LP_TRY((launch_fft_lines<double, -1>(Mx, false, full, full, Lines{0, Mx}, Lines{0, Mx}, My, Mx, Mx, 1.0, 1,
+                                           twx, s)));
+      LP_TRY((launch_fft_lines<double, -1>(My, true, full, full, Lines{0, Mx}, Lines{0, Mx}, Mx, My, My, 1.0, 1, twy,
+                                           s)));
+      LP_TRY(launch_extract_quarter<T>(full, (cx<T>*)qp, Mx, My, s));
+      e.q[kind] = qp;
+    }
+    LP_TRY(hipStreamSynchronize(s));
+  }
+  for (int kk = 0; kk < 3; ++kk) q[kk] = (const cx<T>*)e.q[kk];
+  return PROP_OK;
+}
+
+// --------------------------------------------------------- zoom vectors --
+template <typename T>
+static int get_zoom(int dev, const ZoomSpec& zs, hipStream_t s, const cx<T>** pre, const cx<T>** post,
+                    const cx<T>** chat) {
+  Ctx& C = ctx();
+  const ZoomKey key{dev,    (int)sizeof(T), zs.sigma, zs.beta,  zs.x0,   zs.dx,   zs.X0,  zs.dX,
+                    zs.qin, zs.qout,       zs.Kre,   zs.Kim,   zs.n_in, zs.n_out, zs.L};
+  auto it = C.zooms.find(key);
+  if (it == C.zooms.end()) {
+    ZoomEntry e;
+    const cx<double>* twL;
+    LP_RET(get_tw<double>(dev, zs.L, &twL));
+    Buf& sb = C.scratch[dev];
+    LP_RET(ensure_buf(sb, (size_t)zs.L * sizeof(cx<double>), s));
+    cx<double>* chirp = (cx<double>*)sb.p;
+    hipError_t er;
+    if ((er = hipMalloc(&e.pre, (size_t)zs.n_in * sizeof(cx<T>))) != hipSuccess) return dev_err(er);
+    if ((er = hipMalloc(&e.post, (size_t)zs.n_out * sizeof(cx<T>))) != hipSuccess) return dev_err(er);
+    if ((er = hipMalloc(&e.chat, (size_t)zs.L * sizeof(cx<T>))) != hipSuccess) return dev_err(er);
+    LP_TRY(launch_zoom_vectors<T>(zs, (cx<T>*)e.pre, (cx<T>*)e.post, chirp, s));
+    LP_TRY((launch_fft_lines<double, -1>(zs.L, false, chirp, chirp, Lines{0, zs.L}, Lines{0, zs.L}, 1, zs.L, zs.L, 1.0,
+                                         1, twL, s)));
+    LP_TRY(launch_convert<T>(chirp, (cx<T>*)e.chat, zs.L, s));
+    LP_TRY(hipStreamSynchronize(s));
+    it = C.zooms.emplace(key, e).first;
+  }
+  *pre = (const cx<T>*)it->second.pre;
+  *post = (const cx<T>*)it->second.post;
+  *chat = (const cx<T>*)it->second.chat;
+  return PROP_OK;
+}
+
+// ------------------------------------------------------------ validation --
+static bool is_finite(double v) { return std::isfinite(v); }
+
+static int check_grid(const prop_grid* g) {
+  if (!g) return PROP_ENULL;
+  if (g->nx < 1 || g->ny < 1) return PROP_ESHAPE;
+  if (!(g->dx > 0) || !(g->dy > 0) || !is_finite(g->dx) || !is_finite(g->dy) || !is_finite(g->cx) || !is_finite(g->cy))
+    return PROP_EPARAM;
+  return PROP_OK;
+}
+
+static int check_common(prop_dtype t, int32_t batch, double wl) {
+  if (t != PROP_C64 && t != PROP_C128) return PROP_EPARAM;
+  if (batch < 0) return PROP_ESHAPE;
+  if (!(wl > 0) || !is_finite(wl)) return PROP_EPARAM;
+  return PROP_OK;
+}
+
+static size_t esize(prop_dtype t) { return t == PROP_C64 ? 8 : 16; }
+
+static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+// every output must be disjoint from every input and from each other
+static int check_alias(std::initializer_list<std::pair<const void*, size_t>> ins,
+                       std::initializer_list<std::pair<const void*, size_t>> outs) {
+  std::vector<std::pair<const void*, size_t>> o(outs);
+  for (size_t i = 0; i < o.size(); ++i) {
+    for (auto& in : ins)
+      if (overlap(o[i].first, o[i].second, in.first, in.second)) return PROP_EALIAS;
+    for (size_t j = i + 1; j < o.size(); ++j)
+      if (overlap(o[i].first, o[i].second, o[j].first, o[j].second)) return PROP_EALIAS;
+  }
+  return PROP_OK;
+}
+
+static int sampling(const prop_grid* g, double wl, double z) {
+  const int n[2] = {g->nx, g->ny};
+  const double d[2] = {g->dx, g->dy};
+  for (int a = 0; a < 2; ++a) {
+    if (2.0 * d[a] <= wl) continue;
+    const double L = n[a] * d[a];
+    const double zmin = std::sqrt((2.0 * L * d[a] / wl) * (2.0 * L * d[a] / wl) - L * L);
+    if (z < zmin) return PROP_WUNDERSAMPLED;
+  }
+  return PROP_OK;
+}
+
+// ------------------------------------------------------------- RS runs --
+template <typename T>
+static int rs_run(const void* in, void* out, const prop_grid* g, double wl, double z, int batch, hipStream_t s,
+                  bool adjoint) {
+  int dev;
+  LP_RET(cur_device(&dev));
+  const cx<T>* q[3];
+  int Mx, My;
+  LP_RET(get_rs_spectra<T>(dev, g, wl, z, false, s, q, &Mx, &My));
+  const cx<T> *twx, *twy;
+  LP_RET(get_tw<T>(dev, Mx, &twx));
+  LP_RET(get_tw<T>(dev, My, &twy));
+  const int nx = g->nx, ny = g->ny;
+  Buf& wb = ctx().work[{dev, s}];
+  const int64_t plane = (int64_t)ny * Mx;
+  LP_RET(ensure_buf(wb, (size_t)plane * batch * sizeof(cx<T>), s));
+  cx<T>* W = (cx<T>*)wb.p;
+  const T scale = (T)(g->dx * g->dy / ((double)Mx * (double)My));
+  // P1: row transforms of the ny input rows, zero-padded to Mx
+  LP_TRY((launch_fft_lines<T, -1>(Mx, false, (const cx<T>*)in, W, Lines{(int64_t)ny * nx, nx}, Lines{plane, Mx}, ny,
+                                  nx, Mx, T(1), batch, twx, s)));
+  // P2: column transform, kernel-spectrum multiply, inverse, first ny rows
+  LP_TRY(launch_rs_cols<T>(My, W, plane, Mx, Mx, ny, q[0], Mx, adjoint, batch, twy, s));
+  // P3: inverse row transforms, crop to nx, scale dx dy / (Mx My)
+  LP_TRY((launch_fft_lines<T, 1>(Mx, false, W, (cx<T>*)out, Lines{plane, Mx}, Lines{(int64_t)ny * nx, nx}, ny, Mx, nx,
+                                 scale, batch, twx, s)));
+  return PROP_OK;
+}
+
+static int rs_entry(prop_dtype t, const void* in, void* out, const prop_grid* g, double wl, double z, int32_t batch,
+                    void* stream, bool adjoint) {
+  LP_RET(check_common(t, batch, wl));
+  LP_RET(check_grid(g));
+  if (!(z > 0) || !is_finite(z)) return PROP_EPARAM;
+  if (fft_len(2 * g->nx - 1) < 0 || fft_len(2 * g->ny - 1) < 0) return PROP_ESHAPE;
+  const int warn = sampling(g, wl, z);
+  if (batch == 0) return warn;
+  if (!in || !out) return PROP_ENULL;
+  const size_t bytes = (size_t)g->nx * g->ny * batch * esize(t);
+  LP_RET(check_alias({{in, bytes}}, {{out, bytes}}));
+  std::lock_guard<std::mutex> lk(ctx().mu);
+  const hipStream_t s = (hipStream_t)stream;
+  int r = t == PROP_C64 ? rs_run<float>(in, out, g, wl, z, batch, s, adjoint)
+                        : rs_run<double>(in, out, g, wl, z, batch, s, adjoint);
+  return r < 0 ? r : warn;
+}
+
+// ------------------------------------------------------------ VRS runs --
+template <typename T>
+static int vrs_run(const void* const* ins, int nin, void* const* outs, int nout, const prop_grid* g, double wl,
+                   double z, int batch, hipStream_t s, bool adjoint) {
+  int dev;
+  LP_RET(cur_device(&dev));
+  const cx<T>* q[3];
+  int Mx, My;
+  LP_RET(get_rs_spectra<T>(dev, g, wl, z, true, s, q, &Mx, &My));
+  const cx<T> *twx, *twy;
+  LP_RET(get_tw<T>(dev, Mx, &twx));
+  LP_RET(get_tw<T>(dev, My, &twy));
+  const int nx = g->nx, ny = g->ny;
+  const int64_t pst = (int64_t)ny * Mx;
+  const size_t plane = (size_t)pst * batch;
+  Buf& wb = ctx().work[{dev, s}];
+  LP_RET(ensure_buf(wb, 3 * plane * sizeof(cx<T>), s));
+  cx<T>* W[3];
+  for (int i = 0; i < 3; ++i) W[i] = (cx<T>*)wb.p + i * plane;
+  for (int i = 0; i < nin; ++i)
+    LP_TRY((launch_fft_lines<T, -1>(Mx, false, (const cx<T>*)ins[i], W[i], Lines{(int64_t)ny * nx, nx},
+                                    Lines{pst, Mx}, ny, nx, Mx, T(1), batch, twx, s)));
+  if (!adjoint) {
+    // E_z = -(Hx * E_x0 + Hy * E_y0) first (reads W0, W1), then E_x, E_y in place
+    LP_TRY(launch_mix2_cols<T>(My, W[0], W[1], W[2], pst, Mx, Mx, ny, q[1], 1, T(-1), q[2], 2, T(-1), false, Mx, batch,
+                               twy, s));
+    LP_TRY(launch_rs_cols<T>(My, W[0], pst, Mx, Mx, ny, q[0], Mx, false, batch, twy, s));
+    LP_TRY(launch_rs_cols<T>(My, W[1], pst, Mx, Mx, ny, q[0], Mx, false, batch, twy, s));
+  } else {
+    // g_ex = H^H g_x - Hx^H g_z, g_ey = H^H g_y - Hy^H g_z (in place over W0, W1)
+    LP_TRY(launch_mix2_cols<T>(My, W[0], W[2], W[0], pst, Mx, Mx, ny, q[0], 0, T(1), q[1], 1, T(-1), true, Mx, batch,
+                               twy, s));
+    LP_TRY(launch_mix2_cols<T>(My, W[1], W[2], W[1], pst, Mx, Mx, ny, q[0], 0, T(1), q[2], 2, T(-1), true, Mx, batch,
+                               twy, s));
+  }
+  const T scale = (T)(g->dx * g->dy / ((double)Mx * (double)My));
+  const int src[3] = {adjoint ? 0 : 0, 1, 2};
+  for (int i = 0; i < nout; ++i)
+    LP_TRY((launch_fft_lines<T, 1>(Mx, false, W[src[i]], (cx<T>*)outs[i], Lines{pst, Mx}, Lines{(int64_t)ny * nx, nx},
+                                   ny, Mx, nx, scale, batch, twx, s)));
+  return PROP_OK;
+}
+
+// ------------------------------------------------------------ CZT runs --
+static ZoomSpec zoom_spec(int sigma, double beta, int n_in, double x0, double dx, int n_out, double X0, double dX,
+                          double qin, double qout, double Kre, double Kim) {
+  ZoomSpec z;
+  z.sigma = sigma;
+  z.beta = beta;
+  z.x0 = x0;
+  z.dx = dx;
+  z.X0 = X0;
+  z.dX = dX;
+  z.qin = qin;
+  z.qout = qout;
+  z.Kre = Kre;
+  z.Kim = Kim;
+  z.n_in = n_in;
+  z.n_out = n_out;
+  z.L = fft_len(n_in + n_out - 1);
+  return z;
+}
+
+static double first_x(const prop_grid* g) { return g->cx - (double)(g->nx / 2) * g->dx; }
+static double first_y(const prop_grid* g) { return g->cy - (double)(g->ny / 2) * g->dy; }
+
+// Separable zoom transform: rows (x) then columns (y) for "forward" shapes
+// (input grid gi -> output grid go).  zx / zy describe the 1-D transforms.
+template <typename T>
+static int zoom2d_run(int dev, const cx<T>* in, cx<T>* out, int nxi, int nyi, int nxo, int nyo, const ZoomSpec& zx,
+                      const ZoomSpec& zy, int batch, cx<T>* tmp, hipStream_t s, bool cols_first) {
+  const cx<T> *prex, *postx, *chatx, *prey, *posty, *chaty;
+  LP_RET(get_zoom<T>(dev, zx, s, &prex, &postx, &chatx));
+  LP_RET(get_zoom<T>(dev, zy, s, &prey, &posty, &chaty));
+  const cx<T> *twx, *twy;
+  LP_RET(get_tw<T>(dev, zx.L, &twx));
+  LP_RET(get_tw<T>(dev, zy.L, &twy));
+  if (!cols_first) {
+    // rows: [nyi][nxi] -> tmp [nyi][nxo]; cols: tmp -> out [nyo][nxo]
+    LP_TRY(launch_bluestein<T>(zx.L, false, in, tmp, Lines{(int64_t)nyi * nxi, nxi}, Lines{(int64_t)nyi * nxo, nxo},
+                               nyi, nxi, nxo, prex, chatx, postx, batch, twx, s));
+    LP_TRY(launch_bluestein<T>(zy.L, true, tmp, out, Lines{(int64_t)nyi * nxo, nxo}, Lines{(int64_t)nyo * nxo, nxo},
+                               nxo, nyi, nyo, prey, chaty, posty, batch, twy, s));
+  } else {
+    // cols: [nyi][nxi] -> tmp [nyo][nxi]; rows: tmp -> out [nyo][nxo]
+    LP_TRY(launch_bluestein<T>(zy.L, true, in, tmp, Lines{(int64_t)nyi * nxi, nxi}, Lines{(int64_t)nyo * nxi, nxi},
+                               nxi, nyi, nyo, prey, chaty, posty, batch, twy, s));
+    LP_TRY(launch_bluestein<T>(zx.L, false, tmp, out, Lines{(int64_t)nyo * nxi, nxi}, Lines{(int64_t)nyo * nxo, nxo},
+                               nyo, nxi, nxo, prex, chatx, postx, batch, twx, s));
+  }
+  return PROP_OK;
+}
+
+static void czt_specs(const prop_grid* gi, const prop_grid* go, double wl, double z, bool adjoint, ZoomSpec* zx,
+                      ZoomSpec* zy) {
+  const double k = 2.0 * kPi / wl;
+  const double beta = 1.0 / (wl * z);
+  const double a = gi->dx * gi->dy / (wl * z);
+  const double Kre = a * std::sin(k * z), Kim = -a * std::cos(k * z);  // e^{ikz} dx dy / (i lambda z)
+  const double q = k / (2.0 * z);
+  if (!adjoint) {
+    *zx = zoom_spec(-1, beta, gi->nx, first_x(gi), gi->dx, go->nx, first_x(go), go->dx, q, q, 1.0, 0.0);
+    *zy = zoom_spec(-1, beta, gi->ny, first_y(gi), gi->dy, go->ny, first_y(go), go->dy, q, q, Kre, Kim);
+  } else {
+    *zx = zoom_spec(+1, beta, go->nx, first_x(go), go->dx, gi->nx, first_x(gi), gi->dx, -q, -q, 1.0, 0.0);
+    *zy = zoom_spec(+1, beta, go->ny, first_y(go), go->dy, gi->ny, first_y(gi), gi->dy, -q, -q, Kre, -Kim);
+  }
+}
+
+static void rw_specs(const prop_grid* gi, const prop_grid* go, double wl, const prop_lens* lens, bool adjoint,
+                     ZoomSpec* zx, ZoomSpec* zy) {
+  const double k = 2.0 * kPi / wl;
+  const double f = lens->f;
+  const double beta = 1.0 / (wl * f);
+  const double a = k * f / (2.0 * kPi) * gi->dx * gi->dy / (f * f);
+  const double Kre = a * std::sin(k * f), Kim = a * std::cos(k * f);  // i k f e^{-ikf}/(2 pi) dx dy / f^2
+  if (!adjoint) {
+    *zx = zoom_spec(+1, beta, gi->nx, first_x(gi), gi->dx, go->nx, first_x(go), go->dx, 0, 0, 1.0, 0.0);
+    *zy = zoom_spec(+1, beta, gi->ny, first_y(gi), gi->dy, go->ny, first_y(go), go->dy, 0, 0, Kre, Kim);
+  } else {
+    *zx = zoom_spec(-1, beta, go->nx, first_x(go), go->dx, gi->nx, first_x(gi), gi->dx, 0, 0, 1.0, 0.0);
+    *zy = zoom_spec(-1, beta, go->ny, first_y(go), go->dy, gi->ny, first_y(gi), gi->dy, 0, 0, Kre, -Kim);
+  }
+}
+
+static int check_czt_shapes(const prop_grid* gi, const prop_grid* go) {
+  if (fft_len(gi->nx + go->nx - 1) < 0 || fft_len(gi->ny + go->ny - 1) < 0) return PROP_ESHAPE;
+  return PROP_OK;
+}
+
+// scalar CZT with the caller holding the lock; tmp must hold
+// batch * max(nyi*nxo, nyo*nxi) elements
+template <typename T>
+static int czt_core(int dev, const cx<T>* in, cx<T>* out, const prop_grid* gi, const prop_grid* go, double wl,
+                    double z, int batch, cx<T>* tmp, hipStream_t s, bool adjoint) {
+  ZoomSpec zx, zy;
+  czt_specs(gi, go, wl, z, adjoint, &zx, &zy);
+  if (!adjoint) {
+    const bool cols_first = (int64_t)go->ny * gi->nx < (int64_t)gi->ny * go->nx;
+    return zoom2d_run<T>(dev, in, out, gi->nx, gi->ny, go->nx, go->ny, zx, zy, batch, tmp, s, cols_first);
+  }
+  const bool cols_first = (int64_t)gi->ny * go->nx < (int64_t)go->ny * gi->nx;
+  return zoom2d_run<T>(dev, in, out, go->nx, go->ny, gi->nx, gi->ny, zx, zy, batch, tmp, s, cols_first);
+}
+
+static size_t czt_tmp_elems(const prop_grid* gi, const prop_grid* go) {
+  return std::max((size_t)gi->ny * go->nx, (size_t)go->ny * gi->nx);
+}
+
+template <typename T>
+static int czt_run(const void* in, void* out, const prop_grid* gi, const prop_grid* go, double wl, double z, int batch,
+                   hipStream_t s, bool adjoint) {
+  int dev;
+  LP_RET(cur_device(&dev));
+  Buf& wb = ctx().work[{dev, s}];
+  LP_RET(ensure_buf(wb, czt_tmp_elems(gi, go) * batch * sizeof(cx<T>), s));
+  return czt_core<T>(dev, (const cx<T>*)in, (cx<T>*)out, gi, go, wl, z, batch, (cx<T>*)wb.p, s, adjoint);
+}
+
+static int czt_entry(prop_dtype t, const void* in, void* out, const prop_grid* gi, const prop_grid* go, double wl,
+                     double z, int32_t batch, void* stream, bool adjoint) {
+  LP_RET(check_common(t, batch, wl));
+  LP_RET(check_grid(gi));
+  LP_RET(check_grid(go));
+  if (!(z > 0) || !is_finite(z)) return PROP_EPARAM;
+  LP_RET(check_czt_shapes(gi, go));
+  if (batch == 0) return PROP_OK;
+  if (!in || !out) return PROP_ENULL;
+  const size_t bi = (size_t)gi->nx * gi->ny * batch * esize(t), bo = (size_t)go->nx * go->ny * batch * esize(t);
+  if (!adjoint) LP_RET(check_alias({{in, bi}}, {{out, bo}}));
+  else LP_RET(check_alias({{in, bo}}, {{out, bi}}));
+  std::lock_guard<std::mutex> lk(ctx().mu);
+  const hipStream_t s = (hipStream_t)stream;
+  return t == PROP_C64 ? czt_run<float>(in, out, gi, go, wl, z, batch, s, adjoint)
+                       : czt_run<double>(in, out, gi, go, wl, z, batch, s, adjoint);
+}
+
+// ----------------------------------------------------------- VCZT runs --
+template <typename T>
+static int vczt_free_fwd(const void* ex, const void* ey, void* ox, void* oy, void* oz, const prop_grid* gi,
+                         const prop_grid* go, double wl, double z, int batch, hipStream_t s) {
+  int dev;
+  LP_RET(cur_device(&dev));
+  const size_t ni = (size_t)gi->nx * gi->ny * batch, no = (size_t)go->nx * go->ny * batch;
+  const size_t nt = czt_tmp_elems(gi, go) * batch;
+  Buf& wb = ctx().work[{dev, s}];
+  LP_RET(ensure_buf(wb, (ni + no + nt) * sizeof(cx<T>), s));
+  cx<T>* prep = (cx<T>*)wb.p;
+  cx<T>* c2 = prep + ni;
+  cx<T>* tmp = c2 + no;
+  LP_TRY(launch_vczt_prep<T>((const cx<T>*)ex, (const cx<T>*)ey, prep, gi->nx, gi->ny, gi->dx, gi->dy, gi->cx, gi->cy,
+                             batch, s));
+  LP_RET(czt_core<T>(dev, (const cx<T>*)ex, (cx<T>*)ox, gi, go, wl, z, batch, tmp, s, false));
+  LP_RET(czt_core<T>(dev, (const cx<T>*)ey, (cx<T>*)oy, gi, go, wl, z, batch, tmp, s, false));
+  LP_RET(czt_core<T>(dev, prep, c2, gi, go, wl, z, batch, tmp, s, false));
+  LP_TRY(launch_vczt_combine<T>((const cx<T>*)ox, (const cx<T>*)oy, c2, (cx<T>*)oz, go->nx, go->ny, go->dx, go->dy,
+                                go->cx, go->cy, z, batch, s));
+  return PROP_OK;
+}
+
+template <typename T>
+static int vczt_free_adj(const void* gx, const void* gy, const void* gz, void* gex, void* gey, const prop_grid* gi,
+                         const prop_grid* go, double wl, double z, int batch, hipStream_t s) {
+  int dev;
+  LP_RET(cur_device(&dev));
+  const size_t ni = (size_t)gi->nx * gi->ny * batch, no = (size_t)go->nx * go->ny * batch;
+  const size_t nt = czt_tmp_elems(gi, go) * batch;
+  Buf& wb = ctx().work[{dev, s}];
+  LP_RET(ensure_buf(wb, (2 * no + 3 * ni + nt) * sizeof(cx<T>), s));
+  cx<T>* xg = (cx<T>*)wb.p;
+  cx<T>* yg = xg + no;
+  cx<T>* a2 = yg + no;
+  cx<T>* a3 = a2 + ni;
+  cx<T>* a4 = a3 + ni;
+  cx<T>* tmp = a4 + ni;
+  LP_TRY(launch_vczt_adj_prep<T>((const cx<T>*)gz, xg, yg, go->nx, go->ny, go->dx, go->dy, go->cx, go->cy, z, batch,
+                                 s));
+  LP_RET(czt_core<T>(dev, (const cx<T>*)gx, (cx<T>*)gex, gi, go, wl, z, batch, tmp, s, true));
+  LP_RET(czt_core<T>(dev, (const cx<T>*)gy, (cx<T>*)gey, gi, go, wl, z, batch, tmp, s, true));
+  LP_RET(czt_core<T>(dev, xg, a2, gi, go, wl, z, batch, tmp, s, true));
+  LP_RET(czt_core<T>(dev, yg, a3, gi, go, wl, z, batch, tmp, s, true));
+  LP_RET(czt_core<T>(dev, (const cx<T>*)gz, a4, gi, go, wl, z, batch, tmp, s, true));
+  LP_TRY(launch_vczt_adj_combine<T>((cx<T>*)gex, (cx<T>*)gey, a2, a3, a4, gi->nx, gi->ny, gi->dx, gi->dy, gi->cx,
+                                    gi->cy, z, batch, s));
+  return PROP_OK;
+}
+
+template <typename T>
+static int rw_fwd(const void* ex, const void* ey, void* const* outs, const prop_grid* gi, const prop_grid* go,
+                  double wl, const prop_lens* lens, int batch, hipStream_t s) {
+  int dev;
+  LP_RET(cur_device(&dev));
+  const size_t ni = (size_t)gi->nx * gi->ny * batch;
+  const size_t nm = (size_t)gi->ny * go->nx * batch;
+  Buf& wb = ctx().work[{dev, s}];
+  LP_RET(ensure_buf(wb, 3 * (ni + nm) * sizeof(cx<T>), s));
+  cx<T>* P = (cx<T>*)wb.p;
+  cx<T>* M = P + 3 * ni;
+  LP_TRY(launch_pupil<T>((const cx<T>*)ex, (const cx<T>*)ey, P, P + ni, P + 2 * ni, gi->nx, gi->ny, gi->dx, gi->dy,
+                         gi->cx, gi->cy, lens->f, lens->na, batch, (int64_t)gi->nx * gi->ny, false, s));
+  ZoomSpec zx, zy;
+  rw_specs(gi, go, wl, lens, false, &zx, &zy);
+  const cx<T> *prex, *postx, *chatx, *prey, *posty, *chaty;
+  LP_RET(get_zoom<T>(dev, zx, s, &prex, &postx, &chatx));
+  LP_RET(get_zoom<T>(dev, zy, s, &prey, &posty, &chaty));
+  const cx<T> *twx, *twy;
+  LP_RET(get_tw<T>(dev, zx.L, &twx));
+  LP_RET(get_tw<T>(dev, zy.L, &twy));
+  const int nxi = gi->nx, nyi = gi->ny, nxo = go->nx, nyo = go->ny;
+  LP_TRY(launch_bluestein<T>(zx.L, false, P, M, Lines{(int64_t)nyi * nxi, nxi}, Lines{(int64_t)nyi * nxo, nxo}, nyi,
+                             nxi, nxo, prex, chatx, postx, 3 * batch, twx, s));
+  for (int c = 0; c < 3; ++c)
+    LP_TRY(launch_bluestein<T>(zy.L, true, M + c * nm, (cx<T>*)outs[c], Lines{(int64_t)nyi * nxo, nxo},
+                               Lines{(int64_t)nyo * nxo, nxo}, nxo, nyi, nyo, prey, chaty, posty, batch, twy, s));
+  return PROP_OK;
+}
+
+template <typename T>
+static int rw_adj(const void* const* gs, void* gex, void* gey, const prop_grid* gi, const prop_grid* go, double wl,
+                  const prop_lens* lens, int batch, hipStream_t s) {
+  int dev;
+  LP_RET(cur_device(&dev));
+  const size_t ni = (size_t)gi->nx * gi->ny * batch;
+  const size_t nm = (size_t)gi->ny * go->nx * batch;
+  Buf& wb = ctx().work[{dev, s}];
+  LP_RET(ensure_buf(wb, 3 * (ni + nm) * sizeof(cx<T>), s));
+  cx<T>* P = (cx<T>*)wb.p;
+  cx<T>* M = P + 3 * ni;
+  ZoomSpec zx, zy;
+  rw_specs(gi, go, wl, lens, true, &zx, &zy);
+  const cx<T> *prex, *postx, *chatx, *prey, *posty, *chaty;
+  LP_RET(get_zoom<T>(dev, zx, s, &prex, &postx, &chatx));
+  LP_RET(get_zoom<T>(dev, zy, s, &prey, &posty, &chaty));
+  const cx<T> *twx, *twy;
+  LP_RET(get_tw<T>(dev, zx.L, &twx));
+  LP_RET(get_tw<T>(dev, zy.L, &twy));
+  const int nxi = gi->nx, nyi = gi->ny, nxo = go->nx, nyo = go->ny;
+  for (int c = 0; c < 3; ++c)
+    LP_TRY(launch_bluestein<T>(zy.L, true, (const cx<T>*)gs[c], M + c * nm, Lines{(int64_t)nyo * nxo, nxo},
+                               Lines{(int64_t)nyi * nxo, nxo}, nxo, nyo, nyi, prey, chaty, posty, batch, twy, s));
+  LP_TRY(launch_bluestein<T>(zx.L, false, M, P, Lines{(int64_t)nyi * nxo, nxo}, Lines{(int64_t)nyi * nxi, nxi}, nyi,
+                             nxo, nxi, prex, chatx, postx, 3 * batch, twx, s));
+  LP_TRY(launch_pupil<T>((const cx<T>*)gex, (const cx<T>*)gey, P, P + ni, P + 2 * ni, gi->nx, gi->ny, gi->dx, gi->dy,
+                         gi->cx, gi->cy, lens->f, lens->na, batch, (int64_t)gi->nx * gi->ny, true, s));
+  return PROP_OK;
+}
+
+static int check_lens(const prop_lens* lens) {
+  if (!lens) return PROP_OK;
+  if (!(lens->na > 0) || !(lens->na < 1) || !(lens->f > 0) || !is_finite(lens->f)) return PROP_EPARAM;
+  return PROP_OK;
+}
+
+// ---------------------------------------------------------- elementwise --
+static double jones_cs(double theta, double* c, double* s) {
+  *c = std::cos(theta);
+  *s = std::sin(theta);
+  return 0;
+}
+
+static void jones(double eta, double theta, double J[8]) {
+  double c, s;
+  jones_cs(theta, &c, &s);
+  const double er = std::cos(eta), ei = std::sin(eta);
+  // [[c^2 + e s^2, cs(1-e)], [cs(1-e), s^2 + e c^2]]
+  J[0] = c * c + er * s * s; J[1] = ei * s * s;
+  J[2] = c * s * (1 - er);   J[3] = -c * s * ei;
+  J[4] = J[2];               J[5] = J[3];
+  J[6] = s * s + er * c * c; J[7] = ei * c * c;
+}
+
+static void conj_transpose(const double J[8], double H[8]) {
+  H[0] = J[0]; H[1] = -J[1];
+  H[2] = J[4]; H[3] = -J[5];
+  H[4] = J[2]; H[5] = -J[3];
+  H[6] = J[6]; H[7] = -J[7];
+}
+
+static void jones_derivs(double eta, double theta, double d[16]) {
+  double c, s;
+  jones_cs(theta, &c, &s);
+  const double er = std::cos(eta), ei = std::sin(eta);
+  // dJ/deta = i e [[s^2, -cs], [-cs, c^2]],  i e = (-ei, er)
+  const double ar = -ei, ai = er;
+  const double m[4] = {s * s, -c * s, -c * s, c * c};
+  for (int k = 0; k < 4; ++k) { d[2 * k] = ar * m[k]; d[2 * k + 1] = ai * m[k]; }
+  // dJ/dtheta = (1 - e) [[-sin2t, cos2t], [cos2t, sin2t]]
+  const double br = 1 - er, bi = -ei;
+  const double s2 = std::sin(2 * theta), c2 = std::cos(2 * theta);
+  const double n[4] = {-s2, c2, c2, s2};
+  for (int k = 0; k < 4; ++k) { d[8 + 2 * k] = br * n[k]; d[8 + 2 * k + 1] = bi * n[k]; }
+}
+
+}  // namespace lp
+
+using namespace lp;
+
+// =================================================================== ABI ==
+extern "C" {
+
+int rs_propagate(prop_dtype t, const void* u_in, void* u_out, const prop_grid* g, double wavelength, double z,
+                 int32_t batch, void* stream) {
+  return rs_entry(t, u_in, u_out, g, wavelength, z, batch, stream, false);
+}
+
+int rs_adjoint(prop_dtype t, const void* g_out, void* g_in, const prop_grid* g, double wavelength, double z,
+               int32_t batch, void* stream) {
+  return rs_entry(t, g_out, g_in, g, wavelength, z, batch, stream, true);
+}
+
+int czt_propagate(prop_dtype t, const void* u_in, void* u_out, const prop_grid* g_in, const prop_grid* win,
+                  double wavelength, double z, int32_t batch, void* stream) {
+  return czt_entry(t, u_in, u_out, g_in, win, wavelength, z, batch, stream, false);
+}
+
+int czt_adjoint(prop_dtype t, const void* g_out, void* g_in, const prop_grid* g_in_grid, const prop_grid* win,
+                double wavelength, double z, int32_t batch, void* stream) {
+  return czt_entry(t, g_out, g_in, g_in_grid, win, wavelength, z, batch, stream, true);
+}
+
+int vrs_propagate(prop_dtype t, const void* ex, const void* ey, void* ox, void* oy, void* oz, const prop_grid* g,
+                  double wavelength, double z, int32_t batch, void* stream) {
+  LP_RET(check_common(t, batch, wavelength));
+  LP_RET(check_grid(g));
+  if (!(z > 0) || !is_finite(z)) return PROP_EPARAM;
+  if (fft_len(2 * g->nx - 1) < 0 || fft_len(2 * g->ny - 1) < 0) return PROP_ESHAPE;
+  const int warn = sampling(g, wavelength, z);
+  if (batch == 0) return warn;
+  if (!ex || !ey || !ox || !oy || !oz) return PROP_ENULL;
+  const size_t b = (size_t)g->nx * g->ny * batch * esize(t);
+  LP_RET(check_alias({{ex, b}, {ey, b}}, {{ox, b}, {oy, b}, {oz, b}}));
+  std::lock_guard<std::mutex> lk(ctx().mu);
+  const void* ins[2] = {ex, ey};
+  void* outs[3] = {ox, oy, oz};
+  const hipStream_t s = (hipStream_t)stream;
+  int r = t == PROP_C64 ? vrs_run<float>(ins, 2, outs, 3, g, wavelength, z, batch, s, false)
+                        : vrs_run<double>(ins, 2, outs, 3, g, wavelength, z, batch, s, false);
+  return r < 0 ? r : warn;
+}
+
+int vrs_adjoint(prop_dtype t, const void* gx, const void* gy, const void* gz, void* gex, void* gey, const prop_grid* g,
+                double wavelength, double z, int32_t batch, void* stream) {
+  LP_RET(check_common(t, batch, wavelength));
+  LP_RET(check_grid(g));
+  if (!(z > 0) || !is_finite(z)) return PROP_EPARAM;
+  if (fft_len(2 * g->nx - 1) < 0 || fft_len(2 * g->ny - 1) < 0) return PROP_ESHAPE;
+  const int warn = sampling(g, wavelength, z);
+  if (batch == 0) return warn;
+  if (!gx || !gy || !gz || !gex || !gey) return PROP_ENULL;
+  const size_t b = (size_t)g->nx * g->ny * batch * esize(t);
+  LP_RET(check_alias({{gx, b}, {gy, b}, {gz, b}}, {{gex, b}, {gey, b}}));
+  std::lock_guard<std::mutex> lk(ctx().mu);
+  const void* ins[3] = {gx, gy, gz};
+  void* outs[2] = {gex, gey};
+  const hipStream_t s = (hipStream_t)stream;
+  int r = t == PROP_C64 ? vrs_run<float>(ins, 3, outs, 2, g, wavelength, z, batch, s, true)
+                        : vrs_run<double>(ins, 3, outs, 2, g, wavelength, z, batch, s, true);
+  return r < 0 ? r : warn;
+}
+
+int vczt_propagate(prop_dtype t, const void* ex, const void* ey, void* ox, void* oy, void* oz, const prop_grid* g_in,
+                   const prop_grid* win, double wavelength, double z, const prop_lens* lens, int32_t batch,
+                   void* stream) {
+  LP_RET(check_common(t, batch, wavelength));
+  LP_RET(check_grid(g_in));
+  LP_RET(check_grid(win));
+  LP_RET(check_lens(lens));
+  if (!lens && (!(z > 0) || !is_finite(z))) return PROP_EPARAM;
+  if (lens && !is_finite(z)) return PROP_EPARAM;
+  LP_RET(check_czt_shapes(g_in, win));
+  if (batch == 0) return PROP_OK;
+  if (!ex || !ey || !ox || !oy || !oz) return PROP_ENULL;
+  const size_t bi = (size_t)g_in->nx * g_in->ny * batch * esize(t), bo = (size_t)win->nx * win->ny * batch * esize(t);
+  LP_RET(check_alias({{ex, bi}, {ey, bi}}, {{ox, bo}, {oy, bo}, {oz, bo}}));
+  std::lock_guard<std::mutex> lk(ctx().mu);
+  const hipStream_t s = (hipStream_t)stream;
+  void* outs[3] = {ox, oy, oz};
+  if (lens)
+    return t == PROP_C64 ? rw_fwd<float>(ex, ey, outs, g_in, win, wavelength, lens, batch, s)
+                         : rw_fwd<double>(ex, ey, outs, g_in, win, wavelength, lens, batch, s);
+  return t == PROP_C64 ? vczt_free_fwd<float>(ex, ey, ox, oy, oz, g_in, win, wavelength, z, batch, s)
+                       : vczt_free_fwd<double>(ex, ey, ox, oy, oz, g_in, win, wavelength, z, batch, s);
+}
+
+int vczt_adjoint(prop_dtype t, const void* gx, const void* gy, const void* gz, void* gex, void* gey,
+                 const prop_grid* g_in, const prop_grid* win, double wavelength, double z, const prop_lens* lens,
+                 int32_t batch, void* stream) {
+  LP_RET(check_common(t, batch, wavelength));
+  LP_RET(check_grid(g_in));
+  LP_RET(check_grid(win));
+  LP_RET(check_lens(lens));
+  if (!lens && (!(z > 0) || !is_finite(z))) return PROP_EPARAM;
+  if (lens && !is_finite(z)) return PROP_EPARAM;
+  LP_RET(check_czt_shapes(g_in, win));
+  if (batch == 0) return PROP_OK;
+  if (!gx || !gy || !gz || !gex || !gey) return PROP_ENULL;
+  const size_t bi = (size_t)g_in->nx * g_in->ny * batch * esize(t), bo = (size_t)win->nx * win->ny * batch * esize(t);
+  LP_RET(check_alias({{gx, bo}, {gy, bo}, {gz, bo}}, {{gex, bi}, {gey, bi}}));
+  std::lock_guard<std::mutex> lk(ctx().mu);
+  const hipStream_t s = (hipStream_t)stream;
+  if (lens) {
+    const void* gs[3] = {gx, gy, gz};
+    return t == PROP_C64 ? rw_adj<float>(gs, gex, gey, g_in, win, wavelength, lens, batch, s)
+                         : rw_adj<double>(gs, gex, gey, g_in, win, wavelength, lens, batch, s);
+  }
+  return t == PROP_C64 ? vczt_free_adj<float>(gx, gy, gz, gex, gey, g_in, win, wavelength, z, batch, s)
+                       : vczt_free_adj<double>(gx, gy, gz, gex, gey, g_in, win, wavelength, z, batch, s);
+}
+
+int prop_source_gaussian(prop_dtype t, void* out, const prop_grid* g, double w0, double amplitude, double lens_f,
+                         double wavelength, int32_t batch, void* stream) {
+  LP_RET(check_common(t, batch, wavelength));
+  LP_RET(check_grid(g));
+  if (!(w0 > 0) || !is_finite(w0) || !is_finite(amplitude) || !is_finite(lens_f) || lens_f < 0) return PROP_EPARAM;
+  if (batch == 0) return PROP_OK;
+  if (!out) return PROP_ENULL;
+  const double k = 2.0 * kPi / wavelength;
+  const hipStream_t s = (hipStream_t)stream;
+  hipError_t e = t == PROP_C64 ? launch_source_gaussian<float>((cx<float>*)out, g->nx, g->ny, g->dx, g->dy, g->cx,
+                                                               g->cy, w0, amplitude, lens_f, k, batch, s)
+                               : launch_source_gaussian<double>((cx<double>*)out, g->nx, g->ny, g->dx, g->dy, g->cx,
+                                                                g->cy, w0, amplitude, lens_f, k, batch, s);
+  return e == hipSuccess ? PROP_OK : dev_err(e);
+}
+
+int prop_source_radial(prop_dtype t, void* ex, void* ey, const prop_grid* g, double w0, int32_t batch, void* stream) {
+  LP_RET(check_common(t, batch, 1.0));
+  LP_RET(check_grid(g));
+  if (!(w0 > 0) || !is_finite(w0)) return PROP_EPARAM;
+  if (batch == 0) return PROP_OK;
+  if (!ex || !ey) return PROP_ENULL;
+  const size_t b = (size_t)g->nx * g->ny * batch * esize(t);
+  LP_RET(check_alias({}, {{ex, b}, {ey, b}}));
+  const hipStream_t s = (hipStream_t)stream;
+  hipError_t e = t == PROP_C64 ? launch_source_radial<float>((cx<float>*)ex, (cx<float>*)ey, g->nx, g->ny, g->dx,
+                                                             g->dy, g->cx, g->cy, w0, batch, s)
+                               : launch_source_radial<double>((cx<double>*)ex, (cx<double>*)ey, g->nx, g->ny, g->dx,
+                                                              g->dy, g->cx, g->cy, w0, batch, s);
+  return e == hipSuccess ? PROP_OK : dev_err(e);
+}
+
+int prop_modulate(prop_dtype t, const void* u_in, const void* phase, void* u_out, int64_t npix, int32_t batch,
+                  int32_t phase_batch, void* stream) {
+  if (t != PROP_C64 && t != PROP_C128) return PROP_EPARAM;
+  if (npix < 0 || batch < 0) return PROP_ESHAPE;
+  if (phase_batch != 1 && phase_batch != batch) return PROP_ESHAPE;
+  if (npix == 0 || batch == 0) return PROP_OK;
+  if (!u_in || !phase || !u_out) return PROP_ENULL;
+  // in place (u_out == u_in) is allowed: elementwise
+  const size_t b = (size_t)npix * batch * esize(t);
+  if (u_out != u_in) LP_RET(check_alias({{u_in, b}}, {{u_out, b}}));
+  LP_RET(check_alias({{phase, (size_t)npix * phase_batch * esize(t) / 2}}, {{u_out, b}}));
+  const int64_t pbs = phase_batch == 1 ? 0 : npix;
+  const hipStream_t s = (hipStream_t)stream;
+  hipError_t e = t == PROP_C64 ? launch_modulate<float>((const cx<float>*)u_in, (const float*)phase,
+                                                        (cx<float>*)u_out, npix, batch, pbs, s)
+                               : launch_modulate<double>((const cx<double>*)u_in, (const double*)phase,
+                                                         (cx<double>*)u_out, npix, batch, pbs, s);
+  return e == hipSuccess ? PROP_OK : dev_err(e);
+}
+
+int prop_phase_grad(prop_dtype t, const void* g_u, const void* u, void* grad, int64_t npix, int32_t batch,
+                    int32_t accumulate, void* stream) {
+  if (t != PROP_C64 && t != PROP_C128) return PROP_EPARAM;
+  if (npix < 0 || batch < 0) return PROP_ESHAPE;
+  if (npix == 0 || batch == 0) return PROP_OK;
+  if (!g_u || !u || !grad) return PROP_ENULL;
+  const size_t b = (size_t)npix * batch * esize(t);
+  LP_RET(check_alias({{g_u, b}, {u, b}}, {{grad, b / 2}}));
+  const hipStream_t s = (hipStream_t)stream;
+  hipError_t e = t == PROP_C64 ? launch_phase_grad<float>((const cx<float>*)g_u, (const cx<float>*)u, (float*)grad,
+                                                          npix, batch, accumulate, s)
+                               : launch_phase_grad<double>((const cx<double>*)g_u, (const cx<double>*)u,
+                                                           (double*)grad, npix, batch, accumulate, s);
+  return e == hipSuccess ? PROP_OK : dev_err(e);
+}
+
+int prop_waveplate(prop_dtype t, const void* ex, const void* ey, void* ox, void* oy, double eta, double theta,
+                   int64_t npix, int32_t batch, void* stream) {
+  if (t != PROP_C64 && t != PROP_C128) return PROP_EPARAM;
+  if (!is_finite(eta) || !is_finite(theta)) return PROP_EPARAM;
+  if (npix < 0 || batch < 0) return PROP_ESHAPE;
+  if (npix == 0 || batch == 0) return PROP_OK;
+  if (!ex || !ey || !ox || !oy) return PROP_ENULL;
+  const size_t b = (size_t)npix * batch * esize(t);
+  LP_RET(check_alias({{ex, b}, {ey, b}}, {{ox, b}, {oy, b}}));
+  double J[8];
+  jones(eta, theta, J);
+  const hipStream_t s = (hipStream_t)stream;
+  hipError_t e = t == PROP_C64 ? launch_jones<float>((const cx<float>*)ex, (const cx<float>*)ey, (cx<float>*)ox,
+                                                     (cx<float>*)oy, J, npix, batch, s)
+                               : launch_jones<double>((const cx<double>*)ex, (const cx<double>*)ey, (cx<double>*)ox,
+                                                      (cx<double>*)oy, J, npix, batch, s);
+  return e == hipSuccess ? PROP_OK : dev_err(e);
+}
+
+int prop_waveplate_adjoint(prop_dtype t, const void* gx, const void* gy, const void* ex, const void* ey, void* gex,
+                           void* gey, double eta, double theta, double* dparams, int64_t npix, int32_t batch,
+                           void* stream) {
+  if (t != PROP_C64 && t != PROP_C128) return PROP_EPARAM;
+  if (!is_finite(eta) || !is_finite(theta)) return PROP_EPARAM;
+  if (npix < 0 || batch < 0) return PROP_ESHAPE;
+  if (npix == 0 || batch == 0) return PROP_OK;
+  if (!gx || !gy || !ex || !ey || !gex || !gey || !dparams) return PROP_ENULL;
+  const size_t b = (size_t)npix * batch * esize(t);
+  LP_RET(check_alias({{gx, b}, {gy, b}, {ex, b}, {ey, b}}, {{gex, b}, {gey, b}, {dparams, 16 * (size_t)batch}}));
+  double J[8], H[8], d[16];
+  jones(eta, theta, J);
+  conj_transpose(J, H);
+  jones_derivs(eta, theta, d);
+  std::lock_guard<std::mutex> lk(ctx().mu);
+  int dev;
+  LP_RET(cur_device(&dev));
+  const hipStream_t s = (hipStream_t)stream;
+  const int nblk = 256;
+  Buf& wb = ctx().work[{dev, s}];
+  LP_RET(ensure_buf(wb, (size_t)nblk * batch * 2 * sizeof(double), s));
+  hipError_t e;
+  if (t == PROP_C64) {
+    e = launch_jones<float>((const cx<float>*)gx, (const cx<float>*)gy, (cx<float>*)gex, (cx<float>*)gey, H, npix,
+                            batch, s);
+    if (e == hipSuccess)
+      e = launch_jones_grad<float>((const cx<float>*)gx, (const cx<float>*)gy, (const cx<float>*)ex,
+                                   (const cx<float>*)ey, d, dparams, (double*)wb.p, nblk, npix, batch, s);
+  } else {
+    e = launch_jones<double>((const cx<double>*)gx, (const cx<double>*)gy, (cx<double>*)gex, (cx<double>*)gey, H,
+                             npix, batch, s);
+    if (e == hipSuccess)
+      e = launch_jones_grad<double>((const cx<double>*)gx, (const cx<double>*)gy, (const cx<double>*)ex,
+                                    (const cx<double>*)ey, d, dparams, (double*)wb.p, nblk, npix, batch, s);
+  }
+  return e == hipSuccess ? PROP_OK : dev_err(e);
+}
+
+int prop_spot_loss(prop_dtype t, const void* ex, const void* ey, const void* ez, const prop_grid* win,
+                   double wavelength, double w_fz, double* result, void* gx, void* gy, void* gz, int32_t batch,
+                   void* stream) {
+  LP_RET(check_common(t, batch, wavelength));
+  LP_RET(check_grid(win));
+  if (!is_finite(w_fz)) return PROP_EPARAM;
+  if (batch == 0) return PROP_OK;
+  if (!ex || !ey || !result) return PROP_ENULL;
+  if ((gx == nullptr) != (gy == nullptr)) return PROP_ENULL;
+  const size_t b = (size_t)win->nx * win->ny * batch * esize(t);
+  if (gx) {
+    if (ez && gz) LP_RET(check_alias({{ex, b}, {ey, b}, {ez, b}}, {{gx, b}, {gy, b}, {gz, b}, {result, 64 * (size_t)batch}}));
+    else LP_RET(check_alias({{ex, b}, {ey, b}}, {{gx, b}, {gy, b}, {result, 64 * (size_t)batch}}));
+  }
+  std::lock_guard<std::mutex> lk(ctx().mu);
+  int dev;
+  LP_RET(cur_device(&dev));
+  const hipStream_t s = (hipStream_t)stream;
+  const int nblk = 256;
+  Buf& wb = ctx().work[{dev, s}];
+  LP_RET(ensure_buf(wb, (size_t)nblk * batch * 5 * sizeof(double), s));
+  hipError_t e = t == PROP_C64
+                     ? launch_spot_loss<float>((const cx<float>*)ex, (const cx<float>*)ey, (const cx<float>*)ez,
+                                               win->nx, win->ny, win->dx, win->dy, win->cx, win->cy, wavelength, w_fz,
+                                               result, (double*)wb.p, nblk, (cx<float>*)gx, (cx<float>*)gy,
+                                               (cx<float>*)gz, batch, s)
+                     : launch_spot_loss<double>((const cx<double>*)ex, (const cx<double>*)ey, (const cx<double>*)ez,
+                                                win->nx, win->ny, win->dx, win->dy, win->cx, win->cy, wavelength,
+                                                w_fz, result, (double*)wb.p, nblk, (cx<double>*)gx, (cx<double>*)gy,
+                                                (cx<double>*)gz, batch, s);
+  return e == hipSuccess ? PROP_OK : dev_err(e);
+}
+
+int prop_sampling_check(const prop_grid* g, double wavelength, double z) {
+  LP_RET(check_grid(g));
+  if (!(wavelength > 0) || !is_finite(wavelength) || !(z > 0) || !is_finite(z)) return PROP_EPARAM;
+  return sampling(g, wavelength, z);
+}
+
+int32_t prop_fft_length(int32_t n) { return fft_len(n); }
+
+void prop_cache_clear(void) {
+  Ctx& C = ctx();
+  std::lock_guard<std::mutex> lk(C.mu);
+  (void)hipDeviceSynchronize();
+  for (auto& kv : C.plans) (void)hipFree(kv.second.tw);
+  for (auto& kv : C.specs)
+    for (int k = 0; k < 3; ++k)
+      if (kv.second.q[k]) (void)hipFree(kv.second.q[k]);
+  for (auto& kv : C.zooms) {
+    (void)hipFree(kv.second.pre);
+    (void)hipFree(kv.second.post);
+    (void)hipFree(kv.second.chat);
+  }
+  for (auto& kv : C.work) (void)hipFree(kv.second.p);
+  for (auto& kv : C.scratch) (void)hipFree(kv.second.p);
+  C.plans.clear();
+  C.specs.clear();
+  C.zooms.clear();
+  C.work.clear();
+  C.scratch.clear();
+}
+
+const char* prop_status_string(int status) {
+  switch (status) {
+    case PROP_OK: return "ok";
+    case PROP_WUNDERSAMPLED: return "warning: propagation kernel under-sampled at the largest offset";
+    case PROP_ENULL: return "error: null pointer";
+    case PROP_ESHAPE: return "error: unsupported shape (size < 1, negative batch or transform length > 8192)";
+    case PROP_EPARAM: return "error: invalid parameter (dtype, wavelength, distance, pitch, NA, focal length)";
+    case PROP_EALIAS: return "error: output overlaps an input";
+    case PROP_ENOMEM: return "error: device allocation failed";
+    case PROP_EDEVICE: return "error: HIP call failed (see prop_last_device_error)";
+    default: return "unknown status";
+  }
+}
+
+int prop_last_device_error(void) { return g_last_hip; }
+
+}  // extern "C"
