@@ -1,0 +1,230 @@
+#!/usr/bin/env python
+"""Throughput of the propagation gradient hot path on one MI355X.
+
+Workload: 2048^2 complex64 fields on a 4 mm grid at 650 nm (Gaussian beam
+w0 = 1 mm, thin lens f = 25 mm, smoothed random phase mask), RS over 25 mm on
+a 4096^2 padded transform and CZT to the focal plane onto a 2048^2 window of
+40 um.  One step, for a batch of B fields resident in HBM:
+
+    U = V exp(i phi)                       (SLM)
+    Y = RS(U),  G = RS^H(Y),  g_phi += Im(G conj U)     (grad of |Y|^2 / 2)
+    Y = CZT(U), G = CZT^H(Y), g_phi += Im(G conj U)
+
+i.e. 2 B gradients (one forward + one adjoint of one propagator on one
+field each).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "2048² RS/CZT fwd+adjoint grads/sec, batched FP32 vs plain FP64; HBM BW %"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def inputs(lp, torch, batch, dtype):
+    import numpy as np
+
+    import workloads
+    w = workloads.rs_czt_2048(0)
+    rdt = torch.float32 if dtype == torch.complex64 else torch.float64
+    phases = [w["phase"]] + [workloads.rs_czt_2048(s)["phase"] for s in range(1, batch)]
+    phi = torch.from_numpy(np.stack(phases)).to(rdt).cuda()
+    v = lp.prop_source_gaussian(w["grid"], w["w0"], w["wavelength"], lens_f=w["f"], batch=batch, dtype=dtype)
+    return w, v, phi
+
+
+class Step:
+    """Preallocated buffers and the pass sequence of one gradient step."""
+
+    def __init__(self, lp, torch, w, v, phi):
+        self.lp, self.w, self.v, self.phi = lp, w, v, phi
+        self.u = torch.empty_like(v)
+        self.y = torch.empty_like(v)
+        self.g = torch.empty_like(v)
+        self.grad = torch.empty(v.shape, dtype=phi.dtype, device=v.device)
+
+    def __call__(self):
+        lp, w = self.lp, self.w
+        g, win, wl = w["grid"], w["window"], w["wavelength"]
+        lp.prop_modulate(self.v, self.phi, out=self.u)
+        lp.rs_propagate(self.u, g, wl, w["z_rs"], out=self.y)
+        lp.rs_adjoint(self.y, g, wl, w["z_rs"], out=self.g)
+        lp.prop_phase_grad(self.g, self.u, grad=self.grad)
+        lp.czt_propagate(self.u, g, win, wl, w["z_czt"], out=self.y)
+        lp.czt_adjoint(self.y, g, win, wl, w["z_czt"], out=self.g)
+        lp.prop_phase_grad(self.g, self.u, grad=self.grad, accumulate=True)
+
+
+def time_steps(torch, step, steps, warmup):
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    gpu = ev0.elapsed_time(ev1) / 1e3 / steps
+    return wall, gpu
+
+
+def rel(a, b):
+    import torch
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
+def cpu_baseline():
+    """The FP64 oracle on one 2048^2 field: RS fwd+adj and CZT fwd+adj."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    import oracle
+    import workloads
+    w = workloads.rs_czt_2048(0)
+    g, win, wl = w["grid"], w["window"], w["wavelength"]
+    u = oracle.modulate(oracle.gaussian_beam(g, w["w0"], f=w["f"], wavelength=wl), w["phase"])
+    t0 = time.perf_counter()
+    y = oracle.rs_propagate(u, g, wl, w["z_rs"])
+    gr = oracle.rs_adjoint(y, g, wl, w["z_rs"])
+    grad = oracle.phase_grad(gr, u)
+    yc = oracle.czt_propagate(u, g, win, wl, w["z_czt"])
+    gc = oracle.czt_adjoint(yc, g, win, wl, w["z_czt"])
+    grad = grad + oracle.phase_grad(gc, u)
+    dt = time.perf_counter() - t0
+    threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    return {"value": 2.0 / dt, "unit": "grads/s", "cores": int(threads), "kind": "oracle",
+            "sample": "one 2048^2 field: RS fwd+adj and CZT fwd+adj with the SLM phase gradient, FP64 "
+                      f"(numpy/scipy; {dt:.1f} s; FFT steps single-threaded, matrix products on "
+                      f"{threads} BLAS threads)",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--fp64-steps", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-trace", action="store_true", help="time without per-kernel events")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (the build targets a single MI355X); got --gpus {a.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2310_08408_amd as lp
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    # ---- batched FP32 path -------------------------------------------------
+    log(f"inputs: batch {a.batch} x 2048^2 complex64")
+    w, v, phi = inputs(lp, torch, a.batch, torch.complex64)
+    step = Step(lp, torch, w, v, phi)
+    t_setup = time.perf_counter()
+    step()
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    log(f"first step (includes kernel-spectrum / chirp setup): {t_setup * 1e3:.1f} ms")
+    if not a.no_trace:
+        for _ in range(a.warmup):
+            step()
+        torch.cuda.synchronize()
+        lp.prop_trace_enable(True)
+    wall, gpu = time_steps(torch, step, a.steps, 0 if not a.no_trace else a.warmup)
+    trace = {}
+    if not a.no_trace:
+        trace = lp.prop_trace_read()
+        lp.prop_trace_enable(False)
+    grads = 2 * a.batch
+    value = grads / wall
+    log(f"fp32 batched: {wall * 1e3:.3f} ms/step wall, {gpu * 1e3:.3f} ms/step gpu -> {value:.1f} grads/s")
+
+    per_pass = {}
+    for name, (n, ms, by) in trace.items():
+        avg_ms = ms / max(n, 1)
+        per_pass[name] = {"launches": n, "avg_ms": avg_ms, "bytes_per_launch": by / max(n, 1),
+                          "gbs": (by / max(n, 1)) / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None,
+                          "share": ms / max(sum(t[1] for t in trace.values()), 1e-12)}
+    roofline = None
+    if per_pass:
+        dom = max(per_pass, key=lambda k: per_pass[k]["share"])
+        p = per_pass[dom]
+        roofline = {"bound": "hbm", "achieved": p["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": p["gbs"] / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                    "bytes_per_launch": p["bytes_per_launch"], "avg_ms": p["avg_ms"]}
+    total_model_bytes = sum(t[2] for t in trace.values()) / max(a.steps, 1)
+    step_frac = total_model_bytes / wall / 1e9 / HBM_PEAK_GBS if trace else None
+
+    # ---- errors vs the GPU FP64 path, and its plain single-field timing ----
+    log("fp64 single-field path")
+    w64, v64, phi64 = inputs(lp, torch, 1, torch.complex128)
+    step64 = Step(lp, torch, w64, v64, phi64)
+    step64()
+    torch.cuda.synchronize()
+    errs = {}
+    u32 = step.u[:1]
+    g, win, wl = w["grid"], w["window"], w["wavelength"]
+    y32 = lp.rs_propagate(u32, g, wl, w["z_rs"])
+    y64 = lp.rs_propagate(step64.u, g, wl, w["z_rs"])
+    errs["rs_forward"] = rel(y32.to(torch.complex128), y64)
+    errs["rs_adjoint"] = rel(lp.rs_adjoint(y32, g, wl, w["z_rs"]).to(torch.complex128),
+                             lp.rs_adjoint(y64, g, wl, w["z_rs"]))
+    c32 = lp.czt_propagate(u32, g, win, wl, w["z_czt"])
+    c64 = lp.czt_propagate(step64.u, g, win, wl, w["z_czt"])
+    errs["czt_forward"] = rel(c32.to(torch.complex128), c64)
+    errs["czt_adjoint"] = rel(lp.czt_adjoint(c32, g, win, wl, w["z_czt"]).to(torch.complex128),
+                              lp.czt_adjoint(c64, g, win, wl, w["z_czt"]))
+    errs["phase_grad"] = rel(step.grad[:1].to(torch.float64), step64.grad)
+    log("rel-L2 of FP32 results vs the FP64 GPU path:", {k: f"{v:.2e}" for k, v in errs.items()})
+    wall64, _ = time_steps(torch, step64, a.fp64_steps, 1)
+    value64 = 2 / wall64
+    log(f"fp64 single field: {wall64 * 1e3:.3f} ms/step -> {value64:.1f} grads/s")
+
+    cpu = None
+    if not a.no_cpu:
+        log("cpu baseline (FP64 oracle) ...")
+        cpu = cpu_baseline()
+        log(f"cpu baseline: {cpu['value']:.4f} grads/s ({cpu['seconds']:.1f} s)")
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "grads/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": wall * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "rs_czt_2048: 2048^2 complex64 fields, 4 mm grid, 650 nm; RS z=25 mm (4096^2 padded) "
+                               "+ CZT z=f=25 mm onto a 2048^2 40 um window; SLM phase gradient of |Y|^2/2",
+                   "batch": a.batch, "grads_per_step": grads},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "hbm_frac_step": step_frac,
+        "fp64_single": {"value": value64, "unit": "grads/s", "ms_per_step": wall64 * 1e3,
+                        "speedup_fp32_batched": value / value64},
+        "errors_vs_fp64": errs,
+        "per_pass": per_pass,
+        "gpu_ms_per_step": gpu * 1e3,
+        "first_step_ms": t_setup * 1e3,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -199,6 +199,25 @@ const char* prop_status_string(int status);
 /* hipError_t of the last PROP_EDEVICE on this thread (0 if none). */
 int prop_last_device_error(void);
 
+/* ------------------------------------------------------------- tracing --
+ * Kernel-level timing for benchmarks and profiling.  prop_trace_enable(1)
+ * clears the trace and brackets every subsequent hot-path launch with a
+ * pair of hipEvents recorded on the caller's stream; prop_trace_enable(0)
+ * stops.  prop_trace_read() waits for the recorded events, aggregates them
+ * per pass name (launch count, summed kernel milliseconds, summed
+ * algorithmic bytes = compulsory reads + writes of each launch), writes at
+ * most `max` entries to `out` (caller-owned host memory), clears the trace
+ * and returns the number of passes, or PROP_EDEVICE.
+ */
+typedef struct {
+  char name[32];
+  int32_t launches;
+  double total_ms;
+  double bytes;
+} prop_trace_stat;
+void prop_trace_enable(int32_t on);
+int32_t prop_trace_read(prop_trace_stat* out, int32_t max);
+
 #ifdef __cplusplus
 }
 #endif

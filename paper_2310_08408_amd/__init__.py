@@ -21,7 +21,8 @@ __all__ = [
     "rs_propagate", "rs_adjoint", "czt_propagate", "czt_adjoint", "vrs_propagate", "vrs_adjoint",
     "vczt_propagate", "vczt_adjoint", "prop_source_gaussian", "prop_source_radial", "prop_modulate",
     "prop_phase_grad", "prop_waveplate", "prop_waveplate_adjoint", "prop_spot_loss", "prop_sampling_check",
-    "prop_fft_length", "prop_cache_clear", "PropError", "PropWarning", "library",
+    "prop_fft_length", "prop_cache_clear", "prop_trace_enable", "prop_trace_read", "PropError", "PropWarning",
+    "library",
 ]
 
 
@@ -303,3 +304,18 @@ def prop_fft_length(n: int) -> int:
 
 def prop_cache_clear() -> None:
     library().prop_cache_clear()
+
+
+def prop_trace_enable(on: bool = True) -> None:
+    library().prop_trace_enable(1 if on else 0)
+
+
+def prop_trace_read(max_entries: int = 64) -> dict:
+    """{pass name: (launches, total_ms, bytes)} of the trace since enable (clears it)."""
+    lib = library()
+    buf = (_lib.prop_trace_stat * max_entries)()
+    n = lib.prop_trace_read(ctypes.cast(buf, ctypes.c_void_p), max_entries)
+    if n < 0:
+        raise PropError("prop_trace_read", n)
+    return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms), float(buf[i].bytes))
+            for i in range(n)}

@@ -28,6 +28,10 @@ class prop_grid(ctypes.Structure):
                 ("cx", c_double), ("cy", c_double)]
 
 
+class prop_trace_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", c_int32), ("total_ms", c_double), ("bytes", c_double)]
+
+
 class prop_lens(ctypes.Structure):
     _fields_ = [("na", c_double), ("f", c_double)]
 
@@ -58,6 +62,8 @@ SIGNATURES = {
     "prop_cache_clear": (None, []),
     "prop_status_string": (ctypes.c_char_p, [c_int32]),
     "prop_last_device_error": (c_int32, []),
+    "prop_trace_enable": (None, [c_int32]),
+    "prop_trace_read": (c_int32, [P, c_int32]),
 }
 
 _lib = None

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "kernels.hpp"
 
@@ -32,6 +33,16 @@ struct Cfg {
   static constexpr int threads = C * S::threads * LINES_PER_ITEM;
   static constexpr bool fits = line_bytes <= kLdsBytes && S::threads * LINES_PER_ITEM <= 1024;
 };
+
+// Tuning override of the lines per workgroup of column passes at the long
+// lengths (environment LIBPROP_COL_LINES = 1, 2 or 4; 0 = built-in choice).
+inline int col_lines_override() {
+  static int v = [] {
+    const char* e = std::getenv("LIBPROP_COL_LINES");
+    return e ? std::atoi(e) : 0;
+  }();
+  return v;
+}
 
 // Workgroup i is dispatched to XCD i % 8; give each XCD a contiguous range
 // of tiles so that neighbouring lines (adjacent columns) share one L2.
@@ -152,6 +163,15 @@ __global__ __launch_bounds__(C * S::threads) void k_rs_cols(cx<T>* W, int64_t bs
   fft_line<T, 1, S>(lds, tw, j, load2, store, true);
 }
 
+template <typename T, class S, int C>
+hipError_t launch_rs_cols_c(cx<T>* W, int64_t bstride, int64_t pitch, int ncols, int n_valid, const cx<T>* Sq, int Mx,
+                            bool conj_spec, int batch, const cx<T>* tw, hipStream_t s) {
+  const int tiles = (ncols + C - 1) / C;
+  hipLaunchKernelGGL((k_rs_cols<T, S, C>), dim3(tiles * batch), dim3(C * S::threads), 0, s, W, bstride, pitch, ncols,
+                     n_valid, Sq, Mx, conj_spec ? 1 : 0, tiles, tw);
+  return hipGetLastError();
+}
+
 template <typename T, class S>
 hipError_t launch_rs_cols_s(cx<T>* W, int64_t bstride, int64_t pitch, int ncols, int n_valid, const cx<T>* Sq, int Mx,
                             bool conj_spec, int batch, const cx<T>* tw, hipStream_t s) {
@@ -159,10 +179,12 @@ hipError_t launch_rs_cols_s(cx<T>* W, int64_t bstride, int64_t pitch, int ncols,
   if constexpr (!CF::fits) {
     return hipErrorInvalidValue;
   } else {
-    const int tiles = (ncols + CF::C - 1) / CF::C;
-    hipLaunchKernelGGL((k_rs_cols<T, S, CF::C>), dim3(tiles * batch), dim3(CF::threads), 0, s, W, bstride, pitch,
-                       ncols, n_valid, Sq, Mx, conj_spec ? 1 : 0, tiles, tw);
-    return hipGetLastError();
+    if constexpr (S::n == 4096 && sizeof(T) == 4) {
+      const int o = col_lines_override();
+      if (o == 1) return launch_rs_cols_c<T, S, 1>(W, bstride, pitch, ncols, n_valid, Sq, Mx, conj_spec, batch, tw, s);
+      if (o == 2) return launch_rs_cols_c<T, S, 2>(W, bstride, pitch, ncols, n_valid, Sq, Mx, conj_spec, batch, tw, s);
+    }
+    return launch_rs_cols_c<T, S, CF::C>(W, bstride, pitch, ncols, n_valid, Sq, Mx, conj_spec, batch, tw, s);
   }
 }
 
@@ -308,6 +330,14 @@ hipError_t launch_bluestein_s(const cx<T>* in, cx<T>* out, Lines li, Lines lo, i
   if constexpr (!CF::fits) {
     return hipErrorInvalidValue;
   } else {
+    if constexpr (COL && S::n == 4096 && sizeof(T) == 4) {
+      if (col_lines_override() == 1) {
+        const int tiles = nlines;
+        hipLaunchKernelGGL((k_bluestein<T, COL, S, 1>), dim3(tiles * batch), dim3(S::threads), 0, s, in, out, li, lo,
+                           nlines, n_in, n_out, pre, chat, post, tiles, tw);
+        return hipGetLastError();
+      }
+    }
     const int tiles = (nlines + CF::C - 1) / CF::C;
     hipLaunchKernelGGL((k_bluestein<T, COL, S, CF::C>), dim3(tiles * batch), dim3(CF::threads), 0, s, in, out, li, lo,
                        nlines, n_in, n_out, pre, chat, post, tiles, tw);

@@ -36,6 +36,52 @@ static int dev_err(hipError_t e) {
 
 static const double kPi = 3.14159265358979323846;
 
+// ------------------------------------------------------------- tracing --
+// When enabled, every hot-path launch is bracketed by a pair of hipEvents
+// recorded on the caller's stream, tagged with the pass name and its
+// algorithmic bytes (compulsory reads + writes of that launch).
+struct TraceRec {
+  const char* name;
+  hipEvent_t a, b;
+  double bytes;
+};
+struct Tracer {
+  bool on = false;
+  std::vector<TraceRec> recs;
+  std::vector<hipEvent_t> pool;
+};
+static Tracer& tracer() {
+  static Tracer* t = new Tracer();
+  return *t;
+}
+static hipEvent_t take_event() {
+  Tracer& t = tracer();
+  if (!t.pool.empty()) {
+    hipEvent_t e = t.pool.back();
+    t.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+#define LP_TRACE(NAME, BYTES, S, EXPR)                                                  \
+  do {                                                                                  \
+    Tracer& tr_ = tracer();                                                             \
+    hipEvent_t ea_ = nullptr, eb_ = nullptr;                                            \
+    if (tr_.on) {                                                                       \
+      ea_ = take_event();                                                               \
+      eb_ = take_event();                                                               \
+      if (ea_) (void)hipEventRecord(ea_, S);                                            \
+    }                                                                                   \
+    hipError_t e_ = (EXPR);                                                             \
+    if (tr_.on && ea_ && eb_) {                                                         \
+      (void)hipEventRecord(eb_, S);                                                     \
+      tr_.recs.push_back(TraceRec{NAME, ea_, eb_, (double)(BYTES)});                    \
+    }                                                                                   \
+    if (e_ != hipSuccess) return dev_err(e_);                                           \
+  } while (0)
+
 // ------------------------------------------------------------- lengths --
 static const int kLengths[] = {
 #define LP_LEN(N, ...) N,
@@ -312,13 +358,18 @@ static int rs_run(const void* in, void* out, const prop_grid* g, double wl, doub
   cx<T>* W = (cx<T>*)wb.p;
   const T scale = (T)(g->dx * g->dy / ((double)Mx * (double)My));
   // P1: row transforms of the ny input rows, zero-padded to Mx
-  LP_TRY((launch_fft_lines<T, -1>(Mx, false, (const cx<T>*)in, W, Lines{(int64_t)ny * nx, nx}, Lines{plane, Mx}, ny,
-                                  nx, Mx, T(1), batch, twx, s)));
+  const double es = sizeof(cx<T>);
+  const double qel = (double)(Mx / 2 + 1) * (My / 2 + 1);
+  LP_TRACE("rs_rows_fwd", es * batch * ny * (double)(nx + Mx), s,
+           (launch_fft_lines<T, -1>(Mx, false, (const cx<T>*)in, W, Lines{(int64_t)ny * nx, nx}, Lines{plane, Mx}, ny,
+                                    nx, Mx, T(1), batch, twx, s)));
   // P2: column transform, kernel-spectrum multiply, inverse, first ny rows
-  LP_TRY(launch_rs_cols<T>(My, W, plane, Mx, Mx, ny, q[0], Mx, adjoint, batch, twy, s));
+  LP_TRACE("rs_cols", es * (2.0 * batch * ny * Mx + qel), s,
+           launch_rs_cols<T>(My, W, plane, Mx, Mx, ny, q[0], Mx, adjoint, batch, twy, s));
   // P3: inverse row transforms, crop to nx, scale dx dy / (Mx My)
-  LP_TRY((launch_fft_lines<T, 1>(Mx, false, W, (cx<T>*)out, Lines{plane, Mx}, Lines{(int64_t)ny * nx, nx}, ny, Mx, nx,
-                                 scale, batch, twx, s)));
+  LP_TRACE("rs_rows_inv", es * batch * ny * (double)(nx + Mx), s,
+           (launch_fft_lines<T, 1>(Mx, false, W, (cx<T>*)out, Lines{plane, Mx}, Lines{(int64_t)ny * nx, nx}, ny, Mx, nx,
+                                   scale, batch, twx, s)));
   return PROP_OK;
 }
 
@@ -359,27 +410,37 @@ static int vrs_run(const void* const* ins, int nin, void* const* outs, int nout,
   LP_RET(ensure_buf(wb, 3 * plane * sizeof(cx<T>), s));
   cx<T>* W[3];
   for (int i = 0; i < 3; ++i) W[i] = (cx<T>*)wb.p + i * plane;
+  const double es = sizeof(cx<T>);
+  const double qel = (double)(Mx / 2 + 1) * (My / 2 + 1);
+  const double pl = (double)batch * ny * Mx;
   for (int i = 0; i < nin; ++i)
-    LP_TRY((launch_fft_lines<T, -1>(Mx, false, (const cx<T>*)ins[i], W[i], Lines{(int64_t)ny * nx, nx},
-                                    Lines{pst, Mx}, ny, nx, Mx, T(1), batch, twx, s)));
+    LP_TRACE("rs_rows_fwd", es * batch * ny * (double)(nx + Mx), s,
+             (launch_fft_lines<T, -1>(Mx, false, (const cx<T>*)ins[i], W[i], Lines{(int64_t)ny * nx, nx},
+                                      Lines{pst, Mx}, ny, nx, Mx, T(1), batch, twx, s)));
   if (!adjoint) {
     // E_z = -(Hx * E_x0 + Hy * E_y0) first (reads W0, W1), then E_x, E_y in place
-    LP_TRY(launch_mix2_cols<T>(My, W[0], W[1], W[2], pst, Mx, Mx, ny, q[1], 1, T(-1), q[2], 2, T(-1), false, Mx, batch,
-                               twy, s));
-    LP_TRY(launch_rs_cols<T>(My, W[0], pst, Mx, Mx, ny, q[0], Mx, false, batch, twy, s));
-    LP_TRY(launch_rs_cols<T>(My, W[1], pst, Mx, Mx, ny, q[0], Mx, false, batch, twy, s));
+    LP_TRACE("vrs_mix2", es * (3.0 * pl + 2.0 * qel), s,
+             launch_mix2_cols<T>(My, W[0], W[1], W[2], pst, Mx, Mx, ny, q[1], 1, T(-1), q[2], 2, T(-1), false, Mx,
+                                 batch, twy, s));
+    LP_TRACE("rs_cols", es * (2.0 * pl + qel), s,
+             launch_rs_cols<T>(My, W[0], pst, Mx, Mx, ny, q[0], Mx, false, batch, twy, s));
+    LP_TRACE("rs_cols", es * (2.0 * pl + qel), s,
+             launch_rs_cols<T>(My, W[1], pst, Mx, Mx, ny, q[0], Mx, false, batch, twy, s));
   } else {
     // g_ex = H^H g_x - Hx^H g_z, g_ey = H^H g_y - Hy^H g_z (in place over W0, W1)
-    LP_TRY(launch_mix2_cols<T>(My, W[0], W[2], W[0], pst, Mx, Mx, ny, q[0], 0, T(1), q[1], 1, T(-1), true, Mx, batch,
-                               twy, s));
-    LP_TRY(launch_mix2_cols<T>(My, W[1], W[2], W[1], pst, Mx, Mx, ny, q[0], 0, T(1), q[2], 2, T(-1), true, Mx, batch,
-                               twy, s));
+    LP_TRACE("vrs_mix2", es * (3.0 * pl + 2.0 * qel), s,
+             launch_mix2_cols<T>(My, W[0], W[2], W[0], pst, Mx, Mx, ny, q[0], 0, T(1), q[1], 1, T(-1), true, Mx,
+                                 batch, twy, s));
+    LP_TRACE("vrs_mix2", es * (3.0 * pl + 2.0 * qel), s,
+             launch_mix2_cols<T>(My, W[1], W[2], W[1], pst, Mx, Mx, ny, q[0], 0, T(1), q[2], 2, T(-1), true, Mx,
+                                 batch, twy, s));
   }
   const T scale = (T)(g->dx * g->dy / ((double)Mx * (double)My));
   const int src[3] = {adjoint ? 0 : 0, 1, 2};
   for (int i = 0; i < nout; ++i)
-    LP_TRY((launch_fft_lines<T, 1>(Mx, false, W[src[i]], (cx<T>*)outs[i], Lines{pst, Mx}, Lines{(int64_t)ny * nx, nx},
-                                   ny, Mx, nx, scale, batch, twx, s)));
+    LP_TRACE("rs_rows_inv", es * batch * ny * (double)(nx + Mx), s,
+             (launch_fft_lines<T, 1>(Mx, false, W[src[i]], (cx<T>*)outs[i], Lines{pst, Mx},
+                                     Lines{(int64_t)ny * nx, nx}, ny, Mx, nx, scale, batch, twx, s)));
   return PROP_OK;
 }
 
@@ -417,18 +478,23 @@ static int zoom2d_run(int dev, const cx<T>* in, cx<T>* out, int nxi, int nyi, in
   const cx<T> *twx, *twy;
   LP_RET(get_tw<T>(dev, zx.L, &twx));
   LP_RET(get_tw<T>(dev, zy.L, &twy));
+  const double es = sizeof(cx<T>);
   if (!cols_first) {
     // rows: [nyi][nxi] -> tmp [nyi][nxo]; cols: tmp -> out [nyo][nxo]
-    LP_TRY(launch_bluestein<T>(zx.L, false, in, tmp, Lines{(int64_t)nyi * nxi, nxi}, Lines{(int64_t)nyi * nxo, nxo},
-                               nyi, nxi, nxo, prex, chatx, postx, batch, twx, s));
-    LP_TRY(launch_bluestein<T>(zy.L, true, tmp, out, Lines{(int64_t)nyi * nxo, nxo}, Lines{(int64_t)nyo * nxo, nxo},
-                               nxo, nyi, nyo, prey, chaty, posty, batch, twy, s));
+    LP_TRACE("czt_rows", es * batch * nyi * (double)(nxi + nxo), s,
+             launch_bluestein<T>(zx.L, false, in, tmp, Lines{(int64_t)nyi * nxi, nxi}, Lines{(int64_t)nyi * nxo, nxo},
+                                 nyi, nxi, nxo, prex, chatx, postx, batch, twx, s));
+    LP_TRACE("czt_cols", es * batch * nxo * (double)(nyi + nyo), s,
+             launch_bluestein<T>(zy.L, true, tmp, out, Lines{(int64_t)nyi * nxo, nxo}, Lines{(int64_t)nyo * nxo, nxo},
+                                 nxo, nyi, nyo, prey, chaty, posty, batch, twy, s));
   } else {
     // cols: [nyi][nxi] -> tmp [nyo][nxi]; rows: tmp -> out [nyo][nxo]
-    LP_TRY(launch_bluestein<T>(zy.L, true, in, tmp, Lines{(int64_t)nyi * nxi, nxi}, Lines{(int64_t)nyo * nxi, nxi},
-                               nxi, nyi, nyo, prey, chaty, posty, batch, twy, s));
-    LP_TRY(launch_bluestein<T>(zx.L, false, tmp, out, Lines{(int64_t)nyo * nxi, nxi}, Lines{(int64_t)nyo * nxo, nxo},
-                               nyo, nxi, nxo, prex, chatx, postx, batch, twx, s));
+    LP_TRACE("czt_cols", es * batch * nxi * (double)(nyi + nyo), s,
+             launch_bluestein<T>(zy.L, true, in, tmp, Lines{(int64_t)nyi * nxi, nxi}, Lines{(int64_t)nyo * nxi, nxi},
+                                 nxi, nyi, nyo, prey, chaty, posty, batch, twy, s));
+    LP_TRACE("czt_rows", es * batch * nyo * (double)(nxi + nxo), s,
+             launch_bluestein<T>(zx.L, false, tmp, out, Lines{(int64_t)nyo * nxi, nxi}, Lines{(int64_t)nyo * nxo, nxo},
+                                 nyo, nxi, nxo, prex, chatx, postx, batch, twx, s));
   }
   return PROP_OK;
 }
@@ -578,8 +644,10 @@ static int rw_fwd(const void* ex, const void* ey, void* const* outs, const prop_
   LP_RET(ensure_buf(wb, 3 * (ni + nm) * sizeof(cx<T>), s));
   cx<T>* P = (cx<T>*)wb.p;
   cx<T>* M = P + 3 * ni;
-  LP_TRY(launch_pupil<T>((const cx<T>*)ex, (const cx<T>*)ey, P, P + ni, P + 2 * ni, gi->nx, gi->ny, gi->dx, gi->dy,
-                         gi->cx, gi->cy, lens->f, lens->na, batch, (int64_t)gi->nx * gi->ny, false, s));
+  const double es = sizeof(cx<T>);
+  LP_TRACE("rw_pupil", es * 5.0 * ni, s,
+           launch_pupil<T>((const cx<T>*)ex, (const cx<T>*)ey, P, P + ni, P + 2 * ni, gi->nx, gi->ny, gi->dx, gi->dy,
+                           gi->cx, gi->cy, lens->f, lens->na, batch, (int64_t)gi->nx * gi->ny, false, s));
   ZoomSpec zx, zy;
   rw_specs(gi, go, wl, lens, false, &zx, &zy);
   const cx<T> *prex, *postx, *chatx, *prey, *posty, *chaty;
@@ -589,11 +657,13 @@ static int rw_fwd(const void* ex, const void* ey, void* const* outs, const prop_
   LP_RET(get_tw<T>(dev, zx.L, &twx));
   LP_RET(get_tw<T>(dev, zy.L, &twy));
   const int nxi = gi->nx, nyi = gi->ny, nxo = go->nx, nyo = go->ny;
-  LP_TRY(launch_bluestein<T>(zx.L, false, P, M, Lines{(int64_t)nyi * nxi, nxi}, Lines{(int64_t)nyi * nxo, nxo}, nyi,
-                             nxi, nxo, prex, chatx, postx, 3 * batch, twx, s));
+  LP_TRACE("rw_rows", es * 3.0 * batch * nyi * (double)(nxi + nxo), s,
+           launch_bluestein<T>(zx.L, false, P, M, Lines{(int64_t)nyi * nxi, nxi}, Lines{(int64_t)nyi * nxo, nxo}, nyi,
+                               nxi, nxo, prex, chatx, postx, 3 * batch, twx, s));
   for (int c = 0; c < 3; ++c)
-    LP_TRY(launch_bluestein<T>(zy.L, true, M + c * nm, (cx<T>*)outs[c], Lines{(int64_t)nyi * nxo, nxo},
-                               Lines{(int64_t)nyo * nxo, nxo}, nxo, nyi, nyo, prey, chaty, posty, batch, twy, s));
+    LP_TRACE("rw_cols", es * batch * nxo * (double)(nyi + nyo), s,
+             launch_bluestein<T>(zy.L, true, M + c * nm, (cx<T>*)outs[c], Lines{(int64_t)nyi * nxo, nxo},
+                                 Lines{(int64_t)nyo * nxo, nxo}, nxo, nyi, nyo, prey, chaty, posty, batch, twy, s));
   return PROP_OK;
 }
 
@@ -617,13 +687,17 @@ static int rw_adj(const void* const* gs, void* gex, void* gey, const prop_grid* 
   LP_RET(get_tw<T>(dev, zx.L, &twx));
   LP_RET(get_tw<T>(dev, zy.L, &twy));
   const int nxi = gi->nx, nyi = gi->ny, nxo = go->nx, nyo = go->ny;
+  const double es = sizeof(cx<T>);
   for (int c = 0; c < 3; ++c)
-    LP_TRY(launch_bluestein<T>(zy.L, true, (const cx<T>*)gs[c], M + c * nm, Lines{(int64_t)nyo * nxo, nxo},
-                               Lines{(int64_t)nyi * nxo, nxo}, nxo, nyo, nyi, prey, chaty, posty, batch, twy, s));
-  LP_TRY(launch_bluestein<T>(zx.L, false, M, P, Lines{(int64_t)nyi * nxo, nxo}, Lines{(int64_t)nyi * nxi, nxi}, nyi,
-                             nxo, nxi, prex, chatx, postx, 3 * batch, twx, s));
-  LP_TRY(launch_pupil<T>((const cx<T>*)gex, (const cx<T>*)gey, P, P + ni, P + 2 * ni, gi->nx, gi->ny, gi->dx, gi->dy,
-                         gi->cx, gi->cy, lens->f, lens->na, batch, (int64_t)gi->nx * gi->ny, true, s));
+    LP_TRACE("rw_cols", es * batch * nxo * (double)(nyi + nyo), s,
+             launch_bluestein<T>(zy.L, true, (const cx<T>*)gs[c], M + c * nm, Lines{(int64_t)nyo * nxo, nxo},
+                                 Lines{(int64_t)nyi * nxo, nxo}, nxo, nyo, nyi, prey, chaty, posty, batch, twy, s));
+  LP_TRACE("rw_rows", es * 3.0 * batch * nyi * (double)(nxi + nxo), s,
+           launch_bluestein<T>(zx.L, false, M, P, Lines{(int64_t)nyi * nxo, nxo}, Lines{(int64_t)nyi * nxi, nxi}, nyi,
+                               nxo, nxi, prex, chatx, postx, 3 * batch, twx, s));
+  LP_TRACE("rw_pupil", es * 5.0 * ni, s,
+           launch_pupil<T>((const cx<T>*)gex, (const cx<T>*)gey, P, P + ni, P + 2 * ni, gi->nx, gi->ny, gi->dx, gi->dy,
+                           gi->cx, gi->cy, lens->f, lens->na, batch, (int64_t)gi->nx * gi->ny, true, s));
   return PROP_OK;
 }
 
@@ -834,11 +908,14 @@ int prop_modulate(prop_dtype t, const void* u_in, const void* phase, void* u_out
   LP_RET(check_alias({{phase, (size_t)npix * phase_batch * esize(t) / 2}}, {{u_out, b}}));
   const int64_t pbs = phase_batch == 1 ? 0 : npix;
   const hipStream_t s = (hipStream_t)stream;
-  hipError_t e = t == PROP_C64 ? launch_modulate<float>((const cx<float>*)u_in, (const float*)phase,
-                                                        (cx<float>*)u_out, npix, batch, pbs, s)
-                               : launch_modulate<double>((const cx<double>*)u_in, (const double*)phase,
-                                                         (cx<double>*)u_out, npix, batch, pbs, s);
-  return e == hipSuccess ? PROP_OK : dev_err(e);
+  std::lock_guard<std::mutex> lk(ctx().mu);
+  const double es = (double)esize(t);
+  LP_TRACE("modulate", (double)npix * batch * 2.0 * es + (double)npix * phase_batch * es / 2, s,
+           (t == PROP_C64 ? launch_modulate<float>((const cx<float>*)u_in, (const float*)phase, (cx<float>*)u_out,
+                                                   npix, batch, pbs, s)
+                          : launch_modulate<double>((const cx<double>*)u_in, (const double*)phase,
+                                                    (cx<double>*)u_out, npix, batch, pbs, s)));
+  return PROP_OK;
 }
 
 int prop_phase_grad(prop_dtype t, const void* g_u, const void* u, void* grad, int64_t npix, int32_t batch,
@@ -850,11 +927,13 @@ int prop_phase_grad(prop_dtype t, const void* g_u, const void* u, void* grad, in
   const size_t b = (size_t)npix * batch * esize(t);
   LP_RET(check_alias({{g_u, b}, {u, b}}, {{grad, b / 2}}));
   const hipStream_t s = (hipStream_t)stream;
-  hipError_t e = t == PROP_C64 ? launch_phase_grad<float>((const cx<float>*)g_u, (const cx<float>*)u, (float*)grad,
-                                                          npix, batch, accumulate, s)
-                               : launch_phase_grad<double>((const cx<double>*)g_u, (const cx<double>*)u,
-                                                           (double*)grad, npix, batch, accumulate, s);
-  return e == hipSuccess ? PROP_OK : dev_err(e);
+  std::lock_guard<std::mutex> lk(ctx().mu);
+  LP_TRACE("phase_grad", (double)b * 2.0 + (double)b / 2 * (accumulate ? 2 : 1), s,
+           (t == PROP_C64 ? launch_phase_grad<float>((const cx<float>*)g_u, (const cx<float>*)u, (float*)grad, npix,
+                                                     batch, accumulate, s)
+                          : launch_phase_grad<double>((const cx<double>*)g_u, (const cx<double>*)u, (double*)grad,
+                                                      npix, batch, accumulate, s)));
+  return PROP_OK;
 }
 
 int prop_waveplate(prop_dtype t, const void* ex, const void* ey, void* ox, void* oy, double eta, double theta,
@@ -992,5 +1071,48 @@ const char* prop_status_string(int status) {
 }
 
 int prop_last_device_error(void) { return g_last_hip; }
+
+void prop_trace_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(ctx().mu);
+  Tracer& t = tracer();
+  for (auto& r : t.recs) {
+    (void)hipEventSynchronize(r.b);
+    t.pool.push_back(r.a);
+    t.pool.push_back(r.b);
+  }
+  t.recs.clear();
+  t.on = on != 0;
+}
+
+int32_t prop_trace_read(prop_trace_stat* out, int32_t max) {
+  std::lock_guard<std::mutex> lk(ctx().mu);
+  Tracer& t = tracer();
+  std::vector<prop_trace_stat> agg;
+  int status = 0;
+  for (auto& r : t.recs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) status = -1;
+    prop_trace_stat* e = nullptr;
+    for (auto& a : agg)
+      if (std::strncmp(a.name, r.name, sizeof(a.name)) == 0) e = &a;
+    if (!e) {
+      prop_trace_stat z;
+      std::memset(&z, 0, sizeof(z));
+      std::strncpy(z.name, r.name, sizeof(z.name) - 1);
+      agg.push_back(z);
+      e = &agg.back();
+    }
+    e->launches += 1;
+    e->total_ms += ms;
+    e->bytes += r.bytes;
+    t.pool.push_back(r.a);
+    t.pool.push_back(r.b);
+  }
+  t.recs.clear();
+  if (status < 0) return PROP_EDEVICE;
+  const int n = std::min<int>((int)agg.size(), max);
+  for (int i = 0; i < n && out; ++i) out[i] = agg[i];
+  return n;
+}
 
 }  // extern "C"
