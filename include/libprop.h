@@ -199,6 +199,56 @@ const char* prop_status_string(int status);
 /* hipError_t of the last PROP_EDEVICE on this thread (0 if none). */
 int prop_last_device_error(void);
 
+/* ---------------------------------------------------------------- plans --
+ * Batches of independent setups of uneven sizes and parameters (the paper
+ * evaluates many candidate setups per optimisation step: Results, batches
+ * of setups sharing parameters; Methods, compile-once-per-shape reuse).
+ * prop_plan_create validates every setup, computes all kernel spectra, chirp
+ * vectors and twiddle tables, and allocates all workspace, so that
+ * prop_plan_forward / prop_plan_adjoint only enqueue kernels: they neither
+ * allocate nor synchronise, and may be captured into a caller's hipGraph.
+ * With PROP_PLAN_GRAPH the plan captures its own forward and adjoint once
+ * (setups spread over up to 4 parallel branches) and afterwards replays each
+ * as a single hipGraphLaunch on the caller's stream.
+ *
+ * Per setup (one propagator call on `batch` fields):
+ *   forward: u = in * exp(i phase) * exp(-i k r^2 / (2 lens_f)) (each factor
+ *            optional; the plan keeps u), out = op(u);
+ *   adjoint: g_u = op^H(gout); gin = g_u * conj(factor) (if gin != NULL);
+ *            grad_phase = sum over input components Im(g_u conj(u))
+ *            (if grad_phase != NULL).  Requires a preceding forward.
+ * Scalar ops use in[0], out[0], gout[0], gin[0]; vector ops use two inputs
+ * and three outputs.  phase / grad_phase: real [batch][g_in.ny][g_in.nx]
+ * (float for PROP_C64, double for PROP_C128).  All pointers are device
+ * memory owned by the caller and must stay valid for the plan's lifetime.
+ * Errors: as the single calls, reported by prop_plan_create with *plan set
+ * to NULL; PROP_ESHAPE for an unknown op.
+ */
+enum { PROP_OP_RS = 0, PROP_OP_CZT = 1, PROP_OP_VRS = 2, PROP_OP_VCZT = 3 };
+#define PROP_PLAN_GRAPH 1u
+
+typedef struct {
+  int32_t op;           /* PROP_OP_* */
+  int32_t batch;        /* fields in this setup (>= 1) */
+  prop_grid g_in, win;  /* win: output window of CZT / VCZT (ignored for RS / VRS) */
+  double wavelength, z; /* z ignored by focusing VCZT */
+  int32_t has_lens;     /* VCZT: focusing mode with `lens` */
+  prop_lens lens;
+  double lens_f;        /* > 0: thin-lens phase applied to the input first */
+  const void* phase;    /* optional SLM phase applied to the input */
+  const void* in[2];
+  void* out[3];
+  const void* gout[3];
+  void* gin[2];
+  void* grad_phase;     /* optional: dL/dphase */
+} prop_setup;
+
+typedef struct prop_plan prop_plan;
+int prop_plan_create(prop_dtype t, const prop_setup* setups, int32_t n, uint32_t flags, prop_plan** plan);
+int prop_plan_forward(prop_plan* plan, void* stream);
+int prop_plan_adjoint(prop_plan* plan, void* stream);
+void prop_plan_destroy(prop_plan* plan);
+
 /* ------------------------------------------------------------- tracing --
  * Kernel-level timing for benchmarks and profiling.  prop_trace_enable(1)
  * clears the trace and brackets every subsequent hot-path launch with a

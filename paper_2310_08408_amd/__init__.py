@@ -22,7 +22,7 @@ __all__ = [
     "vczt_propagate", "vczt_adjoint", "prop_source_gaussian", "prop_source_radial", "prop_modulate",
     "prop_phase_grad", "prop_waveplate", "prop_waveplate_adjoint", "prop_spot_loss", "prop_sampling_check",
     "prop_fft_length", "prop_cache_clear", "prop_trace_enable", "prop_trace_read", "PropError", "PropWarning",
-    "library",
+    "library", "Plan", "Setup", "PROP_OP_RS", "PROP_OP_CZT", "PROP_OP_VRS", "PROP_OP_VCZT",
 ]
 
 
@@ -319,3 +319,89 @@ def prop_trace_read(max_entries: int = 64) -> dict:
         raise PropError("prop_trace_read", n)
     return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms), float(buf[i].bytes))
             for i in range(n)}
+
+
+# ---------------------------------------------------------------------- plans --
+
+PROP_OP_RS, PROP_OP_CZT, PROP_OP_VRS, PROP_OP_VCZT = 0, 1, 2, 3
+PROP_PLAN_GRAPH = 1
+
+
+class Setup:
+    """One propagator call of a plan (see prop_setup in include/libprop.h).
+
+    Tensors are device tensors of the plan's dtype; ``inputs``/``outputs``/
+    ``grad_outputs``/``grad_inputs`` are lists (1 or 2 inputs, 1 or 3 outputs).
+    """
+
+    def __init__(self, op, grid, inputs, outputs, grad_outputs, wavelength, z=0.0, window=None, lens=None,
+                 lens_f=0.0, phase=None, grad_inputs=None, grad_phase=None):
+        self.op, self.grid, self.window = op, grid, window
+        self.inputs, self.outputs, self.grad_outputs = list(inputs), list(outputs), list(grad_outputs)
+        self.grad_inputs = list(grad_inputs) if grad_inputs is not None else []
+        self.wavelength, self.z, self.lens, self.lens_f = wavelength, z, lens, lens_f
+        self.phase, self.grad_phase = phase, grad_phase
+
+    def _struct(self):
+        s = _lib.prop_setup()
+        s.op = self.op
+        s.batch = _batch(self.inputs[0], self.grid)
+        s.g_in = _lib.grid(self.grid)
+        if self.window is not None:
+            s.win = _lib.grid(self.window)
+        s.wavelength, s.z = float(self.wavelength), float(self.z)
+        if self.lens is not None:
+            na, f = (self.lens.na, self.lens.f) if hasattr(self.lens, "na") else self.lens
+            s.has_lens, s.lens = 1, _lib.prop_lens(float(na), float(f))
+        s.lens_f = float(self.lens_f)
+        s.phase = self.phase.data_ptr() if self.phase is not None else None
+        for i, t in enumerate(self.inputs):
+            s.in_[i] = _dev(t).data_ptr()
+        for i, t in enumerate(self.outputs):
+            s.out[i] = _dev(t).data_ptr()
+        for i, t in enumerate(self.grad_outputs):
+            s.gout[i] = _dev(t).data_ptr()
+        for i, t in enumerate(self.grad_inputs):
+            s.gin[i] = _dev(t).data_ptr() if t is not None else None
+        s.grad_phase = self.grad_phase.data_ptr() if self.grad_phase is not None else None
+        return s
+
+
+class Plan:
+    """A prop_plan over a list of Setups (keeps their tensors alive)."""
+
+    def __init__(self, setups, dtype=torch.complex64, graph=False, device=None):
+        lib = library()
+        self.setups = list(setups)
+        arr = (_lib.prop_setup * len(self.setups))(*[s._struct() for s in self.setups])
+        self._arr = arr
+        h = ctypes.c_void_p()
+        code = _lib.PROP_C64 if dtype == torch.complex64 else _lib.PROP_C128
+        self.device = device or self.setups[0].inputs[0].device
+        with torch.cuda.device(self.device):
+            st = lib.prop_plan_create(code, ctypes.cast(arr, ctypes.c_void_p), len(self.setups),
+                                      PROP_PLAN_GRAPH if graph else 0, ctypes.byref(h))
+        _lib.check("prop_plan_create", st)
+        self._h = h
+
+    def _stream(self):
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def forward(self):
+        with torch.cuda.device(self.device):
+            _lib.check("prop_plan_forward", library().prop_plan_forward(self._h, self._stream()))
+
+    def adjoint(self):
+        with torch.cuda.device(self.device):
+            _lib.check("prop_plan_adjoint", library().prop_plan_adjoint(self._h, self._stream()))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            library().prop_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -28,12 +28,19 @@ class prop_grid(ctypes.Structure):
                 ("cx", c_double), ("cy", c_double)]
 
 
+class prop_lens(ctypes.Structure):
+    _fields_ = [("na", c_double), ("f", c_double)]
+
+
 class prop_trace_stat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", c_int32), ("total_ms", c_double), ("bytes", c_double)]
 
 
-class prop_lens(ctypes.Structure):
-    _fields_ = [("na", c_double), ("f", c_double)]
+class prop_setup(ctypes.Structure):
+    _fields_ = [("op", c_int32), ("batch", c_int32), ("g_in", prop_grid), ("win", prop_grid),
+                ("wavelength", c_double), ("z", c_double), ("has_lens", c_int32), ("lens", prop_lens),
+                ("lens_f", c_double), ("phase", c_void_p), ("in_", c_void_p * 2), ("out", c_void_p * 3),
+                ("gout", c_void_p * 3), ("gin", c_void_p * 2), ("grad_phase", c_void_p)]
 
 
 G = ctypes.POINTER(prop_grid)
@@ -62,6 +69,10 @@ SIGNATURES = {
     "prop_cache_clear": (None, []),
     "prop_status_string": (ctypes.c_char_p, [c_int32]),
     "prop_last_device_error": (c_int32, []),
+    "prop_plan_create": (c_int32, [c_int32, P, c_int32, ctypes.c_uint32, ctypes.POINTER(c_void_p)]),
+    "prop_plan_forward": (c_int32, [P, P]),
+    "prop_plan_adjoint": (c_int32, [P, P]),
+    "prop_plan_destroy": (None, [P]),
     "prop_trace_enable": (None, [c_int32]),
     "prop_trace_read": (c_int32, [P, c_int32]),
 }

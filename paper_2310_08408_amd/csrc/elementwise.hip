@@ -474,6 +474,85 @@ hipError_t launch_vczt_adj_combine(cx<T>* gex, cx<T>* gey, const cx<T>* cxg, con
   return hipGetLastError();
 }
 
+// ------------------------------------------------- input phase stage --
+// u = in exp(i phase) exp(-i q r^2), q = k / (2 f) (thin lens; q = 0: none).
+// The lens phase is evaluated in FP64 (up to thousands of radians).
+__device__ __forceinline__ void lens_factor(double q, double x, double y, double* c, double* s) {
+  if (q == 0.0) {
+    *c = 1.0;
+    *s = 0.0;
+    return;
+  }
+  sincos(-q * (x * x + y * y), s, c);
+}
+
+template <typename T>
+__global__ void k_phase_stage(const cx<T>* in, const T* phase, cx<T>* out, int nx, int ny, double dx, double dy,
+                              double cx0, double cy0, double q, int64_t npix, int batch, int64_t pbs) {
+  const int64_t total = npix * batch;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = t / npix, i = t - b * npix;
+    const int row = (int)(i / nx), col = (int)(i - (int64_t)row * nx);
+    double lc, ls;
+    lens_factor(q, cx0 + (double)(col - nx / 2) * dx, cy0 + (double)(row - ny / 2) * dy, &lc, &ls);
+    cx<T> f = mk<T>(T(lc), T(ls));
+    if (phase) {
+      T sn, cs;
+      sc<T>(phase[b * pbs + i], &sn, &cs);
+      f = cmul(f, mk<T>(cs, sn));
+    }
+    out[t] = cmul(in[t], f);
+  }
+}
+
+template <typename T>
+__global__ void k_phase_stage_adj(const cx<T>* g, const cx<T>* u, const T* phase, cx<T>* g_in, T* grad, int acc,
+                                  int nx, int ny, double dx, double dy, double cx0, double cy0, double q,
+                                  int64_t npix, int batch, int64_t pbs) {
+  const int64_t total = npix * batch;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = t / npix, i = t - b * npix;
+    const cx<T> gv = g[t];
+    if (g_in) {
+      const int row = (int)(i / nx), col = (int)(i - (int64_t)row * nx);
+      double lc, ls;
+      lens_factor(q, cx0 + (double)(col - nx / 2) * dx, cy0 + (double)(row - ny / 2) * dy, &lc, &ls);
+      cx<T> f = mk<T>(T(lc), T(ls));
+      if (phase) {
+        T sn, cs;
+        sc<T>(phase[b * pbs + i], &sn, &cs);
+        f = cmul(f, mk<T>(cs, sn));
+      }
+      g_in[t] = cmulc(gv, f);
+    }
+    if (grad) {
+      const cx<T> uv = u[t];
+      const T val = gv.y * uv.x - gv.x * uv.y;
+      const int64_t gi = b * pbs + i;
+      grad[gi] = acc ? grad[gi] + val : val;
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_phase_stage(const cx<T>* in, const T* phase, cx<T>* out, int nx, int ny, double dx, double dy,
+                              double cx0, double cy0, double q, int batch, int64_t pbs, hipStream_t s) {
+  const int64_t npix = (int64_t)nx * ny;
+  hipLaunchKernelGGL((k_phase_stage<T>), dim3(ew_blocks(npix * batch)), dim3(256), 0, s, in, phase, out, nx, ny, dx,
+                     dy, cx0, cy0, q, npix, batch, pbs);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_phase_stage_adj(const cx<T>* g, const cx<T>* u, const T* phase, cx<T>* g_in, T* grad, int acc,
+                                  int nx, int ny, double dx, double dy, double cx0, double cy0, double q, int batch,
+                                  int64_t pbs, hipStream_t s) {
+  const int64_t npix = (int64_t)nx * ny;
+  hipLaunchKernelGGL((k_phase_stage_adj<T>), dim3(ew_blocks(npix * batch)), dim3(256), 0, s, g, u, phase, g_in, grad,
+                     acc, nx, ny, dx, dy, cx0, cy0, q, npix, batch, pbs);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------- spot loss --
 template <typename T>
 __global__ __launch_bounds__(256) void k_spot_partial(const cx<T>* ex, const cx<T>* ey, const cx<T>* ez, int nx,
@@ -570,6 +649,10 @@ hipError_t launch_spot_loss(const cx<T>* ex, const cx<T>* ey, const cx<T>* ez, i
   template hipError_t launch_extract_quarter<T>(const cx<double>*, cx<T>*, int, int, hipStream_t);                  \
   template hipError_t launch_zoom_vectors<T>(const ZoomSpec&, cx<T>*, cx<T>*, cx<double>*, hipStream_t);            \
   template hipError_t launch_convert<T>(const cx<double>*, cx<T>*, int64_t, hipStream_t);                           \
+  template hipError_t launch_phase_stage<T>(const cx<T>*, const T*, cx<T>*, int, int, double, double, double,       \
+                                            double, double, int, int64_t, hipStream_t);                             \
+  template hipError_t launch_phase_stage_adj<T>(const cx<T>*, const cx<T>*, const T*, cx<T>*, T*, int, int, int,   \
+                                                double, double, double, double, double, int, int64_t, hipStream_t); \
   template hipError_t launch_modulate<T>(const cx<T>*, const T*, cx<T>*, int64_t, int, int64_t, hipStream_t);      \
   template hipError_t launch_phase_grad<T>(const cx<T>*, const cx<T>*, T*, int64_t, int, int, hipStream_t);         \
   template hipError_t launch_source_gaussian<T>(cx<T>*, int, int, double, double, double, double, double, double,  \

@@ -226,12 +226,21 @@ template <int... Rs> struct Sched {
     return off;
   }
   static constexpr int twsize() { return nst > 1 ? twoff(nst) : 1; }
+  // LDS padding: one element per 2^pad_shift.  With the first radix R0 a
+  // power of two, shift log2(R0) turns the first stage's stride-R0 scatter
+  // into an odd stride (R0 + 1), so a half-wave's writes hit distinct banks.
+  static constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+  static constexpr bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+  static constexpr int pad_shift = (pow2(rad[0]) && rad[0] >= 4) ? ilog2(rad[0]) : 5;
+  static constexpr int line_elems = n + (n >> pad_shift) + 1;
+  __host__ __device__ static constexpr int pad(int i) { return i + (i >> pad_shift); }
 };
 
-__host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 5); }
-__host__ __device__ constexpr int lds_line_elems(int n) { return n + (n >> 5) + 1; }
 
-template <typename T, int DIR, class S, int s, class Load, class Store>
+// HALF_IN: inputs with index >= n/2 are zero (skipped at compile time);
+// HALF_OUT: only outputs with index < n/2 are consumed (the rest is never
+// computed).  Both need an even first (last) radix.
+template <typename T, int DIR, class S, int s, bool HALF_IN, bool HALF_OUT, class Load, class Store>
 __device__ __forceinline__ void ct_stage(cx<T>* __restrict__ lds, const cx<T>* __restrict__ tw, int j,
                                          bool sync_first, Load& load, Store& store) {
   using V = cx<T>;
@@ -239,15 +248,22 @@ __device__ __forceinline__ void ct_stage(cx<T>* __restrict__ lds, const cx<T>* _
   constexpr int nr = S::n / R;
   constexpr int Ns = S::ns(s);
   constexpr bool first = s == 0, last = s == S::nst - 1;
+  constexpr int r_in = (first && HALF_IN) ? R / 2 : R;
+  constexpr int r_out = (last && HALF_OUT) ? R / 2 : R;
+  static_assert(!(first && HALF_IN) || R % 2 == 0, "half input needs an even first radix");
+  static_assert(!(last && HALF_OUT) || R % 2 == 0, "half output needs an even last radix");
   const bool act = j < nr;
   V v[R];
   if (act) {
     if constexpr (first) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[r] = load(j + r * nr);
+      for (int r = 0; r < R; ++r) {
+        if (r < r_in) v[r] = load(j + r * nr);
+        else v[r] = mk<T>(T(0), T(0));
+      }
     } else {
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[r] = lds[lds_pad(j + r * nr)];
+      for (int r = 0; r < R; ++r) v[r] = lds[S::pad(j + r * nr)];
     }
   }
   if (!first || sync_first) __syncthreads();
@@ -265,20 +281,20 @@ __device__ __forceinline__ void ct_stage(cx<T>* __restrict__ lds, const cx<T>* _
     Dft<R, DIR>::template run<T>(v);
     if constexpr (last) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) store(j + r * nr, v[r]);
+      for (int r = 0; r < r_out; ++r) store(j + r * nr, v[r]);
     } else {
       const int base = q * Ns * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds[lds_pad(base + r * Ns)] = v[r];
+      for (int r = 0; r < R; ++r) lds[S::pad(base + r * Ns)] = v[r];
     }
   }
   __syncthreads();
 }
 
-template <typename T, int DIR, class S, class Load, class Store, int... I>
+template <typename T, int DIR, class S, bool HI, bool HO, class Load, class Store, int... I>
 __device__ __forceinline__ void ct_line_impl(cx<T>* lds, const cx<T>* tw, int j, bool sync_first, Load& load,
                                              Store& store, std::integer_sequence<int, I...>) {
-  (ct_stage<T, DIR, S, I>(lds, tw, j, sync_first, load, store), ...);
+  (ct_stage<T, DIR, S, I, HI, HO>(lds, tw, j, sync_first, load, store), ...);
 }
 
 // One transform of one line of length S::n by threads j = 0..S::threads-1.
@@ -286,10 +302,11 @@ __device__ __forceinline__ void ct_line_impl(cx<T>* lds, const cx<T>* tw, int j,
 // DIR = -1: forward (exp(-2 pi i jk/n)); DIR = +1: inverse, unnormalised.
 // load_reads_lds: the load functor reads this workgroup's LDS, so the first
 // stage waits for every read before writing.
-template <typename T, int DIR, class S, class Load, class Store>
+template <typename T, int DIR, class S, bool HALF_IN = false, bool HALF_OUT = false, class Load, class Store>
 __device__ __forceinline__ void fft_line(cx<T>* lds, const cx<T>* tw, int j, Load load, Store store,
                                          bool load_reads_lds = false) {
-  ct_line_impl<T, DIR, S>(lds, tw, j, load_reads_lds, load, store, std::make_integer_sequence<int, S::nst>{});
+  ct_line_impl<T, DIR, S, HALF_IN, HALF_OUT>(lds, tw, j, load_reads_lds, load, store,
+                                            std::make_integer_sequence<int, S::nst>{});
 }
 
 // Host-side description of a length's schedule (for twiddle tables).

@@ -18,12 +18,38 @@ constexpr int kColThreads = 1024;      // thread cap of column-pass workgroups
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
+// Element stride between the LDS lines of one workgroup.  Lanes of a
+// half-wave that belong to different lines must hit different banks:
+// column mode interleaves C lines lane by lane, so lines are offset by
+// 32/C elements modulo 32; row mode with T < 32 threads per line packs
+// 32/T lines per half-wave, so lines are offset by T.
+template <class S, int C, bool COL>
+constexpr int line_stride() {
+  constexpr int base = (S::line_elems + 31) / 32 * 32;
+  constexpr int off = C <= 1 ? 1 : (COL ? (32 / (C < 32 ? C : 32)) % 32 : (S::threads < 32 ? S::threads : 1));
+  return base + off;
+}
+
+// Waves per SIMD that the LDS footprint of a workgroup allows (at most 8):
+// asking the compiler for this occupancy caps its register budget so that
+// registers do not become the tighter limit.
+template <typename T, class S, int C, bool COL, int LPI = 1, int CAP = 4>
+constexpr int waves_per_eu() {
+  constexpr int threads = C * S::threads * LPI;
+  constexpr int wg_waves = (threads + 63) / 64;
+  constexpr int lds = C * LPI * line_stride<S, C, COL>() * (int)sizeof(cx<T>);
+  constexpr int wgs = kLdsBytes / (lds > 0 ? lds : 1);
+  constexpr int w = (wgs * wg_waves) / 4;
+  constexpr int cap = sizeof(T) == 4 ? CAP : 1;  // FP64 kernels: no occupancy request
+  return w < 1 ? 1 : (w > cap ? cap : w);
+}
+
 // Lines per workgroup.  Column passes pack adjacent columns (wide coalesced
 // segments) up to the LDS and thread limits; row passes aim at >= 256
 // threads with at most half the LDS (two workgroups per CU).
 template <typename T, class S, bool COL, int LINES_PER_ITEM = 1, int COL_THREADS = kColThreads>
 struct Cfg {
-  static constexpr int line_bytes = lds_line_elems(S::n) * (int)sizeof(cx<T>) * LINES_PER_ITEM;
+  static constexpr int line_bytes = (S::line_elems + 64) * (int)sizeof(cx<T>) * LINES_PER_ITEM;
   static constexpr int max_threads = COL ? COL_THREADS : 1024;
   static constexpr int c_col = cmax(1, cmin(cmin(16, max_threads / (S::threads * LINES_PER_ITEM)), kLdsBytes / line_bytes));
   static constexpr int c_row =
@@ -61,17 +87,18 @@ __device__ __forceinline__ int64_t line_off(const Lines& L, int b, int l, int i)
 
 // ------------------------------------------------------------ FFT lines --
 template <typename T, int DIR, bool COL, class S, int C>
-__global__ __launch_bounds__(C * S::threads) void k_fft_lines(const cx<T>* in, cx<T>* out, Lines li, Lines lo,
+__global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, COL>())) void k_fft_lines(const cx<T>* in, cx<T>* out, Lines li, Lines lo,
                                                               int nlines, int n_in, int n_out, T scale, int tiles,
                                                               const cx<T>* __restrict__ tw) {
-  __shared__ cx<T> smem[C * lds_line_elems(S::n)];
+  constexpr int LS = line_stride<S, C, COL>();
+  __shared__ cx<T> smem[C * LS];
   const int id = xcd_remap(blockIdx.x, gridDim.x);
   const int b = id / tiles, tile = id - b * tiles;
   const int c = COL ? (int)(threadIdx.x % C) : (int)(threadIdx.x / S::threads);
   const int j = COL ? (int)(threadIdx.x / C) : (int)(threadIdx.x % S::threads);
   const int l = tile * C + c;
   const bool valid = l < nlines;
-  cx<T>* lds = smem + c * lds_line_elems(S::n);
+  cx<T>* lds = smem + c * LS;
   auto load = [&](int i) -> cx<T> {
     cx<T> v = czero<T>();
     if (valid && i < n_in) v = in[line_off<COL>(li, b, l, i)];
@@ -130,18 +157,19 @@ __device__ __forceinline__ cx<T> spec_at(const cx<T>* __restrict__ Sq, int kind,
 // In place on columns kx of W: forward transform of the zero-padded column,
 // multiply by the kernel spectrum (conjugated for the adjoint), inverse
 // transform, keep the first n_valid rows.
-template <typename T, class S, int C>
-__global__ __launch_bounds__(C * S::threads) void k_rs_cols(cx<T>* W, int64_t bstride, int64_t pitch, int ncols,
+template <typename T, class S, int C, bool HALF>
+__global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) void k_rs_cols(cx<T>* W, int64_t bstride, int64_t pitch, int ncols,
                                                             int n_valid, const cx<T>* __restrict__ Sq, int Mx,
                                                             int conj_spec, int tiles, const cx<T>* __restrict__ tw) {
-  __shared__ cx<T> smem[C * lds_line_elems(S::n)];
+  constexpr int LS = line_stride<S, C, true>();
+  __shared__ cx<T> smem[C * LS];
   constexpr int My = S::n;
   const int id = xcd_remap(blockIdx.x, gridDim.x);
   const int b = id / tiles, tile = id - b * tiles;
   const int c = threadIdx.x % C, j = threadIdx.x / C;
   const int kx = tile * C + c;
   const bool valid = kx < ncols;
-  cx<T>* lds = smem + c * lds_line_elems(S::n);
+  cx<T>* lds = smem + c * LS;
   cx<T>* col = W + b * bstride + kx;
   const cx<T>* sq = Sq + (valid ? min(kx, Mx - kx) : 0);
   const int qw = Mx / 2 + 1;
@@ -153,22 +181,30 @@ __global__ __launch_bounds__(C * S::threads) void k_rs_cols(cx<T>* W, int64_t bs
   auto mid = [&](int i, cx<T> v) {
     cx<T> h = czero<T>();
     if (valid) h = sq[(int64_t)min(i, My - i) * qw];
-    lds[lds_pad(i)] = conj_spec ? cmulc(v, h) : cmul(v, h);
+    lds[S::pad(i)] = conj_spec ? cmulc(v, h) : cmul(v, h);
   };
-  fft_line<T, -1, S>(lds, tw, j, load, mid);
-  auto load2 = [&](int i) -> cx<T> { return lds[lds_pad(i)]; };
+  fft_line<T, -1, S, HALF, false>(lds, tw, j, load, mid);
+  auto load2 = [&](int i) -> cx<T> { return lds[S::pad(i)]; };
   auto store = [&](int i, cx<T> v) {
     if (valid && i < n_valid) col[(int64_t)i * pitch] = v;
   };
-  fft_line<T, 1, S>(lds, tw, j, load2, store, true);
+  fft_line<T, 1, S, false, HALF>(lds, tw, j, load2, store, true);
 }
 
 template <typename T, class S, int C>
 hipError_t launch_rs_cols_c(cx<T>* W, int64_t bstride, int64_t pitch, int ncols, int n_valid, const cx<T>* Sq, int Mx,
                             bool conj_spec, int batch, const cx<T>* tw, hipStream_t s) {
   const int tiles = (ncols + C - 1) / C;
-  hipLaunchKernelGGL((k_rs_cols<T, S, C>), dim3(tiles * batch), dim3(C * S::threads), 0, s, W, bstride, pitch, ncols,
-                     n_valid, Sq, Mx, conj_spec ? 1 : 0, tiles, tw);
+  constexpr bool can_half = S::rad[0] % 2 == 0 && S::rad[S::nst - 1] % 2 == 0;
+  if constexpr (can_half) {
+    if (2 * n_valid <= S::n) {
+      hipLaunchKernelGGL((k_rs_cols<T, S, C, true>), dim3(tiles * batch), dim3(C * S::threads), 0, s, W, bstride,
+                         pitch, ncols, n_valid, Sq, Mx, conj_spec ? 1 : 0, tiles, tw);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_rs_cols<T, S, C, false>), dim3(tiles * batch), dim3(C * S::threads), 0, s, W, bstride, pitch,
+                     ncols, n_valid, Sq, Mx, conj_spec ? 1 : 0, tiles, tw);
   return hipGetLastError();
 }
 
@@ -212,9 +248,9 @@ __global__ __launch_bounds__(2 * C * S::threads) void k_mix2_cols(
     const cx<T>* a, const cx<T>* bsrc, cx<T>* out, int64_t bstride, int64_t pitch, int ncols, int n_valid,
     const cx<T>* __restrict__ Sa, int kind_a, T ca, const cx<T>* __restrict__ Sb, int kind_b, T cb, int conj_spec,
     int Mx, int tiles, const cx<T>* __restrict__ tw) {
-  __shared__ cx<T> smem[2 * C * lds_line_elems(S::n)];
+  constexpr int LE = line_stride<S, C, true>();
+  __shared__ cx<T> smem[2 * C * LE];
   constexpr int My = S::n;
-  constexpr int LE = lds_line_elems(S::n);
   const int id = xcd_remap(blockIdx.x, gridDim.x);
   const int bt = id / tiles, tile = id - bt * tiles;
   // thread -> (input slot, column c, butterfly j)
@@ -230,7 +266,7 @@ __global__ __launch_bounds__(2 * C * S::threads) void k_mix2_cols(
     if (valid && i < n_valid) v = src[(int64_t)i * pitch];
     return v;
   };
-  auto st = [&](int i, cx<T> v) { lds[lds_pad(i)] = v; };
+  auto st = [&](int i, cx<T> v) { lds[S::pad(i)] = v; };
   fft_line<T, -1, S>(lds, tw, j, load, st);
   // combine into slot 0 (each (c, k) owned by one thread)
   for (int e = threadIdx.x; e < C * My; e += 2 * C * S::threads) {
@@ -240,7 +276,7 @@ __global__ __launch_bounds__(2 * C * S::threads) void k_mix2_cols(
     cx<T> ha = spec_at(Sa, kind_a, kxx, k, Mx, My);
     cx<T> hb = spec_at(Sb, kind_b, kxx, k, Mx, My);
     if (conj_spec) { ha.y = -ha.y; hb.y = -hb.y; }
-    const int p = lds_pad(k);
+    const int p = S::pad(k);
     const cx<T> va = smem[cc * LE + p], vb = smem[(C + cc) * LE + p];
     const cx<T> r = cadd(cscale(cmul(va, ha), ca), cscale(cmul(vb, hb), cb));
     smem[cc * LE + p] = r;
@@ -250,7 +286,7 @@ __global__ __launch_bounds__(2 * C * S::threads) void k_mix2_cols(
   // an out-of-range butterfly index and only meet the barriers
   cx<T>* dst = out + bt * bstride + kx;
   cx<T>* lds0 = smem + c * LE;
-  auto load2 = [&](int i) -> cx<T> { return lds0[lds_pad(i)]; };
+  auto load2 = [&](int i) -> cx<T> { return lds0[S::pad(i)]; };
   auto store = [&](int i, cx<T> v) {
     if (valid && i < n_valid) dst[(int64_t)i * pitch] = v;
   };
@@ -261,7 +297,7 @@ template <typename T, class S>
 hipError_t launch_mix2_cols_s(const cx<T>* a, const cx<T>* b, cx<T>* out, int64_t bstride, int64_t pitch, int ncols,
                               int n_valid, const cx<T>* Sa, int kind_a, T ca, const cx<T>* Sb, int kind_b, T cb,
                               bool conj_spec, int Mx, int batch, const cx<T>* tw, hipStream_t s) {
-  using CF = Cfg<T, S, true, 2>;
+  using CF = Cfg<T, S, true, 2, 512>;
   if constexpr (!CF::fits) {
     return hipErrorInvalidValue;
   } else {
@@ -291,33 +327,52 @@ hipError_t launch_mix2_cols(int My, const cx<T>* a, const cx<T>* b, cx<T>* out, 
 
 // ----------------------------------------------------------- Bluestein --
 // out[p] = post[p] * IFFT_L( FFT_L(pad(pre .* in)) .* chat )[p], p < n_out.
-template <typename T, bool COL, class S, int C>
-__global__ __launch_bounds__(C * S::threads) void k_bluestein(const cx<T>* in, cx<T>* out, Lines li, Lines lo,
+template <typename T, bool COL, class S, int C, bool HALF>
+__global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, COL, 1, HALF ? (COL ? 4 : 3) : 2>())) void k_bluestein(const cx<T>* in, cx<T>* out, Lines li, Lines lo,
                                                               int nlines, int n_in, int n_out,
                                                               const cx<T>* __restrict__ pre,
                                                               const cx<T>* __restrict__ chat,
                                                               const cx<T>* __restrict__ post, int tiles,
                                                               const cx<T>* __restrict__ tw) {
-  __shared__ cx<T> smem[C * lds_line_elems(S::n)];
+  constexpr int LS = line_stride<S, C, COL>();
+  __shared__ cx<T> smem[C * LS];
   const int id = xcd_remap(blockIdx.x, gridDim.x);
   const int b = id / tiles, tile = id - b * tiles;
   const int c = COL ? (int)(threadIdx.x % C) : (int)(threadIdx.x / S::threads);
   const int j = COL ? (int)(threadIdx.x / C) : (int)(threadIdx.x % S::threads);
   const int l = tile * C + c;
   const bool valid = l < nlines;
-  cx<T>* lds = smem + c * lds_line_elems(S::n);
+  cx<T>* lds = smem + c * LS;
   auto load = [&](int i) -> cx<T> {
     cx<T> v = czero<T>();
     if (valid && i < n_in) v = cmul(in[line_off<COL>(li, b, l, i)], pre[i]);
     return v;
   };
-  auto mid = [&](int i, cx<T> v) { lds[lds_pad(i)] = cmul(v, chat[i]); };
-  fft_line<T, -1, S>(lds, tw, j, load, mid);
-  auto load2 = [&](int i) -> cx<T> { return lds[lds_pad(i)]; };
+  auto mid = [&](int i, cx<T> v) { lds[S::pad(i)] = cmul(v, chat[i]); };
+  fft_line<T, -1, S, HALF, false>(lds, tw, j, load, mid);
+  auto load2 = [&](int i) -> cx<T> { return lds[S::pad(i)]; };
   auto store = [&](int i, cx<T> v) {
     if (valid && i < n_out) out[line_off<COL>(lo, b, l, i)] = cmul(v, post[i]);
   };
-  fft_line<T, 1, S>(lds, tw, j, load2, store, true);
+  fft_line<T, 1, S, false, HALF>(lds, tw, j, load2, store, true);
+}
+
+template <typename T, bool COL, class S, int C>
+hipError_t launch_bluestein_c(const cx<T>* in, cx<T>* out, Lines li, Lines lo, int nlines, int n_in, int n_out,
+                              const cx<T>* pre, const cx<T>* chat, const cx<T>* post, int batch, const cx<T>* tw,
+                              hipStream_t s) {
+  const int tiles = (nlines + C - 1) / C;
+  constexpr bool can_half = S::rad[0] % 2 == 0 && S::rad[S::nst - 1] % 2 == 0;
+  if constexpr (can_half) {
+    if (2 * n_in <= S::n && 2 * n_out <= S::n) {
+      hipLaunchKernelGGL((k_bluestein<T, COL, S, C, true>), dim3(tiles * batch), dim3(C * S::threads), 0, s, in, out,
+                         li, lo, nlines, n_in, n_out, pre, chat, post, tiles, tw);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_bluestein<T, COL, S, C, false>), dim3(tiles * batch), dim3(C * S::threads), 0, s, in, out, li,
+                     lo, nlines, n_in, n_out, pre, chat, post, tiles, tw);
+  return hipGetLastError();
 }
 
 template <typename T, bool COL, class S>
@@ -331,17 +386,10 @@ hipError_t launch_bluestein_s(const cx<T>* in, cx<T>* out, Lines li, Lines lo, i
     return hipErrorInvalidValue;
   } else {
     if constexpr (COL && S::n == 4096 && sizeof(T) == 4) {
-      if (col_lines_override() == 1) {
-        const int tiles = nlines;
-        hipLaunchKernelGGL((k_bluestein<T, COL, S, 1>), dim3(tiles * batch), dim3(S::threads), 0, s, in, out, li, lo,
-                           nlines, n_in, n_out, pre, chat, post, tiles, tw);
-        return hipGetLastError();
-      }
+      if (col_lines_override() == 1)
+        return launch_bluestein_c<T, COL, S, 1>(in, out, li, lo, nlines, n_in, n_out, pre, chat, post, batch, tw, s);
     }
-    const int tiles = (nlines + CF::C - 1) / CF::C;
-    hipLaunchKernelGGL((k_bluestein<T, COL, S, CF::C>), dim3(tiles * batch), dim3(CF::threads), 0, s, in, out, li, lo,
-                       nlines, n_in, n_out, pre, chat, post, tiles, tw);
-    return hipGetLastError();
+    return launch_bluestein_c<T, COL, S, CF::C>(in, out, li, lo, nlines, n_in, n_out, pre, chat, post, batch, tw, s);
   }
 }
 

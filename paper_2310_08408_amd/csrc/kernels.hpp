@@ -98,6 +98,18 @@ hipError_t launch_jones_grad(const cx<T>* gx, const cx<T>* gy, const cx<T>* ex, 
                              const double* dJ /* 2 x 4 complex */, double* out, double* partial,
                              int nblk, int64_t npix, int batch, hipStream_t s);
 
+// input stage of a plan setup: out = in exp(i phase) exp(-i q r^2) (phase may
+// be null, q = k/(2f) of a thin lens or 0), phase batch stride pbs (0 =
+// shared); adjoint: g_in = g conj(factor) (if g_in), grad (+)= Im(g conj(u))
+// (if grad; grad has the phase's layout).
+template <typename T>
+hipError_t launch_phase_stage(const cx<T>* in, const T* phase, cx<T>* out, int nx, int ny, double dx, double dy,
+                              double cx0, double cy0, double q, int batch, int64_t pbs, hipStream_t s);
+template <typename T>
+hipError_t launch_phase_stage_adj(const cx<T>* g, const cx<T>* u, const T* phase, cx<T>* g_in, T* grad, int acc,
+                                  int nx, int ny, double dx, double dy, double cx0, double cy0, double q, int batch,
+                                  int64_t pbs, hipStream_t s);
+
 // focusing pupil map (real 3x2 per sample, 1/sqrt(sz) apodisation folded in)
 template <typename T>
 hipError_t launch_pupil(const cx<T>* ex, const cx<T>* ey, cx<T>* o0, cx<T>* o1, cx<T>* o2,
@@ -122,8 +134,9 @@ hipError_t launch_vczt_adj_combine(cx<T>* gex, cx<T>* gey, const cx<T>* cxg, con
                                    const cx<T>* cz, int nx, int ny, double dx, double dy,
                                    double cx0, double cy0, double z, int batch, hipStream_t s);
 
-// spot-size / E_z-fraction loss: per batch item res[b*4 + {0..3}] =
-// (loss, sigma2, fz, P); seeds g_c = 2 E_c dL/dI_c (optional).
+// spot-size / E_z-fraction loss: per batch item res[b*8 + {0..5}] =
+// (loss, sigma2, fz, P, Xbar - cx, Ybar - cy); seeds g_c = 2 E_c dL/dI_c
+// (optional).
 template <typename T>
 hipError_t launch_spot_loss(const cx<T>* ex, const cx<T>* ey, const cx<T>* ez, int nx, int ny,
                             double dx, double dy, double cx0, double cy0, double wavelength,

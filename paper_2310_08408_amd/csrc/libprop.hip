@@ -54,6 +54,11 @@ static Tracer& tracer() {
   static Tracer* t = new Tracer();
   return *t;
 }
+static bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+  return st != hipStreamCaptureStatusNone;
+}
 static hipEvent_t take_event() {
   Tracer& t = tracer();
   if (!t.pool.empty()) {
@@ -69,7 +74,7 @@ static hipEvent_t take_event() {
   do {                                                                                  \
     Tracer& tr_ = tracer();                                                             \
     hipEvent_t ea_ = nullptr, eb_ = nullptr;                                            \
-    if (tr_.on) {                                                                       \
+    if (tr_.on && !capturing(S)) {                                                      \
       ea_ = take_event();                                                               \
       eb_ = take_event();                                                               \
       if (ea_) (void)hipEventRecord(ea_, S);                                            \
@@ -340,9 +345,13 @@ static int sampling(const prop_grid* g, double wl, double z) {
 }
 
 // ------------------------------------------------------------- RS runs --
+static size_t rs_work_bytes(prop_dtype t, const prop_grid* g, int batch) {
+  return (size_t)g->ny * fft_len(2 * g->nx - 1) * batch * esize(t);
+}
+
 template <typename T>
 static int rs_run(const void* in, void* out, const prop_grid* g, double wl, double z, int batch, hipStream_t s,
-                  bool adjoint) {
+                  bool adjoint, void* work) {
   int dev;
   LP_RET(cur_device(&dev));
   const cx<T>* q[3];
@@ -352,10 +361,8 @@ static int rs_run(const void* in, void* out, const prop_grid* g, double wl, doub
   LP_RET(get_tw<T>(dev, Mx, &twx));
   LP_RET(get_tw<T>(dev, My, &twy));
   const int nx = g->nx, ny = g->ny;
-  Buf& wb = ctx().work[{dev, s}];
   const int64_t plane = (int64_t)ny * Mx;
-  LP_RET(ensure_buf(wb, (size_t)plane * batch * sizeof(cx<T>), s));
-  cx<T>* W = (cx<T>*)wb.p;
+  cx<T>* W = (cx<T>*)work;
   const T scale = (T)(g->dx * g->dy / ((double)Mx * (double)My));
   // P1: row transforms of the ny input rows, zero-padded to Mx
   const double es = sizeof(cx<T>);
@@ -386,15 +393,21 @@ static int rs_entry(prop_dtype t, const void* in, void* out, const prop_grid* g,
   LP_RET(check_alias({{in, bytes}}, {{out, bytes}}));
   std::lock_guard<std::mutex> lk(ctx().mu);
   const hipStream_t s = (hipStream_t)stream;
-  int r = t == PROP_C64 ? rs_run<float>(in, out, g, wl, z, batch, s, adjoint)
-                        : rs_run<double>(in, out, g, wl, z, batch, s, adjoint);
+  int dev;
+  LP_RET(cur_device(&dev));
+  Buf& wb = ctx().work[{dev, s}];
+  LP_RET(ensure_buf(wb, rs_work_bytes(t, g, batch), s));
+  int r = t == PROP_C64 ? rs_run<float>(in, out, g, wl, z, batch, s, adjoint, wb.p)
+                        : rs_run<double>(in, out, g, wl, z, batch, s, adjoint, wb.p);
   return r < 0 ? r : warn;
 }
 
 // ------------------------------------------------------------ VRS runs --
+static size_t vrs_work_bytes(prop_dtype t, const prop_grid* g, int batch) { return 3 * rs_work_bytes(t, g, batch); }
+
 template <typename T>
 static int vrs_run(const void* const* ins, int nin, void* const* outs, int nout, const prop_grid* g, double wl,
-                   double z, int batch, hipStream_t s, bool adjoint) {
+                   double z, int batch, hipStream_t s, bool adjoint, void* work) {
   int dev;
   LP_RET(cur_device(&dev));
   const cx<T>* q[3];
@@ -406,10 +419,8 @@ static int vrs_run(const void* const* ins, int nin, void* const* outs, int nout,
   const int nx = g->nx, ny = g->ny;
   const int64_t pst = (int64_t)ny * Mx;
   const size_t plane = (size_t)pst * batch;
-  Buf& wb = ctx().work[{dev, s}];
-  LP_RET(ensure_buf(wb, 3 * plane * sizeof(cx<T>), s));
   cx<T>* W[3];
-  for (int i = 0; i < 3; ++i) W[i] = (cx<T>*)wb.p + i * plane;
+  for (int i = 0; i < 3; ++i) W[i] = (cx<T>*)work + i * plane;
   const double es = sizeof(cx<T>);
   const double qel = (double)(Mx / 2 + 1) * (My / 2 + 1);
   const double pl = (double)batch * ny * Mx;
@@ -555,14 +566,16 @@ static size_t czt_tmp_elems(const prop_grid* gi, const prop_grid* go) {
   return std::max((size_t)gi->ny * go->nx, (size_t)go->ny * gi->nx);
 }
 
+static size_t czt_work_bytes(prop_dtype t, const prop_grid* gi, const prop_grid* go, int batch) {
+  return czt_tmp_elems(gi, go) * batch * esize(t);
+}
+
 template <typename T>
 static int czt_run(const void* in, void* out, const prop_grid* gi, const prop_grid* go, double wl, double z, int batch,
-                   hipStream_t s, bool adjoint) {
+                   hipStream_t s, bool adjoint, void* work) {
   int dev;
   LP_RET(cur_device(&dev));
-  Buf& wb = ctx().work[{dev, s}];
-  LP_RET(ensure_buf(wb, czt_tmp_elems(gi, go) * batch * sizeof(cx<T>), s));
-  return czt_core<T>(dev, (const cx<T>*)in, (cx<T>*)out, gi, go, wl, z, batch, (cx<T>*)wb.p, s, adjoint);
+  return czt_core<T>(dev, (const cx<T>*)in, (cx<T>*)out, gi, go, wl, z, batch, (cx<T>*)work, s, adjoint);
 }
 
 static int czt_entry(prop_dtype t, const void* in, void* out, const prop_grid* gi, const prop_grid* go, double wl,
@@ -579,21 +592,30 @@ static int czt_entry(prop_dtype t, const void* in, void* out, const prop_grid* g
   else LP_RET(check_alias({{in, bo}}, {{out, bi}}));
   std::lock_guard<std::mutex> lk(ctx().mu);
   const hipStream_t s = (hipStream_t)stream;
-  return t == PROP_C64 ? czt_run<float>(in, out, gi, go, wl, z, batch, s, adjoint)
-                       : czt_run<double>(in, out, gi, go, wl, z, batch, s, adjoint);
+  int dev;
+  LP_RET(cur_device(&dev));
+  Buf& wb = ctx().work[{dev, s}];
+  LP_RET(ensure_buf(wb, czt_work_bytes(t, gi, go, batch), s));
+  return t == PROP_C64 ? czt_run<float>(in, out, gi, go, wl, z, batch, s, adjoint, wb.p)
+                       : czt_run<double>(in, out, gi, go, wl, z, batch, s, adjoint, wb.p);
 }
 
 // ----------------------------------------------------------- VCZT runs --
+static size_t vczt_work_bytes(prop_dtype t, const prop_grid* gi, const prop_grid* go, bool lens, int batch) {
+  const size_t ni = (size_t)gi->nx * gi->ny * batch, no = (size_t)go->nx * go->ny * batch;
+  const size_t nt = czt_tmp_elems(gi, go) * batch;
+  const size_t nm = (size_t)gi->ny * go->nx * batch;
+  const size_t need = lens ? 3 * (ni + nm) : std::max(ni + no + nt, 2 * no + 3 * ni + nt);
+  return need * esize(t);
+}
+
 template <typename T>
 static int vczt_free_fwd(const void* ex, const void* ey, void* ox, void* oy, void* oz, const prop_grid* gi,
-                         const prop_grid* go, double wl, double z, int batch, hipStream_t s) {
+                         const prop_grid* go, double wl, double z, int batch, hipStream_t s, void* work) {
   int dev;
   LP_RET(cur_device(&dev));
   const size_t ni = (size_t)gi->nx * gi->ny * batch, no = (size_t)go->nx * go->ny * batch;
-  const size_t nt = czt_tmp_elems(gi, go) * batch;
-  Buf& wb = ctx().work[{dev, s}];
-  LP_RET(ensure_buf(wb, (ni + no + nt) * sizeof(cx<T>), s));
-  cx<T>* prep = (cx<T>*)wb.p;
+  cx<T>* prep = (cx<T>*)work;
   cx<T>* c2 = prep + ni;
   cx<T>* tmp = c2 + no;
   LP_TRY(launch_vczt_prep<T>((const cx<T>*)ex, (const cx<T>*)ey, prep, gi->nx, gi->ny, gi->dx, gi->dy, gi->cx, gi->cy,
@@ -608,14 +630,11 @@ static int vczt_free_fwd(const void* ex, const void* ey, void* ox, void* oy, voi
 
 template <typename T>
 static int vczt_free_adj(const void* gx, const void* gy, const void* gz, void* gex, void* gey, const prop_grid* gi,
-                         const prop_grid* go, double wl, double z, int batch, hipStream_t s) {
+                         const prop_grid* go, double wl, double z, int batch, hipStream_t s, void* work) {
   int dev;
   LP_RET(cur_device(&dev));
   const size_t ni = (size_t)gi->nx * gi->ny * batch, no = (size_t)go->nx * go->ny * batch;
-  const size_t nt = czt_tmp_elems(gi, go) * batch;
-  Buf& wb = ctx().work[{dev, s}];
-  LP_RET(ensure_buf(wb, (2 * no + 3 * ni + nt) * sizeof(cx<T>), s));
-  cx<T>* xg = (cx<T>*)wb.p;
+  cx<T>* xg = (cx<T>*)work;
   cx<T>* yg = xg + no;
   cx<T>* a2 = yg + no;
   cx<T>* a3 = a2 + ni;
@@ -635,14 +654,12 @@ static int vczt_free_adj(const void* gx, const void* gy, const void* gz, void* g
 
 template <typename T>
 static int rw_fwd(const void* ex, const void* ey, void* const* outs, const prop_grid* gi, const prop_grid* go,
-                  double wl, const prop_lens* lens, int batch, hipStream_t s) {
+                  double wl, const prop_lens* lens, int batch, hipStream_t s, void* work) {
   int dev;
   LP_RET(cur_device(&dev));
   const size_t ni = (size_t)gi->nx * gi->ny * batch;
   const size_t nm = (size_t)gi->ny * go->nx * batch;
-  Buf& wb = ctx().work[{dev, s}];
-  LP_RET(ensure_buf(wb, 3 * (ni + nm) * sizeof(cx<T>), s));
-  cx<T>* P = (cx<T>*)wb.p;
+  cx<T>* P = (cx<T>*)work;
   cx<T>* M = P + 3 * ni;
   const double es = sizeof(cx<T>);
   LP_TRACE("rw_pupil", es * 5.0 * ni, s,
@@ -669,14 +686,12 @@ static int rw_fwd(const void* ex, const void* ey, void* const* outs, const prop_
 
 template <typename T>
 static int rw_adj(const void* const* gs, void* gex, void* gey, const prop_grid* gi, const prop_grid* go, double wl,
-                  const prop_lens* lens, int batch, hipStream_t s) {
+                  const prop_lens* lens, int batch, hipStream_t s, void* work) {
   int dev;
   LP_RET(cur_device(&dev));
   const size_t ni = (size_t)gi->nx * gi->ny * batch;
   const size_t nm = (size_t)gi->ny * go->nx * batch;
-  Buf& wb = ctx().work[{dev, s}];
-  LP_RET(ensure_buf(wb, 3 * (ni + nm) * sizeof(cx<T>), s));
-  cx<T>* P = (cx<T>*)wb.p;
+  cx<T>* P = (cx<T>*)work;
   cx<T>* M = P + 3 * ni;
   ZoomSpec zx, zy;
   rw_specs(gi, go, wl, lens, true, &zx, &zy);
@@ -747,6 +762,205 @@ static void jones_derivs(double eta, double theta, double d[16]) {
   for (int k = 0; k < 4; ++k) { d[8 + 2 * k] = br * n[k]; d[8 + 2 * k + 1] = bi * n[k]; }
 }
 
+
+// ---------------------------------------------------------------- plans --
+struct PlanSetup {
+  prop_setup s;
+  int ncomp_in = 1;
+  bool modulated = false;
+  void* umod = nullptr;  // modulated input (ncomp_in planes) kept for the adjoint
+};
+
+}  // namespace lp
+
+struct prop_plan {
+  prop_dtype t;
+  int dev = 0;
+  uint32_t flags = 0;
+  std::vector<lp::PlanSetup> setups;
+  int nbranch = 1;
+  std::vector<lp::Buf> work;    // per branch
+  std::vector<lp::Buf> gbuf;    // per branch: adjoint g_u planes
+  std::vector<hipStream_t> br;  // capture streams (graph mode)
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+};
+
+namespace lp {
+
+static int ncomp_in(int op) { return (op == PROP_OP_VRS || op == PROP_OP_VCZT) ? 2 : 1; }
+static int ncomp_out(int op) { return (op == PROP_OP_VRS || op == PROP_OP_VCZT) ? 3 : 1; }
+
+static int validate_setup(prop_dtype t, const prop_setup& s) {
+  if (s.op < PROP_OP_RS || s.op > PROP_OP_VCZT) return PROP_ESHAPE;
+  LP_RET(check_common(t, s.batch, s.wavelength));
+  if (s.batch < 1) return PROP_ESHAPE;
+  LP_RET(check_grid(&s.g_in));
+  const bool lensmode = s.op == PROP_OP_VCZT && s.has_lens;
+  if (s.op == PROP_OP_CZT || s.op == PROP_OP_VCZT) {
+    LP_RET(check_grid(&s.win));
+    LP_RET(check_czt_shapes(&s.g_in, &s.win));
+  } else if (fft_len(2 * s.g_in.nx - 1) < 0 || fft_len(2 * s.g_in.ny - 1) < 0) {
+    return PROP_ESHAPE;
+  }
+  if (lensmode) LP_RET(check_lens(&s.lens));
+  if (!lensmode && (!(s.z > 0) || !is_finite(s.z))) return PROP_EPARAM;
+  if (!is_finite(s.lens_f) || s.lens_f < 0) return PROP_EPARAM;
+  for (int c = 0; c < ncomp_in(s.op); ++c)
+    if (!s.in[c]) return PROP_ENULL;
+  for (int c = 0; c < ncomp_out(s.op); ++c)
+    if (!s.out[c] || !s.gout[c]) return PROP_ENULL;
+  return PROP_OK;
+}
+
+static size_t setup_work_bytes(prop_dtype t, const prop_setup& s) {
+  switch (s.op) {
+    case PROP_OP_RS: return rs_work_bytes(t, &s.g_in, s.batch);
+    case PROP_OP_VRS: return vrs_work_bytes(t, &s.g_in, s.batch);
+    case PROP_OP_CZT: return czt_work_bytes(t, &s.g_in, &s.win, s.batch);
+    default: return vczt_work_bytes(t, &s.g_in, &s.win, s.has_lens != 0, s.batch);
+  }
+}
+
+// Fill the caches (spectra, chirps, twiddles) a setup needs, on stream s.
+template <typename T>
+static int warm_setup(int dev, const prop_setup& s, hipStream_t st) {
+  const cx<T>* q[3];
+  const cx<T>* tw;
+  int Mx, My;
+  const cx<T> *a, *b, *c;
+  ZoomSpec zx, zy;
+  switch (s.op) {
+    case PROP_OP_RS:
+    case PROP_OP_VRS:
+      LP_RET(get_rs_spectra<T>(dev, &s.g_in, s.wavelength, s.z, s.op == PROP_OP_VRS, st, q, &Mx, &My));
+      LP_RET(get_tw<T>(dev, Mx, &tw));
+      LP_RET(get_tw<T>(dev, My, &tw));
+      return PROP_OK;
+    default:
+      for (int adj = 0; adj < 2; ++adj) {
+        if (s.op == PROP_OP_VCZT && s.has_lens) rw_specs(&s.g_in, &s.win, s.wavelength, &s.lens, adj, &zx, &zy);
+        else czt_specs(&s.g_in, &s.win, s.wavelength, s.z, adj, &zx, &zy);
+        LP_RET(get_zoom<T>(dev, zx, st, &a, &b, &c));
+        LP_RET(get_zoom<T>(dev, zy, st, &a, &b, &c));
+        LP_RET(get_tw<T>(dev, zx.L, &tw));
+        LP_RET(get_tw<T>(dev, zy.L, &tw));
+      }
+      return PROP_OK;
+  }
+}
+
+template <typename T>
+static int run_setup(prop_plan* p, PlanSetup& ps, bool adjoint, hipStream_t st, int branch) {
+  const prop_setup& s = ps.s;
+  void* work = p->work[branch].p;
+  const int64_t npix = (int64_t)s.g_in.nx * s.g_in.ny;
+  const double q = s.lens_f > 0 ? (2.0 * kPi / s.wavelength) / (2.0 * s.lens_f) : 0.0;
+  const int nin = ps.ncomp_in, nout = ncomp_out(s.op);
+  const size_t plane = (size_t)npix * s.batch;
+  const T* phase = (const T*)s.phase;
+  if (!adjoint) {
+    const void* u[2] = {s.in[0], s.in[1]};
+    if (ps.modulated) {
+      for (int c = 0; c < nin; ++c) {
+        cx<T>* dst = (cx<T>*)ps.umod + c * plane;
+        LP_TRACE("plan_input", (double)plane * (2 * sizeof(cx<T>) + (phase ? sizeof(T) : 0)), st,
+                 launch_phase_stage<T>((const cx<T>*)s.in[c], phase, dst, s.g_in.nx, s.g_in.ny, s.g_in.dx, s.g_in.dy,
+                                       s.g_in.cx, s.g_in.cy, q, s.batch, npix, st));
+        u[c] = dst;
+      }
+    }
+    switch (s.op) {
+      case PROP_OP_RS: return rs_run<T>(u[0], s.out[0], &s.g_in, s.wavelength, s.z, s.batch, st, false, work);
+      case PROP_OP_CZT:
+        return czt_run<T>(u[0], s.out[0], &s.g_in, &s.win, s.wavelength, s.z, s.batch, st, false, work);
+      case PROP_OP_VRS:
+        return vrs_run<T>(u, 2, s.out, 3, &s.g_in, s.wavelength, s.z, s.batch, st, false, work);
+      default:
+        if (s.has_lens) return rw_fwd<T>(u[0], u[1], s.out, &s.g_in, &s.win, s.wavelength, &s.lens, s.batch, st, work);
+        return vczt_free_fwd<T>(u[0], u[1], s.out[0], s.out[1], s.out[2], &s.g_in, &s.win, s.wavelength, s.z, s.batch,
+                                st, work);
+    }
+  }
+  // adjoint: g_u lands in gin directly when there is no input stage
+  void* gu[2] = {s.gin[0], s.gin[1]};
+  if (ps.modulated) {
+    for (int c = 0; c < nin; ++c) gu[c] = (char*)p->gbuf[branch].p + c * plane * sizeof(cx<T>);
+  }
+  switch (s.op) {
+    case PROP_OP_RS: LP_RET(rs_run<T>(s.gout[0], gu[0], &s.g_in, s.wavelength, s.z, s.batch, st, true, work)); break;
+    case PROP_OP_CZT:
+      LP_RET(czt_run<T>(s.gout[0], gu[0], &s.g_in, &s.win, s.wavelength, s.z, s.batch, st, true, work));
+      break;
+    case PROP_OP_VRS:
+      LP_RET(vrs_run<T>(s.gout, 3, gu, 2, &s.g_in, s.wavelength, s.z, s.batch, st, true, work));
+      break;
+    default:
+      if (s.has_lens) LP_RET(rw_adj<T>(s.gout, gu[0], gu[1], &s.g_in, &s.win, s.wavelength, &s.lens, s.batch, st, work));
+      else LP_RET(vczt_free_adj<T>(s.gout[0], s.gout[1], s.gout[2], gu[0], gu[1], &s.g_in, &s.win, s.wavelength, s.z,
+                                  s.batch, st, work));
+  }
+  if (ps.modulated) {
+    for (int c = 0; c < nin; ++c) {
+      const cx<T>* u = (const cx<T>*)ps.umod + c * plane;
+      LP_TRACE("plan_input_adj", (double)plane * 3 * sizeof(cx<T>), st,
+               launch_phase_stage_adj<T>((const cx<T>*)gu[c], u, phase, (cx<T>*)s.gin[c], (T*)s.grad_phase, c > 0 ? 1 : 0,
+                                         s.g_in.nx, s.g_in.ny, s.g_in.dx, s.g_in.dy, s.g_in.cx, s.g_in.cy, q, s.batch,
+                                         npix, st));
+    }
+  }
+  return PROP_OK;
+}
+
+// Enqueue all setups: sequentially on `st`, or over the plan's branch
+// streams (fork/join through events) when `branched`.
+static int plan_enqueue(prop_plan* p, bool adjoint, hipStream_t st, bool branched) {
+  if (branched) {
+    LP_TRY(hipEventRecord(p->fork, st));
+    for (int b = 0; b < p->nbranch; ++b) LP_TRY(hipStreamWaitEvent(p->br[b], p->fork, 0));
+  }
+  for (size_t i = 0; i < p->setups.size(); ++i) {
+    const int b = branched ? (int)(i % p->nbranch) : 0;
+    const hipStream_t s = branched ? p->br[b] : st;
+    LP_RET(p->t == PROP_C64 ? run_setup<float>(p, p->setups[i], adjoint, s, b)
+                            : run_setup<double>(p, p->setups[i], adjoint, s, b));
+  }
+  if (branched) {
+    for (int b = 0; b < p->nbranch; ++b) {
+      LP_TRY(hipEventRecord(p->join[b], p->br[b]));
+      LP_TRY(hipStreamWaitEvent(st, p->join[b], 0));
+    }
+  }
+  return PROP_OK;
+}
+
+static int plan_run(prop_plan* p, bool adjoint, hipStream_t st) {
+  if (!(p->flags & PROP_PLAN_GRAPH)) return plan_enqueue(p, adjoint, st, false);
+  hipGraphExec_t& ex = p->gexec[adjoint ? 1 : 0];
+  if (!ex) {
+    // capture on the first branch stream, forking to the others
+    hipStream_t origin = p->br[0];
+    hipGraph_t graph = nullptr;
+    LP_TRY(hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal));
+    int r = plan_enqueue(p, adjoint, origin, p->nbranch > 1);
+    hipError_t e = hipStreamEndCapture(origin, &graph);
+    if (r < 0) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return r;
+    }
+    if (e != hipSuccess) return dev_err(e);
+    e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      ex = nullptr;
+      return dev_err(e);
+    }
+  }
+  LP_TRY(hipGraphLaunch(ex, st));
+  return PROP_OK;
+}
+
 }  // namespace lp
 
 using namespace lp;
@@ -789,8 +1003,12 @@ int vrs_propagate(prop_dtype t, const void* ex, const void* ey, void* ox, void* 
   const void* ins[2] = {ex, ey};
   void* outs[3] = {ox, oy, oz};
   const hipStream_t s = (hipStream_t)stream;
-  int r = t == PROP_C64 ? vrs_run<float>(ins, 2, outs, 3, g, wavelength, z, batch, s, false)
-                        : vrs_run<double>(ins, 2, outs, 3, g, wavelength, z, batch, s, false);
+  int dev;
+  LP_RET(cur_device(&dev));
+  Buf& wb = ctx().work[{dev, s}];
+  LP_RET(ensure_buf(wb, vrs_work_bytes(t, g, batch), s));
+  int r = t == PROP_C64 ? vrs_run<float>(ins, 2, outs, 3, g, wavelength, z, batch, s, false, wb.p)
+                        : vrs_run<double>(ins, 2, outs, 3, g, wavelength, z, batch, s, false, wb.p);
   return r < 0 ? r : warn;
 }
 
@@ -809,8 +1027,12 @@ int vrs_adjoint(prop_dtype t, const void* gx, const void* gy, const void* gz, vo
   const void* ins[3] = {gx, gy, gz};
   void* outs[2] = {gex, gey};
   const hipStream_t s = (hipStream_t)stream;
-  int r = t == PROP_C64 ? vrs_run<float>(ins, 3, outs, 2, g, wavelength, z, batch, s, true)
-                        : vrs_run<double>(ins, 3, outs, 2, g, wavelength, z, batch, s, true);
+  int dev;
+  LP_RET(cur_device(&dev));
+  Buf& wb = ctx().work[{dev, s}];
+  LP_RET(ensure_buf(wb, vrs_work_bytes(t, g, batch), s));
+  int r = t == PROP_C64 ? vrs_run<float>(ins, 3, outs, 2, g, wavelength, z, batch, s, true, wb.p)
+                        : vrs_run<double>(ins, 3, outs, 2, g, wavelength, z, batch, s, true, wb.p);
   return r < 0 ? r : warn;
 }
 
@@ -830,12 +1052,16 @@ int vczt_propagate(prop_dtype t, const void* ex, const void* ey, void* ox, void*
   LP_RET(check_alias({{ex, bi}, {ey, bi}}, {{ox, bo}, {oy, bo}, {oz, bo}}));
   std::lock_guard<std::mutex> lk(ctx().mu);
   const hipStream_t s = (hipStream_t)stream;
+  int dev;
+  LP_RET(cur_device(&dev));
+  Buf& wb = ctx().work[{dev, s}];
+  LP_RET(ensure_buf(wb, vczt_work_bytes(t, g_in, win, lens != nullptr, batch), s));
   void* outs[3] = {ox, oy, oz};
   if (lens)
-    return t == PROP_C64 ? rw_fwd<float>(ex, ey, outs, g_in, win, wavelength, lens, batch, s)
-                         : rw_fwd<double>(ex, ey, outs, g_in, win, wavelength, lens, batch, s);
-  return t == PROP_C64 ? vczt_free_fwd<float>(ex, ey, ox, oy, oz, g_in, win, wavelength, z, batch, s)
-                       : vczt_free_fwd<double>(ex, ey, ox, oy, oz, g_in, win, wavelength, z, batch, s);
+    return t == PROP_C64 ? rw_fwd<float>(ex, ey, outs, g_in, win, wavelength, lens, batch, s, wb.p)
+                         : rw_fwd<double>(ex, ey, outs, g_in, win, wavelength, lens, batch, s, wb.p);
+  return t == PROP_C64 ? vczt_free_fwd<float>(ex, ey, ox, oy, oz, g_in, win, wavelength, z, batch, s, wb.p)
+                       : vczt_free_fwd<double>(ex, ey, ox, oy, oz, g_in, win, wavelength, z, batch, s, wb.p);
 }
 
 int vczt_adjoint(prop_dtype t, const void* gx, const void* gy, const void* gz, void* gex, void* gey,
@@ -854,13 +1080,17 @@ int vczt_adjoint(prop_dtype t, const void* gx, const void* gy, const void* gz, v
   LP_RET(check_alias({{gx, bo}, {gy, bo}, {gz, bo}}, {{gex, bi}, {gey, bi}}));
   std::lock_guard<std::mutex> lk(ctx().mu);
   const hipStream_t s = (hipStream_t)stream;
+  int dev;
+  LP_RET(cur_device(&dev));
+  Buf& wb = ctx().work[{dev, s}];
+  LP_RET(ensure_buf(wb, vczt_work_bytes(t, g_in, win, lens != nullptr, batch), s));
   if (lens) {
     const void* gs[3] = {gx, gy, gz};
-    return t == PROP_C64 ? rw_adj<float>(gs, gex, gey, g_in, win, wavelength, lens, batch, s)
-                         : rw_adj<double>(gs, gex, gey, g_in, win, wavelength, lens, batch, s);
+    return t == PROP_C64 ? rw_adj<float>(gs, gex, gey, g_in, win, wavelength, lens, batch, s, wb.p)
+                         : rw_adj<double>(gs, gex, gey, g_in, win, wavelength, lens, batch, s, wb.p);
   }
-  return t == PROP_C64 ? vczt_free_adj<float>(gx, gy, gz, gex, gey, g_in, win, wavelength, z, batch, s)
-                       : vczt_free_adj<double>(gx, gy, gz, gex, gey, g_in, win, wavelength, z, batch, s);
+  return t == PROP_C64 ? vczt_free_adj<float>(gx, gy, gz, gex, gey, g_in, win, wavelength, z, batch, s, wb.p)
+                       : vczt_free_adj<double>(gx, gy, gz, gex, gey, g_in, win, wavelength, z, batch, s, wb.p);
 }
 
 int prop_source_gaussian(prop_dtype t, void* out, const prop_grid* g, double w0, double amplitude, double lens_f,
@@ -1068,6 +1298,105 @@ const char* prop_status_string(int status) {
     case PROP_EDEVICE: return "error: HIP call failed (see prop_last_device_error)";
     default: return "unknown status";
   }
+}
+
+
+int prop_plan_create(prop_dtype t, const prop_setup* setups, int32_t n, uint32_t flags, prop_plan** plan) {
+  if (!plan) return PROP_ENULL;
+  *plan = nullptr;
+  if (t != PROP_C64 && t != PROP_C128) return PROP_EPARAM;
+  if (n < 1) return PROP_ESHAPE;
+  if (!setups) return PROP_ENULL;
+  for (int i = 0; i < n; ++i) LP_RET(validate_setup(t, setups[i]));
+  std::lock_guard<std::mutex> lk(ctx().mu);
+  prop_plan* p = new prop_plan();
+  p->t = t;
+  p->flags = flags;
+  auto fail = [&](int r) {
+    for (auto& b : p->work) (void)hipFree(b.p);
+    for (auto& b : p->gbuf) (void)hipFree(b.p);
+    for (auto& s : p->setups) (void)hipFree(s.umod);
+    for (auto s : p->br) (void)hipStreamDestroy(s);
+    if (p->fork) (void)hipEventDestroy(p->fork);
+    for (auto e : p->join) (void)hipEventDestroy(e);
+    delete p;
+    return r;
+  };
+  int r = cur_device(&p->dev);
+  if (r < 0) return fail(r);
+  p->nbranch = (flags & PROP_PLAN_GRAPH) ? std::min(4, n) : 1;
+  size_t wmax = 1, gmax = 1;
+  for (int i = 0; i < n; ++i) {
+    PlanSetup ps;
+    ps.s = setups[i];
+    ps.ncomp_in = ncomp_in(ps.s.op);
+    ps.modulated = ps.s.phase != nullptr || ps.s.lens_f > 0;
+    const size_t plane = (size_t)ps.s.g_in.nx * ps.s.g_in.ny * ps.s.batch * esize(t);
+    if (ps.modulated) {
+      hipError_t e = hipMalloc(&ps.umod, plane * ps.ncomp_in);
+      if (e != hipSuccess) return fail(dev_err(e));
+      gmax = std::max(gmax, plane * ps.ncomp_in);
+    }
+    wmax = std::max(wmax, setup_work_bytes(t, ps.s));
+    p->setups.push_back(ps);
+  }
+  p->work.resize(p->nbranch);
+  p->gbuf.resize(p->nbranch);
+  for (int b = 0; b < p->nbranch; ++b) {
+    r = ensure_buf(p->work[b], wmax, nullptr);
+    if (r < 0) return fail(r);
+    r = ensure_buf(p->gbuf[b], gmax, nullptr);
+    if (r < 0) return fail(r);
+  }
+  for (auto& ps : p->setups) {
+    r = t == PROP_C64 ? warm_setup<float>(p->dev, ps.s, nullptr) : warm_setup<double>(p->dev, ps.s, nullptr);
+    if (r < 0) return fail(r);
+  }
+  if (flags & PROP_PLAN_GRAPH) {
+    for (int b = 0; b < p->nbranch; ++b) {
+      hipStream_t s;
+      hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+      if (e != hipSuccess) return fail(dev_err(e));
+      p->br.push_back(s);
+      hipEvent_t ev;
+      e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+      if (e != hipSuccess) return fail(dev_err(e));
+      p->join.push_back(ev);
+    }
+    hipError_t e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
+    if (e != hipSuccess) return fail(dev_err(e));
+  }
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return fail(dev_err(e));
+  *plan = p;
+  return PROP_OK;
+}
+
+int prop_plan_forward(prop_plan* plan, void* stream) {
+  if (!plan) return PROP_ENULL;
+  std::lock_guard<std::mutex> lk(ctx().mu);
+  return plan_run(plan, false, (hipStream_t)stream);
+}
+
+int prop_plan_adjoint(prop_plan* plan, void* stream) {
+  if (!plan) return PROP_ENULL;
+  std::lock_guard<std::mutex> lk(ctx().mu);
+  return plan_run(plan, true, (hipStream_t)stream);
+}
+
+void prop_plan_destroy(prop_plan* plan) {
+  if (!plan) return;
+  std::lock_guard<std::mutex> lk(ctx().mu);
+  (void)hipDeviceSynchronize();
+  for (int k = 0; k < 2; ++k)
+    if (plan->gexec[k]) (void)hipGraphExecDestroy(plan->gexec[k]);
+  for (auto& b : plan->work) (void)hipFree(b.p);
+  for (auto& b : plan->gbuf) (void)hipFree(b.p);
+  for (auto& s : plan->setups) (void)hipFree(s.umod);
+  for (auto s : plan->br) (void)hipStreamDestroy(s);
+  if (plan->fork) (void)hipEventDestroy(plan->fork);
+  for (auto e : plan->join) (void)hipEventDestroy(e);
+  delete plan;
 }
 
 int prop_last_device_error(void) { return g_last_hip; }
