@@ -544,3 +544,40 @@ def spot_loss(win, wavelength: float, ex, ey, ez=None, w_fz: float = 0.0):
     if ez is None:
         seeds.append(None)
     return float(loss), float(s2), float(fz), tuple(seeds)
+
+
+# --------------------------------------------------------------------------
+# Optical table: SLM -> RS -> SLM -> wave plate -> wave plate -> objective
+# --------------------------------------------------------------------------
+
+def table_chain(v, phi1, phi2, wp1, wp2, g, win, wavelength: float, z: float, na: float, f: float,
+                w_fz: float = 0.0):
+    """One parameter set of the virtual optical table and its gradients.
+
+    Both input polarisation components equal ``v`` (linear 45 degree light
+    with the 1/sqrt 2 already in ``v``).  Elements in order: SLM phi1, RS over
+    z, SLM phi2, wave plate wp1 = (eta, theta), wave plate wp2, high-NA
+    objective into ``win``; loss ``spot_loss`` with weight w_fz on F_z
+    (Results, discovery of sharp-focus and STED-like setups from SLMs, wave
+    plates and a high-NA lens).  Every intermediate is kept; the reverse pass
+    applies the adjoint of each element in reverse order (C5).
+
+    Returns (loss, dL/dphi1, dL/dphi2, (dL/deta1, dL/dtheta1), (dL/deta2, dL/dtheta2)).
+    """
+    v = _as_c128(v)
+    u1 = modulate(v, phi1)
+    s = rs_propagate(u1, g, wavelength, z)
+    a = modulate(s, phi2)
+    bx, by = waveplate(a, a, *wp1)
+    cx, cy = waveplate(bx, by, *wp2)
+    Ex, Ey, Ez = vczt_focus(cx, cy, g, win, wavelength, na, f)
+    loss, _, _, (gx, gy, gz) = spot_loss(win, wavelength, Ex, Ey, Ez, w_fz=w_fz)
+    gcx, gcy = vczt_focus_adjoint(gx, gy, gz, g, win, wavelength, na, f)
+    gbx, gby, de2, dt2 = waveplate_adjoint(gcx, gcy, bx, by, *wp2)
+    gax, gay, de1, dt1 = waveplate_adjoint(gbx, gby, a, a, *wp1)
+    ga = gax + gay
+    g_phi2 = phase_grad(ga, a)
+    gs = ga * np.exp(-1j * np.asarray(phi2, dtype=np.float64))
+    gu1 = rs_adjoint(gs, g, wavelength, z)
+    g_phi1 = phase_grad(gu1, u1)
+    return loss, g_phi1, g_phi2, (de1, dt1), (de2, dt2)

@@ -33,6 +33,62 @@ def _uneven(seed, count, sizes):
     return list(workloads.uneven_96(seed, count=count, sizes=sizes))
 
 
+def _lens(g, wl, f, sign):
+    """exp(sign * i k r^2 / 2f) on grid g (thin lens, C2), FP64."""
+    x, y = oracle.coords(g)
+    return np.exp(sign * 1j * (2 * math.pi / wl) * (x[None, :] ** 2 + y[:, None] ** 2) / (2 * f))
+
+
+def _oracle_setup(w, v_ref, gy):
+    """FP64 oracle of one uneven setup: SLM phase -> RS(z) -> lens f -> CZT at
+    z = f onto the window; then the adjoint chain from the window seed gy."""
+    g, wl, win = w["grid"], w["wavelength"], w["window"]
+    phi = np.asarray(w["phase"], np.float32).astype(np.float64)
+    u = oracle.modulate(v_ref, phi)
+    a = oracle.rs_propagate(u, g, wl, w["z"])
+    y = oracle.czt_propagate(a * _lens(g, wl, w["f"], -1), g, win, wl, w["f"])
+    ga = oracle.czt_adjoint(gy, g, win, wl, w["f"]) * _lens(g, wl, w["f"], +1)
+    gu = oracle.rs_adjoint(ga, g, wl, w["z"])
+    return a, y, ga, oracle.phase_grad(gu, u), gu * np.exp(-1j * phi)
+
+
+def _build_plans(lp, torch, setups, win_of, graph, seed=0):
+    ta, tb, keep = [], [], []
+    rng = np.random.default_rng(seed)
+    for w in setups:
+        g = w["grid"]
+        win = win_of(w)
+        w["window"] = win
+        v = lp.prop_source_gaussian(g, w["w0"], w["wavelength"])
+        phi = torch.tensor(w["phase"][None], dtype=torch.float32, device="cuda")
+        a = torch.empty_like(v)
+        y = torch.empty((1, win.ny, win.nx), dtype=torch.complex64, device="cuda")
+        gy_host = workloads.random_field(rng, (win.ny, win.nx)).astype(np.complex64)
+        gy = torch.from_numpy(gy_host[None]).cuda()
+        ga, gv = torch.empty_like(v), torch.empty_like(v)
+        gphi = torch.empty_like(phi)
+        ta.append(lp.Setup(lp.PROP_OP_RS, g, [v], [a], [ga], w["wavelength"], w["z"], phase=phi, grad_inputs=[gv],
+                           grad_phase=gphi))
+        tb.append(lp.Setup(lp.PROP_OP_CZT, g, [a], [y], [gy], w["wavelength"], w["f"], window=win, lens_f=w["f"],
+                           grad_inputs=[ga]))
+        keep.append(dict(w=w, v=v, phi=phi, a=a, y=y, gy=gy, gy_host=gy_host, ga=ga, gv=gv, gphi=gphi))
+    return lp.Plan(ta, graph=graph), lp.Plan(tb, graph=graph), keep
+
+
+def _check_setup(lp, k, tol_single=1e-6):
+    """Plan results of one setup against single library calls and the oracle."""
+    w = k["w"]
+    g, wl = w["grid"], w["wavelength"]
+    h = lambda t: t.cpu().numpy()[0]
+    u = lp.prop_modulate(k["v"], k["phi"])
+    assert rel_l2(h(k["a"]), h(lp.rs_propagate(u, g, wl, w["z"]))) < tol_single
+    ref = _oracle_setup(w, oracle.gaussian_beam(g, w["w0"]), k["gy_host"].astype(np.complex128))
+    errs = [rel_l2(h(k[name]), r) for name, r in zip(("a", "y", "ga", "gphi", "gv"), ref)]
+    assert max(errs[:3] + errs[4:]) < 1e-5, errs
+    assert errs[3] < 1e-3, errs
+    return errs
+
+
 @pytest.mark.parametrize("graph", [False, True])
 def test_uneven_rs_lens_czt_plans(lp, graph):
     """Uneven setups: SLM phase -> RS(z) [plan A], thin lens f -> CZT at z = f
@@ -40,57 +96,53 @@ def test_uneven_rs_lens_czt_plans(lp, graph):
     import torch
     import warnings
     setups = _uneven(3, 6, (48, 64, 96, 130))
-    ta, tb, keep = [], [], []
     for w in setups:
-        g = w["grid"]
-        n = g.nx
-        win = Grid.square(40, 40 * 0.5e-6)
-        v = lp.prop_source_gaussian(g, 0.6e-3, w["wavelength"])
-        phi = torch.tensor(w["phase"][None], dtype=torch.float32, device="cuda")
-        a = torch.empty_like(v)
-        y = torch.empty((1, 40, 40), dtype=torch.complex64, device="cuda")
-        gy = torch.randn_like(y)
-        ga, gv = torch.empty_like(v), torch.empty_like(v)
-        gphi = torch.empty_like(phi)
-        ta.append(lp.Setup(lp.PROP_OP_RS, g, [v], [a], [ga], w["wavelength"], w["z"], phase=phi, grad_inputs=[gv],
-                           grad_phase=gphi))
-        tb.append(lp.Setup(lp.PROP_OP_CZT, g, [a], [y], [gy], w["wavelength"], w["f"], window=win, lens_f=w["f"],
-                           grad_inputs=[ga]))
-        keep.append((w, v, phi, a, y, gy, ga, gv, gphi, win))
+        w["w0"] = 0.6e-3
     with warnings.catch_warnings():
         warnings.simplefilter("ignore")
-        pa, pb = lp.Plan(ta, graph=graph), lp.Plan(tb, graph=graph)
+        pa, pb, keep = _build_plans(lp, torch, setups, lambda w: Grid.square(40, 40 * 0.5e-6), graph)
         for rep in range(2):  # replays must agree
             pa.forward(); pb.forward(); pb.adjoint(); pa.adjoint()
             torch.cuda.synchronize()
-            for i, (w, v, phi, a, y, gy, ga, gv, gphi, win) in enumerate(keep):
-                g, wl = w["grid"], w["wavelength"]
-                u = lp.prop_modulate(v, phi)
-                ref_a = lp.rs_propagate(u, g, wl, w["z"])
-                assert rel_l2(a.cpu().numpy(), ref_a.cpu().numpy()) < 1e-6
-                # oracle on the same (cast) inputs
-                u64 = u.cpu().numpy().astype(np.complex128)[0]
-                ra = oracle.rs_propagate(u64, g, wl, w["z"])
-                assert rel_l2(a.cpu().numpy()[0], ra) < 1e-5
-                a64 = a.cpu().numpy().astype(np.complex128)[0]
-                lensed = a64 * np.exp(-1j * (2 * math.pi / wl) * (oracle.coords(g)[0][None, :] ** 2 +
-                                                                 oracle.coords(g)[1][:, None] ** 2) / (2 * w["f"]))
-                ry = oracle.czt_propagate(lensed, g, win, wl, w["f"])
-                assert rel_l2(y.cpu().numpy()[0], ry) < 1e-5
-                # adjoint chain against the oracle
-                gy64 = gy.cpu().numpy().astype(np.complex128)[0]
-                g_lensed = oracle.czt_adjoint(gy64, g, win, wl, w["f"])
-                lens_conj = np.exp(1j * (2 * math.pi / wl) * (oracle.coords(g)[0][None, :] ** 2 +
-                                                           oracle.coords(g)[1][:, None] ** 2) / (2 * w["f"]))
-                rga = g_lensed * lens_conj
-                assert rel_l2(ga.cpu().numpy()[0], rga) < 1e-5
-                ga64 = ga.cpu().numpy().astype(np.complex128)[0]
-                gu = oracle.rs_adjoint(ga64, g, wl, w["z"])
-                rgphi = oracle.phase_grad(gu, u64)
-                assert rel_l2(gphi.cpu().numpy()[0], rgphi) < 1e-4
-                rgv = gu * np.exp(-1j * phi.cpu().numpy().astype(np.float64)[0])
-                assert rel_l2(gv.cpu().numpy()[0], rgv) < 1e-5
-            say(f"graph={graph} replay {rep}: {len(keep)} setups agree with single calls and the oracle")
+            worst = np.max([_check_setup(lp, k) for k in keep], axis=0)
+            say(f"graph={graph} replay {rep}: {len(keep)} setups agree with single calls and the oracle; "
+                f"worst rel-L2 a/y/ga/gphi/gv = " + " ".join(f"{e:.1e}" for e in worst))
+    pa.close(); pb.close()
+
+
+def test_uneven_96_full_size_graph(lp):
+    """The 96-setup uneven workload (N in {512..2048}, 1024^2 window) in two
+    graph-replayed plans: forward + adjoint timed over replays; one setup of
+    each size checked in full against single calls and the FP64 oracle."""
+    import time
+    import torch
+    import warnings
+    setups = _uneven(0, 96, workloads.UNEVEN_SIZES)
+    say("uneven 96: sizes", {n: sum(1 for w in setups if w["grid"].nx == n) for n in workloads.UNEVEN_SIZES})
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        t0 = time.perf_counter()
+        pa, pb, keep = _build_plans(lp, torch, setups, lambda w: w["window"], graph=True)
+        torch.cuda.synchronize()
+        say(f"  plans built (spectra, chirps, graphs) in {time.perf_counter() - t0:.2f} s")
+        for _ in range(2):
+            pa.forward(); pb.forward(); pb.adjoint(); pa.adjoint()
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            pa.forward(); pb.forward(); pb.adjoint(); pa.adjoint()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        say(f"  96 setups forward+adjoint: {ms:.2f} ms per replay ({96e3 / ms:.1f} setup-gradients/s)")
+        seen = set()
+        for k in keep:
+            n = k["w"]["grid"].nx
+            if n in seen:
+                continue
+            seen.add(n)
+            errs = _check_setup(lp, k)
+            say(f"  setup {k['w']['index']} N={n}: rel-L2 a/y/ga/gphi/gv = " + " ".join(f"{e:.1e}" for e in errs))
     pa.close(); pb.close()
 
 

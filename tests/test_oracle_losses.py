@@ -128,3 +128,36 @@ def test_focus_chain_gradient_matches_finite_differences():
         Lm = oracle.spot_loss(win, wl, *fwd(pm)[2], w_fz=1.0)[0]
         fd = (Lp - Lm) / (2 * h)
         assert abs(fd - grad[i, j]) <= 1e-6 * np.abs(grad).max()
+
+
+def test_table_chain_gradients_match_finite_differences():
+    """SLM -> RS -> SLM -> WP -> WP -> NA 0.9 objective -> sigma^2/lambda^2 + F_z:
+    the oracle's reverse pass against central differences for both phase
+    masks and all four retarder parameters."""
+    n = 24
+    g = Grid.square(n, 24 * 20e-6)
+    win = Grid.square(15, 15 * 60e-9)
+    wl, z, na = 635e-9, 3e-3, 0.9
+    f = (n * 20e-6 / 2) / na
+    rng = np.random.default_rng(5)
+    v = oracle.gaussian_beam(g, 150e-6) / math.sqrt(2.0)
+    p1, p2 = rng.uniform(-math.pi, math.pi, (2, n, n))
+    wp1, wp2 = (0.7, -0.4), (1.9, 0.25)
+    args = (g, win, wl, z, na, f, 1.0)
+    loss, g1, g2, d1, d2 = oracle.table_chain(v, p1, p2, wp1, wp2, *args)
+    L = lambda a, b, w1, w2: oracle.table_chain(v, a, b, w1, w2, *args)[0]
+    h = 1e-5
+    scale = max(np.abs(g1).max(), np.abs(g2).max())
+    for (i, j) in [(12, 12), (7, 15), (3, 20)]:
+        for which, grad in ((0, g1), (1, g2)):
+            pp = [p1.copy(), p2.copy()]; pm = [p1.copy(), p2.copy()]
+            pp[which][i, j] += h; pm[which][i, j] -= h
+            fd = (L(pp[0], pp[1], wp1, wp2) - L(pm[0], pm[1], wp1, wp2)) / (2 * h)
+            assert abs(fd - grad[i, j]) <= 1e-6 * scale
+    for plate, d in ((0, d1), (1, d2)):
+        for k in range(2):
+            wps = [list(wp1), list(wp2)]
+            wpp = [list(w) for w in wps]; wpm = [list(w) for w in wps]
+            wpp[plate][k] += h; wpm[plate][k] -= h
+            fd = (L(p1, p2, *wpp) - L(p1, p2, *wpm)) / (2 * h)
+            assert abs(fd - d[k]) <= 1e-6 * max(1.0, abs(d[k]))
