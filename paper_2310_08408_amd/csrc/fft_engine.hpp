@@ -234,6 +234,12 @@ template <int... Rs> struct Sched {
   static constexpr int pad_shift = (pow2(rad[0]) && rad[0] >= 4) ? ilog2(rad[0]) : 5;
   static constexpr int line_elems = n + (n >> pad_shift) + 1;
   __host__ __device__ static constexpr int pad(int i) { return i + (i >> pad_shift); }
+  // pad(m R + r) == pad(m R) + r for 0 <= r < R when R divides 2^pad_shift
+  static constexpr bool contiguous_pad(int R) { return ((1 << pad_shift) % R) == 0; }
+  // pad(b + r m) == pad(b) + r pstride(m) when 2^pad_shift divides m: the
+  // strided accesses of a stage become one base plus immediate offsets
+  static constexpr bool stride_pad(int m) { return m % (1 << pad_shift) == 0; }
+  static constexpr int pstride(int m) { return m + (m >> pad_shift); }
 };
 
 
@@ -261,6 +267,10 @@ __device__ __forceinline__ void ct_stage(cx<T>* __restrict__ lds, const cx<T>* _
         if (r < r_in) v[r] = load(j + r * nr);
         else v[r] = mk<T>(T(0), T(0));
       }
+    } else if constexpr (S::stride_pad(nr)) {
+      const cx<T>* p = lds + S::pad(j);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = p[r * S::pstride(nr)];
     } else {
 #pragma unroll
       for (int r = 0; r < R; ++r) v[r] = lds[S::pad(j + r * nr)];
@@ -282,6 +292,15 @@ __device__ __forceinline__ void ct_stage(cx<T>* __restrict__ lds, const cx<T>* _
     if constexpr (last) {
 #pragma unroll
       for (int r = 0; r < r_out; ++r) store(j + r * nr, v[r]);
+    } else if constexpr (Ns > 1 && S::stride_pad(Ns)) {
+      cx<T>* p = lds + S::pad(q * Ns * R + k);
+#pragma unroll
+      for (int r = 0; r < R; ++r) p[r * S::pstride(Ns)] = v[r];
+    } else if constexpr (Ns == 1 && S::contiguous_pad(R)) {
+      // first stage: outputs q R + r are contiguous after padding
+      cx<T>* p = lds + S::pad(q * R);
+#pragma unroll
+      for (int r = 0; r < R; ++r) p[r] = v[r];
     } else {
       const int base = q * Ns * R + k;
 #pragma unroll
@@ -307,6 +326,83 @@ __device__ __forceinline__ void fft_line(cx<T>* lds, const cx<T>* tw, int j, Loa
                                          bool load_reads_lds = false) {
   ct_line_impl<T, DIR, S, HALF_IN, HALF_OUT>(lds, tw, j, load_reads_lds, load, store,
                                             std::make_integer_sequence<int, S::nst>{});
+}
+
+// Forward transform, pointwise multiply, inverse transform of one line
+// (the convolution core of the RS column pass and of Bluestein's method).
+// When the first and last radices agree, the last forward stage and the
+// first inverse stage touch the same indices j + r n/R in the same thread
+// (Stockham order), so the product stays in registers: one LDS write, one
+// LDS read and two barriers fewer than two separate fft_line calls.
+// mult(i, v) returns the product for frequency i.
+template <typename T, class S, class Mult>
+__device__ __forceinline__ void conv_mid_stage(cx<T>* __restrict__ lds, const cx<T>* __restrict__ tw, int j,
+                                               Mult& mult) {
+  using V = cx<T>;
+  constexpr int sl = S::nst - 1;
+  constexpr int R = S::rad[sl];
+  constexpr int nr = S::n / R;
+  static_assert(S::rad[0] == R && S::ns(sl) == nr, "register hand-off needs equal first and last radices");
+  const bool act = j < nr;
+  V v[R];
+  if (act) {
+    if constexpr (S::stride_pad(nr)) {
+      const cx<T>* p = lds + S::pad(j);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = p[r * S::pstride(nr)];
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = lds[S::pad(j + r * nr)];
+    }
+  }
+  __syncthreads();
+  if (act) {
+    const V* t = tw + S::twoff(sl) + j;
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], t[(r - 1) * nr]);
+    Dft<R, -1>::template run<T>(v);
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = mult(j + r * nr, v[r]);
+    Dft<R, 1>::template run<T>(v);
+    // first inverse stage (Ns = 1): outputs j R + r
+    if constexpr (S::contiguous_pad(R)) {
+      cx<T>* p = lds + S::pad(j * R);
+#pragma unroll
+      for (int r = 0; r < R; ++r) p[r] = v[r];
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[S::pad(j * R + r)] = v[r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, class S, bool HI, bool HO, class Load, class Mult, class Store, int... I>
+__device__ __forceinline__ void conv_line_impl(cx<T>* lds, const cx<T>* tw, int j, bool sync_first, Load& load,
+                                               Mult& mult, Store& store, std::integer_sequence<int, I...>) {
+  auto none = [](int, cx<T>) {};
+  (ct_stage<T, -1, S, I, HI, false>(lds, tw, j, sync_first, load, none), ...);
+  conv_mid_stage<T, S>(lds, tw, j, mult);
+  (ct_stage<T, 1, S, I + 1, false, HO>(lds, tw, j, false, load, store), ...);
+}
+
+template <class S>
+constexpr bool conv_in_registers() {
+  return S::nst >= 2 && S::rad[0] == S::rad[S::nst - 1];
+}
+
+template <typename T, class S, bool HALF_IN = false, bool HALF_OUT = false, class Load, class Mult, class Store>
+__device__ __forceinline__ void conv_line(cx<T>* lds, const cx<T>* tw, int j, Load load, Mult mult, Store store,
+                                          bool load_reads_lds = false) {
+  if constexpr (conv_in_registers<S>()) {
+    conv_line_impl<T, S, HALF_IN, HALF_OUT>(lds, tw, j, load_reads_lds, load, mult, store,
+                                            std::make_integer_sequence<int, S::nst - 1>{});
+  } else {
+    auto mid = [&](int i, cx<T> v) { lds[S::pad(i)] = mult(i, v); };
+    fft_line<T, -1, S, HALF_IN, false>(lds, tw, j, load, mid, load_reads_lds);
+    auto load2 = [&](int i) -> cx<T> { return lds[S::pad(i)]; };
+    fft_line<T, 1, S, false, HALF_OUT>(lds, tw, j, load2, store, true);
+  }
 }
 
 // Host-side description of a length's schedule (for twiddle tables).

@@ -178,17 +178,15 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
     if (valid && i < n_valid) v = col[(int64_t)i * pitch];
     return v;
   };
-  auto mid = [&](int i, cx<T> v) {
+  auto mult = [&](int i, cx<T> v) -> cx<T> {
     cx<T> h = czero<T>();
     if (valid) h = sq[(int64_t)min(i, My - i) * qw];
-    lds[S::pad(i)] = conj_spec ? cmulc(v, h) : cmul(v, h);
+    return conj_spec ? cmulc(v, h) : cmul(v, h);
   };
-  fft_line<T, -1, S, HALF, false>(lds, tw, j, load, mid);
-  auto load2 = [&](int i) -> cx<T> { return lds[S::pad(i)]; };
   auto store = [&](int i, cx<T> v) {
     if (valid && i < n_valid) col[(int64_t)i * pitch] = v;
   };
-  fft_line<T, 1, S, false, HALF>(lds, tw, j, load2, store, true);
+  conv_line<T, S, HALF, HALF>(lds, tw, j, load, mult, store);
 }
 
 template <typename T, class S, int C>
@@ -348,13 +346,11 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, COL, 1, HALF
     if (valid && i < n_in) v = cmul(in[line_off<COL>(li, b, l, i)], pre[i]);
     return v;
   };
-  auto mid = [&](int i, cx<T> v) { lds[S::pad(i)] = cmul(v, chat[i]); };
-  fft_line<T, -1, S, HALF, false>(lds, tw, j, load, mid);
-  auto load2 = [&](int i) -> cx<T> { return lds[S::pad(i)]; };
+  auto mult = [&](int i, cx<T> v) -> cx<T> { return cmul(v, chat[i]); };
   auto store = [&](int i, cx<T> v) {
     if (valid && i < n_out) out[line_off<COL>(lo, b, l, i)] = cmul(v, post[i]);
   };
-  fft_line<T, 1, S, false, HALF>(lds, tw, j, load2, store, true);
+  conv_line<T, S, HALF, HALF>(lds, tw, j, load, mult, store);
 }
 
 template <typename T, bool COL, class S, int C>
