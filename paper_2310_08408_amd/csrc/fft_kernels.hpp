@@ -142,6 +142,100 @@ hipError_t launch_fft_lines(int n, bool col, const cx<T>* in, cx<T>* out, Lines 
   }
 }
 
+// ------------------------------------------------------ RS row passes --
+// Forward (DIR = -1): row y of a contiguous field, zero-padded from n_io to
+// n, transformed into the tiled workspace.  Inverse (DIR = +1): workspace
+// row y transformed back, the first n_io outputs scaled into the field.
+// A workgroup holds C >= kTile rows with lanes interleaved across them, so
+// one wave's store or load covers whole tiles (kTile rows x kTile columns,
+// contiguous) on the workspace side and C row segments on the field side.
+// HALF prunes the zero half of the forward input / the unused half of the
+// inverse output at compile time.
+template <typename T, class S>
+struct RowCfg {
+  using CF = Cfg<T, S, false>;
+  static constexpr int line_bytes = (S::line_elems + 64) * (int)sizeof(cx<T>);
+  static constexpr int C = cmax(1, cmin(cmin(cmax(kTile, CF::c_row), kLdsBytes / line_bytes), 1024 / S::threads));
+  static constexpr int threads = C * S::threads;
+  static constexpr bool fits = CF::fits;
+};
+
+template <typename T, int DIR, class S, int C, bool HALF>
+__global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) void k_rs_rows(
+    const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int64_t w_bstride, int nrows, int n_io, T scale, int tiles,
+    const cx<T>* __restrict__ tw) {
+  constexpr int LS = line_stride<S, C, true>();
+  __shared__ cx<T> smem[C * LS];
+  const int id = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = id / tiles, tile = id - b * tiles;
+  const int c = (int)(threadIdx.x % C), j = (int)(threadIdx.x / C);
+  const int y = tile * C + c;
+  const bool valid = y < nrows;
+  cx<T>* lds = smem + c * LS;
+  const int64_t tst = (int64_t)nrows * kTile;  // elements between tiles
+  const int64_t frow = ((int64_t)b * nrows + y) * n_io;
+  const int64_t wrow = b * w_bstride + (int64_t)y * kTile;
+  auto widx = [&](int i) { return wrow + (int64_t)(i >> kTileShift) * tst + (i & (kTile - 1)); };
+  if constexpr (DIR < 0) {
+    auto load = [&](int i) -> cx<T> {
+      cx<T> v = czero<T>();
+      if (valid && i < n_io) v = in[frow + i];
+      return v;
+    };
+    auto store = [&](int i, cx<T> v) {
+      if (valid) out[widx(i)] = v;
+    };
+    fft_line<T, -1, S, HALF, false>(lds, tw, j, load, store);
+  } else {
+    auto load = [&](int i) -> cx<T> {
+      cx<T> v = czero<T>();
+      if (valid) v = in[widx(i)];
+      return v;
+    };
+    auto store = [&](int i, cx<T> v) {
+      if (valid && i < n_io) out[frow + i] = cscale(v, scale);
+    };
+    fft_line<T, 1, S, false, HALF>(lds, tw, j, load, store);
+  }
+}
+
+template <typename T, int DIR, class S>
+hipError_t launch_rs_rows_s(const cx<T>* in, cx<T>* out, int64_t w_bstride, int nrows, int n_io, T scale, int batch,
+                            const cx<T>* tw, hipStream_t s) {
+  using RC = RowCfg<T, S>;
+  if constexpr (!RC::fits) {
+    return hipErrorInvalidValue;
+  } else {
+    constexpr int C = RC::C;
+    const int tiles = (nrows + C - 1) / C;
+    constexpr bool can_half = S::rad[0] % 2 == 0 && S::rad[S::nst - 1] % 2 == 0;
+    if constexpr (can_half) {
+      if (2 * n_io <= S::n) {
+        hipLaunchKernelGGL((k_rs_rows<T, DIR, S, C, true>), dim3(tiles * batch), dim3(RC::threads), 0, s, in, out,
+                           w_bstride, nrows, n_io, scale, tiles, tw);
+        return hipGetLastError();
+      }
+    }
+    hipLaunchKernelGGL((k_rs_rows<T, DIR, S, C, false>), dim3(tiles * batch), dim3(RC::threads), 0, s, in, out,
+                       w_bstride, nrows, n_io, scale, tiles, tw);
+    return hipGetLastError();
+  }
+}
+
+template <typename T, int DIR>
+hipError_t launch_rs_rows(int n, const cx<T>* in, cx<T>* out, int64_t w_bstride, int nrows, int n_io, T scale,
+                          int batch, const cx<T>* tw, hipStream_t s) {
+  if (nrows <= 0 || batch <= 0) return hipSuccess;
+  switch (n) {
+#define LP_CASE(N, ...) \
+  case N: return launch_rs_rows_s<T, DIR, Sched<__VA_ARGS__>>(in, out, w_bstride, nrows, n_io, scale, batch, tw, s);
+    LP_LENGTHS(LP_CASE)
+#undef LP_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
 // ------------------------------------------------- kernel-spectrum access --
 // Quarter table Sq[(M_y/2+1)][(M_x/2+1)] of an RS-type kernel spectrum with
 // parity: kind 0 even/even, 1 odd in kx, 2 odd in ky.
@@ -158,7 +252,7 @@ __device__ __forceinline__ cx<T> spec_at(const cx<T>* __restrict__ Sq, int kind,
 // multiply by the kernel spectrum (conjugated for the adjoint), inverse
 // transform, keep the first n_valid rows.
 template <typename T, class S, int C, bool HALF>
-__global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) void k_rs_cols(cx<T>* W, int64_t bstride, int64_t pitch, int ncols,
+__global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) void k_rs_cols(cx<T>* W, int64_t bstride, int ncols,
                                                             int n_valid, const cx<T>* __restrict__ Sq, int Mx,
                                                             int conj_spec, int tiles, const cx<T>* __restrict__ tw) {
   constexpr int LS = line_stride<S, C, true>();
@@ -170,12 +264,12 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
   const int kx = tile * C + c;
   const bool valid = kx < ncols;
   cx<T>* lds = smem + c * LS;
-  cx<T>* col = W + b * bstride + kx;
+  cx<T>* col = W + b * bstride + (int64_t)(kx >> kTileShift) * n_valid * kTile + (kx & (kTile - 1));
   const cx<T>* sq = Sq + (valid ? min(kx, Mx - kx) : 0);
   const int qw = Mx / 2 + 1;
   auto load = [&](int i) -> cx<T> {
     cx<T> v = czero<T>();
-    if (valid && i < n_valid) v = col[(int64_t)i * pitch];
+    if (valid && i < n_valid) v = col[i * kTile];
     return v;
   };
   auto mult = [&](int i, cx<T> v) -> cx<T> {
@@ -184,51 +278,51 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
     return conj_spec ? cmulc(v, h) : cmul(v, h);
   };
   auto store = [&](int i, cx<T> v) {
-    if (valid && i < n_valid) col[(int64_t)i * pitch] = v;
+    if (valid && i < n_valid) col[i * kTile] = v;
   };
   conv_line<T, S, HALF, HALF>(lds, tw, j, load, mult, store);
 }
 
 template <typename T, class S, int C>
-hipError_t launch_rs_cols_c(cx<T>* W, int64_t bstride, int64_t pitch, int ncols, int n_valid, const cx<T>* Sq, int Mx,
-                            bool conj_spec, int batch, const cx<T>* tw, hipStream_t s) {
+hipError_t launch_rs_cols_c(cx<T>* W, int64_t bstride, int ncols, int n_valid, const cx<T>* Sq, int Mx, bool conj_spec,
+                            int batch, const cx<T>* tw, hipStream_t s) {
   const int tiles = (ncols + C - 1) / C;
   constexpr bool can_half = S::rad[0] % 2 == 0 && S::rad[S::nst - 1] % 2 == 0;
   if constexpr (can_half) {
     if (2 * n_valid <= S::n) {
       hipLaunchKernelGGL((k_rs_cols<T, S, C, true>), dim3(tiles * batch), dim3(C * S::threads), 0, s, W, bstride,
-                         pitch, ncols, n_valid, Sq, Mx, conj_spec ? 1 : 0, tiles, tw);
+                         ncols, n_valid, Sq, Mx, conj_spec ? 1 : 0, tiles, tw);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((k_rs_cols<T, S, C, false>), dim3(tiles * batch), dim3(C * S::threads), 0, s, W, bstride, pitch,
+  hipLaunchKernelGGL((k_rs_cols<T, S, C, false>), dim3(tiles * batch), dim3(C * S::threads), 0, s, W, bstride,
                      ncols, n_valid, Sq, Mx, conj_spec ? 1 : 0, tiles, tw);
   return hipGetLastError();
 }
 
 template <typename T, class S>
-hipError_t launch_rs_cols_s(cx<T>* W, int64_t bstride, int64_t pitch, int ncols, int n_valid, const cx<T>* Sq, int Mx,
-                            bool conj_spec, int batch, const cx<T>* tw, hipStream_t s) {
+hipError_t launch_rs_cols_s(cx<T>* W, int64_t bstride, int ncols, int n_valid, const cx<T>* Sq, int Mx, bool conj_spec,
+                            int batch, const cx<T>* tw, hipStream_t s) {
   using CF = Cfg<T, S, true>;
   if constexpr (!CF::fits) {
     return hipErrorInvalidValue;
   } else {
     if constexpr (S::n == 4096 && sizeof(T) == 4) {
       const int o = col_lines_override();
-      if (o == 1) return launch_rs_cols_c<T, S, 1>(W, bstride, pitch, ncols, n_valid, Sq, Mx, conj_spec, batch, tw, s);
-      if (o == 2) return launch_rs_cols_c<T, S, 2>(W, bstride, pitch, ncols, n_valid, Sq, Mx, conj_spec, batch, tw, s);
+      if (o == 1) return launch_rs_cols_c<T, S, 1>(W, bstride, ncols, n_valid, Sq, Mx, conj_spec, batch, tw, s);
+      if (o == 2) return launch_rs_cols_c<T, S, 2>(W, bstride, ncols, n_valid, Sq, Mx, conj_spec, batch, tw, s);
     }
-    return launch_rs_cols_c<T, S, CF::C>(W, bstride, pitch, ncols, n_valid, Sq, Mx, conj_spec, batch, tw, s);
+    return launch_rs_cols_c<T, S, CF::C>(W, bstride, ncols, n_valid, Sq, Mx, conj_spec, batch, tw, s);
   }
 }
 
 template <typename T>
-hipError_t launch_rs_cols(int My, cx<T>* W, int64_t bstride, int64_t pitch, int ncols, int n_valid, const cx<T>* Sq,
-                          int Mx, bool conj_spec, int batch, const cx<T>* tw, hipStream_t s) {
+hipError_t launch_rs_cols(int My, cx<T>* W, int64_t bstride, int ncols, int n_valid, const cx<T>* Sq, int Mx,
+                          bool conj_spec, int batch, const cx<T>* tw, hipStream_t s) {
   if (batch <= 0 || ncols <= 0) return hipSuccess;
   switch (My) {
 #define LP_CASE(N, ...) \
-  case N: return launch_rs_cols_s<T, Sched<__VA_ARGS__>>(W, bstride, pitch, ncols, n_valid, Sq, Mx, conj_spec, batch, tw, s);
+  case N: return launch_rs_cols_s<T, Sched<__VA_ARGS__>>(W, bstride, ncols, n_valid, Sq, Mx, conj_spec, batch, tw, s);
     LP_LENGTHS(LP_CASE)
 #undef LP_CASE
     default:
@@ -243,7 +337,7 @@ hipError_t launch_rs_cols(int My, cx<T>* W, int64_t bstride, int64_t pitch, int 
 // the same plane as `a` (in place per column).
 template <typename T, class S, int C>
 __global__ __launch_bounds__(2 * C * S::threads) void k_mix2_cols(
-    const cx<T>* a, const cx<T>* bsrc, cx<T>* out, int64_t bstride, int64_t pitch, int ncols, int n_valid,
+    const cx<T>* a, const cx<T>* bsrc, cx<T>* out, int64_t bstride, int ncols, int n_valid,
     const cx<T>* __restrict__ Sa, int kind_a, T ca, const cx<T>* __restrict__ Sb, int kind_b, T cb, int conj_spec,
     int Mx, int tiles, const cx<T>* __restrict__ tw) {
   constexpr int LE = line_stride<S, C, true>();
@@ -258,10 +352,11 @@ __global__ __launch_bounds__(2 * C * S::threads) void k_mix2_cols(
   const int kx = tile * C + c;
   const bool valid = kx < ncols;
   cx<T>* lds = smem + (slot * C + c) * LE;
-  const cx<T>* src = (slot == 0 ? a : bsrc) + bt * bstride + kx;
+  const int64_t coff = bt * bstride + (int64_t)(kx >> kTileShift) * n_valid * kTile + (kx & (kTile - 1));
+  const cx<T>* src = (slot == 0 ? a : bsrc) + coff;
   auto load = [&](int i) -> cx<T> {
     cx<T> v = czero<T>();
-    if (valid && i < n_valid) v = src[(int64_t)i * pitch];
+    if (valid && i < n_valid) v = src[i * kTile];
     return v;
   };
   auto st = [&](int i, cx<T> v) { lds[S::pad(i)] = v; };
@@ -282,18 +377,17 @@ __global__ __launch_bounds__(2 * C * S::threads) void k_mix2_cols(
   __syncthreads();
   // inverse transform of slot 0 by the slot-0 threads; slot-1 threads pass
   // an out-of-range butterfly index and only meet the barriers
-  cx<T>* dst = out + bt * bstride + kx;
+  cx<T>* dst = out + coff;
   cx<T>* lds0 = smem + c * LE;
   auto load2 = [&](int i) -> cx<T> { return lds0[S::pad(i)]; };
   auto store = [&](int i, cx<T> v) {
-    if (valid && i < n_valid) dst[(int64_t)i * pitch] = v;
+    if (valid && i < n_valid) dst[i * kTile] = v;
   };
   fft_line<T, 1, S>(lds0, tw, slot == 0 ? j : S::threads, load2, store, true);
 }
 
 template <typename T, class S>
-hipError_t launch_mix2_cols_s(const cx<T>* a, const cx<T>* b, cx<T>* out, int64_t bstride, int64_t pitch, int ncols,
-                              int n_valid, const cx<T>* Sa, int kind_a, T ca, const cx<T>* Sb, int kind_b, T cb,
+hipError_t launch_mix2_cols_s(const cx<T>* a, const cx<T>* b, cx<T>* out, int64_t bstride, int ncols, int n_valid, const cx<T>* Sa, int kind_a, T ca, const cx<T>* Sb, int kind_b, T cb,
                               bool conj_spec, int Mx, int batch, const cx<T>* tw, hipStream_t s) {
   using CF = Cfg<T, S, true, 2, 512>;
   if constexpr (!CF::fits) {
@@ -301,20 +395,20 @@ hipError_t launch_mix2_cols_s(const cx<T>* a, const cx<T>* b, cx<T>* out, int64_
   } else {
     const int tiles = (ncols + CF::C - 1) / CF::C;
     hipLaunchKernelGGL((k_mix2_cols<T, S, CF::C>), dim3(tiles * batch), dim3(CF::threads), 0, s, a, b, out, bstride,
-                       pitch, ncols, n_valid, Sa, kind_a, ca, Sb, kind_b, cb, conj_spec ? 1 : 0, Mx, tiles, tw);
+                       ncols, n_valid, Sa, kind_a, ca, Sb, kind_b, cb, conj_spec ? 1 : 0, Mx, tiles, tw);
     return hipGetLastError();
   }
 }
 
 template <typename T>
-hipError_t launch_mix2_cols(int My, const cx<T>* a, const cx<T>* b, cx<T>* out, int64_t bstride, int64_t pitch,
-                            int ncols, int n_valid, const cx<T>* Sa, int kind_a, T ca, const cx<T>* Sb, int kind_b,
+hipError_t launch_mix2_cols(int My, const cx<T>* a, const cx<T>* b, cx<T>* out, int64_t bstride, int ncols,
+                            int n_valid, const cx<T>* Sa, int kind_a, T ca, const cx<T>* Sb, int kind_b,
                             T cb, bool conj_spec, int Mx, int batch, const cx<T>* tw, hipStream_t s) {
   if (batch <= 0 || ncols <= 0) return hipSuccess;
   switch (My) {
 #define LP_CASE(N, ...)                                                                                             \
   case N:                                                                                                           \
-    return launch_mix2_cols_s<T, Sched<__VA_ARGS__>>(a, b, out, bstride, pitch, ncols, n_valid, Sa, kind_a, ca, Sb, \
+    return launch_mix2_cols_s<T, Sched<__VA_ARGS__>>(a, b, out, bstride, ncols, n_valid, Sa, kind_a, ca, Sb, \
                                                      kind_b, cb, conj_spec, Mx, batch, tw, s);
     LP_LENGTHS(LP_CASE)
 #undef LP_CASE

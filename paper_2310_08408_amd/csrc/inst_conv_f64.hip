@@ -3,9 +3,9 @@
 #include "fft_kernels.hpp"
 
 namespace lp {
-template hipError_t launch_rs_cols<double>(int, cx<double>*, int64_t, int64_t, int, int, const cx<double>*, int, bool, int,
+template hipError_t launch_rs_cols<double>(int, cx<double>*, int64_t, int, int, const cx<double>*, int, bool, int,
                                        const cx<double>*, hipStream_t);
-template hipError_t launch_mix2_cols<double>(int, const cx<double>*, const cx<double>*, cx<double>*, int64_t, int64_t, int, int,
+template hipError_t launch_mix2_cols<double>(int, const cx<double>*, const cx<double>*, cx<double>*, int64_t, int, int,
                                          const cx<double>*, int, double, const cx<double>*, int, double, bool, int, int,
                                          const cx<double>*, hipStream_t);
 template hipError_t launch_bluestein<double>(int, bool, const cx<double>*, cx<double>*, Lines, Lines, int, int, int,

@@ -22,21 +22,42 @@ template <typename T, int DIR>
 hipError_t launch_fft_lines(int n, bool col, const cx<T>* in, cx<T>* out, Lines li, Lines lo, int nlines, int n_in,
                             int n_out, T scale, int batch, const cx<T>* tw, hipStream_t s);
 
-// RS middle pass, in place on columns kx < ncols of W[b][0..n_valid)[kx]
-// (row pitch `pitch`): transform of length My of the zero-padded column,
-// multiply by the even/even kernel spectrum Sq (quarter table, conjugated
-// for the adjoint), inverse transform, keep the first n_valid rows.
-template <typename T>
-hipError_t launch_rs_cols(int My, cx<T>* W, int64_t bstride, int64_t pitch, int ncols, int n_valid, const cx<T>* Sq,
-                          int Mx, bool conj_spec, int batch, const cx<T>* tw, hipStream_t s);
+// RS workspace layout.  The row-transformed plane of one field (rows y <
+// ny, spectral columns kx < Mx) is stored in tiles of kTile adjacent
+// columns: element (y, kx) at (kx / kTile) * ny * kTile + y * kTile +
+// kx % kTile.  A column pass then reads and writes each tile as one
+// contiguous block, and the row passes touch whole cache lines across
+// kTile neighbouring rows.
+constexpr int kTileShift = 2;
+constexpr int kTile = 1 << kTileShift;
+inline int64_t rs_plane_elems(int ny, int Mx) { return (int64_t)((Mx + kTile - 1) / kTile) * kTile * ny; }
 
-// Vectorial RS middle pass: out column = IFFT(ca Sa FFT(a) + cb Sb FFT(b))
-// with quarter-stored spectra of parity kind 0 (even/even), 1 (odd in kx)
-// or 2 (odd in ky); conj_spec conjugates both spectra.  out may equal a.
+// RS row passes between contiguous fields [batch][nrows][n_io] and the tiled
+// workspace (bstride w_bstride elements per batch item).  DIR = -1: forward
+// transform of length n of each zero-padded input row into the workspace;
+// DIR = +1: inverse transform of each workspace row, first n_io outputs
+// kept and scaled.
+template <typename T, int DIR>
+hipError_t launch_rs_rows(int n, const cx<T>* in, cx<T>* out, int64_t w_bstride, int nrows, int n_io, T scale,
+                          int batch, const cx<T>* tw, hipStream_t s);
+
+// RS middle pass, in place on columns kx < ncols of the tiled workspace
+// (bstride elements per batch item, n_valid rows): transform of length My
+// of the zero-padded column, multiply by the even/even kernel spectrum Sq
+// (quarter table, conjugated for the adjoint), inverse transform, keep the
+// first n_valid rows.
 template <typename T>
-hipError_t launch_mix2_cols(int My, const cx<T>* a, const cx<T>* b, cx<T>* out, int64_t bstride, int64_t pitch,
-                            int ncols, int n_valid, const cx<T>* Sa, int kind_a, T ca, const cx<T>* Sb, int kind_b,
-                            T cb, bool conj_spec, int Mx, int batch, const cx<T>* tw, hipStream_t s);
+hipError_t launch_rs_cols(int My, cx<T>* W, int64_t bstride, int ncols, int n_valid, const cx<T>* Sq, int Mx,
+                          bool conj_spec, int batch, const cx<T>* tw, hipStream_t s);
+
+// Vectorial RS middle pass on tiled workspaces: out column = IFFT(ca Sa
+// FFT(a) + cb Sb FFT(b)) with quarter-stored spectra of parity kind 0
+// (even/even), 1 (odd in kx) or 2 (odd in ky); conj_spec conjugates both
+// spectra.  out may equal a.
+template <typename T>
+hipError_t launch_mix2_cols(int My, const cx<T>* a, const cx<T>* b, cx<T>* out, int64_t bstride, int ncols,
+                            int n_valid, const cx<T>* Sa, int kind_a, T ca, const cx<T>* Sb, int kind_b, T cb,
+                            bool conj_spec, int Mx, int batch, const cx<T>* tw, hipStream_t s);
 
 // Bluestein zoom transform of each line: out[p] = post[p] *
 // IFFT_L(FFT_L(pad(pre .* in)) .* chat)[p], p < n_out.

@@ -346,7 +346,7 @@ static int sampling(const prop_grid* g, double wl, double z) {
 
 // ------------------------------------------------------------- RS runs --
 static size_t rs_work_bytes(prop_dtype t, const prop_grid* g, int batch) {
-  return (size_t)g->ny * fft_len(2 * g->nx - 1) * batch * esize(t);
+  return (size_t)rs_plane_elems(g->ny, fft_len(2 * g->nx - 1)) * batch * esize(t);
 }
 
 template <typename T>
@@ -361,22 +361,21 @@ static int rs_run(const void* in, void* out, const prop_grid* g, double wl, doub
   LP_RET(get_tw<T>(dev, Mx, &twx));
   LP_RET(get_tw<T>(dev, My, &twy));
   const int nx = g->nx, ny = g->ny;
-  const int64_t plane = (int64_t)ny * Mx;
+  const int64_t plane = rs_plane_elems(ny, Mx);
   cx<T>* W = (cx<T>*)work;
   const T scale = (T)(g->dx * g->dy / ((double)Mx * (double)My));
-  // P1: row transforms of the ny input rows, zero-padded to Mx
+  // P1: row transforms of the ny input rows, zero-padded to Mx, into the
+  // tiled workspace
   const double es = sizeof(cx<T>);
   const double qel = (double)(Mx / 2 + 1) * (My / 2 + 1);
   LP_TRACE("rs_rows_fwd", es * batch * ny * (double)(nx + Mx), s,
-           (launch_fft_lines<T, -1>(Mx, false, (const cx<T>*)in, W, Lines{(int64_t)ny * nx, nx}, Lines{plane, Mx}, ny,
-                                    nx, Mx, T(1), batch, twx, s)));
+           (launch_rs_rows<T, -1>(Mx, (const cx<T>*)in, W, plane, ny, nx, T(1), batch, twx, s)));
   // P2: column transform, kernel-spectrum multiply, inverse, first ny rows
   LP_TRACE("rs_cols", es * (2.0 * batch * ny * Mx + qel), s,
-           launch_rs_cols<T>(My, W, plane, Mx, Mx, ny, q[0], Mx, adjoint, batch, twy, s));
+           launch_rs_cols<T>(My, W, plane, Mx, ny, q[0], Mx, adjoint, batch, twy, s));
   // P3: inverse row transforms, crop to nx, scale dx dy / (Mx My)
   LP_TRACE("rs_rows_inv", es * batch * ny * (double)(nx + Mx), s,
-           (launch_fft_lines<T, 1>(Mx, false, W, (cx<T>*)out, Lines{plane, Mx}, Lines{(int64_t)ny * nx, nx}, ny, Mx, nx,
-                                   scale, batch, twx, s)));
+           (launch_rs_rows<T, 1>(Mx, W, (cx<T>*)out, plane, ny, nx, scale, batch, twx, s)));
   return PROP_OK;
 }
 
@@ -417,7 +416,7 @@ static int vrs_run(const void* const* ins, int nin, void* const* outs, int nout,
   LP_RET(get_tw<T>(dev, Mx, &twx));
   LP_RET(get_tw<T>(dev, My, &twy));
   const int nx = g->nx, ny = g->ny;
-  const int64_t pst = (int64_t)ny * Mx;
+  const int64_t pst = rs_plane_elems(ny, Mx);
   const size_t plane = (size_t)pst * batch;
   cx<T>* W[3];
   for (int i = 0; i < 3; ++i) W[i] = (cx<T>*)work + i * plane;
@@ -426,32 +425,30 @@ static int vrs_run(const void* const* ins, int nin, void* const* outs, int nout,
   const double pl = (double)batch * ny * Mx;
   for (int i = 0; i < nin; ++i)
     LP_TRACE("rs_rows_fwd", es * batch * ny * (double)(nx + Mx), s,
-             (launch_fft_lines<T, -1>(Mx, false, (const cx<T>*)ins[i], W[i], Lines{(int64_t)ny * nx, nx},
-                                      Lines{pst, Mx}, ny, nx, Mx, T(1), batch, twx, s)));
+             (launch_rs_rows<T, -1>(Mx, (const cx<T>*)ins[i], W[i], pst, ny, nx, T(1), batch, twx, s)));
   if (!adjoint) {
     // E_z = -(Hx * E_x0 + Hy * E_y0) first (reads W0, W1), then E_x, E_y in place
     LP_TRACE("vrs_mix2", es * (3.0 * pl + 2.0 * qel), s,
-             launch_mix2_cols<T>(My, W[0], W[1], W[2], pst, Mx, Mx, ny, q[1], 1, T(-1), q[2], 2, T(-1), false, Mx,
+             launch_mix2_cols<T>(My, W[0], W[1], W[2], pst, Mx, ny, q[1], 1, T(-1), q[2], 2, T(-1), false, Mx,
                                  batch, twy, s));
     LP_TRACE("rs_cols", es * (2.0 * pl + qel), s,
-             launch_rs_cols<T>(My, W[0], pst, Mx, Mx, ny, q[0], Mx, false, batch, twy, s));
+             launch_rs_cols<T>(My, W[0], pst, Mx, ny, q[0], Mx, false, batch, twy, s));
     LP_TRACE("rs_cols", es * (2.0 * pl + qel), s,
-             launch_rs_cols<T>(My, W[1], pst, Mx, Mx, ny, q[0], Mx, false, batch, twy, s));
+             launch_rs_cols<T>(My, W[1], pst, Mx, ny, q[0], Mx, false, batch, twy, s));
   } else {
     // g_ex = H^H g_x - Hx^H g_z, g_ey = H^H g_y - Hy^H g_z (in place over W0, W1)
     LP_TRACE("vrs_mix2", es * (3.0 * pl + 2.0 * qel), s,
-             launch_mix2_cols<T>(My, W[0], W[2], W[0], pst, Mx, Mx, ny, q[0], 0, T(1), q[1], 1, T(-1), true, Mx,
+             launch_mix2_cols<T>(My, W[0], W[2], W[0], pst, Mx, ny, q[0], 0, T(1), q[1], 1, T(-1), true, Mx,
                                  batch, twy, s));
     LP_TRACE("vrs_mix2", es * (3.0 * pl + 2.0 * qel), s,
-             launch_mix2_cols<T>(My, W[1], W[2], W[1], pst, Mx, Mx, ny, q[0], 0, T(1), q[2], 2, T(-1), true, Mx,
+             launch_mix2_cols<T>(My, W[1], W[2], W[1], pst, Mx, ny, q[0], 0, T(1), q[2], 2, T(-1), true, Mx,
                                  batch, twy, s));
   }
   const T scale = (T)(g->dx * g->dy / ((double)Mx * (double)My));
   const int src[3] = {adjoint ? 0 : 0, 1, 2};
   for (int i = 0; i < nout; ++i)
     LP_TRACE("rs_rows_inv", es * batch * ny * (double)(nx + Mx), s,
-             (launch_fft_lines<T, 1>(Mx, false, W[src[i]], (cx<T>*)outs[i], Lines{pst, Mx},
-                                     Lines{(int64_t)ny * nx, nx}, ny, Mx, nx, scale, batch, twx, s)));
+             (launch_rs_rows<T, 1>(Mx, W[src[i]], (cx<T>*)outs[i], pst, ny, nx, scale, batch, twx, s)));
   return PROP_OK;
 }
 
