@@ -80,8 +80,9 @@ typedef struct {
  *   U(x_m, y_l) = dx dy sum_{i,j} U0(x_j, y_i) H(x_m - x_j, y_l - y_i; z),
  *   H = (1/2pi)(z/r^2)(1/r - i k) exp(i k r),  r = sqrt(X^2 + Y^2 + z^2),
  * evaluated exactly (up to rounding) as a zero-padded FFT convolution of
- * length M >= 2n - 1 per axis (M = 2n for n = 2^a 3^b).  Requires
- * M <= 8192, i.e. nx, ny <= 4096.  u_in/u_out: [batch][ny][nx].
+ * length M = prop_fft_length(2n - 1) per axis (the smallest supported
+ * length >= 2n - 1).  Requires M <= 8192, i.e. nx, ny <= 4096.
+ * u_in/u_out: [batch][ny][nx].
  * Returns PROP_WUNDERSAMPLED when, along some axis with 2 d > lambda,
  * z < sqrt((2 L d / lambda)^2 - L^2) (L = n d), after launching.
  */
@@ -100,7 +101,7 @@ int rs_adjoint(prop_dtype t, const void* g_out, void* g_in, const prop_grid* g, 
  *   K = exp(ikz) dx dy / (i lambda z), Q = exp(ik(x^2+y^2)/2z),
  *   P = exp(ik(X^2+Y^2)/2z),
  * evaluated by separable Bluestein transforms of length
- * L >= n_in + n_out - 1 (2^a 3^b, L <= 8192 per axis).
+ * L = prop_fft_length(n_in + n_out - 1) per axis (L <= 8192).
  * u_in: [batch][g_in.ny][g_in.nx]; u_out: [batch][win.ny][win.nx].
  */
 int czt_propagate(prop_dtype t, const void* u_in, void* u_out, const prop_grid* g_in,
@@ -190,7 +191,8 @@ int prop_spot_loss(prop_dtype t, const void* ex, const void* ey, const void* ez,
 /* ------------------------------------------------------------- utility -- */
 /* Host-only sampling check of RS/VRS: PROP_OK or PROP_WUNDERSAMPLED. */
 int prop_sampling_check(const prop_grid* g, double wavelength, double z);
-/* Smallest supported transform length (2^a 3^b) >= n, or -1 above 8192. */
+/* Smallest supported transform length >= n, or -1 above 8192.  Supported
+ * lengths: powers of two 1..8192 and 3 * 2^k for 96 <= 3 * 2^k <= 6144. */
 int32_t prop_fft_length(int32_t n);
 /* Free cached spectra, chirps, twiddles and workspaces (synchronises the device). */
 void prop_cache_clear(void);
