@@ -258,8 +258,11 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
   constexpr int LS = line_stride<S, C, true>();
   __shared__ cx<T> smem[C * LS];
   constexpr int My = S::n;
+  // batch-minor order: the batch items of one column tile run side by side
+  // on one XCD and share the kernel-spectrum lines in its L2
   const int id = xcd_remap(blockIdx.x, gridDim.x);
-  const int b = id / tiles, tile = id - b * tiles;
+  const int nb = gridDim.x / tiles;
+  const int tile = id / nb, b = id - tile * nb;
   const int c = threadIdx.x % C, j = threadIdx.x / C;
   const int kx = tile * C + c;
   const bool valid = kx < ncols;
