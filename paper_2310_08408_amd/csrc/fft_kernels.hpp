@@ -77,6 +77,25 @@ __device__ __forceinline__ int xcd_remap(int i, int nb) {
   return x * q + min(x, r) + (i >> 3);
 }
 
+// Streaming accesses without cache retention (non-temporal): for passes in
+// which each element is touched once and one workgroup consumes whole
+// lines, so that the transform's twiddle tables stay cached instead.  Not
+// for passes whose lines are shared by neighbouring workgroups.
+template <typename T>
+__device__ __forceinline__ cx<T> load_stream(const cx<T>* p) {
+  using V2 = T __attribute__((ext_vector_type(2)));
+  const V2 v = __builtin_nontemporal_load(reinterpret_cast<const V2*>(p));
+  return mk<T>(v.x, v.y);
+}
+template <typename T>
+__device__ __forceinline__ void store_stream(cx<T>* p, cx<T> a) {
+  using V2 = T __attribute__((ext_vector_type(2)));
+  V2 v;
+  v.x = a.x;
+  v.y = a.y;
+  __builtin_nontemporal_store(v, reinterpret_cast<V2*>(p));
+}
+
 template <typename T> __device__ __forceinline__ cx<T> czero() { return mk<T>(T(0), T(0)); }
 
 // address of element i of line l of batch item b
@@ -272,7 +291,7 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
   const int qw = Mx / 2 + 1;
   auto load = [&](int i) -> cx<T> {
     cx<T> v = czero<T>();
-    if (valid && i < n_valid) v = col[i * kTile];
+    if (valid && i < n_valid) v = load_stream(&col[i * kTile]);
     return v;
   };
   auto mult = [&](int i, cx<T> v) -> cx<T> {
@@ -281,7 +300,7 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
     return conj_spec ? cmulc(v, h) : cmul(v, h);
   };
   auto store = [&](int i, cx<T> v) {
-    if (valid && i < n_valid) col[i * kTile] = v;
+    if (valid && i < n_valid) store_stream(&col[i * kTile], v);
   };
   conv_line<T, S, HALF, HALF>(lds, tw, j, load, mult, store);
 }
