@@ -54,22 +54,22 @@ hipError_t launch_rs_kernel_wrapped(cx<double>* out, int Mx, int My, int nx, int
 }
 
 template <typename T>
-__global__ void k_extract_quarter(const cx<double>* full, cx<T>* q, int Mx, int My) {
-  const int qw = Mx / 2 + 1, qh = My / 2 + 1;
-  const int64_t total = (int64_t)qw * qh;
+__global__ void k_extract_half(const cx<double>* full, cx<T>* q, int Mx, int My) {
+  const int qh = My / 2 + 1;
+  const int64_t total = (int64_t)Mx * qh;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * blockDim.x) {
-    const int a = (int)(t / qw), bcol = (int)(t - (int64_t)a * qw);
-    const cx<double> v = full[(int64_t)a * Mx + bcol];
-    q[t] = mk<T>(T(v.x), T(v.y));
+    const int a = (int)(t / Mx), kx = (int)(t - (int64_t)a * Mx);
+    const cx<double> v = full[t];
+    q[(int64_t)(kx >> 2) * qh * 4 + a * 4 + (kx & 3)] = mk<T>(T(v.x), T(v.y));
   }
 }
 
 template <typename T>
-hipError_t launch_extract_quarter(const cx<double>* full, cx<T>* q, int Mx, int My, hipStream_t s) {
-  const int64_t total = (int64_t)(Mx / 2 + 1) * (My / 2 + 1);
+hipError_t launch_extract_half(const cx<double>* full, cx<T>* q, int Mx, int My, hipStream_t s) {
+  const int64_t total = (int64_t)Mx * (My / 2 + 1);
   const int blocks = (int)std::min<int64_t>((total + 255) / 256, 65536);
-  hipLaunchKernelGGL((k_extract_quarter<T>), dim3(blocks), dim3(256), 0, s, full, q, Mx, My);
+  hipLaunchKernelGGL((k_extract_half<T>), dim3(blocks), dim3(256), 0, s, full, q, Mx, My);
   return hipGetLastError();
 }
 
@@ -646,7 +646,7 @@ hipError_t launch_spot_loss(const cx<T>* ex, const cx<T>* ey, const cx<T>* ez, i
 
 // ------------------------------------------------------ instantiations --
 #define LP_INST(T)                                                                                                  \
-  template hipError_t launch_extract_quarter<T>(const cx<double>*, cx<T>*, int, int, hipStream_t);                  \
+  template hipError_t launch_extract_half<T>(const cx<double>*, cx<T>*, int, int, hipStream_t);                  \
   template hipError_t launch_zoom_vectors<T>(const ZoomSpec&, cx<T>*, cx<T>*, cx<double>*, hipStream_t);            \
   template hipError_t launch_convert<T>(const cx<double>*, cx<T>*, int64_t, hipStream_t);                           \
   template hipError_t launch_phase_stage<T>(const cx<T>*, const T*, cx<T>*, int, int, double, double, double,       \

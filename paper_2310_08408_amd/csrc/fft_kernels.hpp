@@ -256,13 +256,13 @@ hipError_t launch_rs_rows(int n, const cx<T>* in, cx<T>* out, int64_t w_bstride,
 }
 
 // ------------------------------------------------- kernel-spectrum access --
-// Quarter table Sq[(M_y/2+1)][(M_x/2+1)] of an RS-type kernel spectrum with
-// parity: kind 0 even/even, 1 odd in kx, 2 odd in ky.
+// Half table (rows 0..My/2, 4-column tiles) of an RS-type kernel spectrum
+// with parity in ky: kinds 0 (H) and 1 ((X/z) H) even, kind 2 ((Y/z) H) odd.
 template <typename T>
 __device__ __forceinline__ cx<T> spec_at(const cx<T>* __restrict__ Sq, int kind, int kx, int ky, int Mx, int My) {
-  const int qx = min(kx, Mx - kx), qy = min(ky, My - ky);
-  cx<T> h = Sq[(int64_t)qy * (Mx / 2 + 1) + qx];
-  if ((kind == 1 && kx > Mx / 2) || (kind == 2 && ky > My / 2)) { h.x = -h.x; h.y = -h.y; }
+  const int qy = min(ky, My - ky);
+  cx<T> h = Sq[(int64_t)(kx >> 2) * (My / 2 + 1) * 4 + qy * 4 + (kx & 3)];
+  if (kind == 2 && ky > My / 2) { h.x = -h.x; h.y = -h.y; }
   return h;
 }
 
@@ -287,8 +287,7 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
   const bool valid = kx < ncols;
   cx<T>* lds = smem + c * LS;
   cx<T>* col = W + b * bstride + (int64_t)(kx >> kTileShift) * n_valid * kTile + (kx & (kTile - 1));
-  const cx<T>* sq = Sq + (valid ? min(kx, Mx - kx) : 0);
-  const int qw = Mx / 2 + 1;
+  const cx<T>* sq = Sq + (valid ? (int64_t)(kx >> 2) * (My / 2 + 1) * 4 + (kx & 3) : 0);
   auto load = [&](int i) -> cx<T> {
     cx<T> v = czero<T>();
     if (valid && i < n_valid) v = load_stream(&col[i * kTile]);
@@ -296,7 +295,7 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
   };
   auto mult = [&](int i, cx<T> v) -> cx<T> {
     cx<T> h = czero<T>();
-    if (valid) h = sq[(int64_t)min(i, My - i) * qw];
+    if (valid) h = sq[min(i, My - i) * 4];
     return conj_spec ? cmulc(v, h) : cmul(v, h);
   };
   auto store = [&](int i, cx<T> v) {
@@ -354,7 +353,7 @@ hipError_t launch_rs_cols(int My, cx<T>* W, int64_t bstride, int ncols, int n_va
 
 // --------------------------------------------------- two-input mixing --
 // out column = IFFT( ca Sa .* FFT(a) + cb Sb .* FFT(b) ) for the vectorial
-// RS passes; Sa/Sb are quarter-stored kernel spectra of the given parity
+// RS passes; Sa/Sb are half-table kernel spectra of the given parity
 // kinds, ca/cb in {-1, +1}, optionally conjugated (adjoint).  `out` may be
 // the same plane as `a` (in place per column).
 template <typename T, class S, int C>

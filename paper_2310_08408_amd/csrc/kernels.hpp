@@ -44,14 +44,14 @@ hipError_t launch_rs_rows(int n, const cx<T>* in, cx<T>* out, int64_t w_bstride,
 // RS middle pass, in place on columns kx < ncols of the tiled workspace
 // (bstride elements per batch item, n_valid rows): transform of length My
 // of the zero-padded column, multiply by the even/even kernel spectrum Sq
-// (quarter table, conjugated for the adjoint), inverse transform, keep the
+// (half table, conjugated for the adjoint), inverse transform, keep the
 // first n_valid rows.
 template <typename T>
 hipError_t launch_rs_cols(int My, cx<T>* W, int64_t bstride, int ncols, int n_valid, const cx<T>* Sq, int Mx,
                           bool conj_spec, int batch, const cx<T>* tw, hipStream_t s);
 
 // Vectorial RS middle pass on tiled workspaces: out column = IFFT(ca Sa
-// FFT(a) + cb Sb FFT(b)) with quarter-stored spectra of parity kind 0
+// FFT(a) + cb Sb FFT(b)) with half-table spectra of parity kind 0
 // (even/even), 1 (odd in kx) or 2 (odd in ky); conj_spec conjugates both
 // spectra.  out may equal a.
 template <typename T>
@@ -71,9 +71,12 @@ hipError_t launch_bluestein(int L, bool col, const cx<T>* in, cx<T>* out, Lines 
 // 2: (Y/z) H.  Offsets d in [-(n-1), n-1] sit at index d mod M, the rest 0.
 hipError_t launch_rs_kernel_wrapped(cx<double>* out, int Mx, int My, int nx, int ny, double dx,
                                     double dy, double k, double z, int kind, hipStream_t s);
-// Quarter extraction [0..My/2] x [0..Mx/2] with conversion.
+// Kernel-spectrum table: rows ky = 0..My/2 of the full spectrum (the rest
+// follows from its parity in ky), all columns, stored in 4-column tiles
+// like the RS workspace: (ky, kx) at (kx / 4) (My/2+1) 4 + ky 4 + kx % 4, so
+// a column pass reads its tile's spectrum as one contiguous block.
 template <typename T>
-hipError_t launch_extract_quarter(const cx<double>* full, cx<T>* q, int Mx, int My, hipStream_t s);
+hipError_t launch_extract_half(const cx<double>* full, cx<T>* q, int Mx, int My, hipStream_t s);
 
 // 1-D zoom-DFT vectors: sum_j a_j exp(i sigma 2 pi beta X_p x_j) with
 // x_j = x0 + j dx (n_in), X_p = X0 + p dX (n_out):

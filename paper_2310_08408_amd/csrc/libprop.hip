@@ -240,7 +240,7 @@ static int get_rs_spectra(int dev, const prop_grid* g, double wl, double z, bool
     Buf& sb = C.scratch[dev];
     LP_RET(ensure_buf(sb, (size_t)Mx * My * sizeof(cx<double>), s));
     cx<double>* full = (cx<double>*)sb.p;
-    const size_t qbytes = (size_t)(Mx / 2 + 1) * (My / 2 + 1) * sizeof(cx<T>);
+    const size_t qbytes = (size_t)((Mx + 3) / 4 * 4) * (My / 2 + 1) * sizeof(cx<T>);
     const double k = 2.0 * kPi / wl;
     for (int kind = 0; kind < nk; ++kind) {
       if (e.q[kind]) continue;
@@ -252,7 +252,7 @@ static int get_rs_spectra(int dev, const prop_grid* g, double wl, double z, bool
                                            twx, s)));
       LP_TRY((launch_fft_lines<double, -1>(My, true, full, full, Lines{0, Mx}, Lines{0, Mx}, Mx, My, My, 1.0, 1, twy,
                                            s)));
-      LP_TRY(launch_extract_quarter<T>(full, (cx<T>*)qp, Mx, My, s));
+      LP_TRY(launch_extract_half<T>(full, (cx<T>*)qp, Mx, My, s));
       e.q[kind] = qp;
     }
     LP_TRY(hipStreamSynchronize(s));
@@ -367,7 +367,7 @@ static int rs_run(const void* in, void* out, const prop_grid* g, double wl, doub
   // P1: row transforms of the ny input rows, zero-padded to Mx, into the
   // tiled workspace
   const double es = sizeof(cx<T>);
-  const double qel = (double)(Mx / 2 + 1) * (My / 2 + 1);
+  const double qel = (double)Mx * (My / 2 + 1);  // half spectrum table
   LP_TRACE("rs_rows_fwd", es * batch * ny * (double)(nx + Mx), s,
            (launch_rs_rows<T, -1>(Mx, (const cx<T>*)in, W, plane, ny, nx, T(1), batch, twx, s)));
   // P2: column transform, kernel-spectrum multiply, inverse, first ny rows
@@ -421,7 +421,7 @@ static int vrs_run(const void* const* ins, int nin, void* const* outs, int nout,
   cx<T>* W[3];
   for (int i = 0; i < 3; ++i) W[i] = (cx<T>*)work + i * plane;
   const double es = sizeof(cx<T>);
-  const double qel = (double)(Mx / 2 + 1) * (My / 2 + 1);
+  const double qel = (double)Mx * (My / 2 + 1);  // half spectrum table
   const double pl = (double)batch * ny * Mx;
   for (int i = 0; i < nin; ++i)
     LP_TRACE("rs_rows_fwd", es * batch * ny * (double)(nx + Mx), s,
