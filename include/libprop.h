@@ -194,7 +194,19 @@ int prop_sampling_check(const prop_grid* g, double wavelength, double z);
 /* Smallest supported transform length >= n, or -1 above 8192.  Supported
  * lengths: powers of two 1..8192 and 3 * 2^k for 96 <= 3 * 2^k <= 6144. */
 int32_t prop_fft_length(int32_t n);
-/* Free cached spectra, chirps, twiddles and workspaces (synchronises the device). */
+/* Autotuner.  The column passes (RS column convolution, vectorial mixing,
+ * Bluestein columns) have launch variants that differ only in lines per
+ * workgroup and give bit-identical results.  With LIBPROP_AUTOTUNE=1 in the
+ * environment (or during the first execution of a PROP_PLAN_AUTOTUNE plan)
+ * the first launch of each new shape times every variant on scratch buffers
+ * (allocating them and synchronising the stream) and keeps the fastest;
+ * otherwise, and under stream capture, the built-in variant is used.
+ * prop_autotune_report writes one text line per tuned shape (chosen variant
+ * and the measured ms of each) into buf (cap bytes, NUL-terminated) and
+ * returns the size needed including the NUL. */
+int32_t prop_autotune_report(char* buf, int32_t cap);
+/* Free cached spectra, chirps, twiddles, workspaces and autotuner choices
+ * (synchronises the device). */
 void prop_cache_clear(void);
 /* Text for a status code. */
 const char* prop_status_string(int status);
@@ -228,6 +240,11 @@ int prop_last_device_error(void);
  */
 enum { PROP_OP_RS = 0, PROP_OP_CZT = 1, PROP_OP_VRS = 2, PROP_OP_VCZT = 3 };
 #define PROP_PLAN_GRAPH 1u
+/* PROP_PLAN_AUTOTUNE: the first prop_plan_forward and the first
+ * prop_plan_adjoint run eagerly with the autotuner on (see
+ * prop_autotune_report); they allocate scratch memory and synchronise the
+ * stream.  Later calls (and the captured graph) use the chosen variants. */
+#define PROP_PLAN_AUTOTUNE 2u
 
 typedef struct {
   int32_t op;           /* PROP_OP_* */

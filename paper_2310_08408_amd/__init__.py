@@ -21,8 +21,9 @@ __all__ = [
     "rs_propagate", "rs_adjoint", "czt_propagate", "czt_adjoint", "vrs_propagate", "vrs_adjoint",
     "vczt_propagate", "vczt_adjoint", "prop_source_gaussian", "prop_source_radial", "prop_modulate",
     "prop_phase_grad", "prop_waveplate", "prop_waveplate_adjoint", "prop_spot_loss", "prop_sampling_check",
-    "prop_fft_length", "prop_cache_clear", "prop_trace_enable", "prop_trace_read", "PropError", "PropWarning",
-    "library", "Plan", "Setup", "PROP_OP_RS", "PROP_OP_CZT", "PROP_OP_VRS", "PROP_OP_VCZT",
+    "prop_fft_length", "prop_cache_clear", "prop_trace_enable", "prop_trace_read", "prop_autotune_report",
+    "PropError", "PropWarning", "library", "Plan", "Setup", "PROP_OP_RS", "PROP_OP_CZT", "PROP_OP_VRS",
+    "PROP_OP_VCZT", "PROP_PLAN_GRAPH", "PROP_PLAN_AUTOTUNE",
 ]
 
 
@@ -321,10 +322,20 @@ def prop_trace_read(max_entries: int = 64) -> dict:
             for i in range(n)}
 
 
+def prop_autotune_report() -> str:
+    """One line per shape the autotuner has tuned (chosen variant, ms of each)."""
+    lib = library()
+    need = lib.prop_autotune_report(None, 0)
+    buf = ctypes.create_string_buffer(max(int(need), 1))
+    lib.prop_autotune_report(buf, len(buf))
+    return buf.value.decode()
+
+
 # ---------------------------------------------------------------------- plans --
 
 PROP_OP_RS, PROP_OP_CZT, PROP_OP_VRS, PROP_OP_VCZT = 0, 1, 2, 3
 PROP_PLAN_GRAPH = 1
+PROP_PLAN_AUTOTUNE = 2
 
 
 class Setup:
@@ -370,7 +381,7 @@ class Setup:
 class Plan:
     """A prop_plan over a list of Setups (keeps their tensors alive)."""
 
-    def __init__(self, setups, dtype=torch.complex64, graph=False, device=None):
+    def __init__(self, setups, dtype=torch.complex64, graph=False, device=None, autotune=False):
         lib = library()
         self.setups = list(setups)
         arr = (_lib.prop_setup * len(self.setups))(*[s._struct() for s in self.setups])
@@ -380,7 +391,8 @@ class Plan:
         self.device = device or self.setups[0].inputs[0].device
         with torch.cuda.device(self.device):
             st = lib.prop_plan_create(code, ctypes.cast(arr, ctypes.c_void_p), len(self.setups),
-                                      PROP_PLAN_GRAPH if graph else 0, ctypes.byref(h))
+                                      (PROP_PLAN_GRAPH if graph else 0) | (PROP_PLAN_AUTOTUNE if autotune else 0),
+                                      ctypes.byref(h))
         _lib.check("prop_plan_create", st)
         self._h = h
 

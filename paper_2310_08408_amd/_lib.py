@@ -75,6 +75,7 @@ SIGNATURES = {
     "prop_plan_destroy": (None, [P]),
     "prop_trace_enable": (None, [c_int32]),
     "prop_trace_read": (c_int32, [P, c_int32]),
+    "prop_autotune_report": (c_int32, [ctypes.c_char_p, c_int32]),
 }
 
 _lib = None

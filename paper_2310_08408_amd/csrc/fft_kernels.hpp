@@ -60,14 +60,14 @@ struct Cfg {
   static constexpr bool fits = line_bytes <= kLdsBytes && S::threads * LINES_PER_ITEM <= 1024;
 };
 
-// Tuning override of the lines per workgroup of column passes at the long
-// lengths (environment LIBPROP_COL_LINES = 1, 2 or 4; 0 = built-in choice).
-inline int col_lines_override() {
-  static int v = [] {
-    const char* e = std::getenv("LIBPROP_COL_LINES");
-    return e ? std::atoi(e) : 0;
-  }();
-  return v;
+// Tunable launch variants of the column passes: variant v runs C >> v lines
+// per workgroup (at least 1) instead of the built-in C, for lengths >= 512.
+// Every variant computes bit-identical results (only the assignment of
+// lines to workgroups changes); the library's autotuner picks among them.
+constexpr int kTuneMinLength = 512;
+template <class S, int C0>
+constexpr int variant_lines(int v) {
+  return S::n >= kTuneMinLength ? cmax(1, C0 >> v) : C0;
 }
 
 // Workgroup i is dispatched to XCD i % 8; give each XCD a contiguous range
@@ -323,27 +323,26 @@ hipError_t launch_rs_cols_c(cx<T>* W, int64_t bstride, int ncols, int n_valid, c
 
 template <typename T, class S>
 hipError_t launch_rs_cols_s(cx<T>* W, int64_t bstride, int ncols, int n_valid, const cx<T>* Sq, int Mx, bool conj_spec,
-                            int batch, const cx<T>* tw, hipStream_t s) {
+                            int batch, const cx<T>* tw, hipStream_t s, int variant) {
   using CF = Cfg<T, S, true>;
   if constexpr (!CF::fits) {
     return hipErrorInvalidValue;
   } else {
-    if constexpr (S::n == 4096 && sizeof(T) == 4) {
-      const int o = col_lines_override();
-      if (o == 1) return launch_rs_cols_c<T, S, 1>(W, bstride, ncols, n_valid, Sq, Mx, conj_spec, batch, tw, s);
-      if (o == 2) return launch_rs_cols_c<T, S, 2>(W, bstride, ncols, n_valid, Sq, Mx, conj_spec, batch, tw, s);
-    }
+    constexpr int C1 = variant_lines<S, CF::C>(1), C2 = variant_lines<S, CF::C>(2);
+    if (variant == 1) return launch_rs_cols_c<T, S, C1>(W, bstride, ncols, n_valid, Sq, Mx, conj_spec, batch, tw, s);
+    if (variant == 2) return launch_rs_cols_c<T, S, C2>(W, bstride, ncols, n_valid, Sq, Mx, conj_spec, batch, tw, s);
     return launch_rs_cols_c<T, S, CF::C>(W, bstride, ncols, n_valid, Sq, Mx, conj_spec, batch, tw, s);
   }
 }
 
 template <typename T>
 hipError_t launch_rs_cols(int My, cx<T>* W, int64_t bstride, int ncols, int n_valid, const cx<T>* Sq, int Mx,
-                          bool conj_spec, int batch, const cx<T>* tw, hipStream_t s) {
+                          bool conj_spec, int batch, const cx<T>* tw, hipStream_t s, int variant) {
   if (batch <= 0 || ncols <= 0) return hipSuccess;
   switch (My) {
 #define LP_CASE(N, ...) \
-  case N: return launch_rs_cols_s<T, Sched<__VA_ARGS__>>(W, bstride, ncols, n_valid, Sq, Mx, conj_spec, batch, tw, s);
+  case N:                                                                                                  \
+    return launch_rs_cols_s<T, Sched<__VA_ARGS__>>(W, bstride, ncols, n_valid, Sq, Mx, conj_spec, batch, tw, s, variant);
     LP_LENGTHS(LP_CASE)
 #undef LP_CASE
     default:
@@ -407,30 +406,46 @@ __global__ __launch_bounds__(2 * C * S::threads) void k_mix2_cols(
   fft_line<T, 1, S>(lds0, tw, slot == 0 ? j : S::threads, load2, store, true);
 }
 
+template <typename T, class S, int C>
+hipError_t launch_mix2_cols_c(const cx<T>* a, const cx<T>* b, cx<T>* out, int64_t bstride, int ncols, int n_valid,
+                              const cx<T>* Sa, int kind_a, T ca, const cx<T>* Sb, int kind_b, T cb, bool conj_spec,
+                              int Mx, int batch, const cx<T>* tw, hipStream_t s) {
+  const int tiles = (ncols + C - 1) / C;
+  hipLaunchKernelGGL((k_mix2_cols<T, S, C>), dim3(tiles * batch), dim3(2 * C * S::threads), 0, s, a, b, out, bstride,
+                     ncols, n_valid, Sa, kind_a, ca, Sb, kind_b, cb, conj_spec ? 1 : 0, Mx, tiles, tw);
+  return hipGetLastError();
+}
+
 template <typename T, class S>
-hipError_t launch_mix2_cols_s(const cx<T>* a, const cx<T>* b, cx<T>* out, int64_t bstride, int ncols, int n_valid, const cx<T>* Sa, int kind_a, T ca, const cx<T>* Sb, int kind_b, T cb,
-                              bool conj_spec, int Mx, int batch, const cx<T>* tw, hipStream_t s) {
+hipError_t launch_mix2_cols_s(const cx<T>* a, const cx<T>* b, cx<T>* out, int64_t bstride, int ncols, int n_valid,
+                              const cx<T>* Sa, int kind_a, T ca, const cx<T>* Sb, int kind_b, T cb, bool conj_spec,
+                              int Mx, int batch, const cx<T>* tw, hipStream_t s, int variant) {
   using CF = Cfg<T, S, true, 2, 512>;
   if constexpr (!CF::fits) {
     return hipErrorInvalidValue;
   } else {
-    const int tiles = (ncols + CF::C - 1) / CF::C;
-    hipLaunchKernelGGL((k_mix2_cols<T, S, CF::C>), dim3(tiles * batch), dim3(CF::threads), 0, s, a, b, out, bstride,
-                       ncols, n_valid, Sa, kind_a, ca, Sb, kind_b, cb, conj_spec ? 1 : 0, Mx, tiles, tw);
-    return hipGetLastError();
+    constexpr int C1 = variant_lines<S, CF::C>(1), C2 = variant_lines<S, CF::C>(2);
+    if (variant == 1)
+      return launch_mix2_cols_c<T, S, C1>(a, b, out, bstride, ncols, n_valid, Sa, kind_a, ca, Sb, kind_b, cb,
+                                          conj_spec, Mx, batch, tw, s);
+    if (variant == 2)
+      return launch_mix2_cols_c<T, S, C2>(a, b, out, bstride, ncols, n_valid, Sa, kind_a, ca, Sb, kind_b, cb,
+                                          conj_spec, Mx, batch, tw, s);
+    return launch_mix2_cols_c<T, S, CF::C>(a, b, out, bstride, ncols, n_valid, Sa, kind_a, ca, Sb, kind_b, cb,
+                                           conj_spec, Mx, batch, tw, s);
   }
 }
 
 template <typename T>
 hipError_t launch_mix2_cols(int My, const cx<T>* a, const cx<T>* b, cx<T>* out, int64_t bstride, int ncols,
                             int n_valid, const cx<T>* Sa, int kind_a, T ca, const cx<T>* Sb, int kind_b,
-                            T cb, bool conj_spec, int Mx, int batch, const cx<T>* tw, hipStream_t s) {
+                            T cb, bool conj_spec, int Mx, int batch, const cx<T>* tw, hipStream_t s, int variant) {
   if (batch <= 0 || ncols <= 0) return hipSuccess;
   switch (My) {
 #define LP_CASE(N, ...)                                                                                             \
   case N:                                                                                                           \
     return launch_mix2_cols_s<T, Sched<__VA_ARGS__>>(a, b, out, bstride, ncols, n_valid, Sa, kind_a, ca, Sb, \
-                                                     kind_b, cb, conj_spec, Mx, batch, tw, s);
+                                                     kind_b, cb, conj_spec, Mx, batch, tw, s, variant);
     LP_LENGTHS(LP_CASE)
 #undef LP_CASE
     default:
@@ -489,16 +504,19 @@ hipError_t launch_bluestein_c(const cx<T>* in, cx<T>* out, Lines li, Lines lo, i
 template <typename T, bool COL, class S>
 hipError_t launch_bluestein_s(const cx<T>* in, cx<T>* out, Lines li, Lines lo, int nlines, int n_in, int n_out,
                               const cx<T>* pre, const cx<T>* chat, const cx<T>* post, int batch, const cx<T>* tw,
-                              hipStream_t s) {
+                              hipStream_t s, int variant) {
   // two transforms plus the chirp multiplies per line: 512 threads keep the
   // radix-16 stages free of register spills
   using CF = Cfg<T, S, COL, 1, 512>;
   if constexpr (!CF::fits) {
     return hipErrorInvalidValue;
   } else {
-    if constexpr (COL && S::n == 4096 && sizeof(T) == 4) {
-      if (col_lines_override() == 1)
-        return launch_bluestein_c<T, COL, S, 1>(in, out, li, lo, nlines, n_in, n_out, pre, chat, post, batch, tw, s);
+    if constexpr (COL) {
+      constexpr int C1 = variant_lines<S, CF::C>(1), C2 = variant_lines<S, CF::C>(2);
+      if (variant == 1)
+        return launch_bluestein_c<T, COL, S, C1>(in, out, li, lo, nlines, n_in, n_out, pre, chat, post, batch, tw, s);
+      if (variant == 2)
+        return launch_bluestein_c<T, COL, S, C2>(in, out, li, lo, nlines, n_in, n_out, pre, chat, post, batch, tw, s);
     }
     return launch_bluestein_c<T, COL, S, CF::C>(in, out, li, lo, nlines, n_in, n_out, pre, chat, post, batch, tw, s);
   }
@@ -507,19 +525,40 @@ hipError_t launch_bluestein_s(const cx<T>* in, cx<T>* out, Lines li, Lines lo, i
 template <typename T>
 hipError_t launch_bluestein(int L, bool col, const cx<T>* in, cx<T>* out, Lines li, Lines lo, int nlines, int n_in,
                             int n_out, const cx<T>* pre, const cx<T>* chat, const cx<T>* post, int batch,
-                            const cx<T>* tw, hipStream_t s) {
+                            const cx<T>* tw, hipStream_t s, int variant) {
   if (nlines <= 0 || batch <= 0) return hipSuccess;
   switch (L) {
 #define LP_CASE(N, ...)                                                                                             \
   case N:                                                                                                           \
     return col ? launch_bluestein_s<T, true, Sched<__VA_ARGS__>>(in, out, li, lo, nlines, n_in, n_out, pre, chat,   \
-                                                                 post, batch, tw, s)                                \
+                                                                 post, batch, tw, s, variant)                       \
                : launch_bluestein_s<T, false, Sched<__VA_ARGS__>>(in, out, li, lo, nlines, n_in, n_out, pre, chat, \
-                                                                  post, batch, tw, s);
+                                                                  post, batch, tw, s, 0);
     LP_LENGTHS(LP_CASE)
 #undef LP_CASE
     default:
       return hipErrorInvalidValue;
+  }
+}
+
+// Lines per workgroup of a column-pass variant (kind 0: RS column pass,
+// 1: vectorial mixing, 2: Bluestein columns) at length n; 0 if unsupported.
+template <typename T>
+int col_pass_lines(int kind, int n, int variant) {
+  if (variant < 0 || variant >= kColVariants) return 0;
+  switch (n) {
+#define LP_CASE(N, ...)                                                                             \
+  case N: {                                                                                         \
+    using S = Sched<__VA_ARGS__>;                                                                   \
+    constexpr int c0 = Cfg<T, S, true>::C, c1 = Cfg<T, S, true, 2, 512>::C,                         \
+                  c2 = Cfg<T, S, true, 1, 512>::C;                                                  \
+    const int c = kind == 0 ? c0 : (kind == 1 ? c1 : c2);                                           \
+    return S::n >= kTuneMinLength ? cmax(1, c >> variant) : c;                                      \
+  }
+    LP_LENGTHS(LP_CASE)
+#undef LP_CASE
+    default:
+      return 0;
   }
 }
 

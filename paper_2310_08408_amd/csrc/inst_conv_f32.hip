@@ -4,11 +4,12 @@
 
 namespace lp {
 template hipError_t launch_rs_cols<float>(int, cx<float>*, int64_t, int, int, const cx<float>*, int, bool, int,
-                                       const cx<float>*, hipStream_t);
+                                       const cx<float>*, hipStream_t, int);
 template hipError_t launch_mix2_cols<float>(int, const cx<float>*, const cx<float>*, cx<float>*, int64_t, int, int,
                                          const cx<float>*, int, float, const cx<float>*, int, float, bool, int, int,
-                                         const cx<float>*, hipStream_t);
+                                         const cx<float>*, hipStream_t, int);
 template hipError_t launch_bluestein<float>(int, bool, const cx<float>*, cx<float>*, Lines, Lines, int, int, int,
                                          const cx<float>*, const cx<float>*, const cx<float>*, int, const cx<float>*,
-                                         hipStream_t);
+                                         hipStream_t, int);
+template int col_pass_lines<float>(int, int, int);
 }  // namespace lp

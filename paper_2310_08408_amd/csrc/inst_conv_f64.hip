@@ -4,11 +4,12 @@
 
 namespace lp {
 template hipError_t launch_rs_cols<double>(int, cx<double>*, int64_t, int, int, const cx<double>*, int, bool, int,
-                                       const cx<double>*, hipStream_t);
+                                       const cx<double>*, hipStream_t, int);
 template hipError_t launch_mix2_cols<double>(int, const cx<double>*, const cx<double>*, cx<double>*, int64_t, int, int,
                                          const cx<double>*, int, double, const cx<double>*, int, double, bool, int, int,
-                                         const cx<double>*, hipStream_t);
+                                         const cx<double>*, hipStream_t, int);
 template hipError_t launch_bluestein<double>(int, bool, const cx<double>*, cx<double>*, Lines, Lines, int, int, int,
                                          const cx<double>*, const cx<double>*, const cx<double>*, int, const cx<double>*,
-                                         hipStream_t);
+                                         hipStream_t, int);
+template int col_pass_lines<double>(int, int, int);
 }  // namespace lp

@@ -48,7 +48,7 @@ hipError_t launch_rs_rows(int n, const cx<T>* in, cx<T>* out, int64_t w_bstride,
 // first n_valid rows.
 template <typename T>
 hipError_t launch_rs_cols(int My, cx<T>* W, int64_t bstride, int ncols, int n_valid, const cx<T>* Sq, int Mx,
-                          bool conj_spec, int batch, const cx<T>* tw, hipStream_t s);
+                          bool conj_spec, int batch, const cx<T>* tw, hipStream_t s, int variant = 0);
 
 // Vectorial RS middle pass on tiled workspaces: out column = IFFT(ca Sa
 // FFT(a) + cb Sb FFT(b)) with half-table spectra of parity kind 0
@@ -57,14 +57,22 @@ hipError_t launch_rs_cols(int My, cx<T>* W, int64_t bstride, int ncols, int n_va
 template <typename T>
 hipError_t launch_mix2_cols(int My, const cx<T>* a, const cx<T>* b, cx<T>* out, int64_t bstride, int ncols,
                             int n_valid, const cx<T>* Sa, int kind_a, T ca, const cx<T>* Sb, int kind_b, T cb,
-                            bool conj_spec, int Mx, int batch, const cx<T>* tw, hipStream_t s);
+                            bool conj_spec, int Mx, int batch, const cx<T>* tw, hipStream_t s, int variant = 0);
 
 // Bluestein zoom transform of each line: out[p] = post[p] *
 // IFFT_L(FFT_L(pad(pre .* in)) .* chat)[p], p < n_out.
 template <typename T>
 hipError_t launch_bluestein(int L, bool col, const cx<T>* in, cx<T>* out, Lines li, Lines lo, int nlines, int n_in,
                             int n_out, const cx<T>* pre, const cx<T>* chat, const cx<T>* post, int batch,
-                            const cx<T>* tw, hipStream_t s);
+                            const cx<T>* tw, hipStream_t s, int variant = 0);
+
+constexpr int kColVariants = 3;
+// Column-pass launch variants (the `variant` argument above): lines per
+// workgroup of variant v for kind 0 (RS column pass), 1 (vectorial mixing)
+// or 2 (Bluestein columns) at length n, 0 if unsupported.  All variants give
+// bit-identical results.
+template <typename T>
+int col_pass_lines(int kind, int n, int variant);
 
 // ---- FP64 generators (setup work) ----
 // Wrapped RS kernel on an My x Mx grid (complex128), kind 0: H, 1: (X/z) H,

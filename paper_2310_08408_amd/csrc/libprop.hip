@@ -6,9 +6,12 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -157,6 +160,15 @@ using SpecKey = std::tuple<int, int, int, int, double, double, double, double, i
 using ZoomKey = std::tuple<int, int, int, double, double, double, double, double, double, double, double, double,
                            int, int, int>;
 
+// Autotuner record: per (device, element size, pass kind, length, lines,
+// valid input length, kept output length, batch) the chosen launch variant
+// and the measured time of each variant (ms; < 0 = not a distinct variant).
+using TuneKey = std::tuple<int, int, int, int, int, int, int, int>;
+struct TuneEntry {
+  int variant = 0;
+  float ms[kColVariants] = {-1.f, -1.f, -1.f};
+};
+
 struct Ctx {
   std::mutex mu;
   std::map<std::tuple<int, int, int>, PlanEntry> plans;  // (dev, is_double, n)
@@ -164,6 +176,8 @@ struct Ctx {
   std::map<ZoomKey, ZoomEntry> zooms;
   std::map<std::pair<int, hipStream_t>, Buf> work;
   std::map<int, Buf> scratch;  // complex128 setup scratch per device
+  std::map<TuneKey, TuneEntry> tuned;
+  std::map<int, Buf> tune_a, tune_b;  // autotuner scratch per device
 };
 
 static Ctx& ctx() {
@@ -258,6 +272,83 @@ static int get_rs_spectra(int dev, const prop_grid* g, double wl, double z, bool
     LP_TRY(hipStreamSynchronize(s));
   }
   for (int kk = 0; kk < 3; ++kk) q[kk] = (const cx<T>*)e.q[kk];
+  return PROP_OK;
+}
+
+// ----------------------------------------------------------- autotuner --
+// The column passes have bit-exact launch variants (lines per workgroup,
+// col_pass_lines).  When tuning is on, the first launch of each new shape
+// times every distinct variant on scratch buffers of the same size (one
+// warm-up and three timed launches each, HIP events on the caller's stream)
+// and keeps the fastest; later launches of that shape reuse the choice.
+// Tuning is on with LIBPROP_AUTOTUNE=1 in the environment, or for the first
+// execution of a plan created with PROP_PLAN_AUTOTUNE; never while the
+// stream is being captured (the built-in variant 0 is used then).
+enum { TUNE_RS_COLS = 0, TUNE_MIX2 = 1, TUNE_CZT_COLS = 2 };
+static thread_local bool t_tune_request = false;
+
+static bool tune_enabled() {
+  static const bool env = [] {
+    const char* e = std::getenv("LIBPROP_AUTOTUNE");
+    return e && std::atoi(e) != 0;
+  }();
+  return env || t_tune_request;
+}
+
+template <typename T, class Launch>
+static int col_variant(int dev, int kind, int n, int nlines, int n_in, int n_out, int batch, size_t elems_a,
+                       size_t elems_b, hipStream_t s, Launch launch, int* variant) {
+  Ctx& C = ctx();
+  const TuneKey key{dev, (int)sizeof(T), kind, n, nlines, n_in, n_out, batch};
+  auto it = C.tuned.find(key);
+  if (it != C.tuned.end()) {
+    *variant = it->second.variant;
+    return PROP_OK;
+  }
+  *variant = 0;
+  if (!tune_enabled() || capturing(s)) return PROP_OK;
+  Buf& ba = C.tune_a[dev];
+  Buf& bb = C.tune_b[dev];
+  LP_RET(ensure_buf(ba, std::max<size_t>(elems_a, 1) * sizeof(cx<T>), s));
+  LP_RET(ensure_buf(bb, std::max<size_t>(elems_b, 1) * sizeof(cx<T>), s));
+  LP_TRY(hipMemsetAsync(ba.p, 0, ba.bytes, s));
+  LP_TRY(hipMemsetAsync(bb.p, 0, bb.bytes, s));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  LP_TRY(hipEventCreate(&e0));
+  hipError_t er = hipEventCreate(&e1);
+  if (er != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return dev_err(er);
+  }
+  TuneEntry te;
+  float best = 0.f;
+  int seen[kColVariants] = {0, 0, 0};
+  er = hipSuccess;
+  for (int v = 0; v < kColVariants && er == hipSuccess; ++v) {
+    const int lines = col_pass_lines<T>(kind, n, v);
+    bool dup = lines <= 0;
+    for (int u = 0; u < v; ++u) dup = dup || seen[u] == lines;
+    seen[v] = lines;
+    if (dup) continue;
+    er = launch(v, (cx<T>*)ba.p, (cx<T>*)bb.p);
+    if (er == hipSuccess) er = hipEventRecord(e0, s);
+    for (int rep = 0; rep < 3 && er == hipSuccess; ++rep) er = launch(v, (cx<T>*)ba.p, (cx<T>*)bb.p);
+    if (er == hipSuccess) er = hipEventRecord(e1, s);
+    if (er == hipSuccess) er = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (er == hipSuccess) er = hipEventElapsedTime(&ms, e0, e1);
+    if (er != hipSuccess) break;
+    te.ms[v] = ms / 3.f;
+    if (v == 0 || te.ms[v] < best) {
+      best = te.ms[v];
+      te.variant = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (er != hipSuccess) return dev_err(er);
+  C.tuned[key] = te;
+  *variant = te.variant;
   return PROP_OK;
 }
 
@@ -371,8 +462,14 @@ static int rs_run(const void* in, void* out, const prop_grid* g, double wl, doub
   LP_TRACE("rs_rows_fwd", es * batch * ny * (double)(nx + Mx), s,
            (launch_rs_rows<T, -1>(Mx, (const cx<T>*)in, W, plane, ny, nx, T(1), batch, twx, s)));
   // P2: column transform, kernel-spectrum multiply, inverse, first ny rows
+  int v = 0;
+  LP_RET(col_variant<T>(dev, TUNE_RS_COLS, My, Mx, ny, ny, batch, (size_t)plane * batch, 0, s,
+                        [&](int var, cx<T>* a, cx<T>*) {
+                          return launch_rs_cols<T>(My, a, plane, Mx, ny, q[0], Mx, adjoint, batch, twy, s, var);
+                        },
+                        &v));
   LP_TRACE("rs_cols", es * (2.0 * batch * ny * Mx + qel), s,
-           launch_rs_cols<T>(My, W, plane, Mx, ny, q[0], Mx, adjoint, batch, twy, s));
+           launch_rs_cols<T>(My, W, plane, Mx, ny, q[0], Mx, adjoint, batch, twy, s, v));
   // P3: inverse row transforms, crop to nx, scale dx dy / (Mx My)
   LP_TRACE("rs_rows_inv", es * batch * ny * (double)(nx + Mx), s,
            (launch_rs_rows<T, 1>(Mx, W, (cx<T>*)out, plane, ny, nx, scale, batch, twx, s)));
@@ -426,23 +523,35 @@ static int vrs_run(const void* const* ins, int nin, void* const* outs, int nout,
   for (int i = 0; i < nin; ++i)
     LP_TRACE("rs_rows_fwd", es * batch * ny * (double)(nx + Mx), s,
              (launch_rs_rows<T, -1>(Mx, (const cx<T>*)ins[i], W[i], pst, ny, nx, T(1), batch, twx, s)));
+  int vm = 0, vc = 0;
+  LP_RET(col_variant<T>(dev, TUNE_MIX2, My, Mx, ny, ny, batch, (size_t)pst * batch, (size_t)pst * batch, s,
+                        [&](int var, cx<T>* a, cx<T>* b) {
+                          return launch_mix2_cols<T>(My, a, b, a, pst, Mx, ny, q[1], 1, T(-1), q[2], 2, T(-1),
+                                                     false, Mx, batch, twy, s, var);
+                        },
+                        &vm));
   if (!adjoint) {
+    LP_RET(col_variant<T>(dev, TUNE_RS_COLS, My, Mx, ny, ny, batch, (size_t)pst * batch, 0, s,
+                          [&](int var, cx<T>* a, cx<T>*) {
+                            return launch_rs_cols<T>(My, a, pst, Mx, ny, q[0], Mx, false, batch, twy, s, var);
+                          },
+                          &vc));
     // E_z = -(Hx * E_x0 + Hy * E_y0) first (reads W0, W1), then E_x, E_y in place
     LP_TRACE("vrs_mix2", es * (3.0 * pl + 2.0 * qel), s,
              launch_mix2_cols<T>(My, W[0], W[1], W[2], pst, Mx, ny, q[1], 1, T(-1), q[2], 2, T(-1), false, Mx,
-                                 batch, twy, s));
+                                 batch, twy, s, vm));
     LP_TRACE("rs_cols", es * (2.0 * pl + qel), s,
-             launch_rs_cols<T>(My, W[0], pst, Mx, ny, q[0], Mx, false, batch, twy, s));
+             launch_rs_cols<T>(My, W[0], pst, Mx, ny, q[0], Mx, false, batch, twy, s, vc));
     LP_TRACE("rs_cols", es * (2.0 * pl + qel), s,
-             launch_rs_cols<T>(My, W[1], pst, Mx, ny, q[0], Mx, false, batch, twy, s));
+             launch_rs_cols<T>(My, W[1], pst, Mx, ny, q[0], Mx, false, batch, twy, s, vc));
   } else {
     // g_ex = H^H g_x - Hx^H g_z, g_ey = H^H g_y - Hy^H g_z (in place over W0, W1)
     LP_TRACE("vrs_mix2", es * (3.0 * pl + 2.0 * qel), s,
              launch_mix2_cols<T>(My, W[0], W[2], W[0], pst, Mx, ny, q[0], 0, T(1), q[1], 1, T(-1), true, Mx,
-                                 batch, twy, s));
+                                 batch, twy, s, vm));
     LP_TRACE("vrs_mix2", es * (3.0 * pl + 2.0 * qel), s,
              launch_mix2_cols<T>(My, W[1], W[2], W[1], pst, Mx, ny, q[0], 0, T(1), q[2], 2, T(-1), true, Mx,
-                                 batch, twy, s));
+                                 batch, twy, s, vm));
   }
   const T scale = (T)(g->dx * g->dy / ((double)Mx * (double)My));
   const int src[3] = {adjoint ? 0 : 0, 1, 2};
@@ -492,14 +601,30 @@ static int zoom2d_run(int dev, const cx<T>* in, cx<T>* out, int nxi, int nyi, in
     LP_TRACE("czt_rows", es * batch * nyi * (double)(nxi + nxo), s,
              launch_bluestein<T>(zx.L, false, in, tmp, Lines{(int64_t)nyi * nxi, nxi}, Lines{(int64_t)nyi * nxo, nxo},
                                  nyi, nxi, nxo, prex, chatx, postx, batch, twx, s));
+    int v = 0;
+    const Lines li{(int64_t)nyi * nxo, nxo}, lo{(int64_t)nyo * nxo, nxo};
+    LP_RET(col_variant<T>(dev, TUNE_CZT_COLS, zy.L, nxo, nyi, nyo, batch, (size_t)li.bstride * batch,
+                          (size_t)lo.bstride * batch, s,
+                          [&](int var, cx<T>* a, cx<T>* b) {
+                            return launch_bluestein<T>(zy.L, true, a, b, li, lo, nxo, nyi, nyo, prey, chaty, posty,
+                                                       batch, twy, s, var);
+                          },
+                          &v));
     LP_TRACE("czt_cols", es * batch * nxo * (double)(nyi + nyo), s,
-             launch_bluestein<T>(zy.L, true, tmp, out, Lines{(int64_t)nyi * nxo, nxo}, Lines{(int64_t)nyo * nxo, nxo},
-                                 nxo, nyi, nyo, prey, chaty, posty, batch, twy, s));
+             launch_bluestein<T>(zy.L, true, tmp, out, li, lo, nxo, nyi, nyo, prey, chaty, posty, batch, twy, s, v));
   } else {
     // cols: [nyi][nxi] -> tmp [nyo][nxi]; rows: tmp -> out [nyo][nxo]
+    int v = 0;
+    const Lines li{(int64_t)nyi * nxi, nxi}, lo{(int64_t)nyo * nxi, nxi};
+    LP_RET(col_variant<T>(dev, TUNE_CZT_COLS, zy.L, nxi, nyi, nyo, batch, (size_t)li.bstride * batch,
+                          (size_t)lo.bstride * batch, s,
+                          [&](int var, cx<T>* a, cx<T>* b) {
+                            return launch_bluestein<T>(zy.L, true, a, b, li, lo, nxi, nyi, nyo, prey, chaty, posty,
+                                                       batch, twy, s, var);
+                          },
+                          &v));
     LP_TRACE("czt_cols", es * batch * nxi * (double)(nyi + nyo), s,
-             launch_bluestein<T>(zy.L, true, in, tmp, Lines{(int64_t)nyi * nxi, nxi}, Lines{(int64_t)nyo * nxi, nxi},
-                                 nxi, nyi, nyo, prey, chaty, posty, batch, twy, s));
+             launch_bluestein<T>(zy.L, true, in, tmp, li, lo, nxi, nyi, nyo, prey, chaty, posty, batch, twy, s, v));
     LP_TRACE("czt_rows", es * batch * nyo * (double)(nxi + nxo), s,
              launch_bluestein<T>(zx.L, false, tmp, out, Lines{(int64_t)nyo * nxi, nxi}, Lines{(int64_t)nyo * nxo, nxo},
                                  nyo, nxi, nxo, prex, chatx, postx, batch, twx, s));
@@ -674,10 +799,19 @@ static int rw_fwd(const void* ex, const void* ey, void* const* outs, const prop_
   LP_TRACE("rw_rows", es * 3.0 * batch * nyi * (double)(nxi + nxo), s,
            launch_bluestein<T>(zx.L, false, P, M, Lines{(int64_t)nyi * nxi, nxi}, Lines{(int64_t)nyi * nxo, nxo}, nyi,
                                nxi, nxo, prex, chatx, postx, 3 * batch, twx, s));
+  const Lines li{(int64_t)nyi * nxo, nxo}, lo{(int64_t)nyo * nxo, nxo};
+  int v = 0;
+  LP_RET(col_variant<T>(dev, TUNE_CZT_COLS, zy.L, nxo, nyi, nyo, batch, (size_t)li.bstride * batch,
+                        (size_t)lo.bstride * batch, s,
+                        [&](int var, cx<T>* a, cx<T>* b) {
+                          return launch_bluestein<T>(zy.L, true, a, b, li, lo, nxo, nyi, nyo, prey, chaty, posty,
+                                                     batch, twy, s, var);
+                        },
+                        &v));
   for (int c = 0; c < 3; ++c)
     LP_TRACE("rw_cols", es * batch * nxo * (double)(nyi + nyo), s,
-             launch_bluestein<T>(zy.L, true, M + c * nm, (cx<T>*)outs[c], Lines{(int64_t)nyi * nxo, nxo},
-                                 Lines{(int64_t)nyo * nxo, nxo}, nxo, nyi, nyo, prey, chaty, posty, batch, twy, s));
+             launch_bluestein<T>(zy.L, true, M + c * nm, (cx<T>*)outs[c], li, lo, nxo, nyi, nyo, prey, chaty, posty,
+                                 batch, twy, s, v));
   return PROP_OK;
 }
 
@@ -700,10 +834,19 @@ static int rw_adj(const void* const* gs, void* gex, void* gey, const prop_grid* 
   LP_RET(get_tw<T>(dev, zy.L, &twy));
   const int nxi = gi->nx, nyi = gi->ny, nxo = go->nx, nyo = go->ny;
   const double es = sizeof(cx<T>);
+  const Lines li{(int64_t)nyo * nxo, nxo}, lo{(int64_t)nyi * nxo, nxo};
+  int v = 0;
+  LP_RET(col_variant<T>(dev, TUNE_CZT_COLS, zy.L, nxo, nyo, nyi, batch, (size_t)li.bstride * batch,
+                        (size_t)lo.bstride * batch, s,
+                        [&](int var, cx<T>* a, cx<T>* b) {
+                          return launch_bluestein<T>(zy.L, true, a, b, li, lo, nxo, nyo, nyi, prey, chaty, posty,
+                                                     batch, twy, s, var);
+                        },
+                        &v));
   for (int c = 0; c < 3; ++c)
     LP_TRACE("rw_cols", es * batch * nxo * (double)(nyi + nyo), s,
-             launch_bluestein<T>(zy.L, true, (const cx<T>*)gs[c], M + c * nm, Lines{(int64_t)nyo * nxo, nxo},
-                                 Lines{(int64_t)nyi * nxo, nxo}, nxo, nyo, nyi, prey, chaty, posty, batch, twy, s));
+             launch_bluestein<T>(zy.L, true, (const cx<T>*)gs[c], M + c * nm, li, lo, nxo, nyo, nyi, prey, chaty,
+                                 posty, batch, twy, s, v));
   LP_TRACE("rw_rows", es * 3.0 * batch * nyi * (double)(nxi + nxo), s,
            launch_bluestein<T>(zx.L, false, M, P, Lines{(int64_t)nyi * nxo, nxo}, Lines{(int64_t)nyi * nxi, nxi}, nyi,
                                nxo, nxi, prex, chatx, postx, 3 * batch, twx, s));
@@ -782,6 +925,7 @@ struct prop_plan {
   hipEvent_t fork = nullptr;
   std::vector<hipEvent_t> join;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  bool tuned[2] = {false, false};  // PROP_PLAN_AUTOTUNE: first execution tunes
 };
 
 namespace lp {
@@ -933,6 +1077,16 @@ static int plan_enqueue(prop_plan* p, bool adjoint, hipStream_t st, bool branche
 }
 
 static int plan_run(prop_plan* p, bool adjoint, hipStream_t st) {
+  if ((p->flags & PROP_PLAN_AUTOTUNE) && !p->tuned[adjoint ? 1 : 0] && !capturing(st)) {
+    // first execution runs eagerly with the autotuner on; a graph is
+    // captured afterwards with the chosen variants
+    t_tune_request = true;
+    const int r = plan_enqueue(p, adjoint, st, false);
+    t_tune_request = false;
+    LP_RET(r);
+    p->tuned[adjoint ? 1 : 0] = true;
+    return r;
+  }
   if (!(p->flags & PROP_PLAN_GRAPH)) return plan_enqueue(p, adjoint, st, false);
   hipGraphExec_t& ex = p->gexec[adjoint ? 1 : 0];
   if (!ex) {
@@ -1261,6 +1415,36 @@ int prop_sampling_check(const prop_grid* g, double wavelength, double z) {
 
 int32_t prop_fft_length(int32_t n) { return fft_len(n); }
 
+int32_t prop_autotune_report(char* buf, int32_t cap) {
+  Ctx& C = ctx();
+  std::lock_guard<std::mutex> lk(C.mu);
+  std::string out;
+  static const char* kinds[] = {"rs_cols", "vrs_mix2", "czt_cols"};
+  for (const auto& kv : C.tuned) {
+    const TuneKey& k = kv.first;
+    const TuneEntry& e = kv.second;
+    char line[256];
+    const int esz = std::get<1>(k), kind = std::get<2>(k), n = std::get<3>(k);
+    const int lines = esz == 4 ? col_pass_lines<float>(kind, n, e.variant) : col_pass_lines<double>(kind, n, e.variant);
+    int m = std::snprintf(line, sizeof line,
+                          "dev %d %s %s n=%d lines=%d in=%d out=%d batch=%d -> variant %d (%d per workgroup); ms",
+                          std::get<0>(k), esz == 4 ? "c64" : "c128", kinds[kind], n, std::get<4>(k), std::get<5>(k),
+                          std::get<6>(k), std::get<7>(k), e.variant, lines);
+    out.append(line, (size_t)std::max(0, std::min<int>(m, (int)sizeof line - 1)));
+    for (int v = 0; v < kColVariants; ++v) {
+      m = e.ms[v] < 0 ? std::snprintf(line, sizeof line, " -") : std::snprintf(line, sizeof line, " %.4f", e.ms[v]);
+      out.append(line, (size_t)std::max(0, std::min<int>(m, (int)sizeof line - 1)));
+    }
+    out.push_back('\n');
+  }
+  if (buf && cap > 0) {
+    const size_t nc = std::min<size_t>(out.size(), (size_t)cap - 1);
+    std::memcpy(buf, out.data(), nc);
+    buf[nc] = 0;
+  }
+  return (int32_t)out.size() + 1;
+}
+
 void prop_cache_clear(void) {
   Ctx& C = ctx();
   std::lock_guard<std::mutex> lk(C.mu);
@@ -1276,6 +1460,11 @@ void prop_cache_clear(void) {
   }
   for (auto& kv : C.work) (void)hipFree(kv.second.p);
   for (auto& kv : C.scratch) (void)hipFree(kv.second.p);
+  for (auto& kv : C.tune_a) (void)hipFree(kv.second.p);
+  for (auto& kv : C.tune_b) (void)hipFree(kv.second.p);
+  C.tune_a.clear();
+  C.tune_b.clear();
+  C.tuned.clear();
   C.plans.clear();
   C.specs.clear();
   C.zooms.clear();

@@ -193,3 +193,41 @@ def test_plan_rejects_bad_setups(lp):
     bad = lp.Setup(lp.PROP_OP_RS, g, [v], [v.clone()], [v.clone()], -1.0, 1e-3)
     with pytest.raises(lp.PropError):
         lp.Plan([bad])
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_autotuned_plan_is_bit_identical(lp, graph):
+    """PROP_PLAN_AUTOTUNE times the lines-per-workgroup variants of the column
+    passes on scratch buffers at the first execution; every variant computes
+    the same numbers, so results equal those of an untuned plan bit for bit,
+    on the tuning execution and on later (graph) replays."""
+    import torch
+    import warnings
+    g = Grid.square(512, 4e-3)
+    win = Grid.square(512, 40e-6)
+    rng = np.random.default_rng(11)
+
+    def make(autotune):
+        v = torch.from_numpy(workloads.random_field(rng, (2, 512, 512)).astype(np.complex64)).cuda()
+        y_rs, y_czt = torch.empty_like(v), torch.empty_like(v)
+        g_rs, g_czt = torch.empty_like(v), torch.empty_like(v)
+        s1 = lp.Setup(lp.PROP_OP_RS, g, [v], [y_rs], [y_rs], 600e-9, 30e-3, grad_inputs=[g_rs])
+        s2 = lp.Setup(lp.PROP_OP_CZT, g, [v], [y_czt], [y_czt], 600e-9, 40e-3, window=win, grad_inputs=[g_czt])
+        return lp.Plan([s1, s2], graph=graph, autotune=autotune), (v, y_rs, y_czt, g_rs, g_czt)
+
+    rng = np.random.default_rng(11)
+    p0, t0 = make(False)
+    rng = np.random.default_rng(11)
+    p1, t1 = make(True)
+    assert torch.equal(t0[0], t1[0])
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        for rep in range(2):
+            p0.forward(); p0.adjoint(); p1.forward(); p1.adjoint()
+            torch.cuda.synchronize()
+            for a, b in zip(t0[1:], t1[1:]):
+                assert torch.equal(a, b), f"replay {rep}"
+    report = lp.prop_autotune_report()
+    say(report)
+    assert "rs_cols n=1024" in report and "czt_cols n=1024" in report
+    p0.close(); p1.close()
