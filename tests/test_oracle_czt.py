@@ -129,3 +129,17 @@ def test_rs_and_czt_agree_near_axis():
     cz = oracle.czt_propagate(u, gin, win, wl, z)
     sl = slice(256 - 32, 256 + 32)
     assert rel_l2(cz, rs[sl, sl]) < 1e-6
+
+
+def test_czt_grad_z_matches_central_difference_of_loss():
+    gi = Grid(24, 20, 3e-6, 3e-6, 2e-6, -1e-6)
+    win = Grid(14, 12, 0.8e-6, 0.9e-6, 1e-6, 0.5e-6)
+    rng = np.random.default_rng(22)
+    u = rng.standard_normal((20, 24)) + 1j * rng.standard_normal((20, 24))
+    c = rng.standard_normal((12, 14)) + 1j * rng.standard_normal((12, 14))
+    wl, z = 600e-9, 2e-3
+    L = lambda zz: float(np.sum(np.real(np.conj(c) * oracle.czt_propagate(u, gi, win, wl, zz))))
+    h = 1e-11  # k h ~ 1e-4 rad
+    fd = (L(z + h) - L(z - h)) / (2 * h)
+    an = oracle.czt_grad_z(u, c, gi, win, wl, z)
+    assert abs(fd - an) <= 1e-6 * abs(an)

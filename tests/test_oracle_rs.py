@@ -142,3 +142,28 @@ def test_sampling_reading():
     assert not oracle.rs_sampling_ok(g, 650e-9, 20e-3)
     # 128^2 1 mm at 650 nm, z = 5 mm is undersampled (z_min ~ 24 mm)
     assert not oracle.rs_sampling_ok(Grid.square(128, 1e-3), 650e-9, 5e-3)
+
+
+def test_kernel_dz_matches_central_difference():
+    X, Y = np.meshgrid(np.linspace(-40e-6, 40e-6, 9), np.linspace(-30e-6, 50e-6, 7))
+    for z in (20e-6, 3e-3):
+        h = 1e-11  # k h ~ 1e-4 rad: the phase e^{ikr} must barely turn over the step
+        fd = (oracle.rs_kernel(X, Y, z + h, 600e-9) - oracle.rs_kernel(X, Y, z - h, 600e-9)) / (2 * h)
+        an = oracle.rs_kernel_dz(X, Y, z, 600e-9)
+        assert np.abs(fd - an).max() <= 1e-6 * np.abs(an).max()
+
+
+def test_rs_grad_z_matches_central_difference_of_loss():
+    # L(z) = Re <c, RS_z u>: dL/dz from the analytic kernel derivative
+    g = Grid(20, 16, 4e-6, 5e-6)
+    rng = np.random.default_rng(21)
+    u = rng.standard_normal((16, 20)) + 1j * rng.standard_normal((16, 20))
+    c = rng.standard_normal((16, 20)) + 1j * rng.standard_normal((16, 20))
+    wl, z = 550e-9, 150e-6
+    L = lambda zz: float(np.sum(np.real(np.conj(c) * oracle.rs_propagate(u, g, wl, zz))))
+    h = 1e-11
+    fd = (L(z + h) - L(z - h)) / (2 * h)
+    an = oracle.rs_grad_z(u, c, g, wl, z)
+    assert abs(fd - an) <= 1e-6 * abs(an)
+    both = oracle.rs_grad_z(np.stack([u, 2 * u]), np.stack([c, c]), g, wl, z)
+    assert np.allclose(both, [an, 2 * an], rtol=1e-12)
