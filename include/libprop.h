@@ -143,6 +143,30 @@ int vczt_adjoint(prop_dtype t, const void* gx, const void* gy, const void* gz, v
                  const prop_grid* g_in, const prop_grid* win, double wavelength, double z,
                  const prop_lens* lens, int32_t batch, void* stream);
 
+/* ------------------------------------------------- distance gradients --
+ * Derivative of L with respect to the propagation distance z, for a loss
+ * whose gradient seed on the output is g_out (g = dL/dRe + i dL/dIm, the
+ * adjoints' convention).  Every experiment of the paper optimises
+ * distances along with the phase masks (Results; Methods, parameter
+ * spaces include the distances z_i).  dz: device double [batch], one value
+ * per batch item, dL/dz = Re sum conj(g_out) dU/dz (FP64 fixed-order
+ * reduction).
+ * rs_grad_z: dU/dz = dx dy sum U0 dH/dz with the RS-I kernel derivative
+ *   dH/dz = (1/2pi) e^{ikr} [1/r^3 - ik/r^2 + z^2 (k^2/r^3 + 3ik/r^4 - 3/r^5)]
+ *   (one RS pass with that kernel's spectrum, cached like H).  Same limits
+ *   and sampling warning as rs_propagate.
+ * czt_grad_z: differentiating every z-dependent factor of the CZT sum,
+ *   dU/dz = (ik - 1/z - ik|X|^2/(2z^2)) U - (ik/(2z^2)) C[|x|^2 U0]
+ *           + (2 pi i/(lambda z^2)) (X C[x U0] + Y C[y U0]),
+ *   C = czt_propagate; u_out = C[u_in] if the caller has it, else NULL
+ *   (computed internally).
+ */
+int rs_grad_z(prop_dtype t, const void* u_in, const void* g_out, double* dz, const prop_grid* g,
+              double wavelength, double z, int32_t batch, void* stream);
+int czt_grad_z(prop_dtype t, const void* u_in, const void* u_out, const void* g_out, double* dz,
+               const prop_grid* g_in, const prop_grid* win, double wavelength, double z, int32_t batch,
+               void* stream);
+
 /* ------------------------------------------------- sources and elements --
  * Gaussian source (paper: Methods, light sources of any wavelength and
  * power): out = amplitude exp(-r^2/w0^2) [exp(-i k r^2 / 2 lens_f) if

@@ -19,7 +19,7 @@ from ._lib import PropError, PropWarning  # noqa: F401
 
 __all__ = [
     "rs_propagate", "rs_adjoint", "czt_propagate", "czt_adjoint", "vrs_propagate", "vrs_adjoint",
-    "vczt_propagate", "vczt_adjoint", "prop_source_gaussian", "prop_source_radial", "prop_modulate",
+    "vczt_propagate", "vczt_adjoint", "rs_grad_z", "czt_grad_z", "prop_source_gaussian", "prop_source_radial", "prop_modulate",
     "prop_phase_grad", "prop_waveplate", "prop_waveplate_adjoint", "prop_spot_loss", "prop_sampling_check",
     "prop_fft_length", "prop_cache_clear", "prop_trace_enable", "prop_trace_read", "prop_autotune_report",
     "PropError", "PropWarning", "library", "Plan", "Setup", "PROP_OP_RS", "PROP_OP_CZT", "PROP_OP_VRS",
@@ -127,6 +127,37 @@ def czt_adjoint(g_out, grid_in, window, wavelength, z, out=None):
 
 
 # --------------------------------------------------------------- VRS / VCZT --
+
+def rs_grad_z(u, g_out, grid, wavelength, z):
+    """dL/dz per batch item (float64 tensor [batch]) for the RS propagation of
+    u with output gradient seed g_out."""
+    lib = library()
+    _dev(u), _dev(g_out)
+    b = _batch(u, grid)
+    dz = torch.empty((b,), dtype=torch.float64, device=u.device)
+    with torch.cuda.device(u.device):
+        st = lib.rs_grad_z(_dtype_code(u), _ptr(u), _ptr(g_out), _ptr(dz), ctypes.byref(_lib.grid(grid)),
+                           float(wavelength), float(z), b, _stream(u))
+    _lib.check("rs_grad_z", st)
+    return dz
+
+
+def czt_grad_z(u, g_out, grid_in, window, wavelength, z, u_out=None):
+    """dL/dz per batch item for the CZT propagation of u onto `window` with
+    output gradient seed g_out; u_out = czt_propagate(u, ...) if available."""
+    lib = library()
+    _dev(u), _dev(g_out)
+    if u_out is not None:
+        _dev(u_out)
+    b = _batch(u, grid_in)
+    dz = torch.empty((b,), dtype=torch.float64, device=u.device)
+    with torch.cuda.device(u.device):
+        st = lib.czt_grad_z(_dtype_code(u), _ptr(u), _ptr(u_out), _ptr(g_out), _ptr(dz),
+                            ctypes.byref(_lib.grid(grid_in)), ctypes.byref(_lib.grid(window)), float(wavelength),
+                            float(z), b, _stream(u))
+    _lib.check("czt_grad_z", st)
+    return dz
+
 
 def vrs_propagate(ex, ey, grid, wavelength, z):
     lib = library()

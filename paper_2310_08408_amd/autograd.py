@@ -5,38 +5,65 @@ by reverse-mode autodiff; for a linear operator A the backward is A^H).
 With torch's complex gradient convention (g = dL/dRe + i dL/dIm) the
 gradient of an input x of y = A x is A^H g_y; for U = V exp(i phi) it is
 dL/dphi = Im(g_U conj(U)) and g_V = g_U exp(-i phi).
+
+RS and CZT also accept the distance z as a 0-d float64 tensor; when it
+requires grad, backward returns dL/dz (rs_grad_z / czt_grad_z summed over
+the batch, since one z is shared by all batch items).
 """
 from __future__ import annotations
 
 import torch
 
-from . import (czt_adjoint, czt_propagate, prop_modulate, prop_phase_grad, prop_spot_loss, prop_waveplate,
-               prop_waveplate_adjoint, rs_adjoint, rs_propagate, vczt_adjoint, vczt_propagate, vrs_adjoint,
-               vrs_propagate)
+from . import (czt_adjoint, czt_grad_z, czt_propagate, prop_modulate, prop_phase_grad, prop_spot_loss,
+               prop_waveplate, prop_waveplate_adjoint, rs_adjoint, rs_grad_z, rs_propagate, vczt_adjoint,
+               vczt_propagate, vrs_adjoint, vrs_propagate)
+
+
+def _zval(z):
+    return float(z.detach()) if isinstance(z, torch.Tensor) else float(z)
 
 
 class RS(torch.autograd.Function):
     @staticmethod
     def forward(ctx, u, grid, wavelength, z):
-        ctx.args = (grid, wavelength, z)
-        return rs_propagate(u.contiguous(), grid, wavelength, z)
+        u = u.contiguous()
+        ctx.args = (grid, wavelength, _zval(z))
+        ctx.z_tensor = isinstance(z, torch.Tensor)
+        ctx.save_for_backward(u)
+        return rs_propagate(u, grid, wavelength, _zval(z))
 
     @staticmethod
     def backward(ctx, g):
         grid, wl, z = ctx.args
-        return rs_adjoint(g.contiguous(), grid, wl, z), None, None, None
+        (u,) = ctx.saved_tensors
+        g = g.contiguous()
+        gz = None
+        if ctx.z_tensor and ctx.needs_input_grad[3]:
+            gz = rs_grad_z(u, g, grid, wl, z).sum()
+        gu = rs_adjoint(g, grid, wl, z) if ctx.needs_input_grad[0] else None
+        return gu, None, None, gz
 
 
 class CZT(torch.autograd.Function):
     @staticmethod
     def forward(ctx, u, grid_in, window, wavelength, z):
-        ctx.args = (grid_in, window, wavelength, z)
-        return czt_propagate(u.contiguous(), grid_in, window, wavelength, z)
+        u = u.contiguous()
+        ctx.args = (grid_in, window, wavelength, _zval(z))
+        ctx.z_tensor = isinstance(z, torch.Tensor)
+        y = czt_propagate(u, grid_in, window, wavelength, _zval(z))
+        ctx.save_for_backward(u, y)
+        return y
 
     @staticmethod
     def backward(ctx, g):
         gi, win, wl, z = ctx.args
-        return czt_adjoint(g.contiguous(), gi, win, wl, z), None, None, None, None
+        u, y = ctx.saved_tensors
+        g = g.contiguous()
+        gz = None
+        if ctx.z_tensor and ctx.needs_input_grad[4]:
+            gz = czt_grad_z(u, g, gi, win, wl, z, u_out=y).sum()
+        gu = czt_adjoint(g, gi, win, wl, z) if ctx.needs_input_grad[0] else None
+        return gu, None, None, None, gz
 
 
 class VRS(torch.autograd.Function):

@@ -33,12 +33,22 @@ __global__ void k_rs_kernel_wrapped(cx<double>* out, int Mx, int My, int nx, int
       const double r = sqrt(r2);
       double sn, cs;
       sincos(k * r, &sn, &cs);
-      const double pre = z / (kTwoPi * r2);
-      // (1/r - i k) e^{ikr}
-      double re = (cs / r + k * sn) * pre;
-      double im = (sn / r - k * cs) * pre;
-      if (kind == 1) { re *= X / z; im *= X / z; }
-      if (kind == 2) { re *= Y / z; im *= Y / z; }
+      double re, im;
+      if (kind == 3) {
+        // dH/dz = (1/2pi) e^{ikr} [1/r^3 - ik/r^2 + z^2 (k^2/r^3 + 3ik/r^4 - 3/r^5)]
+        const double r3 = r2 * r, z2 = z * z;
+        const double A = (1.0 + z2 * k * k) / r3 - 3.0 * z2 / (r3 * r2);
+        const double B = -k / r2 + 3.0 * k * z2 / (r2 * r2);
+        re = (A * cs - B * sn) / kTwoPi;
+        im = (A * sn + B * cs) / kTwoPi;
+      } else {
+        const double pre = z / (kTwoPi * r2);
+        // (1/r - i k) e^{ikr}
+        re = (cs / r + k * sn) * pre;
+        im = (sn / r - k * cs) * pre;
+        if (kind == 1) { re *= X / z; im *= X / z; }
+        if (kind == 2) { re *= Y / z; im *= Y / z; }
+      }
       h = mk<double>(re, im);
     }
     out[t] = h;
@@ -313,6 +323,108 @@ hipError_t launch_jones_grad(const cx<T>* gx, const cx<T>* gy, const cx<T>* ex, 
   hipLaunchKernelGGL((k_jones_grad_partial<T>), dim3(nblk, batch), dim3(256), 0, s, gx, gy, ex, ey, j8, partial, nblk,
                      npix);
   hipLaunchKernelGGL(k_sum_partials2, dim3(batch), dim3(256), 0, s, partial, nblk, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------- distance gradients --
+// Re sum conj(a) b over each batch item's npix elements (FP64, fixed order).
+template <typename T>
+__global__ __launch_bounds__(256) void k_redot_partial(const cx<T>* a, const cx<T>* b, double* partial, int nblk,
+                                                       int64_t npix) {
+  __shared__ double sh[256];
+  const int bi = blockIdx.y;
+  double acc[1] = {0.0};
+  const int64_t off = (int64_t)bi * npix;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < npix; i += (int64_t)nblk * 256) {
+    const cx<T> x = a[off + i], y = b[off + i];
+    acc[0] += (double)x.x * (double)y.x + (double)x.y * (double)y.y;
+  }
+  block_reduce<1>(acc, sh);
+  if (threadIdx.x == 0) partial[(int64_t)bi * nblk + blockIdx.x] = acc[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials1(const double* partial, int nblk, double* out) {
+  __shared__ double sh[256];
+  const int b = blockIdx.x;
+  double acc[1] = {0.0};
+  for (int i = threadIdx.x; i < nblk; i += 256) acc[0] += partial[(int64_t)b * nblk + i];
+  block_reduce<1>(acc, sh);
+  if (threadIdx.x == 0) out[b] = acc[0];
+}
+
+template <typename T>
+hipError_t launch_redot(const cx<T>* a, const cx<T>* b, double* out, double* partial, int nblk, int64_t npix,
+                        int batch, hipStream_t s) {
+  hipLaunchKernelGGL((k_redot_partial<T>), dim3(nblk, batch), dim3(256), 0, s, a, b, partial, nblk, npix);
+  hipLaunchKernelGGL(k_sum_partials1, dim3(batch), dim3(256), 0, s, partial, nblk, out);
+  return hipGetLastError();
+}
+
+// CZT distance gradient, inputs of the three extra transforms:
+// o = [ (x^2 + y^2) u | x u | y u ], each [batch][ny][nx].
+template <typename T>
+__global__ void k_czt_dz_prep(const cx<T>* u, cx<T>* o, int nx, int ny, double dx, double dy, double cx0,
+                              double cy0, int64_t plane_b) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < plane_b;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t pix = t % ((int64_t)nx * ny);
+    const int i = (int)(pix / nx), j = (int)(pix - (int64_t)i * nx);
+    const double x = cx0 + (j - nx / 2) * dx, y = cy0 + (i - ny / 2) * dy;
+    const cx<T> v = u[t];
+    o[t] = cscale(v, (T)(x * x + y * y));
+    o[plane_b + t] = cscale(v, (T)x);
+    o[2 * plane_b + t] = cscale(v, (T)y);
+  }
+}
+
+template <typename T>
+hipError_t launch_czt_dz_prep(const cx<T>* u, cx<T>* o, int nx, int ny, double dx, double dy, double cx0, double cy0,
+                              int batch, hipStream_t s) {
+  const int64_t pb = (int64_t)nx * ny * batch;
+  hipLaunchKernelGGL((k_czt_dz_prep<T>), dim3(ew_blocks(pb)), dim3(256), 0, s, u, o, nx, ny, dx, dy, cx0, cy0, pb);
+  return hipGetLastError();
+}
+
+// Per batch item: Re sum conj(g) [a U + c1 T1 + c2 (X T2 + Y T3)] with
+// a = -1/z + i (k - k |X|^2 / (2 z^2)), c1 = -i k / (2 z^2),
+// c2 = i 2 pi / (lambda z^2) (the z-derivative of the Fresnel sum).
+template <typename T>
+__global__ __launch_bounds__(256) void k_czt_dz_partial(const cx<T>* g, const cx<T>* U, const cx<T>* Tt, int nx,
+                                                        int ny, double dX, double dY, double cX, double cY, double k,
+                                                        double z, double wl, double* partial, int nblk,
+                                                        int64_t plane_b) {
+  __shared__ double sh[256];
+  const int bi = blockIdx.y;
+  const int64_t npix = (int64_t)nx * ny;
+  const int64_t off = (int64_t)bi * npix;
+  const double iz2 = 1.0 / (z * z);
+  const double c1 = -0.5 * k * iz2;       // times i
+  const double c2 = kTwoPi / wl * iz2;    // times i
+  double acc[1] = {0.0};
+  for (int64_t p = blockIdx.x * 256 + threadIdx.x; p < npix; p += (int64_t)nblk * 256) {
+    const int q = (int)(p / nx), pp = (int)(p - (int64_t)q * nx);
+    const double X = cX + (pp - nx / 2) * dX, Y = cY + (q - ny / 2) * dY;
+    const cx<T> gv = g[off + p], u = U[off + p], t1 = Tt[off + p], t2 = Tt[plane_b + off + p],
+                t3 = Tt[2 * plane_b + off + p];
+    const double ar = -1.0 / z, ai = k - 0.5 * k * (X * X + Y * Y) * iz2;
+    // w = a U + i c1 T1 + i c2 (X T2 + Y T3)
+    const double sr = X * t2.x + Y * t3.x, si = X * t2.y + Y * t3.y;
+    const double wr = ar * u.x - ai * u.y - c1 * t1.y - c2 * si;
+    const double wi = ar * u.y + ai * u.x + c1 * t1.x + c2 * sr;
+    acc[0] += (double)gv.x * wr + (double)gv.y * wi;
+  }
+  block_reduce<1>(acc, sh);
+  if (threadIdx.x == 0) partial[(int64_t)bi * nblk + blockIdx.x] = acc[0];
+}
+
+template <typename T>
+hipError_t launch_czt_dz_reduce(const cx<T>* g, const cx<T>* U, const cx<T>* Tt, int nx, int ny, double dX, double dY,
+                                double cX, double cY, double k, double z, double wl, double* out, double* partial,
+                                int nblk, int batch, hipStream_t s) {
+  const int64_t pb = (int64_t)nx * ny * batch;
+  hipLaunchKernelGGL((k_czt_dz_partial<T>), dim3(nblk, batch), dim3(256), 0, s, g, U, Tt, nx, ny, dX, dY, cX, cY, k,
+                     z, wl, partial, nblk, pb);
+  hipLaunchKernelGGL(k_sum_partials1, dim3(batch), dim3(256), 0, s, partial, nblk, out);
   return hipGetLastError();
 }
 
@@ -647,6 +759,12 @@ hipError_t launch_spot_loss(const cx<T>* ex, const cx<T>* ey, const cx<T>* ez, i
 // ------------------------------------------------------ instantiations --
 #define LP_INST(T)                                                                                                  \
   template hipError_t launch_extract_half<T>(const cx<double>*, cx<T>*, int, int, hipStream_t);                  \
+  template hipError_t launch_redot<T>(const cx<T>*, const cx<T>*, double*, double*, int, int64_t, int, hipStream_t); \
+  template hipError_t launch_czt_dz_prep<T>(const cx<T>*, cx<T>*, int, int, double, double, double, double, int,   \
+                                            hipStream_t);                                                           \
+  template hipError_t launch_czt_dz_reduce<T>(const cx<T>*, const cx<T>*, const cx<T>*, int, int, double, double,  \
+                                              double, double, double, double, double, double*, double*, int, int,  \
+                                              hipStream_t);                                                         \
   template hipError_t launch_zoom_vectors<T>(const ZoomSpec&, cx<T>*, cx<T>*, cx<double>*, hipStream_t);            \
   template hipError_t launch_convert<T>(const cx<double>*, cx<T>*, int64_t, hipStream_t);                           \
   template hipError_t launch_phase_stage<T>(const cx<T>*, const T*, cx<T>*, int, int, double, double, double,       \

@@ -76,13 +76,29 @@ int col_pass_lines(int kind, int n, int variant);
 
 // ---- FP64 generators (setup work) ----
 // Wrapped RS kernel on an My x Mx grid (complex128), kind 0: H, 1: (X/z) H,
-// 2: (Y/z) H.  Offsets d in [-(n-1), n-1] sit at index d mod M, the rest 0.
+// 2: (Y/z) H, 3: dH/dz.  Offsets d in [-(n-1), n-1] sit at index d mod M,
+// the rest 0.
 hipError_t launch_rs_kernel_wrapped(cx<double>* out, int Mx, int My, int nx, int ny, double dx,
                                     double dy, double k, double z, int kind, hipStream_t s);
 // Kernel-spectrum table: rows ky = 0..My/2 of the full spectrum (the rest
 // follows from its parity in ky), all columns, stored in 4-column tiles
 // like the RS workspace: (ky, kx) at (kx / 4) (My/2+1) 4 + ky 4 + kx % 4, so
 // a column pass reads its tile's spectrum as one contiguous block.
+// Distance gradients.  Re sum conj(a) b per batch item (npix elements each)
+// into out[batch] (FP64, fixed order; partial: batch * nblk doubles).
+template <typename T>
+hipError_t launch_redot(const cx<T>* a, const cx<T>* b, double* out, double* partial, int nblk, int64_t npix,
+                        int batch, hipStream_t s);
+// o = [(x^2+y^2) u | x u | y u] on the input grid (three [batch][ny][nx] planes).
+template <typename T>
+hipError_t launch_czt_dz_prep(const cx<T>* u, cx<T>* o, int nx, int ny, double dx, double dy, double cx0, double cy0,
+                              int batch, hipStream_t s);
+// out[b] = Re sum conj(g) dU/dz from U = C[u] and Tt = [C[(x^2+y^2)u] | C[xu] |
+// C[yu]] on the window grid (nx, ny, dX, dY, cX, cY).
+template <typename T>
+hipError_t launch_czt_dz_reduce(const cx<T>* g, const cx<T>* U, const cx<T>* Tt, int nx, int ny, double dX, double dY,
+                                double cX, double cY, double k, double z, double wl, double* out, double* partial,
+                                int nblk, int batch, hipStream_t s);
 template <typename T>
 hipError_t launch_extract_half(const cx<double>* full, cx<T>* q, int Mx, int My, hipStream_t s);
 

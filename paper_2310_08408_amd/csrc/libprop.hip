@@ -146,7 +146,7 @@ struct PlanEntry {
 };
 
 struct SpecEntry {
-  void* q[3] = {nullptr, nullptr, nullptr};
+  void* q[4] = {nullptr, nullptr, nullptr, nullptr};  // kinds: H, (X/z)H, (Y/z)H, dH/dz
   int Mx = 0, My = 0;
 };
 
@@ -234,8 +234,8 @@ static int get_tw(int dev, int n, const cx<T>** tw) {
 
 // ----------------------------------------------------- RS kernel spectra --
 template <typename T>
-static int get_rs_spectra(int dev, const prop_grid* g, double wl, double z, bool vec, hipStream_t s,
-                          const cx<T>* q[3], int* Mx_out, int* My_out) {
+static int get_rs_spectra(int dev, const prop_grid* g, double wl, double z, int kinds, hipStream_t s,
+                          const cx<T>* q[4], int* Mx_out, int* My_out) {
   Ctx& C = ctx();
   const int Mx = fft_len(2 * g->nx - 1), My = fft_len(2 * g->ny - 1);
   *Mx_out = Mx;
@@ -244,9 +244,8 @@ static int get_rs_spectra(int dev, const prop_grid* g, double wl, double z, bool
   SpecEntry& e = C.specs[key];
   e.Mx = Mx;
   e.My = My;
-  const int nk = vec ? 3 : 1;
   bool need = false;
-  for (int k = 0; k < nk; ++k) need |= (e.q[k] == nullptr);
+  for (int k = 0; k < 4; ++k) need |= ((kinds >> k) & 1) && e.q[k] == nullptr;
   if (need) {
     const cx<double> *twx, *twy;
     LP_RET(get_tw<double>(dev, Mx, &twx));
@@ -256,8 +255,8 @@ static int get_rs_spectra(int dev, const prop_grid* g, double wl, double z, bool
     cx<double>* full = (cx<double>*)sb.p;
     const size_t qbytes = (size_t)((Mx + 3) / 4 * 4) * (My / 2 + 1) * sizeof(cx<T>);
     const double k = 2.0 * kPi / wl;
-    for (int kind = 0; kind < nk; ++kind) {
-      if (e.q[kind]) continue;
+    for (int kind = 0; kind < 4; ++kind) {
+      if (!((kinds >> kind) & 1) || e.q[kind]) continue;
       void* qp = nullptr;
       hipError_t er = hipMalloc(&qp, qbytes);
       if (er != hipSuccess) return dev_err(er);
@@ -271,7 +270,7 @@ static int get_rs_spectra(int dev, const prop_grid* g, double wl, double z, bool
     }
     LP_TRY(hipStreamSynchronize(s));
   }
-  for (int kk = 0; kk < 3; ++kk) q[kk] = (const cx<T>*)e.q[kk];
+  for (int kk = 0; kk < 4; ++kk) q[kk] = (const cx<T>*)e.q[kk];
   return PROP_OK;
 }
 
@@ -442,12 +441,13 @@ static size_t rs_work_bytes(prop_dtype t, const prop_grid* g, int batch) {
 
 template <typename T>
 static int rs_run(const void* in, void* out, const prop_grid* g, double wl, double z, int batch, hipStream_t s,
-                  bool adjoint, void* work) {
+                  bool adjoint, void* work, int spec_kind = 0) {
   int dev;
   LP_RET(cur_device(&dev));
-  const cx<T>* q[3];
+  const cx<T>* q[4];
   int Mx, My;
-  LP_RET(get_rs_spectra<T>(dev, g, wl, z, false, s, q, &Mx, &My));
+  LP_RET(get_rs_spectra<T>(dev, g, wl, z, 1 << spec_kind, s, q, &Mx, &My));
+  q[0] = q[spec_kind];
   const cx<T> *twx, *twy;
   LP_RET(get_tw<T>(dev, Mx, &twx));
   LP_RET(get_tw<T>(dev, My, &twy));
@@ -506,9 +506,9 @@ static int vrs_run(const void* const* ins, int nin, void* const* outs, int nout,
                    double z, int batch, hipStream_t s, bool adjoint, void* work) {
   int dev;
   LP_RET(cur_device(&dev));
-  const cx<T>* q[3];
+  const cx<T>* q[4];
   int Mx, My;
-  LP_RET(get_rs_spectra<T>(dev, g, wl, z, true, s, q, &Mx, &My));
+  LP_RET(get_rs_spectra<T>(dev, g, wl, z, 7, s, q, &Mx, &My));
   const cx<T> *twx, *twy;
   LP_RET(get_tw<T>(dev, Mx, &twx));
   LP_RET(get_tw<T>(dev, My, &twy));
@@ -720,6 +720,59 @@ static int czt_entry(prop_dtype t, const void* in, void* out, const prop_grid* g
   LP_RET(ensure_buf(wb, czt_work_bytes(t, gi, go, batch), s));
   return t == PROP_C64 ? czt_run<float>(in, out, gi, go, wl, z, batch, s, adjoint, wb.p)
                        : czt_run<double>(in, out, gi, go, wl, z, batch, s, adjoint, wb.p);
+}
+
+// ------------------------------------------------- distance gradients --
+static int red_blocks(int64_t npix) { return (int)std::max<int64_t>(1, std::min<int64_t>((npix + 255) / 256, 256)); }
+
+static size_t rs_grad_z_bytes(prop_dtype t, const prop_grid* g, int batch) {
+  const size_t plane = (size_t)g->nx * g->ny * batch * esize(t);
+  return rs_work_bytes(t, g, batch) + plane + (size_t)batch * red_blocks((int64_t)g->nx * g->ny) * sizeof(double) + 256;
+}
+
+// dL/dz = Re sum conj(g_out) dU/dz, dU/dz = RS with the kernel dH/dz.
+template <typename T>
+static int rs_grad_z_run(const void* u, const void* gout, double* dz, const prop_grid* g, double wl, double z, int batch,
+                         hipStream_t s, void* work) {
+  const int64_t npix = (int64_t)g->nx * g->ny;
+  char* w = (char*)work;
+  cx<T>* V = (cx<T>*)(w + rs_work_bytes(sizeof(T) == 4 ? PROP_C64 : PROP_C128, g, batch));
+  double* partial = (double*)(((uintptr_t)(V + npix * batch) + 255) & ~(uintptr_t)255);
+  LP_RET(rs_run<T>(u, V, g, wl, z, batch, s, false, work, 3));
+  const int nblk = red_blocks(npix);
+  LP_TRY(launch_redot<T>((const cx<T>*)gout, V, dz, partial, nblk, npix, batch, s));
+  return PROP_OK;
+}
+
+static size_t czt_grad_z_bytes(prop_dtype t, const prop_grid* gi, const prop_grid* go, int batch, bool need_u) {
+  const size_t ni = (size_t)gi->nx * gi->ny * batch, no = (size_t)go->nx * go->ny * batch;
+  return (czt_tmp_elems(gi, go) * 3 * batch + 3 * ni + 3 * no + (need_u ? no : 0)) * esize(t) +
+         (size_t)batch * red_blocks((int64_t)go->nx * go->ny) * sizeof(double) + 256;
+}
+
+// dL/dz = Re sum conj(g_out) dU/dz from U = C[u] and the three extra
+// transforms C[|x|^2 u], C[x u], C[y u] (C = czt_propagate).
+template <typename T>
+static int czt_grad_z_run(const void* u, const void* uo, const void* gout, double* dz, const prop_grid* gi,
+                          const prop_grid* go, double wl, double z, int batch, hipStream_t s, void* work) {
+  const prop_dtype t = sizeof(T) == 4 ? PROP_C64 : PROP_C128;
+  const size_t ni = (size_t)gi->nx * gi->ny * batch, no = (size_t)go->nx * go->ny * batch;
+  cx<T>* P = (cx<T>*)work;  // 3 input planes
+  cx<T>* Tt = P + 3 * ni;   // 3 output planes
+  cx<T>* U = Tt + 3 * no;   // forward result when not given
+  void* cw = U + (uo ? 0 : no);
+  double* partial =
+      (double*)(((uintptr_t)((char*)cw + czt_work_bytes(t, gi, go, 3 * batch)) + 255) & ~(uintptr_t)255);
+  if (!uo) {
+    LP_RET(czt_run<T>(u, U, gi, go, wl, z, batch, s, false, cw));
+    uo = U;
+  }
+  LP_TRY(launch_czt_dz_prep<T>((const cx<T>*)u, P, gi->nx, gi->ny, gi->dx, gi->dy, gi->cx, gi->cy, batch, s));
+  LP_RET(czt_run<T>(P, Tt, gi, go, wl, z, 3 * batch, s, false, cw));
+  const int nblk = red_blocks((int64_t)go->nx * go->ny);
+  LP_TRY(launch_czt_dz_reduce<T>((const cx<T>*)gout, (const cx<T>*)uo, Tt, go->nx, go->ny, go->dx, go->dy, go->cx,
+                                 go->cy, 2.0 * kPi / wl, z, wl, dz, partial, nblk, batch, s));
+  return PROP_OK;
 }
 
 // ----------------------------------------------------------- VCZT runs --
@@ -967,7 +1020,7 @@ static size_t setup_work_bytes(prop_dtype t, const prop_setup& s) {
 // Fill the caches (spectra, chirps, twiddles) a setup needs, on stream s.
 template <typename T>
 static int warm_setup(int dev, const prop_setup& s, hipStream_t st) {
-  const cx<T>* q[3];
+  const cx<T>* q[4];
   const cx<T>* tw;
   int Mx, My;
   const cx<T> *a, *b, *c;
@@ -975,7 +1028,7 @@ static int warm_setup(int dev, const prop_setup& s, hipStream_t st) {
   switch (s.op) {
     case PROP_OP_RS:
     case PROP_OP_VRS:
-      LP_RET(get_rs_spectra<T>(dev, &s.g_in, s.wavelength, s.z, s.op == PROP_OP_VRS, st, q, &Mx, &My));
+      LP_RET(get_rs_spectra<T>(dev, &s.g_in, s.wavelength, s.z, s.op == PROP_OP_VRS ? 7 : 1, st, q, &Mx, &My));
       LP_RET(get_tw<T>(dev, Mx, &tw));
       LP_RET(get_tw<T>(dev, My, &tw));
       return PROP_OK;
@@ -1127,6 +1180,46 @@ int rs_propagate(prop_dtype t, const void* u_in, void* u_out, const prop_grid* g
 int rs_adjoint(prop_dtype t, const void* g_out, void* g_in, const prop_grid* g, double wavelength, double z,
                int32_t batch, void* stream) {
   return rs_entry(t, g_out, g_in, g, wavelength, z, batch, stream, true);
+}
+
+int rs_grad_z(prop_dtype t, const void* u_in, const void* g_out, double* dz, const prop_grid* g, double wavelength,
+              double z, int32_t batch, void* stream) {
+  LP_RET(check_common(t, batch, wavelength));
+  LP_RET(check_grid(g));
+  if (!(z > 0) || !is_finite(z)) return PROP_EPARAM;
+  if (fft_len(2 * g->nx - 1) < 0 || fft_len(2 * g->ny - 1) < 0) return PROP_ESHAPE;
+  const int warn = sampling(g, wavelength, z);
+  if (batch == 0) return warn;
+  if (!u_in || !g_out || !dz) return PROP_ENULL;
+  std::lock_guard<std::mutex> lk(ctx().mu);
+  const hipStream_t s = (hipStream_t)stream;
+  int dev;
+  LP_RET(cur_device(&dev));
+  Buf& wb = ctx().work[{dev, s}];
+  LP_RET(ensure_buf(wb, rs_grad_z_bytes(t, g, batch), s));
+  const int r = t == PROP_C64 ? rs_grad_z_run<float>(u_in, g_out, dz, g, wavelength, z, batch, s, wb.p)
+                              : rs_grad_z_run<double>(u_in, g_out, dz, g, wavelength, z, batch, s, wb.p);
+  return r < 0 ? r : warn;
+}
+
+int czt_grad_z(prop_dtype t, const void* u_in, const void* u_out, const void* g_out, double* dz,
+               const prop_grid* g_in, const prop_grid* win, double wavelength, double z, int32_t batch,
+               void* stream) {
+  LP_RET(check_common(t, batch, wavelength));
+  LP_RET(check_grid(g_in));
+  LP_RET(check_grid(win));
+  if (!(z > 0) || !is_finite(z)) return PROP_EPARAM;
+  LP_RET(check_czt_shapes(g_in, win));
+  if (batch == 0) return PROP_OK;
+  if (!u_in || !g_out || !dz) return PROP_ENULL;
+  std::lock_guard<std::mutex> lk(ctx().mu);
+  const hipStream_t s = (hipStream_t)stream;
+  int dev;
+  LP_RET(cur_device(&dev));
+  Buf& wb = ctx().work[{dev, s}];
+  LP_RET(ensure_buf(wb, czt_grad_z_bytes(t, g_in, win, batch, u_out == nullptr), s));
+  return t == PROP_C64 ? czt_grad_z_run<float>(u_in, u_out, g_out, dz, g_in, win, wavelength, z, batch, s, wb.p)
+                       : czt_grad_z_run<double>(u_in, u_out, g_out, dz, g_in, win, wavelength, z, batch, s, wb.p);
 }
 
 int czt_propagate(prop_dtype t, const void* u_in, void* u_out, const prop_grid* g_in, const prop_grid* win,
@@ -1451,7 +1544,7 @@ void prop_cache_clear(void) {
   (void)hipDeviceSynchronize();
   for (auto& kv : C.plans) (void)hipFree(kv.second.tw);
   for (auto& kv : C.specs)
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < 4; ++k)
       if (kv.second.q[k]) (void)hipFree(kv.second.q[k]);
   for (auto& kv : C.zooms) {
     (void)hipFree(kv.second.pre);
