@@ -636,3 +636,101 @@ def czt_grad_z(u, g_out, g_in, win, wavelength: float, z: float):
           + (TWO_PI * 1j / (wavelength * z * z)) * (X[None, :] * C(x[None, :] * u) + Y[:, None] * C(y[:, None] * u)))
     red = np.sum(np.real(np.conj(g_out) * du), axis=(-2, -1))
     return float(red) if np.ndim(red) == 0 else red
+
+
+# --------------------------------------------------------------------------
+# The paper's detector side: STED effective intensity, threshold-density
+# loss, soft minimum over detectors (Methods: STED microscopy; loss function)
+# --------------------------------------------------------------------------
+
+def sted_intensity(i_ex, i_dep, beta: float):
+    """Effective fluorescence I_eff = I_ex [1 - beta (1 - exp(-I_dep/I_ex))]
+    (Methods, STED microscopy, Beer-Lambert-type quenching).  Where I_ex = 0
+    the paper's limit applies: I_eff = 0."""
+    i_ex = np.asarray(i_ex, dtype=np.float64)
+    i_dep = np.asarray(i_dep, dtype=np.float64)
+    out = np.zeros(np.broadcast(i_ex, i_dep).shape)
+    pos = i_ex > 0
+    r = np.where(pos, i_dep / np.where(pos, i_ex, 1.0), 0.0)
+    out = np.where(pos, i_ex * (1.0 - beta * (1.0 - np.exp(-r))), 0.0)
+    return out
+
+
+def sted_intensity_partials(i_ex, i_dep, beta: float):
+    """(dI_eff/dI_ex, dI_eff/dI_dep), differentiated by hand with r = I_dep/I_ex:
+    dI_eff/dI_ex = 1 - beta + beta e^{-r} (1 + r), dI_eff/dI_dep = -beta e^{-r}.
+    At I_ex = 0 the limits are taken: r -> infinity if I_dep > 0
+    (partials 1 - beta, 0), r = 0 if I_dep = 0 (partials 1, -beta)."""
+    i_ex = np.asarray(i_ex, dtype=np.float64)
+    i_dep = np.asarray(i_dep, dtype=np.float64)
+    pos = i_ex > 0
+    r = np.where(pos, i_dep / np.where(pos, i_ex, 1.0), np.where(i_dep > 0, np.inf, 0.0))
+    e = np.exp(-r)
+    fin = np.isfinite(r)
+    re = np.zeros_like(r)
+    re[fin] = r[fin] * e[fin]  # r e^{-r} -> 0 as r -> infinity
+    return 1.0 - beta + beta * (e + re), -beta * e
+
+
+def intensity_ordered(*fields):
+    """I = sum_c (Re E_c^2 + Im E_c^2), accumulated component by component in
+    FP64 in the order given (the order the GPU reduction also uses, so that
+    threshold decisions are taken on identical values)."""
+    acc = None
+    for e in fields:
+        e = _as_c128(e)
+        t = e.real * e.real + e.imag * e.imag
+        acc = t if acc is None else acc + t
+    return acc
+
+
+def density_loss(intensity, eps: float):
+    """Threshold-density loss L = Area / I_eps (Results, loss function;
+    Methods, loss function): i_eps = i where i > eps * i_max else 0,
+    I_eps = sum i_eps, Area = number of pixels with i_eps > 0.
+
+    The selection is a comparison, so (as with the paper's where()-based
+    evaluation) the gradient flows through the selected values only:
+    dL/di = -Area / I_eps^2 on the selected pixels, 0 elsewhere.
+    Returns (loss, area, I_eps, i_max, dL/di)."""
+    i = np.asarray(intensity, dtype=np.float64)
+    imax = float(i.max())
+    sel = i > eps * imax
+    area = float(np.count_nonzero(sel & (i > 0)))
+    ieps = float(np.sum(np.where(sel, i, 0.0)))
+    loss = area / ieps
+    grad = np.where(sel & (i > 0), -area / (ieps * ieps), 0.0)
+    return loss, area, ieps, imax, grad
+
+
+def density_loss_fields(comps, eps: float, dep=None, beta: float = 1.0):
+    """Density loss of the intensity of field components `comps` (optionally
+    STED-modulated by the depletion components `dep`), with the gradient
+    seeds g_c = 2 E_c dL/dI_c of every component (C5).
+    Returns (loss, area, I_eps, i_max, seeds_comps, seeds_dep)."""
+    i_ex = intensity_ordered(*comps)
+    if dep:
+        i_dep = intensity_ordered(*dep)
+        i = sted_intensity(i_ex, i_dep, beta)
+    else:
+        i = i_ex
+    loss, area, ieps, imax, dldi = density_loss(i, eps)
+    if dep:
+        pe, pd = sted_intensity_partials(i_ex, i_dep, beta)
+        d_ex, d_dep = dldi * pe, dldi * pd
+    else:
+        d_ex, d_dep = dldi, None
+    seeds = [2.0 * d_ex * _as_c128(e) for e in comps]
+    seeds_dep = [2.0 * d_dep * _as_c128(e) for e in dep] if dep else []
+    return loss, area, ieps, imax, seeds, seeds_dep
+
+
+def softmin(losses, beta: float):
+    """Smooth minimum over detectors, -log(sum exp(-beta l)) / beta (Methods,
+    exploration of optical topologies), evaluated with the minimum factored
+    out; returns (value, weights) with weights = d value / d l (a softmax)."""
+    l = np.asarray(losses, dtype=np.float64)
+    m = l.min()
+    w = np.exp(-beta * (l - m))
+    s = w.sum()
+    return float(m - np.log(s) / beta), w / s
