@@ -212,7 +212,35 @@ int prop_spot_loss(prop_dtype t, const void* ex, const void* ey, const void* ez,
                    double wavelength, double w_fz, double* result, void* gx, void* gy, void* gz,
                    int32_t batch, void* stream);
 
-/* ------------------------------------------------------------- utility -- */
+/* The paper's detector side (Methods: STED microscopy; loss function;
+ * exploration of optical topologies).
+ * prop_density_loss: threshold-density loss L = Area / I_eps of the
+ *   detected intensity I, with i_eps = I where I > eps * max I (0 <= eps <= 1),
+ *   I_eps = sum i_eps, Area = number of such pixels.  I is the intensity of
+ *   the ncomp (1..3) field components comps[k] (e.g. E_x, E_y for the radial
+ *   component, E_z alone for the longitudinal one), formed in FP64 as
+ *   sum_k (Re^2 + Im^2) in the order given.  With ndep > 0 it is the STED
+ *   effective intensity I_eff = I_ex [1 - beta (1 - exp(-I_dep / I_ex))]
+ *   (0 where I_ex = 0) of that excitation intensity and the depletion
+ *   intensity of the fields dep[k], quenching efficiency 0 <= beta <= 1.
+ *   Every field: device [batch][npix] of dtype t.  result: device double
+ *   [batch][4] = (L, Area, I_eps, max I).  seeds / dep_seeds (optional
+ *   arrays of ncomp / ndep device pointers, entries may be NULL): gradient
+ *   seeds g_c = 2 E_c dL/dI_c, where dL/dI = -Area / I_eps^2 on the
+ *   selected pixels and 0 elsewhere (the selection itself carries no
+ *   gradient), chained through dI_eff/dI_ex = 1 - beta + beta e^{-r}(1 + r)
+ *   and dI_eff/dI_dep = -beta e^{-r}, r = I_dep / I_ex.
+ * prop_softmin: smooth minimum over ndet detector losses per batch item,
+ *   value = -log(sum exp(-beta l)) / beta (beta > 0), weights (optional,
+ *   [batch][ndet]) = d value / d l.  All pointers are device doubles.
+ */
+int prop_density_loss(prop_dtype t, const void* const* comps, int32_t ncomp, const void* const* dep,
+                      int32_t ndep, double beta, int64_t npix, double eps, double* result,
+                      void* const* seeds, void* const* dep_seeds, int32_t batch, void* stream);
+int prop_softmin(const double* losses, int32_t ndet, double beta, double* value, double* weights,
+                 int32_t batch, void* stream);
+
+/* ------------------------------------------------------------- utility -- *//* ------------------------------------------------------------- utility -- */
 /* Host-only sampling check of RS/VRS: PROP_OK or PROP_WUNDERSAMPLED. */
 int prop_sampling_check(const prop_grid* g, double wavelength, double z);
 /* Smallest supported transform length >= n, or -1 above 8192.  Supported

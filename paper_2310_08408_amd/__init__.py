@@ -20,7 +20,8 @@ from ._lib import PropError, PropWarning  # noqa: F401
 __all__ = [
     "rs_propagate", "rs_adjoint", "czt_propagate", "czt_adjoint", "vrs_propagate", "vrs_adjoint",
     "vczt_propagate", "vczt_adjoint", "rs_grad_z", "czt_grad_z", "prop_source_gaussian", "prop_source_radial", "prop_modulate",
-    "prop_phase_grad", "prop_waveplate", "prop_waveplate_adjoint", "prop_spot_loss", "prop_sampling_check",
+    "prop_phase_grad", "prop_waveplate", "prop_waveplate_adjoint", "prop_spot_loss", "prop_density_loss",
+    "prop_softmin", "prop_sampling_check",
     "prop_fft_length", "prop_cache_clear", "prop_trace_enable", "prop_trace_read", "prop_autotune_report",
     "PropError", "PropWarning", "library", "Plan", "Setup", "PROP_OP_RS", "PROP_OP_CZT", "PROP_OP_VRS",
     "PROP_OP_VCZT", "PROP_PLAN_GRAPH", "PROP_PLAN_AUTOTUNE",
@@ -324,6 +325,52 @@ def prop_spot_loss(ex, ey, ez, window, wavelength, w_fz=0.0, seeds=True):
                                 _stream(ex))
     _lib.check("prop_spot_loss", st)
     return res, ((gx, gy, gz) if seeds else None)
+
+
+def _ptr_array(tensors):
+    arr = (ctypes.c_void_p * max(len(tensors), 1))()
+    for k, t in enumerate(tensors):
+        arr[k] = t.data_ptr() if t is not None else None
+    return arr
+
+
+def prop_density_loss(comps, eps, dep=None, beta=1.0, seeds=True):
+    """Threshold-density loss Area / I_eps of the intensity of `comps` (STED-
+    modulated by `dep` if given).  Returns (result[batch, 4] float64 =
+    (loss, area, I_eps, max I), seeds for comps, seeds for dep)."""
+    lib = library()
+    comps = [c.contiguous() for c in comps]
+    dep = [d.contiguous() for d in (dep or [])]
+    for t in comps + dep:
+        _dev(t)
+    ref = comps[0]
+    npix = ref.shape[-1] * ref.shape[-2]
+    batch = ref.numel() // npix
+    res = torch.empty((batch, 4), dtype=torch.float64, device=ref.device)
+    gs = [torch.empty_like(c) for c in comps] if seeds else []
+    gd = [torch.empty_like(d) for d in dep] if seeds else []
+    with torch.cuda.device(ref.device):
+        st = lib.prop_density_loss(_dtype_code(ref), _ptr_array(comps), len(comps), _ptr_array(dep), len(dep),
+                                   float(beta), npix, float(eps), _ptr(res), _ptr_array(gs) if seeds else None,
+                                   _ptr_array(gd) if (seeds and dep) else None, batch, _stream(ref))
+    _lib.check("prop_density_loss", st)
+    return res, gs, gd
+
+
+def prop_softmin(losses, beta):
+    """Smooth minimum over the last axis of float64 `losses` [batch, ndet]:
+    returns (value[batch], weights[batch, ndet] = d value / d losses)."""
+    lib = library()
+    losses = losses.contiguous()
+    _dev(losses)
+    ndet = losses.shape[-1]
+    batch = losses.numel() // ndet
+    val = torch.empty((batch,), dtype=torch.float64, device=losses.device)
+    w = torch.empty((batch, ndet), dtype=torch.float64, device=losses.device)
+    with torch.cuda.device(losses.device):
+        st = lib.prop_softmin(_ptr(losses), ndet, float(beta), _ptr(val), _ptr(w), batch, _stream(losses))
+    _lib.check("prop_softmin", st)
+    return val, w
 
 
 def prop_sampling_check(grid, wavelength, z) -> int:

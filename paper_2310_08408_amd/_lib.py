@@ -78,6 +78,9 @@ SIGNATURES = {
     "prop_autotune_report": (c_int32, [ctypes.c_char_p, c_int32]),
     "rs_grad_z": (c_int32, [c_int32, P, P, P, G, c_double, c_double, c_int32, P]),
     "czt_grad_z": (c_int32, [c_int32, P, P, P, P, G, G, c_double, c_double, c_int32, P]),
+    "prop_density_loss": (c_int32, [c_int32, P, c_int32, P, c_int32, c_double, c_int64, c_double, P, P, P, c_int32,
+                                     P]),
+    "prop_softmin": (c_int32, [P, c_int32, c_double, P, P, c_int32, P]),
 }
 
 _lib = None

@@ -14,9 +14,9 @@ from __future__ import annotations
 
 import torch
 
-from . import (czt_adjoint, czt_grad_z, czt_propagate, prop_modulate, prop_phase_grad, prop_spot_loss,
-               prop_waveplate, prop_waveplate_adjoint, rs_adjoint, rs_grad_z, rs_propagate, vczt_adjoint,
-               vczt_propagate, vrs_adjoint, vrs_propagate)
+from . import (czt_adjoint, czt_grad_z, czt_propagate, prop_density_loss, prop_modulate, prop_phase_grad,
+               prop_softmin, prop_spot_loss, prop_waveplate, prop_waveplate_adjoint, rs_adjoint, rs_grad_z,
+               rs_propagate, vczt_adjoint, vczt_propagate, vrs_adjoint, vrs_propagate)
 
 
 def _zval(z):
@@ -156,3 +156,42 @@ class SpotLoss(torch.autograd.Function):
         shape = (-1,) + (1,) * (gx.dim() - 1)
         w = g.to(gx.real.dtype).reshape(shape)
         return gx * w, gy * w, (gz * w if ctx.has_ez else None), None, None, None
+
+
+class DensityLoss(torch.autograd.Function):
+    """Threshold-density loss Area / I_eps per batch item (float64 [batch]) of
+    the intensity of the first `ncomp` fields, STED-modulated by the
+    remaining fields (depletion beam) when there are any:
+    DensityLoss.apply(ncomp, eps, beta, *fields)."""
+
+    @staticmethod
+    def forward(ctx, ncomp, eps, beta, *fields):
+        comps, dep = list(fields[:ncomp]), list(fields[ncomp:])
+        res, gs, gd = prop_density_loss(comps, eps, dep or None, beta, seeds=True)
+        ctx.seeds = gs + gd
+        return res[:, 0].clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        scale = g.reshape(-1, 1, 1)
+        out = []
+        for sd in ctx.seeds:
+            out.append((sd.reshape(scale.shape[0], sd.shape[-2], sd.shape[-1]) * scale.to(sd.real.dtype)).reshape(
+                sd.shape))
+        return (None, None, None, *out)
+
+
+class SoftMin(torch.autograd.Function):
+    """Smooth minimum over the last axis of float64 losses [batch, ndet]."""
+
+    @staticmethod
+    def forward(ctx, losses, beta):
+        val, w = prop_softmin(losses, beta)
+        ctx.save_for_backward(w)
+        return val
+
+    @staticmethod
+    def backward(ctx, g):
+        (w,) = ctx.saved_tensors
+        return g.reshape(-1, 1) * w, None
+

@@ -428,6 +428,204 @@ hipError_t launch_czt_dz_reduce(const cx<T>* g, const cx<T>* U, const cx<T>* Tt,
   return hipGetLastError();
 }
 
+// ------------------------------------------------------ detector losses --
+// Threshold-density loss L = Area / I_eps of the intensity of up to three
+// field components, optionally STED-modulated by up to three depletion
+// components: I_eff = I_ex [1 - beta (1 - exp(-I_dep / I_ex))], 0 where
+// I_ex = 0.  Intensities are formed in FP64 without contraction, component
+// by component (re^2 + im^2), so that the threshold decisions do not depend
+// on instruction selection.
+struct Comps {
+  const void* p[3];
+  int n;
+};
+
+template <typename T>
+__device__ __forceinline__ double comp_intensity(const Comps& c, int64_t i) {
+  double acc = 0.0;
+  for (int k = 0; k < c.n; ++k) {
+    const cx<T> v = reinterpret_cast<const cx<T>*>(c.p[k])[i];
+    const double t = __dadd_rn(__dmul_rn((double)v.x, (double)v.x), __dmul_rn((double)v.y, (double)v.y));
+    acc = k == 0 ? t : __dadd_rn(acc, t);
+  }
+  return acc;
+}
+
+__device__ __forceinline__ double sted_eff(double iex, double idep, double beta) {
+  if (!(iex > 0.0)) return 0.0;
+  return iex * (1.0 - beta * (1.0 - exp(-idep / iex)));
+}
+
+template <typename T>
+__device__ __forceinline__ double det_intensity(const Comps& ex, const Comps& dep, double beta, int64_t i,
+                                                double* iex_out, double* idep_out) {
+  const double iex = comp_intensity<T>(ex, i);
+  const double idep = dep.n > 0 ? comp_intensity<T>(dep, i) : 0.0;
+  *iex_out = iex;
+  *idep_out = idep;
+  return dep.n > 0 ? sted_eff(iex, idep, beta) : iex;
+}
+
+__device__ __forceinline__ double block_max256(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_dens_max(Comps ex, Comps dep, double beta, int64_t npix, int nblk,
+                                                  double* pmax) {
+  __shared__ double sh[256];
+  const int b = blockIdx.y;
+  double m = 0.0;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < npix; i += (int64_t)nblk * 256) {
+    double a, d;
+    m = fmax(m, det_intensity<T>(ex, dep, beta, (int64_t)b * npix + i, &a, &d));
+  }
+  const double r = block_max256(m, sh);
+  if (threadIdx.x == 0) pmax[(int64_t)b * nblk + blockIdx.x] = r;
+}
+
+__device__ __forceinline__ double batch_max(const double* pmax, int nblk, int b) {
+  double m = 0.0;
+  for (int k = 0; k < nblk; ++k) m = fmax(m, pmax[(int64_t)b * nblk + k]);
+  return m;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_dens_sum(Comps ex, Comps dep, double beta, double eps, int64_t npix,
+                                                  int nblk, const double* pmax, double* psum) {
+  __shared__ double sh[2 * 256];
+  const int b = blockIdx.y;
+  const double thr = eps * batch_max(pmax, nblk, b);
+  double acc[2] = {0.0, 0.0};
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < npix; i += (int64_t)nblk * 256) {
+    double a, d;
+    const double v = det_intensity<T>(ex, dep, beta, (int64_t)b * npix + i, &a, &d);
+    if (v > thr && v > 0.0) {
+      acc[0] += 1.0;
+      acc[1] += v;
+    }
+  }
+  block_reduce<2>(acc, sh);
+  if (threadIdx.x == 0) {
+    psum[((int64_t)b * nblk + blockIdx.x) * 2 + 0] = acc[0];
+    psum[((int64_t)b * nblk + blockIdx.x) * 2 + 1] = acc[1];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_dens_final(const double* pmax, const double* psum, int nblk, double* res) {
+  __shared__ double sh[2 * 256];
+  const int b = blockIdx.x;
+  double acc[2] = {0.0, 0.0};
+  for (int k = threadIdx.x; k < nblk; k += 256) {
+    acc[0] += psum[((int64_t)b * nblk + k) * 2 + 0];
+    acc[1] += psum[((int64_t)b * nblk + k) * 2 + 1];
+  }
+  block_reduce<2>(acc, sh);
+  if (threadIdx.x == 0) {
+    res[b * 4 + 0] = acc[0] / acc[1];
+    res[b * 4 + 1] = acc[0];
+    res[b * 4 + 2] = acc[1];
+    res[b * 4 + 3] = batch_max(pmax, nblk, b);
+  }
+}
+
+// Seeds g_c = 2 E_c dL/dI_c: dL/dI = -Area / I_eps^2 on the selected pixels,
+// chained through the STED partials dI_eff/dI_ex = 1 - beta + beta e^{-r}
+// (1 + r), dI_eff/dI_dep = -beta e^{-r} (r = I_dep / I_ex; limits at I_ex = 0).
+struct Outs {
+  void* p[3];
+  int n;
+};
+
+template <typename T>
+__global__ void k_dens_seed(Comps ex, Comps dep, double beta, double eps, int64_t npix, int batch, const double* res,
+                            Outs gex, Outs gdep) {
+  const int64_t total = npix * batch;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(t / npix);
+    const double area = res[b * 4 + 1], ieps = res[b * 4 + 2], thr = eps * res[b * 4 + 3];
+    double iex, idep;
+    const double v = det_intensity<T>(ex, dep, beta, t, &iex, &idep);
+    const double dldi = (v > thr && v > 0.0) ? -area / (ieps * ieps) : 0.0;
+    double pe = 1.0, pd = 0.0;
+    if (dep.n > 0) {
+      double r, e;
+      if (iex > 0.0) {
+        r = idep / iex;
+        e = exp(-r);
+        pe = 1.0 - beta + beta * e * (1.0 + r);
+      } else if (idep > 0.0) {
+        e = 0.0;
+        pe = 1.0 - beta;
+      } else {
+        e = 1.0;
+        pe = 1.0;
+      }
+      pd = -beta * e;
+    }
+    for (int k = 0; k < gex.n; ++k) {
+      if (!gex.p[k]) continue;
+      const cx<T> a = reinterpret_cast<const cx<T>*>(ex.p[k])[t];
+      const double f = 2.0 * dldi * pe;
+      reinterpret_cast<cx<T>*>(gex.p[k])[t] = mk<T>((T)(f * a.x), (T)(f * a.y));
+    }
+    for (int k = 0; k < gdep.n; ++k) {
+      if (!gdep.p[k]) continue;
+      const cx<T> a = reinterpret_cast<const cx<T>*>(dep.p[k])[t];
+      const double f = 2.0 * dldi * pd;
+      reinterpret_cast<cx<T>*>(gdep.p[k])[t] = mk<T>((T)(f * a.x), (T)(f * a.y));
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_density_loss(const void* const* comps, int ncomp, const void* const* dep, int ndep, double beta,
+                               int64_t npix, double eps, double* res, double* scratch, int nblk, void* const* seeds,
+                               void* const* dep_seeds, int batch, hipStream_t s) {
+  Comps ce{{nullptr, nullptr, nullptr}, ncomp}, cd{{nullptr, nullptr, nullptr}, ndep};
+  for (int k = 0; k < ncomp; ++k) ce.p[k] = comps[k];
+  for (int k = 0; k < ndep; ++k) cd.p[k] = dep[k];
+  double* pmax = scratch;
+  double* psum = scratch + (size_t)batch * nblk;
+  hipLaunchKernelGGL((k_dens_max<T>), dim3(nblk, batch), dim3(256), 0, s, ce, cd, beta, npix, nblk, pmax);
+  hipLaunchKernelGGL((k_dens_sum<T>), dim3(nblk, batch), dim3(256), 0, s, ce, cd, beta, eps, npix, nblk, pmax, psum);
+  hipLaunchKernelGGL(k_dens_final, dim3(batch), dim3(256), 0, s, pmax, psum, nblk, res);
+  Outs oe{{nullptr, nullptr, nullptr}, seeds ? ncomp : 0}, od{{nullptr, nullptr, nullptr}, dep_seeds ? ndep : 0};
+  bool any = false;
+  for (int k = 0; k < oe.n; ++k) any |= (oe.p[k] = seeds[k]) != nullptr;
+  for (int k = 0; k < od.n; ++k) any |= (od.p[k] = dep_seeds[k]) != nullptr;
+  if (any)
+    hipLaunchKernelGGL((k_dens_seed<T>), dim3(ew_blocks(npix * batch)), dim3(256), 0, s, ce, cd, beta, eps, npix, batch,
+                       res, oe, od);
+  return hipGetLastError();
+}
+
+// Soft minimum over detectors per batch item: value = m - log(sum exp(-beta
+// (l - m))) / beta with m = min l; weights = d value / d l.
+__global__ void k_softmin(const double* l, int ndet, double beta, double* val, double* w, int batch) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  const double* lb = l + (int64_t)b * ndet;
+  double m = lb[0];
+  for (int i = 1; i < ndet; ++i) m = fmin(m, lb[i]);
+  double sum = 0.0;
+  for (int i = 0; i < ndet; ++i) sum += exp(-beta * (lb[i] - m));
+  val[b] = m - log(sum) / beta;
+  if (w)
+    for (int i = 0; i < ndet; ++i) w[(int64_t)b * ndet + i] = exp(-beta * (lb[i] - m)) / sum;
+}
+
+hipError_t launch_softmin(const double* l, int ndet, double beta, double* val, double* w, int batch, hipStream_t s) {
+  hipLaunchKernelGGL(k_softmin, dim3((batch + 63) / 64), dim3(64), 0, s, l, ndet, beta, val, w, batch);
+  return hipGetLastError();
+}
+
 // focusing pupil map
 __device__ __forceinline__ bool pupil_coeffs(double x, double y, double f, double na, double m[6]) {
   const double X2 = x * x + y * y;
@@ -760,6 +958,9 @@ hipError_t launch_spot_loss(const cx<T>* ex, const cx<T>* ey, const cx<T>* ez, i
 #define LP_INST(T)                                                                                                  \
   template hipError_t launch_extract_half<T>(const cx<double>*, cx<T>*, int, int, hipStream_t);                  \
   template hipError_t launch_redot<T>(const cx<T>*, const cx<T>*, double*, double*, int, int64_t, int, hipStream_t); \
+  template hipError_t launch_density_loss<T>(const void* const*, int, const void* const*, int, double, int64_t,     \
+                                             double, double*, double*, int, void* const*, void* const*, int,       \
+                                             hipStream_t);                                                          \
   template hipError_t launch_czt_dz_prep<T>(const cx<T>*, cx<T>*, int, int, double, double, double, double, int,   \
                                             hipStream_t);                                                           \
   template hipError_t launch_czt_dz_reduce<T>(const cx<T>*, const cx<T>*, const cx<T>*, int, int, double, double,  \

@@ -89,6 +89,17 @@ hipError_t launch_rs_kernel_wrapped(cx<double>* out, int Mx, int My, int nx, int
 template <typename T>
 hipError_t launch_redot(const cx<T>* a, const cx<T>* b, double* out, double* partial, int nblk, int64_t npix,
                         int batch, hipStream_t s);
+// Threshold-density detector loss of the intensity of ncomp field
+// components (optionally STED-modulated by ndep depletion components with
+// quenching efficiency beta): res[batch][4] = (Area / I_eps, Area, I_eps,
+// i_max); seeds (optional, per component) g_c = 2 E_c dL/dI_c.  scratch:
+// 3 * batch * nblk doubles.
+template <typename T>
+hipError_t launch_density_loss(const void* const* comps, int ncomp, const void* const* dep, int ndep, double beta,
+                               int64_t npix, double eps, double* res, double* scratch, int nblk, void* const* seeds,
+                               void* const* dep_seeds, int batch, hipStream_t s);
+// Soft minimum of ndet losses per batch item and its weights (d value / d l).
+hipError_t launch_softmin(const double* l, int ndet, double beta, double* val, double* w, int batch, hipStream_t s);
 // o = [(x^2+y^2) u | x u | y u] on the input grid (three [batch][ny][nx] planes).
 template <typename T>
 hipError_t launch_czt_dz_prep(const cx<T>* u, cx<T>* o, int nx, int ny, double dx, double dy, double cx0, double cy0,

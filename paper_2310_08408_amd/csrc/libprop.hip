@@ -1508,6 +1508,42 @@ int prop_sampling_check(const prop_grid* g, double wavelength, double z) {
 
 int32_t prop_fft_length(int32_t n) { return fft_len(n); }
 
+int prop_density_loss(prop_dtype t, const void* const* comps, int32_t ncomp, const void* const* dep, int32_t ndep,
+                      double beta, int64_t npix, double eps, double* result, void* const* seeds,
+                      void* const* dep_seeds, int32_t batch, void* stream) {
+  if (t != PROP_C64 && t != PROP_C128) return PROP_EPARAM;
+  if (ncomp < 1 || ncomp > 3 || ndep < 0 || ndep > 3 || npix < 1 || batch < 0) return PROP_ESHAPE;
+  if (!(eps >= 0.0 && eps <= 1.0) || !(beta >= 0.0 && beta <= 1.0)) return PROP_EPARAM;
+  if (batch == 0) return PROP_OK;
+  if (!comps || !result || (ndep > 0 && !dep)) return PROP_ENULL;
+  for (int k = 0; k < ncomp; ++k)
+    if (!comps[k]) return PROP_ENULL;
+  for (int k = 0; k < ndep; ++k)
+    if (!dep[k]) return PROP_ENULL;
+  std::lock_guard<std::mutex> lk(ctx().mu);
+  const hipStream_t s = (hipStream_t)stream;
+  int dev;
+  LP_RET(cur_device(&dev));
+  const int nblk = red_blocks(npix);
+  Buf& wb = ctx().work[{dev, s}];
+  LP_RET(ensure_buf(wb, (size_t)3 * batch * nblk * sizeof(double), s));
+  LP_TRY(t == PROP_C64 ? launch_density_loss<float>(comps, ncomp, dep, ndep, beta, npix, eps, result, (double*)wb.p,
+                                                    nblk, seeds, dep_seeds, batch, s)
+                       : launch_density_loss<double>(comps, ncomp, dep, ndep, beta, npix, eps, result, (double*)wb.p,
+                                                     nblk, seeds, dep_seeds, batch, s));
+  return PROP_OK;
+}
+
+int prop_softmin(const double* losses, int32_t ndet, double beta, double* value, double* weights, int32_t batch,
+                 void* stream) {
+  if (ndet < 1 || batch < 0) return PROP_ESHAPE;
+  if (!(beta > 0.0) || !is_finite(beta)) return PROP_EPARAM;
+  if (batch == 0) return PROP_OK;
+  if (!losses || !value) return PROP_ENULL;
+  LP_TRY(launch_softmin(losses, ndet, beta, value, weights, batch, (hipStream_t)stream));
+  return PROP_OK;
+}
+
 int32_t prop_autotune_report(char* buf, int32_t cap) {
   Ctx& C = ctx();
   std::lock_guard<std::mutex> lk(C.mu);

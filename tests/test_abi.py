@@ -74,6 +74,18 @@ def test_validation_without_device(lib):
     assert lib.vrs_propagate(0, fake, ctypes.c_void_p(0x2000000), out, out, ctypes.c_void_p(0x300000000),
                              ref(g), 5e-7, 1e-2, 1, None) == -4
     assert lib.prop_modulate(0, fake, fake, out, 10, 2, 3, None) == -2
+    # distance gradients: z = 0 and a missing output
+    assert lib.rs_grad_z(0, fake, fake, out, ref(g), 5e-7, 0.0, 1, None) == -3
+    assert lib.czt_grad_z(0, fake, None, fake, None, ref(g), ref(g), 5e-7, 1e-3, 1, None) == -1
+    # detector side: component counts, threshold and efficiency ranges, softmin beta
+    comps = (ctypes.c_void_p * 3)(fake.value, fake.value, fake.value)
+    assert lib.prop_density_loss(0, comps, 0, None, 0, 1.0, 16, 0.5, out, None, None, 1, None) == -2
+    assert lib.prop_density_loss(0, comps, 2, None, 4, 1.0, 16, 0.5, out, None, None, 1, None) == -2
+    assert lib.prop_density_loss(0, comps, 2, None, 0, 1.0, 16, 1.5, out, None, None, 1, None) == -3
+    assert lib.prop_density_loss(0, comps, 2, None, 1, 1.2, 16, 0.5, out, None, None, 1, None) == -3
+    assert lib.prop_density_loss(0, comps, 2, None, 1, 1.0, 16, 0.5, out, None, None, 1, None) == -1
+    assert lib.prop_softmin(out, 3, 0.0, out, None, 1, None) == -3
+    assert lib.prop_softmin(out, 0, 1.0, out, None, 1, None) == -2
 
 
 def test_lengths_and_sampling(lib):
