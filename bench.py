@@ -7,11 +7,12 @@ a 4096^2 padded transform and CZT to the focal plane onto a 2048^2 window of
 40 um.  One step, for a batch of B fields resident in HBM:
 
     U = V exp(i phi)                       (SLM)
-    Y = RS(U),  G = RS^H(Y),  g_phi += Im(G conj U)     (grad of |Y|^2 / 2)
+    Y = RS(U),  G = RS^H(Y),  g_phi  = Im(G conj U)     (grad of |Y|^2 / 2)
     Y = CZT(U), G = CZT^H(Y), g_phi += Im(G conj U)
 
 i.e. 2 B gradients (one forward + one adjoint of one propagator on one
-field each).  Prints one JSON line.
+field each).  The adjoints write g_phi directly from their last pass
+(rs/czt_adjoint_phase_grad).  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -53,7 +54,6 @@ class Step:
         self.lp, self.w, self.v, self.phi = lp, w, v, phi
         self.u = torch.empty_like(v)
         self.y = torch.empty_like(v)
-        self.g = torch.empty_like(v)
         self.grad = torch.empty(v.shape, dtype=phi.dtype, device=v.device)
 
     def __call__(self):
@@ -61,11 +61,9 @@ class Step:
         g, win, wl = w["grid"], w["window"], w["wavelength"]
         lp.prop_modulate(self.v, self.phi, out=self.u)
         lp.rs_propagate(self.u, g, wl, w["z_rs"], out=self.y)
-        lp.rs_adjoint(self.y, g, wl, w["z_rs"], out=self.g)
-        lp.prop_phase_grad(self.g, self.u, grad=self.grad)
+        lp.rs_adjoint_phase_grad(self.y, self.u, g, wl, w["z_rs"], grad=self.grad)
         lp.czt_propagate(self.u, g, win, wl, w["z_czt"], out=self.y)
-        lp.czt_adjoint(self.y, g, win, wl, w["z_czt"], out=self.g)
-        lp.prop_phase_grad(self.g, self.u, grad=self.grad, accumulate=True)
+        lp.czt_adjoint_phase_grad(self.y, self.u, g, win, wl, w["z_czt"], grad=self.grad, accumulate=True)
 
 
 def time_steps(torch, step, steps, warmup):

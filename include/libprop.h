@@ -143,6 +143,22 @@ int vczt_adjoint(prop_dtype t, const void* gx, const void* gy, const void* gz, v
                  const prop_grid* g_in, const prop_grid* win, double wavelength, double z,
                  const prop_lens* lens, int32_t batch, void* stream);
 
+/* Adjoint fused with the SLM phase gradient (the last pass of the adjoint
+ * writes it directly; paper: Methods, one free phase per SLM pixel, and the
+ * gradients of the loss with respect to it).  For U = V exp(i phi) entering
+ * the propagator, g_U = A^H g_out and dL/dphi = Im(g_U conj U):
+ * grad (real, [batch][ny][nx] of the input grid) receives Im(g_U conj u),
+ * added to its contents when accumulate != 0.  g_u (may be NULL) receives
+ * g_U itself.  u: the modulated field that entered the propagator.  Same
+ * geometry, limits and warnings as rs_adjoint / czt_adjoint.
+ */
+int rs_adjoint_phase_grad(prop_dtype t, const void* g_out, const void* u, void* g_u, void* grad,
+                          int32_t accumulate, const prop_grid* g, double wavelength, double z,
+                          int32_t batch, void* stream);
+int czt_adjoint_phase_grad(prop_dtype t, const void* g_out, const void* u, void* g_u, void* grad,
+                           int32_t accumulate, const prop_grid* g_in, const prop_grid* win,
+                           double wavelength, double z, int32_t batch, void* stream);
+
 /* ------------------------------------------------- distance gradients --
  * Derivative of L with respect to the propagation distance z, for a loss
  * whose gradient seed on the output is g_out (g = dL/dRe + i dL/dIm, the

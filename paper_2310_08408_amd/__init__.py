@@ -19,7 +19,8 @@ from ._lib import PropError, PropWarning  # noqa: F401
 
 __all__ = [
     "rs_propagate", "rs_adjoint", "czt_propagate", "czt_adjoint", "vrs_propagate", "vrs_adjoint",
-    "vczt_propagate", "vczt_adjoint", "rs_grad_z", "czt_grad_z", "prop_source_gaussian", "prop_source_radial", "prop_modulate",
+    "vczt_propagate", "vczt_adjoint", "rs_grad_z", "czt_grad_z", "rs_adjoint_phase_grad", "czt_adjoint_phase_grad",
+    "prop_source_gaussian", "prop_source_radial", "prop_modulate",
     "prop_phase_grad", "prop_waveplate", "prop_waveplate_adjoint", "prop_spot_loss", "prop_density_loss",
     "prop_softmin", "prop_sampling_check",
     "prop_fft_length", "prop_cache_clear", "prop_trace_enable", "prop_trace_read", "prop_autotune_report",
@@ -128,6 +129,43 @@ def czt_adjoint(g_out, grid_in, window, wavelength, z, out=None):
 
 
 # --------------------------------------------------------------- VRS / VCZT --
+
+def _phase_grad_out(u, grad, g_u):
+    if grad is None:
+        grad = torch.empty(u.shape, dtype=_real_dtype(u), device=u.device)
+    gu = torch.empty_like(u) if g_u is True else g_u
+    return grad, (gu if gu is not None and gu is not False else None)
+
+
+def rs_adjoint_phase_grad(g_out, u, grid, wavelength, z, grad=None, accumulate=False, g_u=None):
+    """RS adjoint fused with the SLM phase gradient: grad (+)= Im(g_U conj u),
+    g_U = rs_adjoint(g_out).  g_u=True also returns g_U (or pass a tensor).
+    Returns (grad, g_U or None)."""
+    lib = library()
+    _dev(g_out), _dev(u)
+    grad, gu = _phase_grad_out(u, grad, g_u)
+    b = _batch(u, grid)
+    with torch.cuda.device(u.device):
+        st = lib.rs_adjoint_phase_grad(_dtype_code(u), _ptr(g_out), _ptr(u), _ptr(gu), _ptr(grad),
+                                       1 if accumulate else 0, ctypes.byref(_lib.grid(grid)), float(wavelength),
+                                       float(z), b, _stream(u))
+    _lib.check("rs_adjoint_phase_grad", st)
+    return grad, gu
+
+
+def czt_adjoint_phase_grad(g_out, u, grid_in, window, wavelength, z, grad=None, accumulate=False, g_u=None):
+    """CZT adjoint fused with the SLM phase gradient (see rs_adjoint_phase_grad)."""
+    lib = library()
+    _dev(g_out), _dev(u)
+    grad, gu = _phase_grad_out(u, grad, g_u)
+    b = _batch(u, grid_in)
+    with torch.cuda.device(u.device):
+        st = lib.czt_adjoint_phase_grad(_dtype_code(u), _ptr(g_out), _ptr(u), _ptr(gu), _ptr(grad),
+                                        1 if accumulate else 0, ctypes.byref(_lib.grid(grid_in)),
+                                        ctypes.byref(_lib.grid(window)), float(wavelength), float(z), b, _stream(u))
+    _lib.check("czt_adjoint_phase_grad", st)
+    return grad, gu
+
 
 def rs_grad_z(u, g_out, grid, wavelength, z):
     """dL/dz per batch item (float64 tensor [batch]) for the RS propagation of

@@ -96,6 +96,20 @@ __device__ __forceinline__ void store_stream(cx<T>* p, cx<T> a) {
   __builtin_nontemporal_store(v, reinterpret_cast<V2*>(p));
 }
 
+// Optional fused SLM phase gradient on a pass's store: grad = Im(g conj u)
+// for the stored value g (added to grad when acc), at the output element.
+template <typename T>
+struct PhaseGrad {
+  const cx<T>* u = nullptr;
+  T* grad = nullptr;
+  int acc = 0;
+  __device__ __forceinline__ void put(int64_t o, cx<T> g) const {
+    const cx<T> v = u[o];
+    const T d = g.y * v.x - g.x * v.y;
+    grad[o] = acc ? grad[o] + d : d;
+  }
+};
+
 template <typename T> __device__ __forceinline__ cx<T> czero() { return mk<T>(T(0), T(0)); }
 
 // address of element i of line l of batch item b
@@ -182,7 +196,7 @@ struct RowCfg {
 template <typename T, int DIR, class S, int C, bool HALF>
 __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) void k_rs_rows(
     const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int64_t w_bstride, int nrows, int n_io, T scale, int tiles,
-    const cx<T>* __restrict__ tw) {
+    const cx<T>* __restrict__ tw, PhaseGrad<T> pg) {
   constexpr int LS = line_stride<S, C, true>();
   __shared__ cx<T> smem[C * LS];
   const int id = xcd_remap(blockIdx.x, gridDim.x);
@@ -212,7 +226,11 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
       return v;
     };
     auto store = [&](int i, cx<T> v) {
-      if (valid && i < n_io) out[frow + i] = cscale(v, scale);
+      if (valid && i < n_io) {
+        const cx<T> g = cscale(v, scale);
+        if (out) out[frow + i] = g;
+        if (pg.grad) pg.put(frow + i, g);
+      }
     };
     fft_line<T, 1, S, false, HALF>(lds, tw, j, load, store);
   }
@@ -220,7 +238,7 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
 
 template <typename T, int DIR, class S>
 hipError_t launch_rs_rows_s(const cx<T>* in, cx<T>* out, int64_t w_bstride, int nrows, int n_io, T scale, int batch,
-                            const cx<T>* tw, hipStream_t s) {
+                            const cx<T>* tw, hipStream_t s, PhaseGrad<T> pg) {
   using RC = RowCfg<T, S>;
   if constexpr (!RC::fits) {
     return hipErrorInvalidValue;
@@ -231,23 +249,27 @@ hipError_t launch_rs_rows_s(const cx<T>* in, cx<T>* out, int64_t w_bstride, int 
     if constexpr (can_half) {
       if (2 * n_io <= S::n) {
         hipLaunchKernelGGL((k_rs_rows<T, DIR, S, C, true>), dim3(tiles * batch), dim3(RC::threads), 0, s, in, out,
-                           w_bstride, nrows, n_io, scale, tiles, tw);
+                           w_bstride, nrows, n_io, scale, tiles, tw, pg);
         return hipGetLastError();
       }
     }
     hipLaunchKernelGGL((k_rs_rows<T, DIR, S, C, false>), dim3(tiles * batch), dim3(RC::threads), 0, s, in, out,
-                       w_bstride, nrows, n_io, scale, tiles, tw);
+                       w_bstride, nrows, n_io, scale, tiles, tw, pg);
     return hipGetLastError();
   }
 }
 
 template <typename T, int DIR>
 hipError_t launch_rs_rows(int n, const cx<T>* in, cx<T>* out, int64_t w_bstride, int nrows, int n_io, T scale,
-                          int batch, const cx<T>* tw, hipStream_t s) {
+                          int batch, const cx<T>* tw, hipStream_t s, const cx<T>* pg_u, T* pg_grad, int pg_acc) {
   if (nrows <= 0 || batch <= 0) return hipSuccess;
+  PhaseGrad<T> pg;
+  pg.u = pg_u;
+  pg.grad = pg_grad;
+  pg.acc = pg_acc;
   switch (n) {
 #define LP_CASE(N, ...) \
-  case N: return launch_rs_rows_s<T, DIR, Sched<__VA_ARGS__>>(in, out, w_bstride, nrows, n_io, scale, batch, tw, s);
+  case N: return launch_rs_rows_s<T, DIR, Sched<__VA_ARGS__>>(in, out, w_bstride, nrows, n_io, scale, batch, tw, s, pg);
     LP_LENGTHS(LP_CASE)
 #undef LP_CASE
     default:
@@ -461,7 +483,7 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, COL, 1, HALF
                                                               const cx<T>* __restrict__ pre,
                                                               const cx<T>* __restrict__ chat,
                                                               const cx<T>* __restrict__ post, int tiles,
-                                                              const cx<T>* __restrict__ tw) {
+                                                              const cx<T>* __restrict__ tw, PhaseGrad<T> pg) {
   constexpr int LS = line_stride<S, C, COL>();
   __shared__ cx<T> smem[C * LS];
   const int id = xcd_remap(blockIdx.x, gridDim.x);
@@ -478,7 +500,12 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, COL, 1, HALF
   };
   auto mult = [&](int i, cx<T> v) -> cx<T> { return cmul(v, chat[i]); };
   auto store = [&](int i, cx<T> v) {
-    if (valid && i < n_out) out[line_off<COL>(lo, b, l, i)] = cmul(v, post[i]);
+    if (valid && i < n_out) {
+      const int64_t o = line_off<COL>(lo, b, l, i);
+      const cx<T> g = cmul(v, post[i]);
+      if (out) out[o] = g;
+      if (pg.grad) pg.put(o, g);
+    }
   };
   conv_line<T, S, HALF, HALF>(lds, tw, j, load, mult, store);
 }
@@ -486,25 +513,25 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, COL, 1, HALF
 template <typename T, bool COL, class S, int C>
 hipError_t launch_bluestein_c(const cx<T>* in, cx<T>* out, Lines li, Lines lo, int nlines, int n_in, int n_out,
                               const cx<T>* pre, const cx<T>* chat, const cx<T>* post, int batch, const cx<T>* tw,
-                              hipStream_t s) {
+                              hipStream_t s, PhaseGrad<T> pg) {
   const int tiles = (nlines + C - 1) / C;
   constexpr bool can_half = S::rad[0] % 2 == 0 && S::rad[S::nst - 1] % 2 == 0;
   if constexpr (can_half) {
     if (2 * n_in <= S::n && 2 * n_out <= S::n) {
       hipLaunchKernelGGL((k_bluestein<T, COL, S, C, true>), dim3(tiles * batch), dim3(C * S::threads), 0, s, in, out,
-                         li, lo, nlines, n_in, n_out, pre, chat, post, tiles, tw);
+                         li, lo, nlines, n_in, n_out, pre, chat, post, tiles, tw, pg);
       return hipGetLastError();
     }
   }
   hipLaunchKernelGGL((k_bluestein<T, COL, S, C, false>), dim3(tiles * batch), dim3(C * S::threads), 0, s, in, out, li,
-                     lo, nlines, n_in, n_out, pre, chat, post, tiles, tw);
+                     lo, nlines, n_in, n_out, pre, chat, post, tiles, tw, pg);
   return hipGetLastError();
 }
 
 template <typename T, bool COL, class S>
 hipError_t launch_bluestein_s(const cx<T>* in, cx<T>* out, Lines li, Lines lo, int nlines, int n_in, int n_out,
                               const cx<T>* pre, const cx<T>* chat, const cx<T>* post, int batch, const cx<T>* tw,
-                              hipStream_t s, int variant) {
+                              hipStream_t s, int variant, PhaseGrad<T> pg) {
   // two transforms plus the chirp multiplies per line: 512 threads keep the
   // radix-16 stages free of register spills
   using CF = Cfg<T, S, COL, 1, 512>;
@@ -514,26 +541,33 @@ hipError_t launch_bluestein_s(const cx<T>* in, cx<T>* out, Lines li, Lines lo, i
     if constexpr (COL) {
       constexpr int C1 = variant_lines<S, CF::C>(1), C2 = variant_lines<S, CF::C>(2);
       if (variant == 1)
-        return launch_bluestein_c<T, COL, S, C1>(in, out, li, lo, nlines, n_in, n_out, pre, chat, post, batch, tw, s);
+        return launch_bluestein_c<T, COL, S, C1>(in, out, li, lo, nlines, n_in, n_out, pre, chat, post, batch, tw, s,
+                                                 pg);
       if (variant == 2)
-        return launch_bluestein_c<T, COL, S, C2>(in, out, li, lo, nlines, n_in, n_out, pre, chat, post, batch, tw, s);
+        return launch_bluestein_c<T, COL, S, C2>(in, out, li, lo, nlines, n_in, n_out, pre, chat, post, batch, tw, s,
+                                                 pg);
     }
-    return launch_bluestein_c<T, COL, S, CF::C>(in, out, li, lo, nlines, n_in, n_out, pre, chat, post, batch, tw, s);
+    return launch_bluestein_c<T, COL, S, CF::C>(in, out, li, lo, nlines, n_in, n_out, pre, chat, post, batch, tw, s,
+                                                pg);
   }
 }
 
 template <typename T>
 hipError_t launch_bluestein(int L, bool col, const cx<T>* in, cx<T>* out, Lines li, Lines lo, int nlines, int n_in,
                             int n_out, const cx<T>* pre, const cx<T>* chat, const cx<T>* post, int batch,
-                            const cx<T>* tw, hipStream_t s, int variant) {
+                            const cx<T>* tw, hipStream_t s, int variant, const cx<T>* pg_u, T* pg_grad, int pg_acc) {
   if (nlines <= 0 || batch <= 0) return hipSuccess;
+  PhaseGrad<T> pg;
+  pg.u = pg_u;
+  pg.grad = pg_grad;
+  pg.acc = pg_acc;
   switch (L) {
 #define LP_CASE(N, ...)                                                                                             \
   case N:                                                                                                           \
     return col ? launch_bluestein_s<T, true, Sched<__VA_ARGS__>>(in, out, li, lo, nlines, n_in, n_out, pre, chat,   \
-                                                                 post, batch, tw, s, variant)                       \
+                                                                 post, batch, tw, s, variant, pg)                   \
                : launch_bluestein_s<T, false, Sched<__VA_ARGS__>>(in, out, li, lo, nlines, n_in, n_out, pre, chat, \
-                                                                  post, batch, tw, s, 0);
+                                                                  post, batch, tw, s, 0, pg);
     LP_LENGTHS(LP_CASE)
 #undef LP_CASE
     default:

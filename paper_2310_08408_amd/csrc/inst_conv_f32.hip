@@ -10,6 +10,6 @@ template hipError_t launch_mix2_cols<float>(int, const cx<float>*, const cx<floa
                                          const cx<float>*, hipStream_t, int);
 template hipError_t launch_bluestein<float>(int, bool, const cx<float>*, cx<float>*, Lines, Lines, int, int, int,
                                          const cx<float>*, const cx<float>*, const cx<float>*, int, const cx<float>*,
-                                         hipStream_t, int);
+                                         hipStream_t, int, const cx<float>*, float*, int);
 template int col_pass_lines<float>(int, int, int);
 }  // namespace lp

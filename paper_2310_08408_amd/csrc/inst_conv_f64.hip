@@ -10,6 +10,6 @@ template hipError_t launch_mix2_cols<double>(int, const cx<double>*, const cx<do
                                          const cx<double>*, hipStream_t, int);
 template hipError_t launch_bluestein<double>(int, bool, const cx<double>*, cx<double>*, Lines, Lines, int, int, int,
                                          const cx<double>*, const cx<double>*, const cx<double>*, int, const cx<double>*,
-                                         hipStream_t, int);
+                                         hipStream_t, int, const cx<double>*, double*, int);
 template int col_pass_lines<double>(int, int, int);
 }  // namespace lp

@@ -37,9 +37,13 @@ inline int64_t rs_plane_elems(int ny, int Mx) { return (int64_t)((Mx + kTile - 1
 // transform of length n of each zero-padded input row into the workspace;
 // DIR = +1: inverse transform of each workspace row, first n_io outputs
 // kept and scaled.
+// With pg_grad non-NULL the inverse pass also writes the SLM phase gradient
+// pg_grad = Im(out conj pg_u) (added when pg_acc) of its output; out may
+// then be NULL.
 template <typename T, int DIR>
 hipError_t launch_rs_rows(int n, const cx<T>* in, cx<T>* out, int64_t w_bstride, int nrows, int n_io, T scale,
-                          int batch, const cx<T>* tw, hipStream_t s);
+                          int batch, const cx<T>* tw, hipStream_t s, const cx<T>* pg_u = nullptr,
+                          T* pg_grad = nullptr, int pg_acc = 0);
 
 // RS middle pass, in place on columns kx < ncols of the tiled workspace
 // (bstride elements per batch item, n_valid rows): transform of length My
@@ -64,7 +68,8 @@ hipError_t launch_mix2_cols(int My, const cx<T>* a, const cx<T>* b, cx<T>* out, 
 template <typename T>
 hipError_t launch_bluestein(int L, bool col, const cx<T>* in, cx<T>* out, Lines li, Lines lo, int nlines, int n_in,
                             int n_out, const cx<T>* pre, const cx<T>* chat, const cx<T>* post, int batch,
-                            const cx<T>* tw, hipStream_t s, int variant = 0);
+                            const cx<T>* tw, hipStream_t s, int variant = 0, const cx<T>* pg_u = nullptr,
+                            T* pg_grad = nullptr, int pg_acc = 0);
 
 constexpr int kColVariants = 3;
 // Column-pass launch variants (the `variant` argument above): lines per

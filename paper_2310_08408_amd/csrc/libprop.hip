@@ -441,7 +441,8 @@ static size_t rs_work_bytes(prop_dtype t, const prop_grid* g, int batch) {
 
 template <typename T>
 static int rs_run(const void* in, void* out, const prop_grid* g, double wl, double z, int batch, hipStream_t s,
-                  bool adjoint, void* work, int spec_kind = 0) {
+                  bool adjoint, void* work, int spec_kind = 0, const cx<T>* pg_u = nullptr, T* pg_grad = nullptr,
+                  int pg_acc = 0) {
   int dev;
   LP_RET(cur_device(&dev));
   const cx<T>* q[4];
@@ -471,8 +472,13 @@ static int rs_run(const void* in, void* out, const prop_grid* g, double wl, doub
   LP_TRACE("rs_cols", es * (2.0 * batch * ny * Mx + qel), s,
            launch_rs_cols<T>(My, W, plane, Mx, ny, q[0], Mx, adjoint, batch, twy, s, v));
   // P3: inverse row transforms, crop to nx, scale dx dy / (Mx My)
-  LP_TRACE("rs_rows_inv", es * batch * ny * (double)(nx + Mx), s,
-           (launch_rs_rows<T, 1>(Mx, W, (cx<T>*)out, plane, ny, nx, scale, batch, twx, s)));
+  // inverse pass: reads the workspace rows, writes the field (and with the
+  // fused phase gradient reads u, writes (and reads when accumulating) grad)
+  const double inv_bytes =
+      (double)batch * ny *
+      (es * Mx + (out ? es * nx : 0.0) + (pg_grad ? (es + sizeof(T) * (pg_acc ? 2.0 : 1.0)) * nx : 0.0));
+  LP_TRACE("rs_rows_inv", inv_bytes, s,
+           (launch_rs_rows<T, 1>(Mx, W, (cx<T>*)out, plane, ny, nx, scale, batch, twx, s, pg_u, pg_grad, pg_acc)));
   return PROP_OK;
 }
 
@@ -588,7 +594,8 @@ static double first_y(const prop_grid* g) { return g->cy - (double)(g->ny / 2) *
 // (input grid gi -> output grid go).  zx / zy describe the 1-D transforms.
 template <typename T>
 static int zoom2d_run(int dev, const cx<T>* in, cx<T>* out, int nxi, int nyi, int nxo, int nyo, const ZoomSpec& zx,
-                      const ZoomSpec& zy, int batch, cx<T>* tmp, hipStream_t s, bool cols_first) {
+                      const ZoomSpec& zy, int batch, cx<T>* tmp, hipStream_t s, bool cols_first,
+                      const cx<T>* pg_u = nullptr, T* pg_grad = nullptr, int pg_acc = 0) {
   const cx<T> *prex, *postx, *chatx, *prey, *posty, *chaty;
   LP_RET(get_zoom<T>(dev, zx, s, &prex, &postx, &chatx));
   LP_RET(get_zoom<T>(dev, zy, s, &prey, &posty, &chaty));
@@ -610,8 +617,12 @@ static int zoom2d_run(int dev, const cx<T>* in, cx<T>* out, int nxi, int nyi, in
                                                        batch, twy, s, var);
                           },
                           &v));
-    LP_TRACE("czt_cols", es * batch * nxo * (double)(nyi + nyo), s,
-             launch_bluestein<T>(zy.L, true, tmp, out, li, lo, nxo, nyi, nyo, prey, chaty, posty, batch, twy, s, v));
+    const double last_bytes =
+        (double)batch * nxo *
+        (es * nyi + (out ? es * nyo : 0.0) + (pg_grad ? (es + sizeof(T) * (pg_acc ? 2.0 : 1.0)) * nyo : 0.0));
+    LP_TRACE("czt_cols", last_bytes, s,
+             launch_bluestein<T>(zy.L, true, tmp, out, li, lo, nxo, nyi, nyo, prey, chaty, posty, batch, twy, s, v,
+                                 pg_u, pg_grad, pg_acc));
   } else {
     // cols: [nyi][nxi] -> tmp [nyo][nxi]; rows: tmp -> out [nyo][nxo]
     int v = 0;
@@ -625,9 +636,12 @@ static int zoom2d_run(int dev, const cx<T>* in, cx<T>* out, int nxi, int nyi, in
                           &v));
     LP_TRACE("czt_cols", es * batch * nxi * (double)(nyi + nyo), s,
              launch_bluestein<T>(zy.L, true, in, tmp, li, lo, nxi, nyi, nyo, prey, chaty, posty, batch, twy, s, v));
-    LP_TRACE("czt_rows", es * batch * nyo * (double)(nxi + nxo), s,
+    const double last_bytes =
+        (double)batch * nyo *
+        (es * nxi + (out ? es * nxo : 0.0) + (pg_grad ? (es + sizeof(T) * (pg_acc ? 2.0 : 1.0)) * nxo : 0.0));
+    LP_TRACE("czt_rows", last_bytes, s,
              launch_bluestein<T>(zx.L, false, tmp, out, Lines{(int64_t)nyo * nxi, nxi}, Lines{(int64_t)nyo * nxo, nxo},
-                                 nyo, nxi, nxo, prex, chatx, postx, batch, twx, s));
+                                 nyo, nxi, nxo, prex, chatx, postx, batch, twx, s, 0, pg_u, pg_grad, pg_acc));
   }
   return PROP_OK;
 }
@@ -673,15 +687,19 @@ static int check_czt_shapes(const prop_grid* gi, const prop_grid* go) {
 // batch * max(nyi*nxo, nyo*nxi) elements
 template <typename T>
 static int czt_core(int dev, const cx<T>* in, cx<T>* out, const prop_grid* gi, const prop_grid* go, double wl,
-                    double z, int batch, cx<T>* tmp, hipStream_t s, bool adjoint) {
+                    double z, int batch, cx<T>* tmp, hipStream_t s, bool adjoint, const cx<T>* pg_u = nullptr,
+                    T* pg_grad = nullptr, int pg_acc = 0) {
   ZoomSpec zx, zy;
   czt_specs(gi, go, wl, z, adjoint, &zx, &zy);
   if (!adjoint) {
     const bool cols_first = (int64_t)go->ny * gi->nx < (int64_t)gi->ny * go->nx;
     return zoom2d_run<T>(dev, in, out, gi->nx, gi->ny, go->nx, go->ny, zx, zy, batch, tmp, s, cols_first);
   }
-  const bool cols_first = (int64_t)gi->ny * go->nx < (int64_t)go->ny * gi->nx;
-  return zoom2d_run<T>(dev, in, out, go->nx, go->ny, gi->nx, gi->ny, zx, zy, batch, tmp, s, cols_first);
+  // with a fused phase gradient the row pass goes last, so that the field
+  // and the gradient are read and written along contiguous rows
+  const bool cols_first = pg_grad ? true : (int64_t)gi->ny * go->nx < (int64_t)go->ny * gi->nx;
+  return zoom2d_run<T>(dev, in, out, go->nx, go->ny, gi->nx, gi->ny, zx, zy, batch, tmp, s, cols_first, pg_u,
+                       pg_grad, pg_acc);
 }
 
 static size_t czt_tmp_elems(const prop_grid* gi, const prop_grid* go) {
@@ -1180,6 +1198,56 @@ int rs_propagate(prop_dtype t, const void* u_in, void* u_out, const prop_grid* g
 int rs_adjoint(prop_dtype t, const void* g_out, void* g_in, const prop_grid* g, double wavelength, double z,
                int32_t batch, void* stream) {
   return rs_entry(t, g_out, g_in, g, wavelength, z, batch, stream, true);
+}
+
+int rs_adjoint_phase_grad(prop_dtype t, const void* g_out, const void* u, void* g_u, void* grad, int32_t accumulate,
+                          const prop_grid* g, double wavelength, double z, int32_t batch, void* stream) {
+  LP_RET(check_common(t, batch, wavelength));
+  LP_RET(check_grid(g));
+  if (!(z > 0) || !is_finite(z)) return PROP_EPARAM;
+  if (fft_len(2 * g->nx - 1) < 0 || fft_len(2 * g->ny - 1) < 0) return PROP_ESHAPE;
+  const int warn = sampling(g, wavelength, z);
+  if (batch == 0) return warn;
+  if (!g_out || !u || !grad) return PROP_ENULL;
+  const size_t bytes = (size_t)g->nx * g->ny * batch * esize(t);
+  LP_RET(check_alias({{g_out, bytes}, {u, bytes}}, {{g_u, g_u ? bytes : 0}, {grad, bytes / 2}}));
+  std::lock_guard<std::mutex> lk(ctx().mu);
+  const hipStream_t s = (hipStream_t)stream;
+  int dev;
+  LP_RET(cur_device(&dev));
+  Buf& wb = ctx().work[{dev, s}];
+  LP_RET(ensure_buf(wb, rs_work_bytes(t, g, batch), s));
+  const int r = t == PROP_C64 ? rs_run<float>(g_out, g_u, g, wavelength, z, batch, s, true, wb.p, 0,
+                                              (const cx<float>*)u, (float*)grad, accumulate ? 1 : 0)
+                              : rs_run<double>(g_out, g_u, g, wavelength, z, batch, s, true, wb.p, 0,
+                                               (const cx<double>*)u, (double*)grad, accumulate ? 1 : 0);
+  return r < 0 ? r : warn;
+}
+
+int czt_adjoint_phase_grad(prop_dtype t, const void* g_out, const void* u, void* g_u, void* grad, int32_t accumulate,
+                           const prop_grid* g_in, const prop_grid* win, double wavelength, double z, int32_t batch,
+                           void* stream) {
+  LP_RET(check_common(t, batch, wavelength));
+  LP_RET(check_grid(g_in));
+  LP_RET(check_grid(win));
+  if (!(z > 0) || !is_finite(z)) return PROP_EPARAM;
+  LP_RET(check_czt_shapes(g_in, win));
+  if (batch == 0) return PROP_OK;
+  if (!g_out || !u || !grad) return PROP_ENULL;
+  const size_t bi = (size_t)g_in->nx * g_in->ny * batch * esize(t), bo = (size_t)win->nx * win->ny * batch * esize(t);
+  LP_RET(check_alias({{g_out, bo}, {u, bi}}, {{g_u, g_u ? bi : 0}, {grad, bi / 2}}));
+  std::lock_guard<std::mutex> lk(ctx().mu);
+  const hipStream_t s = (hipStream_t)stream;
+  int dev;
+  LP_RET(cur_device(&dev));
+  Buf& wb = ctx().work[{dev, s}];
+  LP_RET(ensure_buf(wb, czt_work_bytes(t, g_in, win, batch), s));
+  return t == PROP_C64 ? czt_core<float>(dev, (const cx<float>*)g_out, (cx<float>*)g_u, g_in, win, wavelength, z, batch,
+                                         (cx<float>*)wb.p, s, true, (const cx<float>*)u, (float*)grad,
+                                         accumulate ? 1 : 0)
+                       : czt_core<double>(dev, (const cx<double>*)g_out, (cx<double>*)g_u, g_in, win, wavelength, z,
+                                          batch, (cx<double>*)wb.p, s, true, (const cx<double>*)u, (double*)grad,
+                                          accumulate ? 1 : 0);
 }
 
 int rs_grad_z(prop_dtype t, const void* u_in, const void* g_out, double* dz, const prop_grid* g, double wavelength,
