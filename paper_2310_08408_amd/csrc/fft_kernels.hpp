@@ -532,9 +532,9 @@ template <typename T, bool COL, class S>
 hipError_t launch_bluestein_s(const cx<T>* in, cx<T>* out, Lines li, Lines lo, int nlines, int n_in, int n_out,
                               const cx<T>* pre, const cx<T>* chat, const cx<T>* post, int batch, const cx<T>* tw,
                               hipStream_t s, int variant, PhaseGrad<T> pg) {
-  // two transforms plus the chirp multiplies per line: 512 threads keep the
-  // radix-16 stages free of register spills
-  using CF = Cfg<T, S, COL, 1, 512>;
+  // row passes: 512 threads per workgroup; column passes up to 1024 (more
+  // adjacent columns per row segment)
+  using CF = Cfg<T, S, COL, 1, (COL ? 1024 : 512)>;
   if constexpr (!CF::fits) {
     return hipErrorInvalidValue;
   } else {
@@ -585,7 +585,7 @@ int col_pass_lines(int kind, int n, int variant) {
   case N: {                                                                                         \
     using S = Sched<__VA_ARGS__>;                                                                   \
     constexpr int c0 = Cfg<T, S, true>::C, c1 = Cfg<T, S, true, 2, 512>::C,                         \
-                  c2 = Cfg<T, S, true, 1, 512>::C;                                                  \
+                  c2 = Cfg<T, S, true, 1, 1024>::C;                                                 \
     const int c = kind == 0 ? c0 : (kind == 1 ? c1 : c2);                                           \
     return S::n >= kTuneMinLength ? cmax(1, c >> variant) : c;                                      \
   }
