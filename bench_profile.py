@@ -28,9 +28,9 @@ COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 # bench.py pass name -> kernel-name prefix of the FP32 launch it times
 PASS_KERNELS = {
-    "rs_rows_fwd": "void lp::k_fft_lines<float, -1, false,",
+    "rs_rows_fwd": "void lp::k_rs_rows<float, -1,",
     "rs_cols": "void lp::k_rs_cols<float,",
-    "rs_rows_inv": "void lp::k_fft_lines<float, 1, false,",
+    "rs_rows_inv": "void lp::k_rs_rows<float, 1,",
     "czt_rows": "void lp::k_bluestein<float, false,",
     "czt_cols": "void lp::k_bluestein<float, true,",
     "modulate": "void lp::k_modulate<float",
