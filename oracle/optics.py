@@ -734,3 +734,21 @@ def softmin(losses, beta: float):
     w = np.exp(-beta * (l - m))
     s = w.sum()
     return float(m - np.log(s) / beta), w / s
+
+
+# --------------------------------------------------------------------------
+# Optimiser step (the paper optimises with Adam; AdamW in its comparisons)
+# --------------------------------------------------------------------------
+
+def adam_step(p, g, m, v, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
+              weight_decay: float = 0.0):
+    """One Adam step (Kingma & Ba) with bias correction; weight_decay > 0
+    adds the decoupled (AdamW) decay lr * weight_decay * p.  Returns new
+    (p, m, v); step counts from 1."""
+    p, g, m, v = (np.asarray(a, dtype=np.float64) for a in (p, g, m, v))
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** step)
+    vhat = v / (1.0 - beta2 ** step)
+    p = p - lr * weight_decay * p - lr * mhat / (np.sqrt(vhat) + eps)
+    return p, m, v

@@ -161,3 +161,20 @@ def test_table_chain_gradients_match_finite_differences():
             wpp[plate][k] += h; wpm[plate][k] -= h
             fd = (L(p1, p2, *wpp) - L(p1, p2, *wpm)) / (2 * h)
             assert abs(fd - d[k]) <= 1e-6 * max(1.0, abs(d[k]))
+
+
+@pytest.mark.parametrize("wd", [0.0, 0.05])
+def test_adam_step_matches_torch_optim(wd):
+    # the library routines (torch.optim.Adam / AdamW on the CPU) as the pin
+    import torch
+    rng = np.random.default_rng(8)
+    p0 = rng.standard_normal(50)
+    grads = [rng.standard_normal(50) for _ in range(6)]
+    t = torch.tensor(p0, dtype=torch.float64, requires_grad=True)
+    opt = (torch.optim.AdamW([t], lr=0.03, weight_decay=wd) if wd else torch.optim.Adam([t], lr=0.03))
+    p, m, v = p0.copy(), np.zeros(50), np.zeros(50)
+    for k, gk in enumerate(grads, start=1):
+        t.grad = torch.tensor(gk, dtype=torch.float64)
+        opt.step()
+        p, m, v = oracle.adam_step(p, gk, m, v, k, 0.03, weight_decay=wd)
+    assert np.abs(p - t.detach().numpy()).max() < 1e-13
