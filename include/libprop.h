@@ -256,7 +256,18 @@ int prop_density_loss(prop_dtype t, const void* const* comps, int32_t ncomp, con
 int prop_softmin(const double* losses, int32_t ndet, double beta, double* value, double* weights,
                  int32_t batch, void* stream);
 
-/* ------------------------------------------------------------- utility -- *//* ------------------------------------------------------------- utility -- */
+/* Optimiser step on the device (the paper optimises with Adam, comparing
+ * AdamW among others; Methods).  One Adam step with bias correction over n
+ * real parameters: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr wd p + lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps);
+ * weight_decay (wd) > 0 is the decoupled AdamW decay.  t selects the
+ * precision of param, grad, m, v: PROP_C64 -> float, PROP_C128 -> double
+ * (device arrays of n; m and v start at zero, step counts from 1).
+ */
+int prop_adam_step(prop_dtype t, void* param, const void* grad, void* m, void* v, int64_t n, double lr,
+                   double beta1, double beta2, double eps, double weight_decay, int32_t step, void* stream);
+
+/* ------------------------------------------------------------- utility -- */
 /* Host-only sampling check of RS/VRS: PROP_OK or PROP_WUNDERSAMPLED. */
 int prop_sampling_check(const prop_grid* g, double wavelength, double z);
 /* Smallest supported transform length >= n, or -1 above 8192.  Supported

@@ -22,7 +22,7 @@ __all__ = [
     "vczt_propagate", "vczt_adjoint", "rs_grad_z", "czt_grad_z", "rs_adjoint_phase_grad", "czt_adjoint_phase_grad",
     "prop_source_gaussian", "prop_source_radial", "prop_modulate",
     "prop_phase_grad", "prop_waveplate", "prop_waveplate_adjoint", "prop_spot_loss", "prop_density_loss",
-    "prop_softmin", "prop_sampling_check",
+    "prop_softmin", "prop_adam_step", "Adam", "prop_sampling_check",
     "prop_fft_length", "prop_cache_clear", "prop_trace_enable", "prop_trace_read", "prop_autotune_report",
     "PropError", "PropWarning", "library", "Plan", "Setup", "PROP_OP_RS", "PROP_OP_CZT", "PROP_OP_VRS",
     "PROP_OP_VCZT", "PROP_PLAN_GRAPH", "PROP_PLAN_AUTOTUNE",
@@ -409,6 +409,46 @@ def prop_softmin(losses, beta):
         st = lib.prop_softmin(_ptr(losses), ndet, float(beta), _ptr(val), _ptr(w), batch, _stream(losses))
     _lib.check("prop_softmin", st)
     return val, w
+
+
+def prop_adam_step(param, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
+    """In-place Adam (AdamW if weight_decay > 0) step on a real float32 or
+    float64 device tensor with its gradient and moment buffers."""
+    lib = library()
+    for t in (param, grad, m, v):
+        _dev(t)
+        if not t.is_contiguous() or t.dtype != param.dtype or t.numel() != param.numel():
+            raise ValueError("param, grad, m, v: contiguous, same dtype and size")
+    code = _lib.PROP_C64 if param.dtype == torch.float32 else _lib.PROP_C128
+    with torch.cuda.device(param.device):
+        st = lib.prop_adam_step(code, _ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.numel(), float(lr),
+                                float(beta1), float(beta2), float(eps), float(weight_decay), int(step),
+                                _stream(param))
+    _lib.check("prop_adam_step", st)
+
+
+class Adam:
+    """Minimal device optimiser over a list of real tensors (phases, retarder
+    parameters, distances), stepping with prop_adam_step."""
+
+    def __init__(self, params, lr, betas=(0.9, 0.999), eps=1e-8, weight_decay=0.0):
+        self.params = list(params)
+        self.lr, self.betas, self.eps, self.wd = lr, betas, eps, weight_decay
+        self.m = [torch.zeros_like(p) for p in self.params]
+        self.v = [torch.zeros_like(p) for p in self.params]
+        self.t = 0
+
+    def step(self):
+        self.t += 1
+        for p, m, v in zip(self.params, self.m, self.v):
+            if p.grad is None:
+                continue
+            prop_adam_step(p.data, p.grad.contiguous(), m, v, self.t, self.lr, self.betas[0], self.betas[1], self.eps,
+                           self.wd)
+
+    def zero_grad(self):
+        for p in self.params:
+            p.grad = None
 
 
 def prop_sampling_check(grid, wavelength, z) -> int:

@@ -626,6 +626,32 @@ hipError_t launch_softmin(const double* l, int ndet, double beta, double* val, d
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------ optimiser --
+// Adam step with bias correction, in the parameters' precision for the
+// moments and FP64 for the scalar factors; weight_decay > 0 adds the
+// decoupled (AdamW) decay.  One pass: reads p, g, m, v, writes p, m, v.
+template <typename T>
+__global__ void k_adam(T* p, const T* g, T* m, T* v, int64_t n, T lr, T b1, T b2, T c1, T c2, T eps, T lrwd) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const T gi = g[i];
+    const T mi = b1 * m[i] + (T(1) - b1) * gi;
+    const T vi = b2 * v[i] + (T(1) - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const T pi = p[i];
+    p[i] = pi - lrwd * pi - lr * (mi * c1) / (sqrt(vi * c2) + eps);
+  }
+}
+
+template <typename T>
+hipError_t launch_adam(T* p, const T* g, T* m, T* v, int64_t n, double lr, double b1, double b2, double eps,
+                       double wd, int step, hipStream_t s) {
+  const double c1 = 1.0 / (1.0 - std::pow(b1, step)), c2 = 1.0 / (1.0 - std::pow(b2, step));
+  hipLaunchKernelGGL((k_adam<T>), dim3(ew_blocks(n)), dim3(256), 0, s, p, g, m, v, n, (T)lr, (T)b1, (T)b2, (T)c1,
+                     (T)c2, (T)eps, (T)(lr * wd));
+  return hipGetLastError();
+}
+
 // focusing pupil map
 __device__ __forceinline__ bool pupil_coeffs(double x, double y, double f, double na, double m[6]) {
   const double X2 = x * x + y * y;
@@ -958,6 +984,8 @@ hipError_t launch_spot_loss(const cx<T>* ex, const cx<T>* ey, const cx<T>* ez, i
 #define LP_INST(T)                                                                                                  \
   template hipError_t launch_extract_half<T>(const cx<double>*, cx<T>*, int, int, hipStream_t);                  \
   template hipError_t launch_redot<T>(const cx<T>*, const cx<T>*, double*, double*, int, int64_t, int, hipStream_t); \
+  template hipError_t launch_adam<T>(T*, const T*, T*, T*, int64_t, double, double, double, double, double, int,   \
+                                     hipStream_t);                                                                  \
   template hipError_t launch_density_loss<T>(const void* const*, int, const void* const*, int, double, int64_t,     \
                                              double, double*, double*, int, void* const*, void* const*, int,       \
                                              hipStream_t);                                                          \

@@ -103,6 +103,10 @@ template <typename T>
 hipError_t launch_density_loss(const void* const* comps, int ncomp, const void* const* dep, int ndep, double beta,
                                int64_t npix, double eps, double* res, double* scratch, int nblk, void* const* seeds,
                                void* const* dep_seeds, int batch, hipStream_t s);
+// One Adam (AdamW when wd > 0) step over n real parameters, step >= 1.
+template <typename T>
+hipError_t launch_adam(T* p, const T* g, T* m, T* v, int64_t n, double lr, double b1, double b2, double eps,
+                       double wd, int step, hipStream_t s);
 // Soft minimum of ndet losses per batch item and its weights (d value / d l).
 hipError_t launch_softmin(const double* l, int ndet, double beta, double* val, double* w, int batch, hipStream_t s);
 // o = [(x^2+y^2) u | x u | y u] on the input grid (three [batch][ny][nx] planes).

@@ -1602,6 +1602,25 @@ int prop_density_loss(prop_dtype t, const void* const* comps, int32_t ncomp, con
   return PROP_OK;
 }
 
+int prop_adam_step(prop_dtype t, void* param, const void* grad, void* m, void* v, int64_t n, double lr, double beta1,
+                   double beta2, double eps, double weight_decay, int32_t step, void* stream) {
+  if (t != PROP_C64 && t != PROP_C128) return PROP_EPARAM;
+  if (n < 0 || step < 1) return PROP_ESHAPE;
+  if (!(lr >= 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0) ||
+      !(weight_decay >= 0) || !is_finite(lr) || !is_finite(weight_decay))
+    return PROP_EPARAM;
+  if (n == 0) return PROP_OK;
+  if (!param || !grad || !m || !v) return PROP_ENULL;
+  const size_t b = (size_t)n * (t == PROP_C64 ? 4 : 8);
+  LP_RET(check_alias({{grad, b}}, {{param, b}, {m, b}, {v, b}}));
+  const hipStream_t s = (hipStream_t)stream;
+  LP_TRY(t == PROP_C64 ? launch_adam<float>((float*)param, (const float*)grad, (float*)m, (float*)v, n, lr, beta1,
+                                            beta2, eps, weight_decay, step, s)
+                       : launch_adam<double>((double*)param, (const double*)grad, (double*)m, (double*)v, n, lr,
+                                             beta1, beta2, eps, weight_decay, step, s));
+  return PROP_OK;
+}
+
 int prop_softmin(const double* losses, int32_t ndet, double beta, double* value, double* weights, int32_t batch,
                  void* stream) {
   if (ndet < 1 || batch < 0) return PROP_ESHAPE;
