@@ -214,6 +214,41 @@ int prop_waveplate(prop_dtype t, const void* ex, const void* ey, void* ox, void*
 int prop_waveplate_adjoint(prop_dtype t, const void* gx, const void* gy, const void* ex,
                            const void* ey, void* gex, void* gey, double eta, double theta,
                            double* dparams, int64_t npix, int32_t batch, void* stream);
+/* Wave plates with one parameter pair per batch item, read from device
+ * memory: params = device double [batch][2] = (eta, theta), so that
+ * optimised parameters stay on the GPU.  Same matrix as prop_waveplate. */
+int prop_waveplate_batched(prop_dtype t, const void* ex, const void* ey, void* ox, void* oy,
+                           const double* params, int64_t npix, int32_t batch, void* stream);
+/* Adjoint: (g_ex, g_ey) = J_b^H (g_x, g_y) per item; if dparams (device
+ * double [batch][2]) is non-NULL it receives (dL/deta, dL/dtheta) per item
+ * (fixed-order FP64 reduction) and ex, ey (the forward inputs) are
+ * required; otherwise they may be NULL. */
+int prop_waveplate_batched_adjoint(prop_dtype t, const void* gx, const void* gy, const void* ex,
+                                   const void* ey, void* gex, void* gey, const double* params,
+                                   double* dparams, int64_t npix, int32_t batch, void* stream);
+
+/* Beam splitter (paper: Methods, large-scale search space; Results,
+ * large-scale ansatz with beam-splitter ratios [T, R]).  Lossless,
+ * symmetric and polarisation independent, with mixing angle alpha per batch
+ * item (T = cos^2 alpha, R = sin^2 alpha), on each of ncomp (1..3)
+ * components k:
+ *   c_k = cos(alpha) a_k + i sin(alpha) b_k,  d_k = i sin(alpha) a_k + cos(alpha) b_k.
+ * a, b, c, d: host arrays of ncomp device pointers, each a [batch][npix]
+ * plane.  a or b may be NULL: a dark input port (zero field).  alpha:
+ * device double [batch].  Outputs may not overlap inputs or each other
+ * (PROP_EALIAS). */
+int prop_beam_splitter(prop_dtype t, const void* const* a, const void* const* b, void* const* c,
+                       void* const* d, int32_t ncomp, const double* alpha, int64_t npix,
+                       int32_t batch, void* stream);
+/* Adjoint: g_a = cos g_c - i sin g_d, g_b = -i sin g_c + cos g_d (ga or gb
+ * NULL: not wanted).  If dalpha (device double [batch]) is non-NULL it
+ * receives dL/dalpha = Re sum conj(g_c) dc/dalpha + conj(g_d) dd/dalpha per
+ * item (fixed-order FP64 reduction) from the forward inputs a, b (NULL =
+ * dark port). */
+int prop_beam_splitter_adjoint(prop_dtype t, const void* const* gc, const void* const* gd,
+                               const void* const* a, const void* const* b, void* const* ga,
+                               void* const* gb, int32_t ncomp, const double* alpha, double* dalpha,
+                               int64_t npix, int32_t batch, void* stream);
 
 /* -------------------------------------------------------------- losses --
  * Detector loss on window `win`: I = |E_x|^2 + |E_y|^2 + |E_z|^2,

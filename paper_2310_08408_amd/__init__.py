@@ -342,6 +342,102 @@ def prop_waveplate_adjoint(gx, gy, ex, ey, eta, theta):
     return gex, gey, dp
 
 
+def _items(t, npix):
+    return t.numel() // npix
+
+
+def prop_waveplate_batched(ex, ey, params):
+    """Wave plates with one (eta, theta) per batch item: params float64
+    [batch, 2] on the fields' device.  Returns (ox, oy)."""
+    lib = library()
+    ex, ey, params = ex.contiguous(), ey.contiguous(), params.contiguous()
+    for t in (ex, ey, params):
+        _dev(t)
+    npix = ex.shape[-1] * ex.shape[-2]
+    batch = _items(ex, npix)
+    if params.dtype != torch.float64 or params.numel() != 2 * batch:
+        raise ValueError("params must be float64 [batch, 2]")
+    ox, oy = torch.empty_like(ex), torch.empty_like(ey)
+    with torch.cuda.device(ex.device):
+        st = lib.prop_waveplate_batched(_dtype_code(ex), _ptr(ex), _ptr(ey), _ptr(ox), _ptr(oy), _ptr(params), npix,
+                                        batch, _stream(ex))
+    _lib.check("prop_waveplate_batched", st)
+    return ox, oy
+
+
+def prop_waveplate_batched_adjoint(gx, gy, ex, ey, params, grad=True):
+    """Returns (g_ex, g_ey, dparams[batch, 2] float64 or None)."""
+    lib = library()
+    gx, gy, params = gx.contiguous(), gy.contiguous(), params.contiguous()
+    npix = gx.shape[-1] * gx.shape[-2]
+    batch = _items(gx, npix)
+    if params.dtype != torch.float64 or params.numel() != 2 * batch:
+        raise ValueError("params must be float64 [batch, 2]")
+    gex, gey = torch.empty_like(gx), torch.empty_like(gy)
+    dp = torch.empty((batch, 2), dtype=torch.float64, device=gx.device) if grad else None
+    if grad:
+        ex, ey = ex.contiguous(), ey.contiguous()
+    with torch.cuda.device(gx.device):
+        st = lib.prop_waveplate_batched_adjoint(_dtype_code(gx), _ptr(gx), _ptr(gy), _ptr(ex) if grad else None,
+                                                _ptr(ey) if grad else None, _ptr(gex), _ptr(gey), _ptr(params),
+                                                _ptr(dp) if grad else None, npix, batch, _stream(gx))
+    _lib.check("prop_waveplate_batched_adjoint", st)
+    return gex, gey, dp
+
+
+def _port(planes):
+    return None if planes is None else [t.contiguous() for t in planes]
+
+
+def prop_beam_splitter(a, b, alpha):
+    """Beam splitter with one mixing angle per batch item (alpha float64
+    [batch]): a, b are lists of component planes [batch, ny, nx] (or None:
+    dark port).  Returns (c, d) as lists of planes."""
+    lib = library()
+    a, b = _port(a), _port(b)
+    ref = (a or b)[0]
+    ncomp = len(a or b)
+    for t in (a or []) + (b or []):
+        _dev(t)
+    alpha = alpha.contiguous()
+    _dev(alpha)
+    npix = ref.shape[-1] * ref.shape[-2]
+    batch = _items(ref, npix)
+    if alpha.dtype != torch.float64 or alpha.numel() != batch:
+        raise ValueError("alpha must be float64 [batch]")
+    c = [torch.empty_like(ref) for _ in range(ncomp)]
+    d = [torch.empty_like(ref) for _ in range(ncomp)]
+    with torch.cuda.device(ref.device):
+        st = lib.prop_beam_splitter(_dtype_code(ref), _ptr_array(a) if a else None, _ptr_array(b) if b else None,
+                                    _ptr_array(c), _ptr_array(d), ncomp, _ptr(alpha), npix, batch, _stream(ref))
+    _lib.check("prop_beam_splitter", st)
+    return c, d
+
+
+def prop_beam_splitter_adjoint(gc, gd, a, b, alpha, want=(True, True), grad=True):
+    """Returns (g_a or None, g_b or None, dalpha[batch] float64 or None);
+    a, b are the forward inputs (None: dark), needed only for dalpha."""
+    lib = library()
+    gc, gd = _port(gc), _port(gd)
+    a, b = _port(a), _port(b)
+    ref, ncomp = gc[0], len(gc)
+    alpha = alpha.contiguous()
+    npix = ref.shape[-1] * ref.shape[-2]
+    batch = _items(ref, npix)
+    if alpha.dtype != torch.float64 or alpha.numel() != batch:
+        raise ValueError("alpha must be float64 [batch]")
+    ga = [torch.empty_like(ref) for _ in range(ncomp)] if want[0] else None
+    gb = [torch.empty_like(ref) for _ in range(ncomp)] if want[1] else None
+    da = torch.empty((batch,), dtype=torch.float64, device=ref.device) if grad else None
+    with torch.cuda.device(ref.device):
+        st = lib.prop_beam_splitter_adjoint(_dtype_code(ref), _ptr_array(gc), _ptr_array(gd),
+                                            _ptr_array(a) if a else None, _ptr_array(b) if b else None,
+                                            _ptr_array(ga) if ga else None, _ptr_array(gb) if gb else None, ncomp,
+                                            _ptr(alpha), _ptr(da) if grad else None, npix, batch, _stream(ref))
+    _lib.check("prop_beam_splitter_adjoint", st)
+    return ga, gb, da
+
+
 def prop_spot_loss(ex, ey, ez, window, wavelength, w_fz=0.0, seeds=True):
     """Returns (result[batch, 8] float64, (g_x, g_y, g_z) or None).
 

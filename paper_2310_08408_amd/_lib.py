@@ -63,6 +63,10 @@ SIGNATURES = {
     "prop_phase_grad": (c_int32, [c_int32, P, P, P, c_int64, c_int32, c_int32, P]),
     "prop_waveplate": (c_int32, [c_int32, P, P, P, P, c_double, c_double, c_int64, c_int32, P]),
     "prop_waveplate_adjoint": (c_int32, [c_int32, P, P, P, P, P, P, c_double, c_double, P, c_int64, c_int32, P]),
+    "prop_waveplate_batched": (c_int32, [c_int32, P, P, P, P, P, c_int64, c_int32, P]),
+    "prop_waveplate_batched_adjoint": (c_int32, [c_int32, P, P, P, P, P, P, P, P, c_int64, c_int32, P]),
+    "prop_beam_splitter": (c_int32, [c_int32, P, P, P, P, c_int32, P, c_int64, c_int32, P]),
+    "prop_beam_splitter_adjoint": (c_int32, [c_int32, P, P, P, P, P, P, c_int32, P, P, c_int64, c_int32, P]),
     "prop_spot_loss": (c_int32, [c_int32, P, P, P, G, c_double, c_double, P, P, P, P, c_int32, P]),
     "prop_sampling_check": (c_int32, [G, c_double, c_double]),
     "prop_fft_length": (c_int32, [c_int32]),

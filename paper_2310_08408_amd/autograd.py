@@ -14,9 +14,10 @@ from __future__ import annotations
 
 import torch
 
-from . import (czt_adjoint, czt_grad_z, czt_propagate, prop_density_loss, prop_modulate, prop_phase_grad,
-               prop_softmin, prop_spot_loss, prop_waveplate, prop_waveplate_adjoint, rs_adjoint, rs_grad_z,
-               rs_propagate, vczt_adjoint, vczt_propagate, vrs_adjoint, vrs_propagate)
+from . import (czt_adjoint, czt_grad_z, czt_propagate, prop_beam_splitter, prop_beam_splitter_adjoint,
+               prop_density_loss, prop_modulate, prop_phase_grad, prop_softmin, prop_spot_loss, prop_waveplate,
+               prop_waveplate_adjoint, prop_waveplate_batched, prop_waveplate_batched_adjoint, rs_adjoint,
+               rs_grad_z, rs_propagate, vczt_adjoint, vczt_propagate, vrs_adjoint, vrs_propagate)
 
 
 def _zval(z):
@@ -29,6 +30,7 @@ class RS(torch.autograd.Function):
         u = u.contiguous()
         ctx.args = (grid, wavelength, _zval(z))
         ctx.z_tensor = isinstance(z, torch.Tensor)
+        ctx.z_shape = z.shape if ctx.z_tensor else None
         ctx.save_for_backward(u)
         return rs_propagate(u, grid, wavelength, _zval(z))
 
@@ -39,7 +41,7 @@ class RS(torch.autograd.Function):
         g = g.contiguous()
         gz = None
         if ctx.z_tensor and ctx.needs_input_grad[3]:
-            gz = rs_grad_z(u, g, grid, wl, z).sum()
+            gz = rs_grad_z(u, g, grid, wl, z).sum().reshape(ctx.z_shape)
         gu = rs_adjoint(g, grid, wl, z) if ctx.needs_input_grad[0] else None
         return gu, None, None, gz
 
@@ -50,6 +52,7 @@ class CZT(torch.autograd.Function):
         u = u.contiguous()
         ctx.args = (grid_in, window, wavelength, _zval(z))
         ctx.z_tensor = isinstance(z, torch.Tensor)
+        ctx.z_shape = z.shape if ctx.z_tensor else None
         y = czt_propagate(u, grid_in, window, wavelength, _zval(z))
         ctx.save_for_backward(u, y)
         return y
@@ -61,7 +64,7 @@ class CZT(torch.autograd.Function):
         g = g.contiguous()
         gz = None
         if ctx.z_tensor and ctx.needs_input_grad[4]:
-            gz = czt_grad_z(u, g, gi, win, wl, z, u_out=y).sum()
+            gz = czt_grad_z(u, g, gi, win, wl, z, u_out=y).sum().reshape(ctx.z_shape)
         gu = czt_adjoint(g, gi, win, wl, z) if ctx.needs_input_grad[0] else None
         return gu, None, None, None, gz
 
@@ -137,6 +140,61 @@ class WavePlate(torch.autograd.Function):
         gex, gey, dp = prop_waveplate_adjoint(gx, gy, ex, ey, float(eta), float(theta))
         tot = dp.sum(0)
         return gex, gey, tot[0].to(eta.dtype).reshape(eta.shape), tot[1].to(theta.dtype).reshape(theta.shape)
+
+
+class WavePlates(torch.autograd.Function):
+    """Wave plates with one (eta, theta) per batch item: params is a float64
+    [batch, 2] device tensor."""
+
+    @staticmethod
+    def forward(ctx, ex, ey, params):
+        ex, ey = ex.contiguous(), ey.contiguous()
+        ctx.save_for_backward(ex, ey, params)
+        return prop_waveplate_batched(ex, ey, params)
+
+    @staticmethod
+    def backward(ctx, gx, gy):
+        ex, ey, params = ctx.saved_tensors
+        gx = torch.zeros_like(ex) if gx is None else gx
+        gy = torch.zeros_like(ey) if gy is None else gy
+        gex, gey, dp = prop_waveplate_batched_adjoint(gx, gy, ex, ey, params, grad=ctx.needs_input_grad[2])
+        return gex, gey, (dp.reshape(params.shape) if dp is not None else None)
+
+
+class BeamSplitter(torch.autograd.Function):
+    """Beam splitter with one mixing angle per batch item (alpha float64
+    [batch]) on ncomp components per port:
+    BeamSplitter.apply(ncomp, has_a, has_b, alpha, *a_planes, *b_planes)
+    returns the ncomp planes of port c, then the ncomp planes of port d.
+    A port flagged absent is dark and contributes no planes."""
+
+    @staticmethod
+    def forward(ctx, ncomp, has_a, has_b, alpha, *planes):
+        a = list(planes[:ncomp]) if has_a else None
+        b = list(planes[ncomp * int(has_a):]) if has_b else None
+        c, d = prop_beam_splitter(a, b, alpha)
+        ctx.ncomp, ctx.has_a, ctx.has_b = ncomp, has_a, has_b
+        ctx.save_for_backward(alpha, *planes)
+        return (*c, *d)
+
+    @staticmethod
+    def backward(ctx, *g):
+        alpha, *planes = ctx.saved_tensors
+        n, has_a, has_b = ctx.ncomp, ctx.has_a, ctx.has_b
+        ref = next(t for t in list(g) + planes if t is not None)
+        g = [torch.zeros_like(ref) if t is None else t for t in g]
+        a = planes[:n] if has_a else None
+        b = planes[n * int(has_a):] if has_b else None
+        need = ctx.needs_input_grad
+        want_a = has_a and any(need[4:4 + n])
+        want_b = has_b and any(need[4 + n * int(has_a):])
+        ga, gb, da = prop_beam_splitter_adjoint(g[:n], g[n:], a, b, alpha, (want_a, want_b), grad=need[3])
+        outs = []
+        if has_a:
+            outs += list(ga) if ga is not None else [None] * n
+        if has_b:
+            outs += list(gb) if gb is not None else [None] * n
+        return (None, None, None, da, *outs)
 
 
 class SpotLoss(torch.autograd.Function):

@@ -326,6 +326,207 @@ hipError_t launch_jones_grad(const cx<T>* gx, const cx<T>* gy, const cx<T>* ex, 
   return hipGetLastError();
 }
 
+// ------------------------------------ wave plates, per-item parameters --
+// Jones matrix R(-theta) diag(1, e^{i eta}) R(theta) of one batch item, and
+// its derivatives in eta and theta, evaluated on the device from the
+// item's (eta, theta) so that optimised parameters never leave HBM.
+__device__ __forceinline__ void jones_item(double eta, double theta, double J[8]) {
+  double c, s, ei, er;
+  sincos(theta, &s, &c);
+  sincos(eta, &ei, &er);
+  J[0] = c * c + er * s * s; J[1] = ei * s * s;
+  J[2] = c * s * (1 - er);   J[3] = -c * s * ei;
+  J[4] = J[2];               J[5] = J[3];
+  J[6] = s * s + er * c * c; J[7] = ei * c * c;
+}
+
+template <typename T>
+__global__ void k_jones_items(const cx<T>* ex, const cx<T>* ey, cx<T>* ox, cx<T>* oy, const double* params,
+                              int adjoint, int64_t npix) {
+  const int bi = blockIdx.y;
+  double J[8];
+  jones_item(params[2 * bi], params[2 * bi + 1], J);
+  if (adjoint) {  // J^H: transpose (J is symmetric) and conjugate
+    J[1] = -J[1]; J[3] = -J[3]; J[5] = -J[5]; J[7] = -J[7];
+  }
+  const cx<T> a = mk<T>(T(J[0]), T(J[1])), b = mk<T>(T(J[2]), T(J[3]));
+  const cx<T> c = mk<T>(T(J[4]), T(J[5])), d = mk<T>(T(J[6]), T(J[7]));
+  const int64_t off = (int64_t)bi * npix;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < npix; i += (int64_t)gridDim.x * blockDim.x) {
+    const cx<T> x = ex[off + i], y = ey[off + i];
+    ox[off + i] = cadd(cmul(a, x), cmul(b, y));
+    oy[off + i] = cadd(cmul(c, x), cmul(d, y));
+  }
+}
+
+// Blocks per batch item of the per-item elementwise passes: enough for
+// about 4096 workgroups in all, at most one per 256 pixels.
+static int item_blocks(int64_t npix, int batch) {
+  const int64_t want = std::max<int64_t>(8, 4096 / std::max(batch, 1));
+  return (int)std::max<int64_t>(1, std::min<int64_t>((npix + 255) / 256, want));
+}
+
+template <typename T>
+hipError_t launch_jones_items(const cx<T>* ex, const cx<T>* ey, cx<T>* ox, cx<T>* oy, const double* params,
+                              bool adjoint, int64_t npix, int batch, hipStream_t s) {
+  hipLaunchKernelGGL((k_jones_items<T>), dim3(item_blocks(npix, batch), batch), dim3(256), 0, s, ex, ey, ox, oy,
+                     params, adjoint ? 1 : 0, npix);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_jones_items_grad(const cx<T>* gx, const cx<T>* gy, const cx<T>* ex,
+                                                          const cx<T>* ey, const double* params, double* partial,
+                                                          int nblk, int64_t npix) {
+  __shared__ double sh[2 * 256];
+  const int bi = blockIdx.y;
+  const double eta = params[2 * bi], theta = params[2 * bi + 1];
+  double c, s, ei, er, s2, c2;
+  sincos(theta, &s, &c);
+  sincos(eta, &ei, &er);
+  sincos(2 * theta, &s2, &c2);
+  // dJ/deta = i e [[s^2, -cs], [-cs, c^2]];  dJ/dtheta = (1 - e) [[-s2, c2], [c2, s2]]
+  double dJ[16];
+  const double m[4] = {s * s, -c * s, -c * s, c * c};
+  const double n[4] = {-s2, c2, c2, s2};
+  for (int k = 0; k < 4; ++k) {
+    dJ[2 * k] = -ei * m[k];
+    dJ[2 * k + 1] = er * m[k];
+    dJ[8 + 2 * k] = (1 - er) * n[k];
+    dJ[8 + 2 * k + 1] = -ei * n[k];
+  }
+  double acc[2] = {0.0, 0.0};
+  const int64_t off = (int64_t)bi * npix;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < npix; i += (int64_t)nblk * 256) {
+    const cx<T> x = ex[off + i], y = ey[off + i], g0 = gx[off + i], g1 = gy[off + i];
+    const double X[2] = {x.x, x.y}, Y[2] = {y.x, y.y}, G0[2] = {g0.x, g0.y}, G1[2] = {g1.x, g1.y};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const double* d = dJ + 8 * q;
+      const double o0r = d[0] * X[0] - d[1] * X[1] + d[2] * Y[0] - d[3] * Y[1];
+      const double o0i = d[0] * X[1] + d[1] * X[0] + d[2] * Y[1] + d[3] * Y[0];
+      const double o1r = d[4] * X[0] - d[5] * X[1] + d[6] * Y[0] - d[7] * Y[1];
+      const double o1i = d[4] * X[1] + d[5] * X[0] + d[6] * Y[1] + d[7] * Y[0];
+      acc[q] += G0[0] * o0r + G0[1] * o0i + G1[0] * o1r + G1[1] * o1i;
+    }
+  }
+  block_reduce<2>(acc, sh);
+  if (threadIdx.x == 0) {
+    partial[((int64_t)bi * nblk + blockIdx.x) * 2 + 0] = acc[0];
+    partial[((int64_t)bi * nblk + blockIdx.x) * 2 + 1] = acc[1];
+  }
+}
+
+template <typename T>
+hipError_t launch_jones_items_grad(const cx<T>* gx, const cx<T>* gy, const cx<T>* ex, const cx<T>* ey,
+                                   const double* params, double* out, double* partial, int nblk, int64_t npix,
+                                   int batch, hipStream_t s) {
+  hipLaunchKernelGGL((k_jones_items_grad<T>), dim3(nblk, batch), dim3(256), 0, s, gx, gy, ex, ey, params, partial,
+                     nblk, npix);
+  hipLaunchKernelGGL(k_sum_partials2, dim3(batch), dim3(256), 0, s, partial, nblk, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- beam splitter --
+// Lossless symmetric splitter with mixing angle alpha[b] per batch item, on
+// each of ncomp components: c = cos a + i sin b, d = i sin a + cos b.  A
+// port flagged absent reads as zero.
+template <typename T>
+__global__ void k_beam_splitter(Planes a, Planes b, Planes c, Planes d, int ncomp, int has_a, int has_b,
+                                const double* alpha, int64_t npix) {
+  const int bi = blockIdx.y;
+  double sd, cd;
+  sincos(alpha[bi], &sd, &cd);
+  const T ct = T(cd), st = T(sd);
+  const int64_t off = (int64_t)bi * npix;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < npix; i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (k >= ncomp) break;
+      const cx<T> x = has_a ? ((const cx<T>*)a.p[k])[off + i] : mk<T>(T(0), T(0));
+      const cx<T> y = has_b ? ((const cx<T>*)b.p[k])[off + i] : mk<T>(T(0), T(0));
+      ((cx<T>*)c.p[k])[off + i] = mk<T>(ct * x.x - st * y.y, ct * x.y + st * y.x);
+      ((cx<T>*)d.p[k])[off + i] = mk<T>(ct * y.x - st * x.y, ct * y.y + st * x.x);
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_beam_splitter(const Planes& a, const Planes& b, const Planes& c, const Planes& d, int ncomp,
+                                bool has_a, bool has_b, const double* alpha, int64_t npix, int batch, hipStream_t s) {
+  hipLaunchKernelGGL((k_beam_splitter<T>), dim3(item_blocks(npix, batch), batch), dim3(256), 0, s, a, b, c, d, ncomp,
+                     has_a ? 1 : 0, has_b ? 1 : 0, alpha, npix);
+  return hipGetLastError();
+}
+
+// Adjoint: ga = cos gc - i sin gd, gb = -i sin gc + cos gd (when wanted),
+// and per block the FP64 partial sums A = Re(conj(gc) a + conj(gd) b),
+// B = Im(conj(gc) b + conj(gd) a), from which dL/dalpha = -sin A - cos B.
+template <typename T>
+__global__ __launch_bounds__(256) void k_beam_splitter_adj(Planes gc, Planes gd, Planes a, Planes b, Planes ga,
+                                                           Planes gb, int ncomp, int flags, const double* alpha,
+                                                           double* partial, int nblk, int64_t npix) {
+  __shared__ double sh[2 * 256];
+  const bool has_a = flags & 1, has_b = flags & 2, want_ga = flags & 4, want_gb = flags & 8, want_da = flags & 16;
+  const int bi = blockIdx.y;
+  double sd, cd;
+  sincos(alpha[bi], &sd, &cd);
+  const T ct = T(cd), st = T(sd);
+  const int64_t off = (int64_t)bi * npix;
+  double acc[2] = {0.0, 0.0};
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < npix; i += (int64_t)nblk * 256) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (k >= ncomp) break;
+      const cx<T> p = ((const cx<T>*)gc.p[k])[off + i], q = ((const cx<T>*)gd.p[k])[off + i];
+      if (want_ga) ((cx<T>*)ga.p[k])[off + i] = mk<T>(ct * p.x + st * q.y, ct * p.y - st * q.x);
+      if (want_gb) ((cx<T>*)gb.p[k])[off + i] = mk<T>(st * p.y + ct * q.x, ct * q.y - st * p.x);
+      if (want_da) {
+        const cx<T> x = has_a ? ((const cx<T>*)a.p[k])[off + i] : mk<T>(T(0), T(0));
+        const cx<T> y = has_b ? ((const cx<T>*)b.p[k])[off + i] : mk<T>(T(0), T(0));
+        const double px = p.x, py = p.y, qx = q.x, qy = q.y;
+        acc[0] += px * (double)x.x + py * (double)x.y + qx * (double)y.x + qy * (double)y.y;
+        acc[1] += px * (double)y.y - py * (double)y.x + qx * (double)x.y - qy * (double)x.x;
+      }
+    }
+  }
+  if (!want_da) return;  // uniform over the grid
+  block_reduce<2>(acc, sh);
+  if (threadIdx.x == 0) {
+    partial[((int64_t)bi * nblk + blockIdx.x) * 2 + 0] = acc[0];
+    partial[((int64_t)bi * nblk + blockIdx.x) * 2 + 1] = acc[1];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_beam_splitter_dalpha(const double* partial, int nblk, const double* alpha,
+                                                              double* dalpha) {
+  __shared__ double sh[2 * 256];
+  const int b = blockIdx.x;
+  double acc[2] = {0.0, 0.0};
+  for (int i = threadIdx.x; i < nblk; i += 256) {
+    acc[0] += partial[((int64_t)b * nblk + i) * 2 + 0];
+    acc[1] += partial[((int64_t)b * nblk + i) * 2 + 1];
+  }
+  block_reduce<2>(acc, sh);
+  if (threadIdx.x == 0) {
+    double sd, cd;
+    sincos(alpha[b], &sd, &cd);
+    dalpha[b] = -sd * acc[0] - cd * acc[1];
+  }
+}
+
+template <typename T>
+hipError_t launch_beam_splitter_adj(const Planes& gc, const Planes& gd, const Planes& a, const Planes& b,
+                                    const Planes& ga, const Planes& gb, int ncomp, int flags, const double* alpha,
+                                    double* dalpha, double* partial, int nblk, int64_t npix, int batch,
+                                    hipStream_t s) {
+  hipLaunchKernelGGL((k_beam_splitter_adj<T>), dim3(nblk, batch), dim3(256), 0, s, gc, gd, a, b, ga, gb, ncomp, flags,
+                     alpha, partial, nblk, npix);
+  if (flags & 16)
+    hipLaunchKernelGGL(k_beam_splitter_dalpha, dim3(batch), dim3(256), 0, s, partial, nblk, alpha, dalpha);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------- distance gradients --
 // Re sum conj(a) b over each batch item's npix elements (FP64, fixed order).
 template <typename T>
@@ -1010,6 +1211,15 @@ hipError_t launch_spot_loss(const cx<T>* ex, const cx<T>* ey, const cx<T>* ez, i
                                       hipStream_t);                                                                 \
   template hipError_t launch_jones_grad<T>(const cx<T>*, const cx<T>*, const cx<T>*, const cx<T>*, const double*, \
                                            double*, double*, int, int64_t, int, hipStream_t);                       \
+  template hipError_t launch_jones_items<T>(const cx<T>*, const cx<T>*, cx<T>*, cx<T>*, const double*, bool,       \
+                                            int64_t, int, hipStream_t);                                             \
+  template hipError_t launch_jones_items_grad<T>(const cx<T>*, const cx<T>*, const cx<T>*, const cx<T>*,           \
+                                                 const double*, double*, double*, int, int64_t, int, hipStream_t);  \
+  template hipError_t launch_beam_splitter<T>(const Planes&, const Planes&, const Planes&, const Planes&, int, bool, \
+                                              bool, const double*, int64_t, int, hipStream_t);                      \
+  template hipError_t launch_beam_splitter_adj<T>(const Planes&, const Planes&, const Planes&, const Planes&,      \
+                                                  const Planes&, const Planes&, int, int, const double*, double*,  \
+                                                  double*, int, int64_t, int, hipStream_t);                         \
   template hipError_t launch_pupil<T>(const cx<T>*, const cx<T>*, cx<T>*, cx<T>*, cx<T>*, int, int, double,       \
                                       double, double, double, double, double, int, int64_t, bool, hipStream_t);     \
   template hipError_t launch_vczt_prep<T>(const cx<T>*, const cx<T>*, cx<T>*, int, int, double, double, double,    \

@@ -166,6 +166,32 @@ hipError_t launch_jones_grad(const cx<T>* gx, const cx<T>* gy, const cx<T>* ex, 
                              const double* dJ /* 2 x 4 complex */, double* out, double* partial,
                              int nblk, int64_t npix, int batch, hipStream_t s);
 
+// Wave plates with per-batch-item parameters params[b] = (eta, theta)
+// (device doubles): out = J out of (ex, ey), or J^H when adjoint.
+template <typename T>
+hipError_t launch_jones_items(const cx<T>* ex, const cx<T>* ey, cx<T>* ox, cx<T>* oy, const double* params,
+                              bool adjoint, int64_t npix, int batch, hipStream_t s);
+// Per item (dL/deta, dL/dtheta) into out[b*2 + m]; partial: nblk*batch*2 doubles.
+template <typename T>
+hipError_t launch_jones_items_grad(const cx<T>* gx, const cx<T>* gy, const cx<T>* ex, const cx<T>* ey,
+                                   const double* params, double* out, double* partial, int nblk, int64_t npix,
+                                   int batch, hipStream_t s);
+// Up to three component planes of one port ([batch][npix] each).
+struct Planes {
+  const void* p[3];
+};
+// Beam splitter with mixing angle alpha[b] (device doubles) per item.
+template <typename T>
+hipError_t launch_beam_splitter(const Planes& a, const Planes& b, const Planes& c, const Planes& d, int ncomp,
+                                bool has_a, bool has_b, const double* alpha, int64_t npix, int batch, hipStream_t s);
+// Adjoint; flags: 1 a given, 2 b given, 4 write ga, 8 write gb, 16 write
+// dalpha[b] (partial: nblk*batch*2 doubles).
+template <typename T>
+hipError_t launch_beam_splitter_adj(const Planes& gc, const Planes& gd, const Planes& a, const Planes& b,
+                                    const Planes& ga, const Planes& gb, int ncomp, int flags, const double* alpha,
+                                    double* dalpha, double* partial, int nblk, int64_t npix, int batch,
+                                    hipStream_t s);
+
 // input stage of a plan setup: out = in exp(i phase) exp(-i q r^2) (phase may
 // be null, q = k/(2f) of a thin lens or 0), phase batch stride pbs (0 =
 // shared); adjoint: g_in = g conj(factor) (if g_in), grad (+)= Im(g conj(u))

@@ -410,9 +410,9 @@ static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
 }
 
 // every output must be disjoint from every input and from each other
-static int check_alias(std::initializer_list<std::pair<const void*, size_t>> ins,
-                       std::initializer_list<std::pair<const void*, size_t>> outs) {
-  std::vector<std::pair<const void*, size_t>> o(outs);
+using Span = std::pair<const void*, size_t>;
+
+static int check_alias(const std::vector<Span>& ins, const std::vector<Span>& o) {
   for (size_t i = 0; i < o.size(); ++i) {
     for (auto& in : ins)
       if (overlap(o[i].first, o[i].second, in.first, in.second)) return PROP_EALIAS;
@@ -420,6 +420,10 @@ static int check_alias(std::initializer_list<std::pair<const void*, size_t>> ins
       if (overlap(o[i].first, o[i].second, o[j].first, o[j].second)) return PROP_EALIAS;
   }
   return PROP_OK;
+}
+
+static int check_alias(std::initializer_list<Span> ins, std::initializer_list<Span> outs) {
+  return check_alias(std::vector<Span>(ins), std::vector<Span>(outs));
 }
 
 static int sampling(const prop_grid* g, double wl, double z) {
@@ -741,6 +745,12 @@ static int czt_entry(prop_dtype t, const void* in, void* out, const prop_grid* g
 }
 
 // ------------------------------------------------- distance gradients --
+// Blocks per batch item of an elementwise pass without a reduction.
+static int item_blocks_host(int64_t npix, int batch) {
+  const int64_t want = std::max<int64_t>(8, 4096 / std::max(batch, 1));
+  return (int)std::max<int64_t>(1, std::min<int64_t>((npix + 255) / 256, want));
+}
+
 static int red_blocks(int64_t npix) { return (int)std::max<int64_t>(1, std::min<int64_t>((npix + 255) / 256, 256)); }
 
 static size_t rs_grad_z_bytes(prop_dtype t, const prop_grid* g, int batch) {
@@ -1533,6 +1543,136 @@ int prop_waveplate_adjoint(prop_dtype t, const void* gx, const void* gy, const v
                                     (const cx<double>*)ey, d, dparams, (double*)wb.p, nblk, npix, batch, s);
   }
   return e == hipSuccess ? PROP_OK : dev_err(e);
+}
+
+int prop_waveplate_batched(prop_dtype t, const void* ex, const void* ey, void* ox, void* oy, const double* params,
+                           int64_t npix, int32_t batch, void* stream) {
+  if (t != PROP_C64 && t != PROP_C128) return PROP_EPARAM;
+  if (npix < 0 || batch < 0) return PROP_ESHAPE;
+  if (npix == 0 || batch == 0) return PROP_OK;
+  if (!ex || !ey || !ox || !oy || !params) return PROP_ENULL;
+  const size_t b = (size_t)npix * batch * esize(t);
+  LP_RET(check_alias({{ex, b}, {ey, b}, {params, 16 * (size_t)batch}}, {{ox, b}, {oy, b}}));
+  const hipStream_t s = (hipStream_t)stream;
+  LP_TRY(t == PROP_C64 ? launch_jones_items<float>((const cx<float>*)ex, (const cx<float>*)ey, (cx<float>*)ox,
+                                                   (cx<float>*)oy, params, false, npix, batch, s)
+                       : launch_jones_items<double>((const cx<double>*)ex, (const cx<double>*)ey, (cx<double>*)ox,
+                                                    (cx<double>*)oy, params, false, npix, batch, s));
+  return PROP_OK;
+}
+
+int prop_waveplate_batched_adjoint(prop_dtype t, const void* gx, const void* gy, const void* ex, const void* ey,
+                                   void* gex, void* gey, const double* params, double* dparams, int64_t npix,
+                                   int32_t batch, void* stream) {
+  if (t != PROP_C64 && t != PROP_C128) return PROP_EPARAM;
+  if (npix < 0 || batch < 0) return PROP_ESHAPE;
+  if (npix == 0 || batch == 0) return PROP_OK;
+  if (!gx || !gy || !gex || !gey || !params || (dparams && (!ex || !ey))) return PROP_ENULL;
+  const size_t b = (size_t)npix * batch * esize(t);
+  std::vector<Span> ins = {{gx, b}, {gy, b}, {params, 16 * (size_t)batch}};
+  std::vector<Span> outs = {{gex, b}, {gey, b}};
+  if (dparams) {
+    ins.push_back({ex, b});
+    ins.push_back({ey, b});
+    outs.push_back({dparams, 16 * (size_t)batch});
+  }
+  LP_RET(check_alias(ins, outs));
+  const hipStream_t s = (hipStream_t)stream;
+  if (t == PROP_C64)
+    LP_TRY(launch_jones_items<float>((const cx<float>*)gx, (const cx<float>*)gy, (cx<float>*)gex, (cx<float>*)gey,
+                                     params, true, npix, batch, s));
+  else
+    LP_TRY(launch_jones_items<double>((const cx<double>*)gx, (const cx<double>*)gy, (cx<double>*)gex,
+                                      (cx<double>*)gey, params, true, npix, batch, s));
+  if (!dparams) return PROP_OK;
+  std::lock_guard<std::mutex> lk(ctx().mu);
+  int dev;
+  LP_RET(cur_device(&dev));
+  const int nblk = red_blocks(npix);
+  Buf& wb = ctx().work[{dev, s}];
+  LP_RET(ensure_buf(wb, (size_t)nblk * batch * 2 * sizeof(double), s));
+  LP_TRY(t == PROP_C64
+             ? launch_jones_items_grad<float>((const cx<float>*)gx, (const cx<float>*)gy, (const cx<float>*)ex,
+                                              (const cx<float>*)ey, params, dparams, (double*)wb.p, nblk, npix,
+                                              batch, s)
+             : launch_jones_items_grad<double>((const cx<double>*)gx, (const cx<double>*)gy, (const cx<double>*)ex,
+                                               (const cx<double>*)ey, params, dparams, (double*)wb.p, nblk, npix,
+                                               batch, s));
+  return PROP_OK;
+}
+
+// The planes of one port: all ncomp entries of a given array must be set.
+static int port_planes(const void* const* arr, int ncomp, size_t bytes, Planes* out, std::vector<Span>* spans) {
+  *out = Planes{{nullptr, nullptr, nullptr}};
+  if (!arr) return PROP_OK;
+  for (int k = 0; k < ncomp; ++k) {
+    if (!arr[k]) return PROP_ENULL;
+    out->p[k] = arr[k];
+    spans->push_back({arr[k], bytes});
+  }
+  return PROP_OK;
+}
+
+int prop_beam_splitter(prop_dtype t, const void* const* a, const void* const* b, void* const* c, void* const* d,
+                       int32_t ncomp, const double* alpha, int64_t npix, int32_t batch, void* stream) {
+  if (t != PROP_C64 && t != PROP_C128) return PROP_EPARAM;
+  if (ncomp < 1 || ncomp > 3 || npix < 0 || batch < 0) return PROP_ESHAPE;
+  if (npix == 0 || batch == 0) return PROP_OK;
+  if (!c || !d || !alpha) return PROP_ENULL;
+  const size_t bytes = (size_t)npix * batch * esize(t);
+  std::vector<Span> ins = {{alpha, 8 * (size_t)batch}}, outs;
+  Planes pa, pb, pc, pd;
+  LP_RET(port_planes(a, ncomp, bytes, &pa, &ins));
+  LP_RET(port_planes(b, ncomp, bytes, &pb, &ins));
+  LP_RET(port_planes((const void* const*)c, ncomp, bytes, &pc, &outs));
+  LP_RET(port_planes((const void* const*)d, ncomp, bytes, &pd, &outs));
+  LP_RET(check_alias(ins, outs));
+  const hipStream_t s = (hipStream_t)stream;
+  LP_TRY(t == PROP_C64 ? launch_beam_splitter<float>(pa, pb, pc, pd, ncomp, a != nullptr, b != nullptr, alpha, npix,
+                                                     batch, s)
+                       : launch_beam_splitter<double>(pa, pb, pc, pd, ncomp, a != nullptr, b != nullptr, alpha, npix,
+                                                      batch, s));
+  return PROP_OK;
+}
+
+int prop_beam_splitter_adjoint(prop_dtype t, const void* const* gc, const void* const* gd, const void* const* a,
+                               const void* const* b, void* const* ga, void* const* gb, int32_t ncomp,
+                               const double* alpha, double* dalpha, int64_t npix, int32_t batch, void* stream) {
+  if (t != PROP_C64 && t != PROP_C128) return PROP_EPARAM;
+  if (ncomp < 1 || ncomp > 3 || npix < 0 || batch < 0) return PROP_ESHAPE;
+  if (npix == 0 || batch == 0) return PROP_OK;
+  if (!gc || !gd || !alpha) return PROP_ENULL;
+  const size_t bytes = (size_t)npix * batch * esize(t);
+  std::vector<Span> ins = {{alpha, 8 * (size_t)batch}}, outs;
+  Planes pgc, pgd, pa, pb, pga, pgb;
+  LP_RET(port_planes(gc, ncomp, bytes, &pgc, &ins));
+  LP_RET(port_planes(gd, ncomp, bytes, &pgd, &ins));
+  LP_RET(port_planes(dalpha ? a : nullptr, ncomp, bytes, &pa, &ins));
+  LP_RET(port_planes(dalpha ? b : nullptr, ncomp, bytes, &pb, &ins));
+  LP_RET(port_planes((const void* const*)ga, ncomp, bytes, &pga, &outs));
+  LP_RET(port_planes((const void* const*)gb, ncomp, bytes, &pgb, &outs));
+  if (dalpha) outs.push_back({dalpha, 8 * (size_t)batch});
+  LP_RET(check_alias(ins, outs));
+  const int flags = (a && dalpha ? 1 : 0) | (b && dalpha ? 2 : 0) | (ga ? 4 : 0) | (gb ? 8 : 0) | (dalpha ? 16 : 0);
+  if (!(flags & 28)) return PROP_OK;
+  const hipStream_t s = (hipStream_t)stream;
+  std::unique_lock<std::mutex> lk(ctx().mu, std::defer_lock);
+  double* partial = nullptr;
+  int nblk = item_blocks_host(npix, batch);
+  if (dalpha) {
+    lk.lock();
+    int dev;
+    LP_RET(cur_device(&dev));
+    nblk = red_blocks(npix);
+    Buf& wb = ctx().work[{dev, s}];
+    LP_RET(ensure_buf(wb, (size_t)nblk * batch * 2 * sizeof(double), s));
+    partial = (double*)wb.p;
+  }
+  LP_TRY(t == PROP_C64 ? launch_beam_splitter_adj<float>(pgc, pgd, pa, pb, pga, pgb, ncomp, flags, alpha, dalpha,
+                                                         partial, nblk, npix, batch, s)
+                       : launch_beam_splitter_adj<double>(pgc, pgd, pa, pb, pga, pgb, ncomp, flags, alpha, dalpha,
+                                                          partial, nblk, npix, batch, s));
+  return PROP_OK;
 }
 
 int prop_spot_loss(prop_dtype t, const void* ex, const void* ey, const void* ez, const prop_grid* win,

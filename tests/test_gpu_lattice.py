@@ -1,0 +1,260 @@
+"""Beam splitters, per-item wave plates and the splitter lattice on the GPU
+against the FP64 oracle (paper: Methods, large-scale search space and
+discovery experiments; Results, large-scale ansatz)."""
+import math
+import sys
+import time
+import warnings
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from workloads import Grid
+from tests.conftest import rel_l2
+from tests.test_oracle_lattice import small_lattice
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c64": 1e-6, "c128": 1e-14}
+
+
+@pytest.fixture(scope="module")
+def lp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2310_08408_amd as lp
+    lp.library()
+    return lp
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a, kind):
+    import torch
+    dt = torch.complex64 if kind == "c64" else torch.complex128
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dt).cuda()
+
+
+def cast(a, kind):
+    return np.asarray(a, np.complex64 if kind == "c64" else np.complex128).astype(np.complex128)
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.complex128)
+
+
+ALPHAS = np.array([0.0, 0.37, math.pi / 2, -2.2])
+
+
+@pytest.mark.parametrize("kind", ["c64", "c128"])
+@pytest.mark.parametrize("ncomp,ports", [(1, "ab"), (2, "ab"), (3, "ab"), (2, "a"), (3, "b")])
+def test_beam_splitter_vs_oracle(lp, kind, ncomp, ports):
+    import torch
+    rng = np.random.default_rng(ncomp * 7 + len(ports))
+    B, ny, nx = len(ALPHAS), 19, 33
+    rnd = lambda: cast(workloads.random_field(rng, (B, ny, nx)), kind)
+    a = [rnd() for _ in range(ncomp)] if "a" in ports else None
+    b = [rnd() for _ in range(ncomp)] if "b" in ports else None
+    gc = [rnd() for _ in range(ncomp)]
+    gd = [rnd() for _ in range(ncomp)]
+    al = torch.tensor(ALPHAS, dtype=torch.float64, device="cuda")
+    da_ = [dev(x, kind) for x in a] if a else None
+    db_ = [dev(x, kind) for x in b] if b else None
+    c, d = lp.prop_beam_splitter(da_, db_, al)
+    ga, gb, dal = lp.prop_beam_splitter_adjoint([dev(x, kind) for x in gc], [dev(x, kind) for x in gd], da_, db_, al)
+    worst = 0.0
+    for bi, alpha in enumerate(ALPHAS):
+        pick = lambda port: None if port is None else [x[bi] for x in port]
+        rc, rd = oracle.beam_splitter(pick(a), pick(b), alpha)
+        rga, rgb, rda = oracle.beam_splitter_adjoint(pick(gc), pick(gd), pick(a), pick(b), alpha)
+        for got, want in zip(c + d + ga + gb, rc + rd + rga + rgb):
+            e = rel_l2(host(got)[bi], want)
+            worst = max(worst, e)
+            assert e < TOL[kind]
+        assert abs(float(dal[bi]) - rda) <= (1e-6 if kind == "c64" else 1e-12) * max(1.0, abs(rda))
+    say(f"splitter {kind} ncomp {ncomp} ports {ports}: worst rel-L2 {worst:.1e}")
+
+
+def test_beam_splitter_adjoint_options_and_errors(lp):
+    import torch
+    rng = np.random.default_rng(3)
+    B, ny, nx = 2, 8, 8
+    x = [dev(workloads.random_field(rng, (B, ny, nx)), "c128") for _ in range(4)]
+    al = torch.tensor([0.3, 1.1], dtype=torch.float64, device="cuda")
+    ga, gb, da = lp.prop_beam_splitter_adjoint(x[:2], x[2:], None, None, al, want=(True, False), grad=False)
+    assert gb is None and da is None
+    gc1, gd1 = [host(x[0])[1], host(x[1])[1]], [host(x[2])[1], host(x[3])[1]]
+    ref = oracle.beam_splitter_adjoint(gc1, gd1, gc1, gd1, 1.1)  # inputs matter only for dL/dalpha
+    assert rel_l2(host(ga[1])[1], ref[0][1]) < 1e-14
+    with pytest.raises(Exception):
+        lp.prop_beam_splitter(x[:2], x[2:], torch.zeros(3, dtype=torch.float64, device="cuda"))
+    lib = lp.library()
+    import ctypes
+    arr = (ctypes.c_void_p * 2)(x[0].data_ptr(), x[1].data_ptr())
+    out = (ctypes.c_void_p * 2)(x[0].data_ptr(), x[2].data_ptr())
+    out2 = (ctypes.c_void_p * 2)(x[3].data_ptr(), None)
+    spare = torch.empty_like(x[0])
+    out3 = (ctypes.c_void_p * 2)(x[3].data_ptr(), spare.data_ptr())
+    # an output on an input: rejected; a missing output plane: rejected; ncomp 4: rejected
+    assert lib.prop_beam_splitter(1, arr, None, out, out3, 2, al.data_ptr(), ny * nx, B, None) == -4  # PROP_EALIAS
+    assert lib.prop_beam_splitter(1, arr, None, out2, out2, 2, al.data_ptr(), ny * nx, B, None) < 0
+    assert lib.prop_beam_splitter(1, arr, None, out, out2, 4, al.data_ptr(), ny * nx, B, None) < 0
+
+
+@pytest.mark.parametrize("kind", ["c64", "c128"])
+def test_waveplate_batched_vs_oracle(lp, kind):
+    import torch
+    rng = np.random.default_rng(5)
+    B, ny, nx = 3, 21, 17
+    ex, ey, gx, gy = (cast(workloads.random_field(rng, (B, ny, nx)), kind) for _ in range(4))
+    params = np.array([[0.4, -1.0], [math.pi, 0.25], [2.0, 1.3]])
+    pt = torch.tensor(params, device="cuda")
+    ox, oy = lp.prop_waveplate_batched(dev(ex, kind), dev(ey, kind), pt)
+    gex, gey, dp = lp.prop_waveplate_batched_adjoint(dev(gx, kind), dev(gy, kind), dev(ex, kind), dev(ey, kind), pt)
+    for bi in range(B):
+        rx, ry = oracle.waveplate(ex[bi], ey[bi], *params[bi])
+        rgx, rgy, de, dt = oracle.waveplate_adjoint(gx[bi], gy[bi], ex[bi], ey[bi], *params[bi])
+        for got, want in ((ox, rx), (oy, ry), (gex, rgx), (gey, rgy)):
+            assert rel_l2(host(got)[bi], want) < TOL[kind]
+        tol = 1e-6 if kind == "c64" else 1e-12
+        assert abs(float(dp[bi, 0]) - de) <= tol * max(1.0, abs(de))
+        assert abs(float(dp[bi, 1]) - dt) <= tol * max(1.0, abs(dt))
+
+
+def _gpu_params(lp, lat, params, batch, kind):
+    """The oracle's parameter set replicated over `batch` items, as GPU leaves."""
+    import torch
+    from paper_2310_08408_amd.lattice import LatticeParams
+    rdt = torch.float32 if kind == "c64" else torch.float64
+
+    def leaf(a, dt=torch.float64):
+        return torch.tensor(np.array(a), dtype=dt, device="cuda").requires_grad_(True)
+
+    p = LatticeParams()
+    p.phi = [(leaf(np.stack([ph[0]] * batch), rdt), leaf(np.stack([ph[1]] * batch), rdt)) for ph in params["phi"]]
+    p.wp = [leaf(np.stack([w] * batch)) for w in params["wp"]]
+    p.alpha = leaf(np.repeat(np.asarray(params["alpha"]).reshape(-1, 1), batch, axis=1))
+    p.z1 = [leaf(z) for z in params["z1"]]
+    p.z2 = [leaf(z) if z > 0 else 0.0 for z in params["z2"]]
+    return p
+
+
+def _gpu_beams(beams, batch, kind):
+    out = []
+    for beam in beams:
+        src = [None if s is None else tuple(dev(np.stack([cast(c, kind)] * batch), kind) for c in s)
+               for s in beam["sources"]]
+        out.append({"wavelength": beam["wavelength"], "sources": src})
+    return out
+
+
+def gr(t):
+    """Gradient of a leaf; none reached it (a link no light crosses): zero,
+    as in the oracle, which runs such links on zero fields."""
+    return np.zeros(tuple(t.shape)) if t.grad is None else t.grad.detach().cpu().numpy()
+
+
+def _grads_vs_oracle(p, grads, R, C):
+    """Relative errors of the GPU gradients of batch item 0 against the
+    oracle (distances: returned summed over the batch)."""
+    errs = {}
+    gphi = np.stack([np.stack([gr(t)[0] for t in pair]) for pair in p.phi])
+    errs["phi"] = rel_l2(gphi, grads["phi"])
+    errs["wp"] = rel_l2(np.stack([gr(w)[0] for w in p.wp]), grads["wp"])
+    errs["alpha"] = rel_l2(p.alpha.grad.cpu().numpy()[:, 0].reshape(R, C), grads["alpha"])
+    import torch
+    zg = lambda zs: np.array([float(z.grad) if isinstance(z, torch.Tensor) and z.grad is not None else 0.0
+                              for z in zs])
+    return errs, zg(p.z1), zg(p.z2)
+
+
+@pytest.mark.parametrize("variant", ["ez_all_units", "radial_sted_some_units"])
+def test_lattice_fp64_vs_oracle(lp, variant):
+    """The tiny lattice of the oracle pins (2 x 2 splitters, 12 links):
+    objective, per-detector losses and the gradients of every parameter
+    kind (super-SLM phases, wave plates, splitter angles, distances)
+    against the oracle in FP64, for a batch of two identical items."""
+    from paper_2310_08408_amd.lattice import Lattice
+    if variant == "ez_all_units":
+        R, C, g, win, beams, params, kw = small_lattice(0)
+    else:
+        R, C, g, win, beams, params, kw = small_lattice(1, units="some", two_beams=True, comps="radial")
+    obj, losses, grads = oracle.lattice_objective(R, C, g, win, beams, params, **kw)
+    lat = Lattice(R, C, g, win, kw["na"], kw["f"], params["unit"], comps=kw["comps"], eps=kw["eps"],
+                  beta_sted=kw["beta_sted"], beta_soft=kw["beta_soft"])
+    B = 2
+    p = _gpu_params(lp, lat, params, B, "c128")
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        val, lg = lat.forward(_gpu_beams(beams, B, "c128"), p)
+        val.sum().backward()
+    lg = lg.detach().cpu().numpy()
+    assert np.abs(lg[0] - losses).max() <= 1e-10 * np.abs(losses).max()
+    assert abs(float(val.detach()[0]) - obj) <= 1e-10 * abs(obj)
+    # every batch item carries the same set: the summed gradients are twice the oracle's
+    for t in [x for pair in p.phi for x in pair] + list(p.wp):
+        g_ = gr(t)
+        assert np.array_equal(g_[0], g_[1])
+    errs, z1, z2 = _grads_vs_oracle(p, grads, R, C)
+    errs["z1"] = rel_l2(z1, 2 * grads["z1"])
+    errs["z2"] = rel_l2(z2, 2 * grads["z2"])
+    say(f"lattice {variant} fp64: objective {float(val.detach()[0]):.9e} (oracle {obj:.9e}); grad rel-L2 "
+        + " ".join(f"{k} {v:.1e}" for k, v in errs.items()))
+    for k, v in errs.items():
+        assert v < 1e-9, (k, v)
+
+
+def test_lattice_3x3_fp32_vs_fp64_and_timing(lp):
+    """3 x 3 lattice with a building unit on every one of its 24 links (the
+    element counts of the paper's large-scale setup: 9 splitters, 24
+    super-SLMs, 24 wave plates, 6 sources, 6 detectors) at 256^2, STED with
+    a second wavelength and the total intensity: FP32 objective and
+    gradients against the FP64 GPU path (tolerances 1e-5 and 1e-3), then the
+    forward + backward time at 1024^2."""
+    import torch
+    from paper_2310_08408_amd.lattice import Lattice, n_links
+    R = C = 3
+    res = {}
+    for n in (256, 1024):
+        g = Grid.square(n, n * 4.8e-6)
+        win = Grid.square(64, 64 * 20e-9)
+        lat = Lattice(R, C, g, win, 0.9, 2e-3, [True] * n_links(R, C), comps="total", eps=0.5)
+        ex = oracle.gaussian_beam(g, 1.2e-3 * n / 1024) / math.sqrt(2)
+        for kind in (("c64", "c128") if n == 256 else ("c64",)):
+            B = 2
+            src = dev(np.stack([cast(ex, kind)] * B), kind)
+            beams = [{"wavelength": 532e-9, "sources": [(src, src) if s % 2 == 0 else None for s in range(6)]},
+                     {"wavelength": 650e-9, "sources": [(src, src) if s % 2 == 1 else None for s in range(6)]}]
+            p = lat.random_params(B, seed=4, real_dtype=torch.float32 if kind == "c64" else torch.float64,
+                                  z_range=(20e-3, 60e-3))
+            with warnings.catch_warnings():
+                warnings.simplefilter("ignore")
+                for rep in range(2 if n == 1024 else 1):
+                    for t in p.tensors():
+                        t.grad = None
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    val, losses = lat.forward(beams, p)
+                    val.sum().backward()
+                    torch.cuda.synchronize()
+                    dt = time.perf_counter() - t0
+            cat = lambda ts: np.concatenate([gr(t).astype(np.float64).ravel() for t in ts])
+            grads = {"phi": cat([t for pair in p.phi for t in pair]), "wp": cat(p.wp), "alpha": cat([p.alpha]),
+                     "z": cat(list(p.z1) + list(p.z2))}
+            res[(n, kind)] = (val.detach().cpu().numpy(), losses.detach().cpu().numpy(), grads, dt)
+    v32, l32, g32, _ = res[(256, "c64")]
+    v64, l64, g64, _ = res[(256, "c128")]
+    e_obj = np.abs(v32 - v64).max() / np.abs(v64).max()
+    e_loss = np.abs(l32 - l64).max() / np.abs(l64).max()
+    e_grad = {k: rel_l2(g32[k], g64[k]) for k in g64}
+    say(f"3x3 lattice 256^2 STED total: fp32 vs fp64 objective {e_obj:.1e} losses {e_loss:.1e} grads "
+        + " ".join(f"{k} {v:.1e}" for k, v in e_grad.items()))
+    assert e_obj < 1e-5 and e_loss < 1e-5
+    for k, v in e_grad.items():
+        assert v < 1e-3, (k, v)
+    say(f"3x3 lattice 1024^2, 2 beams x 6 sources, batch 2: forward + backward {res[(1024, 'c64')][3]:.3f} s")
