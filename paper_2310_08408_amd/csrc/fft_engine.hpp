@@ -203,6 +203,12 @@ template <int R, int DIR> struct Dft {
 constexpr int kMaxLen = 8192;
 constexpr int kMaxStages = 4;
 
+// Twiddle table layout of an element type (see Sched::twoff).
+template <typename T>
+__host__ __device__ constexpr bool tw_per_thread() {
+  return sizeof(T) == 4;
+}
+
 template <int... Rs> struct Sched {
   static constexpr int nst = sizeof...(Rs);
   static constexpr int rad[nst] = {Rs...};
@@ -218,14 +224,19 @@ template <int... Rs> struct Sched {
     for (int i = 0; i < s; ++i) p *= rad[i];
     return p;
   }
-  // offset of stage s in the twiddle table: stage s >= 1 holds
-  // W_{Ns R}^{r k} at off + (r-1) Ns + k, r = 1..R-1, k = 0..Ns-1
-  static constexpr int twoff(int s) {
+  // Offset of stage s in the twiddle table, for two layouts of W_{Ns R}^{r k}
+  // (r = 0..R-1, k = 0..Ns-1) chosen by element type:
+  //  * per thread (FP32): off + k R + r, with r = 0 (the value 1) stored, so
+  //    a thread's R twiddles are one aligned run of memory: fewer and wider
+  //    loads from one base address;
+  //  * per stage (FP64): off + (r - 1) Ns + k, so the lanes' consecutive k
+  //    read consecutive 16-byte values (the wider loads do not pay there).
+  static constexpr int twoff(int s, bool per_thread) {
     int off = 0;
-    for (int i = 1; i < s; ++i) off += (rad[i] - 1) * ns(i);
+    for (int i = 1; i < s; ++i) off += (per_thread ? rad[i] : rad[i] - 1) * ns(i);
     return off;
   }
-  static constexpr int twsize() { return nst > 1 ? twoff(nst) : 1; }
+  static constexpr int twsize(bool per_thread) { return nst > 1 ? twoff(nst, per_thread) : 1; }
   // LDS padding: one element per 2^pad_shift.  With the first radix R0 a
   // power of two, shift log2(R0) turns the first stage's stride-R0 scatter
   // into an odd stride (R0 + 1), so a half-wave's writes hit distinct banks.
@@ -281,10 +292,11 @@ __device__ __forceinline__ void ct_stage(cx<T>* __restrict__ lds, const cx<T>* _
     const int k = j % Ns;
     const int q = j / Ns;
     if constexpr (!first) {
-      const V* t = tw + S::twoff(s) + k;
+      constexpr bool pt = tw_per_thread<T>();
+      const V* t = tw + S::twoff(s, pt) + (pt ? k * R : k);
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        const V w = t[(r - 1) * Ns];
+        const V w = pt ? t[r] : t[(r - 1) * Ns];
         v[r] = DIR < 0 ? cmul(v[r], w) : cmulc(v[r], w);
       }
     }
@@ -357,9 +369,10 @@ __device__ __forceinline__ void conv_mid_stage(cx<T>* __restrict__ lds, const cx
   }
   __syncthreads();
   if (act) {
-    const V* t = tw + S::twoff(sl) + j;
+    constexpr bool pt = tw_per_thread<T>();
+    const V* t = tw + S::twoff(sl, pt) + (pt ? j * R : j);
 #pragma unroll
-    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], t[(r - 1) * nr]);
+    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], pt ? t[r] : t[(r - 1) * nr]);
     Dft<R, -1>::template run<T>(v);
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = mult(j + r * nr, v[r]);

@@ -477,19 +477,32 @@ hipError_t launch_mix2_cols(int My, const cx<T>* a, const cx<T>* b, cx<T>* out, 
 
 // ----------------------------------------------------------- Bluestein --
 // out[p] = post[p] * IFFT_L( FFT_L(pad(pre .* in)) .* chat )[p], p < n_out.
+// Columns, and FP32 rows, run C lines per workgroup with the lanes of the
+// lines interleaved (c = thread % C): the rows then share each stage's
+// per-thread twiddle loads.  FP64 rows run one line per 256 threads.  The
+// twiddle table is passed without __restrict__: with it the compiler treats
+// the table loads as invariant, lifts every stage's loads ahead of the
+// barriers and runs out of registers next to the chirp and filter loads.
+template <typename T, bool COL>
+constexpr bool bluestein_interleaved() {
+  return COL || tw_per_thread<T>();
+}
+
 template <typename T, bool COL, class S, int C, bool HALF>
-__global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, COL, 1, HALF ? (COL ? 4 : 3) : 2>())) void k_bluestein(const cx<T>* in, cx<T>* out, Lines li, Lines lo,
+__global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, bluestein_interleaved<T, COL>(), 1,
+                                                            HALF ? (bluestein_interleaved<T, COL>() ? 4 : 3) : 2>())) void k_bluestein(const cx<T>* in, cx<T>* out, Lines li, Lines lo,
                                                               int nlines, int n_in, int n_out,
                                                               const cx<T>* __restrict__ pre,
                                                               const cx<T>* __restrict__ chat,
                                                               const cx<T>* __restrict__ post, int tiles,
-                                                              const cx<T>* __restrict__ tw, PhaseGrad<T> pg) {
-  constexpr int LS = line_stride<S, C, COL>();
+                                                              const cx<T>* tw, PhaseGrad<T> pg) {
+  constexpr bool ILV = bluestein_interleaved<T, COL>();
+  constexpr int LS = line_stride<S, C, ILV>();
   __shared__ cx<T> smem[C * LS];
   const int id = xcd_remap(blockIdx.x, gridDim.x);
   const int b = id / tiles, tile = id - b * tiles;
-  const int c = COL ? (int)(threadIdx.x % C) : (int)(threadIdx.x / S::threads);
-  const int j = COL ? (int)(threadIdx.x / C) : (int)(threadIdx.x % S::threads);
+  const int c = ILV ? (int)(threadIdx.x % C) : (int)(threadIdx.x / S::threads);
+  const int j = ILV ? (int)(threadIdx.x / C) : (int)(threadIdx.x % S::threads);
   const int l = tile * C + c;
   const bool valid = l < nlines;
   cx<T>* lds = smem + c * LS;
@@ -532,9 +545,10 @@ template <typename T, bool COL, class S>
 hipError_t launch_bluestein_s(const cx<T>* in, cx<T>* out, Lines li, Lines lo, int nlines, int n_in, int n_out,
                               const cx<T>* pre, const cx<T>* chat, const cx<T>* post, int batch, const cx<T>* tw,
                               hipStream_t s, int variant, PhaseGrad<T> pg) {
-  // row passes: 512 threads per workgroup; column passes up to 1024 (more
-  // adjacent columns per row segment)
-  using CF = Cfg<T, S, COL, 1, (COL ? 1024 : 512)>;
+  // interleaved lines: up to 1024 threads per workgroup (for columns more
+  // adjacent columns per row segment); FP64 rows: 512
+  constexpr bool ILV = bluestein_interleaved<T, COL>();
+  using CF = Cfg<T, S, ILV, 1, (ILV ? 1024 : 512)>;
   if constexpr (!CF::fits) {
     return hipErrorInvalidValue;
   } else {

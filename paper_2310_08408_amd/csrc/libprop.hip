@@ -107,8 +107,10 @@ int fft_len(int n) {
 }
 
 // Twiddle table of a length's schedule: stage s >= 1 holds W_{Ns R}^{r k}
-// at off_s + (r-1) Ns + k (forward sign), computed in long double.
-static bool make_twiddles(int n, std::vector<long double>& twr, std::vector<long double>& twi) {
+// (forward sign), computed in long double, at off_s + k R + r (r = 0..R-1)
+// when per_thread, else at off_s + (r-1) Ns + k (r = 1..R-1); the engine
+// picks the layout by element type (Sched::twoff).
+static bool make_twiddles(int n, bool per_thread, std::vector<long double>& twr, std::vector<long double>& twi) {
   SchedInfo si;
   if (!sched_info(n, &si)) return false;
   twr.clear();
@@ -118,13 +120,19 @@ static bool make_twiddles(int n, std::vector<long double>& twr, std::vector<long
     const int R = si.rad[s];
     if (s > 0) {
       const long span = ns * R;
-      for (int r = 1; r < R; ++r)
-        for (long k = 0; k < ns; ++k) {
-          const long m = (r * k) % span;
-          const long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)span;
-          twr.push_back(cosl(ang));
-          twi.push_back(sinl(ang));
-        }
+      auto put = [&](long k, int r) {
+        const long m = (r * k) % span;
+        const long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)span;
+        twr.push_back(cosl(ang));
+        twi.push_back(sinl(ang));
+      };
+      if (per_thread) {
+        for (long k = 0; k < ns; ++k)
+          for (int r = 0; r < R; ++r) put(k, r);
+      } else {
+        for (int r = 1; r < R; ++r)
+          for (long k = 0; k < ns; ++k) put(k, r);
+      }
     }
     ns *= R;
   }
@@ -217,7 +225,7 @@ static int get_tw(int dev, int n, const cx<T>** tw) {
   if (it == C.plans.end()) {
     PlanEntry e;
     std::vector<long double> wr, wi;
-    if (!make_twiddles(n, wr, wi)) return PROP_ESHAPE;
+    if (!make_twiddles(n, tw_per_thread<T>(), wr, wi)) return PROP_ESHAPE;
     std::vector<cx<T>> h(wr.size());
     for (size_t i = 0; i < wr.size(); ++i) {
       h[i].x = (T)wr[i];
