@@ -199,6 +199,10 @@ int prop_source_radial(prop_dtype t, void* ex, void* ey, const prop_grid* g, dou
  * phase: real [phase_batch][npix] with phase_batch = batch or 1 (shared). */
 int prop_modulate(prop_dtype t, const void* u_in, const void* phase, void* u_out, int64_t npix,
                   int32_t batch, int32_t phase_batch, void* stream);
+/* SLM adjoint: g_in = g_out exp(-i phase) (same layout and rules as
+ * prop_modulate). */
+int prop_modulate_adjoint(prop_dtype t, const void* g_out, const void* phase, void* g_in, int64_t npix,
+                          int32_t batch, int32_t phase_batch, void* stream);
 /* SLM gradient: grad = Im(g_u conj(u)) (u = the modulated field), real
  * [batch][npix]; accumulate != 0 adds to grad. */
 int prop_phase_grad(prop_dtype t, const void* g_u, const void* u, void* grad, int64_t npix,
@@ -219,8 +223,10 @@ int prop_waveplate_adjoint(prop_dtype t, const void* gx, const void* gy, const v
  * optimised parameters stay on the GPU.  Same matrix as prop_waveplate. */
 int prop_waveplate_batched(prop_dtype t, const void* ex, const void* ey, void* ox, void* oy,
                            const double* params, int64_t npix, int32_t batch, void* stream);
-/* Adjoint: (g_ex, g_ey) = J_b^H (g_x, g_y) per item; if dparams (device
- * double [batch][2]) is non-NULL it receives (dL/deta, dL/dtheta) per item
+/* Adjoint: (g_ex, g_ey) = J_b^H (g_x, g_y) per item.  gey may be NULL when
+ * both input components were one field (a wave plate fed (A, A)): gex then
+ * receives g_A = (J^H g)_x + (J^H g)_y.  If dparams (device double
+ * [batch][2]) is non-NULL it receives (dL/deta, dL/dtheta) per item
  * (fixed-order FP64 reduction) and ex, ey (the forward inputs) are
  * required; otherwise they may be NULL. */
 int prop_waveplate_batched_adjoint(prop_dtype t, const void* gx, const void* gy, const void* ex,

@@ -298,6 +298,22 @@ def prop_modulate(u, phase, out=None):
     return out
 
 
+def prop_modulate_adjoint(g, phase, out=None):
+    """g * exp(-i phase): the adjoint of prop_modulate (same broadcasting)."""
+    lib = library()
+    _dev(g), _dev(phase)
+    if phase.dtype != _real_dtype(g):
+        raise TypeError("phase dtype must match the field precision")
+    npix = g.shape[-1] * g.shape[-2]
+    batch = g.numel() // npix
+    pb = phase.numel() // npix
+    out = torch.empty_like(g) if out is None else out
+    with torch.cuda.device(g.device):
+        st = lib.prop_modulate_adjoint(_dtype_code(g), _ptr(g), _ptr(phase), _ptr(out), npix, batch, pb, _stream(g))
+    _lib.check("prop_modulate_adjoint", st)
+    return out
+
+
 def prop_phase_grad(g_u, u, grad=None, accumulate=False):
     """Im(g_u conj(u)) (real, same shape as u)."""
     lib = library()
@@ -365,21 +381,25 @@ def prop_waveplate_batched(ex, ey, params):
     return ox, oy
 
 
-def prop_waveplate_batched_adjoint(gx, gy, ex, ey, params, grad=True):
-    """Returns (g_ex, g_ey, dparams[batch, 2] float64 or None)."""
+def prop_waveplate_batched_adjoint(gx, gy, ex, ey, params, grad=True, shared_input=False):
+    """Returns (g_ex, g_ey, dparams[batch, 2] float64 or None).  With
+    shared_input (the plate was fed one field on both components) it returns
+    (g_A, None, dparams), g_A = g_ex + g_ey."""
     lib = library()
     gx, gy, params = gx.contiguous(), gy.contiguous(), params.contiguous()
     npix = gx.shape[-1] * gx.shape[-2]
     batch = _items(gx, npix)
     if params.dtype != torch.float64 or params.numel() != 2 * batch:
         raise ValueError("params must be float64 [batch, 2]")
-    gex, gey = torch.empty_like(gx), torch.empty_like(gy)
+    gex = torch.empty_like(gx)
+    gey = None if shared_input else torch.empty_like(gy)
     dp = torch.empty((batch, 2), dtype=torch.float64, device=gx.device) if grad else None
     if grad:
         ex, ey = ex.contiguous(), ey.contiguous()
     with torch.cuda.device(gx.device):
         st = lib.prop_waveplate_batched_adjoint(_dtype_code(gx), _ptr(gx), _ptr(gy), _ptr(ex) if grad else None,
-                                                _ptr(ey) if grad else None, _ptr(gex), _ptr(gey), _ptr(params),
+                                                _ptr(ey) if grad else None, _ptr(gex),
+                                                _ptr(gey) if gey is not None else None, _ptr(params),
                                                 _ptr(dp) if grad else None, npix, batch, _stream(gx))
     _lib.check("prop_waveplate_batched_adjoint", st)
     return gex, gey, dp

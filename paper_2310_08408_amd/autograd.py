@@ -15,7 +15,8 @@ from __future__ import annotations
 import torch
 
 from . import (czt_adjoint, czt_grad_z, czt_propagate, prop_beam_splitter, prop_beam_splitter_adjoint,
-               prop_density_loss, prop_modulate, prop_phase_grad, prop_softmin, prop_spot_loss, prop_waveplate,
+               prop_density_loss, prop_modulate, prop_modulate_adjoint, prop_phase_grad, prop_softmin,
+               prop_spot_loss, prop_waveplate,
                prop_waveplate_adjoint, prop_waveplate_batched, prop_waveplate_batched_adjoint, rs_adjoint,
                rs_grad_z, rs_propagate, vczt_adjoint, vczt_propagate, vrs_adjoint, vrs_propagate)
 
@@ -114,7 +115,7 @@ class Modulate(torch.autograd.Function):
     def backward(ctx, g):
         u, phase = ctx.saved_tensors
         g = g.contiguous()
-        g_v = prop_modulate(g, -phase) if ctx.needs_input_grad[0] else None
+        g_v = prop_modulate_adjoint(g, phase) if ctx.needs_input_grad[0] else None
         g_phi = None
         if ctx.needs_input_grad[1]:
             g_phi = prop_phase_grad(g, u)

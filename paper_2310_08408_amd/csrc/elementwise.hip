@@ -151,20 +151,23 @@ template <typename T> __device__ __forceinline__ void sc(T x, T* s, T* c);
 template <> __device__ __forceinline__ void sc<float>(float x, float* s, float* c) { sincosf(x, s, c); }
 template <> __device__ __forceinline__ void sc<double>(double x, double* s, double* c) { sincos(x, s, c); }
 
+// out = in exp(i phase), or in exp(-i phase) when conj (the adjoint)
 template <typename T>
-__global__ void k_modulate(const cx<T>* in, const T* phase, cx<T>* out, int64_t npix, int batch, int64_t pbs) {
+__global__ void k_modulate(const cx<T>* in, const T* phase, cx<T>* out, int64_t npix, int batch, int64_t pbs,
+                           int conj) {
   const int64_t total = npix * batch;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
     const int64_t b = t / npix, i = t - b * npix;
     T sn, cs;
     sc<T>(phase[b * pbs + i], &sn, &cs);
-    out[t] = cmul(in[t], mk<T>(cs, sn));
+    out[t] = cmul(in[t], mk<T>(cs, conj ? -sn : sn));
   }
 }
 template <typename T>
 hipError_t launch_modulate(const cx<T>* in, const T* phase, cx<T>* out, int64_t npix, int batch, int64_t pbs,
-                           hipStream_t s) {
-  hipLaunchKernelGGL((k_modulate<T>), dim3(ew_blocks(npix * batch)), dim3(256), 0, s, in, phase, out, npix, batch, pbs);
+                           hipStream_t s, bool conj) {
+  hipLaunchKernelGGL((k_modulate<T>), dim3(ew_blocks(npix * batch)), dim3(256), 0, s, in, phase, out, npix, batch, pbs,
+                     conj ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -354,8 +357,13 @@ __global__ void k_jones_items(const cx<T>* ex, const cx<T>* ey, cx<T>* ox, cx<T>
   const int64_t off = (int64_t)bi * npix;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < npix; i += (int64_t)gridDim.x * blockDim.x) {
     const cx<T> x = ex[off + i], y = ey[off + i];
-    ox[off + i] = cadd(cmul(a, x), cmul(b, y));
-    oy[off + i] = cadd(cmul(c, x), cmul(d, y));
+    const cx<T> u = cadd(cmul(a, x), cmul(b, y)), v = cadd(cmul(c, x), cmul(d, y));
+    if (oy) {
+      ox[off + i] = u;
+      oy[off + i] = v;
+    } else {
+      ox[off + i] = cadd(u, v);  // both components came from one field
+    }
   }
 }
 
@@ -1201,7 +1209,7 @@ hipError_t launch_spot_loss(const cx<T>* ex, const cx<T>* ey, const cx<T>* ez, i
                                             double, double, int, int64_t, hipStream_t);                             \
   template hipError_t launch_phase_stage_adj<T>(const cx<T>*, const cx<T>*, const T*, cx<T>*, T*, int, int, int,   \
                                                 double, double, double, double, double, int, int64_t, hipStream_t); \
-  template hipError_t launch_modulate<T>(const cx<T>*, const T*, cx<T>*, int64_t, int, int64_t, hipStream_t);      \
+  template hipError_t launch_modulate<T>(const cx<T>*, const T*, cx<T>*, int64_t, int, int64_t, hipStream_t, bool); \
   template hipError_t launch_phase_grad<T>(const cx<T>*, const cx<T>*, T*, int64_t, int, int, hipStream_t);         \
   template hipError_t launch_source_gaussian<T>(cx<T>*, int, int, double, double, double, double, double, double,  \
                                                 double, double, int, hipStream_t);                                  \

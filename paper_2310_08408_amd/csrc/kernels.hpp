@@ -144,7 +144,7 @@ hipError_t launch_convert(const cx<double>* in, cx<T>* out, int64_t n, hipStream
 // ---- elementwise ----
 template <typename T>
 hipError_t launch_modulate(const cx<T>* in, const T* phase, cx<T>* out, int64_t npix, int batch,
-                           int64_t phase_bstride, hipStream_t s);
+                           int64_t phase_bstride, hipStream_t s, bool conj = false);
 template <typename T>
 hipError_t launch_phase_grad(const cx<T>* g, const cx<T>* u, T* grad, int64_t npix, int batch,
                              int accumulate, hipStream_t s);
@@ -167,7 +167,8 @@ hipError_t launch_jones_grad(const cx<T>* gx, const cx<T>* gy, const cx<T>* ex, 
                              int nblk, int64_t npix, int batch, hipStream_t s);
 
 // Wave plates with per-batch-item parameters params[b] = (eta, theta)
-// (device doubles): out = J out of (ex, ey), or J^H when adjoint.
+// (device doubles): out = J out of (ex, ey), or J^H when adjoint; with oy
+// null, ox receives the sum of the two output components.
 template <typename T>
 hipError_t launch_jones_items(const cx<T>* ex, const cx<T>* ey, cx<T>* ox, cx<T>* oy, const double* params,
                               bool adjoint, int64_t npix, int batch, hipStream_t s);

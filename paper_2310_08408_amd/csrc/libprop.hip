@@ -998,6 +998,8 @@ struct PlanSetup {
   int ncomp_in = 1;
   bool modulated = false;
   void* umod = nullptr;  // modulated input (ncomp_in planes) kept for the adjoint
+  int branch = 0;        // capture stream in graph mode
+  double cost = 0.0;     // transform elements per execution (load balancing)
 };
 
 }  // namespace lp
@@ -1015,6 +1017,7 @@ struct prop_plan {
   std::vector<hipEvent_t> join;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   bool tuned[2] = {false, false};  // PROP_PLAN_AUTOTUNE: first execution tunes
+  std::vector<int> order;          // graph mode: setups by decreasing cost
 };
 
 namespace lp {
@@ -1042,6 +1045,18 @@ static int validate_setup(prop_dtype t, const prop_setup& s) {
   for (int c = 0; c < ncomp_out(s.op); ++c)
     if (!s.out[c] || !s.gout[c]) return PROP_ENULL;
   return PROP_OK;
+}
+
+// Transform elements one execution of a setup touches (all passes, both
+// directions alike): the weight of its load-balancing assignment.
+static double setup_cost(const prop_setup& s) {
+  const double b = s.batch * (double)(ncomp_in(s.op) + ncomp_out(s.op));
+  if (s.op == PROP_OP_RS || s.op == PROP_OP_VRS) {
+    const double Mx = fft_len(2 * s.g_in.nx - 1), My = fft_len(2 * s.g_in.ny - 1);
+    return b * (s.g_in.ny * Mx + Mx * My + s.g_in.ny * Mx);
+  }
+  const double Lx = fft_len(s.g_in.nx + s.win.nx - 1), Ly = fft_len(s.g_in.ny + s.win.ny - 1);
+  return b * (s.g_in.ny * Lx + s.win.nx * Ly);
 }
 
 static size_t setup_work_bytes(prop_dtype t, const prop_setup& s) {
@@ -1150,11 +1165,11 @@ static int plan_enqueue(prop_plan* p, bool adjoint, hipStream_t st, bool branche
     LP_TRY(hipEventRecord(p->fork, st));
     for (int b = 0; b < p->nbranch; ++b) LP_TRY(hipStreamWaitEvent(p->br[b], p->fork, 0));
   }
-  for (size_t i = 0; i < p->setups.size(); ++i) {
-    const int b = branched ? (int)(i % p->nbranch) : 0;
+  for (size_t k = 0; k < p->setups.size(); ++k) {
+    PlanSetup& ps = p->setups[branched ? p->order[k] : k];
+    const int b = branched ? ps.branch : 0;
     const hipStream_t s = branched ? p->br[b] : st;
-    LP_RET(p->t == PROP_C64 ? run_setup<float>(p, p->setups[i], adjoint, s, b)
-                            : run_setup<double>(p, p->setups[i], adjoint, s, b));
+    LP_RET(p->t == PROP_C64 ? run_setup<float>(p, ps, adjoint, s, b) : run_setup<double>(p, ps, adjoint, s, b));
   }
   if (branched) {
     for (int b = 0; b < p->nbranch; ++b) {
@@ -1455,8 +1470,8 @@ int prop_source_radial(prop_dtype t, void* ex, void* ey, const prop_grid* g, dou
   return e == hipSuccess ? PROP_OK : dev_err(e);
 }
 
-int prop_modulate(prop_dtype t, const void* u_in, const void* phase, void* u_out, int64_t npix, int32_t batch,
-                  int32_t phase_batch, void* stream) {
+static int modulate_run(prop_dtype t, const void* u_in, const void* phase, void* u_out, int64_t npix, int32_t batch,
+                        int32_t phase_batch, void* stream, bool conj) {
   if (t != PROP_C64 && t != PROP_C128) return PROP_EPARAM;
   if (npix < 0 || batch < 0) return PROP_ESHAPE;
   if (phase_batch != 1 && phase_batch != batch) return PROP_ESHAPE;
@@ -1472,10 +1487,20 @@ int prop_modulate(prop_dtype t, const void* u_in, const void* phase, void* u_out
   const double es = (double)esize(t);
   LP_TRACE("modulate", (double)npix * batch * 2.0 * es + (double)npix * phase_batch * es / 2, s,
            (t == PROP_C64 ? launch_modulate<float>((const cx<float>*)u_in, (const float*)phase, (cx<float>*)u_out,
-                                                   npix, batch, pbs, s)
+                                                   npix, batch, pbs, s, conj)
                           : launch_modulate<double>((const cx<double>*)u_in, (const double*)phase,
-                                                    (cx<double>*)u_out, npix, batch, pbs, s)));
+                                                    (cx<double>*)u_out, npix, batch, pbs, s, conj)));
   return PROP_OK;
+}
+
+int prop_modulate(prop_dtype t, const void* u_in, const void* phase, void* u_out, int64_t npix, int32_t batch,
+                  int32_t phase_batch, void* stream) {
+  return modulate_run(t, u_in, phase, u_out, npix, batch, phase_batch, stream, false);
+}
+
+int prop_modulate_adjoint(prop_dtype t, const void* g_out, const void* phase, void* g_in, int64_t npix,
+                          int32_t batch, int32_t phase_batch, void* stream) {
+  return modulate_run(t, g_out, phase, g_in, npix, batch, phase_batch, stream, true);
 }
 
 int prop_phase_grad(prop_dtype t, const void* g_u, const void* u, void* grad, int64_t npix, int32_t batch,
@@ -1575,10 +1600,11 @@ int prop_waveplate_batched_adjoint(prop_dtype t, const void* gx, const void* gy,
   if (t != PROP_C64 && t != PROP_C128) return PROP_EPARAM;
   if (npix < 0 || batch < 0) return PROP_ESHAPE;
   if (npix == 0 || batch == 0) return PROP_OK;
-  if (!gx || !gy || !gex || !gey || !params || (dparams && (!ex || !ey))) return PROP_ENULL;
+  if (!gx || !gy || !gex || !params || (dparams && (!ex || !ey))) return PROP_ENULL;
   const size_t b = (size_t)npix * batch * esize(t);
   std::vector<Span> ins = {{gx, b}, {gy, b}, {params, 16 * (size_t)batch}};
-  std::vector<Span> outs = {{gex, b}, {gey, b}};
+  std::vector<Span> outs = {{gex, b}};
+  if (gey) outs.push_back({gey, b});
   if (dparams) {
     ins.push_back({ex, b});
     ins.push_back({ey, b});
@@ -1888,7 +1914,20 @@ int prop_plan_create(prop_dtype t, const prop_setup* setups, int32_t n, uint32_t
       gmax = std::max(gmax, plane * ps.ncomp_in);
     }
     wmax = std::max(wmax, setup_work_bytes(t, ps.s));
+    ps.cost = setup_cost(ps.s);
     p->setups.push_back(ps);
+  }
+  // branches: longest-first onto the least-loaded stream, so the concurrent
+  // streams of a graph finish together
+  p->order.resize(n);
+  for (int i = 0; i < n; ++i) p->order[i] = i;
+  std::stable_sort(p->order.begin(), p->order.end(),
+                   [&](int a, int b) { return p->setups[a].cost > p->setups[b].cost; });
+  std::vector<double> load(p->nbranch, 0.0);
+  for (int i : p->order) {
+    const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    p->setups[i].branch = b;
+    load[b] += p->setups[i].cost;
   }
   p->work.resize(p->nbranch);
   p->gbuf.resize(p->nbranch);

@@ -86,6 +86,22 @@ def test_validation_without_device(lib):
     assert lib.prop_density_loss(0, comps, 2, None, 1, 1.0, 16, 0.5, out, None, None, 1, None) == -1
     assert lib.prop_softmin(out, 3, 0.0, out, None, 1, None) == -3
     assert lib.prop_softmin(out, 0, 1.0, out, None, 1, None) == -2
+    # beam splitter: component count, missing output plane, output on an input
+    pa = (ctypes.c_void_p * 2)(0x10000000, 0x20000000)
+    pc = (ctypes.c_void_p * 2)(0x30000000, 0x40000000)
+    pd = (ctypes.c_void_p * 2)(0x50000000, None)
+    pe = (ctypes.c_void_p * 2)(0x60000000, 0x10000000)
+    assert lib.prop_beam_splitter(0, pa, None, pc, pc, 0, out, 16, 1, None) == -2
+    assert lib.prop_beam_splitter(0, pa, None, pc, pc, 4, out, 16, 1, None) == -2
+    assert lib.prop_beam_splitter(0, pa, None, pc, pd, 2, out, 16, 1, None) == -1
+    assert lib.prop_beam_splitter(0, pa, None, pc, pe, 2, out, 16, 1, None) == -4
+    assert lib.prop_beam_splitter(0, pa, None, None, pc, 2, out, 16, 1, None) == -1
+    assert lib.prop_beam_splitter(0, pa, None, pc, pc, 2, out, 0, 1, None) == 0    # nothing to do
+    assert lib.prop_beam_splitter_adjoint(0, pa, None, None, None, None, None, 2, out, None, 16, 1, None) == -1
+    # per-item wave plates: missing parameters, forward inputs needed for the gradient
+    assert lib.prop_waveplate_batched(0, fake, fake, out, out, None, 16, 1, None) == -1
+    assert lib.prop_waveplate_batched_adjoint(0, fake, fake, None, None, out, None, fake, out, 16, 1, None) == -1
+    assert lib.prop_modulate_adjoint(0, fake, fake, out, 10, 2, 3, None) == -2
 
 
 def test_lengths_and_sampling(lib):

@@ -126,6 +126,36 @@ def test_waveplate_batched_vs_oracle(lp, kind):
         assert abs(float(dp[bi, 1]) - dt) <= tol * max(1.0, abs(dt))
 
 
+@pytest.mark.parametrize("kind", ["c64", "c128"])
+def test_modulate_adjoint_and_shared_input_waveplate(lp, kind):
+    """SLM adjoint g exp(-i phi), per set and shared phases; the wave-plate
+    adjoint for one field fed to both components (g_A = g_ex + g_ey)."""
+    import torch
+    rng = np.random.default_rng(11)
+    B, ny, nx = 3, 17, 23
+    g = cast(workloads.random_field(rng, (B, ny, nx)), kind)
+    rdt = torch.float32 if kind == "c64" else torch.float64
+    for shared in (False, True):
+        phi = rng.uniform(-math.pi, math.pi, (1 if shared else B, ny, nx))
+        if kind == "c64":
+            phi = phi.astype(np.float32).astype(np.float64)
+        out = lp.prop_modulate_adjoint(dev(g, kind), torch.tensor(phi, dtype=rdt, device="cuda"))
+        want = g * np.exp(-1j * phi)
+        assert rel_l2(host(out), want) < TOL[kind] * 5
+    a = cast(workloads.random_field(rng, (B, ny, nx)), kind)
+    gx, gy = (cast(workloads.random_field(rng, (B, ny, nx)), kind) for _ in range(2))
+    params = np.array([[0.4, -1.0], [math.pi, 0.25], [2.0, 1.3]])
+    pt = torch.tensor(params, device="cuda")
+    ga, none, dp = lp.prop_waveplate_batched_adjoint(dev(gx, kind), dev(gy, kind), dev(a, kind), dev(a, kind), pt,
+                                                     shared_input=True)
+    assert none is None
+    for bi in range(B):
+        rgx, rgy, de, dt = oracle.waveplate_adjoint(gx[bi], gy[bi], a[bi], a[bi], *params[bi])
+        assert rel_l2(host(ga)[bi], rgx + rgy) < TOL[kind] * 5
+        tol = 1e-6 if kind == "c64" else 1e-12
+        assert abs(float(dp[bi, 0]) - de) <= tol * max(1.0, abs(de))
+
+
 def _gpu_params(lp, lat, params, batch, kind):
     """The oracle's parameter set replicated over `batch` items, as GPU leaves."""
     import torch
