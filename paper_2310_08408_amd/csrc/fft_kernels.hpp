@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -193,7 +194,10 @@ struct RowCfg {
   static constexpr bool fits = CF::fits;
 };
 
-template <typename T, int DIR, class S, int C, bool HALF>
+// EXACT (with HALF): the valid length is exactly n/2 and the line count a
+// multiple of C, so no load or store needs a guard; the guards' branches
+// otherwise split every access into its own exec-masked block.
+template <typename T, int DIR, class S, int C, bool HALF, bool EXACT = false>
 __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) void k_rs_rows(
     const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int64_t w_bstride, int nrows, int n_io, T scale, int tiles,
     const cx<T>* __restrict__ tw, PhaseGrad<T> pg) {
@@ -203,7 +207,7 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
   const int b = id / tiles, tile = id - b * tiles;
   const int c = (int)(threadIdx.x % C), j = (int)(threadIdx.x / C);
   const int y = tile * C + c;
-  const bool valid = y < nrows;
+  const bool valid = EXACT || y < nrows;
   cx<T>* lds = smem + c * LS;
   const int64_t tst = (int64_t)nrows * kTile;  // elements between tiles
   const int64_t frow = ((int64_t)b * nrows + y) * n_io;
@@ -212,7 +216,7 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
   if constexpr (DIR < 0) {
     auto load = [&](int i) -> cx<T> {
       cx<T> v = czero<T>();
-      if (valid && i < n_io) v = in[frow + i];
+      if (valid && (EXACT || i < n_io)) v = in[frow + i];
       return v;
     };
     auto store = [&](int i, cx<T> v) {
@@ -226,7 +230,7 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
       return v;
     };
     auto store = [&](int i, cx<T> v) {
-      if (valid && i < n_io) {
+      if (valid && (EXACT || i < n_io)) {
         const cx<T> g = cscale(v, scale);
         if (out) out[frow + i] = g;
         if (pg.grad) pg.put(frow + i, g);
@@ -247,6 +251,11 @@ hipError_t launch_rs_rows_s(const cx<T>* in, cx<T>* out, int64_t w_bstride, int 
     const int tiles = (nrows + C - 1) / C;
     constexpr bool can_half = S::rad[0] % 2 == 0 && S::rad[S::nst - 1] % 2 == 0;
     if constexpr (can_half) {
+      if (2 * n_io == S::n && nrows % C == 0) {
+        hipLaunchKernelGGL((k_rs_rows<T, DIR, S, C, true, true>), dim3(tiles * batch), dim3(RC::threads), 0, s, in,
+                           out, w_bstride, nrows, n_io, scale, tiles, tw, pg);
+        return hipGetLastError();
+      }
       if (2 * n_io <= S::n) {
         hipLaunchKernelGGL((k_rs_rows<T, DIR, S, C, true>), dim3(tiles * batch), dim3(RC::threads), 0, s, in, out,
                            w_bstride, nrows, n_io, scale, tiles, tw, pg);
@@ -288,14 +297,29 @@ __device__ __forceinline__ cx<T> spec_at(const cx<T>* __restrict__ Sq, int kind,
   return h;
 }
 
+// A read-only table (kernel spectrum, twiddles) passed either as a
+// __restrict__ kernel argument -- the compiler may then treat its loads as
+// invariant and lift them across barriers, which hides their latency while
+// registers last -- or boxed in a struct, which keeps the loads where the
+// code issues them (for kernels whose lifted loads would spill).
+template <typename T> struct TableBox { const cx<T>* p; };
+template <typename T, bool BOX>
+using TableArg = std::conditional_t<BOX, TableBox<T>, const cx<T>* __restrict__>;
+template <typename T> __device__ __forceinline__ const cx<T>* table_ptr(TableBox<T> b) { return b.p; }
+template <typename T> __device__ __forceinline__ const cx<T>* table_ptr(const cx<T>* p) { return p; }
+
 // ------------------------------------------------------ RS column pass --
 // In place on columns kx of W: forward transform of the zero-padded column,
 // multiply by the kernel spectrum (conjugated for the adjoint), inverse
 // transform, keep the first n_valid rows.
-template <typename T, class S, int C, bool HALF>
+// EXACT: as for the row pass; its unguarded loads are issued early enough
+// by themselves, so the tables are boxed (lifting them too would spill).
+template <typename T, class S, int C, bool HALF, bool EXACT = false>
 __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) void k_rs_cols(cx<T>* W, int64_t bstride, int ncols,
-                                                            int n_valid, const cx<T>* __restrict__ Sq, int Mx,
-                                                            int conj_spec, int tiles, const cx<T>* __restrict__ tw) {
+                                                            int n_valid, TableArg<T, EXACT> Sq_, int Mx,
+                                                            int conj_spec, int tiles, TableArg<T, EXACT> tw_) {
+  const cx<T>* Sq = table_ptr<T>(Sq_);
+  const cx<T>* tw = table_ptr<T>(tw_);
   constexpr int LS = line_stride<S, C, true>();
   __shared__ cx<T> smem[C * LS];
   constexpr int My = S::n;
@@ -306,13 +330,13 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
   const int tile = id / nb, b = id - tile * nb;
   const int c = threadIdx.x % C, j = threadIdx.x / C;
   const int kx = tile * C + c;
-  const bool valid = kx < ncols;
+  const bool valid = EXACT || kx < ncols;
   cx<T>* lds = smem + c * LS;
   cx<T>* col = W + b * bstride + (int64_t)(kx >> kTileShift) * n_valid * kTile + (kx & (kTile - 1));
   const cx<T>* sq = Sq + (valid ? (int64_t)(kx >> 2) * (My / 2 + 1) * 4 + (kx & 3) : 0);
   auto load = [&](int i) -> cx<T> {
     cx<T> v = czero<T>();
-    if (valid && i < n_valid) v = load_stream(&col[i * kTile]);
+    if (valid && (EXACT || i < n_valid)) v = load_stream(&col[i * kTile]);
     return v;
   };
   auto mult = [&](int i, cx<T> v) -> cx<T> {
@@ -321,7 +345,7 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
     return conj_spec ? cmulc(v, h) : cmul(v, h);
   };
   auto store = [&](int i, cx<T> v) {
-    if (valid && i < n_valid) store_stream(&col[i * kTile], v);
+    if (valid && (EXACT || i < n_valid)) store_stream(&col[i * kTile], v);
   };
   conv_line<T, S, HALF, HALF>(lds, tw, j, load, mult, store);
 }
@@ -332,6 +356,11 @@ hipError_t launch_rs_cols_c(cx<T>* W, int64_t bstride, int ncols, int n_valid, c
   const int tiles = (ncols + C - 1) / C;
   constexpr bool can_half = S::rad[0] % 2 == 0 && S::rad[S::nst - 1] % 2 == 0;
   if constexpr (can_half) {
+    if (2 * n_valid == S::n && ncols % C == 0) {
+      hipLaunchKernelGGL((k_rs_cols<T, S, C, true, true>), dim3(tiles * batch), dim3(C * S::threads), 0, s, W,
+                         bstride, ncols, n_valid, TableBox<T>{Sq}, Mx, conj_spec ? 1 : 0, tiles, TableBox<T>{tw});
+      return hipGetLastError();
+    }
     if (2 * n_valid <= S::n) {
       hipLaunchKernelGGL((k_rs_cols<T, S, C, true>), dim3(tiles * batch), dim3(C * S::threads), 0, s, W, bstride,
                          ncols, n_valid, Sq, Mx, conj_spec ? 1 : 0, tiles, tw);
@@ -488,7 +517,7 @@ constexpr bool bluestein_interleaved() {
   return COL || tw_per_thread<T>();
 }
 
-template <typename T, bool COL, class S, int C, bool HALF>
+template <typename T, bool COL, class S, int C, bool HALF, bool EXACT = false>
 __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, bluestein_interleaved<T, COL>(), 1,
                                                             HALF ? (bluestein_interleaved<T, COL>() ? 4 : 3) : 2>())) void k_bluestein(const cx<T>* in, cx<T>* out, Lines li, Lines lo,
                                                               int nlines, int n_in, int n_out,
@@ -504,16 +533,16 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, bluestein_in
   const int c = ILV ? (int)(threadIdx.x % C) : (int)(threadIdx.x / S::threads);
   const int j = ILV ? (int)(threadIdx.x / C) : (int)(threadIdx.x % S::threads);
   const int l = tile * C + c;
-  const bool valid = l < nlines;
+  const bool valid = EXACT || l < nlines;
   cx<T>* lds = smem + c * LS;
   auto load = [&](int i) -> cx<T> {
     cx<T> v = czero<T>();
-    if (valid && i < n_in) v = cmul(in[line_off<COL>(li, b, l, i)], pre[i]);
+    if (valid && (EXACT || i < n_in)) v = cmul(in[line_off<COL>(li, b, l, i)], pre[i]);
     return v;
   };
   auto mult = [&](int i, cx<T> v) -> cx<T> { return cmul(v, chat[i]); };
   auto store = [&](int i, cx<T> v) {
-    if (valid && i < n_out) {
+    if (valid && (EXACT || i < n_out)) {
       const int64_t o = line_off<COL>(lo, b, l, i);
       const cx<T> g = cmul(v, post[i]);
       if (out) out[o] = g;
@@ -530,6 +559,11 @@ hipError_t launch_bluestein_c(const cx<T>* in, cx<T>* out, Lines li, Lines lo, i
   const int tiles = (nlines + C - 1) / C;
   constexpr bool can_half = S::rad[0] % 2 == 0 && S::rad[S::nst - 1] % 2 == 0;
   if constexpr (can_half) {
+    if (2 * n_in == S::n && 2 * n_out == S::n && nlines % C == 0) {
+      hipLaunchKernelGGL((k_bluestein<T, COL, S, C, true, true>), dim3(tiles * batch), dim3(C * S::threads), 0, s, in,
+                         out, li, lo, nlines, n_in, n_out, pre, chat, post, tiles, tw, pg);
+      return hipGetLastError();
+    }
     if (2 * n_in <= S::n && 2 * n_out <= S::n) {
       hipLaunchKernelGGL((k_bluestein<T, COL, S, C, true>), dim3(tiles * batch), dim3(C * S::threads), 0, s, in, out,
                          li, lo, nlines, n_in, n_out, pre, chat, post, tiles, tw, pg);
