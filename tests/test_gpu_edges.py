@@ -1,0 +1,132 @@
+"""Edge cases on the GPU against the FP64 oracle: the largest transform
+lengths (8192 per axis for RS; n_in + n_out - 1 = 8192 and 6144 for CZT,
+half-pruned and not), full-size 4096^2 RS at sampled pixels, and empty
+batches (paper: Methods, RS and CZT propagation; the limits are the
+library's, stated in its header)."""
+import sys
+import warnings
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from workloads import Grid
+from tests.conftest import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c64": 1e-5, "c128": 1e-12}
+
+
+@pytest.fixture(scope="module")
+def lp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2310_08408_amd as lp
+    lp.library()
+    return lp
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a, kind):
+    import torch
+    dt = torch.complex64 if kind == "c64" else torch.complex128
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dt).cuda()
+
+
+def cast(a, kind):
+    return np.asarray(a, np.complex64 if kind == "c64" else np.complex128).astype(np.complex128)
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.complex128)
+
+
+RS_STRIPS = [(Grid(4096, 3, 1e-6, 2e-6), 2, 633e-9, 3e-3),    # 8192 along x
+             (Grid(3, 4096, 2e-6, 1e-6), 1, 633e-9, 3e-3),    # 8192 along y
+             (Grid(3072, 2, 1e-6, 1e-6), 1, 500e-9, 2e-3)]    # 6144 along x
+
+
+@pytest.mark.parametrize("kind", ["c64", "c128"])
+@pytest.mark.parametrize("case", range(len(RS_STRIPS)))
+def test_rs_longest_transforms(lp, kind, case):
+    g, b, wl, z = RS_STRIPS[case]
+    rng = np.random.default_rng(case + 30)
+    u = cast(workloads.random_field(rng, (b, g.ny, g.nx)), kind)
+    v = cast(workloads.random_field(rng, (b, g.ny, g.nx)), kind)
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        out = host(lp.rs_propagate(dev(u, kind), g, wl, z))
+        back = host(lp.rs_adjoint(dev(v, kind), g, wl, z))
+    ef = rel_l2(out, oracle.rs_propagate(u, g, wl, z))
+    ea = rel_l2(back, oracle.rs_adjoint(v, g, wl, z))
+    say(f"rs {g.nx}x{g.ny} {kind}: transform {lp.prop_fft_length(2 * max(g.nx, g.ny) - 1)}, "
+        f"fwd {ef:.1e} adj {ea:.1e}")
+    assert ef < TOL[kind] and ea < TOL[kind]
+
+
+CZT_LONG = [(Grid(4096, 2, 1e-6, 1e-6), Grid(4097, 3, 2e-7, 1e-6), 1, 633e-9, 20e-3),   # L = 8192, not half
+            (Grid(4096, 3, 1e-6, 1e-6), Grid(4096, 2, 2e-7, 1e-6), 1, 633e-9, 20e-3),   # L = 8192, half
+            (Grid(2, 3072, 1e-6, 1e-6), Grid(3, 3073, 1e-6, 2e-7), 1, 600e-9, 20e-3)]   # L = 6144 along y
+
+
+@pytest.mark.parametrize("kind", ["c64", "c128"])
+@pytest.mark.parametrize("case", range(len(CZT_LONG)))
+def test_czt_longest_transforms(lp, kind, case):
+    gi, win, b, wl, z = CZT_LONG[case]
+    rng = np.random.default_rng(case + 40)
+    u = cast(workloads.random_field(rng, (b, gi.ny, gi.nx)), kind)
+    v = cast(workloads.random_field(rng, (b, win.ny, win.nx)), kind)
+    out = host(lp.czt_propagate(dev(u, kind), gi, win, wl, z))
+    back = host(lp.czt_adjoint(dev(v, kind), gi, win, wl, z))
+    ef = rel_l2(out, oracle.czt_propagate(u, gi, win, wl, z))
+    ea = rel_l2(back, oracle.czt_adjoint(v, gi, win, wl, z))
+    L = lp.prop_fft_length(max(gi.nx + win.nx, gi.ny + win.ny) - 1)
+    say(f"czt {gi.nx}x{gi.ny} -> {win.nx}x{win.ny} {kind}: L {L}, fwd {ef:.1e} adj {ea:.1e}")
+    assert ef < TOL[kind] and ea < TOL[kind]
+
+
+def test_rs_full_4096_sampled(lp):
+    """4096^2 (8192^2 padded), the largest RS grid: FP32 against the FP64
+    GPU path over the whole field, and FP64 at sampled pixels against the
+    oracle's direct sums."""
+    import torch
+    g = Grid.square(4096, 4096 * 2e-6)
+    wl, z = 633e-9, 40e-3
+    u = workloads.random_field(np.random.default_rng(5), (1, 4096, 4096)).astype(np.complex64).astype(np.complex128)
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        y64 = lp.rs_propagate(dev(u, "c128"), g, wl, z)
+        y32 = lp.rs_propagate(dev(u, "c64"), g, wl, z)
+    e = float(torch.linalg.vector_norm(y32.to(torch.complex128) - y64) / torch.linalg.vector_norm(y64))
+    pix = [(0, 0), (4095, 4095), (2048, 2048), (17, 3001), (3900, 250), (1024, 4000)]
+    got = np.array([complex(y64[0, l, m]) for l, m in pix])
+    ref = oracle.rs_at(u[0], g, wl, z, pix)
+    es = rel_l2(got, ref)
+    say(f"rs 4096^2: fp32 vs fp64 {e:.1e}; fp64 vs direct sums at {len(pix)} pixels {es:.1e}")
+    # FP64 bar: the kernel phase k r reaches 4e5 rad on this grid, so each
+    # implementation rounds every term's phase by ~k r eps = 4e-11 rad
+    k_r = 2 * np.pi / wl * np.hypot(np.hypot(4096 * 2e-6, 4096 * 2e-6), z)
+    assert e < 1e-5 and es < 2.5 * k_r * np.finfo(float).eps
+
+
+def test_empty_batches(lp):
+    """A batch of zero fields is a no-op that returns empty outputs."""
+    import torch
+    g = Grid(16, 12, 1e-6, 1e-6)
+    win = Grid(8, 8, 0.1e-6, 0.1e-6)
+    for dt in (torch.complex64, torch.complex128):
+        u = torch.empty((0, 12, 16), dtype=dt, device="cuda")
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore")
+            assert lp.rs_propagate(u, g, 500e-9, 1e-3).shape == (0, 12, 16)
+            assert lp.rs_adjoint(u, g, 500e-9, 1e-3).shape == (0, 12, 16)
+        assert lp.czt_propagate(u, g, win, 500e-9, 1e-3).shape == (0, 8, 8)
+        w = torch.empty((0, 8, 8), dtype=dt, device="cuda")
+        assert lp.czt_adjoint(w, g, win, 500e-9, 1e-3).shape == (0, 12, 16)
+    torch.cuda.synchronize()
