@@ -207,6 +207,18 @@ int prop_modulate_adjoint(prop_dtype t, const void* g_out, const void* phase, vo
  * [batch][npix]; accumulate != 0 adds to grad. */
 int prop_phase_grad(prop_dtype t, const void* g_u, const void* u, void* grad, int64_t npix,
                     int32_t batch, int32_t accumulate, void* stream);
+/* SLM gradient of a phase shared by the whole batch (phase_batch 1 in
+ * prop_modulate): grad[pix] = sum_b Im(g_u[b][pix] conj(u[b][pix])), the
+ * batch summed per pixel in a fixed order in FP64; real [npix];
+ * accumulate != 0 adds to grad. */
+int prop_phase_grad_sum(prop_dtype t, const void* g_u, const void* u, void* grad, int64_t npix,
+                        int32_t batch, int32_t accumulate, void* stream);
+/* out[k][b][.] = in[k][b][.] * scale[b] for k < nplanes (1..3), scale a
+ * device double [batch] (e.g. an upstream gradient applied to per-item
+ * gradient seeds).  in, out: host arrays of device pointers; out[k] may be
+ * in[k] (in place), other overlaps are rejected (PROP_EALIAS). */
+int prop_scale_items(prop_dtype t, const void* const* in, void* const* out, int32_t nplanes,
+                     const double* scale, int64_t npix, int32_t batch, void* stream);
 /* Wave plate / variable retarder (paper: Methods, variable retarders with
  * retardance eta and angle theta): (ox, oy) = J (ex, ey),
  * J = R(-theta) diag(1, e^{i eta}) R(theta). */

@@ -314,6 +314,41 @@ def prop_modulate_adjoint(g, phase, out=None):
     return out
 
 
+def prop_phase_grad_sum(g_u, u, grad=None, accumulate=False):
+    """sum over the batch of Im(g_u conj(u)): the gradient of a phase shared
+    by all batch items (real [ny, nx])."""
+    lib = library()
+    _dev(g_u), _dev(u)
+    npix = u.shape[-1] * u.shape[-2]
+    batch = u.numel() // npix
+    if grad is None:
+        grad = torch.empty(tuple(u.shape[-2:]), dtype=_real_dtype(u), device=u.device)
+    with torch.cuda.device(u.device):
+        st = lib.prop_phase_grad_sum(_dtype_code(u), _ptr(g_u.contiguous()), _ptr(u.contiguous()), _ptr(grad), npix,
+                                     batch, 1 if accumulate else 0, _stream(u))
+    _lib.check("prop_phase_grad_sum", st)
+    return grad
+
+
+def prop_scale_items(planes, scale, out=None):
+    """Each plane's batch item b times scale[b] (float64 [batch]); into new
+    planes, or into `out` (which may be `planes`: in place)."""
+    lib = library()
+    ref = planes[0]
+    npix = ref.shape[-1] * ref.shape[-2]
+    batch = ref.numel() // npix
+    scale = scale.to(torch.float64).contiguous()
+    if scale.numel() != batch:
+        raise ValueError("scale must have one entry per batch item")
+    planes = [t.contiguous() for t in planes]
+    out = [torch.empty_like(t) for t in planes] if out is None else list(out)
+    with torch.cuda.device(ref.device):
+        st = lib.prop_scale_items(_dtype_code(ref), _ptr_array(planes), _ptr_array(out), len(planes), _ptr(scale),
+                                  npix, batch, _stream(ref))
+    _lib.check("prop_scale_items", st)
+    return out
+
+
 def prop_phase_grad(g_u, u, grad=None, accumulate=False):
     """Im(g_u conj(u)) (real, same shape as u)."""
     lib = library()

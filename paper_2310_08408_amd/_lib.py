@@ -61,6 +61,8 @@ SIGNATURES = {
     "prop_source_radial": (c_int32, [c_int32, P, P, G, c_double, c_int32, P]),
     "prop_modulate": (c_int32, [c_int32, P, P, P, c_int64, c_int32, c_int32, P]),
     "prop_modulate_adjoint": (c_int32, [c_int32, P, P, P, c_int64, c_int32, c_int32, P]),
+    "prop_phase_grad_sum": (c_int32, [c_int32, P, P, P, c_int64, c_int32, c_int32, P]),
+    "prop_scale_items": (c_int32, [c_int32, P, P, c_int32, P, c_int64, c_int32, P]),
     "prop_phase_grad": (c_int32, [c_int32, P, P, P, c_int64, c_int32, c_int32, P]),
     "prop_waveplate": (c_int32, [c_int32, P, P, P, P, c_double, c_double, c_int64, c_int32, P]),
     "prop_waveplate_adjoint": (c_int32, [c_int32, P, P, P, P, P, P, c_double, c_double, P, c_int64, c_int32, P]),

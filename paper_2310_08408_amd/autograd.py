@@ -15,8 +15,8 @@ from __future__ import annotations
 import torch
 
 from . import (czt_adjoint, czt_grad_z, czt_propagate, prop_beam_splitter, prop_beam_splitter_adjoint,
-               prop_density_loss, prop_modulate, prop_modulate_adjoint, prop_phase_grad, prop_softmin,
-               prop_spot_loss, prop_waveplate,
+               prop_density_loss, prop_modulate, prop_modulate_adjoint, prop_phase_grad, prop_phase_grad_sum,
+               prop_scale_items, prop_softmin, prop_spot_loss, prop_waveplate,
                prop_waveplate_adjoint, prop_waveplate_batched, prop_waveplate_batched_adjoint, rs_adjoint,
                rs_grad_z, rs_propagate, vczt_adjoint, vczt_propagate, vrs_adjoint, vrs_propagate)
 
@@ -118,9 +118,10 @@ class Modulate(torch.autograd.Function):
         g_v = prop_modulate_adjoint(g, phase) if ctx.needs_input_grad[0] else None
         g_phi = None
         if ctx.needs_input_grad[1]:
-            g_phi = prop_phase_grad(g, u)
             if ctx.shared:
-                g_phi = g_phi.reshape((-1,) + tuple(phase.shape[-2:])).sum(0).reshape(phase.shape)
+                g_phi = prop_phase_grad_sum(g, u).reshape(phase.shape)
+            else:
+                g_phi = prop_phase_grad(g, u)
         return g_v, g_phi
 
 
@@ -211,10 +212,10 @@ class SpotLoss(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g):
-        gx, gy, gz = ctx.seeds
-        shape = (-1,) + (1,) * (gx.dim() - 1)
-        w = g.to(gx.real.dtype).reshape(shape)
-        return gx * w, gy * w, (gz * w if ctx.has_ez else None), None, None, None
+        # the seeds times the upstream gradient, into new planes (the kept
+        # seeds serve further backward passes)
+        planes = prop_scale_items([t for t in ctx.seeds if t is not None], g)
+        return planes[0], planes[1], (planes[2] if ctx.has_ez else None), None, None, None
 
 
 class DensityLoss(torch.autograd.Function):
@@ -232,11 +233,10 @@ class DensityLoss(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g):
-        scale = g.reshape(-1, 1, 1)
+        seeds = ctx.seeds
         out = []
-        for sd in ctx.seeds:
-            out.append((sd.reshape(scale.shape[0], sd.shape[-2], sd.shape[-1]) * scale.to(sd.real.dtype)).reshape(
-                sd.shape))
+        for k in range(0, len(seeds), 3):
+            out += prop_scale_items(seeds[k:k + 3], g)
         return (None, None, None, *out)
 
 

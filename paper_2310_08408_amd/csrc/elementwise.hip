@@ -187,6 +187,52 @@ hipError_t launch_phase_grad(const cx<T>* g, const cx<T>* u, T* grad, int64_t np
   return hipGetLastError();
 }
 
+// Phase gradient of a phase shared by the batch: grad[pix] (+)= sum over b
+// of Im(g conj(u)), the batch summed in a fixed order per pixel (FP64).
+template <typename T>
+__global__ void k_phase_grad_sum(const cx<T>* g, const cx<T>* u, T* grad, int64_t npix, int batch, int accumulate) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < npix; t += (int64_t)gridDim.x * blockDim.x) {
+    double acc = accumulate ? (double)grad[t] : 0.0;
+    for (int b = 0; b < batch; ++b) {
+      const cx<T> a = g[(int64_t)b * npix + t], v = u[(int64_t)b * npix + t];
+      acc += (double)a.y * (double)v.x - (double)a.x * (double)v.y;
+    }
+    grad[t] = T(acc);
+  }
+}
+template <typename T>
+hipError_t launch_phase_grad_sum(const cx<T>* g, const cx<T>* u, T* grad, int64_t npix, int batch, int accumulate,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL((k_phase_grad_sum<T>), dim3(ew_blocks(npix)), dim3(256), 0, s, g, u, grad, npix, batch,
+                     accumulate);
+  return hipGetLastError();
+}
+
+// out[k] item b = in[k] item b times the real scale[b] (device FP64); out
+// may be in (element by element).
+template <typename T>
+__global__ void k_scale_items(Planes in, Planes out, int nplanes, const double* scale, int64_t npix) {
+  const int b = blockIdx.y;
+  const T f = T(scale[b]);
+  const int64_t off = (int64_t)b * npix;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < npix; i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (k >= nplanes) break;
+      const cx<T> v = ((const cx<T>*)in.p[k])[off + i];
+      ((cx<T>*)out.p[k])[off + i] = mk<T>(v.x * f, v.y * f);
+    }
+  }
+}
+template <typename T>
+hipError_t launch_scale_items(const Planes& in, const Planes& out, int nplanes, const double* scale, int64_t npix,
+                              int batch, hipStream_t s) {
+  const int64_t want = std::max<int64_t>(8, 4096 / std::max(batch, 1));
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>((npix + 255) / 256, want));
+  hipLaunchKernelGGL((k_scale_items<T>), dim3(nb, batch), dim3(256), 0, s, in, out, nplanes, scale, npix);
+  return hipGetLastError();
+}
+
 template <typename T>
 __global__ void k_source_gaussian(cx<T>* out, int nx, int ny, double dx, double dy, double cx0, double cy0,
                                   double w0, double amp, double f, double k, int batch) {
@@ -1211,6 +1257,9 @@ hipError_t launch_spot_loss(const cx<T>* ex, const cx<T>* ey, const cx<T>* ez, i
                                                 double, double, double, double, double, int, int64_t, hipStream_t); \
   template hipError_t launch_modulate<T>(const cx<T>*, const T*, cx<T>*, int64_t, int, int64_t, hipStream_t, bool); \
   template hipError_t launch_phase_grad<T>(const cx<T>*, const cx<T>*, T*, int64_t, int, int, hipStream_t);         \
+  template hipError_t launch_phase_grad_sum<T>(const cx<T>*, const cx<T>*, T*, int64_t, int, int, hipStream_t);     \
+  template hipError_t launch_scale_items<T>(const Planes&, const Planes&, int, const double*, int64_t, int,     \
+                                            hipStream_t);                                                           \
   template hipError_t launch_source_gaussian<T>(cx<T>*, int, int, double, double, double, double, double, double,  \
                                                 double, double, int, hipStream_t);                                  \
   template hipError_t launch_source_radial<T>(cx<T>*, cx<T>*, int, int, double, double, double, double, double,    \

@@ -181,6 +181,14 @@ hipError_t launch_jones_items_grad(const cx<T>* gx, const cx<T>* gy, const cx<T>
 struct Planes {
   const void* p[3];
 };
+// grad[pix] (+)= sum_b Im(g conj(u)) (a phase shared by the batch).
+template <typename T>
+hipError_t launch_phase_grad_sum(const cx<T>* g, const cx<T>* u, T* grad, int64_t npix, int batch, int accumulate,
+                                 hipStream_t s);
+// out[k][b] = in[k][b] * scale[b] (device FP64), k < nplanes <= 3.
+template <typename T>
+hipError_t launch_scale_items(const Planes& in, const Planes& out, int nplanes, const double* scale, int64_t npix,
+                              int batch, hipStream_t s);
 // Beam splitter with mixing angle alpha[b] (device doubles) per item.
 template <typename T>
 hipError_t launch_beam_splitter(const Planes& a, const Planes& b, const Planes& c, const Planes& d, int ncomp,

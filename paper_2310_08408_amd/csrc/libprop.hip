@@ -1521,6 +1521,59 @@ int prop_phase_grad(prop_dtype t, const void* g_u, const void* u, void* grad, in
   return PROP_OK;
 }
 
+// The planes of one port: all ncomp entries of a given array must be set.
+static int port_planes(const void* const* arr, int ncomp, size_t bytes, Planes* out, std::vector<Span>* spans) {
+  *out = Planes{{nullptr, nullptr, nullptr}};
+  if (!arr) return PROP_OK;
+  for (int k = 0; k < ncomp; ++k) {
+    if (!arr[k]) return PROP_ENULL;
+    out->p[k] = arr[k];
+    spans->push_back({arr[k], bytes});
+  }
+  return PROP_OK;
+}
+
+int prop_phase_grad_sum(prop_dtype t, const void* g_u, const void* u, void* grad, int64_t npix, int32_t batch,
+                        int32_t accumulate, void* stream) {
+  if (t != PROP_C64 && t != PROP_C128) return PROP_EPARAM;
+  if (npix < 0 || batch < 0) return PROP_ESHAPE;
+  if (npix == 0) return PROP_OK;
+  if (!grad || (batch > 0 && (!g_u || !u))) return PROP_ENULL;
+  const size_t b = (size_t)npix * batch * esize(t);
+  LP_RET(check_alias({{g_u, b}, {u, b}}, {{grad, (size_t)npix * esize(t) / 2}}));
+  const hipStream_t s = (hipStream_t)stream;
+  LP_TRY(t == PROP_C64 ? launch_phase_grad_sum<float>((const cx<float>*)g_u, (const cx<float>*)u, (float*)grad, npix,
+                                                      batch, accumulate, s)
+                       : launch_phase_grad_sum<double>((const cx<double>*)g_u, (const cx<double>*)u, (double*)grad,
+                                                       npix, batch, accumulate, s));
+  return PROP_OK;
+}
+
+int prop_scale_items(prop_dtype t, const void* const* in, void* const* out, int32_t nplanes, const double* scale,
+                     int64_t npix, int32_t batch, void* stream) {
+  if (t != PROP_C64 && t != PROP_C128) return PROP_EPARAM;
+  if (nplanes < 1 || nplanes > 3 || npix < 0 || batch < 0) return PROP_ESHAPE;
+  if (npix == 0 || batch == 0) return PROP_OK;
+  if (!in || !out || !scale) return PROP_ENULL;
+  const size_t bytes = (size_t)npix * batch * esize(t);
+  std::vector<Span> ins = {{scale, 8 * (size_t)batch}}, outs;
+  Planes pi, po;
+  LP_RET(port_planes(in, nplanes, bytes, &pi, &ins));
+  LP_RET(port_planes((const void* const*)out, nplanes, bytes, &po, &outs));
+  // plane k may be written in place; any other overlap is rejected
+  for (int k = 0; k < nplanes; ++k) {
+    for (int m = 0; m < nplanes; ++m)
+      if (!(m == k && out[k] == in[k]) && overlap(out[k], bytes, in[m], bytes)) return PROP_EALIAS;
+    if (overlap(out[k], bytes, scale, 8 * (size_t)batch)) return PROP_EALIAS;
+    for (int m = k + 1; m < nplanes; ++m)
+      if (overlap(out[k], bytes, out[m], bytes)) return PROP_EALIAS;
+  }
+  const hipStream_t s = (hipStream_t)stream;
+  LP_TRY(t == PROP_C64 ? launch_scale_items<float>(pi, po, nplanes, scale, npix, batch, s)
+                       : launch_scale_items<double>(pi, po, nplanes, scale, npix, batch, s));
+  return PROP_OK;
+}
+
 int prop_waveplate(prop_dtype t, const void* ex, const void* ey, void* ox, void* oy, double eta, double theta,
                    int64_t npix, int32_t batch, void* stream) {
   if (t != PROP_C64 && t != PROP_C128) return PROP_EPARAM;
@@ -1632,18 +1685,6 @@ int prop_waveplate_batched_adjoint(prop_dtype t, const void* gx, const void* gy,
              : launch_jones_items_grad<double>((const cx<double>*)gx, (const cx<double>*)gy, (const cx<double>*)ex,
                                                (const cx<double>*)ey, params, dparams, (double*)wb.p, nblk, npix,
                                                batch, s));
-  return PROP_OK;
-}
-
-// The planes of one port: all ncomp entries of a given array must be set.
-static int port_planes(const void* const* arr, int ncomp, size_t bytes, Planes* out, std::vector<Span>* spans) {
-  *out = Planes{{nullptr, nullptr, nullptr}};
-  if (!arr) return PROP_OK;
-  for (int k = 0; k < ncomp; ++k) {
-    if (!arr[k]) return PROP_ENULL;
-    out->p[k] = arr[k];
-    spans->push_back({arr[k], bytes});
-  }
   return PROP_OK;
 }
 

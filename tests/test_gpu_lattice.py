@@ -156,6 +156,41 @@ def test_modulate_adjoint_and_shared_input_waveplate(lp, kind):
         assert abs(float(dp[bi, 0]) - de) <= tol * max(1.0, abs(de))
 
 
+@pytest.mark.parametrize("kind", ["c64", "c128"])
+def test_shared_phase_gradient_and_item_scaling(lp, kind):
+    """The gradient of an SLM phase shared by the batch (summed over items,
+    also through the autograd Modulate with a one-item phase), and the
+    per-item scaling of gradient seeds."""
+    import torch
+    from paper_2310_08408_amd.autograd import Modulate
+    rng = np.random.default_rng(12)
+    B, ny, nx = 5, 19, 13
+    g = cast(workloads.random_field(rng, (B, ny, nx)), kind)
+    u = cast(workloads.random_field(rng, (B, ny, nx)), kind)
+    want = sum(oracle.phase_grad(g[b], u[b]) for b in range(B))
+    got = lp.prop_phase_grad_sum(dev(g, kind), dev(u, kind)).cpu().numpy()
+    assert rel_l2(got, want) < (1e-6 if kind == "c64" else 1e-14)
+    # through autograd: L = Re sum conj(w) (v exp(i phi)), one phi for all items
+    rdt = torch.float32 if kind == "c64" else torch.float64
+    v = cast(workloads.random_field(rng, (B, ny, nx)), kind)
+    w = cast(workloads.random_field(rng, (B, ny, nx)), kind)
+    phi = rng.uniform(-np.pi, np.pi, (1, ny, nx))
+    pt = torch.tensor(phi, dtype=rdt, device="cuda", requires_grad=True)
+    out = Modulate.apply(dev(v, kind), pt)
+    (torch.conj(dev(w, kind)) * out).real.sum().backward()
+    ref = sum(oracle.phase_grad(w[b], oracle.modulate(v[b], phi[0])) for b in range(B))
+    assert rel_l2(pt.grad.cpu().numpy()[0], ref) < (1e-5 if kind == "c64" else 1e-13)
+    # seeds times a per-item scale, into new planes and in place
+    planes = [dev(cast(workloads.random_field(rng, (B, ny, nx)), kind), kind) for _ in range(3)]
+    before = [host(t) for t in planes]
+    sc = rng.uniform(-2, 2, B)
+    scaled = lp.prop_scale_items(planes, torch.tensor(sc, device="cuda"))
+    lp.prop_scale_items(planes[:2], torch.tensor(sc, device="cuda"), out=planes[:2])
+    for t, b0 in zip(scaled + planes[:2], before + before[:2]):
+        assert rel_l2(host(t), b0 * sc[:, None, None]) < (1e-7 if kind == "c64" else 1e-15)
+    assert np.array_equal(host(planes[2]), before[2])
+
+
 def _gpu_params(lp, lat, params, batch, kind):
     """The oracle's parameter set replicated over `batch` items, as GPU leaves."""
     import torch
