@@ -274,6 +274,44 @@ def test_lattice_fp64_vs_oracle(lp, variant):
         assert v < 1e-9, (k, v)
 
 
+def test_lattice_distinct_items_fp64_vs_oracle(lp):
+    """Two batch items with different phases, wave plates and splitter
+    angles (shared distances) in one launch sequence: each item's objective
+    and gradients against its own oracle run."""
+    import torch
+    from paper_2310_08408_amd.lattice import Lattice, LatticeParams
+    runs = [small_lattice(3, units="some"), small_lattice(4, units="some")]
+    R, C, g, win, beams, p0, kw = runs[0]
+    p1 = dict(runs[1][5])
+    p1["z1"], p1["z2"], p1["unit"] = p0["z1"], p0["z2"], p0["unit"]   # distances are shared by the batch
+    lat = Lattice(R, C, g, win, kw["na"], kw["f"], p0["unit"], comps=kw["comps"], eps=kw["eps"],
+                  beta_sted=kw["beta_sted"], beta_soft=kw["beta_soft"])
+
+    def leaf(a):
+        return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda").requires_grad_(True)
+
+    p = LatticeParams()
+    p.phi = [tuple(leaf(np.stack([p0["phi"][k][c], p1["phi"][k][c]])) for c in range(2))
+             for k in range(len(p0["phi"]))]
+    p.wp = [leaf(np.stack([p0["wp"][k], p1["wp"][k]])) for k in range(len(p0["wp"]))]
+    p.alpha = leaf(np.stack([np.asarray(p0["alpha"]).ravel(), np.asarray(p1["alpha"]).ravel()], axis=1))
+    p.z1 = [float(z) for z in p0["z1"]]
+    p.z2 = [float(z) for z in p0["z2"]]
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        val, _ = lat.forward(_gpu_beams(beams, 2, "c128"), p)
+        val.sum().backward()
+    for b, pb in enumerate((p0, p1)):
+        obj, _, grads = oracle.lattice_objective(R, C, g, win, beams, pb, **kw)
+        assert abs(float(val.detach()[b]) - obj) <= 1e-10 * abs(obj)
+        gphi = np.stack([np.stack([gr(t)[b] for t in pair]) for pair in p.phi])
+        e = (rel_l2(gphi, grads["phi"]), rel_l2(np.stack([gr(w)[b] for w in p.wp]), grads["wp"]),
+             rel_l2(p.alpha.grad.cpu().numpy()[:, b].reshape(R, C), grads["alpha"]))
+        say(f"lattice item {b}: objective {float(val.detach()[b]):.6e}; grad rel-L2 phi/wp/alpha "
+            + " ".join(f"{x:.1e}" for x in e))
+        assert max(e) < 1e-9
+
+
 def test_lattice_3x3_fp32_vs_fp64_and_timing(lp):
     """3 x 3 lattice with a building unit on every one of its 24 links (the
     element counts of the paper's large-scale setup: 9 splitters, 24
