@@ -297,11 +297,11 @@ __device__ __forceinline__ cx<T> spec_at(const cx<T>* __restrict__ Sq, int kind,
   return h;
 }
 
-// A read-only table (kernel spectrum, twiddles) passed either as a
-// __restrict__ kernel argument -- the compiler may then treat its loads as
-// invariant and lift them across barriers, which hides their latency while
-// registers last -- or boxed in a struct, which keeps the loads where the
-// code issues them (for kernels whose lifted loads would spill).
+// A read-only table (kernel spectrum, twiddles) boxed in a struct.  Passed
+// as a __restrict__ pointer instead, the compiler may treat its loads as
+// invariant and lift them across barriers: that hides their latency while
+// registers last, and spills where they do not.  Boxed, the loads stay where
+// the code issues them.
 template <typename T> struct TableBox { const cx<T>* p; };
 template <typename T, bool BOX>
 using TableArg = std::conditional_t<BOX, TableBox<T>, const cx<T>* __restrict__>;
@@ -312,8 +312,8 @@ template <typename T> __device__ __forceinline__ const cx<T>* table_ptr(const cx
 // In place on columns kx of W: forward transform of the zero-padded column,
 // multiply by the kernel spectrum (conjugated for the adjoint), inverse
 // transform, keep the first n_valid rows.
-// EXACT: as for the row pass; its unguarded loads are issued early enough
-// by themselves, so the tables are boxed (lifting them too would spill).
+// EXACT: as for the row pass.  Its unguarded loads are scheduled early by
+// themselves, so the tables come boxed (lifting them as well would spill).
 template <typename T, class S, int C, bool HALF, bool EXACT = false>
 __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) void k_rs_cols(cx<T>* W, int64_t bstride, int ncols,
                                                             int n_valid, TableArg<T, EXACT> Sq_, int Mx,
@@ -350,6 +350,82 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
   conv_line<T, S, HALF, HALF>(lds, tw, j, load, mult, store);
 }
 
+// Exact-half column pass (valid length n/2, column count a multiple of C)
+// in persistent form, for FP32 schedules whose first and last radix are
+// equal and at most 16 (elsewhere the prefetch registers would spill): one workgroup per CU walks a contiguous run of
+// (column tile, batch item) work items -- batch-minor, so consecutive items
+// share their spectrum lines -- and loads the next item's input while it
+// transforms the current one.  No access needs a guard; the tables are
+// boxed (lifted table loads would spill next to the prefetch).
+template <typename T, class S, int C>
+__global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) void k_rs_cols_persist(
+    cx<T>* W, int64_t bstride, int n_valid, TableBox<T> Sq_, int conj_spec, int nb, int items, int per,
+    TableBox<T> tw_) {
+  const cx<T>* Sq = Sq_.p;
+  const cx<T>* tw = tw_.p;
+  constexpr int LS = line_stride<S, C, true>();
+  __shared__ cx<T> smem[C * LS];
+  constexpr int My = S::n, nr0 = S::n / S::rad[0], RIN = S::rad[0] / 2;
+  const int chunk = xcd_remap(blockIdx.x, gridDim.x);
+  const int first = chunk * per, last = min(first + per, items);
+  const int c = threadIdx.x % C, j = threadIdx.x / C;
+  cx<T>* lds = smem + c * LS;
+  auto colp = [&](int id) -> cx<T>* {
+    const int tile = id / nb, b = id - tile * nb;
+    const int kx = tile * C + c;
+    return W + b * bstride + (int64_t)(kx >> kTileShift) * n_valid * kTile + (kx & (kTile - 1));
+  };
+  // threads j >= nr0 exist when a later radix is smaller than the first;
+  // they take no part in the first stage and load nothing
+  const bool loader = j < nr0;
+  cx<T> nxt[RIN];
+  if (loader && first < last) {
+    cx<T>* col = colp(first);
+#pragma unroll
+    for (int r = 0; r < RIN; ++r) nxt[r] = load_stream(&col[(j + r * nr0) * kTile]);
+  }
+  for (int id = first; id < last; ++id) {
+    cx<T> cur[RIN];
+#pragma unroll
+    for (int r = 0; r < RIN; ++r) cur[r] = nxt[r];
+    if (loader && id + 1 < last) {
+      cx<T>* coln = colp(id + 1);
+#pragma unroll
+      for (int r = 0; r < RIN; ++r) nxt[r] = load_stream(&coln[(j + r * nr0) * kTile]);
+    }
+    const int kx = (id / nb) * C + c;
+    cx<T>* col = colp(id);
+    const cx<T>* sq = Sq + (int64_t)(kx >> 2) * (My / 2 + 1) * 4 + (kx & 3);
+    // the first stage asks for i = j + r nr0, r < RIN: register r of cur
+    auto load = [&](int i) -> cx<T> { return cur[(i - j) / nr0]; };
+    auto mult = [&](int i, cx<T> v) -> cx<T> {
+      const cx<T> h = sq[min(i, My - i) * 4];
+      return conj_spec ? cmulc(v, h) : cmul(v, h);
+    };
+    auto store = [&](int i, cx<T> v) { store_stream(&col[i * kTile], v); };
+    conv_line<T, S, true, true>(lds, tw, j, load, mult, store);
+  }
+}
+
+// Compute units of the current device (cached per device).
+inline int cu_count() {
+  static int counts[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!counts[dev]) {
+    int v = 0;
+    counts[dev] = (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+                      ? v
+                      : 256;
+  }
+  return counts[dev];
+}
+
+template <typename T, class S>
+constexpr bool cols_persistent() {
+  return tw_per_thread<T>() && conv_in_registers<S>() && S::rad[0] <= 16;
+}
+
 template <typename T, class S, int C>
 hipError_t launch_rs_cols_c(cx<T>* W, int64_t bstride, int ncols, int n_valid, const cx<T>* Sq, int Mx, bool conj_spec,
                             int batch, const cx<T>* tw, hipStream_t s) {
@@ -357,8 +433,18 @@ hipError_t launch_rs_cols_c(cx<T>* W, int64_t bstride, int ncols, int n_valid, c
   constexpr bool can_half = S::rad[0] % 2 == 0 && S::rad[S::nst - 1] % 2 == 0;
   if constexpr (can_half) {
     if (2 * n_valid == S::n && ncols % C == 0) {
-      hipLaunchKernelGGL((k_rs_cols<T, S, C, true, true>), dim3(tiles * batch), dim3(C * S::threads), 0, s, W,
-                         bstride, ncols, n_valid, TableBox<T>{Sq}, Mx, conj_spec ? 1 : 0, tiles, TableBox<T>{tw});
+      if constexpr (cols_persistent<T, S>()) {
+        // one workgroup per CU (the LDS footprint allows no more), each a
+        // contiguous run of `per` items
+        const int items = tiles * batch;
+        const int per = (items + cu_count() - 1) / cu_count();
+        const int groups = (items + per - 1) / per;
+        hipLaunchKernelGGL((k_rs_cols_persist<T, S, C>), dim3(groups), dim3(C * S::threads), 0, s, W, bstride,
+                           n_valid, TableBox<T>{Sq}, conj_spec ? 1 : 0, batch, items, per, TableBox<T>{tw});
+      } else {
+        hipLaunchKernelGGL((k_rs_cols<T, S, C, true, true>), dim3(tiles * batch), dim3(C * S::threads), 0, s, W,
+                           bstride, ncols, n_valid, TableBox<T>{Sq}, Mx, conj_spec ? 1 : 0, tiles, TableBox<T>{tw});
+      }
       return hipGetLastError();
     }
     if (2 * n_valid <= S::n) {
