@@ -78,6 +78,20 @@ __device__ __forceinline__ int xcd_remap(int i, int nb) {
   return x * q + min(x, r) + (i >> 3);
 }
 
+// Compute units of the current device (cached per device).
+inline int cu_count() {
+  static int counts[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!counts[dev]) {
+    int v = 0;
+    counts[dev] = (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+                      ? v
+                      : 256;
+  }
+  return counts[dev];
+}
+
 // Streaming accesses without cache retention (non-temporal): for passes in
 // which each element is touched once and one workgroup consumes whole
 // lines, so that the transform's twiddle tables stay cached instead.  Not
@@ -176,6 +190,17 @@ hipError_t launch_fft_lines(int n, bool col, const cx<T>* in, cx<T>* out, Lines 
   }
 }
 
+// A read-only table (kernel spectrum, twiddles) boxed in a struct.  Passed
+// as a __restrict__ pointer instead, the compiler may treat its loads as
+// invariant and lift them across barriers: that hides their latency while
+// registers last, and spills where they do not.  Boxed, the loads stay where
+// the code issues them.
+template <typename T> struct TableBox { const cx<T>* p; };
+template <typename T, bool BOX>
+using TableArg = std::conditional_t<BOX, TableBox<T>, const cx<T>* __restrict__>;
+template <typename T> __device__ __forceinline__ const cx<T>* table_ptr(TableBox<T> b) { return b.p; }
+template <typename T> __device__ __forceinline__ const cx<T>* table_ptr(const cx<T>* p) { return p; }
+
 // ------------------------------------------------------ RS row passes --
 // Forward (DIR = -1): row y of a contiguous field, zero-padded from n_io to
 // n, transformed into the tiled workspace.  Inverse (DIR = +1): workspace
@@ -240,6 +265,53 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
   }
 }
 
+// Forward exact-half row pass in persistent form (FP32 tables in per-thread
+// runs, first radix <= 16): one workgroup per CU walks a contiguous run of
+// (batch item, row tile) items and loads the next item's row segment into
+// registers while it transforms the current one.  The engine reads the half
+// input as elements j + r n/R0 (r < R0/2) of the threads j < n/R0 only, so
+// those threads alone prefetch, each its own elements.
+template <typename T, class S, int C>
+__global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) void k_rs_rows_fwd_persist(
+    const cx<T>* in, cx<T>* out, int64_t w_bstride, int nrows, int n_io, int tiles, int items, int per,
+    TableBox<T> tw_) {
+  const cx<T>* tw = tw_.p;
+  constexpr int LS = line_stride<S, C, true>();
+  __shared__ cx<T> smem[C * LS];
+  constexpr int nr0 = S::n / S::rad[0], RIN = S::rad[0] / 2;
+  const int chunk = xcd_remap(blockIdx.x, gridDim.x);
+  const int first = chunk * per, last = min(first + per, items);
+  const int c = (int)(threadIdx.x % C), j = (int)(threadIdx.x / C);
+  cx<T>* lds = smem + c * LS;
+  const int64_t tst = (int64_t)nrows * kTile;
+  const bool loader = j < nr0;
+  auto frow = [&](int id) -> int64_t {
+    const int b = id / tiles, y = (id - b * tiles) * C + c;
+    return ((int64_t)b * nrows + y) * n_io;
+  };
+  cx<T> nxt[RIN];
+  if (loader && first < last) {
+    const cx<T>* src = in + frow(first);
+#pragma unroll
+    for (int r = 0; r < RIN; ++r) nxt[r] = src[j + r * nr0];
+  }
+  for (int id = first; id < last; ++id) {
+    cx<T> cur[RIN];
+#pragma unroll
+    for (int r = 0; r < RIN; ++r) cur[r] = nxt[r];
+    if (loader && id + 1 < last) {
+      const cx<T>* src = in + frow(id + 1);
+#pragma unroll
+      for (int r = 0; r < RIN; ++r) nxt[r] = src[j + r * nr0];
+    }
+    const int b = id / tiles, y = (id - b * tiles) * C + c;
+    const int64_t wrow = b * w_bstride + (int64_t)y * kTile;
+    auto load = [&](int i) -> cx<T> { return cur[(i - j) / nr0]; };
+    auto store = [&](int i, cx<T> v) { out[wrow + (int64_t)(i >> kTileShift) * tst + (i & (kTile - 1))] = v; };
+    fft_line<T, -1, S, true, false>(lds, tw, j, load, store);
+  }
+}
+
 template <typename T, int DIR, class S>
 hipError_t launch_rs_rows_s(const cx<T>* in, cx<T>* out, int64_t w_bstride, int nrows, int n_io, T scale, int batch,
                             const cx<T>* tw, hipStream_t s, PhaseGrad<T> pg) {
@@ -252,8 +324,16 @@ hipError_t launch_rs_rows_s(const cx<T>* in, cx<T>* out, int64_t w_bstride, int 
     constexpr bool can_half = S::rad[0] % 2 == 0 && S::rad[S::nst - 1] % 2 == 0;
     if constexpr (can_half) {
       if (2 * n_io == S::n && nrows % C == 0) {
-        hipLaunchKernelGGL((k_rs_rows<T, DIR, S, C, true, true>), dim3(tiles * batch), dim3(RC::threads), 0, s, in,
-                           out, w_bstride, nrows, n_io, scale, tiles, tw, pg);
+        if constexpr (DIR < 0 && tw_per_thread<T>() && S::rad[0] <= 16) {
+          const int items = tiles * batch;
+          const int per = (items + cu_count() - 1) / cu_count();
+          const int groups = (items + per - 1) / per;
+          hipLaunchKernelGGL((k_rs_rows_fwd_persist<T, S, C>), dim3(groups), dim3(RC::threads), 0, s, in, out,
+                             w_bstride, nrows, n_io, tiles, items, per, TableBox<T>{tw});
+        } else {
+          hipLaunchKernelGGL((k_rs_rows<T, DIR, S, C, true, true>), dim3(tiles * batch), dim3(RC::threads), 0, s,
+                             in, out, w_bstride, nrows, n_io, scale, tiles, tw, pg);
+        }
         return hipGetLastError();
       }
       if (2 * n_io <= S::n) {
@@ -296,17 +376,6 @@ __device__ __forceinline__ cx<T> spec_at(const cx<T>* __restrict__ Sq, int kind,
   if (kind == 2 && ky > My / 2) { h.x = -h.x; h.y = -h.y; }
   return h;
 }
-
-// A read-only table (kernel spectrum, twiddles) boxed in a struct.  Passed
-// as a __restrict__ pointer instead, the compiler may treat its loads as
-// invariant and lift them across barriers: that hides their latency while
-// registers last, and spills where they do not.  Boxed, the loads stay where
-// the code issues them.
-template <typename T> struct TableBox { const cx<T>* p; };
-template <typename T, bool BOX>
-using TableArg = std::conditional_t<BOX, TableBox<T>, const cx<T>* __restrict__>;
-template <typename T> __device__ __forceinline__ const cx<T>* table_ptr(TableBox<T> b) { return b.p; }
-template <typename T> __device__ __forceinline__ const cx<T>* table_ptr(const cx<T>* p) { return p; }
 
 // ------------------------------------------------------ RS column pass --
 // In place on columns kx of W: forward transform of the zero-padded column,
@@ -405,20 +474,6 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
     auto store = [&](int i, cx<T> v) { store_stream(&col[i * kTile], v); };
     conv_line<T, S, true, true>(lds, tw, j, load, mult, store);
   }
-}
-
-// Compute units of the current device (cached per device).
-inline int cu_count() {
-  static int counts[64] = {};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-  if (!counts[dev]) {
-    int v = 0;
-    counts[dev] = (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-                      ? v
-                      : 256;
-  }
-  return counts[dev];
 }
 
 template <typename T, class S>
