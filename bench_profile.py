@@ -26,10 +26,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 512 * 1024 * 1024
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
-# bench.py pass name -> kernel-name prefix of the FP32 launch it times
+# bench.py pass name -> kernel-name prefix(es) of the FP32 launch it times
+# (exact-half shapes run the persistent forms of the row and column passes)
 PASS_KERNELS = {
-    "rs_rows_fwd": "void lp::k_rs_rows<float, -1,",
-    "rs_cols": "void lp::k_rs_cols<float,",
+    "rs_rows_fwd": ("void lp::k_rs_rows<float, -1,", "void lp::k_rs_rows_fwd_persist<float,"),
+    "rs_cols": ("void lp::k_rs_cols<float,", "void lp::k_rs_cols_persist<float,"),
     "rs_rows_inv": "void lp::k_rs_rows<float, 1,",
     "czt_rows": "void lp::k_bluestein<float, false,",
     "czt_cols": "void lp::k_bluestein<float, true,",
