@@ -125,6 +125,46 @@ struct PhaseGrad {
   }
 };
 
+// The phase-gradient epilogue of an exact-half line pass whose last stage
+// (radix RL) stores outputs j + r n/RL, r < RL/2: the field values it needs
+// and the gradient it accumulates into are loaded when the kernel starts, so
+// their HBM latency overlaps the transform instead of stalling every store
+// at the end.  FP32 with a first radix of at most 16 only: there the
+// registers fit beside the transform.
+template <typename T, class S, bool EXACT_HALF>
+constexpr bool pg_preload() {
+  return EXACT_HALF && sizeof(T) == 4 && S::rad[0] <= 16;
+}
+template <typename T, class S, bool ON>
+struct PhaseGradPre {
+  static constexpr int RL = S::rad[S::nst - 1], nr = S::n / RL, P = ON ? RL / 2 : 1;
+  cx<T> u[P];
+  T g[P];
+  template <class Off>
+  __device__ __forceinline__ void load(const PhaseGrad<T>& pg, int j, Off off) {
+    if constexpr (ON) {
+      if (pg.grad && j < nr) {
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+          const int64_t o = off(j + r * nr);
+          u[r] = pg.u[o];
+          g[r] = pg.acc ? pg.grad[o] : T(0);
+        }
+      }
+    }
+  }
+  // store of output i (= j + r n/RL) at offset o
+  __device__ __forceinline__ void put(const PhaseGrad<T>& pg, int i, int j, int64_t o, cx<T> v) const {
+    if constexpr (ON) {
+      const int r = (i - j) / nr;
+      const T d = v.y * u[r].x - v.x * u[r].y;
+      pg.grad[o] = pg.acc ? g[r] + d : d;
+    } else {
+      pg.put(o, v);
+    }
+  }
+};
+
 template <typename T> __device__ __forceinline__ cx<T> czero() { return mk<T>(T(0), T(0)); }
 
 // address of element i of line l of batch item b
@@ -254,11 +294,13 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
       if (valid) v = in[widx(i)];
       return v;
     };
+    PhaseGradPre<T, S, pg_preload<T, S, EXACT && HALF>()> pre_pg;
+    pre_pg.load(pg, j, [&](int i) { return frow + i; });
     auto store = [&](int i, cx<T> v) {
       if (valid && (EXACT || i < n_io)) {
         const cx<T> g = cscale(v, scale);
         if (out) out[frow + i] = g;
-        if (pg.grad) pg.put(frow + i, g);
+        if (pg.grad) pre_pg.put(pg, i, j, frow + i, g);
       }
     };
     fft_line<T, 1, S, false, HALF>(lds, tw, j, load, store);
@@ -682,12 +724,14 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, bluestein_in
     return v;
   };
   auto mult = [&](int i, cx<T> v) -> cx<T> { return cmul(v, chat[i]); };
+  PhaseGradPre<T, S, pg_preload<T, S, EXACT && HALF>()> pre_pg;
+  pre_pg.load(pg, j, [&](int i) { return line_off<COL>(lo, b, l, i); });
   auto store = [&](int i, cx<T> v) {
     if (valid && (EXACT || i < n_out)) {
       const int64_t o = line_off<COL>(lo, b, l, i);
       const cx<T> g = cmul(v, post[i]);
       if (out) out[o] = g;
-      if (pg.grad) pg.put(o, g);
+      if (pg.grad) pre_pg.put(pg, i, j, o, g);
     }
   };
   conv_line<T, S, HALF, HALF>(lds, tw, j, load, mult, store);
