@@ -760,6 +760,21 @@ hipError_t launch_bluestein_c(const cx<T>* in, cx<T>* out, Lines li, Lines lo, i
   return hipGetLastError();
 }
 
+// Lines per workgroup of an interleaved Bluestein row pass.  Rows are
+// contiguous, so fewer lines per workgroup still load whole row segments;
+// halving (down to 2) until two workgroups fit in a CU's LDS lets one
+// workgroup's barrier waits overlap the other's arithmetic.  At 4096 points
+// this turns one 4-line workgroup per CU into two 2-line ones (15% faster);
+// a single line per workgroup loses again (each lane then needs its own
+// twiddle run).
+template <typename T, class S, int C0>
+constexpr int bluestein_row_lines() {
+  constexpr int line = ((S::line_elems + 31) / 32 * 32 + 32) * (int)sizeof(cx<T>);  // bound on one LDS line
+  int c = C0;
+  while (c > 2 && 2 * c * line > kLdsBytes) c /= 2;
+  return c;
+}
+
 template <typename T, bool COL, class S>
 hipError_t launch_bluestein_s(const cx<T>* in, cx<T>* out, Lines li, Lines lo, int nlines, int n_in, int n_out,
                               const cx<T>* pre, const cx<T>* chat, const cx<T>* post, int batch, const cx<T>* tw,
@@ -780,8 +795,8 @@ hipError_t launch_bluestein_s(const cx<T>* in, cx<T>* out, Lines li, Lines lo, i
         return launch_bluestein_c<T, COL, S, C2>(in, out, li, lo, nlines, n_in, n_out, pre, chat, post, batch, tw, s,
                                                  pg);
     }
-    return launch_bluestein_c<T, COL, S, CF::C>(in, out, li, lo, nlines, n_in, n_out, pre, chat, post, batch, tw, s,
-                                                pg);
+    constexpr int C = (ILV && !COL) ? bluestein_row_lines<T, S, CF::C>() : CF::C;
+    return launch_bluestein_c<T, COL, S, C>(in, out, li, lo, nlines, n_in, n_out, pre, chat, post, batch, tw, s, pg);
   }
 }
 
