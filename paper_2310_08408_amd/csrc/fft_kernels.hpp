@@ -45,6 +45,21 @@ constexpr int waves_per_eu() {
   return w < 1 ? 1 : (w > cap ? cap : w);
 }
 
+// Lines per workgroup of a row pass that interleaves C0 lines lane by lane.
+// Rows are contiguous, so fewer lines per workgroup still move whole row
+// segments; halving (down to 2) until two workgroups fit in a CU's LDS
+// lets one workgroup's barrier waits overlap the other's arithmetic.  At
+// 4096 points this turns one 4-line workgroup per CU into two 2-line ones
+// (Bluestein rows 15% faster, RS inverse rows 6%); a single line per
+// workgroup loses again (each lane then needs its own twiddle run).
+template <typename T, class S, int C0>
+constexpr int row_lines_two_per_cu() {
+  constexpr int line = ((S::line_elems + 31) / 32 * 32 + 32) * (int)sizeof(cx<T>);  // bound on one LDS line
+  int c = C0;
+  while (c > 2 && c % 2 == 0 && 2 * c * line > kLdsBytes) c /= 2;  // stays a divisor of C0
+  return c;
+}
+
 // Lines per workgroup.  Column passes pack adjacent columns (wide coalesced
 // segments) up to the LDS and thread limits; row passes aim at >= 256
 // threads with at most half the LDS (two workgroups per CU).
@@ -245,9 +260,11 @@ template <typename T> __device__ __forceinline__ const cx<T>* table_ptr(const cx
 // Forward (DIR = -1): row y of a contiguous field, zero-padded from n_io to
 // n, transformed into the tiled workspace.  Inverse (DIR = +1): workspace
 // row y transformed back, the first n_io outputs scaled into the field.
-// A workgroup holds C >= kTile rows with lanes interleaved across them, so
-// one wave's store or load covers whole tiles (kTile rows x kTile columns,
-// contiguous) on the workspace side and C row segments on the field side.
+// A workgroup holds C rows with lanes interleaved across them.  With
+// C >= kTile one wave's store or load covers whole tiles (kTile rows x kTile
+// columns, contiguous) on the workspace side and C row segments on the field
+// side; the exact inverse pass may take fewer rows (row_lines_two_per_cu),
+// neighbouring workgroups then sharing tiles through the L2.
 // HALF prunes the zero half of the forward input / the unused half of the
 // inverse output at compile time.
 template <typename T, class S>
@@ -373,8 +390,11 @@ hipError_t launch_rs_rows_s(const cx<T>* in, cx<T>* out, int64_t w_bstride, int 
           hipLaunchKernelGGL((k_rs_rows_fwd_persist<T, S, C>), dim3(groups), dim3(RC::threads), 0, s, in, out,
                              w_bstride, nrows, n_io, tiles, items, per, TableBox<T>{tw});
         } else {
-          hipLaunchKernelGGL((k_rs_rows<T, DIR, S, C, true, true>), dim3(tiles * batch), dim3(RC::threads), 0, s,
-                             in, out, w_bstride, nrows, n_io, scale, tiles, tw, pg);
+          // rows need not fill whole workspace tiles: C2 may be below kTile
+          constexpr int C2 = row_lines_two_per_cu<T, S, C>();
+          const int tiles2 = nrows / C2;
+          hipLaunchKernelGGL((k_rs_rows<T, DIR, S, C2, true, true>), dim3(tiles2 * batch), dim3(C2 * S::threads), 0,
+                             s, in, out, w_bstride, nrows, n_io, scale, tiles2, tw, pg);
         }
         return hipGetLastError();
       }
@@ -760,21 +780,6 @@ hipError_t launch_bluestein_c(const cx<T>* in, cx<T>* out, Lines li, Lines lo, i
   return hipGetLastError();
 }
 
-// Lines per workgroup of an interleaved Bluestein row pass.  Rows are
-// contiguous, so fewer lines per workgroup still load whole row segments;
-// halving (down to 2) until two workgroups fit in a CU's LDS lets one
-// workgroup's barrier waits overlap the other's arithmetic.  At 4096 points
-// this turns one 4-line workgroup per CU into two 2-line ones (15% faster);
-// a single line per workgroup loses again (each lane then needs its own
-// twiddle run).
-template <typename T, class S, int C0>
-constexpr int bluestein_row_lines() {
-  constexpr int line = ((S::line_elems + 31) / 32 * 32 + 32) * (int)sizeof(cx<T>);  // bound on one LDS line
-  int c = C0;
-  while (c > 2 && 2 * c * line > kLdsBytes) c /= 2;
-  return c;
-}
-
 template <typename T, bool COL, class S>
 hipError_t launch_bluestein_s(const cx<T>* in, cx<T>* out, Lines li, Lines lo, int nlines, int n_in, int n_out,
                               const cx<T>* pre, const cx<T>* chat, const cx<T>* post, int batch, const cx<T>* tw,
@@ -795,7 +800,7 @@ hipError_t launch_bluestein_s(const cx<T>* in, cx<T>* out, Lines li, Lines lo, i
         return launch_bluestein_c<T, COL, S, C2>(in, out, li, lo, nlines, n_in, n_out, pre, chat, post, batch, tw, s,
                                                  pg);
     }
-    constexpr int C = (ILV && !COL) ? bluestein_row_lines<T, S, CF::C>() : CF::C;
+    constexpr int C = (ILV && !COL) ? row_lines_two_per_cu<T, S, CF::C>() : CF::C;
     return launch_bluestein_c<T, COL, S, C>(in, out, li, lo, nlines, n_in, n_out, pre, chat, post, batch, tw, s, pg);
   }
 }
