@@ -87,3 +87,47 @@ def test_czt_adjoint_phase_grad(lp, kind, case):
     say(f"czt fused {kind} case {case}: grad {e_grad:.2e} g_U {e_gu:.2e}")
     assert e_grad < TOL[kind] and e_gu < TOL[kind]
     assert rel_l2(grad2.cpu().numpy(), grad.cpu().numpy()) < 1e-15
+
+
+def test_fused_phase_grad_2048_sampled(lp):
+    """The fused adjoints at the benchmark's 2048^2 shape (FP32, batch 2),
+    where the exact-half row passes load u and the accumulated gradient when
+    they start: the gradient at sampled pixels against the oracle's direct
+    adjoint sums, a different u per batch item, and accumulation onto the
+    first result doubling it."""
+    import torch
+    w = workloads.rs_czt_2048(0)
+    g, win, wl = w["grid"], w["window"], w["wavelength"]
+    u0 = cast(oracle.modulate(oracle.gaussian_beam(g, w["w0"], f=w["f"], wavelength=wl), w["phase"]), "c64")
+    u1 = cast(np.conj(u0) * np.exp(0.3j), "c64")
+    du = dev(np.stack([u0, u1]), "c64")
+    rng = np.random.default_rng(11)
+    pix = sorted({(0, 0), (2047, 2047), (1024, 1024), (5, 2040), (1500, 17)} |
+                 {tuple(int(v) for v in rng.integers(0, 2048, 2)) for _ in range(7)})
+    for name in ("rs", "czt"):
+        shape = (g.ny, g.nx) if name == "rs" else (win.ny, win.nx)
+        go = cast(workloads.random_field(rng, shape), "c64")
+        dgo = dev(np.stack([go, go]), "c64")
+        say(f"2048 fused {name} adjoint + phase gradient")
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore")
+            if name == "rs":
+                grad, none = lp.rs_adjoint_phase_grad(dgo, du, g, wl, w["z_rs"])
+                twice, _ = lp.rs_adjoint_phase_grad(dgo, du, g, wl, w["z_rs"], grad=grad.clone(), accumulate=True)
+                gu = oracle.rs_adjoint_at(go, g, wl, w["z_rs"], pix)
+            else:
+                grad, none = lp.czt_adjoint_phase_grad(dgo, du, g, win, wl, w["z_czt"])
+                twice, _ = lp.czt_adjoint_phase_grad(dgo, du, g, win, wl, w["z_czt"], grad=grad.clone(),
+                                                     accumulate=True)
+                gu = oracle.czt_adjoint_at(go, g, win, wl, w["z_czt"], pix)
+        assert none is None
+        got = grad.cpu().numpy().astype(np.float64)
+        errs = []
+        for b, u in enumerate((u0, u1)):
+            ref = oracle.phase_grad(gu, np.array([u[p] for p in pix]))
+            errs.append(rel_l2(np.array([got[b][p] for p in pix]), ref))
+        # the accumulating call adds the same FP32 values again: exactly 2x
+        doubled = torch.equal(twice, 2 * grad)
+        say(f"  sampled rel-L2 item 0 {errs[0]:.2e}, item 1 {errs[1]:.2e}; accumulate doubles: {doubled}")
+        assert max(errs) < TOL["c64"]
+        assert doubled
