@@ -752,3 +752,21 @@ def adam_step(p, g, m, v, step: int, lr: float, beta1: float = 0.9, beta2: float
     vhat = v / (1.0 - beta2 ** step)
     p = p - lr * weight_decay * p - lr * mhat / (np.sqrt(vhat) + eps)
     return p, m, v
+
+
+def stop_step(losses, patience: int = 500, check_every: int = 100):
+    """Stopping condition of the discovery runs (Methods): stop once the loss
+    has not improved over `patience` consecutive steps, with the condition
+    checked every `check_every` steps.  Improvement means strictly below the
+    best loss so far (the first finite loss always improves; NaN never does).
+    losses[k] is the loss of step k + 1.  Returns the number of steps taken
+    when the rule first fires, or None if it never does."""
+    best = math.inf
+    last_improvement = 0        # step of the last improvement (0: none yet)
+    for step, loss in enumerate(losses, start=1):
+        if loss < best:
+            best = loss
+            last_improvement = step
+        if step % check_every == 0 and step - last_improvement >= patience:
+            return step
+    return None

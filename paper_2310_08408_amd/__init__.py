@@ -22,7 +22,7 @@ __all__ = [
     "vczt_propagate", "vczt_adjoint", "rs_grad_z", "czt_grad_z", "rs_adjoint_phase_grad", "czt_adjoint_phase_grad",
     "prop_source_gaussian", "prop_source_radial", "prop_modulate",
     "prop_phase_grad", "prop_waveplate", "prop_waveplate_adjoint", "prop_spot_loss", "prop_density_loss",
-    "prop_softmin", "prop_adam_step", "Adam", "prop_sampling_check",
+    "prop_softmin", "prop_adam_step", "Adam", "prop_track_best", "StopRule", "prop_sampling_check",
     "prop_fft_length", "prop_cache_clear", "prop_trace_enable", "prop_trace_read", "prop_autotune_report",
     "PropError", "PropWarning", "library", "Plan", "Setup", "PROP_OP_RS", "PROP_OP_CZT", "PROP_OP_VRS",
     "PROP_OP_VCZT", "PROP_PLAN_GRAPH", "PROP_PLAN_AUTOTUNE",
@@ -600,6 +600,49 @@ class Adam:
     def zero_grad(self):
         for p in self.params:
             p.grad = None
+
+
+def prop_track_best(loss, best, since):
+    """One step of the stopping rule's bookkeeping on the device: per batch
+    item, best = loss and since = 0 where loss < best, else since += 1.
+    loss, best: float64 [B]; since: int64 [B] (updated in place)."""
+    lib = library()
+    for t, dt in ((loss, torch.float64), (best, torch.float64), (since, torch.int64)):
+        _dev(t)
+        if t.dtype != dt or not t.is_contiguous() or t.numel() != loss.numel():
+            raise ValueError("loss, best: float64 [B]; since: int64 [B]; contiguous")
+    with torch.cuda.device(loss.device):
+        st = lib.prop_track_best(_ptr(loss), _ptr(best), _ptr(since), loss.numel(), _stream(loss))
+    _lib.check("prop_track_best", st)
+
+
+class StopRule:
+    """The paper's stopping condition: stop once the objective has not
+    improved for `patience` consecutive steps, checked every `check_every`
+    steps (500 and 100 in its discovery runs).  The best value and the steps
+    since it fell stay on the device; `update` reads them back only at
+    checks.  With a batch of objectives, `update` reports True once every
+    item has stalled; `stalled` gives the per-item state of the last check."""
+
+    def __init__(self, patience=500, check_every=100, batch=1, device="cuda"):
+        if patience < 1 or check_every < 1:
+            raise ValueError("patience and check_every must be positive")
+        self.patience, self.check_every = int(patience), int(check_every)
+        self.best = torch.full((batch,), float("inf"), dtype=torch.float64, device=device)
+        self.since = torch.zeros(batch, dtype=torch.int64, device=device)
+        self.steps = 0
+        self.stalled = torch.zeros(batch, dtype=torch.bool)
+
+    def update(self, loss) -> bool:
+        loss = loss.detach().reshape(-1)
+        if loss.dtype != torch.float64:
+            loss = loss.to(torch.float64)
+        prop_track_best(loss.contiguous(), self.best, self.since)
+        self.steps += 1
+        if self.steps % self.check_every:
+            return False
+        self.stalled = self.since.cpu() >= self.patience
+        return bool(self.stalled.all())
 
 
 def prop_sampling_check(grid, wavelength, z) -> int:

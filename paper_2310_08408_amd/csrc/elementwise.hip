@@ -882,6 +882,26 @@ hipError_t launch_softmin(const double* l, int ndet, double beta, double* val, d
 }
 
 // ------------------------------------------------------------ optimiser --
+// Stopping rule: per batch item, the best objective so far and the number of
+// steps since it last fell.  A step improves only when its objective is
+// strictly below the best (a NaN objective never improves).
+__global__ void k_track_best(const double* loss, double* best, int64_t* since, int batch) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  const double l = loss[b];
+  if (l < best[b]) {
+    best[b] = l;
+    since[b] = 0;
+  } else {
+    since[b] = since[b] + 1;
+  }
+}
+
+hipError_t launch_track_best(const double* loss, double* best, int64_t* since, int batch, hipStream_t s) {
+  hipLaunchKernelGGL(k_track_best, dim3((batch + 63) / 64), dim3(64), 0, s, loss, best, since, batch);
+  return hipGetLastError();
+}
+
 // Adam step with bias correction, in the parameters' precision for the
 // moments and FP64 for the scalar factors; weight_decay > 0 adds the
 // decoupled (AdamW) decay.  One pass: reads p, g, m, v, writes p, m, v.

@@ -1846,6 +1846,16 @@ int prop_softmin(const double* losses, int32_t ndet, double beta, double* value,
   return PROP_OK;
 }
 
+int prop_track_best(const double* loss, double* best, int64_t* since, int32_t batch, void* stream) {
+  if (batch < 0) return PROP_ESHAPE;
+  if (batch == 0) return PROP_OK;
+  if (!loss || !best || !since) return PROP_ENULL;
+  const size_t nb = (size_t)batch;
+  LP_RET(check_alias({{loss, nb * sizeof(double)}}, {{best, nb * sizeof(double)}, {since, nb * sizeof(int64_t)}}));
+  LP_TRY(launch_track_best(loss, best, since, batch, (hipStream_t)stream));
+  return PROP_OK;
+}
+
 int32_t prop_autotune_report(char* buf, int32_t cap) {
   Ctx& C = ctx();
   std::lock_guard<std::mutex> lk(C.mu);

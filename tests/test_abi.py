@@ -86,6 +86,13 @@ def test_validation_without_device(lib):
     assert lib.prop_density_loss(0, comps, 2, None, 1, 1.0, 16, 0.5, out, None, None, 1, None) == -1
     assert lib.prop_softmin(out, 3, 0.0, out, None, 1, None) == -3
     assert lib.prop_softmin(out, 0, 1.0, out, None, 1, None) == -2
+    # stopping-rule bookkeeping: batch, missing arrays, best or since on the loss or on each other
+    lo, be, si = ctypes.c_void_p(0x70000000), ctypes.c_void_p(0x71000000), ctypes.c_void_p(0x72000000)
+    assert lib.prop_track_best(lo, be, si, -1, None) == -2
+    assert lib.prop_track_best(lo, be, si, 0, None) == 0     # nothing to do
+    assert lib.prop_track_best(lo, None, si, 4, None) == -1
+    assert lib.prop_track_best(lo, lo, si, 4, None) == -4
+    assert lib.prop_track_best(lo, be, be, 4, None) == -4
     # beam splitter: component count, missing output plane, output on an input
     pa = (ctypes.c_void_p * 2)(0x10000000, 0x20000000)
     pc = (ctypes.c_void_p * 2)(0x30000000, 0x40000000)

@@ -76,3 +76,37 @@ def test_focus_discovery_loop(lp):
         losses.append(float(loss.detach()))
     say(f"discovery loop: loss {losses[0]:.4f} -> {losses[-1]:.4f}")
     assert losses[-1] < 0.8 * losses[0]
+
+
+def test_stop_rule_on_device_vs_oracle(lp):
+    """The device-side stopping bookkeeping (prop_track_best behind
+    StopRule) over a batch of three loss sequences: each item first counts
+    as stalled at the check where the oracle's rule fires, and update()
+    reports True exactly when every item is stalled."""
+    import torch
+    rng = np.random.default_rng(4)
+    n = 3000
+    seqs = [1.0 + rng.random(n),                                                   # noise: new lows get rare
+            np.maximum(0.0, 1.0 - np.arange(n) / 1500.0) + 0.05 * rng.random(n),  # trend, then noise
+            np.linspace(3.0, 1.0, n)]                                               # always improving
+    seqs[0][700] = np.nan                                                           # NaN never improves
+    want = [oracle.stop_step(list(s), 500, 100) for s in seqs]
+    say("oracle stop steps", want)
+    assert want[0] is not None and want[1] is not None and want[2] is None
+    rule = lp.StopRule(patience=500, check_every=100, batch=3)
+    losses = torch.tensor(np.stack(seqs, axis=1), dtype=torch.float32, device="cuda")   # FP32 objectives
+    want32 = [oracle.stop_step([float(np.float32(v)) for v in s], 500, 100) for s in seqs]
+    first = [None] * 3
+    for k in range(n):
+        stop = rule.update(losses[k])
+        if (k + 1) % 100 == 0:
+            assert stop == bool(rule.stalled.all())
+            for b in range(3):
+                if first[b] is None and bool(rule.stalled[b]):
+                    first[b] = k + 1
+    say("device first stalls", first)
+    assert first == want32
+    assert rule.steps == n
+    # invalid arguments are refused before any launch
+    with pytest.raises(ValueError):
+        lp.prop_track_best(losses[0].double(), rule.best, rule.since.float())
