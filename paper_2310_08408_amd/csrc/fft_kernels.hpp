@@ -473,7 +473,8 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
   auto mult = [&](int i, cx<T> v) -> cx<T> {
     cx<T> h = czero<T>();
     if (valid) h = sq[min(i, My - i) * 4];
-    return conj_spec ? cmulc(v, h) : cmul(v, h);
+    if (conj_spec) h.y = -h.y;  // one product, not two and a select
+    return cmul(v, h);
   };
   auto store = [&](int i, cx<T> v) {
     if (valid && (EXACT || i < n_valid)) store_stream(&col[i * kTile], v);
@@ -488,10 +489,12 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
 // share their spectrum lines -- and loads the next item's input while it
 // transforms the current one.  No access needs a guard; the tables are
 // boxed (lifted table loads would spill next to the prefetch).
-template <typename T, class S, int C>
+// CONJ (the adjoint's conjugated spectrum) is a template parameter: as a
+// runtime flag the compiler forms both products and selects, 6% of the
+// kernel's VALU instructions.
+template <typename T, class S, int C, bool CONJ>
 __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) void k_rs_cols_persist(
-    cx<T>* W, int64_t bstride, int n_valid, TableBox<T> Sq_, int conj_spec, int nb, int items, int per,
-    TableBox<T> tw_) {
+    cx<T>* W, int64_t bstride, int n_valid, TableBox<T> Sq_, int nb, int items, int per, TableBox<T> tw_) {
   const cx<T>* Sq = Sq_.p;
   const cx<T>* tw = tw_.p;
   constexpr int LS = line_stride<S, C, true>();
@@ -531,7 +534,7 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
     auto load = [&](int i) -> cx<T> { return cur[(i - j) / nr0]; };
     auto mult = [&](int i, cx<T> v) -> cx<T> {
       const cx<T> h = sq[min(i, My - i) * 4];
-      return conj_spec ? cmulc(v, h) : cmul(v, h);
+      return CONJ ? cmulc(v, h) : cmul(v, h);
     };
     auto store = [&](int i, cx<T> v) { store_stream(&col[i * kTile], v); };
     conv_line<T, S, true, true>(lds, tw, j, load, mult, store);
@@ -556,8 +559,12 @@ hipError_t launch_rs_cols_c(cx<T>* W, int64_t bstride, int ncols, int n_valid, c
         const int items = tiles * batch;
         const int per = (items + cu_count() - 1) / cu_count();
         const int groups = (items + per - 1) / per;
-        hipLaunchKernelGGL((k_rs_cols_persist<T, S, C>), dim3(groups), dim3(C * S::threads), 0, s, W, bstride,
-                           n_valid, TableBox<T>{Sq}, conj_spec ? 1 : 0, batch, items, per, TableBox<T>{tw});
+        if (conj_spec)
+          hipLaunchKernelGGL((k_rs_cols_persist<T, S, C, true>), dim3(groups), dim3(C * S::threads), 0, s, W,
+                             bstride, n_valid, TableBox<T>{Sq}, batch, items, per, TableBox<T>{tw});
+        else
+          hipLaunchKernelGGL((k_rs_cols_persist<T, S, C, false>), dim3(groups), dim3(C * S::threads), 0, s, W,
+                             bstride, n_valid, TableBox<T>{Sq}, batch, items, per, TableBox<T>{tw});
       } else {
         hipLaunchKernelGGL((k_rs_cols<T, S, C, true, true>), dim3(tiles * batch), dim3(C * S::threads), 0, s, W,
                            bstride, ncols, n_valid, TableBox<T>{Sq}, Mx, conj_spec ? 1 : 0, tiles, TableBox<T>{tw});
