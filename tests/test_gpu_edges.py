@@ -130,3 +130,25 @@ def test_empty_batches(lp):
         w = torch.empty((0, 8, 8), dtype=dt, device="cuda")
         assert lp.czt_adjoint(w, g, win, 500e-9, 1e-3).shape == (0, 12, 16)
     torch.cuda.synchronize()
+
+
+def test_czt_odd_line_count_at_4096(lp):
+    """FP32 Bluestein row passes at L = 4096 hold two rows per workgroup; with
+    2047 rows the last workgroup has one valid row (forward: input rows;
+    adjoint: output rows).  Sampled outputs against the oracle's direct sums."""
+    import torch
+    gi = Grid(2048, 2047, 1.953125e-6, 1.953125e-6)
+    win = Grid(2048, 2049, 19.53125e-9, 19.53125e-9)
+    wl, z = 650e-9, 25e-3
+    rng = np.random.default_rng(61)
+    u = cast(workloads.random_field(rng, (1, gi.ny, gi.nx)), "c64")
+    v = cast(workloads.random_field(rng, (1, win.ny, win.nx)), "c64")
+    out = lp.czt_propagate(dev(u, "c64"), gi, win, wl, z)
+    back = lp.czt_adjoint(dev(v, "c64"), gi, win, wl, z)
+    torch.cuda.synchronize()
+    pout = [(0, 0), (2048, 2047), (2048, 0), (1024, 1500), (7, 2040), (1999, 3)]
+    pin = [(0, 0), (2046, 2047), (2046, 0), (1023, 1024), (5, 2040), (2045, 77)]
+    ef = rel_l2(np.array([complex(out[0][p]) for p in pout]), oracle.czt_at(u[0], gi, win, wl, z, pout))
+    ea = rel_l2(np.array([complex(back[0][p]) for p in pin]), oracle.czt_adjoint_at(v[0], gi, win, wl, z, pin))
+    say(f"czt 2048x2047 -> 2048x2049 (L 4096, odd rows): fwd {ef:.1e} adj {ea:.1e}")
+    assert ef < TOL["c64"] and ea < TOL["c64"]
