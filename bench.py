@@ -225,6 +225,24 @@ def main():
     value64 = 2 / wall64
     log(f"fp64 single field: {wall64 * 1e3:.3f} ms/step -> {value64:.1f} grads/s")
 
+    # achievable HBM rate for context: a plain 512 MiB device-to-device copy
+    # (reads 512 MiB, writes 512 MiB), best of 10, after the timed region
+    src = torch.empty(64 * 1024 * 1024, dtype=torch.complex64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = None
+    for _ in range(10):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    copy_gbs = 2 * src.numel() * 8 / (best * 1e-3) / 1e9
+    del src, dst
+    log(f"device copy of 512 MiB: {copy_gbs:.0f} GB/s")
+
     cpu = None
     if not a.no_cpu:
         log("cpu baseline (FP64 oracle) ...")
@@ -241,6 +259,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "hbm_frac_step": step_frac,
+        "hbm_copy": {"gbs": copy_gbs, "bytes": 2 * 512 * 2 ** 20, "what": "512 MiB device-to-device copy, best of 10",
+                     "dominant_frac_of_copy": (roofline["achieved"] / copy_gbs) if roofline else None},
         "fp64_single": {"value": value64, "unit": "grads/s", "ms_per_step": wall64 * 1e3,
                         "speedup_fp32_batched": value / value64},
         "errors_vs_fp64": errs,
