@@ -264,6 +264,37 @@ def _vrs_one(ex, ey, g, wavelength, z):
     return Ex, Ey, Ez
 
 
+def vrs_at(ex, ey, g, wavelength: float, z: float, pixels):
+    """Direct VRS sums at selected output pixels [(l, m), ...] (no FFT):
+    (E_x, E_y, E_z) with E_z = -dx dy sum [E_x0 (x_m - x')/z + E_y0 (y_l - y')/z] H."""
+    ex, ey = _as_c128(ex), _as_c128(ey)
+    x, y = coords(g)
+    s = g.dx * g.dy
+    out = np.empty((3, len(pixels)), dtype=C128)
+    for n, (l, m) in enumerate(pixels):
+        X, Y = x[m] - x[None, :], y[l] - y[:, None]
+        H = rs_kernel(X, Y, z, wavelength)
+        out[0, n] = np.sum(ex * H) * s
+        out[1, n] = np.sum(ey * H) * s
+        out[2, n] = -np.sum((ex * X / z + ey * Y / z) * H) * s
+    return out[0], out[1], out[2]
+
+
+def vrs_adjoint_at(gx, gy, gz, g, wavelength: float, z: float, pixels):
+    """Direct adjoint VRS sums at selected input pixels [(i, j), ...]:
+    g_ex = dx dy sum conj(H) g_x - conj((x - x_j)/z H) g_z, and likewise for g_ey."""
+    gx, gy, gz = _as_c128(gx), _as_c128(gy), _as_c128(gz)
+    x, y = coords(g)
+    s = g.dx * g.dy
+    out = np.empty((2, len(pixels)), dtype=C128)
+    for n, (i, j) in enumerate(pixels):
+        X, Y = x[None, :] - x[j], y[:, None] - y[i]
+        Hc = np.conj(rs_kernel(X, Y, z, wavelength))
+        out[0, n] = np.sum(Hc * gx - (X / z) * Hc * gz) * s
+        out[1, n] = np.sum(Hc * gy - (Y / z) * Hc * gz) * s
+    return out[0], out[1]
+
+
 def vrs_propagate(ex, ey, g, wavelength: float, z: float):
     """E_x, E_y by scalar RS; E_z = -dx dy sum [E_x0 (x-x')/z + E_y0 (y-y')/z] H.
 
@@ -493,6 +524,41 @@ def _rw_adj_one(gx, gy, gz, g_in, win, wavelength, na, f):
     gex = M[0, 0] * w[0] + M[1, 0] * w[1] + M[2, 0] * w[2]
     gey = M[0, 1] * w[0] + M[1, 1] * w[1] + M[2, 1] * w[2]
     return gex, gey
+
+
+def vczt_focus_at(ex, ey, g_in, win, wavelength: float, na: float, f: float, pixels):
+    """The focal field at selected window pixels [(q, p), ...]: the same
+    Richards-Wolf sum as vczt_focus, taken pixel by pixel over the pupil."""
+    ex, ey = _as_c128(ex), _as_c128(ey)
+    M = rw_pupil_matrix(g_in, na, f)
+    k = TWO_PI / wavelength
+    x, y = coords(g_in)
+    X, Y = coords(win)
+    K = 1j * k * f * np.exp(-1j * k * f) / TWO_PI * (g_in.dx * g_in.dy) / (f * f)
+    F = [M[c, 0] * ex + M[c, 1] * ey for c in range(3)]
+    out = np.empty((3, len(pixels)), dtype=C128)
+    for n, (q, p) in enumerate(pixels):
+        phase = np.exp(1j * k * (Y[q] * y[:, None] + X[p] * x[None, :]) / f)
+        for c in range(3):
+            out[c, n] = K * np.sum(F[c] * phase)
+    return out[0], out[1], out[2]
+
+
+def vczt_focus_adjoint_at(gx, gy, gz, g_in, win, wavelength: float, na: float, f: float, pixels):
+    """The focus adjoint at selected pupil pixels [(i, j), ...]."""
+    gs = [_as_c128(a) for a in (gx, gy, gz)]
+    M = rw_pupil_matrix(g_in, na, f)
+    k = TWO_PI / wavelength
+    x, y = coords(g_in)
+    X, Y = coords(win)
+    K = 1j * k * f * np.exp(-1j * k * f) / TWO_PI * (g_in.dx * g_in.dy) / (f * f)
+    out = np.empty((2, len(pixels)), dtype=C128)
+    for n, (i, j) in enumerate(pixels):
+        phase = np.exp(-1j * k * (Y[:, None] * y[i] + X[None, :] * x[j]) / f)
+        w = [np.conj(K) * np.sum(gc * phase) for gc in gs]
+        out[0, n] = M[0, 0][i, j] * w[0] + M[1, 0][i, j] * w[1] + M[2, 0][i, j] * w[2]
+        out[1, n] = M[0, 1][i, j] * w[0] + M[1, 1][i, j] * w[1] + M[2, 1][i, j] * w[2]
+    return out[0], out[1]
 
 
 def vczt_focus_adjoint(gx, gy, gz, g_in, win, wavelength: float, na: float, f: float):
