@@ -320,9 +320,9 @@ int prop_softmin(const double* losses, int32_t ndet, double beta, double* value,
 int prop_adam_step(prop_dtype t, void* param, const void* grad, void* m, void* v, int64_t n, double lr,
                    double beta1, double beta2, double eps, double weight_decay, int32_t step, void* stream);
 
-/* Stopping rule of the optimisation (the paper stops when the loss has not
- * improved over 500 consecutive steps, checked every 100 steps; Methods,
- * discovery experiments).  Per batch item b: if loss[b] < best[b] then
+/* Stopping rule of the optimisation (Methods, discovery experiments: a run
+ * ends once its best loss has stood for 500 steps, looked at every 100
+ * steps).  Per batch item b: if loss[b] < best[b] then
  * best[b] = loss[b], since[b] = 0, else since[b] += 1 (a NaN loss never
  * improves).  Device arrays of batch entries, owned by the caller: loss
  * (float64, read), best (float64, start at +inf) and since (int64, start at

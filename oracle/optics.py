@@ -821,9 +821,9 @@ def adam_step(p, g, m, v, step: int, lr: float, beta1: float = 0.9, beta2: float
 
 
 def stop_step(losses, patience: int = 500, check_every: int = 100):
-    """Stopping condition of the discovery runs (Methods): stop once the loss
-    has not improved over `patience` consecutive steps, with the condition
-    checked every `check_every` steps.  Improvement means strictly below the
+    """Stopping condition of the discovery runs (Methods): every
+    `check_every` steps, stop if the best loss so far was reached
+    `patience` or more steps ago.  Improvement means strictly below the
     best loss so far (the first finite loss always improves; NaN never does).
     losses[k] is the loss of step k + 1.  Returns the number of steps taken
     when the rule first fires, or None if it never does."""

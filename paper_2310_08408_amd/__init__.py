@@ -617,9 +617,9 @@ def prop_track_best(loss, best, since):
 
 
 class StopRule:
-    """The paper's stopping condition: stop once the objective has not
-    improved for `patience` consecutive steps, checked every `check_every`
-    steps (500 and 100 in its discovery runs).  The best value and the steps
+    """The paper's stopping condition: every `check_every` steps, stop if
+    the best objective so far is `patience` or more steps old (500 and 100
+    in its discovery runs).  The best value and the steps
     since it fell stay on the device; `update` reads them back only at
     checks.  With a batch of objectives, `update` reports True once every
     item has stalled; `stalled` gives the per-item state of the last check."""

@@ -1,7 +1,7 @@
-"""Pins of the oracle's stopping rule (paper: Methods, the discovery runs
-stop when the loss has not improved over 500 consecutive steps, checked
-every 100 steps): stop steps derived by hand from that statement, and
-agreement with an independent window formulation of it."""
+"""Pins of the oracle's stopping rule (paper: Methods; a discovery run ends
+once its best loss has stood for 500 steps, looked at every 100 steps):
+stop steps derived by hand from that rule, and agreement with an
+independent window formulation of it."""
 import math
 
 import numpy as np
