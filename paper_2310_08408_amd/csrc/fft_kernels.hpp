@@ -390,11 +390,18 @@ hipError_t launch_rs_rows_s(const cx<T>* in, cx<T>* out, int64_t w_bstride, int 
           hipLaunchKernelGGL((k_rs_rows_fwd_persist<T, S, C>), dim3(groups), dim3(RC::threads), 0, s, in, out,
                              w_bstride, nrows, n_io, tiles, items, per, TableBox<T>{tw});
         } else {
-          // rows need not fill whole workspace tiles: C2 may be below kTile
+          // rows need not fill whole workspace tiles: C2 may be below kTile.
+          // With the phase-gradient epilogue fused, C lines measure faster
+          // (4096: 248 against 257 us; plain: 218 against 212 us at C2).
           constexpr int C2 = row_lines_two_per_cu<T, S, C>();
-          const int tiles2 = nrows / C2;
-          hipLaunchKernelGGL((k_rs_rows<T, DIR, S, C2, true, true>), dim3(tiles2 * batch), dim3(C2 * S::threads), 0,
-                             s, in, out, w_bstride, nrows, n_io, scale, tiles2, tw, pg);
+          if (C2 != C && !pg.grad) {
+            const int tiles2 = nrows / C2;
+            hipLaunchKernelGGL((k_rs_rows<T, DIR, S, C2, true, true>), dim3(tiles2 * batch), dim3(C2 * S::threads),
+                               0, s, in, out, w_bstride, nrows, n_io, scale, tiles2, tw, pg);
+          } else {
+            hipLaunchKernelGGL((k_rs_rows<T, DIR, S, C, true, true>), dim3(tiles * batch), dim3(RC::threads), 0, s,
+                               in, out, w_bstride, nrows, n_io, scale, tiles, tw, pg);
+          }
         }
         return hipGetLastError();
       }
