@@ -113,7 +113,9 @@ def rel(a, b):
 
 def cpu_baseline(reps=2):
     """The FP64 oracle on one 2048^2 field: RS fwd+adj and CZT fwd+adj,
-    `reps` times over (about 10 s of host work at reps=2)."""
+    `reps` times over (about 10 s of host work at reps=2).  Returns the
+    timing record and the oracle's results (RS and CZT forward fields, the
+    summed phase gradient) for that field."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
@@ -132,11 +134,12 @@ def cpu_baseline(reps=2):
         grad = grad + oracle.phase_grad(gc, u)
     dt = time.perf_counter() - t0
     threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    ref = {"rs_forward": y, "czt_forward": yc, "phase_grad": grad}
     return {"value": 2.0 * reps / dt, "unit": "grads/s", "cores": int(threads), "kind": "oracle",
             "sample": f"one 2048^2 field, {reps} passes: RS fwd+adj and CZT fwd+adj with the SLM phase gradient, "
                       f"FP64 (numpy/scipy; {dt:.1f} s; FFT steps single-threaded, matrix products on "
                       f"{threads} BLAS threads)",
-            "seconds": dt}
+            "seconds": dt}, ref
 
 
 def main():
@@ -245,11 +248,19 @@ def main():
     del src, dst
     log(f"device copy of 512 MiB: {copy_gbs:.0f} GB/s")
 
-    cpu = None
+    cpu, errs_oracle = None, None
     if not a.no_cpu:
+        import numpy as np
         log("cpu baseline (FP64 oracle) ...")
-        cpu = cpu_baseline()
+        cpu, ref = cpu_baseline()
         log(f"cpu baseline: {cpu['value']:.4f} grads/s ({cpu['seconds']:.1f} s)")
+        # item 0 of the batch is the oracle's field: FP32 results against it
+        got = {"rs_forward": y32[0], "czt_forward": c32[0], "phase_grad": step.grad[0]}
+        errs_oracle = {}
+        for k, t in got.items():
+            x = t.detach().cpu().numpy().astype(np.complex128)
+            errs_oracle[k] = float(np.linalg.norm(x - ref[k]) / np.linalg.norm(ref[k]))
+        log("rel-L2 of FP32 results (item 0) vs the FP64 oracle:", {k: f"{v:.2e}" for k, v in errs_oracle.items()})
 
     out = {
         "metric": METRIC, "value": value, "unit": "grads/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -266,6 +277,7 @@ def main():
         "fp64_single": {"value": value64, "unit": "grads/s", "ms_per_step": wall64 * 1e3,
                         "speedup_fp32_batched": value / value64},
         "errors_vs_fp64": errs,
+        "errors_vs_oracle": errs_oracle,
         "per_pass": per_pass,
         "gpu_ms_per_step": gpu * 1e3,
         "first_step_ms": t_setup * 1e3,
