@@ -430,6 +430,12 @@ typedef struct {
 } prop_trace_stat;
 void prop_trace_enable(int32_t on);
 int32_t prop_trace_read(prop_trace_stat* out, int32_t max);
+/* Restrict tracing to the launches of one pass (its name as reported by
+ * prop_trace_read; the string is copied), or trace every pass again with
+ * NULL.  Each traced launch records two events on its stream, which adds a
+ * few microseconds between dependent kernels, so a timed run can trace just
+ * the pass it reports on. */
+void prop_trace_only(const char* name);
 
 #ifdef __cplusplus
 }

@@ -23,7 +23,7 @@ __all__ = [
     "prop_source_gaussian", "prop_source_radial", "prop_modulate",
     "prop_phase_grad", "prop_waveplate", "prop_waveplate_adjoint", "prop_spot_loss", "prop_density_loss",
     "prop_softmin", "prop_adam_step", "Adam", "prop_track_best", "StopRule", "prop_sampling_check",
-    "prop_fft_length", "prop_cache_clear", "prop_trace_enable", "prop_trace_read", "prop_autotune_report",
+    "prop_fft_length", "prop_cache_clear", "prop_trace_enable", "prop_trace_read", "prop_trace_only", "prop_autotune_report",
     "PropError", "PropWarning", "library", "Plan", "Setup", "PROP_OP_RS", "PROP_OP_CZT", "PROP_OP_VRS",
     "PROP_OP_VCZT", "PROP_PLAN_GRAPH", "PROP_PLAN_AUTOTUNE",
 ]
@@ -659,6 +659,11 @@ def prop_cache_clear() -> None:
 
 def prop_trace_enable(on: bool = True) -> None:
     library().prop_trace_enable(1 if on else 0)
+
+
+def prop_trace_only(name=None) -> None:
+    """Trace only the launches of pass `name` (None: every pass again)."""
+    library().prop_trace_only(None if name is None else str(name).encode())
 
 
 def prop_trace_read(max_entries: int = 64) -> dict:

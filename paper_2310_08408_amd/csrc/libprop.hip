@@ -50,8 +50,10 @@ struct TraceRec {
 };
 struct Tracer {
   bool on = false;
+  std::string only;  // pass name to trace; empty: every pass
   std::vector<TraceRec> recs;
   std::vector<hipEvent_t> pool;
+  bool want(const char* name) const { return on && (only.empty() || only == name); }
 };
 static Tracer& tracer() {
   static Tracer* t = new Tracer();
@@ -77,13 +79,13 @@ static hipEvent_t take_event() {
   do {                                                                                  \
     Tracer& tr_ = tracer();                                                             \
     hipEvent_t ea_ = nullptr, eb_ = nullptr;                                            \
-    if (tr_.on && !capturing(S)) {                                                      \
+    if (tr_.want(NAME) && !capturing(S)) {                                              \
       ea_ = take_event();                                                               \
       eb_ = take_event();                                                               \
       if (ea_) (void)hipEventRecord(ea_, S);                                            \
     }                                                                                   \
     hipError_t e_ = (EXPR);                                                             \
-    if (tr_.on && ea_ && eb_) {                                                         \
+    if (ea_ && eb_) {                                                                   \
       (void)hipEventRecord(eb_, S);                                                     \
       tr_.recs.push_back(TraceRec{NAME, ea_, eb_, (double)(BYTES)});                    \
     }                                                                                   \
@@ -2051,6 +2053,11 @@ void prop_trace_enable(int32_t on) {
   }
   t.recs.clear();
   t.on = on != 0;
+}
+
+void prop_trace_only(const char* name) {
+  std::lock_guard<std::mutex> lk(ctx().mu);
+  tracer().only = name ? name : "";
 }
 
 int32_t prop_trace_read(prop_trace_stat* out, int32_t max) {
