@@ -192,3 +192,41 @@ def test_nan_propagates(lp):
     u[5, 7] = np.nan
     out = host(lp.rs_propagate(dev(u, "c64"), g, 600e-9, 1e-3))
     assert np.isnan(out).any()
+
+
+def test_trace_all_passes_and_one_pass(lp):
+    """The launch trace the benchmark reads: with every pass traced, an RS
+    and a CZT call report their passes with launch counts, positive times
+    and the algorithmic bytes of each launch; restricted to one pass, only
+    that pass is reported; reading clears the trace."""
+    import torch
+    import warnings
+    g = Grid.square(256, 1e-3)
+    win = Grid.square(128, 20e-6)
+    u = dev(rnd((2, 256, 256), 3), "c64")
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        lp.rs_propagate(u, g, 600e-9, 5e-3)
+        lp.czt_propagate(u, g, win, 600e-9, 5e-3)
+        torch.cuda.synchronize()
+        lp.prop_trace_enable(True)
+        for _ in range(3):
+            lp.rs_propagate(u, g, 600e-9, 5e-3)
+            lp.czt_propagate(u, g, win, 600e-9, 5e-3)
+        every = lp.prop_trace_read()
+        lp.prop_trace_only("rs_cols")
+        for _ in range(2):
+            lp.rs_propagate(u, g, 600e-9, 5e-3)
+            lp.czt_propagate(u, g, win, 600e-9, 5e-3)
+        one = lp.prop_trace_read()
+        empty = lp.prop_trace_read()
+        lp.prop_trace_enable(False)
+        lp.prop_trace_only(None)
+    say("traced passes", {k: v[0] for k, v in every.items()}, "filtered", {k: v[0] for k, v in one.items()})
+    assert {"rs_rows_fwd", "rs_cols", "rs_rows_inv", "czt_rows", "czt_cols"} <= set(every)
+    assert all(v[0] == 3 and v[1] > 0 for k, v in every.items() if k.startswith(("rs_", "czt_")))
+    # RS column pass: reads and writes the 256 x 512 workspace of each field, plus the spectrum once
+    n, ms, by = every["rs_cols"]
+    assert by / n >= 2 * 8 * 2 * 256 * 512
+    assert set(one) == {"rs_cols"} and one["rs_cols"][0] == 2 and one["rs_cols"][1] > 0
+    assert empty == {}
