@@ -156,7 +156,7 @@ def main():
                     help="finish with a plain 512 MiB device copy (reference for memory counters)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (the build targets a single MI355X); got --gpus {a.gpus}",
+        print(f"bench.py runs on one GPU only: libprop shards no work across GPUs (got --gpus {a.gpus})",
               file=sys.stderr)
         sys.exit(2)
 
