@@ -279,7 +279,9 @@ struct RowCfg {
 // EXACT (with HALF): the valid length is exactly n/2 and the line count a
 // multiple of C, so no load or store needs a guard; the guards' branches
 // otherwise split every access into its own exec-masked block.
-template <typename T, int DIR, class S, int C, bool HALF, bool EXACT = false>
+// PG = false: an instance without the phase-gradient epilogue, for launches
+// that have none (its early loads would hold 24 VGPRs for nothing).
+template <typename T, int DIR, class S, int C, bool HALF, bool EXACT = false, bool PG = true>
 __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) void k_rs_rows(
     const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int64_t w_bstride, int nrows, int n_io, T scale, int tiles,
     const cx<T>* __restrict__ tw, PhaseGrad<T> pg) {
@@ -311,13 +313,15 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
       if (valid) v = in[widx(i)];
       return v;
     };
-    PhaseGradPre<T, S, pg_preload<T, S, EXACT && HALF>()> pre_pg;
+    PhaseGradPre<T, S, PG && pg_preload<T, S, EXACT && HALF>()> pre_pg;
     pre_pg.load(pg, j, [&](int i) { return frow + i; });
     auto store = [&](int i, cx<T> v) {
       if (valid && (EXACT || i < n_io)) {
         const cx<T> g = cscale(v, scale);
         if (out) out[frow + i] = g;
-        if (pg.grad) pre_pg.put(pg, i, j, frow + i, g);
+        if constexpr (PG) {
+          if (pg.grad) pre_pg.put(pg, i, j, frow + i, g);
+        }
       }
     };
     fft_line<T, 1, S, false, HALF>(lds, tw, j, load, store);
@@ -396,8 +400,8 @@ hipError_t launch_rs_rows_s(const cx<T>* in, cx<T>* out, int64_t w_bstride, int 
           constexpr int C2 = row_lines_two_per_cu<T, S, C>();
           if (C2 != C && !pg.grad) {
             const int tiles2 = nrows / C2;
-            hipLaunchKernelGGL((k_rs_rows<T, DIR, S, C2, true, true>), dim3(tiles2 * batch), dim3(C2 * S::threads),
-                               0, s, in, out, w_bstride, nrows, n_io, scale, tiles2, tw, pg);
+            hipLaunchKernelGGL((k_rs_rows<T, DIR, S, C2, true, true, false>), dim3(tiles2 * batch),
+                               dim3(C2 * S::threads), 0, s, in, out, w_bstride, nrows, n_io, scale, tiles2, tw, pg);
           } else {
             hipLaunchKernelGGL((k_rs_rows<T, DIR, S, C, true, true>), dim3(tiles * batch), dim3(RC::threads), 0, s,
                                in, out, w_bstride, nrows, n_io, scale, tiles, tw, pg);
@@ -734,7 +738,9 @@ constexpr bool bluestein_interleaved() {
   return COL || tw_per_thread<T>();
 }
 
-template <typename T, bool COL, class S, int C, bool HALF, bool EXACT = false>
+// PG = false: as for the row pass, an instance without the phase-gradient
+// epilogue (used for row lines; the column instance measured no better).
+template <typename T, bool COL, class S, int C, bool HALF, bool EXACT = false, bool PG = true>
 __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, bluestein_interleaved<T, COL>(), 1,
                                                             HALF ? (bluestein_interleaved<T, COL>() ? 4 : 3) : 2>())) void k_bluestein(const cx<T>* in, cx<T>* out, Lines li, Lines lo,
                                                               int nlines, int n_in, int n_out,
@@ -758,14 +764,16 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, bluestein_in
     return v;
   };
   auto mult = [&](int i, cx<T> v) -> cx<T> { return cmul(v, chat[i]); };
-  PhaseGradPre<T, S, pg_preload<T, S, EXACT && HALF>()> pre_pg;
+  PhaseGradPre<T, S, PG && pg_preload<T, S, EXACT && HALF>()> pre_pg;
   pre_pg.load(pg, j, [&](int i) { return line_off<COL>(lo, b, l, i); });
   auto store = [&](int i, cx<T> v) {
     if (valid && (EXACT || i < n_out)) {
       const int64_t o = line_off<COL>(lo, b, l, i);
       const cx<T> g = cmul(v, post[i]);
       if (out) out[o] = g;
-      if (pg.grad) pre_pg.put(pg, i, j, o, g);
+      if constexpr (PG) {
+        if (pg.grad) pre_pg.put(pg, i, j, o, g);
+      }
     }
   };
   conv_line<T, S, HALF, HALF>(lds, tw, j, load, mult, store);
@@ -779,8 +787,12 @@ hipError_t launch_bluestein_c(const cx<T>* in, cx<T>* out, Lines li, Lines lo, i
   constexpr bool can_half = S::rad[0] % 2 == 0 && S::rad[S::nst - 1] % 2 == 0;
   if constexpr (can_half) {
     if (2 * n_in == S::n && 2 * n_out == S::n && nlines % C == 0) {
-      hipLaunchKernelGGL((k_bluestein<T, COL, S, C, true, true>), dim3(tiles * batch), dim3(C * S::threads), 0, s, in,
-                         out, li, lo, nlines, n_in, n_out, pre, chat, post, tiles, tw, pg);
+      if (COL || pg.grad)
+        hipLaunchKernelGGL((k_bluestein<T, COL, S, C, true, true>), dim3(tiles * batch), dim3(C * S::threads), 0, s,
+                           in, out, li, lo, nlines, n_in, n_out, pre, chat, post, tiles, tw, pg);
+      else
+        hipLaunchKernelGGL((k_bluestein<T, COL, S, C, true, true, COL>), dim3(tiles * batch), dim3(C * S::threads),
+                           0, s, in, out, li, lo, nlines, n_in, n_out, pre, chat, post, tiles, tw, pg);
       return hipGetLastError();
     }
     if (2 * n_in <= S::n && 2 * n_out <= S::n) {
