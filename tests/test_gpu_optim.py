@@ -110,3 +110,27 @@ def test_stop_rule_on_device_vs_oracle(lp):
     # invalid arguments are refused before any launch
     with pytest.raises(ValueError):
         lp.prop_track_best(losses[0].double(), rule.best, rule.since.float())
+
+
+def test_stop_rule_many_items(lp):
+    """130 items (three blocks of the bookkeeping kernel, the last ragged),
+    patience 200 checked every 50 steps: each item's first stall on the
+    device equals the oracle's stop step for its sequence."""
+    import torch
+    rng = np.random.default_rng(9)
+    n, B = 1200, 130
+    scale = rng.uniform(100.0, 2000.0, B)
+    seqs = np.maximum(0.0, 1.0 - np.arange(n)[:, None] / scale[None, :]) + 0.02 * rng.random((n, B))
+    want = [oracle.stop_step(list(seqs[:, b]), 200, 50) for b in range(B)]
+    rule = lp.StopRule(patience=200, check_every=50, batch=B)
+    losses = torch.tensor(seqs, dtype=torch.float64, device="cuda")
+    first = [None] * B
+    for k in range(n):
+        rule.update(losses[k])
+        if (k + 1) % 50 == 0:
+            for b in np.flatnonzero(rule.stalled.numpy()):
+                if first[b] is None:
+                    first[b] = k + 1
+    say(f"items stalled: {sum(f is not None for f in first)} of {B}")
+    assert first == want
+    assert any(w is None for w in want) and any(w is not None for w in want)
