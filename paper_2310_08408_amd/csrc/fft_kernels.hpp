@@ -234,9 +234,9 @@ hipError_t launch_fft_lines(int n, bool col, const cx<T>* in, cx<T>* out, Lines 
   switch (n) {
 #define LP_CASE(N, ...)                                                                                          \
   case N:                                                                                                        \
-    return col ? launch_fft_lines_s<T, DIR, true, Sched<__VA_ARGS__>>(in, out, li, lo, nlines, n_in, n_out, scale, \
+    return col ? launch_fft_lines_s<T, DIR, true, SchedOf<T, Sched<__VA_ARGS__>>>(in, out, li, lo, nlines, n_in, n_out, scale, \
                                                                      batch, tw, s)                               \
-               : launch_fft_lines_s<T, DIR, false, Sched<__VA_ARGS__>>(in, out, li, lo, nlines, n_in, n_out,     \
+               : launch_fft_lines_s<T, DIR, false, SchedOf<T, Sched<__VA_ARGS__>>>(in, out, li, lo, nlines, n_in, n_out,     \
                                                                       scale, batch, tw, s);
     LP_LENGTHS(LP_CASE)
 #undef LP_CASE
@@ -431,7 +431,7 @@ hipError_t launch_rs_rows(int n, const cx<T>* in, cx<T>* out, int64_t w_bstride,
   pg.acc = pg_acc;
   switch (n) {
 #define LP_CASE(N, ...) \
-  case N: return launch_rs_rows_s<T, DIR, Sched<__VA_ARGS__>>(in, out, w_bstride, nrows, n_io, scale, batch, tw, s, pg);
+  case N: return launch_rs_rows_s<T, DIR, SchedOf<T, Sched<__VA_ARGS__>>>(in, out, w_bstride, nrows, n_io, scale, batch, tw, s, pg);
     LP_LENGTHS(LP_CASE)
 #undef LP_CASE
     default:
@@ -614,7 +614,7 @@ hipError_t launch_rs_cols(int My, cx<T>* W, int64_t bstride, int ncols, int n_va
   switch (My) {
 #define LP_CASE(N, ...) \
   case N:                                                                                                  \
-    return launch_rs_cols_s<T, Sched<__VA_ARGS__>>(W, bstride, ncols, n_valid, Sq, Mx, conj_spec, batch, tw, s, variant);
+    return launch_rs_cols_s<T, SchedOf<T, Sched<__VA_ARGS__>>>(W, bstride, ncols, n_valid, Sq, Mx, conj_spec, batch, tw, s, variant);
     LP_LENGTHS(LP_CASE)
 #undef LP_CASE
     default:
@@ -716,7 +716,7 @@ hipError_t launch_mix2_cols(int My, const cx<T>* a, const cx<T>* b, cx<T>* out, 
   switch (My) {
 #define LP_CASE(N, ...)                                                                                             \
   case N:                                                                                                           \
-    return launch_mix2_cols_s<T, Sched<__VA_ARGS__>>(a, b, out, bstride, ncols, n_valid, Sa, kind_a, ca, Sb, \
+    return launch_mix2_cols_s<T, SchedOf<T, Sched<__VA_ARGS__>>>(a, b, out, bstride, ncols, n_valid, Sa, kind_a, ca, Sb, \
                                                      kind_b, cb, conj_spec, Mx, batch, tw, s, variant);
     LP_LENGTHS(LP_CASE)
 #undef LP_CASE
@@ -843,9 +843,9 @@ hipError_t launch_bluestein(int L, bool col, const cx<T>* in, cx<T>* out, Lines 
   switch (L) {
 #define LP_CASE(N, ...)                                                                                             \
   case N:                                                                                                           \
-    return col ? launch_bluestein_s<T, true, Sched<__VA_ARGS__>>(in, out, li, lo, nlines, n_in, n_out, pre, chat,   \
+    return col ? launch_bluestein_s<T, true, SchedOf<T, Sched<__VA_ARGS__>>>(in, out, li, lo, nlines, n_in, n_out, pre, chat,   \
                                                                  post, batch, tw, s, variant, pg)                   \
-               : launch_bluestein_s<T, false, Sched<__VA_ARGS__>>(in, out, li, lo, nlines, n_in, n_out, pre, chat, \
+               : launch_bluestein_s<T, false, SchedOf<T, Sched<__VA_ARGS__>>>(in, out, li, lo, nlines, n_in, n_out, pre, chat, \
                                                                   post, batch, tw, s, 0, pg);
     LP_LENGTHS(LP_CASE)
 #undef LP_CASE
@@ -862,7 +862,7 @@ int col_pass_lines(int kind, int n, int variant) {
   switch (n) {
 #define LP_CASE(N, ...)                                                                             \
   case N: {                                                                                         \
-    using S = Sched<__VA_ARGS__>;                                                                   \
+    using S = SchedOf<T, Sched<__VA_ARGS__>>;                                                                   \
     constexpr int c0 = Cfg<T, S, true>::C, c1 = Cfg<T, S, true, 2, 512>::C,                         \
                   c2 = Cfg<T, S, true, 1, 1024>::C;                                                 \
     const int c = kind == 0 ? c0 : (kind == 1 ? c1 : c2);                                           \

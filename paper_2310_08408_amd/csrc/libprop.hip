@@ -114,7 +114,7 @@ int fft_len(int n) {
 // picks the layout by element type (Sched::twoff).
 static bool make_twiddles(int n, bool per_thread, std::vector<long double>& twr, std::vector<long double>& twi) {
   SchedInfo si;
-  if (!sched_info(n, &si)) return false;
+  if (!sched_info(n, &si, !per_thread)) return false;  // per-stage layout: FP64
   twr.clear();
   twi.clear();
   long ns = 1;
