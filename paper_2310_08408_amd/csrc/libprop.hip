@@ -108,13 +108,16 @@ int fft_len(int n) {
   return best;
 }
 
-// Twiddle table of a length's schedule: stage s >= 1 holds W_{Ns R}^{r k}
-// (forward sign), computed in long double, at off_s + k R + r (r = 0..R-1)
-// when per_thread, else at off_s + (r-1) Ns + k (r = 1..R-1); the engine
-// picks the layout by element type (Sched::twoff).
-static bool make_twiddles(int n, bool per_thread, std::vector<long double>& twr, std::vector<long double>& twi) {
+// Twiddle table of the schedule that element type T runs at length n:
+// stage s >= 1 holds W_{Ns R}^{r k} (forward sign), computed in long double,
+// at off_s + k R + r (r = 0..R-1) in the per-thread layout, else at
+// off_s + (r-1) Ns + k (r = 1..R-1); both the layout and the schedule follow
+// the element type, as in the engine (tw_per_thread, SchedOf).
+template <typename T>
+static bool make_twiddles(int n, std::vector<long double>& twr, std::vector<long double>& twi) {
+  constexpr bool per_thread = tw_per_thread<T>();
   SchedInfo si;
-  if (!sched_info(n, &si, !per_thread)) return false;  // per-stage layout: FP64
+  if (!sched_info(n, &si, sizeof(T) == 8)) return false;
   twr.clear();
   twi.clear();
   long ns = 1;
@@ -227,7 +230,7 @@ static int get_tw(int dev, int n, const cx<T>** tw) {
   if (it == C.plans.end()) {
     PlanEntry e;
     std::vector<long double> wr, wi;
-    if (!make_twiddles(n, tw_per_thread<T>(), wr, wi)) return PROP_ESHAPE;
+    if (!make_twiddles<T>(n, wr, wi)) return PROP_ESHAPE;
     std::vector<cx<T>> h(wr.size());
     for (size_t i = 0; i < wr.size(); ++i) {
       h[i].x = (T)wr[i];
