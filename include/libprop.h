@@ -29,10 +29,14 @@
  * torch tensor); the library neither retains nor frees it.  Inputs and
  * outputs must not overlap (PROP_EALIAS).  All calls are asynchronous on
  * `stream` (a hipStream_t; NULL = the legacy default stream).  Kernel
- * spectra, chirp vectors and twiddle tables are computed on first use and
- * cached per geometry (that first call synchronises its stream); workspace
- * is cached per stream.  Calls on one stream are ordered; calls on
- * different streams may run concurrently.
+ * spectra, chirp vectors and twiddle tables are computed on first use, on
+ * the caller's stream, and cached per geometry; a call on another stream
+ * waits for them on the device.  Spectra and chirp vectors live in a
+ * least-recently-used cache with a byte budget (prop_cache_set_limit);
+ * workspace is cached per stream.  Calls on one stream are ordered; calls
+ * on different streams may run concurrently.  A one-shot call may be
+ * captured into a hipGraph once the same geometry has been computed
+ * outside the capture.
  *
  * Status: 0 on success, > 0 success with a warning, < 0 error (nothing was
  * launched; outputs untouched).  Device-side numeric problems are not
@@ -58,7 +62,15 @@ enum {
   PROP_EDEVICE = -6       /* a HIP call failed; prop_last_device_error() has the code */
 };
 
-typedef enum { PROP_C64 = 0, PROP_C128 = 1 } prop_dtype;
+/* The two sentinels give the enum the value range of int32_t, so that an
+ * out-of-range value from a C caller stays defined in C++ and is rejected
+ * with PROP_EPARAM instead of being assumed away by the compiler. */
+typedef enum {
+  PROP_C64 = 0,
+  PROP_C128 = 1,
+  PROP_DTYPE_MIN_ENUM_ = -0x7fffffff - 1,
+  PROP_DTYPE_MAX_ENUM_ = 0x7fffffff
+} prop_dtype;
 
 /* Sampling grid: nx, ny samples with pitch dx, dy, centred at (cx, cy). */
 typedef struct {
@@ -350,8 +362,29 @@ int32_t prop_fft_length(int32_t n);
  * returns the size needed including the NUL. */
 int32_t prop_autotune_report(char* buf, int32_t cap);
 /* Free cached spectra, chirps, twiddles, workspaces and autotuner choices
- * (synchronises the device). */
+ * (synchronises the device).  Tables pinned by live plans are kept: their
+ * kernels and captured graphs address them until prop_plan_destroy. */
 void prop_cache_clear(void);
+/* Byte budget of the cached kernel spectra and zoom chirp vectors (default
+ * 8 GiB, or LIBPROP_CACHE_MB from the environment; bytes <= 0 restores the
+ * default).  Distances are optimised in every experiment of the paper
+ * (Results; Methods, the large-scale search space), and each new distance
+ * needs new tables; once the cached tables exceed the budget, the least
+ * recently used ones that no plan pins and no call in progress uses are
+ * freed, down to 3/4 of the budget.  Each such eviction round first
+ * synchronises the device once (enqueued kernels may still read a
+ * victim).  Pinned tables never count against eviction. */
+void prop_cache_set_limit(int64_t bytes);
+typedef struct {
+  int64_t table_bytes;    /* bytes of cached spectra and zoom vectors */
+  int64_t limit;          /* current budget */
+  int64_t spectra, zooms, twiddles; /* cached entries */
+  int64_t pinned;         /* entries pinned by live plans */
+  int64_t evictions;      /* entries evicted so far */
+  int64_t eviction_syncs; /* device synchronisations of eviction rounds */
+} prop_cache_stats;
+/* Snapshot of the cache (host struct owned by the caller; NULL: no-op). */
+void prop_cache_info(prop_cache_stats* out);
 /* Text for a status code. */
 const char* prop_status_string(int status);
 /* hipError_t of the last PROP_EDEVICE on this thread (0 if none). */
@@ -362,7 +395,9 @@ int prop_last_device_error(void);
  * evaluates many candidate setups per optimisation step: Results, batches
  * of setups sharing parameters; Methods, compile-once-per-shape reuse).
  * prop_plan_create validates every setup, computes all kernel spectra, chirp
- * vectors and twiddle tables, and allocates all workspace, so that
+ * vectors and twiddle tables (pinned in the cache for the plan's lifetime:
+ * neither eviction nor prop_cache_clear frees them), and allocates all
+ * workspace, so that
  * prop_plan_forward / prop_plan_adjoint only enqueue kernels: they neither
  * allocate nor synchronise, and may be captured into a caller's hipGraph.
  * With PROP_PLAN_GRAPH the plan captures its own forward and adjoint once
@@ -389,6 +424,11 @@ enum { PROP_OP_RS = 0, PROP_OP_CZT = 1, PROP_OP_VRS = 2, PROP_OP_VCZT = 3 };
  * prop_autotune_report); they allocate scratch memory and synchronise the
  * stream.  Later calls (and the captured graph) use the chosen variants. */
 #define PROP_PLAN_AUTOTUNE 2u
+/* PROP_PLAN_FAULT_NOMEM (fault injection, for testing callers' error paths):
+ * prop_plan_create fails as if its workspace allocation had failed on an
+ * exhausted device: it returns PROP_ENOMEM, sets *plan to NULL, frees
+ * everything it allocated and launches nothing on the caller's buffers. */
+#define PROP_PLAN_FAULT_NOMEM 0x100u
 
 typedef struct {
   int32_t op;           /* PROP_OP_* */

@@ -25,7 +25,8 @@ __all__ = [
     "prop_softmin", "prop_adam_step", "Adam", "prop_track_best", "StopRule", "prop_sampling_check",
     "prop_fft_length", "prop_cache_clear", "prop_trace_enable", "prop_trace_read", "prop_trace_only", "prop_autotune_report",
     "PropError", "PropWarning", "library", "Plan", "Setup", "PROP_OP_RS", "PROP_OP_CZT", "PROP_OP_VRS",
-    "PROP_OP_VCZT", "PROP_PLAN_GRAPH", "PROP_PLAN_AUTOTUNE",
+    "PROP_OP_VCZT", "PROP_PLAN_GRAPH", "PROP_PLAN_AUTOTUNE", "PROP_PLAN_FAULT_NOMEM", "prop_cache_set_limit",
+    "prop_cache_info",
 ]
 
 
@@ -45,11 +46,50 @@ def _real_dtype(t: torch.Tensor):
     return torch.float32 if t.dtype == torch.complex64 else torch.float64
 
 
-def _dev(t: torch.Tensor):
+def _dev(t: torch.Tensor, name: str = "tensor"):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor, got {type(t).__name__}")
     if not t.is_cuda:
-        raise ValueError("libprop operates on GPU tensors")
+        raise ValueError(f"{name}: libprop operates on GPU tensors")
     if not t.is_contiguous():
-        raise ValueError("libprop needs contiguous tensors")
+        raise ValueError(f"{name}: libprop needs contiguous tensors")
+    return t
+
+
+def _arg(t, name, ref, grid=None, items=None, real=False, dtype=None):
+    """Check one tensor argument against the call's reference tensor before
+    its pointer reaches the library: a contiguous GPU tensor on ref's device,
+    of ref's dtype (its real counterpart with real=True, or `dtype`), and --
+    with `grid` -- shaped [..., ny, nx] with `items` planes (every pointer
+    the library receives addresses items * ny * nx elements)."""
+    _dev(t, name)
+    if t.device != ref.device:
+        raise ValueError(f"{name}: on {t.device}, the call's fields are on {ref.device}")
+    want = dtype if dtype is not None else (_real_dtype(ref) if real else ref.dtype)
+    if t.dtype != want:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {want}")
+    if grid is not None:
+        ny, nx = int(grid.ny), int(grid.nx)
+        if t.dim() < 2 or t.shape[-1] != nx or t.shape[-2] != ny:
+            raise ValueError(f"{name}: shape {tuple(t.shape)} does not end in (ny, nx) = ({ny}, {nx})")
+        if items is not None and t.numel() != items * ny * nx:
+            raise ValueError(f"{name}: {t.numel() // (ny * nx)} planes, expected {items}")
+    return t
+
+
+class _Plane:
+    """(ny, nx) of a reference tensor's last two dimensions, as a grid."""
+
+    def __init__(self, t):
+        if t.dim() < 2:
+            raise ValueError(f"expected [..., ny, nx], got shape {tuple(t.shape)}")
+        self.ny, self.nx = int(t.shape[-2]), int(t.shape[-1])
+
+
+def _field(t, name="u"):
+    """The reference field of a call: a contiguous complex GPU tensor."""
+    _dev(t, name)
+    _dtype_code(t)
     return t
 
 
@@ -72,9 +112,9 @@ def _like(t: torch.Tensor, g, out):
     shape = tuple(t.shape[:-2]) + (int(g.ny), int(g.nx))
     if out is None:
         return torch.empty(shape, dtype=t.dtype, device=t.device)
-    _dev(out)
-    if tuple(out.shape) != shape or out.dtype != t.dtype:
-        raise ValueError("out has the wrong shape or dtype")
+    _arg(out, "out", t)
+    if tuple(out.shape) != shape:
+        raise ValueError(f"out: shape {tuple(out.shape)}, expected {shape}")
     return out
 
 
@@ -83,7 +123,7 @@ def _like(t: torch.Tensor, g, out):
 def rs_propagate(u, grid, wavelength, z, out=None):
     """Scalar RS over z onto the input grid (see include/libprop.h)."""
     lib = library()
-    _dev(u)
+    _field(u)
     out = _like(u, grid, out)
     with torch.cuda.device(u.device):
         st = lib.rs_propagate(_dtype_code(u), _ptr(u), _ptr(out), ctypes.byref(_lib.grid(grid)), float(wavelength),
@@ -94,7 +134,7 @@ def rs_propagate(u, grid, wavelength, z, out=None):
 
 def rs_adjoint(g_out, grid, wavelength, z, out=None):
     lib = library()
-    _dev(g_out)
+    _field(g_out, "g_out")
     out = _like(g_out, grid, out)
     with torch.cuda.device(g_out.device):
         st = lib.rs_adjoint(_dtype_code(g_out), _ptr(g_out), _ptr(out), ctypes.byref(_lib.grid(grid)),
@@ -106,7 +146,7 @@ def rs_adjoint(g_out, grid, wavelength, z, out=None):
 def czt_propagate(u, grid_in, window, wavelength, z, out=None):
     """Fresnel/CZT propagation over z onto ``window``."""
     lib = library()
-    _dev(u)
+    _field(u)
     b = _batch(u, grid_in)
     out = _like(u, window, out)
     with torch.cuda.device(u.device):
@@ -118,7 +158,7 @@ def czt_propagate(u, grid_in, window, wavelength, z, out=None):
 
 def czt_adjoint(g_out, grid_in, window, wavelength, z, out=None):
     lib = library()
-    _dev(g_out)
+    _field(g_out, "g_out")
     b = _batch(g_out, window)
     out = _like(g_out, grid_in, out)
     with torch.cuda.device(g_out.device):
@@ -130,11 +170,16 @@ def czt_adjoint(g_out, grid_in, window, wavelength, z, out=None):
 
 # --------------------------------------------------------------- VRS / VCZT --
 
-def _phase_grad_out(u, grad, g_u):
+def _phase_grad_out(u, grid, grad, g_u):
+    b = _batch(u, grid)
     if grad is None:
         grad = torch.empty(u.shape, dtype=_real_dtype(u), device=u.device)
+    _arg(grad, "grad", u, grid, b, real=True)
     gu = torch.empty_like(u) if g_u is True else g_u
-    return grad, (gu if gu is not None and gu is not False else None)
+    gu = gu if gu is not None and gu is not False else None
+    if gu is not None:
+        _arg(gu, "g_u", u, grid, b)
+    return grad, gu
 
 
 def rs_adjoint_phase_grad(g_out, u, grid, wavelength, z, grad=None, accumulate=False, g_u=None):
@@ -142,9 +187,10 @@ def rs_adjoint_phase_grad(g_out, u, grid, wavelength, z, grad=None, accumulate=F
     g_U = rs_adjoint(g_out).  g_u=True also returns g_U (or pass a tensor).
     Returns (grad, g_U or None)."""
     lib = library()
-    _dev(g_out), _dev(u)
-    grad, gu = _phase_grad_out(u, grad, g_u)
+    _field(u)
     b = _batch(u, grid)
+    _arg(g_out, "g_out", u, grid, b)
+    grad, gu = _phase_grad_out(u, grid, grad, g_u)
     with torch.cuda.device(u.device):
         st = lib.rs_adjoint_phase_grad(_dtype_code(u), _ptr(g_out), _ptr(u), _ptr(gu), _ptr(grad),
                                        1 if accumulate else 0, ctypes.byref(_lib.grid(grid)), float(wavelength),
@@ -156,9 +202,10 @@ def rs_adjoint_phase_grad(g_out, u, grid, wavelength, z, grad=None, accumulate=F
 def czt_adjoint_phase_grad(g_out, u, grid_in, window, wavelength, z, grad=None, accumulate=False, g_u=None):
     """CZT adjoint fused with the SLM phase gradient (see rs_adjoint_phase_grad)."""
     lib = library()
-    _dev(g_out), _dev(u)
-    grad, gu = _phase_grad_out(u, grad, g_u)
+    _field(u)
     b = _batch(u, grid_in)
+    _arg(g_out, "g_out", u, window, b)
+    grad, gu = _phase_grad_out(u, grid_in, grad, g_u)
     with torch.cuda.device(u.device):
         st = lib.czt_adjoint_phase_grad(_dtype_code(u), _ptr(g_out), _ptr(u), _ptr(gu), _ptr(grad),
                                         1 if accumulate else 0, ctypes.byref(_lib.grid(grid_in)),
@@ -171,8 +218,9 @@ def rs_grad_z(u, g_out, grid, wavelength, z):
     """dL/dz per batch item (float64 tensor [batch]) for the RS propagation of
     u with output gradient seed g_out."""
     lib = library()
-    _dev(u), _dev(g_out)
+    _field(u)
     b = _batch(u, grid)
+    _arg(g_out, "g_out", u, grid, b)
     dz = torch.empty((b,), dtype=torch.float64, device=u.device)
     with torch.cuda.device(u.device):
         st = lib.rs_grad_z(_dtype_code(u), _ptr(u), _ptr(g_out), _ptr(dz), ctypes.byref(_lib.grid(grid)),
@@ -185,10 +233,11 @@ def czt_grad_z(u, g_out, grid_in, window, wavelength, z, u_out=None):
     """dL/dz per batch item for the CZT propagation of u onto `window` with
     output gradient seed g_out; u_out = czt_propagate(u, ...) if available."""
     lib = library()
-    _dev(u), _dev(g_out)
-    if u_out is not None:
-        _dev(u_out)
+    _field(u)
     b = _batch(u, grid_in)
+    _arg(g_out, "g_out", u, window, b)
+    if u_out is not None:
+        _arg(u_out, "u_out", u, window, b)
     dz = torch.empty((b,), dtype=torch.float64, device=u.device)
     with torch.cuda.device(u.device):
         st = lib.czt_grad_z(_dtype_code(u), _ptr(u), _ptr(u_out), _ptr(g_out), _ptr(dz),
@@ -200,8 +249,9 @@ def czt_grad_z(u, g_out, grid_in, window, wavelength, z, u_out=None):
 
 def vrs_propagate(ex, ey, grid, wavelength, z):
     lib = library()
-    _dev(ex), _dev(ey)
+    _field(ex, "ex")
     b = _batch(ex, grid)
+    _arg(ey, "ey", ex, grid, b)
     ox, oy, oz = (torch.empty_like(ex) for _ in range(3))
     with torch.cuda.device(ex.device):
         st = lib.vrs_propagate(_dtype_code(ex), _ptr(ex), _ptr(ey), _ptr(ox), _ptr(oy), _ptr(oz),
@@ -212,9 +262,9 @@ def vrs_propagate(ex, ey, grid, wavelength, z):
 
 def vrs_adjoint(gx, gy, gz, grid, wavelength, z):
     lib = library()
-    for t in (gx, gy, gz):
-        _dev(t)
+    _field(gx, "gx")
     b = _batch(gx, grid)
+    _arg(gy, "gy", gx, grid, b), _arg(gz, "gz", gx, grid, b)
     gex, gey = torch.empty_like(gx), torch.empty_like(gx)
     with torch.cuda.device(gx.device):
         st = lib.vrs_adjoint(_dtype_code(gx), _ptr(gx), _ptr(gy), _ptr(gz), _ptr(gex), _ptr(gey),
@@ -233,8 +283,9 @@ def _lens(lens):
 def vczt_propagate(ex, ey, grid_in, window, wavelength, z=0.0, lens=None):
     """Vectorial CZT; ``lens=(na, f)`` selects the focusing (objective) mode."""
     lib = library()
-    _dev(ex), _dev(ey)
+    _field(ex, "ex")
     b = _batch(ex, grid_in)
+    _arg(ey, "ey", ex, grid_in, b)
     ox, oy, oz = (_like(ex, window, None) for _ in range(3))
     with torch.cuda.device(ex.device):
         st = lib.vczt_propagate(_dtype_code(ex), _ptr(ex), _ptr(ey), _ptr(ox), _ptr(oy), _ptr(oz),
@@ -246,9 +297,9 @@ def vczt_propagate(ex, ey, grid_in, window, wavelength, z=0.0, lens=None):
 
 def vczt_adjoint(gx, gy, gz, grid_in, window, wavelength, z=0.0, lens=None):
     lib = library()
-    for t in (gx, gy, gz):
-        _dev(t)
+    _field(gx, "gx")
     b = _batch(gx, window)
+    _arg(gy, "gy", gx, window, b), _arg(gz, "gz", gx, window, b)
     gex, gey = _like(gx, grid_in, None), _like(gx, grid_in, None)
     with torch.cuda.device(gx.device):
         st = lib.vczt_adjoint(_dtype_code(gx), _ptr(gx), _ptr(gy), _ptr(gz), _ptr(gex), _ptr(gey),
@@ -285,13 +336,15 @@ def prop_source_radial(grid, w0, batch=1, dtype=torch.complex64, device="cuda"):
 def prop_modulate(u, phase, out=None):
     """u * exp(i phase); phase [..., ny, nx] (real) broadcast over the batch if it has one item."""
     lib = library()
-    _dev(u), _dev(phase)
-    if phase.dtype != _real_dtype(u):
-        raise TypeError("phase dtype must match the field precision")
-    npix = u.shape[-1] * u.shape[-2]
+    _field(u)
+    pl = _Plane(u)
+    npix = pl.nx * pl.ny
     batch = u.numel() // npix
+    _arg(phase, "phase", u, pl, None, real=True)
     pb = phase.numel() // npix
-    out = torch.empty_like(u) if out is None else out
+    if pb not in (1, batch):
+        raise ValueError(f"phase: {pb} planes, expected 1 or {batch}")
+    out = torch.empty_like(u) if out is None else _arg(out, "out", u, pl, batch)
     with torch.cuda.device(u.device):
         st = lib.prop_modulate(_dtype_code(u), _ptr(u), _ptr(phase), _ptr(out), npix, batch, pb, _stream(u))
     _lib.check("prop_modulate", st)
@@ -301,13 +354,15 @@ def prop_modulate(u, phase, out=None):
 def prop_modulate_adjoint(g, phase, out=None):
     """g * exp(-i phase): the adjoint of prop_modulate (same broadcasting)."""
     lib = library()
-    _dev(g), _dev(phase)
-    if phase.dtype != _real_dtype(g):
-        raise TypeError("phase dtype must match the field precision")
-    npix = g.shape[-1] * g.shape[-2]
+    _field(g, "g")
+    pl = _Plane(g)
+    npix = pl.nx * pl.ny
     batch = g.numel() // npix
+    _arg(phase, "phase", g, pl, None, real=True)
     pb = phase.numel() // npix
-    out = torch.empty_like(g) if out is None else out
+    if pb not in (1, batch):
+        raise ValueError(f"phase: {pb} planes, expected 1 or {batch}")
+    out = torch.empty_like(g) if out is None else _arg(out, "out", g, pl, batch)
     with torch.cuda.device(g.device):
         st = lib.prop_modulate_adjoint(_dtype_code(g), _ptr(g), _ptr(phase), _ptr(out), npix, batch, pb, _stream(g))
     _lib.check("prop_modulate_adjoint", st)
@@ -318,13 +373,16 @@ def prop_phase_grad_sum(g_u, u, grad=None, accumulate=False):
     """sum over the batch of Im(g_u conj(u)): the gradient of a phase shared
     by all batch items (real [ny, nx])."""
     lib = library()
-    _dev(g_u), _dev(u)
-    npix = u.shape[-1] * u.shape[-2]
+    _field(u)
+    pl = _Plane(u)
+    npix = pl.nx * pl.ny
     batch = u.numel() // npix
+    _arg(g_u, "g_u", u, pl, batch)
     if grad is None:
         grad = torch.empty(tuple(u.shape[-2:]), dtype=_real_dtype(u), device=u.device)
+    _arg(grad, "grad", u, pl, 1, real=True)
     with torch.cuda.device(u.device):
-        st = lib.prop_phase_grad_sum(_dtype_code(u), _ptr(g_u.contiguous()), _ptr(u.contiguous()), _ptr(grad), npix,
+        st = lib.prop_phase_grad_sum(_dtype_code(u), _ptr(g_u), _ptr(u), _ptr(grad), npix,
                                      batch, 1 if accumulate else 0, _stream(u))
     _lib.check("prop_phase_grad_sum", st)
     return grad
@@ -334,14 +392,22 @@ def prop_scale_items(planes, scale, out=None):
     """Each plane's batch item b times scale[b] (float64 [batch]); into new
     planes, or into `out` (which may be `planes`: in place)."""
     lib = library()
-    ref = planes[0]
-    npix = ref.shape[-1] * ref.shape[-2]
+    planes = [t.contiguous() for t in planes]
+    ref = _field(planes[0], "planes[0]")
+    pl = _Plane(ref)
+    npix = pl.nx * pl.ny
     batch = ref.numel() // npix
+    for k, t in enumerate(planes):
+        _arg(t, f"planes[{k}]", ref, pl, batch)
     scale = scale.to(torch.float64).contiguous()
+    _arg(scale, "scale", ref, dtype=torch.float64)
     if scale.numel() != batch:
         raise ValueError("scale must have one entry per batch item")
-    planes = [t.contiguous() for t in planes]
     out = [torch.empty_like(t) for t in planes] if out is None else list(out)
+    if len(out) != len(planes):
+        raise ValueError("out must hold one plane per input plane")
+    for k, t in enumerate(out):
+        _arg(t, f"out[{k}]", ref, pl, batch)
     with torch.cuda.device(ref.device):
         st = lib.prop_scale_items(_dtype_code(ref), _ptr_array(planes), _ptr_array(out), len(planes), _ptr(scale),
                                   npix, batch, _stream(ref))
@@ -352,11 +418,14 @@ def prop_scale_items(planes, scale, out=None):
 def prop_phase_grad(g_u, u, grad=None, accumulate=False):
     """Im(g_u conj(u)) (real, same shape as u)."""
     lib = library()
-    _dev(g_u), _dev(u)
-    npix = u.shape[-1] * u.shape[-2]
+    _field(u)
+    pl = _Plane(u)
+    npix = pl.nx * pl.ny
     batch = u.numel() // npix
+    _arg(g_u, "g_u", u, pl, batch)
     if grad is None:
         grad = torch.empty(u.shape, dtype=_real_dtype(u), device=u.device)
+    _arg(grad, "grad", u, pl, batch, real=True)
     with torch.cuda.device(u.device):
         st = lib.prop_phase_grad(_dtype_code(u), _ptr(g_u), _ptr(u), _ptr(grad), npix, batch, int(accumulate),
                                  _stream(u))
@@ -366,9 +435,11 @@ def prop_phase_grad(g_u, u, grad=None, accumulate=False):
 
 def prop_waveplate(ex, ey, eta, theta):
     lib = library()
-    _dev(ex), _dev(ey)
-    npix = ex.shape[-1] * ex.shape[-2]
+    _field(ex, "ex")
+    pl = _Plane(ex)
+    npix = pl.nx * pl.ny
     batch = ex.numel() // npix
+    _arg(ey, "ey", ex, pl, batch)
     ox, oy = torch.empty_like(ex), torch.empty_like(ey)
     with torch.cuda.device(ex.device):
         st = lib.prop_waveplate(_dtype_code(ex), _ptr(ex), _ptr(ey), _ptr(ox), _ptr(oy), float(eta), float(theta),
@@ -380,10 +451,11 @@ def prop_waveplate(ex, ey, eta, theta):
 def prop_waveplate_adjoint(gx, gy, ex, ey, eta, theta):
     """Returns (g_ex, g_ey, dparams[batch, 2] = (dL/deta, dL/dtheta))."""
     lib = library()
-    for t in (gx, gy, ex, ey):
-        _dev(t)
-    npix = ex.shape[-1] * ex.shape[-2]
+    _field(ex, "ex")
+    pl = _Plane(ex)
+    npix = pl.nx * pl.ny
     batch = ex.numel() // npix
+    _arg(ey, "ey", ex, pl, batch), _arg(gx, "gx", ex, pl, batch), _arg(gy, "gy", ex, pl, batch)
     gex, gey = torch.empty_like(gx), torch.empty_like(gy)
     dp = torch.empty((batch, 2), dtype=torch.float64, device=ex.device)
     with torch.cuda.device(ex.device):
@@ -402,11 +474,13 @@ def prop_waveplate_batched(ex, ey, params):
     [batch, 2] on the fields' device.  Returns (ox, oy)."""
     lib = library()
     ex, ey, params = ex.contiguous(), ey.contiguous(), params.contiguous()
-    for t in (ex, ey, params):
-        _dev(t)
-    npix = ex.shape[-1] * ex.shape[-2]
+    _field(ex, "ex")
+    pl = _Plane(ex)
+    npix = pl.nx * pl.ny
     batch = _items(ex, npix)
-    if params.dtype != torch.float64 or params.numel() != 2 * batch:
+    _arg(ey, "ey", ex, pl, batch)
+    _arg(params, "params", ex, dtype=torch.float64)
+    if params.numel() != 2 * batch:
         raise ValueError("params must be float64 [batch, 2]")
     ox, oy = torch.empty_like(ex), torch.empty_like(ey)
     with torch.cuda.device(ex.device):
@@ -422,15 +496,20 @@ def prop_waveplate_batched_adjoint(gx, gy, ex, ey, params, grad=True, shared_inp
     (g_A, None, dparams), g_A = g_ex + g_ey."""
     lib = library()
     gx, gy, params = gx.contiguous(), gy.contiguous(), params.contiguous()
-    npix = gx.shape[-1] * gx.shape[-2]
+    _field(gx, "gx")
+    pl = _Plane(gx)
+    npix = pl.nx * pl.ny
     batch = _items(gx, npix)
-    if params.dtype != torch.float64 or params.numel() != 2 * batch:
+    _arg(gy, "gy", gx, pl, batch)
+    _arg(params, "params", gx, dtype=torch.float64)
+    if params.numel() != 2 * batch:
         raise ValueError("params must be float64 [batch, 2]")
     gex = torch.empty_like(gx)
     gey = None if shared_input else torch.empty_like(gy)
     dp = torch.empty((batch, 2), dtype=torch.float64, device=gx.device) if grad else None
     if grad:
         ex, ey = ex.contiguous(), ey.contiguous()
+        _arg(ex, "ex", gx, pl, batch), _arg(ey, "ey", gx, pl, batch)
     with torch.cuda.device(gx.device):
         st = lib.prop_waveplate_batched_adjoint(_dtype_code(gx), _ptr(gx), _ptr(gy), _ptr(ex) if grad else None,
                                                 _ptr(ey) if grad else None, _ptr(gex),
@@ -450,15 +529,20 @@ def prop_beam_splitter(a, b, alpha):
     dark port).  Returns (c, d) as lists of planes."""
     lib = library()
     a, b = _port(a), _port(b)
-    ref = (a or b)[0]
+    if not (a or b):
+        raise ValueError("at least one input port must carry a field")
+    ref = _field((a or b)[0], "port")
     ncomp = len(a or b)
-    for t in (a or []) + (b or []):
-        _dev(t)
-    alpha = alpha.contiguous()
-    _dev(alpha)
-    npix = ref.shape[-1] * ref.shape[-2]
+    if a and b and len(a) != len(b):
+        raise ValueError("both ports must have the same number of components")
+    pl = _Plane(ref)
+    npix = pl.nx * pl.ny
     batch = _items(ref, npix)
-    if alpha.dtype != torch.float64 or alpha.numel() != batch:
+    for k, t in enumerate((a or []) + (b or [])):
+        _arg(t, f"port plane {k}", ref, pl, batch)
+    alpha = alpha.contiguous()
+    _arg(alpha, "alpha", ref, dtype=torch.float64)
+    if alpha.numel() != batch:
         raise ValueError("alpha must be float64 [batch]")
     c = [torch.empty_like(ref) for _ in range(ncomp)]
     d = [torch.empty_like(ref) for _ in range(ncomp)]
@@ -475,11 +559,17 @@ def prop_beam_splitter_adjoint(gc, gd, a, b, alpha, want=(True, True), grad=True
     lib = library()
     gc, gd = _port(gc), _port(gd)
     a, b = _port(a), _port(b)
-    ref, ncomp = gc[0], len(gc)
-    alpha = alpha.contiguous()
-    npix = ref.shape[-1] * ref.shape[-2]
+    ref, ncomp = _field(gc[0], "gc[0]"), len(gc)
+    pl = _Plane(ref)
+    npix = pl.nx * pl.ny
     batch = _items(ref, npix)
-    if alpha.dtype != torch.float64 or alpha.numel() != batch:
+    if len(gd) != ncomp or (a and len(a) != ncomp) or (b and len(b) != ncomp):
+        raise ValueError("every port must have the same number of components")
+    for k, t in enumerate(gc + gd + (a or []) + (b or [])):
+        _arg(t, f"port plane {k}", ref, pl, batch)
+    alpha = alpha.contiguous()
+    _arg(alpha, "alpha", ref, dtype=torch.float64)
+    if alpha.numel() != batch:
         raise ValueError("alpha must be float64 [batch]")
     ga = [torch.empty_like(ref) for _ in range(ncomp)] if want[0] else None
     gb = [torch.empty_like(ref) for _ in range(ncomp)] if want[1] else None
@@ -499,10 +589,11 @@ def prop_spot_loss(ex, ey, ez, window, wavelength, w_fz=0.0, seeds=True):
     result columns: loss, sigma^2, F_z, P, Xbar - cx, Ybar - cy, 0, 0.
     """
     lib = library()
-    _dev(ex), _dev(ey)
-    if ez is not None:
-        _dev(ez)
+    _field(ex, "ex")
     b = _batch(ex, window)
+    _arg(ey, "ey", ex, window, b)
+    if ez is not None:
+        _arg(ez, "ez", ex, window, b)
     res = torch.empty((b, 8), dtype=torch.float64, device=ex.device)
     gx = gy = gz = None
     if seeds:
@@ -530,11 +621,12 @@ def prop_density_loss(comps, eps, dep=None, beta=1.0, seeds=True):
     lib = library()
     comps = [c.contiguous() for c in comps]
     dep = [d.contiguous() for d in (dep or [])]
-    for t in comps + dep:
-        _dev(t)
-    ref = comps[0]
-    npix = ref.shape[-1] * ref.shape[-2]
+    ref = _field(comps[0], "comps[0]")
+    pl = _Plane(ref)
+    npix = pl.nx * pl.ny
     batch = ref.numel() // npix
+    for k, t in enumerate(comps + dep):
+        _arg(t, f"component {k}", ref, pl, batch)
     res = torch.empty((batch, 4), dtype=torch.float64, device=ref.device)
     gs = [torch.empty_like(c) for c in comps] if seeds else []
     gd = [torch.empty_like(d) for d in dep] if seeds else []
@@ -657,6 +749,18 @@ def prop_cache_clear() -> None:
     library().prop_cache_clear()
 
 
+def prop_cache_set_limit(nbytes: int) -> None:
+    """Byte budget of the cached kernel spectra and zoom vectors (<= 0: default)."""
+    library().prop_cache_set_limit(int(nbytes))
+
+
+def prop_cache_info() -> dict:
+    """Snapshot of the table cache (bytes, limit, entries, pins, evictions)."""
+    st = _lib.prop_cache_stats()
+    library().prop_cache_info(ctypes.byref(st))
+    return {name: int(getattr(st, name)) for name, _ in _lib.prop_cache_stats._fields_}
+
+
 def prop_trace_enable(on: bool = True) -> None:
     library().prop_trace_enable(1 if on else 0)
 
@@ -691,6 +795,7 @@ def prop_autotune_report() -> str:
 PROP_OP_RS, PROP_OP_CZT, PROP_OP_VRS, PROP_OP_VCZT = 0, 1, 2, 3
 PROP_PLAN_GRAPH = 1
 PROP_PLAN_AUTOTUNE = 2
+PROP_PLAN_FAULT_NOMEM = 0x100
 
 
 class Setup:
@@ -708,10 +813,37 @@ class Setup:
         self.wavelength, self.z, self.lens, self.lens_f = wavelength, z, lens, lens_f
         self.phase, self.grad_phase = phase, grad_phase
 
-    def _struct(self):
+    def _struct(self, dtype, device):
+        """The prop_setup of this setup, after checking every tensor against
+        the plan's dtype and device and the setup's grids and batch."""
+        vec = self.op in (PROP_OP_VRS, PROP_OP_VCZT)
+        nin, nout = (2, 3) if vec else (1, 1)
+        if self.op not in (PROP_OP_RS, PROP_OP_CZT, PROP_OP_VRS, PROP_OP_VCZT):
+            raise ValueError(f"unknown op {self.op}")
+        if len(self.inputs) != nin or len(self.outputs) != nout or len(self.grad_outputs) != nout:
+            raise ValueError(f"op {self.op} takes {nin} inputs, {nout} outputs and {nout} output gradients")
+        if self.grad_inputs and len(self.grad_inputs) != nin:
+            raise ValueError(f"op {self.op} takes {nin} input gradients")
+        ref = _field(self.inputs[0], "inputs[0]")
+        if ref.dtype != dtype:
+            raise ValueError(f"setup dtype {ref.dtype} differs from the plan's {dtype}")
+        if ref.device != device:
+            raise ValueError(f"setup tensors on {ref.device}, the plan runs on {device}")
+        b = _batch(ref, self.grid)
+        out_grid = self.window if self.op in (PROP_OP_CZT, PROP_OP_VCZT) else self.grid
+        if out_grid is None:
+            raise ValueError("CZT and VCZT setups need an output window")
+        for name, ts, g in (("inputs", self.inputs, self.grid), ("outputs", self.outputs, out_grid),
+                            ("grad_outputs", self.grad_outputs, out_grid), ("grad_inputs", self.grad_inputs, self.grid)):
+            for i, t in enumerate(ts):
+                if t is not None:
+                    _arg(t, f"{name}[{i}]", ref, g, b)
+        for name, t in (("phase", self.phase), ("grad_phase", self.grad_phase)):
+            if t is not None:
+                _arg(t, name, ref, self.grid, b, real=True)
         s = _lib.prop_setup()
         s.op = self.op
-        s.batch = _batch(self.inputs[0], self.grid)
+        s.batch = b
         s.g_in = _lib.grid(self.grid)
         if self.window is not None:
             s.win = _lib.grid(self.window)
@@ -722,13 +854,13 @@ class Setup:
         s.lens_f = float(self.lens_f)
         s.phase = self.phase.data_ptr() if self.phase is not None else None
         for i, t in enumerate(self.inputs):
-            s.in_[i] = _dev(t).data_ptr()
+            s.in_[i] = t.data_ptr()
         for i, t in enumerate(self.outputs):
-            s.out[i] = _dev(t).data_ptr()
+            s.out[i] = t.data_ptr()
         for i, t in enumerate(self.grad_outputs):
-            s.gout[i] = _dev(t).data_ptr()
+            s.gout[i] = t.data_ptr()
         for i, t in enumerate(self.grad_inputs):
-            s.gin[i] = _dev(t).data_ptr() if t is not None else None
+            s.gin[i] = t.data_ptr() if t is not None else None
         s.grad_phase = self.grad_phase.data_ptr() if self.grad_phase is not None else None
         return s
 
@@ -736,17 +868,21 @@ class Setup:
 class Plan:
     """A prop_plan over a list of Setups (keeps their tensors alive)."""
 
-    def __init__(self, setups, dtype=torch.complex64, graph=False, device=None, autotune=False):
+    def __init__(self, setups, dtype=torch.complex64, graph=False, device=None, autotune=False, flags=0):
         lib = library()
         self.setups = list(setups)
-        arr = (_lib.prop_setup * len(self.setups))(*[s._struct() for s in self.setups])
+        if not self.setups:
+            raise ValueError("a plan needs at least one setup")
+        if dtype not in (torch.complex64, torch.complex128):
+            raise TypeError(f"plan dtype must be complex64 or complex128, got {dtype}")
+        self.device = torch.device(device) if device is not None else self.setups[0].inputs[0].device
+        arr = (_lib.prop_setup * len(self.setups))(*[s._struct(dtype, self.device) for s in self.setups])
         self._arr = arr
         h = ctypes.c_void_p()
         code = _lib.PROP_C64 if dtype == torch.complex64 else _lib.PROP_C128
-        self.device = device or self.setups[0].inputs[0].device
+        fl = (PROP_PLAN_GRAPH if graph else 0) | (PROP_PLAN_AUTOTUNE if autotune else 0) | int(flags)
         with torch.cuda.device(self.device):
-            st = lib.prop_plan_create(code, ctypes.cast(arr, ctypes.c_void_p), len(self.setups),
-                                      (PROP_PLAN_GRAPH if graph else 0) | (PROP_PLAN_AUTOTUNE if autotune else 0),
+            st = lib.prop_plan_create(code, ctypes.cast(arr, ctypes.c_void_p), len(self.setups), fl,
                                       ctypes.byref(h))
         _lib.check("prop_plan_create", st)
         self._h = h

@@ -13,7 +13,9 @@ import warnings
 import torch  # noqa: F401  (must precede loading libprop.so)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libprop.so")
+# LIBPROP_PATH selects another build of the same library (the host-sanitized
+# variant of the ABI tests); by default the in-tree libprop.so.
+LIB_PATH = os.environ.get("LIBPROP_PATH") or os.path.join(HERE, "libprop.so")
 
 c_int32, c_int64, c_double, c_void_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
 P = c_void_p
@@ -41,6 +43,11 @@ class prop_setup(ctypes.Structure):
                 ("wavelength", c_double), ("z", c_double), ("has_lens", c_int32), ("lens", prop_lens),
                 ("lens_f", c_double), ("phase", c_void_p), ("in_", c_void_p * 2), ("out", c_void_p * 3),
                 ("gout", c_void_p * 3), ("gin", c_void_p * 2), ("grad_phase", c_void_p)]
+
+
+class prop_cache_stats(ctypes.Structure):
+    _fields_ = [("table_bytes", c_int64), ("limit", c_int64), ("spectra", c_int64), ("zooms", c_int64),
+                ("twiddles", c_int64), ("pinned", c_int64), ("evictions", c_int64), ("eviction_syncs", c_int64)]
 
 
 G = ctypes.POINTER(prop_grid)
@@ -74,6 +81,8 @@ SIGNATURES = {
     "prop_sampling_check": (c_int32, [G, c_double, c_double]),
     "prop_fft_length": (c_int32, [c_int32]),
     "prop_cache_clear": (None, []),
+    "prop_cache_set_limit": (None, [c_int64]),
+    "prop_cache_info": (None, [P]),
     "prop_status_string": (ctypes.c_char_p, [c_int32]),
     "prop_last_device_error": (c_int32, []),
     "prop_plan_create": (c_int32, [c_int32, P, c_int32, ctypes.c_uint32, ctypes.POINTER(c_void_p)]),

@@ -78,6 +78,50 @@ def build(jobs: int | None = None, report: bool = False) -> str:
     return LIB
 
 
+# Host-side AddressSanitizer + UBSan for the ABI layer (argument validation,
+# caches, plans) of libprop.hip; device code is built as usual.  Each
+# sanitizer flag is scoped to the host compilation.
+SANITIZE_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all"]
+SAN_LIB = os.path.join(BUILD, "sanitized", "libprop.so")
+
+
+def sanitizer_runtime() -> str:
+    """The clang ASan runtime (it also carries the UBSan handlers) to preload."""
+    base = "/opt/rocm/llvm/lib/clang"
+    for ver in sorted(os.listdir(base), reverse=True) if os.path.isdir(base) else []:
+        cand = os.path.join(base, ver, "lib", "linux", "libclang_rt.asan-x86_64.so")
+        if os.path.exists(cand):
+            return cand
+    raise RuntimeError("clang ASan runtime not found")
+
+
+def build_host_sanitized() -> str:
+    """libprop variant with a sanitized ABI layer, for the host-only ABI tests
+    (preload sanitizer_runtime(); the sanitizer runtime is resolved from it,
+    not linked in).  Reuses the other translation units of the plain build."""
+    os.makedirs(os.path.dirname(SAN_LIB), exist_ok=True)
+    objs = []
+    for src in SOURCES:
+        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+        if src == "libprop.hip":
+            obj = os.path.join(BUILD, "sanitized", "libprop.o")
+            cmd = [hipcc(), *FLAGS, *SANITIZE_HOST, "-g", "-c", os.path.join(CSRC, src), "-o", obj]
+            p = subprocess.run(cmd, capture_output=True, text=True)
+            if p.returncode != 0:
+                raise RuntimeError(f"hipcc failed for {src}:\n{p.stderr}")
+        elif not os.path.exists(obj):
+            _compile(src, False)
+        objs.append(obj)
+    tmp = SAN_LIB + ".tmp"
+    p = subprocess.run([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp],
+                       capture_output=True, text=True)
+    if p.returncode != 0:
+        raise RuntimeError(f"link failed:\n{p.stdout}\n{p.stderr}")
+    os.replace(tmp, SAN_LIB)
+    return SAN_LIB
+
+
 def _print_report(log: str) -> None:
     cur = {}
     rows = []

@@ -19,6 +19,8 @@
 
 #include <utility>
 
+#include "lengths.hpp"
+
 namespace lp {
 
 // ---------------------------------------------------------------- complex --
@@ -190,17 +192,7 @@ template <int R, int DIR> struct Dft {
 };
 
 // ------------------------------------------------------- radix schedules --
-// Every transform length the library uses, with its compile-time radix
-// schedule (largest radix first).  Requested sizes are rounded up to the
-// next length in this list, which is exact for zero-padded convolution and
-// for Bluestein.  X(n, radices...)
-#define LP_LENGTHS(X)                                                                            \
-  X(1, 1) X(2, 2) X(4, 4) X(8, 8) X(16, 16) X(32, 8, 4) X(64, 8, 8) X(96, 12, 8) X(128, 16, 8)  \
-  X(192, 16, 12) X(256, 16, 16) X(384, 8, 8, 6) X(512, 8, 8, 8) X(768, 12, 8, 8)                \
-  X(1024, 16, 8, 8) X(1536, 16, 12, 8) X(2048, 16, 8, 16) X(3072, 16, 16, 12)                   \
-  X(4096, 16, 16, 16) X(6144, 32, 16, 12) X(8192, 32, 16, 16)
-
-constexpr int kMaxLen = 8192;
+// The supported lengths and their schedules: LP_LENGTHS (lengths.hpp).
 constexpr int kMaxStages = 4;
 
 // Twiddle table layout of an element type (see Sched::twoff).
@@ -262,6 +254,23 @@ template <int... Rs> struct Sched {
 template <typename T, class S> struct SchedFor { using type = S; };
 template <> struct SchedFor<double, Sched<16, 8, 16>> { using type = Sched<16, 16, 8>; };
 template <typename T, class S> using SchedOf = typename SchedFor<T, S>::type;
+
+// Inputs of the first stage of a half-input transform: thread j < n/R0
+// reads elements j + r n/R0 for r < R0/2, which cover [0, n/2) once each.
+// Persistent passes prefetch exactly these elements.
+template <class S> struct HalfIn {
+  static constexpr int nr = S::n / S::rad[0], R = S::rad[0] / 2;
+  __host__ __device__ static constexpr bool loads(int j) { return j < nr; }
+  __host__ __device__ static constexpr int index(int j, int r) { return j + r * nr; }
+};
+// Outputs of the last stage of a half-output transform: thread j < n/RL
+// stores elements j + r n/RL for r < RL/2, covering [0, n/2) once each.
+template <class S> struct HalfOut {
+  static constexpr int RL = S::rad[S::nst - 1];
+  static constexpr int nr = S::n / RL, R = RL / 2;
+  __host__ __device__ static constexpr bool stores(int j) { return j < nr; }
+  __host__ __device__ static constexpr int index(int j, int r) { return j + r * nr; }
+};
 
 // HALF_IN: inputs with index >= n/2 are zero (skipped at compile time);
 // HALF_OUT: only outputs with index < n/2 are consumed (the rest is never

@@ -88,9 +88,20 @@ constexpr int variant_lines(int v) {
 
 // Workgroup i is dispatched to XCD i % 8; give each XCD a contiguous range
 // of tiles so that neighbouring lines (adjacent columns) share one L2.
-__device__ __forceinline__ int xcd_remap(int i, int nb) {
+__host__ __device__ __forceinline__ int xcd_remap(int i, int nb) {
   const int q = nb >> 3, r = nb & 7, x = i & 7;
-  return x * q + min(x, r) + (i >> 3);
+  return x * q + (x < r ? x : r) + (i >> 3);
+}
+
+// Work split of a persistent pass over `items` work items: `per` items per
+// workgroup, `groups` workgroups, at most one per compute unit; every
+// workgroup gets a non-empty contiguous run.
+struct PersistSplit {
+  int per, groups;
+};
+__host__ __device__ constexpr PersistSplit persist_split(int items, int cus) {
+  const int per = (items + cus - 1) / cus;
+  return PersistSplit{per, (items + per - 1) / per};
 }
 
 // Compute units of the current device (cached per device).
@@ -152,16 +163,17 @@ constexpr bool pg_preload() {
 }
 template <typename T, class S, bool ON>
 struct PhaseGradPre {
-  static constexpr int RL = S::rad[S::nst - 1], nr = S::n / RL, P = ON ? RL / 2 : 1;
+  using HO = HalfOut<S>;
+  static constexpr int nr = HO::nr, P = ON ? HO::R : 1;
   cx<T> u[P];
   T g[P];
   template <class Off>
   __device__ __forceinline__ void load(const PhaseGrad<T>& pg, int j, Off off) {
     if constexpr (ON) {
-      if (pg.grad && j < nr) {
+      if (pg.grad && HO::stores(j)) {
 #pragma unroll
         for (int r = 0; r < P; ++r) {
-          const int64_t o = off(j + r * nr);
+          const int64_t o = off(HO::index(j, r));
           u[r] = pg.u[o];
           g[r] = pg.acc ? pg.grad[o] : T(0);
         }
@@ -341,13 +353,14 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
   const cx<T>* tw = tw_.p;
   constexpr int LS = line_stride<S, C, true>();
   __shared__ cx<T> smem[C * LS];
-  constexpr int nr0 = S::n / S::rad[0], RIN = S::rad[0] / 2;
+  using HI = HalfIn<S>;
+  constexpr int RIN = HI::R;
   const int chunk = xcd_remap(blockIdx.x, gridDim.x);
   const int first = chunk * per, last = min(first + per, items);
   const int c = (int)(threadIdx.x % C), j = (int)(threadIdx.x / C);
   cx<T>* lds = smem + c * LS;
   const int64_t tst = (int64_t)nrows * kTile;
-  const bool loader = j < nr0;
+  const bool loader = HI::loads(j);
   auto frow = [&](int id) -> int64_t {
     const int b = id / tiles, y = (id - b * tiles) * C + c;
     return ((int64_t)b * nrows + y) * n_io;
@@ -356,7 +369,7 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
   if (loader && first < last) {
     const cx<T>* src = in + frow(first);
 #pragma unroll
-    for (int r = 0; r < RIN; ++r) nxt[r] = src[j + r * nr0];
+    for (int r = 0; r < RIN; ++r) nxt[r] = src[HI::index(j, r)];
   }
   for (int id = first; id < last; ++id) {
     cx<T> cur[RIN];
@@ -365,11 +378,12 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
     if (loader && id + 1 < last) {
       const cx<T>* src = in + frow(id + 1);
 #pragma unroll
-      for (int r = 0; r < RIN; ++r) nxt[r] = src[j + r * nr0];
+      for (int r = 0; r < RIN; ++r) nxt[r] = src[HI::index(j, r)];
     }
     const int b = id / tiles, y = (id - b * tiles) * C + c;
     const int64_t wrow = b * w_bstride + (int64_t)y * kTile;
-    auto load = [&](int i) -> cx<T> { return cur[(i - j) / nr0]; };
+    // the first stage asks for i = HI::index(j, r): register r of cur
+    auto load = [&](int i) -> cx<T> { return cur[(i - j) / HI::nr]; };
     auto store = [&](int i, cx<T> v) { out[wrow + (int64_t)(i >> kTileShift) * tst + (i & (kTile - 1))] = v; };
     fft_line<T, -1, S, true, false>(lds, tw, j, load, store);
   }
@@ -389,10 +403,9 @@ hipError_t launch_rs_rows_s(const cx<T>* in, cx<T>* out, int64_t w_bstride, int 
       if (2 * n_io == S::n && nrows % C == 0) {
         if constexpr (DIR < 0 && tw_per_thread<T>() && S::rad[0] <= 16) {
           const int items = tiles * batch;
-          const int per = (items + cu_count() - 1) / cu_count();
-          const int groups = (items + per - 1) / per;
-          hipLaunchKernelGGL((k_rs_rows_fwd_persist<T, S, C>), dim3(groups), dim3(RC::threads), 0, s, in, out,
-                             w_bstride, nrows, n_io, tiles, items, per, TableBox<T>{tw});
+          const PersistSplit sp = persist_split(items, cu_count());
+          hipLaunchKernelGGL((k_rs_rows_fwd_persist<T, S, C>), dim3(sp.groups), dim3(RC::threads), 0, s, in, out,
+                             w_bstride, nrows, n_io, tiles, items, sp.per, TableBox<T>{tw});
         } else {
           // rows need not fill whole workspace tiles: C2 may be below kTile.
           // With the phase-gradient epilogue fused, C lines measure faster
@@ -510,7 +523,8 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
   const cx<T>* tw = tw_.p;
   constexpr int LS = line_stride<S, C, true>();
   __shared__ cx<T> smem[C * LS];
-  constexpr int My = S::n, nr0 = S::n / S::rad[0], RIN = S::rad[0] / 2;
+  using HI = HalfIn<S>;
+  constexpr int My = S::n, RIN = HI::R;
   const int chunk = xcd_remap(blockIdx.x, gridDim.x);
   const int first = chunk * per, last = min(first + per, items);
   const int c = threadIdx.x % C, j = threadIdx.x / C;
@@ -520,14 +534,14 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
     const int kx = tile * C + c;
     return W + b * bstride + (int64_t)(kx >> kTileShift) * n_valid * kTile + (kx & (kTile - 1));
   };
-  // threads j >= nr0 exist when a later radix is smaller than the first;
+  // threads j >= n/R0 exist when a later radix is smaller than the first;
   // they take no part in the first stage and load nothing
-  const bool loader = j < nr0;
+  const bool loader = HI::loads(j);
   cx<T> nxt[RIN];
   if (loader && first < last) {
     cx<T>* col = colp(first);
 #pragma unroll
-    for (int r = 0; r < RIN; ++r) nxt[r] = load_stream(&col[(j + r * nr0) * kTile]);
+    for (int r = 0; r < RIN; ++r) nxt[r] = load_stream(&col[HI::index(j, r) * kTile]);
   }
   for (int id = first; id < last; ++id) {
     cx<T> cur[RIN];
@@ -536,13 +550,13 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
     if (loader && id + 1 < last) {
       cx<T>* coln = colp(id + 1);
 #pragma unroll
-      for (int r = 0; r < RIN; ++r) nxt[r] = load_stream(&coln[(j + r * nr0) * kTile]);
+      for (int r = 0; r < RIN; ++r) nxt[r] = load_stream(&coln[HI::index(j, r) * kTile]);
     }
     const int kx = (id / nb) * C + c;
     cx<T>* col = colp(id);
     const cx<T>* sq = Sq + (int64_t)(kx >> 2) * (My / 2 + 1) * 4 + (kx & 3);
-    // the first stage asks for i = j + r nr0, r < RIN: register r of cur
-    auto load = [&](int i) -> cx<T> { return cur[(i - j) / nr0]; };
+    // the first stage asks for i = HI::index(j, r): register r of cur
+    auto load = [&](int i) -> cx<T> { return cur[(i - j) / HI::nr]; };
     auto mult = [&](int i, cx<T> v) -> cx<T> {
       const cx<T> h = sq[min(i, My - i) * 4];
       return CONJ ? cmulc(v, h) : cmul(v, h);
@@ -568,14 +582,13 @@ hipError_t launch_rs_cols_c(cx<T>* W, int64_t bstride, int ncols, int n_valid, c
         // one workgroup per CU (the LDS footprint allows no more), each a
         // contiguous run of `per` items
         const int items = tiles * batch;
-        const int per = (items + cu_count() - 1) / cu_count();
-        const int groups = (items + per - 1) / per;
+        const PersistSplit sp = persist_split(items, cu_count());
         if (conj_spec)
-          hipLaunchKernelGGL((k_rs_cols_persist<T, S, C, true>), dim3(groups), dim3(C * S::threads), 0, s, W,
-                             bstride, n_valid, TableBox<T>{Sq}, batch, items, per, TableBox<T>{tw});
+          hipLaunchKernelGGL((k_rs_cols_persist<T, S, C, true>), dim3(sp.groups), dim3(C * S::threads), 0, s, W,
+                             bstride, n_valid, TableBox<T>{Sq}, batch, items, sp.per, TableBox<T>{tw});
         else
-          hipLaunchKernelGGL((k_rs_cols_persist<T, S, C, false>), dim3(groups), dim3(C * S::threads), 0, s, W,
-                             bstride, n_valid, TableBox<T>{Sq}, batch, items, per, TableBox<T>{tw});
+          hipLaunchKernelGGL((k_rs_cols_persist<T, S, C, false>), dim3(sp.groups), dim3(C * S::threads), 0, s, W,
+                             bstride, n_valid, TableBox<T>{Sq}, batch, items, sp.per, TableBox<T>{tw});
       } else {
         hipLaunchKernelGGL((k_rs_cols<T, S, C, true, true>), dim3(tiles * batch), dim3(C * S::threads), 0, s, W,
                            bstride, ncols, n_valid, TableBox<T>{Sq}, Mx, conj_spec ? 1 : 0, tiles, TableBox<T>{tw});

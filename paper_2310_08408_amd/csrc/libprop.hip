@@ -10,13 +10,16 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
 
 #include "libprop.h"
+#include "cache.hpp"
 #include "kernels.hpp"
+#include "validate.hpp"
 
 namespace lp {
 
@@ -92,22 +95,6 @@ static hipEvent_t take_event() {
     if (e_ != hipSuccess) return dev_err(e_);                                           \
   } while (0)
 
-// ------------------------------------------------------------- lengths --
-static const int kLengths[] = {
-#define LP_LEN(N, ...) N,
-    LP_LENGTHS(LP_LEN)
-#undef LP_LEN
-};
-
-// Smallest supported transform length >= n, or -1.
-int fft_len(int n) {
-  if (n < 1) return -1;
-  int best = -1;
-  for (int v : kLengths)
-    if (v >= n && (best < 0 || v < best)) best = v;
-  return best;
-}
-
 // Twiddle table of the schedule that element type T runs at length n:
 // stage s >= 1 holds W_{Ns R}^{r k} (forward sign), computed in long double,
 // at off_s + k R + r (r = 0..R-1) in the per-thread layout, else at
@@ -154,21 +141,34 @@ struct Buf {
   size_t bytes = 0;
 };
 
-struct PlanEntry {
+struct TwEntry {
   void* tw = nullptr;
+};
+
+// Tables generated on a stream carry an event recorded after their last
+// generating kernel.  A call on another stream makes that stream wait for
+// the event (on the device, no host synchronisation) until the host has
+// seen it complete.
+struct Ready {
+  hipEvent_t ev = nullptr;
+  hipStream_t gen = nullptr;
+  bool done = true;
 };
 
 struct SpecEntry {
   void* q[4] = {nullptr, nullptr, nullptr, nullptr};  // kinds: H, (X/z)H, (Y/z)H, dH/dz
   int Mx = 0, My = 0;
+  Ready ready;
 };
 
 struct ZoomEntry {
   void* pre = nullptr;
   void* post = nullptr;
   void* chat = nullptr;
+  Ready ready;
 };
 
+using TwKey = std::tuple<int, int, int>;  // (device, element size, length)
 using SpecKey = std::tuple<int, int, int, int, double, double, double, double, int>;
 using ZoomKey = std::tuple<int, int, int, double, double, double, double, double, double, double, double, double,
                            int, int, int>;
@@ -182,21 +182,46 @@ struct TuneEntry {
   float ms[kColVariants] = {-1.f, -1.f, -1.f};
 };
 
+// Tables a plan holds pins on (released by prop_plan_destroy).
+struct Pins {
+  std::vector<TwKey> tw;
+  std::vector<SpecKey> spec;
+  std::vector<ZoomKey> zoom;
+};
+
+// Default byte budget of the cached kernel spectra and zoom vectors
+// (LIBPROP_CACHE_MB overrides it; prop_cache_set_limit at run time).
+static size_t default_cache_limit() {
+  const char* e = std::getenv("LIBPROP_CACHE_MB");
+  const long long mb = e ? std::atoll(e) : 0;
+  return mb > 0 ? (size_t)mb << 20 : (size_t)8 << 30;
+}
+
 struct Ctx {
   std::mutex mu;
-  std::map<std::tuple<int, int, int>, PlanEntry> plans;  // (dev, is_double, n)
-  std::map<SpecKey, SpecEntry> specs;
-  std::map<ZoomKey, ZoomEntry> zooms;
+  uint64_t epoch = 0;  // one per locked library call
+  size_t limit = default_cache_limit();
+  TableCache<TwKey, TwEntry> tws;
+  TableCache<SpecKey, SpecEntry> specs;
+  TableCache<ZoomKey, ZoomEntry> zooms;
   std::map<std::pair<int, hipStream_t>, Buf> work;
-  std::map<int, Buf> scratch;  // complex128 setup scratch per device
+  std::map<std::pair<int, hipStream_t>, Buf> scratch;  // complex128 table-generation scratch per stream
   std::map<TuneKey, TuneEntry> tuned;
   std::map<int, Buf> tune_a, tune_b;  // autotuner scratch per device
+  Pins* pins = nullptr;               // set while a plan warms its tables
+  uint64_t evict_syncs = 0;           // device synchronisations of eviction rounds
 };
 
 static Ctx& ctx() {
   static Ctx* c = new Ctx();
   return *c;
 }
+
+// The library mutex, held for a whole call; each call is one cache epoch.
+struct CtxLock {
+  std::unique_lock<std::mutex> lk;
+  CtxLock() : lk(ctx().mu) { ++ctx().epoch; }
+};
 
 static int cur_device(int* dev) {
   LP_TRY(hipGetDevice(dev));
@@ -222,13 +247,90 @@ static int ensure_buf(Buf& b, size_t bytes, hipStream_t s) {
   return PROP_OK;
 }
 
+// ------------------------------------------------------ table lifetime --
+static int ready_mark(Ready& r, hipStream_t s) {
+  if (!r.ev) LP_TRY(hipEventCreateWithFlags(&r.ev, hipEventDisableTiming));
+  LP_TRY(hipEventRecord(r.ev, s));
+  r.gen = s;
+  r.done = false;
+  return PROP_OK;
+}
+
+static int ready_wait(Ready& r, hipStream_t s) {
+  if (r.done || s == r.gen) return PROP_OK;  // complete, or ordered by the stream itself
+  const hipError_t q = hipEventQuery(r.ev);
+  if (q == hipSuccess) {
+    r.done = true;
+    return PROP_OK;
+  }
+  if (q != hipErrorNotReady) return dev_err(q);
+  (void)hipGetLastError();
+  LP_TRY(hipStreamWaitEvent(s, r.ev, 0));
+  return PROP_OK;
+}
+
+static void release_spec(SpecEntry& e) {
+  for (int k = 0; k < 4; ++k)
+    if (e.q[k]) (void)hipFree(e.q[k]);
+  if (e.ready.ev) (void)hipEventDestroy(e.ready.ev);
+}
+
+static void release_zoom(ZoomEntry& e) {
+  (void)hipFree(e.pre);
+  (void)hipFree(e.post);
+  (void)hipFree(e.chat);
+  if (e.ready.ev) (void)hipEventDestroy(e.ready.ev);
+}
+
+// Evict least recently used, unpinned spectra and zoom vectors of earlier
+// calls until their bytes fall to `target`.  Kernels already enqueued may
+// still read a victim, so one device synchronisation precedes each round's
+// frees; rounds start above the budget and go down to 3/4 of it, so a
+// distance-optimisation loop pays that synchronisation once per many new
+// distances, not per call.
+static void evict_tables(Ctx& C, size_t target) {
+  bool synced = false;
+  auto before = [&](size_t) {
+    if (!synced) {
+      (void)hipDeviceSynchronize();
+      synced = true;
+      ++C.evict_syncs;
+    }
+  };
+  const size_t zb = C.zooms.bytes();
+  C.specs.evict_to(target > zb ? target - zb : 0, C.epoch, before, release_spec);
+  const size_t sb = C.specs.bytes();
+  C.zooms.evict_to(target > sb ? target - sb : 0, C.epoch, before, release_zoom);
+}
+
+static void trim_tables(Ctx& C) {
+  if (C.specs.bytes() + C.zooms.bytes() > C.limit) evict_tables(C, C.limit / 4 * 3);
+}
+
+// Device table allocation; on exhaustion every evictable table is dropped
+// and the allocation tried once more.
+static int table_alloc(Ctx& C, void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    evict_tables(C, 0);
+    e = hipMalloc(p, bytes);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return dev_err(e);
+  }
+  return PROP_OK;
+}
+
 template <typename T>
 static int get_tw(int dev, int n, const cx<T>** tw) {
   Ctx& C = ctx();
-  const auto key = std::make_tuple(dev, (int)sizeof(T), n);
-  auto it = C.plans.find(key);
-  if (it == C.plans.end()) {
-    PlanEntry e;
+  const TwKey key{dev, (int)sizeof(T), n};
+  auto* slot = C.tws.find(key, C.epoch);
+  if (!slot) {
+    TwEntry e;
     std::vector<long double> wr, wi;
     if (!make_twiddles<T>(n, wr, wi)) return PROP_ESHAPE;
     std::vector<cx<T>> h(wr.size());
@@ -236,12 +338,17 @@ static int get_tw(int dev, int n, const cx<T>** tw) {
       h[i].x = (T)wr[i];
       h[i].y = (T)wi[i];
     }
-    hipError_t er = hipMalloc(&e.tw, h.size() * sizeof(cx<T>));
-    if (er != hipSuccess) return dev_err(er);
-    LP_TRY(hipMemcpy(e.tw, h.data(), h.size() * sizeof(cx<T>), hipMemcpyHostToDevice));
-    it = C.plans.emplace(key, e).first;
+    const size_t bytes = h.size() * sizeof(cx<T>);
+    LP_RET(table_alloc(C, &e.tw, bytes));
+    const hipError_t er = hipMemcpy(e.tw, h.data(), bytes, hipMemcpyHostToDevice);
+    if (er != hipSuccess) {
+      (void)hipFree(e.tw);
+      return dev_err(er);
+    }
+    slot = C.tws.insert(key, e, bytes, C.epoch);
   }
-  *tw = (const cx<T>*)it->second.tw;
+  if (C.pins && C.tws.pin(key)) C.pins->tw.push_back(key);
+  *tw = (const cx<T>*)slot->v.tw;
   return PROP_OK;
 }
 
@@ -254,35 +361,52 @@ static int get_rs_spectra(int dev, const prop_grid* g, double wl, double z, int 
   *Mx_out = Mx;
   *My_out = My;
   const SpecKey key{dev, (int)sizeof(T), g->nx, g->ny, g->dx, g->dy, wl, z, 0};
-  SpecEntry& e = C.specs[key];
-  e.Mx = Mx;
-  e.My = My;
+  auto* slot = C.specs.find(key, C.epoch);
+  if (!slot) {
+    SpecEntry fresh;
+    fresh.Mx = Mx;
+    fresh.My = My;
+    slot = C.specs.insert(key, fresh, 0, C.epoch);
+  }
+  SpecEntry& e = slot->v;
   bool need = false;
   for (int k = 0; k < 4; ++k) need |= ((kinds >> k) & 1) && e.q[k] == nullptr;
   if (need) {
+    // generated on the caller's stream: the FP64 kernel samples, their FP64
+    // transform and the half-table extraction share the stream's scratch,
+    // which stream order keeps from being reused early
     const cx<double> *twx, *twy;
     LP_RET(get_tw<double>(dev, Mx, &twx));
     LP_RET(get_tw<double>(dev, My, &twy));
-    Buf& sb = C.scratch[dev];
+    Buf& sb = C.scratch[{dev, s}];
     LP_RET(ensure_buf(sb, (size_t)Mx * My * sizeof(cx<double>), s));
+    LP_RET(ready_wait(e.ready, s));
     cx<double>* full = (cx<double>*)sb.p;
     const size_t qbytes = (size_t)((Mx + 3) / 4 * 4) * (My / 2 + 1) * sizeof(cx<T>);
     const double k = 2.0 * kPi / wl;
     for (int kind = 0; kind < 4; ++kind) {
       if (!((kinds >> kind) & 1) || e.q[kind]) continue;
       void* qp = nullptr;
-      hipError_t er = hipMalloc(&qp, qbytes);
-      if (er != hipSuccess) return dev_err(er);
-      LP_TRY(launch_rs_kernel_wrapped(full, Mx, My, g->nx, g->ny, g->dx, g->dy, k, z, kind, s));
-      LP_TRY((launch_fft_lines<double, -1>(Mx, false, full, full, Lines{0, Mx}, Lines{0, Mx}, My, Mx, Mx, 1.0, 1,
-                                           twx, s)));
-      LP_TRY((launch_fft_lines<double, -1>(My, true, full, full, Lines{0, Mx}, Lines{0, Mx}, Mx, My, My, 1.0, 1, twy,
-                                           s)));
-      LP_TRY(launch_extract_half<T>(full, (cx<T>*)qp, Mx, My, s));
+      LP_RET(table_alloc(C, &qp, qbytes));
+      hipError_t er = launch_rs_kernel_wrapped(full, Mx, My, g->nx, g->ny, g->dx, g->dy, k, z, kind, s);
+      if (er == hipSuccess)
+        er = launch_fft_lines<double, -1>(Mx, false, full, full, Lines{0, Mx}, Lines{0, Mx}, My, Mx, Mx, 1.0, 1, twx, s);
+      if (er == hipSuccess)
+        er = launch_fft_lines<double, -1>(My, true, full, full, Lines{0, Mx}, Lines{0, Mx}, Mx, My, My, 1.0, 1, twy, s);
+      if (er == hipSuccess) er = launch_extract_half<T>(full, (cx<T>*)qp, Mx, My, s);
+      if (er != hipSuccess) {
+        (void)hipFree(qp);
+        return dev_err(er);
+      }
       e.q[kind] = qp;
+      C.specs.add_bytes(key, qbytes);
     }
-    LP_TRY(hipStreamSynchronize(s));
+    LP_RET(ready_mark(e.ready, s));
+    trim_tables(C);
+  } else {
+    LP_RET(ready_wait(e.ready, s));
   }
+  if (C.pins && C.specs.pin(key)) C.pins->spec.push_back(key);
   for (int kk = 0; kk < 4; ++kk) q[kk] = (const cx<T>*)e.q[kk];
   return PROP_OK;
 }
@@ -371,85 +495,45 @@ static int get_zoom(int dev, const ZoomSpec& zs, hipStream_t s, const cx<T>** pr
   Ctx& C = ctx();
   const ZoomKey key{dev,    (int)sizeof(T), zs.sigma, zs.beta,  zs.x0,   zs.dx,   zs.X0,  zs.dX,
                     zs.qin, zs.qout,       zs.Kre,   zs.Kim,   zs.n_in, zs.n_out, zs.L};
-  auto it = C.zooms.find(key);
-  if (it == C.zooms.end()) {
+  auto* slot = C.zooms.find(key, C.epoch);
+  if (!slot) {
     ZoomEntry e;
     const cx<double>* twL;
     LP_RET(get_tw<double>(dev, zs.L, &twL));
-    Buf& sb = C.scratch[dev];
+    Buf& sb = C.scratch[{dev, s}];
     LP_RET(ensure_buf(sb, (size_t)zs.L * sizeof(cx<double>), s));
     cx<double>* chirp = (cx<double>*)sb.p;
-    hipError_t er;
-    if ((er = hipMalloc(&e.pre, (size_t)zs.n_in * sizeof(cx<T>))) != hipSuccess) return dev_err(er);
-    if ((er = hipMalloc(&e.post, (size_t)zs.n_out * sizeof(cx<T>))) != hipSuccess) return dev_err(er);
-    if ((er = hipMalloc(&e.chat, (size_t)zs.L * sizeof(cx<T>))) != hipSuccess) return dev_err(er);
-    LP_TRY(launch_zoom_vectors<T>(zs, (cx<T>*)e.pre, (cx<T>*)e.post, chirp, s));
-    LP_TRY((launch_fft_lines<double, -1>(zs.L, false, chirp, chirp, Lines{0, zs.L}, Lines{0, zs.L}, 1, zs.L, zs.L, 1.0,
-                                         1, twL, s)));
-    LP_TRY(launch_convert<T>(chirp, (cx<T>*)e.chat, zs.L, s));
-    LP_TRY(hipStreamSynchronize(s));
-    it = C.zooms.emplace(key, e).first;
+    const size_t bytes = ((size_t)zs.n_in + zs.n_out + zs.L) * sizeof(cx<T>);
+    auto fail = [&](int r) {
+      (void)hipFree(e.pre);
+      (void)hipFree(e.post);
+      (void)hipFree(e.chat);
+      return r;
+    };
+    int r = table_alloc(C, &e.pre, (size_t)zs.n_in * sizeof(cx<T>));
+    if (r == PROP_OK) r = table_alloc(C, &e.post, (size_t)zs.n_out * sizeof(cx<T>));
+    if (r == PROP_OK) r = table_alloc(C, &e.chat, (size_t)zs.L * sizeof(cx<T>));
+    if (r < 0) return fail(r);
+    hipError_t er = launch_zoom_vectors<T>(zs, (cx<T>*)e.pre, (cx<T>*)e.post, chirp, s);
+    if (er == hipSuccess)
+      er = launch_fft_lines<double, -1>(zs.L, false, chirp, chirp, Lines{0, zs.L}, Lines{0, zs.L}, 1, zs.L, zs.L, 1.0,
+                                        1, twL, s);
+    if (er == hipSuccess) er = launch_convert<T>(chirp, (cx<T>*)e.chat, zs.L, s);
+    if (er != hipSuccess) return fail(dev_err(er));
+    r = ready_mark(e.ready, s);
+    if (r < 0) return fail(r);
+    slot = C.zooms.insert(key, e, bytes, C.epoch);
+    trim_tables(C);
+  } else {
+    LP_RET(ready_wait(slot->v.ready, s));
   }
-  *pre = (const cx<T>*)it->second.pre;
-  *post = (const cx<T>*)it->second.post;
-  *chat = (const cx<T>*)it->second.chat;
+  if (C.pins && C.zooms.pin(key)) C.pins->zoom.push_back(key);
+  *pre = (const cx<T>*)slot->v.pre;
+  *post = (const cx<T>*)slot->v.post;
+  *chat = (const cx<T>*)slot->v.chat;
   return PROP_OK;
 }
 
-// ------------------------------------------------------------ validation --
-static bool is_finite(double v) { return std::isfinite(v); }
-
-static int check_grid(const prop_grid* g) {
-  if (!g) return PROP_ENULL;
-  if (g->nx < 1 || g->ny < 1) return PROP_ESHAPE;
-  if (!(g->dx > 0) || !(g->dy > 0) || !is_finite(g->dx) || !is_finite(g->dy) || !is_finite(g->cx) || !is_finite(g->cy))
-    return PROP_EPARAM;
-  return PROP_OK;
-}
-
-static int check_common(prop_dtype t, int32_t batch, double wl) {
-  if (t != PROP_C64 && t != PROP_C128) return PROP_EPARAM;
-  if (batch < 0) return PROP_ESHAPE;
-  if (!(wl > 0) || !is_finite(wl)) return PROP_EPARAM;
-  return PROP_OK;
-}
-
-static size_t esize(prop_dtype t) { return t == PROP_C64 ? 8 : 16; }
-
-static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
-  const char* pa = (const char*)a;
-  const char* pb = (const char*)b;
-  return pa < pb + nb && pb < pa + na;
-}
-
-// every output must be disjoint from every input and from each other
-using Span = std::pair<const void*, size_t>;
-
-static int check_alias(const std::vector<Span>& ins, const std::vector<Span>& o) {
-  for (size_t i = 0; i < o.size(); ++i) {
-    for (auto& in : ins)
-      if (overlap(o[i].first, o[i].second, in.first, in.second)) return PROP_EALIAS;
-    for (size_t j = i + 1; j < o.size(); ++j)
-      if (overlap(o[i].first, o[i].second, o[j].first, o[j].second)) return PROP_EALIAS;
-  }
-  return PROP_OK;
-}
-
-static int check_alias(std::initializer_list<Span> ins, std::initializer_list<Span> outs) {
-  return check_alias(std::vector<Span>(ins), std::vector<Span>(outs));
-}
-
-static int sampling(const prop_grid* g, double wl, double z) {
-  const int n[2] = {g->nx, g->ny};
-  const double d[2] = {g->dx, g->dy};
-  for (int a = 0; a < 2; ++a) {
-    if (2.0 * d[a] <= wl) continue;
-    const double L = n[a] * d[a];
-    const double zmin = std::sqrt((2.0 * L * d[a] / wl) * (2.0 * L * d[a] / wl) - L * L);
-    if (z < zmin) return PROP_WUNDERSAMPLED;
-  }
-  return PROP_OK;
-}
 
 // ------------------------------------------------------------- RS runs --
 static size_t rs_work_bytes(prop_dtype t, const prop_grid* g, int batch) {
@@ -510,7 +594,7 @@ static int rs_entry(prop_dtype t, const void* in, void* out, const prop_grid* g,
   if (!in || !out) return PROP_ENULL;
   const size_t bytes = (size_t)g->nx * g->ny * batch * esize(t);
   LP_RET(check_alias({{in, bytes}}, {{out, bytes}}));
-  std::lock_guard<std::mutex> lk(ctx().mu);
+  CtxLock lk;
   const hipStream_t s = (hipStream_t)stream;
   int dev;
   LP_RET(cur_device(&dev));
@@ -695,11 +779,6 @@ static void rw_specs(const prop_grid* gi, const prop_grid* go, double wl, const 
   }
 }
 
-static int check_czt_shapes(const prop_grid* gi, const prop_grid* go) {
-  if (fft_len(gi->nx + go->nx - 1) < 0 || fft_len(gi->ny + go->ny - 1) < 0) return PROP_ESHAPE;
-  return PROP_OK;
-}
-
 // scalar CZT with the caller holding the lock; tmp must hold
 // batch * max(nyi*nxo, nyo*nxi) elements
 template <typename T>
@@ -747,7 +826,7 @@ static int czt_entry(prop_dtype t, const void* in, void* out, const prop_grid* g
   const size_t bi = (size_t)gi->nx * gi->ny * batch * esize(t), bo = (size_t)go->nx * go->ny * batch * esize(t);
   if (!adjoint) LP_RET(check_alias({{in, bi}}, {{out, bo}}));
   else LP_RET(check_alias({{in, bo}}, {{out, bi}}));
-  std::lock_guard<std::mutex> lk(ctx().mu);
+  CtxLock lk;
   const hipStream_t s = (hipStream_t)stream;
   int dev;
   LP_RET(cur_device(&dev));
@@ -950,12 +1029,6 @@ static int rw_adj(const void* const* gs, void* gex, void* gey, const prop_grid* 
   return PROP_OK;
 }
 
-static int check_lens(const prop_lens* lens) {
-  if (!lens) return PROP_OK;
-  if (!(lens->na > 0) || !(lens->na < 1) || !(lens->f > 0) || !is_finite(lens->f)) return PROP_EPARAM;
-  return PROP_OK;
-}
-
 // ---------------------------------------------------------- elementwise --
 static double jones_cs(double theta, double* c, double* s) {
   *c = std::cos(theta);
@@ -1023,9 +1096,31 @@ struct prop_plan {
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   bool tuned[2] = {false, false};  // PROP_PLAN_AUTOTUNE: first execution tunes
   std::vector<int> order;          // graph mode: setups by decreasing cost
+  lp::Pins pins;                   // cached tables this plan's kernels address
 };
 
 namespace lp {
+
+// Drop a plan's pins (under the library lock); its tables become ordinary
+// cache entries again.
+static void unpin_all(Pins& p) {
+  Ctx& C = ctx();
+  for (auto& k : p.tw) C.tws.unpin(k);
+  for (auto& k : p.spec) C.specs.unpin(k);
+  for (auto& k : p.zoom) C.zooms.unpin(k);
+  p.tw.clear();
+  p.spec.clear();
+  p.zoom.clear();
+}
+
+// After a device synchronisation every pinned table of the plan is complete.
+static void mark_ready(Pins& p) {
+  Ctx& C = ctx();
+  for (auto& k : p.spec)
+    if (auto* sl = C.specs.find(k, 0)) sl->v.ready.done = true;
+  for (auto& k : p.zoom)
+    if (auto* sl = C.zooms.find(k, 0)) sl->v.ready.done = true;
+}
 
 static int ncomp_in(int op) { return (op == PROP_OP_VRS || op == PROP_OP_VCZT) ? 2 : 1; }
 static int ncomp_out(int op) { return (op == PROP_OP_VRS || op == PROP_OP_VCZT) ? 3 : 1; }
@@ -1249,7 +1344,7 @@ int rs_adjoint_phase_grad(prop_dtype t, const void* g_out, const void* u, void* 
   if (!g_out || !u || !grad) return PROP_ENULL;
   const size_t bytes = (size_t)g->nx * g->ny * batch * esize(t);
   LP_RET(check_alias({{g_out, bytes}, {u, bytes}}, {{g_u, g_u ? bytes : 0}, {grad, bytes / 2}}));
-  std::lock_guard<std::mutex> lk(ctx().mu);
+  CtxLock lk;
   const hipStream_t s = (hipStream_t)stream;
   int dev;
   LP_RET(cur_device(&dev));
@@ -1274,7 +1369,7 @@ int czt_adjoint_phase_grad(prop_dtype t, const void* g_out, const void* u, void*
   if (!g_out || !u || !grad) return PROP_ENULL;
   const size_t bi = (size_t)g_in->nx * g_in->ny * batch * esize(t), bo = (size_t)win->nx * win->ny * batch * esize(t);
   LP_RET(check_alias({{g_out, bo}, {u, bi}}, {{g_u, g_u ? bi : 0}, {grad, bi / 2}}));
-  std::lock_guard<std::mutex> lk(ctx().mu);
+  CtxLock lk;
   const hipStream_t s = (hipStream_t)stream;
   int dev;
   LP_RET(cur_device(&dev));
@@ -1297,7 +1392,7 @@ int rs_grad_z(prop_dtype t, const void* u_in, const void* g_out, double* dz, con
   const int warn = sampling(g, wavelength, z);
   if (batch == 0) return warn;
   if (!u_in || !g_out || !dz) return PROP_ENULL;
-  std::lock_guard<std::mutex> lk(ctx().mu);
+  CtxLock lk;
   const hipStream_t s = (hipStream_t)stream;
   int dev;
   LP_RET(cur_device(&dev));
@@ -1318,7 +1413,7 @@ int czt_grad_z(prop_dtype t, const void* u_in, const void* u_out, const void* g_
   LP_RET(check_czt_shapes(g_in, win));
   if (batch == 0) return PROP_OK;
   if (!u_in || !g_out || !dz) return PROP_ENULL;
-  std::lock_guard<std::mutex> lk(ctx().mu);
+  CtxLock lk;
   const hipStream_t s = (hipStream_t)stream;
   int dev;
   LP_RET(cur_device(&dev));
@@ -1349,7 +1444,7 @@ int vrs_propagate(prop_dtype t, const void* ex, const void* ey, void* ox, void* 
   if (!ex || !ey || !ox || !oy || !oz) return PROP_ENULL;
   const size_t b = (size_t)g->nx * g->ny * batch * esize(t);
   LP_RET(check_alias({{ex, b}, {ey, b}}, {{ox, b}, {oy, b}, {oz, b}}));
-  std::lock_guard<std::mutex> lk(ctx().mu);
+  CtxLock lk;
   const void* ins[2] = {ex, ey};
   void* outs[3] = {ox, oy, oz};
   const hipStream_t s = (hipStream_t)stream;
@@ -1373,7 +1468,7 @@ int vrs_adjoint(prop_dtype t, const void* gx, const void* gy, const void* gz, vo
   if (!gx || !gy || !gz || !gex || !gey) return PROP_ENULL;
   const size_t b = (size_t)g->nx * g->ny * batch * esize(t);
   LP_RET(check_alias({{gx, b}, {gy, b}, {gz, b}}, {{gex, b}, {gey, b}}));
-  std::lock_guard<std::mutex> lk(ctx().mu);
+  CtxLock lk;
   const void* ins[3] = {gx, gy, gz};
   void* outs[2] = {gex, gey};
   const hipStream_t s = (hipStream_t)stream;
@@ -1400,7 +1495,7 @@ int vczt_propagate(prop_dtype t, const void* ex, const void* ey, void* ox, void*
   if (!ex || !ey || !ox || !oy || !oz) return PROP_ENULL;
   const size_t bi = (size_t)g_in->nx * g_in->ny * batch * esize(t), bo = (size_t)win->nx * win->ny * batch * esize(t);
   LP_RET(check_alias({{ex, bi}, {ey, bi}}, {{ox, bo}, {oy, bo}, {oz, bo}}));
-  std::lock_guard<std::mutex> lk(ctx().mu);
+  CtxLock lk;
   const hipStream_t s = (hipStream_t)stream;
   int dev;
   LP_RET(cur_device(&dev));
@@ -1428,7 +1523,7 @@ int vczt_adjoint(prop_dtype t, const void* gx, const void* gy, const void* gz, v
   if (!gx || !gy || !gz || !gex || !gey) return PROP_ENULL;
   const size_t bi = (size_t)g_in->nx * g_in->ny * batch * esize(t), bo = (size_t)win->nx * win->ny * batch * esize(t);
   LP_RET(check_alias({{gx, bo}, {gy, bo}, {gz, bo}}, {{gex, bi}, {gey, bi}}));
-  std::lock_guard<std::mutex> lk(ctx().mu);
+  CtxLock lk;
   const hipStream_t s = (hipStream_t)stream;
   int dev;
   LP_RET(cur_device(&dev));
@@ -1488,7 +1583,7 @@ static int modulate_run(prop_dtype t, const void* u_in, const void* phase, void*
   LP_RET(check_alias({{phase, (size_t)npix * phase_batch * esize(t) / 2}}, {{u_out, b}}));
   const int64_t pbs = phase_batch == 1 ? 0 : npix;
   const hipStream_t s = (hipStream_t)stream;
-  std::lock_guard<std::mutex> lk(ctx().mu);
+  CtxLock lk;
   const double es = (double)esize(t);
   LP_TRACE("modulate", (double)npix * batch * 2.0 * es + (double)npix * phase_batch * es / 2, s,
            (t == PROP_C64 ? launch_modulate<float>((const cx<float>*)u_in, (const float*)phase, (cx<float>*)u_out,
@@ -1517,7 +1612,7 @@ int prop_phase_grad(prop_dtype t, const void* g_u, const void* u, void* grad, in
   const size_t b = (size_t)npix * batch * esize(t);
   LP_RET(check_alias({{g_u, b}, {u, b}}, {{grad, b / 2}}));
   const hipStream_t s = (hipStream_t)stream;
-  std::lock_guard<std::mutex> lk(ctx().mu);
+  CtxLock lk;
   LP_TRACE("phase_grad", (double)b * 2.0 + (double)b / 2 * (accumulate ? 2 : 1), s,
            (t == PROP_C64 ? launch_phase_grad<float>((const cx<float>*)g_u, (const cx<float>*)u, (float*)grad, npix,
                                                      batch, accumulate, s)
@@ -1612,7 +1707,7 @@ int prop_waveplate_adjoint(prop_dtype t, const void* gx, const void* gy, const v
   jones(eta, theta, J);
   conj_transpose(J, H);
   jones_derivs(eta, theta, d);
-  std::lock_guard<std::mutex> lk(ctx().mu);
+  CtxLock lk;
   int dev;
   LP_RET(cur_device(&dev));
   const hipStream_t s = (hipStream_t)stream;
@@ -1677,7 +1772,7 @@ int prop_waveplate_batched_adjoint(prop_dtype t, const void* gx, const void* gy,
     LP_TRY(launch_jones_items<double>((const cx<double>*)gx, (const cx<double>*)gy, (cx<double>*)gex,
                                       (cx<double>*)gey, params, true, npix, batch, s));
   if (!dparams) return PROP_OK;
-  std::lock_guard<std::mutex> lk(ctx().mu);
+  CtxLock lk;
   int dev;
   LP_RET(cur_device(&dev));
   const int nblk = red_blocks(npix);
@@ -1736,11 +1831,11 @@ int prop_beam_splitter_adjoint(prop_dtype t, const void* const* gc, const void* 
   const int flags = (a && dalpha ? 1 : 0) | (b && dalpha ? 2 : 0) | (ga ? 4 : 0) | (gb ? 8 : 0) | (dalpha ? 16 : 0);
   if (!(flags & 28)) return PROP_OK;
   const hipStream_t s = (hipStream_t)stream;
-  std::unique_lock<std::mutex> lk(ctx().mu, std::defer_lock);
+  std::unique_ptr<CtxLock> lk;
   double* partial = nullptr;
   int nblk = item_blocks_host(npix, batch);
   if (dalpha) {
-    lk.lock();
+    lk.reset(new CtxLock());
     int dev;
     LP_RET(cur_device(&dev));
     nblk = red_blocks(npix);
@@ -1769,7 +1864,7 @@ int prop_spot_loss(prop_dtype t, const void* ex, const void* ey, const void* ez,
     if (ez && gz) LP_RET(check_alias({{ex, b}, {ey, b}, {ez, b}}, {{gx, b}, {gy, b}, {gz, b}, {result, 64 * (size_t)batch}}));
     else LP_RET(check_alias({{ex, b}, {ey, b}}, {{gx, b}, {gy, b}, {result, 64 * (size_t)batch}}));
   }
-  std::lock_guard<std::mutex> lk(ctx().mu);
+  CtxLock lk;
   int dev;
   LP_RET(cur_device(&dev));
   const hipStream_t s = (hipStream_t)stream;
@@ -1808,7 +1903,7 @@ int prop_density_loss(prop_dtype t, const void* const* comps, int32_t ncomp, con
     if (!comps[k]) return PROP_ENULL;
   for (int k = 0; k < ndep; ++k)
     if (!dep[k]) return PROP_ENULL;
-  std::lock_guard<std::mutex> lk(ctx().mu);
+  CtxLock lk;
   const hipStream_t s = (hipStream_t)stream;
   int dev;
   LP_RET(cur_device(&dev));
@@ -1862,8 +1957,8 @@ int prop_track_best(const double* loss, double* best, int64_t* since, int32_t ba
 }
 
 int32_t prop_autotune_report(char* buf, int32_t cap) {
+  CtxLock lk;
   Ctx& C = ctx();
-  std::lock_guard<std::mutex> lk(C.mu);
   std::string out;
   static const char* kinds[] = {"rs_cols", "vrs_mix2", "czt_cols"};
   for (const auto& kv : C.tuned) {
@@ -1892,18 +1987,13 @@ int32_t prop_autotune_report(char* buf, int32_t cap) {
 }
 
 void prop_cache_clear(void) {
+  CtxLock lk;
   Ctx& C = ctx();
-  std::lock_guard<std::mutex> lk(C.mu);
   (void)hipDeviceSynchronize();
-  for (auto& kv : C.plans) (void)hipFree(kv.second.tw);
-  for (auto& kv : C.specs)
-    for (int k = 0; k < 4; ++k)
-      if (kv.second.q[k]) (void)hipFree(kv.second.q[k]);
-  for (auto& kv : C.zooms) {
-    (void)hipFree(kv.second.pre);
-    (void)hipFree(kv.second.post);
-    (void)hipFree(kv.second.chat);
-  }
+  // tables pinned by live plans stay: their kernels and graphs address them
+  C.tws.clear_unpinned([](TwEntry& e) { (void)hipFree(e.tw); });
+  C.specs.clear_unpinned(release_spec);
+  C.zooms.clear_unpinned(release_zoom);
   for (auto& kv : C.work) (void)hipFree(kv.second.p);
   for (auto& kv : C.scratch) (void)hipFree(kv.second.p);
   for (auto& kv : C.tune_a) (void)hipFree(kv.second.p);
@@ -1911,11 +2001,29 @@ void prop_cache_clear(void) {
   C.tune_a.clear();
   C.tune_b.clear();
   C.tuned.clear();
-  C.plans.clear();
-  C.specs.clear();
-  C.zooms.clear();
   C.work.clear();
   C.scratch.clear();
+}
+
+void prop_cache_set_limit(int64_t bytes) {
+  CtxLock lk;
+  Ctx& C = ctx();
+  C.limit = bytes > 0 ? (size_t)bytes : default_cache_limit();
+  if (C.specs.bytes() + C.zooms.bytes() > C.limit) evict_tables(C, C.limit);
+}
+
+void prop_cache_info(prop_cache_stats* out) {
+  if (!out) return;
+  CtxLock lk;
+  Ctx& C = ctx();
+  out->table_bytes = (int64_t)(C.specs.bytes() + C.zooms.bytes());
+  out->limit = (int64_t)C.limit;
+  out->spectra = (int64_t)C.specs.size();
+  out->zooms = (int64_t)C.zooms.size();
+  out->twiddles = (int64_t)C.tws.size();
+  out->pinned = (int64_t)(C.specs.pinned() + C.zooms.pinned() + C.tws.pinned());
+  out->evictions = (int64_t)(C.specs.evictions() + C.zooms.evictions());
+  out->eviction_syncs = (int64_t)C.evict_syncs;
 }
 
 const char* prop_status_string(int status) {
@@ -1940,7 +2048,7 @@ int prop_plan_create(prop_dtype t, const prop_setup* setups, int32_t n, uint32_t
   if (n < 1) return PROP_ESHAPE;
   if (!setups) return PROP_ENULL;
   for (int i = 0; i < n; ++i) LP_RET(validate_setup(t, setups[i]));
-  std::lock_guard<std::mutex> lk(ctx().mu);
+  CtxLock lk;
   prop_plan* p = new prop_plan();
   p->t = t;
   p->flags = flags;
@@ -1951,6 +2059,8 @@ int prop_plan_create(prop_dtype t, const prop_setup* setups, int32_t n, uint32_t
     for (auto s : p->br) (void)hipStreamDestroy(s);
     if (p->fork) (void)hipEventDestroy(p->fork);
     for (auto e : p->join) (void)hipEventDestroy(e);
+    ctx().pins = nullptr;
+    unpin_all(p->pins);
     delete p;
     return r;
   };
@@ -1988,15 +2098,20 @@ int prop_plan_create(prop_dtype t, const prop_setup* setups, int32_t n, uint32_t
   p->work.resize(p->nbranch);
   p->gbuf.resize(p->nbranch);
   for (int b = 0; b < p->nbranch; ++b) {
-    r = ensure_buf(p->work[b], wmax, nullptr);
+    // fault injection: the workspace allocation fails as on an exhausted device
+    r = (flags & PROP_PLAN_FAULT_NOMEM) ? dev_err(hipErrorOutOfMemory) : ensure_buf(p->work[b], wmax, nullptr);
     if (r < 0) return fail(r);
     r = ensure_buf(p->gbuf[b], gmax, nullptr);
     if (r < 0) return fail(r);
   }
+  // every table the setups use is computed now and pinned for the plan's
+  // lifetime: its kernels (and captured graphs) address them directly
+  ctx().pins = &p->pins;
   for (auto& ps : p->setups) {
     r = t == PROP_C64 ? warm_setup<float>(p->dev, ps.s, nullptr) : warm_setup<double>(p->dev, ps.s, nullptr);
     if (r < 0) return fail(r);
   }
+  ctx().pins = nullptr;
   if (flags & PROP_PLAN_GRAPH) {
     for (int b = 0; b < p->nbranch; ++b) {
       hipStream_t s;
@@ -2013,25 +2128,26 @@ int prop_plan_create(prop_dtype t, const prop_setup* setups, int32_t n, uint32_t
   }
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return fail(dev_err(e));
+  mark_ready(p->pins);
   *plan = p;
   return PROP_OK;
 }
 
 int prop_plan_forward(prop_plan* plan, void* stream) {
   if (!plan) return PROP_ENULL;
-  std::lock_guard<std::mutex> lk(ctx().mu);
+  CtxLock lk;
   return plan_run(plan, false, (hipStream_t)stream);
 }
 
 int prop_plan_adjoint(prop_plan* plan, void* stream) {
   if (!plan) return PROP_ENULL;
-  std::lock_guard<std::mutex> lk(ctx().mu);
+  CtxLock lk;
   return plan_run(plan, true, (hipStream_t)stream);
 }
 
 void prop_plan_destroy(prop_plan* plan) {
   if (!plan) return;
-  std::lock_guard<std::mutex> lk(ctx().mu);
+  CtxLock lk;
   (void)hipDeviceSynchronize();
   for (int k = 0; k < 2; ++k)
     if (plan->gexec[k]) (void)hipGraphExecDestroy(plan->gexec[k]);
@@ -2041,13 +2157,14 @@ void prop_plan_destroy(prop_plan* plan) {
   for (auto s : plan->br) (void)hipStreamDestroy(s);
   if (plan->fork) (void)hipEventDestroy(plan->fork);
   for (auto e : plan->join) (void)hipEventDestroy(e);
+  unpin_all(plan->pins);
   delete plan;
 }
 
 int prop_last_device_error(void) { return g_last_hip; }
 
 void prop_trace_enable(int32_t on) {
-  std::lock_guard<std::mutex> lk(ctx().mu);
+  CtxLock lk;
   Tracer& t = tracer();
   for (auto& r : t.recs) {
     (void)hipEventSynchronize(r.b);
@@ -2059,12 +2176,12 @@ void prop_trace_enable(int32_t on) {
 }
 
 void prop_trace_only(const char* name) {
-  std::lock_guard<std::mutex> lk(ctx().mu);
+  CtxLock lk;
   tracer().only = name ? name : "";
 }
 
 int32_t prop_trace_read(prop_trace_stat* out, int32_t max) {
-  std::lock_guard<std::mutex> lk(ctx().mu);
+  CtxLock lk;
   Tracer& t = tracer();
   std::vector<prop_trace_stat> agg;
   int status = 0;

@@ -10,7 +10,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "libprop.h")
-LIB = os.path.join(ROOT, "paper_2310_08408_amd", "libprop.so")
+LIB = os.environ.get("LIBPROP_PATH") or os.path.join(ROOT, "paper_2310_08408_amd", "libprop.so")
 
 pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libprop.so not built")
 
