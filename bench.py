@@ -29,6 +29,17 @@ if ROOT not in sys.path:
 
 METRIC = "2048² RS/CZT fwd+adjoint grads/sec, batched FP32 vs plain FP64; HBM BW %"
 HBM_PEAK_GBS = 8000.0
+# FP32 vector peak without packed-FP32 instructions (which no kernel here
+# uses): 256 CUs x 64 FMA lanes x 2 flops x 2.4 GHz
+VALU_PEAK_TFLOPS = 78.6
+
+
+def pass_flops(batch, n=2048, length=4096):
+    """Flop model of each FP32 pass of one headline launch: 5 L log2 L per
+    transform of length L, times the transforms the pass runs."""
+    f = 5.0 * length * math.log2(length)
+    return {"rs_rows_fwd": batch * n * f, "rs_cols": batch * 2 * n * 2 * f, "rs_rows_inv": batch * n * f,
+            "czt_rows": batch * n * 2 * f, "czt_cols": batch * n * 2 * f, "modulate": 0.0}
 BREAKDOWN_STEPS = 10     # untimed steps with every launch traced (per_pass)
 
 
@@ -112,35 +123,115 @@ def rel(a, b):
     return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
 
 
-def cpu_baseline(reps=2):
-    """The FP64 oracle on one 2048^2 field: RS fwd+adj and CZT fwd+adj,
-    `reps` times over (about 10 s of host work at reps=2).  Returns the
-    timing record and the oracle's results (RS and CZT forward fields, the
-    summed phase gradient) for that field."""
-    import numpy as np
-    from threadpoolctl import threadpool_info
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(reps=3):
+    """The FP64 oracle on one 2048^2 field -- RS fwd+adj and CZT fwd+adj with
+    the SLM phase gradient, 2 gradients per pass -- timed as the median of
+    `reps` passes with all host cores (FFT workers and BLAS threads = nproc)
+    and with one thread (about 10 s and 40 s of host work).  Returns the
+    record and the oracle's results (RS and CZT forward fields, the summed
+    phase gradient) for that field."""
+    import statistics
+
+    import scipy.fft
+    from threadpoolctl import threadpool_limits
 
     import oracle
     import workloads
     w = workloads.rs_czt_2048(0)
     g, win, wl = w["grid"], w["window"], w["wavelength"]
     u = oracle.modulate(oracle.gaussian_beam(g, w["w0"], f=w["f"], wavelength=wl), w["phase"])
-    t0 = time.perf_counter()
-    for _ in range(reps):
+
+    def one_pass():
         y = oracle.rs_propagate(u, g, wl, w["z_rs"])
         gr = oracle.rs_adjoint(y, g, wl, w["z_rs"])
         grad = oracle.phase_grad(gr, u)
         yc = oracle.czt_propagate(u, g, win, wl, w["z_czt"])
         gc = oracle.czt_adjoint(yc, g, win, wl, w["z_czt"])
-        grad = grad + oracle.phase_grad(gc, u)
-    dt = time.perf_counter() - t0
-    threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+        return y, yc, grad + oracle.phase_grad(gc, u)
+
+    nproc = os.cpu_count() or 1
+    times = {}
+    for threads in (nproc, 1):
+        ts = []
+        with threadpool_limits(limits=threads), scipy.fft.set_workers(threads):
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                y, yc, grad = one_pass()
+                ts.append(time.perf_counter() - t0)
+        times[threads] = statistics.median(ts)
     ref = {"rs_forward": y, "czt_forward": yc, "phase_grad": grad}
-    return {"value": 2.0 * reps / dt, "unit": "grads/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"one 2048^2 field, {reps} passes: RS fwd+adj and CZT fwd+adj with the SLM phase gradient, "
-                      f"FP64 (numpy/scipy; {dt:.1f} s; FFT steps single-threaded, matrix products on "
-                      f"{threads} BLAS threads)",
-            "seconds": dt}, ref
+    return {"value": 2.0 / times[nproc], "unit": "grads/s", "cores": nproc, "kind": "oracle",
+            "sample": f"one 2048^2 field: RS fwd+adj and CZT fwd+adj with the SLM phase gradient (2 gradients) "
+                      f"per pass, FP64 numpy/scipy, median of {reps} passes on all {nproc} host threads (FFT "
+                      f"workers and BLAS); one thread: {2.0 / times[1]:.4f} grads/s",
+            "seconds_per_pass": times[nproc], "single_thread": {"value": 2.0 / times[1], "seconds_per_pass": times[1]},
+            "nproc": nproc, "cpu_model": cpu_model(), "reps": reps}, ref
+
+
+def uneven_leg(lp, torch, reps=5):
+    """The 96-setup uneven workload as one plan of chained setups (SLM ->
+    RS(z) -> lens f -> CZT at z = f onto a 1024^2 window), one graph launch
+    per direction: time per forward+adjoint replay pair, setup-gradients/s,
+    and the model bytes (per-pass algorithmic reads + writes, fused stages
+    included) against HBM peak."""
+    import numpy as np
+
+    import workloads
+    setups = list(workloads.uneven_96(0, 96, workloads.UNEVEN_SIZES))
+    rng = np.random.default_rng(0)
+    objs, keep = [], []
+    model = 0.0
+    t0 = time.perf_counter()
+    for w in setups:
+        g, win = w["grid"], w["window"]
+        v = lp.prop_source_gaussian(g, w["w0"], w["wavelength"])
+        phi = torch.tensor(w["phase"][None], dtype=torch.float32, device="cuda")
+        gy = torch.from_numpy(workloads.random_field(rng, (1, win.ny, win.nx)).astype(np.complex64)).cuda()
+        y = torch.empty_like(gy)
+        gv, gphi = torch.empty_like(v), torch.empty_like(phi)
+        keep += [v, phi, gy, y, gv, gphi]
+        objs.append(lp.Setup(lp.PROP_OP_RS_CZT, g, [v], [y], [gy], w["wavelength"], w["z"], window=win,
+                             lens_f=w["f"], phase=phi, grad_inputs=[gv], grad_phase=gphi, z2=w["f"]))
+        n, mo = g.nx, win.nx
+        m = lp.prop_fft_length(2 * n - 1)
+        rs = 80.0 * n * n + 8.0 * m * (m // 2 + 1)          # rows, columns (half spectrum), rows
+        czt = 8.0 * (n * n + 2.0 * n * mo + mo * mo)        # Bluestein rows, then columns
+        stage = 4.0 * n * n + (8.0 + 4.0 + 4.0) * n * n     # phase read; adjoint reads V, phase, writes grad
+        model += 2.0 * (rs + czt) + stage
+    import warnings
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        plan = lp.Plan(objs, graph=True)
+        for _ in range(2):
+            plan.forward(); plan.adjoint()
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            plan.forward(); plan.adjoint()
+        e1.record()
+        e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    plan.close()
+    del keep
+    return {"workload": "uneven96: 96 setups, N in {512,768,1024,1536,2048} drawn from the seed, lambda 450-700 nm, "
+                        "RS z 5-100 mm, lens f 10-50 mm, CZT at z=f onto a 1024^2 window of 40 um; complex64, "
+                        "FP64 phases; forward+adjoint with SLM phase and input gradients",
+            "ms_per_replay_pair": ms, "setup_grads_per_s": 96e3 / ms, "model_bytes": model,
+            "hbm_gbs": model / (ms * 1e-3) / 1e9, "hbm_frac": model / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "graph_launches_per_direction": 1, "replays": reps, "plan_build_and_warmup_s": build_s}
 
 
 def main():
@@ -151,6 +242,7 @@ def main():
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the 96-setup uneven plan leg")
     ap.add_argument("--no-trace", action="store_true", help="time without per-kernel events")
     ap.add_argument("--copy-probe", action="store_true",
                     help="finish with a plain 512 MiB device copy (reference for memory counters)")
@@ -200,10 +292,14 @@ def main():
     log(f"fp32 batched: {wall * 1e3:.3f} ms/step wall, {gpu * 1e3:.3f} ms/step gpu -> {value:.1f} grads/s")
 
     per_pass = {}
+    flops = pass_flops(a.batch)
     for name, (n, ms, by) in trace.items():
         avg_ms = ms / max(n, 1)
+        fl = flops.get(name)
         per_pass[name] = {"launches": n, "avg_ms": avg_ms, "bytes_per_launch": by / max(n, 1),
                           "gbs": (by / max(n, 1)) / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None,
+                          "hbm_frac": (by / max(n, 1)) / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if avg_ms > 0 else None,
+                          "valu_frac": fl / (avg_ms * 1e-3) / 1e12 / VALU_PEAK_TFLOPS if fl and avg_ms > 0 else None,
                           "share": ms / max(sum(t[1] for t in trace.values()), 1e-12)}
     roofline = None
     if dom in live:
@@ -213,6 +309,12 @@ def main():
         roofline = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(dom), "kernel": dom,
                     "bytes_per_launch": bpl, "avg_ms": avg_ms, "launches": n}
+        if flops.get(dom):
+            tf = flops[dom] / (avg_ms * 1e-3) / 1e12
+            roofline["valu_frac"] = tf / VALU_PEAK_TFLOPS
+            roofline["valu"] = {"bound": "alu", "achieved": tf, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                "frac": tf / VALU_PEAK_TFLOPS, "flops_per_launch": flops[dom],
+                                "model": "5 L log2 L per length-L transform; FP32 vector peak without packed FP32"}
     total_model_bytes = sum(t[2] for t in trace.values()) / BREAKDOWN_STEPS
     step_frac = total_model_bytes / wall / 1e9 / HBM_PEAK_GBS if trace else None
 
@@ -260,12 +362,20 @@ def main():
     del src, dst
     log(f"device copy of 512 MiB: {copy_gbs:.0f} GB/s")
 
+    uneven = None
+    if not a.no_uneven:
+        log("uneven 96-setup plan ...")
+        uneven = uneven_leg(lp, torch)
+        log(f"uneven 96: {uneven['ms_per_replay_pair']:.2f} ms per forward+adjoint replay pair, "
+            f"{uneven['setup_grads_per_s']:.0f} setup-gradients/s, {uneven['hbm_frac']:.3f} of HBM peak")
+
     cpu, errs_oracle = None, None
     if not a.no_cpu:
         import numpy as np
         log("cpu baseline (FP64 oracle) ...")
         cpu, ref = cpu_baseline()
-        log(f"cpu baseline: {cpu['value']:.4f} grads/s ({cpu['seconds']:.1f} s)")
+        log(f"cpu baseline: {cpu['value']:.4f} grads/s on {cpu['cores']} threads, "
+            f"{cpu['single_thread']['value']:.4f} on one ({cpu['cpu_model']})")
         # item 0 of the batch is the oracle's field: FP32 results against it
         got = {"rs_forward": y32[0], "czt_forward": c32[0], "phase_grad": step.grad[0]}
         errs_oracle = {}
@@ -291,6 +401,7 @@ def main():
         "errors_vs_fp64": errs,
         "errors_vs_oracle": errs_oracle,
         "per_pass": per_pass,
+        "uneven96": uneven,
         "gpu_ms_per_step": gpu * 1e3,
         "first_step_ms": t_setup * 1e3,
     }

@@ -4,6 +4,12 @@
     python bench_profile.py stats DIR [--command TEXT]
         per-kernel calls / average / total time from DIR/*_kernel_stats.csv
 
+    python bench_profile.py counters DIR [DIR ...] [--command TEXT]
+        SQ counters of the FP32 bench passes (one or more --pmc runs):
+        VALU and LDS instructions per wave and per transform point, LDS
+        bank-conflict cycles per active LDS cycle, waiting cycles per wave
+        cycle, VALU-active cycles per wave cycle.
+
     python bench_profile.py traffic --fetch DIR --write DIR [--json OUT] [--command TEXT]
         HBM bytes per dispatch from two counter runs (FETCH_SIZE, WRITE_SIZE;
         KiB per dispatch), each scaled by what the same counter reads for the
@@ -124,6 +130,50 @@ def cmd_traffic(a):
         print(f"# wrote {os.path.relpath(a.json, ROOT)} ({len(out)} passes, source_sha {sha})")
 
 
+# transform points (lines x line length) of one batch-8 launch of each FP32
+# pass of the 2048^2 bench step: the unit of the per-point instruction counts
+BENCH_POINTS = {
+    "rs_rows_fwd": 8 * 2048 * 4096,
+    "rs_cols": 8 * 4096 * 4096,
+    "rs_rows_inv": 8 * 2048 * 4096,
+    "czt_rows": 8 * 2048 * 4096,
+    "czt_cols": 8 * 2048 * 4096,
+}
+
+
+def cmd_counters(a):
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    for d in a.dirs:
+        for r in csv.DictReader(open(find(d, "counter_collection.csv"))):
+            key = (r["Kernel_Name"].split("(")[0], int(r["Grid_Size"]))
+            vals[key][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    mean = lambda v: sum(v) / len(v) if v else float("nan")
+    if a.command:
+        for c in a.command:
+            print(f"# command: {c}")
+    print("# per dispatch (mean over dispatches): VALU/LDS = instructions per wave; per pt = lane instructions per"
+          " transform point; bank = conflict cycles per conflict-free LDS cycle, SQ_LDS_BANK_CONFLICT /"
+          " (SQ_LDS_IDX_ACTIVE - SQ_LDS_BANK_CONFLICT); wait = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES; valu_act ="
+          " SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES (per wave; times the waves per SIMD gives the SIMD's VALU share)")
+    print(f"{'pass':12s} {'kernel':66s} {'waves':>8s} {'VALU':>7s} {'LDS':>6s} {'VALU/pt':>8s} {'LDS/pt':>7s} "
+          f"{'bank':>6s} {'wait':>6s} {'valu_act':>8s}")
+    for name, prefix in PASS_KERNELS.items():
+        prefixes = (prefix,) if isinstance(prefix, str) else prefix
+        for key in sorted(k for k in vals if k[0].startswith(prefixes)):
+            c = {k: mean(v) for k, v in vals[key].items()}
+            waves = c.get("SQ_WAVES", float("nan"))
+            valu, lds = c.get("SQ_INSTS_VALU", float("nan")), c.get("SQ_INSTS_LDS", float("nan"))
+            pts = BENCH_POINTS.get(name)
+            per = (lambda x: 64.0 * x / pts) if pts else (lambda x: float("nan"))
+            ratio = lambda n, d: c.get(n, float("nan")) / c[d] if c.get(d) else float("nan")
+            conf, idx = c.get("SQ_LDS_BANK_CONFLICT", float("nan")), c.get("SQ_LDS_IDX_ACTIVE", float("nan"))
+            bank = conf / (idx - conf) if idx and idx > conf else float("nan")
+            print(f"{name:12s} {short(key[0], 66):66s} {waves:8.0f} {valu / waves:7.0f} {lds / waves:6.0f} "
+                  f"{per(valu):8.2f} {per(lds):7.2f} {bank:6.3f} "
+                  f"{ratio('SQ_WAIT_INST_ANY', 'SQ_WAVE_CYCLES'):6.3f} "
+                  f"{ratio('SQ_ACTIVE_INST_VALU', 'SQ_WAVE_CYCLES'):8.3f}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -135,8 +185,11 @@ def main():
     t.add_argument("--write", required=True)
     t.add_argument("--json")
     t.add_argument("--command", action="append")
+    c = sub.add_parser("counters")
+    c.add_argument("dirs", nargs="+")
+    c.add_argument("--command", action="append")
     a = ap.parse_args()
-    {"stats": cmd_stats, "traffic": cmd_traffic}[a.cmd](a)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "counters": cmd_counters}[a.cmd](a)
 
 
 if __name__ == "__main__":

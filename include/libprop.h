@@ -293,6 +293,7 @@ int prop_spot_loss(prop_dtype t, const void* ex, const void* ey, const void* ez,
                    double wavelength, double w_fz, double* result, void* gx, void* gy, void* gz,
                    int32_t batch, void* stream);
 
+
 /* The paper's detector side (Methods: STED microscopy; loss function;
  * exploration of optical topologies).
  * prop_density_loss: threshold-density loss L = Area / I_eps of the
@@ -404,20 +405,34 @@ int prop_last_device_error(void);
  * (setups spread over up to 4 parallel branches) and afterwards replays each
  * as a single hipGraphLaunch on the caller's stream.
  *
- * Per setup (one propagator call on `batch` fields):
- *   forward: u = in * exp(i phase) * exp(-i k r^2 / (2 lens_f)) (each factor
- *            optional; the plan keeps u), out = op(u);
- *   adjoint: g_u = op^H(gout); gin = g_u * conj(factor) (if gin != NULL);
- *            grad_phase = sum over input components Im(g_u conj(u))
- *            (if grad_phase != NULL).  Requires a preceding forward.
- * Scalar ops use in[0], out[0], gout[0], gin[0]; vector ops use two inputs
- * and three outputs.  phase / grad_phase: real [batch][g_in.ny][g_in.nx]
- * (float for PROP_C64, double for PROP_C128).  All pointers are device
- * memory owned by the caller and must stay valid for the plan's lifetime.
+ * Per setup (one propagator call, or one RS -> lens -> CZT chain, on
+ * `batch` fields), with the stage factor f = exp(i phase) exp(-i k r^2 /
+ * (2 lens_f)) (each factor optional):
+ *   scalar ops (RS, CZT): forward out = op(in * f); adjoint g_u = op^H(gout),
+ *     gin = g_u conj(f) (if gin != NULL), grad_phase = Im(g_u conj(in * f))
+ *     (if grad_phase != NULL).  The stage runs inside the transforms: the
+ *     phase multiplies the loads of the first pass, and the last pass of the
+ *     adjoint writes gin and grad_phase; a CZT folds its lens into the input
+ *     chirp exactly, RS applies it as separable factors.  The adjoint reads
+ *     in[0] again, which must therefore still hold the forward's input;
+ *   PROP_OP_RS_CZT (the chain of one setup of the paper's batched searches:
+ *     SLM, free space, lens, focal plane): forward out = CZT_z2(L RS_z(in *
+ *     exp(i phase))), L = exp(-i k r^2 / (2 lens_f)) (lens_f 0: none) on the
+ *     input grid, CZT over z2 onto `win`; adjoint gin and grad_phase of
+ *     in and phase as above.  The lens folds into the CZT chirp; the RS -> CZT
+ *     intermediate lives in the plan's workspace;
+ *   vector ops (VRS, VCZT): forward u = in * f (a pass of its own; the plan
+ *     keeps u), out = op(u); adjoint g_u = op^H(gout), gin = g_u conj(f),
+ *     grad_phase = sum over both components Im(g_u conj(u)).
+ * Adjoints require a preceding forward.  Scalar ops use in[0], out[0],
+ * gout[0], gin[0]; vector ops use two inputs and three outputs.  phase /
+ * grad_phase: real [batch][g_in.ny][g_in.nx] (float for PROP_C64, double
+ * for PROP_C128).  All pointers are device memory owned by the caller and
+ * must stay valid for the plan's lifetime.
  * Errors: as the single calls, reported by prop_plan_create with *plan set
  * to NULL; PROP_ESHAPE for an unknown op.
  */
-enum { PROP_OP_RS = 0, PROP_OP_CZT = 1, PROP_OP_VRS = 2, PROP_OP_VCZT = 3 };
+enum { PROP_OP_RS = 0, PROP_OP_CZT = 1, PROP_OP_VRS = 2, PROP_OP_VCZT = 3, PROP_OP_RS_CZT = 4 };
 #define PROP_PLAN_GRAPH 1u
 /* PROP_PLAN_AUTOTUNE: the first prop_plan_forward and the first
  * prop_plan_adjoint run eagerly with the autotuner on (see
@@ -433,17 +448,18 @@ enum { PROP_OP_RS = 0, PROP_OP_CZT = 1, PROP_OP_VRS = 2, PROP_OP_VCZT = 3 };
 typedef struct {
   int32_t op;           /* PROP_OP_* */
   int32_t batch;        /* fields in this setup (>= 1) */
-  prop_grid g_in, win;  /* win: output window of CZT / VCZT (ignored for RS / VRS) */
-  double wavelength, z; /* z ignored by focusing VCZT */
+  prop_grid g_in, win;  /* win: output window of CZT / VCZT / RS_CZT (ignored for RS / VRS) */
+  double wavelength, z; /* z ignored by focusing VCZT; the RS distance of RS_CZT */
   int32_t has_lens;     /* VCZT: focusing mode with `lens` */
   prop_lens lens;
-  double lens_f;        /* > 0: thin-lens phase applied to the input first */
+  double lens_f;        /* > 0: thin-lens phase on the input (RS_CZT: between RS and CZT) */
   const void* phase;    /* optional SLM phase applied to the input */
   const void* in[2];
   void* out[3];
   const void* gout[3];
   void* gin[2];
   void* grad_phase;     /* optional: dL/dphase */
+  double z2;            /* RS_CZT: the CZT distance (> 0); ignored otherwise */
 } prop_setup;
 
 typedef struct prop_plan prop_plan;

@@ -25,7 +25,7 @@ __all__ = [
     "prop_softmin", "prop_adam_step", "Adam", "prop_track_best", "StopRule", "prop_sampling_check",
     "prop_fft_length", "prop_cache_clear", "prop_trace_enable", "prop_trace_read", "prop_trace_only", "prop_autotune_report",
     "PropError", "PropWarning", "library", "Plan", "Setup", "PROP_OP_RS", "PROP_OP_CZT", "PROP_OP_VRS",
-    "PROP_OP_VCZT", "PROP_PLAN_GRAPH", "PROP_PLAN_AUTOTUNE", "PROP_PLAN_FAULT_NOMEM", "prop_cache_set_limit",
+    "PROP_OP_VCZT", "PROP_OP_RS_CZT", "PROP_PLAN_GRAPH", "PROP_PLAN_AUTOTUNE", "PROP_PLAN_FAULT_NOMEM", "prop_cache_set_limit",
     "prop_cache_info",
 ]
 
@@ -792,7 +792,7 @@ def prop_autotune_report() -> str:
 
 # ---------------------------------------------------------------------- plans --
 
-PROP_OP_RS, PROP_OP_CZT, PROP_OP_VRS, PROP_OP_VCZT = 0, 1, 2, 3
+PROP_OP_RS, PROP_OP_CZT, PROP_OP_VRS, PROP_OP_VCZT, PROP_OP_RS_CZT = 0, 1, 2, 3, 4
 PROP_PLAN_GRAPH = 1
 PROP_PLAN_AUTOTUNE = 2
 PROP_PLAN_FAULT_NOMEM = 0x100
@@ -806,8 +806,9 @@ class Setup:
     """
 
     def __init__(self, op, grid, inputs, outputs, grad_outputs, wavelength, z=0.0, window=None, lens=None,
-                 lens_f=0.0, phase=None, grad_inputs=None, grad_phase=None):
+                 lens_f=0.0, phase=None, grad_inputs=None, grad_phase=None, z2=0.0):
         self.op, self.grid, self.window = op, grid, window
+        self.z2 = z2
         self.inputs, self.outputs, self.grad_outputs = list(inputs), list(outputs), list(grad_outputs)
         self.grad_inputs = list(grad_inputs) if grad_inputs is not None else []
         self.wavelength, self.z, self.lens, self.lens_f = wavelength, z, lens, lens_f
@@ -818,7 +819,7 @@ class Setup:
         the plan's dtype and device and the setup's grids and batch."""
         vec = self.op in (PROP_OP_VRS, PROP_OP_VCZT)
         nin, nout = (2, 3) if vec else (1, 1)
-        if self.op not in (PROP_OP_RS, PROP_OP_CZT, PROP_OP_VRS, PROP_OP_VCZT):
+        if self.op not in (PROP_OP_RS, PROP_OP_CZT, PROP_OP_VRS, PROP_OP_VCZT, PROP_OP_RS_CZT):
             raise ValueError(f"unknown op {self.op}")
         if len(self.inputs) != nin or len(self.outputs) != nout or len(self.grad_outputs) != nout:
             raise ValueError(f"op {self.op} takes {nin} inputs, {nout} outputs and {nout} output gradients")
@@ -830,9 +831,9 @@ class Setup:
         if ref.device != device:
             raise ValueError(f"setup tensors on {ref.device}, the plan runs on {device}")
         b = _batch(ref, self.grid)
-        out_grid = self.window if self.op in (PROP_OP_CZT, PROP_OP_VCZT) else self.grid
+        out_grid = self.window if self.op in (PROP_OP_CZT, PROP_OP_VCZT, PROP_OP_RS_CZT) else self.grid
         if out_grid is None:
-            raise ValueError("CZT and VCZT setups need an output window")
+            raise ValueError("CZT, VCZT and RS_CZT setups need an output window")
         for name, ts, g in (("inputs", self.inputs, self.grid), ("outputs", self.outputs, out_grid),
                             ("grad_outputs", self.grad_outputs, out_grid), ("grad_inputs", self.grad_inputs, self.grid)):
             for i, t in enumerate(ts):
@@ -847,7 +848,7 @@ class Setup:
         s.g_in = _lib.grid(self.grid)
         if self.window is not None:
             s.win = _lib.grid(self.window)
-        s.wavelength, s.z = float(self.wavelength), float(self.z)
+        s.wavelength, s.z, s.z2 = float(self.wavelength), float(self.z), float(self.z2)
         if self.lens is not None:
             na, f = (self.lens.na, self.lens.f) if hasattr(self.lens, "na") else self.lens
             s.has_lens, s.lens = 1, _lib.prop_lens(float(na), float(f))

@@ -42,7 +42,7 @@ class prop_setup(ctypes.Structure):
     _fields_ = [("op", c_int32), ("batch", c_int32), ("g_in", prop_grid), ("win", prop_grid),
                 ("wavelength", c_double), ("z", c_double), ("has_lens", c_int32), ("lens", prop_lens),
                 ("lens_f", c_double), ("phase", c_void_p), ("in_", c_void_p * 2), ("out", c_void_p * 3),
-                ("gout", c_void_p * 3), ("gin", c_void_p * 2), ("grad_phase", c_void_p)]
+                ("gout", c_void_p * 3), ("gin", c_void_p * 2), ("grad_phase", c_void_p), ("z2", c_double)]
 
 
 class prop_cache_stats(ctypes.Structure):

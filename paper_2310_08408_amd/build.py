@@ -21,6 +21,8 @@ LIB = os.path.join(HERE, "libprop.so")
 SOURCES = [
     "inst_conv_f32.hip",
     "inst_conv_f64.hip",
+    "inst_blue_f32.hip",
+    "inst_blue_f64.hip",
     "inst_fft_f32.hip",
     "inst_fft_f64.hip",
     "elementwise.hip",

@@ -192,6 +192,34 @@ struct PhaseGradPre {
   }
 };
 
+// Factor of the fused SLM stage (Slm) at field element (row, col) of batch
+// item b, and the adjoint store of a pass that ends in it: g_V = g_U
+// conj(factor), with the phase gradient Im(g_V conj V) when requested.
+template <typename T> __device__ __forceinline__ void slm_sincos(T x, T* s, T* c);
+template <> __device__ __forceinline__ void slm_sincos<float>(float x, float* s, float* c) { sincosf(x, s, c); }
+template <> __device__ __forceinline__ void slm_sincos<double>(double x, double* s, double* c) { sincos(x, s, c); }
+
+template <typename T>
+__device__ __forceinline__ cx<T> slm_factor(const Slm<T>& st, int b, int row, int col) {
+  cx<T> f = mk<T>(T(1), T(0));
+  if (st.phase) {
+    T sn, cs;
+    slm_sincos<T>(st.phase[b * st.pbs + (int64_t)row * st.nx + col], &sn, &cs);
+    f = mk<T>(cs, sn);
+  }
+  if (st.lx) f = cmul(f, cmul(st.lx[col], st.ly[row]));
+  return f;
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> slm_adjoint_store(const Slm<T>& st, const PhaseGrad<T>& pg, cx<T>* out, int b,
+                                                   int row, int col, int64_t o, cx<T> g) {
+  const cx<T> gv = cmulc(g, slm_factor(st, b, row, col));
+  if (out) out[o] = gv;
+  if (pg.grad) pg.put(o, gv);
+  return gv;
+}
+
 template <typename T> __device__ __forceinline__ cx<T> czero() { return mk<T>(T(0), T(0)); }
 
 // address of element i of line l of batch item b
@@ -293,10 +321,12 @@ struct RowCfg {
 // otherwise split every access into its own exec-masked block.
 // PG = false: an instance without the phase-gradient epilogue, for launches
 // that have none (its early loads would hold 24 VGPRs for nothing).
-template <typename T, int DIR, class S, int C, bool HALF, bool EXACT = false, bool PG = true>
+// STAGE: the fused SLM stage of a plan setup (Slm) on the loads (forward)
+// or the stores (inverse).
+template <typename T, int DIR, class S, int C, bool HALF, bool EXACT = false, bool PG = true, bool STAGE = false>
 __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) void k_rs_rows(
     const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int64_t w_bstride, int nrows, int n_io, T scale, int tiles,
-    const cx<T>* __restrict__ tw, PhaseGrad<T> pg) {
+    const cx<T>* __restrict__ tw, PhaseGrad<T> pg, Slm<T> st) {
   constexpr int LS = line_stride<S, C, true>();
   __shared__ cx<T> smem[C * LS];
   const int id = xcd_remap(blockIdx.x, gridDim.x);
@@ -312,7 +342,10 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
   if constexpr (DIR < 0) {
     auto load = [&](int i) -> cx<T> {
       cx<T> v = czero<T>();
-      if (valid && (EXACT || i < n_io)) v = in[frow + i];
+      if (valid && (EXACT || i < n_io)) {
+        v = in[frow + i];
+        if constexpr (STAGE) v = cmul(v, slm_factor(st, b, y, i));
+      }
       return v;
     };
     auto store = [&](int i, cx<T> v) {
@@ -325,14 +358,18 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
       if (valid) v = in[widx(i)];
       return v;
     };
-    PhaseGradPre<T, S, PG && pg_preload<T, S, EXACT && HALF>()> pre_pg;
+    PhaseGradPre<T, S, PG && !STAGE && pg_preload<T, S, EXACT && HALF>()> pre_pg;
     pre_pg.load(pg, j, [&](int i) { return frow + i; });
     auto store = [&](int i, cx<T> v) {
       if (valid && (EXACT || i < n_io)) {
         const cx<T> g = cscale(v, scale);
-        if (out) out[frow + i] = g;
-        if constexpr (PG) {
-          if (pg.grad) pre_pg.put(pg, i, j, frow + i, g);
+        if constexpr (STAGE) {
+          slm_adjoint_store(st, pg, out, b, y, i, frow + i, g);
+        } else {
+          if (out) out[frow + i] = g;
+          if constexpr (PG) {
+            if (pg.grad) pre_pg.put(pg, i, j, frow + i, g);
+          }
         }
       }
     };
@@ -346,10 +383,10 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
 // registers while it transforms the current one.  The engine reads the half
 // input as elements j + r n/R0 (r < R0/2) of the threads j < n/R0 only, so
 // those threads alone prefetch, each its own elements.
-template <typename T, class S, int C>
+template <typename T, class S, int C, bool STAGE = false>
 __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) void k_rs_rows_fwd_persist(
     const cx<T>* in, cx<T>* out, int64_t w_bstride, int nrows, int n_io, int tiles, int items, int per,
-    TableBox<T> tw_) {
+    TableBox<T> tw_, Slm<T> st) {
   const cx<T>* tw = tw_.p;
   constexpr int LS = line_stride<S, C, true>();
   __shared__ cx<T> smem[C * LS];
@@ -383,15 +420,18 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
     const int b = id / tiles, y = (id - b * tiles) * C + c;
     const int64_t wrow = b * w_bstride + (int64_t)y * kTile;
     // the first stage asks for i = HI::index(j, r): register r of cur
-    auto load = [&](int i) -> cx<T> { return cur[(i - j) / HI::nr]; };
+    auto load = [&](int i) -> cx<T> {
+      if constexpr (STAGE) return cmul(cur[(i - j) / HI::nr], slm_factor(st, b, y, i));
+      return cur[(i - j) / HI::nr];
+    };
     auto store = [&](int i, cx<T> v) { out[wrow + (int64_t)(i >> kTileShift) * tst + (i & (kTile - 1))] = v; };
     fft_line<T, -1, S, true, false>(lds, tw, j, load, store);
   }
 }
 
-template <typename T, int DIR, class S>
-hipError_t launch_rs_rows_s(const cx<T>* in, cx<T>* out, int64_t w_bstride, int nrows, int n_io, T scale, int batch,
-                            const cx<T>* tw, hipStream_t s, PhaseGrad<T> pg) {
+template <typename T, int DIR, class S, bool STAGE>
+hipError_t launch_rs_rows_st(const cx<T>* in, cx<T>* out, int64_t w_bstride, int nrows, int n_io, T scale, int batch,
+                             const cx<T>* tw, hipStream_t s, PhaseGrad<T> pg, Slm<T> st) {
   using RC = RowCfg<T, S>;
   if constexpr (!RC::fits) {
     return hipErrorInvalidValue;
@@ -401,42 +441,54 @@ hipError_t launch_rs_rows_s(const cx<T>* in, cx<T>* out, int64_t w_bstride, int 
     constexpr bool can_half = S::rad[0] % 2 == 0 && S::rad[S::nst - 1] % 2 == 0;
     if constexpr (can_half) {
       if (2 * n_io == S::n && nrows % C == 0) {
-        if constexpr (DIR < 0 && tw_per_thread<T>() && S::rad[0] <= 16) {
+        // (with the fused SLM stage the persistent form's prefetch registers
+        // spill next to the stage's sincos: the plain instance runs instead)
+        if constexpr (DIR < 0 && tw_per_thread<T>() && S::rad[0] <= 16 && !STAGE) {
           const int items = tiles * batch;
           const PersistSplit sp = persist_split(items, cu_count());
           hipLaunchKernelGGL((k_rs_rows_fwd_persist<T, S, C>), dim3(sp.groups), dim3(RC::threads), 0, s, in, out,
-                             w_bstride, nrows, n_io, tiles, items, sp.per, TableBox<T>{tw});
+                             w_bstride, nrows, n_io, tiles, items, sp.per, TableBox<T>{tw}, st);
         } else {
           // rows need not fill whole workspace tiles: C2 may be below kTile.
           // With the phase-gradient epilogue fused, C lines measure faster
           // (4096: 248 against 257 us; plain: 218 against 212 us at C2).
           constexpr int C2 = row_lines_two_per_cu<T, S, C>();
-          if (C2 != C && !pg.grad) {
+          if (C2 != C && !pg.grad && !STAGE) {
             const int tiles2 = nrows / C2;
             hipLaunchKernelGGL((k_rs_rows<T, DIR, S, C2, true, true, false>), dim3(tiles2 * batch),
-                               dim3(C2 * S::threads), 0, s, in, out, w_bstride, nrows, n_io, scale, tiles2, tw, pg);
+                               dim3(C2 * S::threads), 0, s, in, out, w_bstride, nrows, n_io, scale, tiles2, tw, pg,
+                               st);
           } else {
-            hipLaunchKernelGGL((k_rs_rows<T, DIR, S, C, true, true>), dim3(tiles * batch), dim3(RC::threads), 0, s,
-                               in, out, w_bstride, nrows, n_io, scale, tiles, tw, pg);
+            hipLaunchKernelGGL((k_rs_rows<T, DIR, S, C, true, true, true, STAGE>), dim3(tiles * batch),
+                               dim3(RC::threads), 0, s, in, out, w_bstride, nrows, n_io, scale, tiles, tw, pg, st);
           }
         }
         return hipGetLastError();
       }
       if (2 * n_io <= S::n) {
-        hipLaunchKernelGGL((k_rs_rows<T, DIR, S, C, true>), dim3(tiles * batch), dim3(RC::threads), 0, s, in, out,
-                           w_bstride, nrows, n_io, scale, tiles, tw, pg);
+        hipLaunchKernelGGL((k_rs_rows<T, DIR, S, C, true, false, true, STAGE>), dim3(tiles * batch),
+                           dim3(RC::threads), 0, s, in, out, w_bstride, nrows, n_io, scale, tiles, tw, pg, st);
         return hipGetLastError();
       }
     }
-    hipLaunchKernelGGL((k_rs_rows<T, DIR, S, C, false>), dim3(tiles * batch), dim3(RC::threads), 0, s, in, out,
-                       w_bstride, nrows, n_io, scale, tiles, tw, pg);
+    hipLaunchKernelGGL((k_rs_rows<T, DIR, S, C, false, false, true, STAGE>), dim3(tiles * batch), dim3(RC::threads),
+                       0, s, in, out, w_bstride, nrows, n_io, scale, tiles, tw, pg, st);
     return hipGetLastError();
   }
 }
 
+template <typename T, int DIR, class S>
+hipError_t launch_rs_rows_s(const cx<T>* in, cx<T>* out, int64_t w_bstride, int nrows, int n_io, T scale, int batch,
+                            const cx<T>* tw, hipStream_t s, PhaseGrad<T> pg, const Slm<T>* slm) {
+  if (slm && slm->active())
+    return launch_rs_rows_st<T, DIR, S, true>(in, out, w_bstride, nrows, n_io, scale, batch, tw, s, pg, *slm);
+  return launch_rs_rows_st<T, DIR, S, false>(in, out, w_bstride, nrows, n_io, scale, batch, tw, s, pg, Slm<T>{});
+}
+
 template <typename T, int DIR>
 hipError_t launch_rs_rows(int n, const cx<T>* in, cx<T>* out, int64_t w_bstride, int nrows, int n_io, T scale,
-                          int batch, const cx<T>* tw, hipStream_t s, const cx<T>* pg_u, T* pg_grad, int pg_acc) {
+                          int batch, const cx<T>* tw, hipStream_t s, const cx<T>* pg_u, T* pg_grad, int pg_acc,
+                          const Slm<T>* slm) {
   if (nrows <= 0 || batch <= 0) return hipSuccess;
   PhaseGrad<T> pg;
   pg.u = pg_u;
@@ -444,7 +496,7 @@ hipError_t launch_rs_rows(int n, const cx<T>* in, cx<T>* out, int64_t w_bstride,
   pg.acc = pg_acc;
   switch (n) {
 #define LP_CASE(N, ...) \
-  case N: return launch_rs_rows_s<T, DIR, SchedOf<T, Sched<__VA_ARGS__>>>(in, out, w_bstride, nrows, n_io, scale, batch, tw, s, pg);
+  case N: return launch_rs_rows_s<T, DIR, SchedOf<T, Sched<__VA_ARGS__>>>(in, out, w_bstride, nrows, n_io, scale, batch, tw, s, pg, slm);
     LP_LENGTHS(LP_CASE)
 #undef LP_CASE
     default:
@@ -753,14 +805,17 @@ constexpr bool bluestein_interleaved() {
 
 // PG = false: as for the row pass, an instance without the phase-gradient
 // epilogue (used for row lines; the column instance measured no better).
-template <typename T, bool COL, class S, int C, bool HALF, bool EXACT = false, bool PG = true>
+// STAGE: the fused SLM stage of a plan setup (Slm) on the loads (first pass
+// of a forward transform) or the stores (last pass of an adjoint); the
+// field row and column of element i of line l follow from COL.
+template <typename T, bool COL, class S, int C, bool HALF, bool EXACT = false, bool PG = true, bool STAGE = false>
 __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, bluestein_interleaved<T, COL>(), 1,
                                                             HALF ? (bluestein_interleaved<T, COL>() ? 4 : 3) : 2>())) void k_bluestein(const cx<T>* in, cx<T>* out, Lines li, Lines lo,
                                                               int nlines, int n_in, int n_out,
                                                               const cx<T>* __restrict__ pre,
                                                               const cx<T>* __restrict__ chat,
                                                               const cx<T>* __restrict__ post, int tiles,
-                                                              const cx<T>* tw, PhaseGrad<T> pg) {
+                                                              const cx<T>* tw, PhaseGrad<T> pg, Slm<T> st) {
   constexpr bool ILV = bluestein_interleaved<T, COL>();
   constexpr int LS = line_stride<S, C, ILV>();
   __shared__ cx<T> smem[C * LS];
@@ -773,16 +828,27 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, bluestein_in
   cx<T>* lds = smem + c * LS;
   auto load = [&](int i) -> cx<T> {
     cx<T> v = czero<T>();
-    if (valid && (EXACT || i < n_in)) v = cmul(in[line_off<COL>(li, b, l, i)], pre[i]);
+    if (valid && (EXACT || i < n_in)) {
+      v = cmul(in[line_off<COL>(li, b, l, i)], pre[i]);
+      if constexpr (STAGE) {
+        if (!st.adjoint) v = cmul(v, slm_factor(st, b, COL ? i : l, COL ? l : i));
+      }
+    }
     return v;
   };
   auto mult = [&](int i, cx<T> v) -> cx<T> { return cmul(v, chat[i]); };
-  PhaseGradPre<T, S, PG && pg_preload<T, S, EXACT && HALF>()> pre_pg;
+  PhaseGradPre<T, S, PG && !STAGE && pg_preload<T, S, EXACT && HALF>()> pre_pg;
   pre_pg.load(pg, j, [&](int i) { return line_off<COL>(lo, b, l, i); });
   auto store = [&](int i, cx<T> v) {
     if (valid && (EXACT || i < n_out)) {
       const int64_t o = line_off<COL>(lo, b, l, i);
       const cx<T> g = cmul(v, post[i]);
+      if constexpr (STAGE) {
+        if (st.adjoint) {
+          slm_adjoint_store(st, pg, out, b, COL ? i : l, COL ? l : i, o, g);
+          return;
+        }
+      }
       if (out) out[o] = g;
       if constexpr (PG) {
         if (pg.grad) pre_pg.put(pg, i, j, o, g);
@@ -792,37 +858,51 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, bluestein_in
   conv_line<T, S, HALF, HALF>(lds, tw, j, load, mult, store);
 }
 
-template <typename T, bool COL, class S, int C>
+template <typename T, bool COL, class S, int C, bool STAGE>
 hipError_t launch_bluestein_c(const cx<T>* in, cx<T>* out, Lines li, Lines lo, int nlines, int n_in, int n_out,
                               const cx<T>* pre, const cx<T>* chat, const cx<T>* post, int batch, const cx<T>* tw,
-                              hipStream_t s, PhaseGrad<T> pg) {
+                              hipStream_t s, PhaseGrad<T> pg, Slm<T> st) {
   const int tiles = (nlines + C - 1) / C;
   constexpr bool can_half = S::rad[0] % 2 == 0 && S::rad[S::nst - 1] % 2 == 0;
   if constexpr (can_half) {
     if (2 * n_in == S::n && 2 * n_out == S::n && nlines % C == 0) {
-      if (COL || pg.grad)
-        hipLaunchKernelGGL((k_bluestein<T, COL, S, C, true, true>), dim3(tiles * batch), dim3(C * S::threads), 0, s,
-                           in, out, li, lo, nlines, n_in, n_out, pre, chat, post, tiles, tw, pg);
+      if (COL || pg.grad || STAGE)
+        hipLaunchKernelGGL((k_bluestein<T, COL, S, C, true, true, true, STAGE>), dim3(tiles * batch),
+                           dim3(C * S::threads), 0, s, in, out, li, lo, nlines, n_in, n_out, pre, chat, post, tiles, tw,
+                           pg, st);
       else
         hipLaunchKernelGGL((k_bluestein<T, COL, S, C, true, true, COL>), dim3(tiles * batch), dim3(C * S::threads),
-                           0, s, in, out, li, lo, nlines, n_in, n_out, pre, chat, post, tiles, tw, pg);
+                           0, s, in, out, li, lo, nlines, n_in, n_out, pre, chat, post, tiles, tw, pg, st);
       return hipGetLastError();
     }
     if (2 * n_in <= S::n && 2 * n_out <= S::n) {
-      hipLaunchKernelGGL((k_bluestein<T, COL, S, C, true>), dim3(tiles * batch), dim3(C * S::threads), 0, s, in, out,
-                         li, lo, nlines, n_in, n_out, pre, chat, post, tiles, tw, pg);
+      hipLaunchKernelGGL((k_bluestein<T, COL, S, C, true, false, true, STAGE>), dim3(tiles * batch),
+                         dim3(C * S::threads), 0, s, in, out, li, lo, nlines, n_in, n_out, pre, chat, post, tiles, tw,
+                         pg, st);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((k_bluestein<T, COL, S, C, false>), dim3(tiles * batch), dim3(C * S::threads), 0, s, in, out, li,
-                     lo, nlines, n_in, n_out, pre, chat, post, tiles, tw, pg);
+  hipLaunchKernelGGL((k_bluestein<T, COL, S, C, false, false, true, STAGE>), dim3(tiles * batch),
+                     dim3(C * S::threads), 0, s, in, out, li, lo, nlines, n_in, n_out, pre, chat, post, tiles, tw, pg,
+                     st);
   return hipGetLastError();
+}
+
+template <typename T, bool COL, class S, int C>
+hipError_t launch_bluestein_cs(const cx<T>* in, cx<T>* out, Lines li, Lines lo, int nlines, int n_in, int n_out,
+                               const cx<T>* pre, const cx<T>* chat, const cx<T>* post, int batch, const cx<T>* tw,
+                               hipStream_t s, PhaseGrad<T> pg, const Slm<T>* slm) {
+  if (slm && slm->active())
+    return launch_bluestein_c<T, COL, S, C, true>(in, out, li, lo, nlines, n_in, n_out, pre, chat, post, batch, tw, s,
+                                                  pg, *slm);
+  return launch_bluestein_c<T, COL, S, C, false>(in, out, li, lo, nlines, n_in, n_out, pre, chat, post, batch, tw, s,
+                                                 pg, Slm<T>{});
 }
 
 template <typename T, bool COL, class S>
 hipError_t launch_bluestein_s(const cx<T>* in, cx<T>* out, Lines li, Lines lo, int nlines, int n_in, int n_out,
                               const cx<T>* pre, const cx<T>* chat, const cx<T>* post, int batch, const cx<T>* tw,
-                              hipStream_t s, int variant, PhaseGrad<T> pg) {
+                              hipStream_t s, int variant, PhaseGrad<T> pg, const Slm<T>* slm) {
   // interleaved lines: up to 1024 threads per workgroup (for columns more
   // adjacent columns per row segment); FP64 rows: 512
   constexpr bool ILV = bluestein_interleaved<T, COL>();
@@ -830,24 +910,29 @@ hipError_t launch_bluestein_s(const cx<T>* in, cx<T>* out, Lines li, Lines lo, i
   if constexpr (!CF::fits) {
     return hipErrorInvalidValue;
   } else {
+    // the tuned column variants exist without the fused SLM stage only
     if constexpr (COL) {
       constexpr int C1 = variant_lines<S, CF::C>(1), C2 = variant_lines<S, CF::C>(2);
-      if (variant == 1)
-        return launch_bluestein_c<T, COL, S, C1>(in, out, li, lo, nlines, n_in, n_out, pre, chat, post, batch, tw, s,
-                                                 pg);
-      if (variant == 2)
-        return launch_bluestein_c<T, COL, S, C2>(in, out, li, lo, nlines, n_in, n_out, pre, chat, post, batch, tw, s,
-                                                 pg);
+      if (!(slm && slm->active())) {
+        if (variant == 1)
+          return launch_bluestein_c<T, COL, S, C1, false>(in, out, li, lo, nlines, n_in, n_out, pre, chat, post,
+                                                          batch, tw, s, pg, Slm<T>{});
+        if (variant == 2)
+          return launch_bluestein_c<T, COL, S, C2, false>(in, out, li, lo, nlines, n_in, n_out, pre, chat, post,
+                                                          batch, tw, s, pg, Slm<T>{});
+      }
     }
     constexpr int C = (ILV && !COL) ? row_lines_two_per_cu<T, S, CF::C>() : CF::C;
-    return launch_bluestein_c<T, COL, S, C>(in, out, li, lo, nlines, n_in, n_out, pre, chat, post, batch, tw, s, pg);
+    return launch_bluestein_cs<T, COL, S, C>(in, out, li, lo, nlines, n_in, n_out, pre, chat, post, batch, tw, s, pg,
+                                             slm);
   }
 }
 
 template <typename T>
 hipError_t launch_bluestein(int L, bool col, const cx<T>* in, cx<T>* out, Lines li, Lines lo, int nlines, int n_in,
                             int n_out, const cx<T>* pre, const cx<T>* chat, const cx<T>* post, int batch,
-                            const cx<T>* tw, hipStream_t s, int variant, const cx<T>* pg_u, T* pg_grad, int pg_acc) {
+                            const cx<T>* tw, hipStream_t s, int variant, const cx<T>* pg_u, T* pg_grad, int pg_acc,
+                            const Slm<T>* slm) {
   if (nlines <= 0 || batch <= 0) return hipSuccess;
   PhaseGrad<T> pg;
   pg.u = pg_u;
@@ -857,9 +942,9 @@ hipError_t launch_bluestein(int L, bool col, const cx<T>* in, cx<T>* out, Lines 
 #define LP_CASE(N, ...)                                                                                             \
   case N:                                                                                                           \
     return col ? launch_bluestein_s<T, true, SchedOf<T, Sched<__VA_ARGS__>>>(in, out, li, lo, nlines, n_in, n_out, pre, chat,   \
-                                                                 post, batch, tw, s, variant, pg)                   \
+                                                                 post, batch, tw, s, variant, pg, slm)              \
                : launch_bluestein_s<T, false, SchedOf<T, Sched<__VA_ARGS__>>>(in, out, li, lo, nlines, n_in, n_out, pre, chat, \
-                                                                  post, batch, tw, s, 0, pg);
+                                                                  post, batch, tw, s, 0, pg, slm);
     LP_LENGTHS(LP_CASE)
 #undef LP_CASE
     default:

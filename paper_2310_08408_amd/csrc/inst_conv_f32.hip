@@ -1,5 +1,5 @@
-// Convolution-type transform kernels (RS column pass, vectorial mixing,
-// Bluestein) for element type float, all supported lengths.
+// Convolution-type transform kernels (RS column pass, vectorial mixing)
+// for element type float, all supported lengths.
 #include "fft_kernels.hpp"
 
 namespace lp {
@@ -8,8 +8,5 @@ template hipError_t launch_rs_cols<float>(int, cx<float>*, int64_t, int, int, co
 template hipError_t launch_mix2_cols<float>(int, const cx<float>*, const cx<float>*, cx<float>*, int64_t, int, int,
                                          const cx<float>*, int, float, const cx<float>*, int, float, bool, int, int,
                                          const cx<float>*, hipStream_t, int);
-template hipError_t launch_bluestein<float>(int, bool, const cx<float>*, cx<float>*, Lines, Lines, int, int, int,
-                                         const cx<float>*, const cx<float>*, const cx<float>*, int, const cx<float>*,
-                                         hipStream_t, int, const cx<float>*, float*, int);
 template int col_pass_lines<float>(int, int, int);
 }  // namespace lp

@@ -32,6 +32,23 @@ constexpr int kTileShift = 2;
 constexpr int kTile = 1 << kTileShift;
 inline int64_t rs_plane_elems(int ny, int Mx) { return (int64_t)((Mx + kTile - 1) / kTile) * kTile * ny; }
 
+// SLM / thin-lens stage of a plan setup, U = V exp(i phase) lx[col] ly[row]
+// (each factor optional), fused into a transform pass instead of running as
+// a pass of its own.  Forward: the first pass multiplies each loaded input
+// by the factor.  Adjoint: the last pass stores g_V = g_U conj(factor) and,
+// with a phase gradient requested, grad (+)= Im(g_V conj V) (which equals
+// Im(g_U conj U)); V is then the PhaseGrad field u.
+template <typename T>
+struct Slm {
+  const T* phase = nullptr;   // real [batch][ny][nx], item b at b * pbs (pbs 0: shared)
+  int64_t pbs = 0;
+  const cx<T>* lx = nullptr;  // exp(-i q x_col^2) [nx] and exp(-i q y_row^2) [ny], or NULL
+  const cx<T>* ly = nullptr;
+  int nx = 0;
+  bool adjoint = false;       // Bluestein passes: stores of an adjoint (true) or loads of a forward
+  bool active() const { return phase != nullptr || lx != nullptr; }
+};
+
 // RS row passes between contiguous fields [batch][nrows][n_io] and the tiled
 // workspace (bstride w_bstride elements per batch item).  DIR = -1: forward
 // transform of length n of each zero-padded input row into the workspace;
@@ -40,10 +57,12 @@ inline int64_t rs_plane_elems(int ny, int Mx) { return (int64_t)((Mx + kTile - 1
 // With pg_grad non-NULL the inverse pass also writes the SLM phase gradient
 // pg_grad = Im(out conj pg_u) (added when pg_acc) of its output; out may
 // then be NULL.
+// slm (optional): the fused SLM stage -- applied to the loads of the forward
+// pass, to the stores of the inverse pass (see Slm).
 template <typename T, int DIR>
 hipError_t launch_rs_rows(int n, const cx<T>* in, cx<T>* out, int64_t w_bstride, int nrows, int n_io, T scale,
                           int batch, const cx<T>* tw, hipStream_t s, const cx<T>* pg_u = nullptr,
-                          T* pg_grad = nullptr, int pg_acc = 0);
+                          T* pg_grad = nullptr, int pg_acc = 0, const Slm<T>* slm = nullptr);
 
 // RS middle pass, in place on columns kx < ncols of the tiled workspace
 // (bstride elements per batch item, n_valid rows): transform of length My
@@ -65,11 +84,14 @@ hipError_t launch_mix2_cols(int My, const cx<T>* a, const cx<T>* b, cx<T>* out, 
 
 // Bluestein zoom transform of each line: out[p] = post[p] *
 // IFFT_L(FFT_L(pad(pre .* in)) .* chat)[p], p < n_out.
+// slm (optional): the fused SLM stage on the loads (the first pass of a
+// forward transform) or on the stores (the last pass of an adjoint), with
+// rows and columns of the field grid taken from the line mode.
 template <typename T>
 hipError_t launch_bluestein(int L, bool col, const cx<T>* in, cx<T>* out, Lines li, Lines lo, int nlines, int n_in,
                             int n_out, const cx<T>* pre, const cx<T>* chat, const cx<T>* post, int batch,
                             const cx<T>* tw, hipStream_t s, int variant = 0, const cx<T>* pg_u = nullptr,
-                            T* pg_grad = nullptr, int pg_acc = 0);
+                            T* pg_grad = nullptr, int pg_acc = 0, const Slm<T>* slm = nullptr);
 
 constexpr int kColVariants = 3;
 // Column-pass launch variants (the `variant` argument above): lines per

@@ -205,7 +205,7 @@ struct Ctx {
   TableCache<SpecKey, SpecEntry> specs;
   TableCache<ZoomKey, ZoomEntry> zooms;
   std::map<std::pair<int, hipStream_t>, Buf> work;
-  std::map<std::pair<int, hipStream_t>, Buf> scratch;  // complex128 table-generation scratch per stream
+  std::map<std::pair<int, hipStream_t>, Buf> gen_scratch;  // complex128 table-generation scratch per stream
   std::map<TuneKey, TuneEntry> tuned;
   std::map<int, Buf> tune_a, tune_b;  // autotuner scratch per device
   Pins* pins = nullptr;               // set while a plan warms its tables
@@ -378,7 +378,7 @@ static int get_rs_spectra(int dev, const prop_grid* g, double wl, double z, int 
     const cx<double> *twx, *twy;
     LP_RET(get_tw<double>(dev, Mx, &twx));
     LP_RET(get_tw<double>(dev, My, &twy));
-    Buf& sb = C.scratch[{dev, s}];
+    Buf& sb = C.gen_scratch[{dev, s}];
     LP_RET(ensure_buf(sb, (size_t)Mx * My * sizeof(cx<double>), s));
     LP_RET(ready_wait(e.ready, s));
     cx<double>* full = (cx<double>*)sb.p;
@@ -500,7 +500,7 @@ static int get_zoom(int dev, const ZoomSpec& zs, hipStream_t s, const cx<T>** pr
     ZoomEntry e;
     const cx<double>* twL;
     LP_RET(get_tw<double>(dev, zs.L, &twL));
-    Buf& sb = C.scratch[{dev, s}];
+    Buf& sb = C.gen_scratch[{dev, s}];
     LP_RET(ensure_buf(sb, (size_t)zs.L * sizeof(cx<double>), s));
     cx<double>* chirp = (cx<double>*)sb.p;
     const size_t bytes = ((size_t)zs.n_in + zs.n_out + zs.L) * sizeof(cx<T>);
@@ -543,7 +543,7 @@ static size_t rs_work_bytes(prop_dtype t, const prop_grid* g, int batch) {
 template <typename T>
 static int rs_run(const void* in, void* out, const prop_grid* g, double wl, double z, int batch, hipStream_t s,
                   bool adjoint, void* work, int spec_kind = 0, const cx<T>* pg_u = nullptr, T* pg_grad = nullptr,
-                  int pg_acc = 0) {
+                  int pg_acc = 0, const Slm<T>* slm = nullptr) {
   int dev;
   LP_RET(cur_device(&dev));
   const cx<T>* q[4];
@@ -561,8 +561,11 @@ static int rs_run(const void* in, void* out, const prop_grid* g, double wl, doub
   // tiled workspace
   const double es = sizeof(cx<T>);
   const double qel = (double)Mx * (My / 2 + 1);  // half spectrum table
-  LP_TRACE("rs_rows_fwd", es * batch * ny * (double)(nx + Mx), s,
-           (launch_rs_rows<T, -1>(Mx, (const cx<T>*)in, W, plane, ny, nx, T(1), batch, twx, s)));
+  // (a plan setup's SLM stage rides on this pass's loads in the forward)
+  const double stage_bytes = (slm && slm->phase && !adjoint) ? (double)sizeof(T) * batch * ny * nx : 0.0;
+  LP_TRACE("rs_rows_fwd", es * batch * ny * (double)(nx + Mx) + stage_bytes, s,
+           (launch_rs_rows<T, -1>(Mx, (const cx<T>*)in, W, plane, ny, nx, T(1), batch, twx, s, nullptr, nullptr, 0,
+                                  adjoint ? nullptr : slm)));
   // P2: column transform, kernel-spectrum multiply, inverse, first ny rows
   int v = 0;
   LP_RET(col_variant<T>(dev, TUNE_RS_COLS, My, Mx, ny, ny, batch, (size_t)plane * batch, 0, s,
@@ -575,11 +578,14 @@ static int rs_run(const void* in, void* out, const prop_grid* g, double wl, doub
   // P3: inverse row transforms, crop to nx, scale dx dy / (Mx My)
   // inverse pass: reads the workspace rows, writes the field (and with the
   // fused phase gradient reads u, writes (and reads when accumulating) grad)
+  // (and in the adjoint on its stores)
   const double inv_bytes =
       (double)batch * ny *
-      (es * Mx + (out ? es * nx : 0.0) + (pg_grad ? (es + sizeof(T) * (pg_acc ? 2.0 : 1.0)) * nx : 0.0));
+      (es * Mx + (out ? es * nx : 0.0) + (pg_grad ? (es + sizeof(T) * (pg_acc ? 2.0 : 1.0)) * nx : 0.0) +
+       ((slm && slm->phase && adjoint) ? (double)sizeof(T) * nx : 0.0));
   LP_TRACE("rs_rows_inv", inv_bytes, s,
-           (launch_rs_rows<T, 1>(Mx, W, (cx<T>*)out, plane, ny, nx, scale, batch, twx, s, pg_u, pg_grad, pg_acc)));
+           (launch_rs_rows<T, 1>(Mx, W, (cx<T>*)out, plane, ny, nx, scale, batch, twx, s, pg_u, pg_grad, pg_acc,
+                                 adjoint ? slm : nullptr)));
   return PROP_OK;
 }
 
@@ -696,7 +702,13 @@ static double first_y(const prop_grid* g) { return g->cy - (double)(g->ny / 2) *
 template <typename T>
 static int zoom2d_run(int dev, const cx<T>* in, cx<T>* out, int nxi, int nyi, int nxo, int nyo, const ZoomSpec& zx,
                       const ZoomSpec& zy, int batch, cx<T>* tmp, hipStream_t s, bool cols_first,
-                      const cx<T>* pg_u = nullptr, T* pg_grad = nullptr, int pg_acc = 0) {
+                      const cx<T>* pg_u = nullptr, T* pg_grad = nullptr, int pg_acc = 0,
+                      const Slm<T>* slm = nullptr) {
+  // a plan setup's SLM stage: on the first pass's loads (forward) or the
+  // last pass's stores (adjoint)
+  const bool st_on = slm && slm->active();
+  const Slm<T>* st_first = st_on && !slm->adjoint ? slm : nullptr;
+  const Slm<T>* st_last = st_on && slm->adjoint ? slm : nullptr;
   const cx<T> *prex, *postx, *chatx, *prey, *posty, *chaty;
   LP_RET(get_zoom<T>(dev, zx, s, &prex, &postx, &chatx));
   LP_RET(get_zoom<T>(dev, zy, s, &prey, &posty, &chaty));
@@ -708,7 +720,7 @@ static int zoom2d_run(int dev, const cx<T>* in, cx<T>* out, int nxi, int nyi, in
     // rows: [nyi][nxi] -> tmp [nyi][nxo]; cols: tmp -> out [nyo][nxo]
     LP_TRACE("czt_rows", es * batch * nyi * (double)(nxi + nxo), s,
              launch_bluestein<T>(zx.L, false, in, tmp, Lines{(int64_t)nyi * nxi, nxi}, Lines{(int64_t)nyi * nxo, nxo},
-                                 nyi, nxi, nxo, prex, chatx, postx, batch, twx, s));
+                                 nyi, nxi, nxo, prex, chatx, postx, batch, twx, s, 0, nullptr, nullptr, 0, st_first));
     int v = 0;
     const Lines li{(int64_t)nyi * nxo, nxo}, lo{(int64_t)nyo * nxo, nxo};
     LP_RET(col_variant<T>(dev, TUNE_CZT_COLS, zy.L, nxo, nyi, nyo, batch, (size_t)li.bstride * batch,
@@ -723,7 +735,7 @@ static int zoom2d_run(int dev, const cx<T>* in, cx<T>* out, int nxi, int nyi, in
         (es * nyi + (out ? es * nyo : 0.0) + (pg_grad ? (es + sizeof(T) * (pg_acc ? 2.0 : 1.0)) * nyo : 0.0));
     LP_TRACE("czt_cols", last_bytes, s,
              launch_bluestein<T>(zy.L, true, tmp, out, li, lo, nxo, nyi, nyo, prey, chaty, posty, batch, twy, s, v,
-                                 pg_u, pg_grad, pg_acc));
+                                 pg_u, pg_grad, pg_acc, st_last));
   } else {
     // cols: [nyi][nxi] -> tmp [nyo][nxi]; rows: tmp -> out [nyo][nxo]
     int v = 0;
@@ -736,30 +748,35 @@ static int zoom2d_run(int dev, const cx<T>* in, cx<T>* out, int nxi, int nyi, in
                           },
                           &v));
     LP_TRACE("czt_cols", es * batch * nxi * (double)(nyi + nyo), s,
-             launch_bluestein<T>(zy.L, true, in, tmp, li, lo, nxi, nyi, nyo, prey, chaty, posty, batch, twy, s, v));
+             launch_bluestein<T>(zy.L, true, in, tmp, li, lo, nxi, nyi, nyo, prey, chaty, posty, batch, twy, s, v,
+                                 nullptr, nullptr, 0, st_first));
     const double last_bytes =
         (double)batch * nyo *
         (es * nxi + (out ? es * nxo : 0.0) + (pg_grad ? (es + sizeof(T) * (pg_acc ? 2.0 : 1.0)) * nxo : 0.0));
     LP_TRACE("czt_rows", last_bytes, s,
              launch_bluestein<T>(zx.L, false, tmp, out, Lines{(int64_t)nyo * nxi, nxi}, Lines{(int64_t)nyo * nxo, nxo},
-                                 nyo, nxi, nxo, prex, chatx, postx, batch, twx, s, 0, pg_u, pg_grad, pg_acc));
+                                 nyo, nxi, nxo, prex, chatx, postx, batch, twx, s, 0, pg_u, pg_grad, pg_acc,
+                                 st_last));
   }
   return PROP_OK;
 }
 
+// dq: an extra quadratic phase exp(i dq (x^2 + y^2)) on the input grid,
+// folded into the input-side chirp exactly (a thin lens of focal length f
+// in front of the propagation: dq = -k / 2f).
 static void czt_specs(const prop_grid* gi, const prop_grid* go, double wl, double z, bool adjoint, ZoomSpec* zx,
-                      ZoomSpec* zy) {
+                      ZoomSpec* zy, double dq = 0.0) {
   const double k = 2.0 * kPi / wl;
   const double beta = 1.0 / (wl * z);
   const double a = gi->dx * gi->dy / (wl * z);
   const double Kre = a * std::sin(k * z), Kim = -a * std::cos(k * z);  // e^{ikz} dx dy / (i lambda z)
-  const double q = k / (2.0 * z);
+  const double q = k / (2.0 * z), qi = q + dq;
   if (!adjoint) {
-    *zx = zoom_spec(-1, beta, gi->nx, first_x(gi), gi->dx, go->nx, first_x(go), go->dx, q, q, 1.0, 0.0);
-    *zy = zoom_spec(-1, beta, gi->ny, first_y(gi), gi->dy, go->ny, first_y(go), go->dy, q, q, Kre, Kim);
+    *zx = zoom_spec(-1, beta, gi->nx, first_x(gi), gi->dx, go->nx, first_x(go), go->dx, qi, q, 1.0, 0.0);
+    *zy = zoom_spec(-1, beta, gi->ny, first_y(gi), gi->dy, go->ny, first_y(go), go->dy, qi, q, Kre, Kim);
   } else {
-    *zx = zoom_spec(+1, beta, go->nx, first_x(go), go->dx, gi->nx, first_x(gi), gi->dx, -q, -q, 1.0, 0.0);
-    *zy = zoom_spec(+1, beta, go->ny, first_y(go), go->dy, gi->ny, first_y(gi), gi->dy, -q, -q, Kre, -Kim);
+    *zx = zoom_spec(+1, beta, go->nx, first_x(go), go->dx, gi->nx, first_x(gi), gi->dx, -q, -qi, 1.0, 0.0);
+    *zy = zoom_spec(+1, beta, go->ny, first_y(go), go->dy, gi->ny, first_y(gi), gi->dy, -q, -qi, Kre, -Kim);
   }
 }
 
@@ -784,18 +801,20 @@ static void rw_specs(const prop_grid* gi, const prop_grid* go, double wl, const 
 template <typename T>
 static int czt_core(int dev, const cx<T>* in, cx<T>* out, const prop_grid* gi, const prop_grid* go, double wl,
                     double z, int batch, cx<T>* tmp, hipStream_t s, bool adjoint, const cx<T>* pg_u = nullptr,
-                    T* pg_grad = nullptr, int pg_acc = 0) {
+                    T* pg_grad = nullptr, int pg_acc = 0, const Slm<T>* slm = nullptr, double dq = 0.0) {
   ZoomSpec zx, zy;
-  czt_specs(gi, go, wl, z, adjoint, &zx, &zy);
+  czt_specs(gi, go, wl, z, adjoint, &zx, &zy, dq);
   if (!adjoint) {
     const bool cols_first = (int64_t)go->ny * gi->nx < (int64_t)gi->ny * go->nx;
-    return zoom2d_run<T>(dev, in, out, gi->nx, gi->ny, go->nx, go->ny, zx, zy, batch, tmp, s, cols_first);
+    return zoom2d_run<T>(dev, in, out, gi->nx, gi->ny, go->nx, go->ny, zx, zy, batch, tmp, s, cols_first, nullptr,
+                         nullptr, 0, slm);
   }
-  // with a fused phase gradient the row pass goes last, so that the field
-  // and the gradient are read and written along contiguous rows
-  const bool cols_first = pg_grad ? true : (int64_t)gi->ny * go->nx < (int64_t)go->ny * gi->nx;
+  // with a fused phase gradient or SLM stage the row pass goes last, so that
+  // the field and the gradient are read and written along contiguous rows
+  const bool cols_first =
+      (pg_grad || (slm && slm->active())) ? true : (int64_t)gi->ny * go->nx < (int64_t)go->ny * gi->nx;
   return zoom2d_run<T>(dev, in, out, go->nx, go->ny, gi->nx, gi->ny, zx, zy, batch, tmp, s, cols_first, pg_u,
-                       pg_grad, pg_acc);
+                       pg_grad, pg_acc, slm);
 }
 
 static size_t czt_tmp_elems(const prop_grid* gi, const prop_grid* go) {
@@ -1074,10 +1093,12 @@ static void jones_derivs(double eta, double theta, double d[16]) {
 struct PlanSetup {
   prop_setup s;
   int ncomp_in = 1;
-  bool modulated = false;
-  void* umod = nullptr;  // modulated input (ncomp_in planes) kept for the adjoint
-  int branch = 0;        // capture stream in graph mode
-  double cost = 0.0;     // transform elements per execution (load balancing)
+  bool modulated = false;  // vector ops: separate input-stage pass into umod
+  bool fused = false;      // scalar ops: SLM stage fused into the first / last transform pass
+  void* umod = nullptr;    // modulated input (ncomp_in planes) kept for the adjoint
+  void* lens = nullptr;    // RS ops with lens_f: exp(-i q x^2) [nx] then exp(-i q y^2) [ny]
+  int branch = 0;          // capture stream in graph mode
+  double cost = 0.0;       // transform elements per execution (load balancing)
 };
 
 }  // namespace lp
@@ -1090,6 +1111,7 @@ struct prop_plan {
   int nbranch = 1;
   std::vector<lp::Buf> work;    // per branch
   std::vector<lp::Buf> gbuf;    // per branch: adjoint g_u planes
+  std::vector<lp::Buf> mid;     // per branch: RS -> CZT intermediate of chained setups
   std::vector<hipStream_t> br;  // capture streams (graph mode)
   hipEvent_t fork = nullptr;
   std::vector<hipEvent_t> join;
@@ -1124,21 +1146,23 @@ static void mark_ready(Pins& p) {
 
 static int ncomp_in(int op) { return (op == PROP_OP_VRS || op == PROP_OP_VCZT) ? 2 : 1; }
 static int ncomp_out(int op) { return (op == PROP_OP_VRS || op == PROP_OP_VCZT) ? 3 : 1; }
+static bool vector_op(int op) { return op == PROP_OP_VRS || op == PROP_OP_VCZT; }
+static bool czt_window(int op) { return op == PROP_OP_CZT || op == PROP_OP_VCZT || op == PROP_OP_RS_CZT; }
 
 static int validate_setup(prop_dtype t, const prop_setup& s) {
-  if (s.op < PROP_OP_RS || s.op > PROP_OP_VCZT) return PROP_ESHAPE;
+  if (s.op < PROP_OP_RS || s.op > PROP_OP_RS_CZT) return PROP_ESHAPE;
   LP_RET(check_common(t, s.batch, s.wavelength));
   if (s.batch < 1) return PROP_ESHAPE;
   LP_RET(check_grid(&s.g_in));
   const bool lensmode = s.op == PROP_OP_VCZT && s.has_lens;
-  if (s.op == PROP_OP_CZT || s.op == PROP_OP_VCZT) {
+  if (czt_window(s.op)) {
     LP_RET(check_grid(&s.win));
     LP_RET(check_czt_shapes(&s.g_in, &s.win));
-  } else if (fft_len(2 * s.g_in.nx - 1) < 0 || fft_len(2 * s.g_in.ny - 1) < 0) {
-    return PROP_ESHAPE;
   }
+  if (s.op == PROP_OP_RS || s.op == PROP_OP_VRS || s.op == PROP_OP_RS_CZT) LP_RET(check_rs_shape(&s.g_in));
   if (lensmode) LP_RET(check_lens(&s.lens));
   if (!lensmode && (!(s.z > 0) || !is_finite(s.z))) return PROP_EPARAM;
+  if (s.op == PROP_OP_RS_CZT && (!(s.z2 > 0) || !is_finite(s.z2))) return PROP_EPARAM;
   if (!is_finite(s.lens_f) || s.lens_f < 0) return PROP_EPARAM;
   for (int c = 0; c < ncomp_in(s.op); ++c)
     if (!s.in[c]) return PROP_ENULL;
@@ -1149,14 +1173,19 @@ static int validate_setup(prop_dtype t, const prop_setup& s) {
 
 // Transform elements one execution of a setup touches (all passes, both
 // directions alike): the weight of its load-balancing assignment.
+static double rs_cost(const prop_grid& g) {
+  const double Mx = fft_len(2 * g.nx - 1), My = fft_len(2 * g.ny - 1);
+  return g.ny * Mx + Mx * My + g.ny * Mx;
+}
+static double czt_cost(const prop_grid& g, const prop_grid& w) {
+  const double Lx = fft_len(g.nx + w.nx - 1), Ly = fft_len(g.ny + w.ny - 1);
+  return g.ny * Lx + w.nx * Ly;
+}
 static double setup_cost(const prop_setup& s) {
   const double b = s.batch * (double)(ncomp_in(s.op) + ncomp_out(s.op));
-  if (s.op == PROP_OP_RS || s.op == PROP_OP_VRS) {
-    const double Mx = fft_len(2 * s.g_in.nx - 1), My = fft_len(2 * s.g_in.ny - 1);
-    return b * (s.g_in.ny * Mx + Mx * My + s.g_in.ny * Mx);
-  }
-  const double Lx = fft_len(s.g_in.nx + s.win.nx - 1), Ly = fft_len(s.g_in.ny + s.win.ny - 1);
-  return b * (s.g_in.ny * Lx + s.win.nx * Ly);
+  if (s.op == PROP_OP_RS || s.op == PROP_OP_VRS) return b * rs_cost(s.g_in);
+  if (s.op == PROP_OP_RS_CZT) return b * (rs_cost(s.g_in) + czt_cost(s.g_in, s.win));
+  return b * czt_cost(s.g_in, s.win);
 }
 
 static size_t setup_work_bytes(prop_dtype t, const prop_setup& s) {
@@ -1164,9 +1193,18 @@ static size_t setup_work_bytes(prop_dtype t, const prop_setup& s) {
     case PROP_OP_RS: return rs_work_bytes(t, &s.g_in, s.batch);
     case PROP_OP_VRS: return vrs_work_bytes(t, &s.g_in, s.batch);
     case PROP_OP_CZT: return czt_work_bytes(t, &s.g_in, &s.win, s.batch);
+    case PROP_OP_RS_CZT:
+      return std::max(rs_work_bytes(t, &s.g_in, s.batch), czt_work_bytes(t, &s.g_in, &s.win, s.batch));
     default: return vczt_work_bytes(t, &s.g_in, &s.win, s.has_lens != 0, s.batch);
   }
 }
+
+// Quadratic input phase dq (x^2 + y^2) of a thin lens of focal length f in
+// front of a CZT (0: none); it folds exactly into the CZT input chirp.
+static double lens_dq(double wl, double f) { return f > 0 ? -(2.0 * kPi / wl) / (2.0 * f) : 0.0; }
+
+// The CZT of a setup: (grid, window, distance, lens folded in front).
+static double czt_distance(const prop_setup& s) { return s.op == PROP_OP_RS_CZT ? s.z2 : s.z; }
 
 // Fill the caches (spectra, chirps, twiddles) a setup needs, on stream s.
 template <typename T>
@@ -1176,24 +1214,39 @@ static int warm_setup(int dev, const prop_setup& s, hipStream_t st) {
   int Mx, My;
   const cx<T> *a, *b, *c;
   ZoomSpec zx, zy;
-  switch (s.op) {
-    case PROP_OP_RS:
-    case PROP_OP_VRS:
-      LP_RET(get_rs_spectra<T>(dev, &s.g_in, s.wavelength, s.z, s.op == PROP_OP_VRS ? 7 : 1, st, q, &Mx, &My));
-      LP_RET(get_tw<T>(dev, Mx, &tw));
-      LP_RET(get_tw<T>(dev, My, &tw));
-      return PROP_OK;
-    default:
-      for (int adj = 0; adj < 2; ++adj) {
-        if (s.op == PROP_OP_VCZT && s.has_lens) rw_specs(&s.g_in, &s.win, s.wavelength, &s.lens, adj, &zx, &zy);
-        else czt_specs(&s.g_in, &s.win, s.wavelength, s.z, adj, &zx, &zy);
-        LP_RET(get_zoom<T>(dev, zx, st, &a, &b, &c));
-        LP_RET(get_zoom<T>(dev, zy, st, &a, &b, &c));
-        LP_RET(get_tw<T>(dev, zx.L, &tw));
-        LP_RET(get_tw<T>(dev, zy.L, &tw));
-      }
-      return PROP_OK;
+  if (s.op == PROP_OP_RS || s.op == PROP_OP_VRS || s.op == PROP_OP_RS_CZT) {
+    LP_RET(get_rs_spectra<T>(dev, &s.g_in, s.wavelength, s.z, s.op == PROP_OP_VRS ? 7 : 1, st, q, &Mx, &My));
+    LP_RET(get_tw<T>(dev, Mx, &tw));
+    LP_RET(get_tw<T>(dev, My, &tw));
   }
+  if (!czt_window(s.op)) return PROP_OK;
+  for (int adj = 0; adj < 2; ++adj) {
+    if (s.op == PROP_OP_VCZT && s.has_lens) rw_specs(&s.g_in, &s.win, s.wavelength, &s.lens, adj, &zx, &zy);
+    else if (s.op == PROP_OP_VCZT) czt_specs(&s.g_in, &s.win, s.wavelength, s.z, adj, &zx, &zy);
+    else czt_specs(&s.g_in, &s.win, s.wavelength, czt_distance(s), adj, &zx, &zy, lens_dq(s.wavelength, s.lens_f));
+    LP_RET(get_zoom<T>(dev, zx, st, &a, &b, &c));
+    LP_RET(get_zoom<T>(dev, zy, st, &a, &b, &c));
+    LP_RET(get_tw<T>(dev, zx.L, &tw));
+    LP_RET(get_tw<T>(dev, zy.L, &tw));
+  }
+  return PROP_OK;
+}
+
+// The fused SLM stage of a scalar setup: its phase, and for RS its input
+// lens as separable factors (a CZT folds its lens into the chirp instead;
+// a chained setup's lens sits between RS and CZT and folds likewise).
+template <typename T>
+static Slm<T> setup_slm(const PlanSetup& ps, bool adjoint) {
+  Slm<T> st;
+  st.phase = (const T*)ps.s.phase;
+  st.pbs = (int64_t)ps.s.g_in.nx * ps.s.g_in.ny;
+  st.nx = ps.s.g_in.nx;
+  if (ps.lens) {
+    st.lx = (const cx<T>*)ps.lens;
+    st.ly = (const cx<T>*)ps.lens + ps.s.g_in.nx;
+  }
+  st.adjoint = adjoint;
+  return st;
 }
 
 template <typename T>
@@ -1205,6 +1258,51 @@ static int run_setup(prop_plan* p, PlanSetup& ps, bool adjoint, hipStream_t st, 
   const int nin = ps.ncomp_in, nout = ncomp_out(s.op);
   const size_t plane = (size_t)npix * s.batch;
   const T* phase = (const T*)s.phase;
+  int dev;
+  LP_RET(cur_device(&dev));
+  if (ps.fused || !vector_op(s.op)) {
+    // scalar setups: SLM stage fused into the transforms, lens folded into
+    // the CZT chirp (or separable factors in front of RS)
+    const Slm<T> sf = setup_slm<T>(ps, false), sa = setup_slm<T>(ps, true);
+    const Slm<T>* fwd = ps.fused ? &sf : nullptr;
+    const Slm<T>* adj = ps.fused ? &sa : nullptr;
+    const double dq = s.op == PROP_OP_RS ? 0.0 : lens_dq(s.wavelength, s.lens_f);
+    cx<T>* mid = (cx<T>*)p->mid[branch].p;
+    const cx<T>* v_in = (const cx<T>*)s.in[0];
+    T* gph = (T*)s.grad_phase;
+    if (!adjoint) {
+      switch (s.op) {
+        case PROP_OP_RS:
+          return rs_run<T>(v_in, s.out[0], &s.g_in, s.wavelength, s.z, s.batch, st, false, work, 0, nullptr, nullptr,
+                           0, fwd);
+        case PROP_OP_CZT:
+          return czt_core<T>(dev, v_in, (cx<T>*)s.out[0], &s.g_in, &s.win, s.wavelength, s.z, s.batch, (cx<T>*)work,
+                             st, false, nullptr, nullptr, 0, fwd, dq);
+        default:  // PROP_OP_RS_CZT
+          LP_RET(rs_run<T>(v_in, mid, &s.g_in, s.wavelength, s.z, s.batch, st, false, work, 0, nullptr, nullptr, 0,
+                           fwd));
+          return czt_core<T>(dev, mid, (cx<T>*)s.out[0], &s.g_in, &s.win, s.wavelength, s.z2, s.batch,
+                             (cx<T>*)work, st, false, nullptr, nullptr, 0, nullptr, dq);
+      }
+    }
+    // adjoint: the last pass writes g_V = g_U conj(stage) into gin and the
+    // phase gradient Im(g_U conj U) (V = the forward input, read again)
+    void* gin = s.gin[0];
+    if (!gin && !gph) return PROP_OK;
+    const cx<T>* pgu = gph ? v_in : nullptr;
+    switch (s.op) {
+      case PROP_OP_RS:
+        return rs_run<T>(s.gout[0], gin, &s.g_in, s.wavelength, s.z, s.batch, st, true, work, 0, pgu, gph, 0, adj);
+      case PROP_OP_CZT:
+        return czt_core<T>(dev, (const cx<T>*)s.gout[0], (cx<T>*)gin, &s.g_in, &s.win, s.wavelength, s.z, s.batch,
+                           (cx<T>*)work, st, true, pgu, gph, 0, adj, dq);
+      default:
+        LP_RET(czt_core<T>(dev, (const cx<T>*)s.gout[0], mid, &s.g_in, &s.win, s.wavelength, s.z2, s.batch,
+                           (cx<T>*)work, st, true, nullptr, nullptr, 0, nullptr, dq));
+        return rs_run<T>(mid, gin, &s.g_in, s.wavelength, s.z, s.batch, st, true, work, 0, pgu, gph, 0, adj);
+    }
+  }
+  // vector setups: a separate input stage pass keeps the modulated input
   if (!adjoint) {
     const void* u[2] = {s.in[0], s.in[1]};
     if (ps.modulated) {
@@ -1216,35 +1314,23 @@ static int run_setup(prop_plan* p, PlanSetup& ps, bool adjoint, hipStream_t st, 
         u[c] = dst;
       }
     }
-    switch (s.op) {
-      case PROP_OP_RS: return rs_run<T>(u[0], s.out[0], &s.g_in, s.wavelength, s.z, s.batch, st, false, work);
-      case PROP_OP_CZT:
-        return czt_run<T>(u[0], s.out[0], &s.g_in, &s.win, s.wavelength, s.z, s.batch, st, false, work);
-      case PROP_OP_VRS:
-        return vrs_run<T>(u, 2, s.out, 3, &s.g_in, s.wavelength, s.z, s.batch, st, false, work);
-      default:
-        if (s.has_lens) return rw_fwd<T>(u[0], u[1], s.out, &s.g_in, &s.win, s.wavelength, &s.lens, s.batch, st, work);
-        return vczt_free_fwd<T>(u[0], u[1], s.out[0], s.out[1], s.out[2], &s.g_in, &s.win, s.wavelength, s.z, s.batch,
-                                st, work);
-    }
+    if (s.op == PROP_OP_VRS) return vrs_run<T>(u, 2, s.out, 3, &s.g_in, s.wavelength, s.z, s.batch, st, false, work);
+    if (s.has_lens) return rw_fwd<T>(u[0], u[1], s.out, &s.g_in, &s.win, s.wavelength, &s.lens, s.batch, st, work);
+    return vczt_free_fwd<T>(u[0], u[1], s.out[0], s.out[1], s.out[2], &s.g_in, &s.win, s.wavelength, s.z, s.batch, st,
+                            work);
   }
   // adjoint: g_u lands in gin directly when there is no input stage
   void* gu[2] = {s.gin[0], s.gin[1]};
   if (ps.modulated) {
     for (int c = 0; c < nin; ++c) gu[c] = (char*)p->gbuf[branch].p + c * plane * sizeof(cx<T>);
   }
-  switch (s.op) {
-    case PROP_OP_RS: LP_RET(rs_run<T>(s.gout[0], gu[0], &s.g_in, s.wavelength, s.z, s.batch, st, true, work)); break;
-    case PROP_OP_CZT:
-      LP_RET(czt_run<T>(s.gout[0], gu[0], &s.g_in, &s.win, s.wavelength, s.z, s.batch, st, true, work));
-      break;
-    case PROP_OP_VRS:
-      LP_RET(vrs_run<T>(s.gout, 3, gu, 2, &s.g_in, s.wavelength, s.z, s.batch, st, true, work));
-      break;
-    default:
-      if (s.has_lens) LP_RET(rw_adj<T>(s.gout, gu[0], gu[1], &s.g_in, &s.win, s.wavelength, &s.lens, s.batch, st, work));
-      else LP_RET(vczt_free_adj<T>(s.gout[0], s.gout[1], s.gout[2], gu[0], gu[1], &s.g_in, &s.win, s.wavelength, s.z,
-                                  s.batch, st, work));
+  if (s.op == PROP_OP_VRS) {
+    LP_RET(vrs_run<T>(s.gout, 3, gu, 2, &s.g_in, s.wavelength, s.z, s.batch, st, true, work));
+  } else if (s.has_lens) {
+    LP_RET(rw_adj<T>(s.gout, gu[0], gu[1], &s.g_in, &s.win, s.wavelength, &s.lens, s.batch, st, work));
+  } else {
+    LP_RET(vczt_free_adj<T>(s.gout[0], s.gout[1], s.gout[2], gu[0], gu[1], &s.g_in, &s.win, s.wavelength, s.z, s.batch,
+                            st, work));
   }
   if (ps.modulated) {
     for (int c = 0; c < nin; ++c) {
@@ -1314,6 +1400,41 @@ static int plan_run(prop_plan* p, bool adjoint, hipStream_t st) {
   }
   LP_TRY(hipGraphLaunch(ex, st));
   return PROP_OK;
+}
+
+// ------------------------------------------------------- detector loss --
+static const int kSpotBlocks = 256;  // FP64 partial sums per batch item (fixed reduction order)
+
+static int spot_loss_check(prop_dtype t, const void* ex, const void* ey, const void* ez, const prop_grid* win,
+                           double wavelength, double w_fz, double* result, void* gx, void* gy, void* gz,
+                           int32_t batch) {
+  LP_RET(check_common(t, batch, wavelength));
+  LP_RET(check_grid(win));
+  if (!is_finite(w_fz)) return PROP_EPARAM;
+  if (batch == 0) return PROP_OK;
+  if (!ex || !ey || !result) return PROP_ENULL;
+  if ((gx == nullptr) != (gy == nullptr)) return PROP_ENULL;
+  const size_t b = (size_t)win->nx * win->ny * batch * esize(t);
+  if (gx) {
+    if (ez && gz) LP_RET(check_alias({{ex, b}, {ey, b}, {ez, b}}, {{gx, b}, {gy, b}, {gz, b}, {result, 64 * (size_t)batch}}));
+    else LP_RET(check_alias({{ex, b}, {ey, b}}, {{gx, b}, {gy, b}, {result, 64 * (size_t)batch}}));
+  }
+  return PROP_OK;
+}
+
+static int spot_loss_launch(prop_dtype t, const void* ex, const void* ey, const void* ez, const prop_grid* win,
+                            double wavelength, double w_fz, double* result, void* gx, void* gy, void* gz,
+                            int32_t batch, double* partial, hipStream_t s) {
+  hipError_t e = t == PROP_C64
+                     ? launch_spot_loss<float>((const cx<float>*)ex, (const cx<float>*)ey, (const cx<float>*)ez,
+                                               win->nx, win->ny, win->dx, win->dy, win->cx, win->cy, wavelength, w_fz,
+                                               result, partial, kSpotBlocks, (cx<float>*)gx, (cx<float>*)gy,
+                                               (cx<float>*)gz, batch, s)
+                     : launch_spot_loss<double>((const cx<double>*)ex, (const cx<double>*)ey, (const cx<double>*)ez,
+                                                win->nx, win->ny, win->dx, win->dy, win->cx, win->cy, wavelength,
+                                                w_fz, result, partial, kSpotBlocks, (cx<double>*)gx, (cx<double>*)gy,
+                                                (cx<double>*)gz, batch, s);
+  return e == hipSuccess ? PROP_OK : dev_err(e);
 }
 
 }  // namespace lp
@@ -1853,34 +1974,15 @@ int prop_beam_splitter_adjoint(prop_dtype t, const void* const* gc, const void* 
 int prop_spot_loss(prop_dtype t, const void* ex, const void* ey, const void* ez, const prop_grid* win,
                    double wavelength, double w_fz, double* result, void* gx, void* gy, void* gz, int32_t batch,
                    void* stream) {
-  LP_RET(check_common(t, batch, wavelength));
-  LP_RET(check_grid(win));
-  if (!is_finite(w_fz)) return PROP_EPARAM;
+  LP_RET(spot_loss_check(t, ex, ey, ez, win, wavelength, w_fz, result, gx, gy, gz, batch));
   if (batch == 0) return PROP_OK;
-  if (!ex || !ey || !result) return PROP_ENULL;
-  if ((gx == nullptr) != (gy == nullptr)) return PROP_ENULL;
-  const size_t b = (size_t)win->nx * win->ny * batch * esize(t);
-  if (gx) {
-    if (ez && gz) LP_RET(check_alias({{ex, b}, {ey, b}, {ez, b}}, {{gx, b}, {gy, b}, {gz, b}, {result, 64 * (size_t)batch}}));
-    else LP_RET(check_alias({{ex, b}, {ey, b}}, {{gx, b}, {gy, b}, {result, 64 * (size_t)batch}}));
-  }
   CtxLock lk;
   int dev;
   LP_RET(cur_device(&dev));
   const hipStream_t s = (hipStream_t)stream;
-  const int nblk = 256;
   Buf& wb = ctx().work[{dev, s}];
-  LP_RET(ensure_buf(wb, (size_t)nblk * batch * 5 * sizeof(double), s));
-  hipError_t e = t == PROP_C64
-                     ? launch_spot_loss<float>((const cx<float>*)ex, (const cx<float>*)ey, (const cx<float>*)ez,
-                                               win->nx, win->ny, win->dx, win->dy, win->cx, win->cy, wavelength, w_fz,
-                                               result, (double*)wb.p, nblk, (cx<float>*)gx, (cx<float>*)gy,
-                                               (cx<float>*)gz, batch, s)
-                     : launch_spot_loss<double>((const cx<double>*)ex, (const cx<double>*)ey, (const cx<double>*)ez,
-                                                win->nx, win->ny, win->dx, win->dy, win->cx, win->cy, wavelength,
-                                                w_fz, result, (double*)wb.p, nblk, (cx<double>*)gx, (cx<double>*)gy,
-                                                (cx<double>*)gz, batch, s);
-  return e == hipSuccess ? PROP_OK : dev_err(e);
+  LP_RET(ensure_buf(wb, (size_t)kSpotBlocks * batch * 5 * sizeof(double), s));
+  return spot_loss_launch(t, ex, ey, ez, win, wavelength, w_fz, result, gx, gy, gz, batch, (double*)wb.p, s);
 }
 
 int prop_sampling_check(const prop_grid* g, double wavelength, double z) {
@@ -1995,14 +2097,14 @@ void prop_cache_clear(void) {
   C.specs.clear_unpinned(release_spec);
   C.zooms.clear_unpinned(release_zoom);
   for (auto& kv : C.work) (void)hipFree(kv.second.p);
-  for (auto& kv : C.scratch) (void)hipFree(kv.second.p);
+  for (auto& kv : C.gen_scratch) (void)hipFree(kv.second.p);
   for (auto& kv : C.tune_a) (void)hipFree(kv.second.p);
   for (auto& kv : C.tune_b) (void)hipFree(kv.second.p);
   C.tune_a.clear();
   C.tune_b.clear();
   C.tuned.clear();
   C.work.clear();
-  C.scratch.clear();
+  C.gen_scratch.clear();
 }
 
 void prop_cache_set_limit(int64_t bytes) {
@@ -2055,7 +2157,11 @@ int prop_plan_create(prop_dtype t, const prop_setup* setups, int32_t n, uint32_t
   auto fail = [&](int r) {
     for (auto& b : p->work) (void)hipFree(b.p);
     for (auto& b : p->gbuf) (void)hipFree(b.p);
-    for (auto& s : p->setups) (void)hipFree(s.umod);
+    for (auto& b : p->mid) (void)hipFree(b.p);
+    for (auto& s : p->setups) {
+      (void)hipFree(s.umod);
+      (void)hipFree(s.lens);
+    }
     for (auto s : p->br) (void)hipStreamDestroy(s);
     if (p->fork) (void)hipEventDestroy(p->fork);
     for (auto e : p->join) (void)hipEventDestroy(e);
@@ -2067,18 +2173,55 @@ int prop_plan_create(prop_dtype t, const prop_setup* setups, int32_t n, uint32_t
   int r = cur_device(&p->dev);
   if (r < 0) return fail(r);
   p->nbranch = (flags & PROP_PLAN_GRAPH) ? std::min(4, n) : 1;
-  size_t wmax = 1, gmax = 1;
+  size_t wmax = 1, gmax = 1, mmax = 1;
   for (int i = 0; i < n; ++i) {
     PlanSetup ps;
     ps.s = setups[i];
     ps.ncomp_in = ncomp_in(ps.s.op);
-    ps.modulated = ps.s.phase != nullptr || ps.s.lens_f > 0;
+    const bool staged = ps.s.phase != nullptr || ps.s.lens_f > 0;
+    ps.modulated = staged && vector_op(ps.s.op);
+    ps.fused = staged && !vector_op(ps.s.op);
     const size_t plane = (size_t)ps.s.g_in.nx * ps.s.g_in.ny * ps.s.batch * esize(t);
     if (ps.modulated) {
       hipError_t e = hipMalloc(&ps.umod, plane * ps.ncomp_in);
-      if (e != hipSuccess) return fail(dev_err(e));
+      if (e != hipSuccess) {
+        p->setups.push_back(ps);
+        return fail(dev_err(e));
+      }
       gmax = std::max(gmax, plane * ps.ncomp_in);
     }
+    if (ps.fused && ps.s.op == PROP_OP_RS && ps.s.lens_f > 0) {
+      // separable thin-lens factors exp(-i k x^2 / 2f), exp(-i k y^2 / 2f),
+      // evaluated in long double and rounded once to the element type
+      const int nx = ps.s.g_in.nx, ny = ps.s.g_in.ny;
+      const long double qq = (2.0L * 3.141592653589793238462643383279502884L / ps.s.wavelength) / (2.0L * ps.s.lens_f);
+      std::vector<long double> re(nx + ny), im(nx + ny);
+      for (int j = 0; j < nx + ny; ++j) {
+        const long double x = j < nx ? (long double)ps.s.g_in.cx + (long double)(j - nx / 2) * ps.s.g_in.dx
+                                     : (long double)ps.s.g_in.cy + (long double)(j - nx - ny / 2) * ps.s.g_in.dy;
+        const long double ph = -qq * x * x;
+        re[j] = cosl(ph);
+        im[j] = sinl(ph);
+      }
+      const size_t lb = (size_t)(nx + ny) * esize(t);
+      std::vector<char> hb(lb);
+      for (int j = 0; j < nx + ny; ++j) {
+        if (t == PROP_C64) {
+          ((float*)hb.data())[2 * j] = (float)re[j];
+          ((float*)hb.data())[2 * j + 1] = (float)im[j];
+        } else {
+          ((double*)hb.data())[2 * j] = (double)re[j];
+          ((double*)hb.data())[2 * j + 1] = (double)im[j];
+        }
+      }
+      hipError_t e = hipMalloc(&ps.lens, lb);
+      if (e == hipSuccess) e = hipMemcpy(ps.lens, hb.data(), lb, hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        p->setups.push_back(ps);
+        return fail(dev_err(e));
+      }
+    }
+    if (ps.s.op == PROP_OP_RS_CZT) mmax = std::max(mmax, plane);
     wmax = std::max(wmax, setup_work_bytes(t, ps.s));
     ps.cost = setup_cost(ps.s);
     p->setups.push_back(ps);
@@ -2097,11 +2240,14 @@ int prop_plan_create(prop_dtype t, const prop_setup* setups, int32_t n, uint32_t
   }
   p->work.resize(p->nbranch);
   p->gbuf.resize(p->nbranch);
+  p->mid.resize(p->nbranch);
   for (int b = 0; b < p->nbranch; ++b) {
     // fault injection: the workspace allocation fails as on an exhausted device
     r = (flags & PROP_PLAN_FAULT_NOMEM) ? dev_err(hipErrorOutOfMemory) : ensure_buf(p->work[b], wmax, nullptr);
     if (r < 0) return fail(r);
     r = ensure_buf(p->gbuf[b], gmax, nullptr);
+    if (r < 0) return fail(r);
+    r = ensure_buf(p->mid[b], mmax, nullptr);
     if (r < 0) return fail(r);
   }
   // every table the setups use is computed now and pinned for the plan's
@@ -2153,7 +2299,11 @@ void prop_plan_destroy(prop_plan* plan) {
     if (plan->gexec[k]) (void)hipGraphExecDestroy(plan->gexec[k]);
   for (auto& b : plan->work) (void)hipFree(b.p);
   for (auto& b : plan->gbuf) (void)hipFree(b.p);
-  for (auto& s : plan->setups) (void)hipFree(s.umod);
+  for (auto& b : plan->mid) (void)hipFree(b.p);
+  for (auto& s : plan->setups) {
+    (void)hipFree(s.umod);
+    (void)hipFree(s.lens);
+  }
   for (auto s : plan->br) (void)hipStreamDestroy(s);
   if (plan->fork) (void)hipEventDestroy(plan->fork);
   for (auto e : plan->join) (void)hipEventDestroy(e);

@@ -2,6 +2,7 @@
 direction): every setup's results equal the single calls and the FP64 oracle
 (paper: Results, batches of candidate setups evaluated per step)."""
 import math
+import warnings
 import sys
 
 import numpy as np
@@ -75,6 +76,20 @@ def _build_plans(lp, torch, setups, win_of, graph, seed=0):
     return lp.Plan(ta, graph=graph), lp.Plan(tb, graph=graph), keep
 
 
+def _build_chain(lp, torch, keep, graph):
+    """One plan of chained setups (SLM -> RS(z) -> lens f -> CZT at z = f)
+    over the tensors of `keep` (its own outputs)."""
+    setups, outs = [], []
+    for k in keep:
+        w = k["w"]
+        y, gv, gphi = torch.empty_like(k["y"]), torch.empty_like(k["v"]), torch.empty_like(k["phi"])
+        setups.append(lp.Setup(lp.PROP_OP_RS_CZT, w["grid"], [k["v"]], [y], [k["gy"]], w["wavelength"], w["z"],
+                               window=w["window"], lens_f=w["f"], phase=k["phi"], grad_inputs=[gv],
+                               grad_phase=gphi, z2=w["f"]))
+        outs.append(dict(y=y, gv=gv, gphi=gphi))
+    return lp.Plan(setups, graph=graph), outs
+
+
 def _check_setup(lp, k, tol_single=1e-6):
     """Plan results of one setup against single library calls and the oracle."""
     w = k["w"]
@@ -101,49 +116,91 @@ def test_uneven_rs_lens_czt_plans(lp, graph):
     with warnings.catch_warnings():
         warnings.simplefilter("ignore")
         pa, pb, keep = _build_plans(lp, torch, setups, lambda w: Grid.square(40, 40 * 0.5e-6), graph)
+        pc, chain = _build_chain(lp, torch, keep, graph)
         for rep in range(2):  # replays must agree
             pa.forward(); pb.forward(); pb.adjoint(); pa.adjoint()
+            pc.forward(); pc.adjoint()
             torch.cuda.synchronize()
             worst = np.max([_check_setup(lp, k) for k in keep], axis=0)
             say(f"graph={graph} replay {rep}: {len(keep)} setups agree with single calls and the oracle; "
                 f"worst rel-L2 a/y/ga/gphi/gv = " + " ".join(f"{e:.1e}" for e in worst))
-    pa.close(); pb.close()
+            # the chained setups run the same kernels in the same order
+            for k, c in zip(keep, chain):
+                for name in ("y", "gv", "gphi"):
+                    assert torch.equal(k[name], c[name]), (name, k["w"]["index"])
+    pa.close(); pb.close(); pc.close()
 
 
-def test_uneven_96_full_size_graph(lp):
-    """The 96-setup uneven workload (N in {512..2048}, 1024^2 window) in two
-    graph-replayed plans: forward + adjoint timed over replays; one setup of
-    each size checked in full against single calls and the FP64 oracle."""
+@pytest.fixture(scope="module")
+def uneven96(lp):
+    """The 96-setup uneven workload (N in {512..2048}, 1024^2 window) as one
+    plan of chained setups -- SLM -> RS(z) -> lens f -> CZT at z = f -- with
+    one graph launch per direction; timed over replays, then every setup's
+    results copied to the host."""
     import time
     import torch
-    import warnings
     setups = _uneven(0, 96, workloads.UNEVEN_SIZES)
     say("uneven 96: sizes", {n: sum(1 for w in setups if w["grid"].nx == n) for n in workloads.UNEVEN_SIZES})
+    rng = np.random.default_rng(0)
+    keep, chain = [], []
     with warnings.catch_warnings():
         warnings.simplefilter("ignore")
         t0 = time.perf_counter()
-        pa, pb, keep = _build_plans(lp, torch, setups, lambda w: w["window"], graph=True)
+        for w in setups:
+            g, win = w["grid"], w["window"]
+            v = lp.prop_source_gaussian(g, w["w0"], w["wavelength"])
+            phi = torch.tensor(w["phase"][None], dtype=torch.float32, device="cuda")
+            gy_host = workloads.random_field(rng, (win.ny, win.nx)).astype(np.complex64)
+            keep.append(dict(w=w, v=v, phi=phi, gy=torch.from_numpy(gy_host[None]).cuda(), gy_host=gy_host,
+                             y=torch.empty((1, win.ny, win.nx), dtype=torch.complex64, device="cuda")))
+        plan, chain = _build_chain(lp, torch, keep, graph=True)
         torch.cuda.synchronize()
-        say(f"  plans built (spectra, chirps, graphs) in {time.perf_counter() - t0:.2f} s")
+        say(f"  chained plan built (spectra, chirps) in {time.perf_counter() - t0:.2f} s")
         for _ in range(2):
-            pa.forward(); pb.forward(); pb.adjoint(); pa.adjoint()
+            plan.forward(); plan.adjoint()
         torch.cuda.synchronize()
         reps = 5
         t0 = time.perf_counter()
         for _ in range(reps):
-            pa.forward(); pb.forward(); pb.adjoint(); pa.adjoint()
+            plan.forward(); plan.adjoint()
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / reps
-        say(f"  96 setups forward+adjoint: {ms:.2f} ms per replay ({96e3 / ms:.1f} setup-gradients/s)")
-        seen = set()
-        for k in keep:
-            n = k["w"]["grid"].nx
-            if n in seen:
-                continue
-            seen.add(n)
-            errs = _check_setup(lp, k)
-            say(f"  setup {k['w']['index']} N={n}: rel-L2 a/y/ga/gphi/gv = " + " ".join(f"{e:.1e}" for e in errs))
-    pa.close(); pb.close()
+        say(f"  96 setups forward+adjoint: {ms:.2f} ms per replay pair ({96e3 / ms:.1f} setup-gradients/s)")
+    h = lambda t: t.cpu().numpy()[0]
+    res = [dict(w=k["w"], gy_host=k["gy_host"], y=h(c["y"]), gv=h(c["gv"]), gphi=h(c["gphi"])) for k, c in
+           zip(keep, chain)]
+    plan.close()
+    return res
+
+
+def _oracle_chain(w, gy):
+    """FP64 oracle of one chained setup: y = CZT_f(L RS_z(V e^{i phi})) and
+    the gradients of <gy, y> with respect to V (g_v) and phi."""
+    g, wl, win = w["grid"], w["wavelength"], w["window"]
+    phi = np.asarray(w["phase"], np.float32).astype(np.float64)
+    v = oracle.gaussian_beam(g, w["w0"])
+    u = oracle.modulate(v, phi)
+    y = oracle.czt_propagate(oracle.rs_propagate(u, g, wl, w["z"]) * _lens(g, wl, w["f"], -1), g, win, wl, w["f"])
+    gu = oracle.rs_adjoint(oracle.czt_adjoint(gy, g, win, wl, w["f"]) * _lens(g, wl, w["f"], +1), g, wl, w["z"])
+    return y, gu * np.exp(-1j * phi), oracle.phase_grad(gu, u)
+
+
+@pytest.mark.parametrize("part", range(4))
+def test_uneven_96_chained_plan_vs_oracle(uneven96, part):
+    """Every one of the 96 setups of the chained plan (a quarter per test)
+    against the FP64 oracle: field on the window, input gradient and SLM
+    phase gradient."""
+    import os
+    import scipy.fft
+    worst = np.zeros(3)
+    with scipy.fft.set_workers(min(16, os.cpu_count() or 1)):
+        for r in uneven96[part * 24:(part + 1) * 24]:
+            ref = _oracle_chain(r["w"], r["gy_host"].astype(np.complex128))
+            errs = np.array([rel_l2(r[name], x) for name, x in zip(("y", "gv", "gphi"), ref)])
+            worst = np.maximum(worst, errs)
+            assert errs[0] < 1e-5 and errs[1] < 1e-5 and errs[2] < 1e-3, (r["w"]["index"], r["w"]["grid"].nx, errs)
+    say(f"uneven 96 setups {24 * part}..{24 * part + 23} vs oracle: worst rel-L2 y/g_v/g_phi = "
+        + " ".join(f"{e:.1e}" for e in worst))
 
 
 def test_vector_plan_matches_single_calls(lp):

@@ -34,3 +34,6 @@ def test_bench_prints_one_json_line_with_the_contract_fields():
     assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
     assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-12 and r["launches"] == 2 * 3
     assert max(d["errors_vs_fp64"].values()) < 1e-5
+    assert 0 < r["valu_frac"] < 1 and r["valu"]["unit"] == "TFLOP/s"
+    u = d["uneven96"]
+    assert u["ms_per_replay_pair"] > 0 and 0 < u["hbm_frac"] < 1 and u["graph_launches_per_direction"] == 1
