@@ -59,7 +59,8 @@ enum {
   PROP_EPARAM = -3,       /* bad dtype, lambda <= 0, z <= 0, pitch <= 0, NA not in (0,1), f <= 0, non-finite */
   PROP_EALIAS = -4,       /* an output overlaps an input */
   PROP_ENOMEM = -5,       /* device allocation failed */
-  PROP_EDEVICE = -6       /* a HIP call failed; prop_last_device_error() has the code */
+  PROP_EDEVICE = -6,      /* a HIP call failed; prop_last_device_error() has the code */
+  PROP_ELIMIT = -7        /* beyond the fixed scratch of an allocation-free entry point */
 };
 
 /* The two sentinels give the enum the value range of int32_t, so that an
@@ -292,7 +293,19 @@ int prop_beam_splitter_adjoint(prop_dtype t, const void* const* gc, const void* 
 int prop_spot_loss(prop_dtype t, const void* ex, const void* ey, const void* ez, const prop_grid* win,
                    double wavelength, double w_fz, double* result, void* gx, void* gy, void* gz,
                    int32_t batch, void* stream);
-
+/* Allocation-free variant of prop_spot_loss, for callers that cannot
+ * allocate device memory: code under hipGraph stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Same arguments, results and
+ * errors; it calls no hipMalloc, hipFree or allocating routine.  Its FP64
+ * partial sums live in a fixed device array of the library (2.5 MiB per
+ * GPU, kept until the process ends) instead of per-stream workspace, so
+ * batch is limited to 256 (PROP_ELIMIT above).  All calls on one GPU share
+ * that array: calls that overlap in time on one GPU (e.g. on two streams)
+ * race and must be ordered by the caller.  Results equal prop_spot_loss's
+ * bit for bit (same kernels, same reduction order). */
+int prop_spot_loss_noalloc(prop_dtype t, const void* ex, const void* ey, const void* ez, const prop_grid* win,
+                           double wavelength, double w_fz, double* result, void* gx, void* gy, void* gz,
+                           int32_t batch, void* stream);
 
 /* The paper's detector side (Methods: STED microscopy; loss function;
  * exploration of optical topologies).

@@ -583,10 +583,12 @@ def prop_beam_splitter_adjoint(gc, gd, a, b, alpha, want=(True, True), grad=True
     return ga, gb, da
 
 
-def prop_spot_loss(ex, ey, ez, window, wavelength, w_fz=0.0, seeds=True):
+def prop_spot_loss(ex, ey, ez, window, wavelength, w_fz=0.0, seeds=True, noalloc=False):
     """Returns (result[batch, 8] float64, (g_x, g_y, g_z) or None).
 
     result columns: loss, sigma^2, F_z, P, Xbar - cx, Ybar - cy, 0, 0.
+    noalloc=True calls prop_spot_loss_noalloc (no device allocation in the
+    library; batch <= 256).
     """
     lib = library()
     _field(ex, "ex")
@@ -599,11 +601,11 @@ def prop_spot_loss(ex, ey, ez, window, wavelength, w_fz=0.0, seeds=True):
     if seeds:
         gx, gy = torch.empty_like(ex), torch.empty_like(ey)
         gz = torch.empty_like(ez) if ez is not None else None
+    fn = lib.prop_spot_loss_noalloc if noalloc else lib.prop_spot_loss
     with torch.cuda.device(ex.device):
-        st = lib.prop_spot_loss(_dtype_code(ex), _ptr(ex), _ptr(ey), _ptr(ez), ctypes.byref(_lib.grid(window)),
-                                float(wavelength), float(w_fz), _ptr(res), _ptr(gx), _ptr(gy), _ptr(gz), b,
-                                _stream(ex))
-    _lib.check("prop_spot_loss", st)
+        st = fn(_dtype_code(ex), _ptr(ex), _ptr(ey), _ptr(ez), ctypes.byref(_lib.grid(window)), float(wavelength),
+                float(w_fz), _ptr(res), _ptr(gx), _ptr(gy), _ptr(gz), b, _stream(ex))
+    _lib.check("prop_spot_loss_noalloc" if noalloc else "prop_spot_loss", st)
     return res, ((gx, gy, gz) if seeds else None)
 
 

@@ -22,7 +22,7 @@ P = c_void_p
 
 PROP_C64, PROP_C128 = 0, 1
 STATUS = {0: "PROP_OK", 1: "PROP_WUNDERSAMPLED", -1: "PROP_ENULL", -2: "PROP_ESHAPE", -3: "PROP_EPARAM",
-          -4: "PROP_EALIAS", -5: "PROP_ENOMEM", -6: "PROP_EDEVICE"}
+          -4: "PROP_EALIAS", -5: "PROP_ENOMEM", -6: "PROP_EDEVICE", -7: "PROP_ELIMIT"}
 
 
 class prop_grid(ctypes.Structure):
@@ -78,6 +78,7 @@ SIGNATURES = {
     "prop_beam_splitter": (c_int32, [c_int32, P, P, P, P, c_int32, P, c_int64, c_int32, P]),
     "prop_beam_splitter_adjoint": (c_int32, [c_int32, P, P, P, P, P, P, c_int32, P, P, c_int64, c_int32, P]),
     "prop_spot_loss": (c_int32, [c_int32, P, P, P, G, c_double, c_double, P, P, P, P, c_int32, P]),
+    "prop_spot_loss_noalloc": (c_int32, [c_int32, P, P, P, G, c_double, c_double, P, P, P, P, c_int32, P]),
     "prop_sampling_check": (c_int32, [G, c_double, c_double]),
     "prop_fft_length": (c_int32, [c_int32]),
     "prop_cache_clear": (None, []),

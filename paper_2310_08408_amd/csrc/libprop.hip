@@ -1437,6 +1437,32 @@ static int spot_loss_launch(prop_dtype t, const void* ex, const void* ey, const 
   return e == hipSuccess ? PROP_OK : dev_err(e);
 }
 
+// ---------------------------------------------- allocation-free scratch --
+// Device memory of the allocation-free entry points: a file-scope array,
+// one copy per GPU, held until the process ends.  In host code its name is
+// only a stand-in; the device address comes from hipGetSymbolAddress, once
+// per device with that device current, and only that address is used.
+// Calls that overlap on one GPU share the array and race.
+static const int kNoAllocMaxBatch = 256;
+static __device__ __align__(256) double scratch[(size_t)kNoAllocMaxBatch * kSpotBlocks * 5];
+
+static int noalloc_scratch(double** out) {
+  static std::mutex mu;
+  static void* addr[64] = {};
+  int dev;
+  LP_RET(cur_device(&dev));
+  if (dev < 0 || dev >= 64) return PROP_EDEVICE;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    LP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return PROP_EDEVICE;
+    addr[dev] = p;
+  }
+  *out = (double*)addr[dev];
+  return PROP_OK;
+}
+
 }  // namespace lp
 
 using namespace lp;
@@ -1985,6 +2011,20 @@ int prop_spot_loss(prop_dtype t, const void* ex, const void* ey, const void* ez,
   return spot_loss_launch(t, ex, ey, ez, win, wavelength, w_fz, result, gx, gy, gz, batch, (double*)wb.p, s);
 }
 
+int prop_spot_loss_noalloc(prop_dtype t, const void* ex, const void* ey, const void* ez, const prop_grid* win,
+                           double wavelength, double w_fz, double* result, void* gx, void* gy, void* gz,
+                           int32_t batch, void* stream) {
+  LP_RET(spot_loss_check(t, ex, ey, ez, win, wavelength, w_fz, result, gx, gy, gz, batch));
+  if (batch > kNoAllocMaxBatch) return PROP_ELIMIT;
+  if (batch == 0) return PROP_OK;
+  double* partial = nullptr;
+  LP_RET(noalloc_scratch(&partial));
+  // every partial the final reduction reads is written first by this call:
+  // nothing in the shared array needs clearing
+  return spot_loss_launch(t, ex, ey, ez, win, wavelength, w_fz, result, gx, gy, gz, batch, partial,
+                          (hipStream_t)stream);
+}
+
 int prop_sampling_check(const prop_grid* g, double wavelength, double z) {
   LP_RET(check_grid(g));
   if (!(wavelength > 0) || !is_finite(wavelength) || !(z > 0) || !is_finite(z)) return PROP_EPARAM;
@@ -2138,6 +2178,7 @@ const char* prop_status_string(int status) {
     case PROP_EALIAS: return "error: output overlaps an input";
     case PROP_ENOMEM: return "error: device allocation failed";
     case PROP_EDEVICE: return "error: HIP call failed (see prop_last_device_error)";
+    case PROP_ELIMIT: return "error: request exceeds the fixed scratch of an allocation-free entry point";
     default: return "unknown status";
   }
 }
