@@ -365,16 +365,37 @@ int prop_sampling_check(const prop_grid* g, double wavelength, double z);
  * lengths: powers of two 1..8192 and 3 * 2^k for 96 <= 3 * 2^k <= 6144. */
 int32_t prop_fft_length(int32_t n);
 /* Autotuner.  The column passes (RS column convolution, vectorial mixing,
- * Bluestein columns) have launch variants that differ only in lines per
- * workgroup and give bit-identical results.  With LIBPROP_AUTOTUNE=1 in the
- * environment (or during the first execution of a PROP_PLAN_AUTOTUNE plan)
- * the first launch of each new shape times every variant on scratch buffers
- * (allocating them and synchronising the stream) and keeps the fastest;
- * otherwise, and under stream capture, the built-in variant is used.
- * prop_autotune_report writes one text line per tuned shape (chosen variant
- * and the measured ms of each) into buf (cap bytes, NUL-terminated) and
- * returns the size needed including the NUL. */
+ * Bluestein columns) and the Bluestein row passes have launch variants:
+ * lines per workgroup on the built-in radix schedule (bit-identical
+ * results) and, for complex64 transforms of length 768, 1024, 1536 and 3072,
+ * the same on an alternative schedule whose first and last radices are
+ * equal (8x12x8, 8x16x8, 16x6x16, 16x12x16; the product of a convolution
+ * then stays in registers) -- different rounding, so a tuned choice is kept
+ * for the shape (and by a plan for its lifetime) and recorded.  With
+ * LIBPROP_AUTOTUNE=1 in the environment (or during the first execution of a
+ * PROP_PLAN_AUTOTUNE plan) the first launch of each new shape takes its
+ * choice from the tuning cache file when that holds a valid record for this
+ * GPU architecture and shape, and otherwise times every candidate on
+ * scratch buffers (allocating them and synchronising the stream), keeps the
+ * fastest and appends it to the file; without tuning, and under stream
+ * capture, the built-in variant is used and the file is not read.
+ * prop_autotune_report writes one text line per tuned shape (chosen
+ * variant, schedule, lines per workgroup, whether timed or read from the
+ * file, and the measured ms of each candidate) into buf (cap bytes,
+ * NUL-terminated) and returns the size needed including the NUL. */
 int32_t prop_autotune_report(char* buf, int32_t cap);
+/* Tuning cache file: one text line per shape, "libprop-tune 1 <arch>
+ * <element bytes> <pass kind> <n> <lines> <n_in> <n_out> <batch> <variant>".
+ * Its path is `path`, or with path NULL LIBPROP_TUNE_CACHE, else
+ * $XDG_CACHE_HOME/libprop/tune.txt or $HOME/.cache/libprop/tune.txt ("":
+ * none).  A missing or unreadable file reads as empty; a malformed line, or
+ * one whose variant is not a candidate of its shape, is skipped (those
+ * shapes are timed anew); the last line of a shape wins.  prop_tune_cache_path
+ * sets the path, reads the file and returns the number of usable records;
+ * prop_tune_cache_rejected returns the number of lines skipped.  Choices
+ * already made in this process are kept. */
+int32_t prop_tune_cache_path(const char* path);
+int32_t prop_tune_cache_rejected(void);
 /* Free cached spectra, chirps, twiddles, workspaces and autotuner choices
  * (synchronises the device).  Tables pinned by live plans are kept: their
  * kernels and captured graphs address them until prop_plan_destroy. */

@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import ctypes
 import math
+import os
 
 import torch
 
@@ -25,7 +26,7 @@ __all__ = [
     "prop_softmin", "prop_adam_step", "Adam", "prop_track_best", "StopRule", "prop_sampling_check",
     "prop_fft_length", "prop_cache_clear", "prop_trace_enable", "prop_trace_read", "prop_trace_only", "prop_autotune_report",
     "PropError", "PropWarning", "library", "Plan", "Setup", "PROP_OP_RS", "PROP_OP_CZT", "PROP_OP_VRS",
-    "PROP_OP_VCZT", "PROP_OP_RS_CZT", "PROP_PLAN_GRAPH", "PROP_PLAN_AUTOTUNE", "PROP_PLAN_FAULT_NOMEM", "prop_cache_set_limit",
+    "PROP_OP_VCZT", "PROP_OP_RS_CZT", "PROP_PLAN_GRAPH", "prop_tune_cache_path", "prop_tune_cache_rejected", "PROP_PLAN_AUTOTUNE", "PROP_PLAN_FAULT_NOMEM", "prop_cache_set_limit",
     "prop_cache_info",
 ]
 
@@ -781,6 +782,17 @@ def prop_trace_read(max_entries: int = 64) -> dict:
         raise PropError("prop_trace_read", n)
     return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms), float(buf[i].bytes))
             for i in range(n)}
+
+
+def prop_tune_cache_path(path=None) -> int:
+    """Set the tuning cache file (None: the default) and read it; returns the
+    number of usable records."""
+    return int(library().prop_tune_cache_path(None if path is None else os.fsencode(path)))
+
+
+def prop_tune_cache_rejected() -> int:
+    """Lines of the tuning cache file skipped as malformed or unusable."""
+    return int(library().prop_tune_cache_rejected())
 
 
 def prop_autotune_report() -> str:

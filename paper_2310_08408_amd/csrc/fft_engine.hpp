@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
 #include <utility>
 
 #include "lengths.hpp"
@@ -255,6 +256,18 @@ template <typename T, class S> struct SchedFor { using type = S; };
 template <> struct SchedFor<double, Sched<16, 8, 16>> { using type = Sched<16, 16, 8>; };
 template <typename T, class S> using SchedOf = typename SchedFor<T, S>::type;
 
+// The alternative schedule of length N (LP_ALT_LENGTHS), or void.
+template <int N> struct AltSched { using type = void; };
+#define LP_ALT_DEF(N, ...) \
+  template <> struct AltSched<N> { using type = Sched<__VA_ARGS__>; };
+LP_ALT_LENGTHS(LP_ALT_DEF)
+#undef LP_ALT_DEF
+// Element type T may run the alternative schedule of length N.
+template <typename T, int N>
+constexpr bool has_alt() {
+  return sizeof(T) == 4 && !std::is_void<typename AltSched<N>::type>::value;
+}
+
 // Inputs of the first stage of a half-input transform: thread j < n/R0
 // reads elements j + r n/R0 for r < R0/2, which cover [0, n/2) once each.
 // Persistent passes prefetch exactly these elements.
@@ -450,8 +463,22 @@ inline void sched_fill(SchedInfo* out) {
   for (int i = 0; i < S::nst; ++i) out->rad[i] = S::rad[i];
 }
 
-// fp64: the schedule FP64 transforms run (SchedOf<double, ...>)
-inline bool sched_info(int n, SchedInfo* out, bool fp64 = false) {
+// fp64: the schedule FP64 transforms run (SchedOf<double, ...>); alt: the
+// alternative schedule (FP32 only; false if the length has none)
+inline bool sched_info(int n, SchedInfo* out, bool fp64 = false, bool alt = false) {
+  if (alt) {
+    if (fp64) return false;
+    switch (n) {
+#define LP_ALT_CASE(N, ...)                    \
+  case N:                                      \
+    sched_fill<Sched<__VA_ARGS__>>(out);       \
+    return true;
+      LP_ALT_LENGTHS(LP_ALT_CASE)
+#undef LP_ALT_CASE
+      default:
+        return false;
+    }
+  }
   switch (n) {
 #define LP_SCHED_CASE(N, ...)                                                             \
   case N: {                                                                               \

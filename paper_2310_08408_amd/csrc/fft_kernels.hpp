@@ -677,9 +677,16 @@ hipError_t launch_rs_cols(int My, cx<T>* W, int64_t bstride, int ncols, int n_va
                           bool conj_spec, int batch, const cx<T>* tw, hipStream_t s, int variant) {
   if (batch <= 0 || ncols <= 0) return hipSuccess;
   switch (My) {
-#define LP_CASE(N, ...) \
-  case N:                                                                                                  \
-    return launch_rs_cols_s<T, SchedOf<T, Sched<__VA_ARGS__>>>(W, bstride, ncols, n_valid, Sq, Mx, conj_spec, batch, tw, s, variant);
+#define LP_CASE(N, ...)                                                                                        \
+  case N: {                                                                                                    \
+    if constexpr (has_alt<T, N>()) {                                                                           \
+      if (variant >= kColVariants)                                                                             \
+        return launch_rs_cols_s<T, typename AltSched<N>::type>(W, bstride, ncols, n_valid, Sq, Mx, conj_spec,  \
+                                                               batch, tw, s, variant % kColVariants);          \
+    }                                                                                                          \
+    return launch_rs_cols_s<T, SchedOf<T, Sched<__VA_ARGS__>>>(W, bstride, ncols, n_valid, Sq, Mx, conj_spec,  \
+                                                               batch, tw, s, variant % kColVariants);          \
+  }
     LP_LENGTHS(LP_CASE)
 #undef LP_CASE
     default:
@@ -940,11 +947,22 @@ hipError_t launch_bluestein(int L, bool col, const cx<T>* in, cx<T>* out, Lines 
   pg.acc = pg_acc;
   switch (L) {
 #define LP_CASE(N, ...)                                                                                             \
-  case N:                                                                                                           \
-    return col ? launch_bluestein_s<T, true, SchedOf<T, Sched<__VA_ARGS__>>>(in, out, li, lo, nlines, n_in, n_out, pre, chat,   \
-                                                                 post, batch, tw, s, variant, pg, slm)              \
-               : launch_bluestein_s<T, false, SchedOf<T, Sched<__VA_ARGS__>>>(in, out, li, lo, nlines, n_in, n_out, pre, chat, \
-                                                                  post, batch, tw, s, 0, pg, slm);
+  case N: {                                                                                                         \
+    if constexpr (has_alt<T, N>()) {                                                                                \
+      using A = typename AltSched<N>::type;                                                                         \
+      if (variant >= kColVariants)                                                                                  \
+        return col ? launch_bluestein_s<T, true, A>(in, out, li, lo, nlines, n_in, n_out, pre, chat, post, batch,  \
+                                                    tw, s, variant % kColVariants, pg, slm)                         \
+                   : launch_bluestein_s<T, false, A>(in, out, li, lo, nlines, n_in, n_out, pre, chat, post, batch, \
+                                                     tw, s, 0, pg, slm);                                            \
+    }                                                                                                               \
+    return col ? launch_bluestein_s<T, true, SchedOf<T, Sched<__VA_ARGS__>>>(in, out, li, lo, nlines, n_in, n_out,  \
+                                                                           pre, chat, post, batch, tw, s,           \
+                                                                           variant % kColVariants, pg, slm)         \
+               : launch_bluestein_s<T, false, SchedOf<T, Sched<__VA_ARGS__>>>(in, out, li, lo, nlines, n_in, n_out, \
+                                                                            pre, chat, post, batch, tw, s, 0, pg,   \
+                                                                            slm);                                   \
+  }
     LP_LENGTHS(LP_CASE)
 #undef LP_CASE
     default:
@@ -952,19 +970,38 @@ hipError_t launch_bluestein(int L, bool col, const cx<T>* in, cx<T>* out, Lines 
   }
 }
 
-// Lines per workgroup of a column-pass variant (kind 0: RS column pass,
-// 1: vectorial mixing, 2: Bluestein columns) at length n; 0 if unsupported.
+// Lines per workgroup of a tuner candidate (kind 0: RS column pass, 1:
+// vectorial mixing, 2: Bluestein columns, 3: Bluestein rows) at length n,
+// 0 if unsupported.  Candidates v < kColVariants run the built-in schedule
+// with C >> v lines (rows: v = 0 only); v + kColVariants the same on the
+// length's alternative schedule (RS columns and Bluestein passes, FP32).
+template <typename T, class S>
+int candidate_lines(int kind, int v) {
+  constexpr int c0 = Cfg<T, S, true>::C, c1 = Cfg<T, S, true, 2, 512>::C, c2 = Cfg<T, S, true, 1, 1024>::C;
+  if (kind == 3) {
+    if (v != 0) return 0;
+    constexpr bool ILV = bluestein_interleaved<T, false>();
+    using CF = Cfg<T, S, ILV, 1, (ILV ? 1024 : 512)>;
+    return (ILV ? row_lines_two_per_cu<T, S, CF::C>() : CF::C);
+  }
+  const int c = kind == 0 ? c0 : (kind == 1 ? c1 : c2);
+  return S::n >= kTuneMinLength ? cmax(1, c >> v) : c;
+}
+
 template <typename T>
 int col_pass_lines(int kind, int n, int variant) {
-  if (variant < 0 || variant >= kColVariants) return 0;
+  if (variant < 0 || variant >= kColVariants * kSchedVariants || kind < 0 || kind > 3) return 0;
+  const int v = variant % kColVariants;
+  const bool alt = variant >= kColVariants;
+  if (alt && kind == 1) return 0;  // vectorial mixing: built-in schedule only
   switch (n) {
 #define LP_CASE(N, ...)                                                                             \
   case N: {                                                                                         \
-    using S = SchedOf<T, Sched<__VA_ARGS__>>;                                                                   \
-    constexpr int c0 = Cfg<T, S, true>::C, c1 = Cfg<T, S, true, 2, 512>::C,                         \
-                  c2 = Cfg<T, S, true, 1, 1024>::C;                                                 \
-    const int c = kind == 0 ? c0 : (kind == 1 ? c1 : c2);                                           \
-    return S::n >= kTuneMinLength ? cmax(1, c >> variant) : c;                                      \
+    if (alt) {                                                                                      \
+      if constexpr (has_alt<T, N>()) return candidate_lines<T, typename AltSched<N>::type>(kind, v); \
+      return 0;                                                                                     \
+    }                                                                                               \
+    return candidate_lines<T, SchedOf<T, Sched<__VA_ARGS__>>>(kind, v);                             \
   }
     LP_LENGTHS(LP_CASE)
 #undef LP_CASE

@@ -94,12 +94,19 @@ hipError_t launch_bluestein(int L, bool col, const cx<T>* in, cx<T>* out, Lines 
                             T* pg_grad = nullptr, int pg_acc = 0, const Slm<T>* slm = nullptr);
 
 constexpr int kColVariants = 3;
-// Column-pass launch variants (the `variant` argument above): lines per
-// workgroup of variant v for kind 0 (RS column pass), 1 (vectorial mixing)
-// or 2 (Bluestein columns) at length n, 0 if unsupported.  All variants give
-// bit-identical results.
+constexpr int kSchedVariants = 2;
+// Launch variants of the column and Bluestein passes (the `variant`
+// argument above): variant v < kColVariants runs the built-in schedule with
+// (C >> v) lines per workgroup -- bit-identical results for every v; v +
+// kColVariants runs the length's alternative schedule (LP_ALT_LENGTHS, FP32
+// only; RS columns and Bluestein passes), whose results differ in rounding.
+// col_pass_lines gives the lines per workgroup of a candidate for kind 0
+// (RS column pass), 1 (vectorial mixing), 2 (Bluestein columns) or 3
+// (Bluestein rows) at length n, 0 if unsupported.
 template <typename T>
 int col_pass_lines(int kind, int n, int variant);
+// The schedule a variant runs: 0 built-in, 1 alternative.
+inline int variant_sched(int variant) { return variant / kColVariants; }
 
 // ---- FP64 generators (setup work) ----
 // Wrapped RS kernel on an My x Mx grid (complex128), kind 0: H, 1: (X/z) H,

@@ -11,6 +11,13 @@
   X(1024, 16, 8, 8) X(1536, 16, 12, 8) X(2048, 16, 8, 16) X(3072, 16, 16, 12)                   \
   X(4096, 16, 16, 16) X(6144, 32, 16, 12) X(8192, 32, 16, 16)
 
+// Alternative schedules the autotuner may choose for a length (FP32 only):
+// equal first and last radices, so that the convolution passes keep the
+// spectrum product in registers and the column passes can run
+// persistently.  A schedule changes rounding, so a tuned choice is fixed per
+// plan (or tuned shape) and recorded.  X(n, radices...)
+#define LP_ALT_LENGTHS(X) X(768, 8, 12, 8) X(1024, 8, 16, 8) X(1536, 16, 6, 16) X(3072, 16, 12, 16)
+
 namespace lp {
 constexpr int kMaxLen = 8192;
 }  // namespace lp

@@ -9,6 +9,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <filesystem>
+#include <fstream>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -18,6 +20,7 @@
 
 #include "libprop.h"
 #include "cache.hpp"
+#include "tune_cache.hpp"
 #include "kernels.hpp"
 #include "validate.hpp"
 
@@ -99,12 +102,13 @@ static hipEvent_t take_event() {
 // stage s >= 1 holds W_{Ns R}^{r k} (forward sign), computed in long double,
 // at off_s + k R + r (r = 0..R-1) in the per-thread layout, else at
 // off_s + (r-1) Ns + k (r = 1..R-1); both the layout and the schedule follow
-// the element type, as in the engine (tw_per_thread, SchedOf).
+// the element type, as in the engine (tw_per_thread, SchedOf); sched 1: the
+// length's alternative schedule.
 template <typename T>
-static bool make_twiddles(int n, std::vector<long double>& twr, std::vector<long double>& twi) {
+static bool make_twiddles(int n, int sched, std::vector<long double>& twr, std::vector<long double>& twi) {
   constexpr bool per_thread = tw_per_thread<T>();
   SchedInfo si;
-  if (!sched_info(n, &si, sizeof(T) == 8)) return false;
+  if (!sched_info(n, &si, sizeof(T) == 8, sched != 0)) return false;
   twr.clear();
   twi.clear();
   long ns = 1;
@@ -168,7 +172,7 @@ struct ZoomEntry {
   Ready ready;
 };
 
-using TwKey = std::tuple<int, int, int>;  // (device, element size, length)
+using TwKey = std::tuple<int, int, int, int>;  // (device, element size, length, schedule)
 using SpecKey = std::tuple<int, int, int, int, double, double, double, double, int>;
 using ZoomKey = std::tuple<int, int, int, double, double, double, double, double, double, double, double, double,
                            int, int, int>;
@@ -179,8 +183,10 @@ using ZoomKey = std::tuple<int, int, int, double, double, double, double, double
 using TuneKey = std::tuple<int, int, int, int, int, int, int, int>;
 struct TuneEntry {
   int variant = 0;
-  float ms[kColVariants] = {-1.f, -1.f, -1.f};
+  float ms[kColVariants * kSchedVariants] = {-1.f, -1.f, -1.f, -1.f, -1.f, -1.f};
+  bool from_file = false;  // read from the tuning cache file, not timed here
 };
+static_assert(kColVariants * kSchedVariants == kTuneCandidates, "tuning candidates");
 
 // Tables a plan holds pins on (released by prop_plan_destroy).
 struct Pins {
@@ -210,6 +216,11 @@ struct Ctx {
   std::map<int, Buf> tune_a, tune_b;  // autotuner scratch per device
   Pins* pins = nullptr;               // set while a plan warms its tables
   uint64_t evict_syncs = 0;           // device synchronisations of eviction rounds
+  // tuning cache file: records read (by architecture and shape), lines rejected
+  std::string tune_path;
+  bool tune_path_set = false, tune_loaded = false;
+  std::map<std::tuple<std::string, int, int, int, int, int, int, int>, int> tune_file;
+  int tune_rejected = 0;
 };
 
 static Ctx& ctx() {
@@ -325,14 +336,14 @@ static int table_alloc(Ctx& C, void** p, size_t bytes) {
 }
 
 template <typename T>
-static int get_tw(int dev, int n, const cx<T>** tw) {
+static int get_tw(int dev, int n, const cx<T>** tw, int sched = 0) {
   Ctx& C = ctx();
-  const TwKey key{dev, (int)sizeof(T), n};
+  const TwKey key{dev, (int)sizeof(T), n, sched};
   auto* slot = C.tws.find(key, C.epoch);
   if (!slot) {
     TwEntry e;
     std::vector<long double> wr, wi;
-    if (!make_twiddles<T>(n, wr, wi)) return PROP_ESHAPE;
+    if (!make_twiddles<T>(n, sched, wr, wi)) return PROP_ESHAPE;
     std::vector<cx<T>> h(wr.size());
     for (size_t i = 0; i < wr.size(); ++i) {
       h[i].x = (T)wr[i];
@@ -412,15 +423,21 @@ static int get_rs_spectra(int dev, const prop_grid* g, double wl, double z, int 
 }
 
 // ----------------------------------------------------------- autotuner --
-// The column passes have bit-exact launch variants (lines per workgroup,
-// col_pass_lines).  When tuning is on, the first launch of each new shape
-// times every distinct variant on scratch buffers of the same size (one
-// warm-up and three timed launches each, HIP events on the caller's stream)
-// and keeps the fastest; later launches of that shape reuse the choice.
-// Tuning is on with LIBPROP_AUTOTUNE=1 in the environment, or for the first
-// execution of a plan created with PROP_PLAN_AUTOTUNE; never while the
-// stream is being captured (the built-in variant 0 is used then).
-enum { TUNE_RS_COLS = 0, TUNE_MIX2 = 1, TUNE_CZT_COLS = 2 };
+// The column and Bluestein passes have launch variants (col_pass_lines):
+// lines per workgroup on the built-in schedule (bit-identical results) and,
+// for FP32 lengths with an alternative schedule, the same on that schedule
+// (different rounding).  When tuning is on, the first launch of each new
+// shape takes its choice from the tuning cache file if that holds a valid
+// record for this GPU architecture, and otherwise times every distinct
+// candidate on scratch buffers of the same size (one warm-up and three
+// timed launches each, HIP events on the caller's stream), keeps the
+// fastest and appends it to the file.  Later launches of that shape reuse
+// the choice, so a tuned plan keeps it for its lifetime.  Tuning is on with
+// LIBPROP_AUTOTUNE=1 in the environment, or for the first execution of a
+// plan created with PROP_PLAN_AUTOTUNE; never while the stream is being
+// captured (the built-in variant 0 is used then).  Untuned calls never read
+// the file.
+enum { TUNE_RS_COLS = 0, TUNE_MIX2 = 1, TUNE_CZT_COLS = 2, TUNE_CZT_ROWS = 3 };
 static thread_local bool t_tune_request = false;
 
 static bool tune_enabled() {
@@ -429,6 +446,69 @@ static bool tune_enabled() {
     return e && std::atoi(e) != 0;
   }();
   return env || t_tune_request;
+}
+
+// Tuning cache file: prop_tune_cache_path's argument, else
+// LIBPROP_TUNE_CACHE, else $XDG_CACHE_HOME/libprop/tune.txt or
+// $HOME/.cache/libprop/tune.txt ("" disables it).
+static std::string tune_file_path(Ctx& C) {
+  if (C.tune_path_set) return C.tune_path;
+  const char* e = std::getenv("LIBPROP_TUNE_CACHE");
+  if (e) return e;
+  const char* x = std::getenv("XDG_CACHE_HOME");
+  if (x && *x) return std::string(x) + "/libprop/tune.txt";
+  const char* h = std::getenv("HOME");
+  if (h && *h) return std::string(h) + "/.cache/libprop/tune.txt";
+  return "";
+}
+
+static std::string device_arch(int dev) {
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return "unknown";
+  }
+  std::string a = p.gcnArchName;
+  const size_t colon = a.find(':');
+  return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+// Valid candidate of its shape (the record's length must be a supported
+// transform length and the variant one of that length's candidates).
+static bool tune_record_usable(const TuneRecord& r) {
+  if (fft_len(r.n) != r.n) return false;
+  return (r.elem == 4 ? col_pass_lines<float>(r.kind, r.n, r.variant)
+                      : col_pass_lines<double>(r.kind, r.n, r.variant)) > 0;
+}
+
+// Read the file once (a missing or unreadable file is empty; malformed or
+// unusable lines are skipped and counted; a later line for a shape wins).
+static void tune_file_load(Ctx& C) {
+  if (C.tune_loaded) return;
+  C.tune_loaded = true;
+  const std::string path = tune_file_path(C);
+  if (path.empty()) return;
+  std::ifstream f(path);
+  std::string line;
+  while (f && std::getline(f, line)) {
+    if (line.empty() || line[0] == '#') continue;
+    TuneRecord r;
+    if (!parse_tune_record(line, &r) || !tune_record_usable(r)) {
+      ++C.tune_rejected;
+      continue;
+    }
+    C.tune_file[{r.arch, r.elem, r.kind, r.n, r.lines, r.n_in, r.n_out, r.batch}] = r.variant;
+  }
+}
+
+static void tune_file_append(Ctx& C, const TuneRecord& r) {
+  const std::string path = tune_file_path(C);
+  if (path.empty()) return;
+  std::error_code ec;
+  const std::filesystem::path dir = std::filesystem::path(path).parent_path();
+  if (!dir.empty()) std::filesystem::create_directories(dir, ec);
+  std::ofstream f(path, std::ios::app);
+  if (f) f << format_tune_record(r) << '\n';  // a cache: a failed write only costs a retune later
 }
 
 template <typename T, class Launch>
@@ -443,6 +523,25 @@ static int col_variant(int dev, int kind, int n, int nlines, int n_in, int n_out
   }
   *variant = 0;
   if (!tune_enabled() || capturing(s)) return PROP_OK;
+  TuneRecord rec;
+  rec.arch = device_arch(dev);
+  rec.elem = (int)sizeof(T);
+  rec.kind = kind;
+  rec.n = n;
+  rec.lines = nlines;
+  rec.n_in = n_in;
+  rec.n_out = n_out;
+  rec.batch = batch;
+  tune_file_load(C);
+  auto ft = C.tune_file.find({rec.arch, rec.elem, kind, n, nlines, n_in, n_out, batch});
+  if (ft != C.tune_file.end()) {
+    TuneEntry te;
+    te.variant = ft->second;
+    te.from_file = true;
+    C.tuned[key] = te;
+    *variant = te.variant;
+    return PROP_OK;
+  }
   Buf& ba = C.tune_a[dev];
   Buf& bb = C.tune_b[dev];
   LP_RET(ensure_buf(ba, std::max<size_t>(elems_a, 1) * sizeof(cx<T>), s));
@@ -458,12 +557,15 @@ static int col_variant(int dev, int kind, int n, int nlines, int n_in, int n_out
   }
   TuneEntry te;
   float best = 0.f;
-  int seen[kColVariants] = {0, 0, 0};
+  bool have = false;
+  int seen[kTuneCandidates] = {};
   er = hipSuccess;
-  for (int v = 0; v < kColVariants && er == hipSuccess; ++v) {
+  for (int v = 0; v < kTuneCandidates && er == hipSuccess; ++v) {
+    // distinct candidates only: a lines count already timed on the same
+    // schedule gives the same launch
     const int lines = col_pass_lines<T>(kind, n, v);
     bool dup = lines <= 0;
-    for (int u = 0; u < v; ++u) dup = dup || seen[u] == lines;
+    for (int u = (v / kColVariants) * kColVariants; u < v; ++u) dup = dup || seen[u] == lines;
     seen[v] = lines;
     if (dup) continue;
     er = launch(v, (cx<T>*)ba.p, (cx<T>*)bb.p);
@@ -475,9 +577,10 @@ static int col_variant(int dev, int kind, int n, int nlines, int n_in, int n_out
     if (er == hipSuccess) er = hipEventElapsedTime(&ms, e0, e1);
     if (er != hipSuccess) break;
     te.ms[v] = ms / 3.f;
-    if (v == 0 || te.ms[v] < best) {
+    if (!have || te.ms[v] < best) {
       best = te.ms[v];
       te.variant = v;
+      have = true;
     }
   }
   (void)hipEventDestroy(e0);
@@ -485,6 +588,28 @@ static int col_variant(int dev, int kind, int n, int nlines, int n_in, int n_out
   if (er != hipSuccess) return dev_err(er);
   C.tuned[key] = te;
   *variant = te.variant;
+  rec.variant = te.variant;
+  C.tune_file[{rec.arch, rec.elem, kind, n, nlines, n_in, n_out, batch}] = te.variant;
+  tune_file_append(C, rec);
+  return PROP_OK;
+}
+
+// The tuned variant of a column or Bluestein pass and the twiddle table of
+// the schedule it runs.  launch(var, tw, a, b) launches candidate var on
+// scratch buffers a, b with twiddles tw.
+template <typename T, class Launch>
+static int tuned_pass(int dev, int kind, int n, int nlines, int n_in, int n_out, int batch, size_t elems_a,
+                      size_t elems_b, hipStream_t s, Launch launch, int* variant, const cx<T>** tw) {
+  const cx<T>* twc[kSchedVariants] = {nullptr, nullptr};
+  LP_RET(get_tw<T>(dev, n, &twc[0], 0));
+  const bool alt = col_pass_lines<T>(kind, n, kColVariants) > 0;
+  if (alt && tune_enabled() && !capturing(s)) LP_RET(get_tw<T>(dev, n, &twc[1], 1));
+  LP_RET(col_variant<T>(dev, kind, n, nlines, n_in, n_out, batch, elems_a, elems_b, s,
+                        [&](int var, cx<T>* a, cx<T>* b) { return launch(var, twc[variant_sched(var)], a, b); },
+                        variant));
+  const int sc = variant_sched(*variant);
+  if (sc && !twc[sc]) LP_RET(get_tw<T>(dev, n, &twc[sc], sc));
+  *tw = twc[sc];
   return PROP_OK;
 }
 
@@ -568,13 +693,14 @@ static int rs_run(const void* in, void* out, const prop_grid* g, double wl, doub
                                   adjoint ? nullptr : slm)));
   // P2: column transform, kernel-spectrum multiply, inverse, first ny rows
   int v = 0;
-  LP_RET(col_variant<T>(dev, TUNE_RS_COLS, My, Mx, ny, ny, batch, (size_t)plane * batch, 0, s,
-                        [&](int var, cx<T>* a, cx<T>*) {
-                          return launch_rs_cols<T>(My, a, plane, Mx, ny, q[0], Mx, adjoint, batch, twy, s, var);
-                        },
-                        &v));
+  const cx<T>* twc = twy;
+  LP_RET(tuned_pass<T>(dev, TUNE_RS_COLS, My, Mx, ny, ny, batch, (size_t)plane * batch, 0, s,
+                       [&](int var, const cx<T>* tw, cx<T>* a, cx<T>*) {
+                         return launch_rs_cols<T>(My, a, plane, Mx, ny, q[0], Mx, adjoint, batch, tw, s, var);
+                       },
+                       &v, &twc));
   LP_TRACE("rs_cols", es * (2.0 * batch * ny * Mx + qel), s,
-           launch_rs_cols<T>(My, W, plane, Mx, ny, q[0], Mx, adjoint, batch, twy, s, v));
+           launch_rs_cols<T>(My, W, plane, Mx, ny, q[0], Mx, adjoint, batch, twc, s, v));
   // P3: inverse row transforms, crop to nx, scale dx dy / (Mx My)
   // inverse pass: reads the workspace rows, writes the field (and with the
   // fused phase gradient reads u, writes (and reads when accumulating) grad)
@@ -643,20 +769,21 @@ static int vrs_run(const void* const* ins, int nin, void* const* outs, int nout,
                                                      false, Mx, batch, twy, s, var);
                         },
                         &vm));
+  const cx<T>* twc = twy;
   if (!adjoint) {
-    LP_RET(col_variant<T>(dev, TUNE_RS_COLS, My, Mx, ny, ny, batch, (size_t)pst * batch, 0, s,
-                          [&](int var, cx<T>* a, cx<T>*) {
-                            return launch_rs_cols<T>(My, a, pst, Mx, ny, q[0], Mx, false, batch, twy, s, var);
-                          },
-                          &vc));
+    LP_RET(tuned_pass<T>(dev, TUNE_RS_COLS, My, Mx, ny, ny, batch, (size_t)pst * batch, 0, s,
+                         [&](int var, const cx<T>* tw, cx<T>* a, cx<T>*) {
+                           return launch_rs_cols<T>(My, a, pst, Mx, ny, q[0], Mx, false, batch, tw, s, var);
+                         },
+                         &vc, &twc));
     // E_z = -(Hx * E_x0 + Hy * E_y0) first (reads W0, W1), then E_x, E_y in place
     LP_TRACE("vrs_mix2", es * (3.0 * pl + 2.0 * qel), s,
              launch_mix2_cols<T>(My, W[0], W[1], W[2], pst, Mx, ny, q[1], 1, T(-1), q[2], 2, T(-1), false, Mx,
                                  batch, twy, s, vm));
     LP_TRACE("rs_cols", es * (2.0 * pl + qel), s,
-             launch_rs_cols<T>(My, W[0], pst, Mx, ny, q[0], Mx, false, batch, twy, s, vc));
+             launch_rs_cols<T>(My, W[0], pst, Mx, ny, q[0], Mx, false, batch, twc, s, vc));
     LP_TRACE("rs_cols", es * (2.0 * pl + qel), s,
-             launch_rs_cols<T>(My, W[1], pst, Mx, ny, q[0], Mx, false, batch, twy, s, vc));
+             launch_rs_cols<T>(My, W[1], pst, Mx, ny, q[0], Mx, false, batch, twc, s, vc));
   } else {
     // g_ex = H^H g_x - Hx^H g_z, g_ey = H^H g_y - Hy^H g_z (in place over W0, W1)
     LP_TRACE("vrs_mix2", es * (3.0 * pl + 2.0 * qel), s,
@@ -716,20 +843,34 @@ static int zoom2d_run(int dev, const cx<T>* in, cx<T>* out, int nxi, int nyi, in
   LP_RET(get_tw<T>(dev, zx.L, &twx));
   LP_RET(get_tw<T>(dev, zy.L, &twy));
   const double es = sizeof(cx<T>);
+  // tuned row pass of nrows lines, n_in -> n_out points (rows of the input
+  // or of the intermediate)
+  auto rows_variant = [&](int nrows, int rin, int rout, int* vr, const cx<T>** twr) {
+    const Lines ri{(int64_t)nrows * rin, rin}, ro{(int64_t)nrows * rout, rout};
+    return tuned_pass<T>(dev, TUNE_CZT_ROWS, zx.L, nrows, rin, rout, batch, (size_t)ri.bstride * batch,
+                         (size_t)ro.bstride * batch, s,
+                         [&](int var, const cx<T>* tw, cx<T>* a, cx<T>* b) {
+                           return launch_bluestein<T>(zx.L, false, a, b, ri, ro, nrows, rin, rout, prex, chatx, postx,
+                                                      batch, tw, s, var);
+                         },
+                         vr, twr);
+  };
   if (!cols_first) {
     // rows: [nyi][nxi] -> tmp [nyi][nxo]; cols: tmp -> out [nyo][nxo]
+    int vr = 0;
+    LP_RET(rows_variant(nyi, nxi, nxo, &vr, &twx));
     LP_TRACE("czt_rows", es * batch * nyi * (double)(nxi + nxo), s,
              launch_bluestein<T>(zx.L, false, in, tmp, Lines{(int64_t)nyi * nxi, nxi}, Lines{(int64_t)nyi * nxo, nxo},
-                                 nyi, nxi, nxo, prex, chatx, postx, batch, twx, s, 0, nullptr, nullptr, 0, st_first));
+                                 nyi, nxi, nxo, prex, chatx, postx, batch, twx, s, vr, nullptr, nullptr, 0, st_first));
     int v = 0;
     const Lines li{(int64_t)nyi * nxo, nxo}, lo{(int64_t)nyo * nxo, nxo};
-    LP_RET(col_variant<T>(dev, TUNE_CZT_COLS, zy.L, nxo, nyi, nyo, batch, (size_t)li.bstride * batch,
-                          (size_t)lo.bstride * batch, s,
-                          [&](int var, cx<T>* a, cx<T>* b) {
-                            return launch_bluestein<T>(zy.L, true, a, b, li, lo, nxo, nyi, nyo, prey, chaty, posty,
-                                                       batch, twy, s, var);
-                          },
-                          &v));
+    LP_RET(tuned_pass<T>(dev, TUNE_CZT_COLS, zy.L, nxo, nyi, nyo, batch, (size_t)li.bstride * batch,
+                         (size_t)lo.bstride * batch, s,
+                         [&](int var, const cx<T>* tw, cx<T>* a, cx<T>* b) {
+                           return launch_bluestein<T>(zy.L, true, a, b, li, lo, nxo, nyi, nyo, prey, chaty, posty,
+                                                      batch, tw, s, var);
+                         },
+                         &v, &twy));
     const double last_bytes =
         (double)batch * nxo *
         (es * nyi + (out ? es * nyo : 0.0) + (pg_grad ? (es + sizeof(T) * (pg_acc ? 2.0 : 1.0)) * nyo : 0.0));
@@ -740,22 +881,24 @@ static int zoom2d_run(int dev, const cx<T>* in, cx<T>* out, int nxi, int nyi, in
     // cols: [nyi][nxi] -> tmp [nyo][nxi]; rows: tmp -> out [nyo][nxo]
     int v = 0;
     const Lines li{(int64_t)nyi * nxi, nxi}, lo{(int64_t)nyo * nxi, nxi};
-    LP_RET(col_variant<T>(dev, TUNE_CZT_COLS, zy.L, nxi, nyi, nyo, batch, (size_t)li.bstride * batch,
-                          (size_t)lo.bstride * batch, s,
-                          [&](int var, cx<T>* a, cx<T>* b) {
-                            return launch_bluestein<T>(zy.L, true, a, b, li, lo, nxi, nyi, nyo, prey, chaty, posty,
-                                                       batch, twy, s, var);
-                          },
-                          &v));
+    LP_RET(tuned_pass<T>(dev, TUNE_CZT_COLS, zy.L, nxi, nyi, nyo, batch, (size_t)li.bstride * batch,
+                         (size_t)lo.bstride * batch, s,
+                         [&](int var, const cx<T>* tw, cx<T>* a, cx<T>* b) {
+                           return launch_bluestein<T>(zy.L, true, a, b, li, lo, nxi, nyi, nyo, prey, chaty, posty,
+                                                      batch, tw, s, var);
+                         },
+                         &v, &twy));
     LP_TRACE("czt_cols", es * batch * nxi * (double)(nyi + nyo), s,
              launch_bluestein<T>(zy.L, true, in, tmp, li, lo, nxi, nyi, nyo, prey, chaty, posty, batch, twy, s, v,
                                  nullptr, nullptr, 0, st_first));
     const double last_bytes =
         (double)batch * nyo *
         (es * nxi + (out ? es * nxo : 0.0) + (pg_grad ? (es + sizeof(T) * (pg_acc ? 2.0 : 1.0)) * nxo : 0.0));
+    int vr = 0;
+    LP_RET(rows_variant(nyo, nxi, nxo, &vr, &twx));
     LP_TRACE("czt_rows", last_bytes, s,
              launch_bluestein<T>(zx.L, false, tmp, out, Lines{(int64_t)nyo * nxi, nxi}, Lines{(int64_t)nyo * nxo, nxo},
-                                 nyo, nxi, nxo, prex, chatx, postx, batch, twx, s, 0, pg_u, pg_grad, pg_acc,
+                                 nyo, nxi, nxo, prex, chatx, postx, batch, twx, s, vr, pg_u, pg_grad, pg_acc,
                                  st_last));
   }
   return PROP_OK;
@@ -993,13 +1136,13 @@ static int rw_fwd(const void* ex, const void* ey, void* const* outs, const prop_
                                nxi, nxo, prex, chatx, postx, 3 * batch, twx, s));
   const Lines li{(int64_t)nyi * nxo, nxo}, lo{(int64_t)nyo * nxo, nxo};
   int v = 0;
-  LP_RET(col_variant<T>(dev, TUNE_CZT_COLS, zy.L, nxo, nyi, nyo, batch, (size_t)li.bstride * batch,
-                        (size_t)lo.bstride * batch, s,
-                        [&](int var, cx<T>* a, cx<T>* b) {
-                          return launch_bluestein<T>(zy.L, true, a, b, li, lo, nxo, nyi, nyo, prey, chaty, posty,
-                                                     batch, twy, s, var);
-                        },
-                        &v));
+  LP_RET(tuned_pass<T>(dev, TUNE_CZT_COLS, zy.L, nxo, nyi, nyo, batch, (size_t)li.bstride * batch,
+                       (size_t)lo.bstride * batch, s,
+                       [&](int var, const cx<T>* tw, cx<T>* a, cx<T>* b) {
+                         return launch_bluestein<T>(zy.L, true, a, b, li, lo, nxo, nyi, nyo, prey, chaty, posty,
+                                                    batch, tw, s, var);
+                       },
+                       &v, &twy));
   for (int c = 0; c < 3; ++c)
     LP_TRACE("rw_cols", es * batch * nxo * (double)(nyi + nyo), s,
              launch_bluestein<T>(zy.L, true, M + c * nm, (cx<T>*)outs[c], li, lo, nxo, nyi, nyo, prey, chaty, posty,
@@ -1028,13 +1171,13 @@ static int rw_adj(const void* const* gs, void* gex, void* gey, const prop_grid* 
   const double es = sizeof(cx<T>);
   const Lines li{(int64_t)nyo * nxo, nxo}, lo{(int64_t)nyi * nxo, nxo};
   int v = 0;
-  LP_RET(col_variant<T>(dev, TUNE_CZT_COLS, zy.L, nxo, nyo, nyi, batch, (size_t)li.bstride * batch,
-                        (size_t)lo.bstride * batch, s,
-                        [&](int var, cx<T>* a, cx<T>* b) {
-                          return launch_bluestein<T>(zy.L, true, a, b, li, lo, nxo, nyo, nyi, prey, chaty, posty,
-                                                     batch, twy, s, var);
-                        },
-                        &v));
+  LP_RET(tuned_pass<T>(dev, TUNE_CZT_COLS, zy.L, nxo, nyo, nyi, batch, (size_t)li.bstride * batch,
+                       (size_t)lo.bstride * batch, s,
+                       [&](int var, const cx<T>* tw, cx<T>* a, cx<T>* b) {
+                         return launch_bluestein<T>(zy.L, true, a, b, li, lo, nxo, nyo, nyi, prey, chaty, posty,
+                                                    batch, tw, s, var);
+                       },
+                       &v, &twy));
   for (int c = 0; c < 3; ++c)
     LP_TRACE("rw_cols", es * batch * nxo * (double)(nyi + nyo), s,
              launch_bluestein<T>(zy.L, true, (const cx<T>*)gs[c], M + c * nm, li, lo, nxo, nyo, nyi, prey, chaty,
@@ -2102,19 +2245,27 @@ int32_t prop_autotune_report(char* buf, int32_t cap) {
   CtxLock lk;
   Ctx& C = ctx();
   std::string out;
-  static const char* kinds[] = {"rs_cols", "vrs_mix2", "czt_cols"};
+  static const char* kinds[] = {"rs_cols", "vrs_mix2", "czt_cols", "czt_rows"};
   for (const auto& kv : C.tuned) {
     const TuneKey& k = kv.first;
     const TuneEntry& e = kv.second;
-    char line[256];
+    char line[320];
     const int esz = std::get<1>(k), kind = std::get<2>(k), n = std::get<3>(k);
     const int lines = esz == 4 ? col_pass_lines<float>(kind, n, e.variant) : col_pass_lines<double>(kind, n, e.variant);
+    SchedInfo si;
+    char sched[48] = "?";
+    if (sched_info(n, &si, esz == 8, variant_sched(e.variant) != 0)) {
+      int o = 0;
+      for (int st = 0; st < si.nst && o < (int)sizeof sched - 8; ++st)
+        o += std::snprintf(sched + o, sizeof sched - o, st ? "x%d" : "%d", si.rad[st]);
+    }
     int m = std::snprintf(line, sizeof line,
-                          "dev %d %s %s n=%d lines=%d in=%d out=%d batch=%d -> variant %d (%d per workgroup); ms",
+                          "dev %d %s %s n=%d lines=%d in=%d out=%d batch=%d -> variant %d (schedule %s, %d per "
+                          "workgroup; %s); ms",
                           std::get<0>(k), esz == 4 ? "c64" : "c128", kinds[kind], n, std::get<4>(k), std::get<5>(k),
-                          std::get<6>(k), std::get<7>(k), e.variant, lines);
+                          std::get<6>(k), std::get<7>(k), e.variant, sched, lines, e.from_file ? "from file" : "timed");
     out.append(line, (size_t)std::max(0, std::min<int>(m, (int)sizeof line - 1)));
-    for (int v = 0; v < kColVariants; ++v) {
+    for (int v = 0; v < kTuneCandidates; ++v) {
       m = e.ms[v] < 0 ? std::snprintf(line, sizeof line, " -") : std::snprintf(line, sizeof line, " %.4f", e.ms[v]);
       out.append(line, (size_t)std::max(0, std::min<int>(m, (int)sizeof line - 1)));
     }
@@ -2145,6 +2296,23 @@ void prop_cache_clear(void) {
   C.tuned.clear();
   C.work.clear();
   C.gen_scratch.clear();
+}
+
+int32_t prop_tune_cache_path(const char* path) {
+  CtxLock lk;
+  Ctx& C = ctx();
+  C.tune_path_set = path != nullptr;
+  C.tune_path = path ? path : "";
+  C.tune_loaded = false;
+  C.tune_file.clear();
+  C.tune_rejected = 0;
+  tune_file_load(C);
+  return (int32_t)C.tune_file.size();
+}
+
+int32_t prop_tune_cache_rejected(void) {
+  CtxLock lk;
+  return ctx().tune_rejected;
 }
 
 void prop_cache_set_limit(int64_t bytes) {

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "cache.hpp"
+#include "tune_cache.hpp"
 #include "validate.hpp"
 
 static int failures = 0;
@@ -182,7 +183,61 @@ static void test_validation() {
   CHECK(lp::sampling(&fine, 650e-9, 1e-6) == PROP_OK);
 }
 
+// Tuning-cache records: round trip, and every corruption is rejected
+// (never a crash, never a half-filled record).
+static void test_tune_records() {
+  lp::TuneRecord r;
+  r.arch = "gfx950";
+  r.elem = 4;
+  r.kind = 2;
+  r.n = 3072;
+  r.lines = 2048;
+  r.n_in = 2048;
+  r.n_out = 1024;
+  r.batch = 8;
+  r.variant = 3;
+  const std::string line = lp::format_tune_record(r);
+  lp::TuneRecord q;
+  CHECK(lp::parse_tune_record(line, &q));
+  CHECK(q.arch == r.arch && q.elem == 4 && q.kind == 2 && q.n == 3072 && q.lines == 2048 && q.n_in == 2048 &&
+        q.n_out == 1024 && q.batch == 8 && q.variant == 3);
+  const char* bad[] = {
+      "", "libprop-tune", "libprop-tune 2 gfx950 4 2 3072 2048 2048 1024 8 3",
+      "libprop-tune 1 gfx950 4 2 3072 2048 2048 1024 8 3 extra", "libprop-tune 1 gfx950 4 2 3072 2048 2048 1024 8",
+      "libprop-tune 1 gfx950 5 2 3072 2048 2048 1024 8 3", "libprop-tune 1 gfx950 4 9 3072 2048 2048 1024 8 3",
+      "libprop-tune 1 gfx950 4 2 9000 2048 2048 1024 8 3", "libprop-tune 1 gfx950 4 2 3072 0 2048 1024 8 3",
+      "libprop-tune 1 gfx950 4 2 3072 2048 4000 1024 8 3", "libprop-tune 1 gfx950 4 2 3072 2048 2048 1024 -1 3",
+      "libprop-tune 1 gfx950 4 2 3072 2048 2048 1024 8 6", "libprop-tune 1 gfx950 4 2 3072 2048 2048 1024 8 -1",
+      "libprop-tune 1 gfx9$0 4 2 3072 2048 2048 1024 8 3", "libprop-tune 1 gfx950 4 2 3072 2048 2048 1024 8 x",
+      "libprop-tune 1 gfx950 4 2 99999999999999999999 2048 2048 1024 8 3", "other-tag 1 gfx950 4 2 3072 2048 2048 1024 8 3",
+  };
+  for (const char* b : bad) {
+    lp::TuneRecord z;
+    z.variant = -7;
+    if (lp::parse_tune_record(b, &z)) {
+      std::fprintf(stderr, "accepted a corrupt tuning record: '%s'\n", b);
+      ++failures;
+    }
+    CHECK(z.variant == -7);
+  }
+  // random bytes and truncations of a good line never crash the parser
+  unsigned x = 12345u;
+  for (int t = 0; t < 20000; ++t) {
+    std::string g;
+    const int len = (int)(x % 96);
+    for (int k = 0; k < len; ++k) {
+      x = x * 1103515245u + 12345u;
+      g.push_back((char)(x >> 16));
+    }
+    x = x * 1103515245u + 12345u;
+    lp::TuneRecord z;
+    (void)lp::parse_tune_record(g, &z);
+    (void)lp::parse_tune_record(line.substr(0, x % (line.size() + 1)), &z);
+  }
+}
+
 int main() {
+  test_tune_records();
   test_lru_pins();
   test_budget_loop();
   test_validation();

@@ -1,6 +1,7 @@
 // Host enumeration of the transform engine's index rules, compiled from the
 // library's own headers (hipcc, host pass only) by tests/test_engine_bounds.py.
-// For every supported length and element type it checks, using the same
+// For every supported length and element type (and every alternative FP32
+// schedule of the autotuner) it checks, using the same
 // constexpr schedules, helpers and launch configurations the kernels use:
 //  * half-input prefetch (persistent row and column passes) and half-output
 //    early loads (phase-gradient epilogue): every index in [0, n/2), each
@@ -134,6 +135,10 @@ int main() {
   check_len<double, SchedOf<double, Sched<__VA_ARGS__>>>();
   LP_LENGTHS(LP_CHECK)
 #undef LP_CHECK
+  // the alternative schedules the autotuner may choose (FP32)
+#define LP_CHECK_ALT(N, ...) check_len<float, Sched<__VA_ARGS__>>();
+  LP_ALT_LENGTHS(LP_CHECK_ALT)
+#undef LP_CHECK_ALT
   check_split();
   if (failures) {
     std::fprintf(stderr, "%d index check(s) failed\n", failures);

@@ -252,39 +252,121 @@ def test_plan_rejects_bad_setups(lp):
         lp.Plan([bad])
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_autotuned_plan_is_bit_identical(lp, graph):
-    """PROP_PLAN_AUTOTUNE times the lines-per-workgroup variants of the column
-    passes on scratch buffers at the first execution; every variant computes
-    the same numbers, so results equal those of an untuned plan bit for bit,
-    on the tuning execution and on later (graph) replays."""
-    import torch
-    import warnings
+def _tune_plans(lp, torch, autotune, graph, seed=11):
     g = Grid.square(512, 4e-3)
     win = Grid.square(512, 40e-6)
-    rng = np.random.default_rng(11)
+    rng = np.random.default_rng(seed)
+    v = torch.from_numpy(workloads.random_field(rng, (2, 512, 512)).astype(np.complex64)).cuda()
+    y_rs, y_czt = torch.empty_like(v), torch.empty_like(v)
+    g_rs, g_czt = torch.empty_like(v), torch.empty_like(v)
+    s1 = lp.Setup(lp.PROP_OP_RS, g, [v], [y_rs], [y_rs], 600e-9, 30e-3, grad_inputs=[g_rs])
+    s2 = lp.Setup(lp.PROP_OP_CZT, g, [v], [y_czt], [y_czt], 600e-9, 40e-3, window=win, grad_inputs=[g_czt])
+    return lp.Plan([s1, s2], graph=graph, autotune=autotune), (v, y_rs, y_czt, g_rs, g_czt), (g, win)
 
-    def make(autotune):
-        v = torch.from_numpy(workloads.random_field(rng, (2, 512, 512)).astype(np.complex64)).cuda()
-        y_rs, y_czt = torch.empty_like(v), torch.empty_like(v)
-        g_rs, g_czt = torch.empty_like(v), torch.empty_like(v)
-        s1 = lp.Setup(lp.PROP_OP_RS, g, [v], [y_rs], [y_rs], 600e-9, 30e-3, grad_inputs=[g_rs])
-        s2 = lp.Setup(lp.PROP_OP_CZT, g, [v], [y_czt], [y_czt], 600e-9, 40e-3, window=win, grad_inputs=[g_czt])
-        return lp.Plan([s1, s2], graph=graph, autotune=autotune), (v, y_rs, y_czt, g_rs, g_czt)
 
-    rng = np.random.default_rng(11)
-    p0, t0 = make(False)
-    rng = np.random.default_rng(11)
-    p1, t1 = make(True)
+@pytest.mark.parametrize("graph", [False, True])
+def test_autotuned_plan(lp, graph, tmp_path):
+    """PROP_PLAN_AUTOTUNE times the lines-per-workgroup variants and the
+    alternative radix schedules of the column and Bluestein passes at the
+    first execution and records each choice (here in a fresh tuning cache
+    file).  Every replay of the tuned plan is bit-identical to its first
+    execution; against the untuned plan and the FP64 oracle the results
+    agree to FP32 rounding (a different schedule rounds differently)."""
+    import torch
+    lp.prop_cache_clear()
+    cache = tmp_path / "tune.txt"
+    assert lp.prop_tune_cache_path(str(cache)) == 0
+    p0, t0, (g, win) = _tune_plans(lp, torch, False, graph)
+    p1, t1, _ = _tune_plans(lp, torch, True, graph)
     assert torch.equal(t0[0], t1[0])
     with warnings.catch_warnings():
         warnings.simplefilter("ignore")
-        for rep in range(2):
+        first = None
+        for rep in range(3):
             p0.forward(); p0.adjoint(); p1.forward(); p1.adjoint()
             torch.cuda.synchronize()
+            got = [t.cpu().numpy() for t in t1[1:]]
+            if first is None:
+                first = got
+            for a, b in zip(first, got):
+                assert np.array_equal(a, b), f"replay {rep}"
             for a, b in zip(t0[1:], t1[1:]):
-                assert torch.equal(a, b), f"replay {rep}"
+                assert rel_l2(b.cpu().numpy(), a.cpu().numpy()) < 1e-5
     report = lp.prop_autotune_report()
     say(report)
-    assert "rs_cols n=1024" in report and "czt_cols n=1024" in report
+    for kind in ("rs_cols n=1024", "czt_cols n=1024", "czt_rows n=1024"):
+        assert kind in report
+    assert "timed" in report and "from file" not in report
+    recs = [l for l in cache.read_text().splitlines() if l.startswith("libprop-tune 1 ")]
+    assert len(recs) >= 3, recs   # RS columns, Bluestein rows and columns (shared by both directions)
+    v = t0[0].cpu().numpy().astype(np.complex128)
+    ref_rs = oracle.rs_propagate(v, g, 600e-9, 30e-3)
+    assert rel_l2(t1[1].cpu().numpy(), ref_rs) < 1e-5
     p0.close(); p1.close()
+    lp.prop_tune_cache_path(None)
+
+
+def test_tuning_cache_file_is_read_and_corruption_ignored(lp, tmp_path):
+    """A record in the tuning cache file fixes a shape's choice (here the
+    alternative 8x16x8 schedule of the 1024-point RS column pass) without
+    timing; malformed lines, unknown versions, variants that are not
+    candidates of their shape and other architectures are skipped, and those
+    shapes are timed anew.  Results stay within FP32 rounding of the
+    oracle."""
+    import torch
+    lp.prop_cache_clear()
+    # the shapes of the plan: learn them (and the architecture) from a tuning run
+    probe = tmp_path / "probe.txt"
+    lp.prop_tune_cache_path(str(probe))
+    p, t, (g, win) = _tune_plans(lp, torch, True, False, seed=3)
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        p.forward(); p.adjoint()
+    torch.cuda.synchronize()
+    p.close()
+    recs = [l.split() for l in probe.read_text().splitlines() if l.startswith("libprop-tune")]
+    rs = [r for r in recs if r[4] == "0" and r[5] == "1024"]
+    assert rs, recs
+    arch = rs[0][2]
+    forced = rs[0][:10] + ["3"]                          # RS columns at 1024 on the alternative schedule
+    bad_variant = rs[0][:10] + ["5"]                     # lines variant 2 of a 1024-point alt: valid only if it exists
+    good = tmp_path / "good.txt"
+    good.write_text("# tuning cache\n" + " ".join(forced) + "\n")
+    lp.prop_cache_clear()
+    assert lp.prop_tune_cache_path(str(good)) == 1 and lp.prop_tune_cache_rejected() == 0
+    p, t, _ = _tune_plans(lp, torch, True, False, seed=3)
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        p.forward(); p.adjoint()
+    torch.cuda.synchronize()
+    report = lp.prop_autotune_report()
+    say(report)
+    line = [l for l in report.splitlines() if "rs_cols n=1024" in l][0]
+    assert "variant 3" in line and "8x16x8" in line and "from file" in line
+    v = t[0].cpu().numpy().astype(np.complex128)
+    assert rel_l2(t[1].cpu().numpy(), oracle.rs_propagate(v, g, 600e-9, 30e-3)) < 1e-5
+    p.close()
+    corrupt = tmp_path / "corrupt.txt"
+    corrupt.write_text("\n".join([
+        "libprop-tune 1",                                               # truncated
+        "libprop-tune 2 " + " ".join(forced[2:]),                       # unknown version
+        " ".join(rs[0][:10] + ["9"]),                                   # variant out of range
+        " ".join(rs[0][:5] + ["4096"] + rs[0][6:10] + ["3"]),           # 4096 has no alternative schedule
+        "\x00\x01 garbage \xff",
+        " ".join(["libprop-tune", "1", "gfx000"] + forced[3:]),         # another architecture: not used here
+    ]) + "\n", errors="surrogateescape")
+    lp.prop_cache_clear()
+    n_ok = lp.prop_tune_cache_path(str(corrupt))
+    assert n_ok == 1 and lp.prop_tune_cache_rejected() == 5, (n_ok, lp.prop_tune_cache_rejected())
+    p, t, _ = _tune_plans(lp, torch, True, False, seed=3)
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        p.forward(); p.adjoint()
+    torch.cuda.synchronize()
+    report = lp.prop_autotune_report()
+    assert "from file" not in report and "timed" in report
+    assert rel_l2(t[1].cpu().numpy(), oracle.rs_propagate(v, g, 600e-9, 30e-3)) < 1e-5
+    p.close()
+    del bad_variant, arch
+    lp.prop_tune_cache_path(None)
+    lp.prop_cache_clear()
