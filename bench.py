@@ -179,7 +179,7 @@ def cpu_baseline(reps=3):
             "nproc": nproc, "cpu_model": cpu_model(), "reps": reps}, ref
 
 
-def uneven_leg(lp, torch, reps=5):
+def uneven_leg(lp, torch, reps=5, autotune=False):
     """The 96-setup uneven workload as one plan of chained setups (SLM ->
     RS(z) -> lens f -> CZT at z = f onto a 1024^2 window), one graph launch
     per direction: time per forward+adjoint replay pair, setup-gradients/s,
@@ -212,7 +212,7 @@ def uneven_leg(lp, torch, reps=5):
     import warnings
     with warnings.catch_warnings():
         warnings.simplefilter("ignore")
-        plan = lp.Plan(objs, graph=True)
+        plan = lp.Plan(objs, graph=True, autotune=autotune)
         for _ in range(2):
             plan.forward(); plan.adjoint()
         torch.cuda.synchronize()
@@ -231,7 +231,8 @@ def uneven_leg(lp, torch, reps=5):
                         "FP64 phases; forward+adjoint with SLM phase and input gradients",
             "ms_per_replay_pair": ms, "setup_grads_per_s": 96e3 / ms, "model_bytes": model,
             "hbm_gbs": model / (ms * 1e-3) / 1e9, "hbm_frac": model / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "graph_launches_per_direction": 1, "replays": reps, "plan_build_and_warmup_s": build_s}
+            "graph_launches_per_direction": 1, "replays": reps, "plan_build_and_warmup_s": build_s,
+            "autotuned": autotune}
 
 
 def main():
@@ -243,6 +244,9 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-uneven", action="store_true", help="skip the 96-setup uneven plan leg")
+    ap.add_argument("--only-uneven", action="store_true",
+                    help="run only the 96-setup uneven plan leg and print its record (profiling)")
+    ap.add_argument("--autotune", action="store_true", help="autotune the 96-setup plan at its first execution")
     ap.add_argument("--no-trace", action="store_true", help="time without per-kernel events")
     ap.add_argument("--copy-probe", action="store_true",
                     help="finish with a plain 512 MiB device copy (reference for memory counters)")
@@ -257,6 +261,9 @@ def main():
     import paper_2310_08408_amd as lp
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if a.only_uneven:
+        print(json.dumps(uneven_leg(lp, torch, autotune=a.autotune)), flush=True)
+        return
 
     # ---- batched FP32 path -------------------------------------------------
     log(f"inputs: batch {a.batch} x 2048^2 complex64")
@@ -365,7 +372,7 @@ def main():
     uneven = None
     if not a.no_uneven:
         log("uneven 96-setup plan ...")
-        uneven = uneven_leg(lp, torch)
+        uneven = uneven_leg(lp, torch, autotune=a.autotune)
         log(f"uneven 96: {uneven['ms_per_replay_pair']:.2f} ms per forward+adjoint replay pair, "
             f"{uneven['setup_grads_per_s']:.0f} setup-gradients/s, {uneven['hbm_frac']:.3f} of HBM peak")
 

@@ -10,6 +10,11 @@
         bank-conflict cycles per active LDS cycle, waiting cycles per wave
         cycle, VALU-active cycles per wave cycle.
 
+    python bench_profile.py busy DIR [--last N] [--command TEXT]
+        GPU busy time over the window of the last N kernels of a kernel
+        trace (union of kernel intervals, idle gaps between them): how much
+        launch or dependency overhead a graph replay leaves.
+
     python bench_profile.py traffic --fetch DIR --write DIR [--json OUT] [--command TEXT]
         HBM bytes per dispatch from two counter runs (FETCH_SIZE, WRITE_SIZE;
         KiB per dispatch), each scaled by what the same counter reads for the
@@ -174,6 +179,33 @@ def cmd_counters(a):
                   f"{ratio('SQ_ACTIVE_INST_VALU', 'SQ_WAVE_CYCLES'):8.3f}")
 
 
+def cmd_busy(a):
+    rows = list(csv.DictReader(open(find(a.dir, "kernel_trace.csv"))))
+    iv = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]) for r in rows)
+    iv = iv[-a.last:] if a.last else iv
+    t0, t1 = iv[0][0], max(e for _, e, _ in iv)
+    busy, cur_s, cur_e, gaps = 0, iv[0][0], iv[0][1], []
+    for st, en, _ in iv[1:]:
+        if st > cur_e:
+            busy += cur_e - cur_s
+            gaps.append(st - cur_e)
+            cur_s, cur_e = st, en
+        else:
+            cur_e = max(cur_e, en)
+    busy += cur_e - cur_s
+    ksum = sum(e - s for s, e, _ in iv)
+    if a.command:
+        for c in a.command:
+            print(f"# command: {c}")
+    span = t1 - t0
+    print(f"# window: last {len(iv)} kernels of {len(rows)}; span {span / 1e6:.3f} ms")
+    print(f"busy (union of kernel intervals) {busy / 1e6:.3f} ms = {busy / span:.4f} of the span; "
+          f"idle {(span - busy) / 1e6:.3f} ms in {len(gaps)} gaps (mean {sum(gaps) / max(len(gaps), 1) / 1e3:.2f} us, "
+          f"max {max(gaps or [0]) / 1e3:.2f} us)")
+    print(f"sum of kernel durations {ksum / 1e6:.3f} ms (> busy where branches overlap: concurrency "
+          f"{ksum / max(busy, 1):.2f})")
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -185,11 +217,15 @@ def main():
     t.add_argument("--write", required=True)
     t.add_argument("--json")
     t.add_argument("--command", action="append")
+    b = sub.add_parser("busy")
+    b.add_argument("dir")
+    b.add_argument("--last", type=int, default=0)
+    b.add_argument("--command", action="append")
     c = sub.add_parser("counters")
     c.add_argument("dirs", nargs="+")
     c.add_argument("--command", action="append")
     a = ap.parse_args()
-    {"stats": cmd_stats, "traffic": cmd_traffic, "counters": cmd_counters}[a.cmd](a)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "counters": cmd_counters, "busy": cmd_busy}[a.cmd](a)
 
 
 if __name__ == "__main__":
