@@ -79,19 +79,24 @@ class Step:
 
 
 def time_steps(torch, step, steps, warmup):
+    """Wall and GPU time per step of `steps` steps between synchronisations,
+    and the median of the per-step GPU times (an event between consecutive
+    steps on the launch stream)."""
+    import statistics
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    ev0.record()
-    for _ in range(steps):
+    evs[0].record()
+    for i in range(steps):
         step()
-    ev1.record()
+        evs[i + 1].record()
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
-    gpu = ev0.elapsed_time(ev1) / 1e3 / steps
-    return wall, gpu
+    gpu = evs[0].elapsed_time(evs[-1]) / 1e3 / steps
+    med = statistics.median(evs[i].elapsed_time(evs[i + 1]) for i in range(steps)) / 1e3
+    return wall, gpu, med
 
 
 def source_hash():
@@ -289,7 +294,7 @@ def main():
         # the timed steps trace only the dominant pass (two events per launch)
         lp.prop_trace_only(dom)
         lp.prop_trace_enable(True)
-    wall, gpu = time_steps(torch, step, a.steps, 0 if not a.no_trace else a.warmup)
+    wall, gpu, med = time_steps(torch, step, a.steps, 0 if not a.no_trace else a.warmup)
     if not a.no_trace:
         live = lp.prop_trace_read()
         lp.prop_trace_enable(False)
@@ -347,7 +352,7 @@ def main():
                               lp.czt_adjoint(c64, g, win, wl, w["z_czt"]))
     errs["phase_grad"] = rel(step.grad[:1].to(torch.float64), step64.grad)
     log("rel-L2 of FP32 results vs the FP64 GPU path:", {k: f"{v:.2e}" for k, v in errs.items()})
-    wall64, _ = time_steps(torch, step64, a.fp64_steps, 1)
+    wall64, _, _ = time_steps(torch, step64, a.fp64_steps, 1)
     value64 = 2 / wall64
     log(f"fp64 single field: {wall64 * 1e3:.3f} ms/step -> {value64:.1f} grads/s")
 
@@ -410,6 +415,7 @@ def main():
         "per_pass": per_pass,
         "uneven96": uneven,
         "gpu_ms_per_step": gpu * 1e3,
+        "gpu_ms_per_step_median": med * 1e3,
         "first_step_ms": t_setup * 1e3,
     }
     print(json.dumps(out), flush=True)

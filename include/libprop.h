@@ -358,6 +358,12 @@ int prop_adam_step(prop_dtype t, void* param, const void* grad, void* m, void* v
  */
 int prop_track_best(const double* loss, double* best, int64_t* since, int32_t batch, void* stream);
 
+/* Gradient of a parameter shared by a batch (a distance, a wave plate):
+ * out[j] = sum over items i < n of in[i * m + j], summed in item order in
+ * FP64.  in: device double [n][m]; out: device double [m], not overlapping
+ * in (PROP_EALIAS); n, m >= 1 (PROP_ESHAPE). */
+int prop_sum_items(const double* in, double* out, int32_t n, int32_t m, void* stream);
+
 /* ------------------------------------------------------------- utility -- */
 /* Host-only sampling check of RS/VRS: PROP_OK or PROP_WUNDERSAMPLED. */
 int prop_sampling_check(const prop_grid* g, double wavelength, double z);

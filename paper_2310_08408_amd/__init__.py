@@ -23,7 +23,7 @@ __all__ = [
     "vczt_propagate", "vczt_adjoint", "rs_grad_z", "czt_grad_z", "rs_adjoint_phase_grad", "czt_adjoint_phase_grad",
     "prop_source_gaussian", "prop_source_radial", "prop_modulate",
     "prop_phase_grad", "prop_waveplate", "prop_waveplate_adjoint", "prop_spot_loss", "prop_density_loss",
-    "prop_softmin", "prop_adam_step", "Adam", "prop_track_best", "StopRule", "prop_sampling_check",
+    "prop_softmin", "prop_adam_step", "Adam", "prop_track_best", "prop_sum_items", "StopRule", "prop_sampling_check",
     "prop_fft_length", "prop_cache_clear", "prop_trace_enable", "prop_trace_read", "prop_trace_only", "prop_autotune_report",
     "PropError", "PropWarning", "library", "Plan", "Setup", "PROP_OP_RS", "PROP_OP_CZT", "PROP_OP_VRS",
     "PROP_OP_VCZT", "PROP_OP_RS_CZT", "PROP_PLAN_GRAPH", "prop_tune_cache_path", "prop_tune_cache_rejected", "PROP_PLAN_AUTOTUNE", "PROP_PLAN_FAULT_NOMEM", "prop_cache_set_limit",
@@ -695,6 +695,23 @@ class Adam:
     def zero_grad(self):
         for p in self.params:
             p.grad = None
+
+
+def prop_sum_items(x):
+    """Sum over the leading (batch) axis of a float64 device tensor, in item
+    order on the device: [n, ...] -> [...] (a batch-shared parameter's
+    gradient from per-item gradients)."""
+    lib = library()
+    _dev(x, "x")
+    if x.dtype != torch.float64 or x.dim() < 1 or x.shape[0] < 1 or x.numel() < 1:
+        raise ValueError("x must be a non-empty float64 [n, ...] tensor")
+    n = int(x.shape[0])
+    m = x.numel() // n
+    out = torch.empty(tuple(x.shape[1:]), dtype=torch.float64, device=x.device)
+    with torch.cuda.device(x.device):
+        st = lib.prop_sum_items(_ptr(x), _ptr(out), n, m, _stream(x))
+    _lib.check("prop_sum_items", st)
+    return out
 
 
 def prop_track_best(loss, best, since):

@@ -104,6 +104,7 @@ SIGNATURES = {
                                      P]),
     "prop_softmin": (c_int32, [P, c_int32, c_double, P, P, c_int32, P]),
     "prop_track_best": (c_int32, [P, P, P, c_int32, P]),
+    "prop_sum_items": (c_int32, [P, P, c_int32, c_int32, P]),
     "prop_adam_step": (c_int32, [c_int32, P, P, P, P, c_int64, c_double, c_double, c_double, c_double, c_double,
                                  c_int32, P]),
 }

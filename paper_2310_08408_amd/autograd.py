@@ -14,7 +14,7 @@ from __future__ import annotations
 
 import torch
 
-from . import (czt_adjoint, czt_grad_z, czt_propagate, prop_beam_splitter, prop_beam_splitter_adjoint,
+from . import (prop_sum_items, czt_adjoint, czt_grad_z, czt_propagate, prop_beam_splitter, prop_beam_splitter_adjoint,
                prop_density_loss, prop_modulate, prop_modulate_adjoint, prop_phase_grad, prop_phase_grad_sum,
                prop_scale_items, prop_softmin, prop_spot_loss, prop_waveplate,
                prop_waveplate_adjoint, prop_waveplate_batched, prop_waveplate_batched_adjoint, rs_adjoint,
@@ -42,7 +42,7 @@ class RS(torch.autograd.Function):
         g = g.contiguous()
         gz = None
         if ctx.z_tensor and ctx.needs_input_grad[3]:
-            gz = rs_grad_z(u, g, grid, wl, z).sum().reshape(ctx.z_shape)
+            gz = prop_sum_items(rs_grad_z(u, g, grid, wl, z)).reshape(ctx.z_shape)
         gu = rs_adjoint(g, grid, wl, z) if ctx.needs_input_grad[0] else None
         return gu, None, None, gz
 
@@ -65,7 +65,7 @@ class CZT(torch.autograd.Function):
         g = g.contiguous()
         gz = None
         if ctx.z_tensor and ctx.needs_input_grad[4]:
-            gz = czt_grad_z(u, g, gi, win, wl, z, u_out=y).sum().reshape(ctx.z_shape)
+            gz = prop_sum_items(czt_grad_z(u, g, gi, win, wl, z, u_out=y)).reshape(ctx.z_shape)
         gu = czt_adjoint(g, gi, win, wl, z) if ctx.needs_input_grad[0] else None
         return gu, None, None, None, gz
 
@@ -140,7 +140,7 @@ class WavePlate(torch.autograd.Function):
         gx = torch.zeros_like(ex) if gx is None else gx.contiguous()
         gy = torch.zeros_like(ey) if gy is None else gy.contiguous()
         gex, gey, dp = prop_waveplate_adjoint(gx, gy, ex, ey, float(eta), float(theta))
-        tot = dp.sum(0)
+        tot = prop_sum_items(dp)
         return gex, gey, tot[0].to(eta.dtype).reshape(eta.shape), tot[1].to(theta.dtype).reshape(theta.shape)
 
 

@@ -1164,6 +1164,23 @@ hipError_t launch_phase_stage_adj(const cx<T>* g, const cx<T>* u, const T* phase
   return hipGetLastError();
 }
 
+// --------------------------------------------------- batch reductions --
+// out[j] = sum_i in[i * m + j] over i = 0..n-1, in order (FP64): per-item
+// gradients of a parameter shared by the batch.
+__global__ void k_sum_items(const double* in, double* out, int n, int m) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < m; j += gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i) acc += in[(int64_t)i * m + j];
+    out[j] = acc;
+  }
+}
+
+hipError_t launch_sum_items(const double* in, double* out, int n, int m, hipStream_t s) {
+  const int blocks = std::max(1, std::min((m + 255) / 256, 1024));
+  hipLaunchKernelGGL(k_sum_items, dim3(blocks), dim3(256), 0, s, in, out, n, m);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------- spot loss --
 template <typename T>
 __global__ __launch_bounds__(256) void k_spot_partial(const cx<T>* ex, const cx<T>* ey, const cx<T>* ez, int nx,

@@ -139,6 +139,8 @@ hipError_t launch_adam(T* p, const T* g, T* m, T* v, int64_t n, double lr, doubl
 // Soft minimum of ndet losses per batch item and its weights (d value / d l).
 hipError_t launch_softmin(const double* l, int ndet, double beta, double* val, double* w, int batch, hipStream_t s);
 hipError_t launch_track_best(const double* loss, double* best, int64_t* since, int batch, hipStream_t s);
+// out[j] = sum over i < n of in[i * m + j], in order (FP64).
+hipError_t launch_sum_items(const double* in, double* out, int n, int m, hipStream_t s);
 // o = [(x^2+y^2) u | x u | y u] on the input grid (three [batch][ny][nx] planes).
 template <typename T>
 hipError_t launch_czt_dz_prep(const cx<T>* u, cx<T>* o, int nx, int ny, double dx, double dy, double cx0, double cy0,

@@ -2241,6 +2241,14 @@ int prop_track_best(const double* loss, double* best, int64_t* since, int32_t ba
   return PROP_OK;
 }
 
+int prop_sum_items(const double* in, double* out, int32_t n, int32_t m, void* stream) {
+  if (n < 1 || m < 1) return PROP_ESHAPE;
+  if (!in || !out) return PROP_ENULL;
+  LP_RET(check_alias({{in, (size_t)n * m * sizeof(double)}}, {{out, (size_t)m * sizeof(double)}}));
+  LP_TRY(launch_sum_items(in, out, n, m, (hipStream_t)stream));
+  return PROP_OK;
+}
+
 int32_t prop_autotune_report(char* buf, int32_t cap) {
   CtxLock lk;
   Ctx& C = ctx();

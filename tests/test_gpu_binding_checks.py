@@ -104,3 +104,19 @@ def test_plan_rejects_mismatched_setups(lp):
             lp.Plan(setups, dtype=dt)
     p = lp.Plan([ok], dtype=torch.complex128)
     p.close()
+
+
+def test_sum_items(lp):
+    """prop_sum_items: the per-item sum of a batch-shared parameter's
+    gradients, in item order in FP64 on the device."""
+    import torch
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((7, 5, 2))
+    got = lp.prop_sum_items(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = np.zeros((5, 2))
+    for i in range(7):
+        ref = ref + x[i]
+    assert np.array_equal(got, ref)
+    assert float(lp.prop_sum_items(torch.tensor([1.5, -2.0, 4.0], dtype=torch.float64, device="cuda"))) == 3.5
+    with pytest.raises(ValueError):
+        lp.prop_sum_items(torch.zeros(3, dtype=torch.float32, device="cuda"))

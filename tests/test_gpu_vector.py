@@ -222,5 +222,8 @@ def test_vector_config_2048_sampled(lp, kind):
     if kind == "c64":
         assert max(e_vf, e_vb, e_ff, e_fb) < TOL["c64"]
     else:
+        # the phase-conditioning bar of the FP64 RS kernel (derived in
+        # test_gpu_edges.test_rs_full_4096_sampled): <= 3.5 eps k r between two
+        # independent FP64 evaluations of k r
         k_r = 2 * np.pi / wl * np.hypot(np.hypot(n * g.dx, n * g.dy), z)
-        assert max(e_vf, e_vb) < 2.5 * k_r * np.finfo(float).eps and max(e_ff, e_fb) < TOL["c128"]
+        assert max(e_vf, e_vb) < 3.5 * k_r * np.finfo(float).eps and max(e_ff, e_fb) < TOL["c128"]
