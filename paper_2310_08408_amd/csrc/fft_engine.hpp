@@ -285,10 +285,41 @@ template <class S> struct HalfOut {
   __host__ __device__ static constexpr int index(int j, int r) { return j + r * nr; }
 };
 
+// Twiddles of the FP32 4096-point schedule Sched<16, 16, 16> from LDS: two
+// 16 x 16 tables, T0[r][k] = W_4096^{k r} at tl[16 r + k] and T1[r][k] =
+// W_256^{k r} at tl[256 + 16 r + k] (k, r < 16), 4 KiB next to the line
+// buffers.  The first twiddled stage (Ns = 16) reads T1 directly; the second
+// (Ns = 256) forms W_4096^{k r} = W_256^{(k / 16) r} W_4096^{(k % 16) r}, one
+// complex product of two correctly rounded values.  Lanes with consecutive k
+// read consecutive entries.  A kernel using them fills the tables once
+// (tw_lds_fill) and passes their LDS address in place of the global table,
+// with the engine's TL flag set.
+constexpr int kTwLdsElems = 512;
+template <class S>
+constexpr bool tw_lds_ok() {
+  return S::nst == 3 && S::rad[0] == 16 && S::rad[1] == 16 && S::rad[2] == 16;
+}
+template <int s>
+__device__ __forceinline__ cx<float> tw_lds(const cx<float>* tl, int k, int r) {
+  static_assert(s == 1 || s == 2, "twiddled stages of 16*16*16");
+  if constexpr (s == 1) return tl[256 + 16 * r + k];
+  else return cmul(tl[256 + 16 * r + (k >> 4)], tl[16 * r + (k & 15)]);
+}
+// Fill the tables from the global per-thread table of Sched<16, 16, 16>
+// (stage 1 at 16 k + r, stage 2 at 256 + 16 k + r); threads tid < 512 of the
+// workgroup take one entry each; the caller synchronises before use.
+__device__ __forceinline__ void tw_lds_fill(cx<float>* tl, const cx<float>* tw, int tid, int nthreads) {
+  for (int e = tid; e < kTwLdsElems; e += nthreads) {
+    const int r = (e >> 4) & 15, k = e & 15;
+    tl[e] = e < 256 ? tw[256 + 16 * k + r] : tw[16 * k + r];
+  }
+}
+
 // HALF_IN: inputs with index >= n/2 are zero (skipped at compile time);
 // HALF_OUT: only outputs with index < n/2 are consumed (the rest is never
 // computed).  Both need an even first (last) radix.
-template <typename T, int DIR, class S, int s, bool HALF_IN, bool HALF_OUT, class Load, class Store>
+// TL: tw is the LDS table pair of tw_lds (FP32 16*16*16 only).
+template <typename T, int DIR, class S, int s, bool HALF_IN, bool HALF_OUT, bool TL, class Load, class Store>
 __device__ __forceinline__ void ct_stage(cx<T>* __restrict__ lds, const cx<T>* __restrict__ tw, int j,
                                          bool sync_first, Load& load, Store& store) {
   using V = cx<T>;
@@ -322,7 +353,14 @@ __device__ __forceinline__ void ct_stage(cx<T>* __restrict__ lds, const cx<T>* _
   if (act) {
     const int k = j % Ns;
     const int q = j / Ns;
-    if constexpr (!first) {
+    if constexpr (!first && TL) {
+      static_assert(std::is_same<T, float>::value && tw_lds_ok<S>(), "LDS twiddles: FP32 16*16*16");
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const V w = tw_lds<s>(tw, k, r);
+        v[r] = DIR < 0 ? cmul(v[r], w) : cmulc(v[r], w);
+      }
+    } else if constexpr (!first) {
       constexpr bool pt = tw_per_thread<T>();
       const V* t = tw + S::twoff(s, pt) + (pt ? k * R : k);
 #pragma unroll
@@ -353,10 +391,10 @@ __device__ __forceinline__ void ct_stage(cx<T>* __restrict__ lds, const cx<T>* _
   __syncthreads();
 }
 
-template <typename T, int DIR, class S, bool HI, bool HO, class Load, class Store, int... I>
+template <typename T, int DIR, class S, bool HI, bool HO, bool TL, class Load, class Store, int... I>
 __device__ __forceinline__ void ct_line_impl(cx<T>* lds, const cx<T>* tw, int j, bool sync_first, Load& load,
                                              Store& store, std::integer_sequence<int, I...>) {
-  (ct_stage<T, DIR, S, I, HI, HO>(lds, tw, j, sync_first, load, store), ...);
+  (ct_stage<T, DIR, S, I, HI, HO, TL>(lds, tw, j, sync_first, load, store), ...);
 }
 
 // One transform of one line of length S::n by threads j = 0..S::threads-1.
@@ -364,11 +402,12 @@ __device__ __forceinline__ void ct_line_impl(cx<T>* lds, const cx<T>* tw, int j,
 // DIR = -1: forward (exp(-2 pi i jk/n)); DIR = +1: inverse, unnormalised.
 // load_reads_lds: the load functor reads this workgroup's LDS, so the first
 // stage waits for every read before writing.
-template <typename T, int DIR, class S, bool HALF_IN = false, bool HALF_OUT = false, class Load, class Store>
+template <typename T, int DIR, class S, bool HALF_IN = false, bool HALF_OUT = false, bool TL = false, class Load,
+          class Store>
 __device__ __forceinline__ void fft_line(cx<T>* lds, const cx<T>* tw, int j, Load load, Store store,
                                          bool load_reads_lds = false) {
-  ct_line_impl<T, DIR, S, HALF_IN, HALF_OUT>(lds, tw, j, load_reads_lds, load, store,
-                                            std::make_integer_sequence<int, S::nst>{});
+  ct_line_impl<T, DIR, S, HALF_IN, HALF_OUT, TL>(lds, tw, j, load_reads_lds, load, store,
+                                                std::make_integer_sequence<int, S::nst>{});
 }
 
 // Forward transform, pointwise multiply, inverse transform of one line
@@ -378,7 +417,7 @@ __device__ __forceinline__ void fft_line(cx<T>* lds, const cx<T>* tw, int j, Loa
 // (Stockham order), so the product stays in registers: one LDS write, one
 // LDS read and two barriers fewer than two separate fft_line calls.
 // mult(i, v) returns the product for frequency i.
-template <typename T, class S, class Mult>
+template <typename T, class S, bool TL, class Mult>
 __device__ __forceinline__ void conv_mid_stage(cx<T>* __restrict__ lds, const cx<T>* __restrict__ tw, int j,
                                                Mult& mult) {
   using V = cx<T>;
@@ -400,10 +439,16 @@ __device__ __forceinline__ void conv_mid_stage(cx<T>* __restrict__ lds, const cx
   }
   __syncthreads();
   if (act) {
-    constexpr bool pt = tw_per_thread<T>();
-    const V* t = tw + S::twoff(sl, pt) + (pt ? j * R : j);
+    if constexpr (TL) {
+      static_assert(std::is_same<T, float>::value && tw_lds_ok<S>(), "LDS twiddles: FP32 16*16*16");
 #pragma unroll
-    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], pt ? t[r] : t[(r - 1) * nr]);
+      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw_lds<sl>(tw, j, r));
+    } else {
+      constexpr bool pt = tw_per_thread<T>();
+      const V* t = tw + S::twoff(sl, pt) + (pt ? j * R : j);
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], pt ? t[r] : t[(r - 1) * nr]);
+    }
     Dft<R, -1>::template run<T>(v);
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = mult(j + r * nr, v[r]);
@@ -421,13 +466,13 @@ __device__ __forceinline__ void conv_mid_stage(cx<T>* __restrict__ lds, const cx
   __syncthreads();
 }
 
-template <typename T, class S, bool HI, bool HO, class Load, class Mult, class Store, int... I>
+template <typename T, class S, bool HI, bool HO, bool TL, class Load, class Mult, class Store, int... I>
 __device__ __forceinline__ void conv_line_impl(cx<T>* lds, const cx<T>* tw, int j, bool sync_first, Load& load,
                                                Mult& mult, Store& store, std::integer_sequence<int, I...>) {
   auto none = [](int, cx<T>) {};
-  (ct_stage<T, -1, S, I, HI, false>(lds, tw, j, sync_first, load, none), ...);
-  conv_mid_stage<T, S>(lds, tw, j, mult);
-  (ct_stage<T, 1, S, I + 1, false, HO>(lds, tw, j, false, load, store), ...);
+  (ct_stage<T, -1, S, I, HI, false, TL>(lds, tw, j, sync_first, load, none), ...);
+  conv_mid_stage<T, S, TL>(lds, tw, j, mult);
+  (ct_stage<T, 1, S, I + 1, false, HO, TL>(lds, tw, j, false, load, store), ...);
 }
 
 template <class S>
@@ -435,13 +480,15 @@ constexpr bool conv_in_registers() {
   return S::nst >= 2 && S::rad[0] == S::rad[S::nst - 1];
 }
 
-template <typename T, class S, bool HALF_IN = false, bool HALF_OUT = false, class Load, class Mult, class Store>
+template <typename T, class S, bool HALF_IN = false, bool HALF_OUT = false, bool TL = false, class Load, class Mult,
+          class Store>
 __device__ __forceinline__ void conv_line(cx<T>* lds, const cx<T>* tw, int j, Load load, Mult mult, Store store,
                                           bool load_reads_lds = false) {
   if constexpr (conv_in_registers<S>()) {
-    conv_line_impl<T, S, HALF_IN, HALF_OUT>(lds, tw, j, load_reads_lds, load, mult, store,
-                                            std::make_integer_sequence<int, S::nst - 1>{});
+    conv_line_impl<T, S, HALF_IN, HALF_OUT, TL>(lds, tw, j, load_reads_lds, load, mult, store,
+                                                std::make_integer_sequence<int, S::nst - 1>{});
   } else {
+    static_assert(!TL, "LDS twiddles: register hand-off schedules only");
     auto mid = [&](int i, cx<T> v) { lds[S::pad(i)] = mult(i, v); };
     fft_line<T, -1, S, HALF_IN, false>(lds, tw, j, load, mid, load_reads_lds);
     auto load2 = [&](int i) -> cx<T> { return lds[S::pad(i)]; };

@@ -118,6 +118,30 @@ inline int cu_count() {
   return counts[dev];
 }
 
+// FP32 row passes of the 4096-point schedule (RS rows, Bluestein rows) take
+// their twiddles from LDS (tw_lds_fill) instead of per-thread global runs.
+// At 2048^2, batch 8: Bluestein rows 285 -> 228 us, RS inverse rows 226 ->
+// 213, persistent forward rows 164 -> 155.  The column passes keep the
+// global table: there the LDS form measured slower (RS columns 422 -> 435
+// us; Bluestein columns 319 -> 349, where it also spills).
+template <typename T, class S>
+constexpr bool tw_lds() {
+  return std::is_same<T, float>::value && tw_lds_ok<S>();
+}
+
+// The twiddles a pass reads: with TL the LDS table pair after the line
+// buffers (filled here; the caller's next barrier publishes it), else the
+// global table.
+template <bool TL, typename T>
+__device__ __forceinline__ const cx<T>* tw_source(cx<T>* tl, const cx<T>* tw, int nthreads) {
+  if constexpr (TL) {
+    tw_lds_fill(tl, tw, threadIdx.x, nthreads);
+    return tl;
+  } else {
+    return tw;
+  }
+}
+
 // Streaming accesses without cache retention (non-temporal): for passes in
 // which each element is touched once and one workgroup consumes whole
 // lines, so that the transform's twiddle tables stay cached instead.  Not
@@ -326,9 +350,12 @@ struct RowCfg {
 template <typename T, int DIR, class S, int C, bool HALF, bool EXACT = false, bool PG = true, bool STAGE = false>
 __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) void k_rs_rows(
     const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int64_t w_bstride, int nrows, int n_io, T scale, int tiles,
-    const cx<T>* __restrict__ tw, PhaseGrad<T> pg, Slm<T> st) {
+    const cx<T>* __restrict__ tw_g, PhaseGrad<T> pg, Slm<T> st) {
   constexpr int LS = line_stride<S, C, true>();
-  __shared__ cx<T> smem[C * LS];
+  constexpr bool TL = tw_lds<T, S>();
+  __shared__ cx<T> smem[C * LS + (TL ? kTwLdsElems : 0)];
+  // (the first stage's barrier publishes the LDS twiddles before their use)
+  const cx<T>* tw = tw_source<TL>(smem + C * LS, tw_g, C * S::threads);
   const int id = xcd_remap(blockIdx.x, gridDim.x);
   const int b = id / tiles, tile = id - b * tiles;
   const int c = (int)(threadIdx.x % C), j = (int)(threadIdx.x / C);
@@ -351,7 +378,7 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
     auto store = [&](int i, cx<T> v) {
       if (valid) out[widx(i)] = v;
     };
-    fft_line<T, -1, S, HALF, false>(lds, tw, j, load, store);
+    fft_line<T, -1, S, HALF, false, TL>(lds, tw, j, load, store);
   } else {
     auto load = [&](int i) -> cx<T> {
       cx<T> v = czero<T>();
@@ -373,7 +400,7 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
         }
       }
     };
-    fft_line<T, 1, S, false, HALF>(lds, tw, j, load, store);
+    fft_line<T, 1, S, false, HALF, TL>(lds, tw, j, load, store);
   }
 }
 
@@ -387,9 +414,11 @@ template <typename T, class S, int C, bool STAGE = false>
 __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) void k_rs_rows_fwd_persist(
     const cx<T>* in, cx<T>* out, int64_t w_bstride, int nrows, int n_io, int tiles, int items, int per,
     TableBox<T> tw_, Slm<T> st) {
-  const cx<T>* tw = tw_.p;
   constexpr int LS = line_stride<S, C, true>();
-  __shared__ cx<T> smem[C * LS];
+  constexpr bool TL = tw_lds<T, S>();
+  __shared__ cx<T> smem[C * LS + (TL ? kTwLdsElems : 0)];
+  // (the first stage's barrier publishes the LDS twiddles before their use)
+  const cx<T>* tw = tw_source<TL>(smem + C * LS, tw_.p, C * S::threads);
   using HI = HalfIn<S>;
   constexpr int RIN = HI::R;
   const int chunk = xcd_remap(blockIdx.x, gridDim.x);
@@ -425,7 +454,7 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
       return cur[(i - j) / HI::nr];
     };
     auto store = [&](int i, cx<T> v) { out[wrow + (int64_t)(i >> kTileShift) * tst + (i & (kTile - 1))] = v; };
-    fft_line<T, -1, S, true, false>(lds, tw, j, load, store);
+    fft_line<T, -1, S, true, false, TL>(lds, tw, j, load, store);
   }
 }
 
@@ -572,9 +601,9 @@ template <typename T, class S, int C, bool CONJ>
 __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) void k_rs_cols_persist(
     cx<T>* W, int64_t bstride, int n_valid, TableBox<T> Sq_, int nb, int items, int per, TableBox<T> tw_) {
   const cx<T>* Sq = Sq_.p;
-  const cx<T>* tw = tw_.p;
   constexpr int LS = line_stride<S, C, true>();
   __shared__ cx<T> smem[C * LS];
+  const cx<T>* tw = tw_.p;
   using HI = HalfIn<S>;
   constexpr int My = S::n, RIN = HI::R;
   const int chunk = xcd_remap(blockIdx.x, gridDim.x);
@@ -825,7 +854,10 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, bluestein_in
                                                               const cx<T>* tw, PhaseGrad<T> pg, Slm<T> st) {
   constexpr bool ILV = bluestein_interleaved<T, COL>();
   constexpr int LS = line_stride<S, C, ILV>();
-  __shared__ cx<T> smem[C * LS];
+  constexpr bool TL = !COL && tw_lds<T, S>();
+  __shared__ cx<T> smem[C * LS + (TL ? kTwLdsElems : 0)];
+  // (the first stage's barrier publishes the LDS twiddles before their use)
+  tw = tw_source<TL>(smem + C * LS, tw, C * S::threads);
   const int id = xcd_remap(blockIdx.x, gridDim.x);
   const int b = id / tiles, tile = id - b * tiles;
   const int c = ILV ? (int)(threadIdx.x % C) : (int)(threadIdx.x / S::threads);
@@ -862,7 +894,7 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, bluestein_in
       }
     }
   };
-  conv_line<T, S, HALF, HALF>(lds, tw, j, load, mult, store);
+  conv_line<T, S, HALF, HALF, TL>(lds, tw, j, load, mult, store);
 }
 
 template <typename T, bool COL, class S, int C, bool STAGE>
