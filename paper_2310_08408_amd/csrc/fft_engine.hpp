@@ -285,40 +285,52 @@ template <class S> struct HalfOut {
   __host__ __device__ static constexpr int index(int j, int r) { return j + r * nr; }
 };
 
-// Twiddles of the FP32 4096-point schedule Sched<16, 16, 16> from LDS: two
-// 16 x 16 tables, T0[r][k] = W_4096^{k r} at tl[16 r + k] and T1[r][k] =
-// W_256^{k r} at tl[256 + 16 r + k] (k, r < 16), 4 KiB next to the line
-// buffers.  The first twiddled stage (Ns = 16) reads T1 directly; the second
-// (Ns = 256) forms W_4096^{k r} = W_256^{(k / 16) r} W_4096^{(k % 16) r}, one
-// complex product of two correctly rounded values.  Lanes with consecutive k
-// read consecutive entries.  A kernel using them fills the tables once
-// (tw_lds_fill) and passes their LDS address in place of the global table,
+// FP32 twiddles from LDS tables, for schedules of two or three stages
+// R0 R1 (R2).  The first twiddled stage (Ns = R0) reads T1[r][k] =
+// W_{R0 R1}^{k r} (k < R0, r < R1) directly.  The second (Ns = R0 R1, three
+// stages) forms W_n^{k r} = W_{R1 R2}^{a r} W_n^{b r} with k = R0 a + b from
+// Thi[r][a] (a < R1, r < R2) and Tlo[r][b] (b < R0): one complex product of
+// two correctly rounded values.  When R0 = R1 = R2, Thi is T1 and is stored
+// once (16*16*16: 512 entries, 4 KiB).  Lanes with consecutive k read
+// consecutive entries.  A kernel using them fills the tables once per
+// workgroup (fill) and passes their LDS address in place of the global table,
 // with the engine's TL flag set.
-constexpr int kTwLdsElems = 512;
 template <class S>
-constexpr bool tw_lds_ok() {
-  return S::nst == 3 && S::rad[0] == 16 && S::rad[1] == 16 && S::rad[2] == 16;
-}
-template <int s>
-__device__ __forceinline__ cx<float> tw_lds(const cx<float>* tl, int k, int r) {
-  static_assert(s == 1 || s == 2, "twiddled stages of 16*16*16");
-  if constexpr (s == 1) return tl[256 + 16 * r + k];
-  else return cmul(tl[256 + 16 * r + (k >> 4)], tl[16 * r + (k & 15)]);
-}
-// Fill the tables from the global per-thread table of Sched<16, 16, 16>
-// (stage 1 at 16 k + r, stage 2 at 256 + 16 k + r); threads tid < 512 of the
-// workgroup take one entry each; the caller synchronises before use.
-__device__ __forceinline__ void tw_lds_fill(cx<float>* tl, const cx<float>* tw, int tid, int nthreads) {
-  for (int e = tid; e < kTwLdsElems; e += nthreads) {
-    const int r = (e >> 4) & 15, k = e & 15;
-    tl[e] = e < 256 ? tw[256 + 16 * k + r] : tw[16 * k + r];
+struct TwLds {
+  static constexpr bool ok = S::nst == 2 || S::nst == 3;
+  static constexpr int R0 = S::rad[0], R1 = ok ? S::rad[1] : 1, R2 = S::nst == 3 ? S::rad[2] : 1;
+  static constexpr bool shared_hi = S::nst == 3 && R0 == R1 && R1 == R2;
+  static constexpr int o_hi = shared_hi ? 0 : R0 * R1;
+  static constexpr int o_lo = shared_hi ? R0 * R1 : R0 * R1 + R1 * R2;
+  static constexpr int elems = S::nst == 3 ? o_lo + R0 * R2 : R0 * R1;
+  // LDS entry of the first twiddled stage's W^{k r}; the two entries whose
+  // product is the second's
+  __host__ __device__ static constexpr int at1(int k, int r) { return r * R0 + k; }
+  __host__ __device__ static constexpr int at2_hi(int k, int r) { return o_hi + r * R1 + k / R0; }
+  __host__ __device__ static constexpr int at2_lo(int k, int r) { return o_lo + r * R0 + k % R0; }
+  // the global per-thread FP32 table entry (stage 1 at k R1 + r, stage 2 at
+  // R0 R1 + k R2 + r) that LDS entry e copies
+  __host__ __device__ static constexpr int src(int e) {
+    return e < R0 * R1 ? (e % R0) * R1 + e / R0
+           : e < o_lo  ? R0 * R1 + R0 * ((e - R0 * R1) % R1) * R2 + (e - R0 * R1) / R1
+                       : R0 * R1 + ((e - o_lo) % R0) * R2 + (e - o_lo) / R0;
   }
-}
+  template <int s>
+  __device__ __forceinline__ static cx<float> get(const cx<float>* tl, int k, int r) {
+    static_assert(s == 1 || (s == 2 && S::nst == 3), "twiddled stages of two- and three-stage schedules");
+    if constexpr (s == 1) return tl[at1(k, r)];
+    else return cmul(tl[at2_hi(k, r)], tl[at2_lo(k, r)]);
+  }
+  // every thread of the workgroup calls this; the caller synchronises before use
+  __device__ __forceinline__ static void fill(cx<float>* tl, const cx<float>* tw, int tid, int nthreads) {
+    for (int e = tid; e < elems; e += nthreads) tl[e] = tw[src(e)];
+  }
+};
 
 // HALF_IN: inputs with index >= n/2 are zero (skipped at compile time);
 // HALF_OUT: only outputs with index < n/2 are consumed (the rest is never
 // computed).  Both need an even first (last) radix.
-// TL: tw is the LDS table pair of tw_lds (FP32 16*16*16 only).
+// TL: tw is the LDS twiddle tables of TwLds<S> (FP32, two or three stages).
 template <typename T, int DIR, class S, int s, bool HALF_IN, bool HALF_OUT, bool TL, class Load, class Store>
 __device__ __forceinline__ void ct_stage(cx<T>* __restrict__ lds, const cx<T>* __restrict__ tw, int j,
                                          bool sync_first, Load& load, Store& store) {
@@ -354,10 +366,10 @@ __device__ __forceinline__ void ct_stage(cx<T>* __restrict__ lds, const cx<T>* _
     const int k = j % Ns;
     const int q = j / Ns;
     if constexpr (!first && TL) {
-      static_assert(std::is_same<T, float>::value && tw_lds_ok<S>(), "LDS twiddles: FP32 16*16*16");
+      static_assert(std::is_same<T, float>::value && TwLds<S>::ok, "LDS twiddles: FP32, two or three stages");
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        const V w = tw_lds<s>(tw, k, r);
+        const V w = TwLds<S>::template get<s>(tw, k, r);
         v[r] = DIR < 0 ? cmul(v[r], w) : cmulc(v[r], w);
       }
     } else if constexpr (!first) {
@@ -440,9 +452,9 @@ __device__ __forceinline__ void conv_mid_stage(cx<T>* __restrict__ lds, const cx
   __syncthreads();
   if (act) {
     if constexpr (TL) {
-      static_assert(std::is_same<T, float>::value && tw_lds_ok<S>(), "LDS twiddles: FP32 16*16*16");
+      static_assert(std::is_same<T, float>::value && TwLds<S>::ok, "LDS twiddles: FP32, two or three stages");
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw_lds<sl>(tw, j, r));
+      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], TwLds<S>::template get<sl>(tw, j, r));
     } else {
       constexpr bool pt = tw_per_thread<T>();
       const V* t = tw + S::twoff(sl, pt) + (pt ? j * R : j);

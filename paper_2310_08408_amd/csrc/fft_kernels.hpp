@@ -118,24 +118,33 @@ inline int cu_count() {
   return counts[dev];
 }
 
-// FP32 row passes of the 4096-point schedule (RS rows, Bluestein rows) take
-// their twiddles from LDS (tw_lds_fill) instead of per-thread global runs.
-// At 2048^2, batch 8: Bluestein rows 285 -> 228 us, RS inverse rows 226 ->
-// 213, persistent forward rows 164 -> 155.  The column passes keep the
-// global table: there the LDS form measured slower (RS columns 422 -> 435
-// us; Bluestein columns 319 -> 349, where it also spills).
-template <typename T, class S>
+// FP32 row passes (RS rows, Bluestein rows) of two- and three-stage
+// schedules take their twiddles from LDS tables (TwLds) instead of the
+// per-thread global runs, whose L2 round trip every wave of a workgroup
+// waits for at once -- where the tables keep the workgroups per CU that the
+// line buffers allow.  At 2048^2, batch 8 (4096 points): Bluestein rows 285
+// -> 228 us, RS inverse rows 226 -> 213, persistent forward rows 164 -> 155.
+// The column passes keep the global table: there the LDS form measured
+// slower (RS columns 422 -> 435 us; Bluestein columns 319 -> 349, where it
+// also spills).
+template <typename T, class S, int C, bool ILV>
 constexpr bool tw_lds() {
-  return std::is_same<T, float>::value && tw_lds_ok<S>();
+  if constexpr (!std::is_same<T, float>::value || !TwLds<S>::ok) {
+    return false;
+  } else {
+    constexpr int base = C * line_stride<S, C, ILV>() * (int)sizeof(cx<T>);
+    constexpr int with = base + TwLds<S>::elems * (int)sizeof(cx<T>);
+    return with <= kLdsBytes && kLdsBytes / with == kLdsBytes / base;
+  }
 }
 
 // The twiddles a pass reads: with TL the LDS table pair after the line
 // buffers (filled here; the caller's next barrier publishes it), else the
 // global table.
-template <bool TL, typename T>
+template <bool TL, class S, typename T>
 __device__ __forceinline__ const cx<T>* tw_source(cx<T>* tl, const cx<T>* tw, int nthreads) {
   if constexpr (TL) {
-    tw_lds_fill(tl, tw, threadIdx.x, nthreads);
+    TwLds<S>::fill(tl, tw, threadIdx.x, nthreads);
     return tl;
   } else {
     return tw;
@@ -352,10 +361,10 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
     const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int64_t w_bstride, int nrows, int n_io, T scale, int tiles,
     const cx<T>* __restrict__ tw_g, PhaseGrad<T> pg, Slm<T> st) {
   constexpr int LS = line_stride<S, C, true>();
-  constexpr bool TL = tw_lds<T, S>();
-  __shared__ cx<T> smem[C * LS + (TL ? kTwLdsElems : 0)];
+  constexpr bool TL = tw_lds<T, S, C, true>();
+  __shared__ cx<T> smem[C * LS + (TL ? TwLds<S>::elems : 0)];
   // (the first stage's barrier publishes the LDS twiddles before their use)
-  const cx<T>* tw = tw_source<TL>(smem + C * LS, tw_g, C * S::threads);
+  const cx<T>* tw = tw_source<TL, S>(smem + C * LS, tw_g, C * S::threads);
   const int id = xcd_remap(blockIdx.x, gridDim.x);
   const int b = id / tiles, tile = id - b * tiles;
   const int c = (int)(threadIdx.x % C), j = (int)(threadIdx.x / C);
@@ -415,10 +424,10 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
     const cx<T>* in, cx<T>* out, int64_t w_bstride, int nrows, int n_io, int tiles, int items, int per,
     TableBox<T> tw_, Slm<T> st) {
   constexpr int LS = line_stride<S, C, true>();
-  constexpr bool TL = tw_lds<T, S>();
-  __shared__ cx<T> smem[C * LS + (TL ? kTwLdsElems : 0)];
+  constexpr bool TL = tw_lds<T, S, C, true>();
+  __shared__ cx<T> smem[C * LS + (TL ? TwLds<S>::elems : 0)];
   // (the first stage's barrier publishes the LDS twiddles before their use)
-  const cx<T>* tw = tw_source<TL>(smem + C * LS, tw_.p, C * S::threads);
+  const cx<T>* tw = tw_source<TL, S>(smem + C * LS, tw_.p, C * S::threads);
   using HI = HalfIn<S>;
   constexpr int RIN = HI::R;
   const int chunk = xcd_remap(blockIdx.x, gridDim.x);
@@ -854,10 +863,10 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, bluestein_in
                                                               const cx<T>* tw, PhaseGrad<T> pg, Slm<T> st) {
   constexpr bool ILV = bluestein_interleaved<T, COL>();
   constexpr int LS = line_stride<S, C, ILV>();
-  constexpr bool TL = !COL && tw_lds<T, S>();
-  __shared__ cx<T> smem[C * LS + (TL ? kTwLdsElems : 0)];
+  constexpr bool TL = !COL && ILV && conv_in_registers<S>() && tw_lds<T, S, C, ILV>();
+  __shared__ cx<T> smem[C * LS + (TL ? TwLds<S>::elems : 0)];
   // (the first stage's barrier publishes the LDS twiddles before their use)
-  tw = tw_source<TL>(smem + C * LS, tw, C * S::threads);
+  tw = tw_source<TL, S>(smem + C * LS, tw, C * S::threads);
   const int id = xcd_remap(blockIdx.x, gridDim.x);
   const int b = id / tiles, tile = id - b * tiles;
   const int c = ILV ? (int)(threadIdx.x % C) : (int)(threadIdx.x / S::threads);

@@ -11,7 +11,11 @@
 //    strides) address exactly the padded element;
 //  * each launch configuration fits the LDS and thread limits;
 //  * the persistent work split and the XCD remap cover each workgroup and
-//    work item exactly once.
+//    work item exactly once;
+//  * the LDS twiddle tables of the FP32 row passes (TwLds) give every
+//    twiddled stage's W^{k r}: the global table entries they copy have the
+//    right exponents (one entry for the first twiddled stage, two whose
+//    exponents add up for the second), and every entry is in range.
 #include <cstdio>
 #include <vector>
 
@@ -106,6 +110,47 @@ static void check_len() {
   }
 }
 
+// Exponent e (W_n^e) of entry x of the global per-thread FP32 table of S:
+// stage 1 (Ns = R0) holds W_{R0 R1}^{k r} = W_n^{k r n / (R0 R1)} at k R1 + r,
+// stage 2 (Ns = R0 R1) W_n^{k r} at R0 R1 + k R2 + r.
+template <class S>
+static long tw_exponent(int x) {
+  constexpr int R0 = S::rad[0], R1 = S::rad[1], R2 = S::nst == 3 ? S::rad[2] : 1;
+  if (x < R0 * R1) return (long)(x / R1) * (x % R1) * (S::n / (R0 * R1));
+  const int y = x - R0 * R1;
+  return (long)(y / R2) * (y % R2);
+}
+
+template <class S>
+static void check_twlds() {
+  using L = TwLds<S>;
+  if constexpr (L::ok) {
+    const int n = S::n, R0 = S::rad[0], R1 = S::rad[1];
+    const int size = S::twsize(true);
+    for (int e = 0; e < L::elems; ++e)
+      if (L::src(e) < 0 || L::src(e) >= size) fail("LDS twiddle source out of table", n, 4, e, L::src(e));
+    for (int k = 0; k < R0; ++k)
+      for (int r = 0; r < R1; ++r) {
+        const int a = L::at1(k, r);
+        if (a < 0 || a >= L::elems) fail("LDS twiddle entry out of range", n, 4, k, r);
+        else if (tw_exponent<S>(L::src(a)) % n != (long)k * r * (n / (R0 * R1)) % n)
+          fail("first-stage LDS twiddle exponent", n, 4, k, r);
+      }
+    if constexpr (S::nst == 3) {
+      for (int k = 0; k < R0 * R1; ++k)
+        for (int r = 0; r < S::rad[2]; ++r) {
+          const int h = L::at2_hi(k, r), l = L::at2_lo(k, r);
+          if (h < 0 || h >= L::elems || l < 0 || l >= L::elems) {
+            fail("LDS twiddle entry out of range", n, 4, k, r);
+            continue;
+          }
+          if ((tw_exponent<S>(L::src(h)) + tw_exponent<S>(L::src(l))) % n != (long)k * r % n)
+            fail("second-stage LDS twiddle exponent", n, 4, k, r);
+        }
+    }
+  }
+}
+
 static void check_split() {
   for (int cus : {1, 7, 8, 64, 255, 256}) {
     for (int items = 1; items <= 3000; items += (items < 300 ? 1 : 37)) {
@@ -130,13 +175,16 @@ static void check_split() {
 }
 
 int main() {
-#define LP_CHECK(N, ...)                                  \
-  check_len<float, SchedOf<float, Sched<__VA_ARGS__>>>(); \
-  check_len<double, SchedOf<double, Sched<__VA_ARGS__>>>();
+#define LP_CHECK(N, ...)                                    \
+  check_len<float, SchedOf<float, Sched<__VA_ARGS__>>>();   \
+  check_len<double, SchedOf<double, Sched<__VA_ARGS__>>>(); \
+  check_twlds<SchedOf<float, Sched<__VA_ARGS__>>>();
   LP_LENGTHS(LP_CHECK)
 #undef LP_CHECK
   // the alternative schedules the autotuner may choose (FP32)
-#define LP_CHECK_ALT(N, ...) check_len<float, Sched<__VA_ARGS__>>();
+#define LP_CHECK_ALT(N, ...) \
+  check_len<float, Sched<__VA_ARGS__>>(); \
+  check_twlds<Sched<__VA_ARGS__>>();
   LP_ALT_LENGTHS(LP_CHECK_ALT)
 #undef LP_CHECK_ALT
   check_split();
