@@ -429,16 +429,19 @@ __device__ __forceinline__ void fft_line(cx<T>* lds, const cx<T>* tw, int j, Loa
 // (Stockham order), so the product stays in registers: one LDS write, one
 // LDS read and two barriers fewer than two separate fft_line calls.
 // mult(i, v) returns the product for frequency i.
-template <typename T, class S, bool TL, class Mult>
-__device__ __forceinline__ void conv_mid_stage(cx<T>* __restrict__ lds, const cx<T>* __restrict__ tw, int j,
-                                               Mult& mult) {
+// The two halves of the register hand-off: conv_fwd_last reads the last
+// forward stage's inputs from LDS and leaves its outputs, frequencies
+// j + r n/R, in v; conv_inv_first runs the first inverse stage on v and
+// writes its outputs to LDS.
+template <typename T, class S, bool TL>
+__device__ __forceinline__ void conv_fwd_last(cx<T>* __restrict__ lds, const cx<T>* __restrict__ tw, int j,
+                                              cx<T> (&v)[S::rad[S::nst - 1]]) {
   using V = cx<T>;
   constexpr int sl = S::nst - 1;
   constexpr int R = S::rad[sl];
   constexpr int nr = S::n / R;
   static_assert(S::rad[0] == R && S::ns(sl) == nr, "register hand-off needs equal first and last radices");
   const bool act = j < nr;
-  V v[R];
   if (act) {
     if constexpr (S::stride_pad(nr)) {
       const cx<T>* p = lds + S::pad(j);
@@ -462,8 +465,14 @@ __device__ __forceinline__ void conv_mid_stage(cx<T>* __restrict__ lds, const cx
       for (int r = 1; r < R; ++r) v[r] = cmul(v[r], pt ? t[r] : t[(r - 1) * nr]);
     }
     Dft<R, -1>::template run<T>(v);
-#pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = mult(j + r * nr, v[r]);
+  }
+}
+
+template <typename T, class S>
+__device__ __forceinline__ void conv_inv_first(cx<T>* __restrict__ lds, int j, cx<T> (&v)[S::rad[S::nst - 1]]) {
+  constexpr int R = S::rad[S::nst - 1];
+  constexpr int nr = S::n / R;
+  if (j < nr) {
     Dft<R, 1>::template run<T>(v);
     // first inverse stage (Ns = 1): outputs j R + r
     if constexpr (S::contiguous_pad(R)) {
@@ -476,6 +485,20 @@ __device__ __forceinline__ void conv_mid_stage(cx<T>* __restrict__ lds, const cx
     }
   }
   __syncthreads();
+}
+
+template <typename T, class S, bool TL, class Mult>
+__device__ __forceinline__ void conv_mid_stage(cx<T>* __restrict__ lds, const cx<T>* __restrict__ tw, int j,
+                                               Mult& mult) {
+  constexpr int R = S::rad[S::nst - 1];
+  constexpr int nr = S::n / R;
+  cx<T> v[R];
+  conv_fwd_last<T, S, TL>(lds, tw, j, v);
+  if (j < nr) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = mult(j + r * nr, v[r]);
+  }
+  conv_inv_first<T, S>(lds, j, v);
 }
 
 template <typename T, class S, bool HI, bool HO, bool TL, class Load, class Mult, class Store, int... I>
@@ -506,6 +529,37 @@ __device__ __forceinline__ void conv_line(cx<T>* lds, const cx<T>* tw, int j, Lo
     auto load2 = [&](int i) -> cx<T> { return lds[S::pad(i)]; };
     fft_line<T, 1, S, false, HALF_OUT>(lds, tw, j, load2, store, true);
   }
+}
+
+// Two-input convolution of one line: out = IFFT( mix(k, FFT(a)[k], FFT(b)[k]) )
+// with zero upper input halves and the lower output half kept.  The same
+// threads transform a and then b, holding FFT(a) in registers while b runs
+// through the LDS stages; one inverse transform follows.  Needs the register
+// hand-off (equal first and last radix).
+template <typename T, class S, class LoadA, class LoadB, class Mix, class Store, int... I>
+__device__ __forceinline__ void mix2_line_impl(cx<T>* lds, const cx<T>* tw, int j, LoadA& load_a, LoadB& load_b,
+                                               Mix& mix, Store& store, std::integer_sequence<int, I...>) {
+  constexpr int R = S::rad[S::nst - 1];
+  constexpr int nr = S::n / R;
+  auto none = [](int, cx<T>) {};
+  cx<T> va[R], vb[R];
+  (ct_stage<T, -1, S, I, true, false, false>(lds, tw, j, false, load_a, none), ...);
+  conv_fwd_last<T, S, false>(lds, tw, j, va);
+  (ct_stage<T, -1, S, I, true, false, false>(lds, tw, j, false, load_b, none), ...);
+  conv_fwd_last<T, S, false>(lds, tw, j, vb);
+  if (j < nr) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) va[r] = mix(j + r * nr, va[r], vb[r]);
+  }
+  conv_inv_first<T, S>(lds, j, va);
+  (ct_stage<T, 1, S, I + 1, false, true, false>(lds, tw, j, false, load_a, store), ...);
+}
+
+template <typename T, class S, class LoadA, class LoadB, class Mix, class Store>
+__device__ __forceinline__ void mix2_line(cx<T>* lds, const cx<T>* tw, int j, LoadA load_a, LoadB load_b, Mix mix,
+                                          Store store) {
+  static_assert(conv_in_registers<S>(), "two-input convolution needs the register hand-off");
+  mix2_line_impl<T, S>(lds, tw, j, load_a, load_b, mix, store, std::make_integer_sequence<int, S::nst - 1>{});
 }
 
 // Host-side description of a length's schedule (for twiddle tables).

@@ -788,6 +788,54 @@ __global__ __launch_bounds__(2 * C * S::threads) void k_mix2_cols(
   fft_line<T, 1, S>(lds0, tw, slot == 0 ? j : S::threads, load2, store, true);
 }
 
+// Exact-half form (valid length n/2, column count a multiple of kTile; FP32
+// schedules with the register hand-off): one column tile of kTile columns
+// per workgroup, lanes of the columns interleaved, so every wave reads whole
+// 32-byte tile rows (512 contiguous bytes); each column's threads transform a,
+// then b (mix2_line), and run the one inverse transform.  The general form
+// above gives each column its own pair of 256-thread slots with one column
+// per workgroup, so its accesses are 8-byte segments.
+template <typename T, class S>
+constexpr bool mix2_exact_ok() {
+  return tw_per_thread<T>() && conv_in_registers<S>() && S::threads * kTile <= kColThreads &&
+         kTile * line_stride<S, kTile, true>() * (int)sizeof(cx<T>) <= kLdsBytes;
+}
+
+template <typename T, class S>
+__global__ __launch_bounds__(kTile * S::threads, (waves_per_eu<T, S, kTile, true>())) void k_mix2_cols_x(
+    const cx<T>* a, const cx<T>* bsrc, cx<T>* out, int64_t bstride, int n_valid, TableBox<T> Sa_, int kind_a, T ca,
+    TableBox<T> Sb_, int kind_b, T cb, int conj_spec, int Mx, int tiles, TableBox<T> tw_) {
+  constexpr int C = kTile;
+  constexpr int LS = line_stride<S, C, true>();
+  __shared__ cx<T> smem[C * LS];
+  constexpr int My = S::n;
+  const cx<T>* Sa = Sa_.p;
+  const cx<T>* Sb = Sb_.p;
+  // batch-minor order, as in the RS column pass
+  const int id = xcd_remap(blockIdx.x, gridDim.x);
+  const int nb = gridDim.x / tiles;
+  const int tile = id / nb, bt = id - tile * nb;
+  const int c = (int)(threadIdx.x % C), j = (int)(threadIdx.x / C);
+  const int kx = tile * C + c;
+  cx<T>* lds = smem + c * LS;
+  const int64_t coff = bt * bstride + (int64_t)tile * n_valid * kTile + c;
+  const cx<T>* pa = a + coff;
+  const cx<T>* pb = bsrc + coff;
+  cx<T>* po = out + coff;
+  auto load_a = [&](int i) -> cx<T> { return load_stream(&pa[i * kTile]); };
+  auto load_b = [&](int i) -> cx<T> { return load_stream(&pb[i * kTile]); };
+  auto mix = [&](int k, cx<T> va, cx<T> vb) -> cx<T> {
+    cx<T> ha = spec_at(Sa, kind_a, kx, k, Mx, My), hb = spec_at(Sb, kind_b, kx, k, Mx, My);
+    if (conj_spec) {
+      ha.y = -ha.y;
+      hb.y = -hb.y;
+    }
+    return cadd(cscale(cmul(va, ha), ca), cscale(cmul(vb, hb), cb));
+  };
+  auto store = [&](int i, cx<T> v) { store_stream(&po[i * kTile], v); };
+  mix2_line<T, S>(lds, tw_.p, j, load_a, load_b, mix, store);
+}
+
 template <typename T, class S, int C>
 hipError_t launch_mix2_cols_c(const cx<T>* a, const cx<T>* b, cx<T>* out, int64_t bstride, int ncols, int n_valid,
                               const cx<T>* Sa, int kind_a, T ca, const cx<T>* Sb, int kind_b, T cb, bool conj_spec,
@@ -806,6 +854,15 @@ hipError_t launch_mix2_cols_s(const cx<T>* a, const cx<T>* b, cx<T>* out, int64_
   if constexpr (!CF::fits) {
     return hipErrorInvalidValue;
   } else {
+    if constexpr (mix2_exact_ok<T, S>()) {
+      if (variant == 0 && 2 * n_valid == S::n && ncols % kTile == 0) {
+        const int tiles = ncols / kTile;
+        hipLaunchKernelGGL((k_mix2_cols_x<T, S>), dim3(tiles * batch), dim3(kTile * S::threads), 0, s, a, b, out,
+                           bstride, n_valid, TableBox<T>{Sa}, kind_a, ca, TableBox<T>{Sb}, kind_b, cb,
+                           conj_spec ? 1 : 0, Mx, tiles, TableBox<T>{tw});
+        return hipGetLastError();
+      }
+    }
     constexpr int C1 = variant_lines<S, CF::C>(1), C2 = variant_lines<S, CF::C>(2);
     if (variant == 1)
       return launch_mix2_cols_c<T, S, C1>(a, b, out, bstride, ncols, n_valid, Sa, kind_a, ca, Sb, kind_b, cb,

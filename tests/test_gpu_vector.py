@@ -57,6 +57,12 @@ VRS_CASES = [
     (Grid(48, 40, 2e-6, 2.5e-6, 1e-6, -1e-6), 1, 600e-9, 300e-6),
     (Grid(96, 96, 3e-6, 3e-6), 2, 532e-9, 2e-3),
     (Grid(1, 5, 1e-6, 1e-6), 1, 500e-9, 1e-5),
+    # exact halves on schedules with the register hand-off (256 = 16*16,
+    # 512 = 8*8*8): the complex64 mixing pass runs one 4-column tile per
+    # workgroup with both transforms on the same threads
+    (Grid(128, 128, 4e-6, 4e-6), 3, 633e-9, 4e-3),
+    (Grid(256, 256, 2e-6, 2e-6, 0.5e-6, 0), 2, 532e-9, 1.5e-3),
+    (Grid(1024, 1024, 4e-6, 4e-6), 1, 532e-9, 30e-3),      # 2048 = 16*8*16
 ]
 
 
@@ -74,8 +80,13 @@ def test_vrs_forward_and_adjoint(lp, kind, case):
         back = [host(t) for t in lp.vrs_adjoint(*(dev(a, kind) for a in gs), g, wl, z)]
     ef = errs(out, oracle.vrs_propagate(ex, ey, g, wl, z))
     ea = errs(back, oracle.vrs_adjoint(*gs, g, wl, z))
-    say(f"  fwd {ef:.2e} adj {ea:.2e}")
-    assert ef < TOL[kind] and ea < TOL[kind]
+    # FP64: the phase-conditioning bar of the FP64 RS kernel (derived in
+    # test_gpu_edges.test_rs_full_4096_sampled): <= 3.5 eps k r between two
+    # independent FP64 evaluations of k r (3.6e5 rad at 1024^2 over 30 mm)
+    k_r = 2 * np.pi / wl * np.sqrt((g.nx * g.dx) ** 2 + (g.ny * g.dy) ** 2 + z * z)
+    tol = TOL[kind] if kind == "c64" else max(TOL[kind], 3.5 * k_r * np.finfo(float).eps)
+    say(f"  fwd {ef:.2e} adj {ea:.2e} (bar {tol:.1e})")
+    assert ef < tol and ea < tol
 
 
 VCZT_CASES = [
