@@ -93,3 +93,28 @@ def test_headline_whole_field_item(run, b):
         assert errs[k] <= FIELD_TOL, (k, errs[k])
     for k in ("grad_rs", "grad"):
         assert errs[k] <= GRAD_TOL, (k, errs[k])
+
+
+def test_overlapped_step_equals_serial_step():
+    """The benchmarked step runs the CZT forward on a second stream while
+    the RS forward and adjoint run on the launch stream; its outputs and
+    the accumulated phase gradient equal the serial step's bit for bit
+    (same kernels, same accumulation order), over several steps in a row."""
+    import torch
+    import bench
+    import paper_2310_08408_amd as lp
+    lp.library()
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        w, v, phi = bench.inputs(lp, torch, BATCH, torch.complex64)
+        ser = bench.Step(lp, torch, w, v, phi, overlap=False)
+        ovl = bench.Step(lp, torch, w, v, phi, overlap=True)
+        for k in range(3):
+            ser()
+            ovl()
+            torch.cuda.synchronize()
+            assert torch.equal(ser.u, ovl.u), k
+            assert torch.equal(ser.grad, ovl.grad), k
+            # the CZT output (the serial step writes it over the RS output)
+            assert torch.equal(ser.yc, ovl.yc), k
+    say(f"overlapped step = serial step over 3 steps (batch {BATCH})")
