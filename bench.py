@@ -123,11 +123,17 @@ def time_steps(torch, step, steps, warmup):
 
 
 def source_hash():
+    """Hash of the transform sources' code: comments and white space are
+    left out, so that a change of documentation keeps the measured traffic."""
     import hashlib
+    import re
     h = hashlib.sha1()
     for f in ("fft_engine.hpp", "fft_kernels.hpp"):
-        with open(os.path.join(ROOT, "paper_2310_08408_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2310_08408_amd", "csrc", f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -86,12 +86,9 @@ def per_dispatch(d: str, counter: str):
 
 
 def source_hash() -> str:
-    import hashlib
-    h = hashlib.sha1()
-    for f in ("fft_engine.hpp", "fft_kernels.hpp"):
-        with open(os.path.join(ROOT, "paper_2310_08408_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    """The stamp bench.py checks before it reports measured traffic."""
+    import bench
+    return bench.source_hash()
 
 
 def cmd_traffic(a):

@@ -10,8 +10,10 @@
 // through LDS, and the last stage hands natural-order outputs to a store
 // functor (global memory with cropping/post-multiplication, or LDS for a
 // following transform).  The twiddle table holds, for stage s, the values
-// W_{Ns R}^{r k} (r = 1..R-1, k = 0..Ns-1) at tw[off_s + (r-1) Ns + k], so
-// lanes with consecutive k read consecutive entries.
+// W_{Ns R}^{r k} (r < R, k < Ns): for FP64 at tw[off_s + (r-1) Ns + k], so
+// lanes with consecutive k read consecutive entries; for FP32 as one run per
+// thread, tw[off_s + k R + r] (Sched::twoff).  FP32 row passes may read them
+// from small LDS tables instead (TwLds).
 #pragma once
 
 #include <hip/hip_runtime.h>
