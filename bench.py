@@ -278,6 +278,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-uneven", action="store_true", help="skip the 96-setup uneven plan leg")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the batch 1 / 8 / 32 context timings")
     ap.add_argument("--only-uneven", action="store_true",
                     help="run only the 96-setup uneven plan leg and print its record (profiling)")
     ap.add_argument("--autotune", action="store_true", help="autotune the 96-setup plan at its first execution")
@@ -418,6 +419,23 @@ def main():
     del src, dst
     log(f"device copy of 512 MiB: {copy_gbs:.0f} GB/s")
 
+    # the same step at the other batch sizes of the protocol (B in {1, 8, 32});
+    # context only: the headline stays at --batch
+    sweep = None
+    if not a.no_sweep:
+        sweep = {}
+        for b in (1, 8, 32):
+            if b == a.batch:
+                continue
+            wb, vb, phib = inputs(lp, torch, b, torch.complex64)
+            sb = Step(lp, torch, wb, vb, phib, overlap=not a.serial)
+            wall_b, _, med_b = time_steps(torch, sb, 20, 5)
+            sweep[str(b)] = {"ms_per_step": wall_b * 1e3, "gpu_ms_per_step_median": med_b * 1e3,
+                             "value": 2 * b / wall_b, "unit": "grads/s"}
+            log(f"batch {b}: {wall_b * 1e3:.3f} ms/step -> {2 * b / wall_b:.1f} grads/s")
+            del sb, vb, phib
+        torch.cuda.empty_cache()
+
     uneven = None
     if not a.no_uneven:
         log("uneven 96-setup plan ...")
@@ -460,6 +478,7 @@ def main():
         "errors_vs_oracle": errs_oracle,
         "per_pass": per_pass,
         "uneven96": uneven,
+        "batch_sweep": sweep,
         "gpu_ms_per_step": gpu * 1e3,
         "gpu_ms_per_step_median": med * 1e3,
         "first_step_ms": t_setup * 1e3,

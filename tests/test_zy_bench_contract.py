@@ -35,5 +35,7 @@ def test_bench_prints_one_json_line_with_the_contract_fields():
     assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-12 and r["launches"] == 2 * 3
     assert max(d["errors_vs_fp64"].values()) < 1e-5
     assert 0 < r["valu_frac"] < 1 and r["valu"]["unit"] == "TFLOP/s"
+    sw = d["batch_sweep"]
+    assert set(sw) == {"1", "32"} and all(v["value"] > 0 and v["unit"] == "grads/s" for v in sw.values())
     u = d["uneven96"]
     assert u["ms_per_replay_pair"] > 0 and 0 < u["hbm_frac"] < 1 and u["graph_launches_per_direction"] == 1
