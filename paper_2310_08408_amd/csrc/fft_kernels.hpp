@@ -905,6 +905,20 @@ constexpr bool bluestein_interleaved() {
   return COL || tw_per_thread<T>();
 }
 
+// Row lines of a Bluestein pass stream their input and output without cache
+// retention (non-temporal) when the pass moves more than a cache could keep
+// for the next pass anyway (128 MiB, half the MALL): the chirp and filter
+// vectors, which every line reads, then stay cached (2048^2 at batch 8:
+// rows 229.7 -> 223.3 us).  Smaller passes keep normal accesses, so that a
+// following pass finds their output in the caches (the 96-setup plan lost
+// 2% with streamed rows at batch 1).  Column lines are shared by
+// neighbouring workgroups and never stream.
+template <typename T>
+inline bool bluestein_rows_streamed(bool col, int batch, int nlines, int n_in, int n_out) {
+  const double bytes = (double)batch * nlines * (double)(n_in + n_out) * sizeof(cx<T>);
+  return !col && bytes >= 128.0 * 1024 * 1024;
+}
+
 // PG = false: as for the row pass, an instance without the phase-gradient
 // epilogue (used for row lines; the column instance measured no better).
 // STAGE: the fused SLM stage of a plan setup (Slm) on the loads (first pass
@@ -917,7 +931,8 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, bluestein_in
                                                               const cx<T>* __restrict__ pre,
                                                               const cx<T>* __restrict__ chat,
                                                               const cx<T>* __restrict__ post, int tiles,
-                                                              const cx<T>* tw, PhaseGrad<T> pg, Slm<T> st) {
+                                                              const cx<T>* tw, PhaseGrad<T> pg, Slm<T> st,
+                                                              bool nt) {
   constexpr bool ILV = bluestein_interleaved<T, COL>();
   constexpr int LS = line_stride<S, C, ILV>();
   constexpr bool TL = !COL && ILV && conv_in_registers<S>() && tw_lds<T, S, C, ILV>();
@@ -934,7 +949,8 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, bluestein_in
   auto load = [&](int i) -> cx<T> {
     cx<T> v = czero<T>();
     if (valid && (EXACT || i < n_in)) {
-      v = cmul(in[line_off<COL>(li, b, l, i)], pre[i]);
+      const int64_t io = line_off<COL>(li, b, l, i);
+      v = cmul((COL || !nt) ? in[io] : load_stream(&in[io]), pre[i]);
       if constexpr (STAGE) {
         if (!st.adjoint) v = cmul(v, slm_factor(st, b, COL ? i : l, COL ? l : i));
       }
@@ -954,7 +970,10 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, bluestein_in
           return;
         }
       }
-      if (out) out[o] = g;
+      if (out) {
+        if (COL || !nt) out[o] = g;
+        else store_stream(&out[o], g);
+      }
       if constexpr (PG) {
         if (pg.grad) pre_pg.put(pg, i, j, o, g);
       }
@@ -968,28 +987,29 @@ hipError_t launch_bluestein_c(const cx<T>* in, cx<T>* out, Lines li, Lines lo, i
                               const cx<T>* pre, const cx<T>* chat, const cx<T>* post, int batch, const cx<T>* tw,
                               hipStream_t s, PhaseGrad<T> pg, Slm<T> st) {
   const int tiles = (nlines + C - 1) / C;
+  const bool nt = bluestein_rows_streamed<T>(COL, batch, nlines, n_in, n_out);
   constexpr bool can_half = S::rad[0] % 2 == 0 && S::rad[S::nst - 1] % 2 == 0;
   if constexpr (can_half) {
     if (2 * n_in == S::n && 2 * n_out == S::n && nlines % C == 0) {
       if (COL || pg.grad || STAGE)
         hipLaunchKernelGGL((k_bluestein<T, COL, S, C, true, true, true, STAGE>), dim3(tiles * batch),
                            dim3(C * S::threads), 0, s, in, out, li, lo, nlines, n_in, n_out, pre, chat, post, tiles, tw,
-                           pg, st);
+                           pg, st, nt);
       else
         hipLaunchKernelGGL((k_bluestein<T, COL, S, C, true, true, COL>), dim3(tiles * batch), dim3(C * S::threads),
-                           0, s, in, out, li, lo, nlines, n_in, n_out, pre, chat, post, tiles, tw, pg, st);
+                           0, s, in, out, li, lo, nlines, n_in, n_out, pre, chat, post, tiles, tw, pg, st, nt);
       return hipGetLastError();
     }
     if (2 * n_in <= S::n && 2 * n_out <= S::n) {
       hipLaunchKernelGGL((k_bluestein<T, COL, S, C, true, false, true, STAGE>), dim3(tiles * batch),
                          dim3(C * S::threads), 0, s, in, out, li, lo, nlines, n_in, n_out, pre, chat, post, tiles, tw,
-                         pg, st);
+                         pg, st, nt);
       return hipGetLastError();
     }
   }
   hipLaunchKernelGGL((k_bluestein<T, COL, S, C, false, false, true, STAGE>), dim3(tiles * batch),
                      dim3(C * S::threads), 0, s, in, out, li, lo, nlines, n_in, n_out, pre, chat, post, tiles, tw, pg,
-                     st);
+                     st, nt);
   return hipGetLastError();
 }
 
