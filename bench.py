@@ -213,12 +213,14 @@ def cpu_baseline(reps=3):
             "nproc": nproc, "cpu_model": cpu_model(), "reps": reps}, ref
 
 
-def uneven_leg(lp, torch, reps=5, autotune=False):
+def uneven_leg(lp, torch, reps=5, autotune=True):
     """The 96-setup uneven workload as one plan of chained setups (SLM ->
     RS(z) -> lens f -> CZT at z = f onto a 1024^2 window), one graph launch
-    per direction: time per forward+adjoint replay pair, setup-gradients/s,
-    and the model bytes (per-pass algorithmic reads + writes, fused stages
-    included) against HBM peak."""
+    per direction, by default with lines per workgroup and radix schedules
+    picked by the library's autotuner at the plan's first execution (outside
+    the timed replays): time per forward+adjoint replay pair,
+    setup-gradients/s, the model bytes (per-pass algorithmic reads + writes,
+    fused stages included) against HBM peak, and the tuner's choices."""
     import numpy as np
 
     import workloads
@@ -258,6 +260,9 @@ def uneven_leg(lp, torch, reps=5, autotune=False):
         e1.record()
         e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
+    # one report line per tuned pass shape: "... -> variant v (schedule ..., k per workgroup; timed) ..."
+    tuned = [l.split(" -> ")[0].replace("dev 0 ", "") + " -> " + l.split(" -> ")[1].split(";")[0] + ")"
+             for l in lp.prop_autotune_report().splitlines() if " -> " in l] if autotune else []
     plan.close()
     del keep
     return {"workload": "uneven96: 96 setups, N in {512,768,1024,1536,2048} drawn from the seed, lambda 450-700 nm, "
@@ -266,7 +271,7 @@ def uneven_leg(lp, torch, reps=5, autotune=False):
             "ms_per_replay_pair": ms, "setup_grads_per_s": 96e3 / ms, "model_bytes": model,
             "hbm_gbs": model / (ms * 1e-3) / 1e9, "hbm_frac": model / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "graph_launches_per_direction": 1, "replays": reps, "plan_build_and_warmup_s": build_s,
-            "autotuned": autotune}
+            "autotuned": autotune, "tuned_shapes": tuned}
 
 
 def main():
@@ -281,7 +286,9 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the batch 1 / 8 / 32 context timings")
     ap.add_argument("--only-uneven", action="store_true",
                     help="run only the 96-setup uneven plan leg and print its record (profiling)")
-    ap.add_argument("--autotune", action="store_true", help="autotune the 96-setup plan at its first execution")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="run the 96-setup plan on the built-in schedules (by default the library's autotuner "
+                         "picks lines per workgroup and radix schedules at the plan's first execution)")
     ap.add_argument("--no-trace", action="store_true", help="time without per-kernel events")
     ap.add_argument("--serial", action="store_true", help="run every pass of the step on one stream")
     ap.add_argument("--copy-probe", action="store_true",
@@ -298,7 +305,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if a.only_uneven:
-        print(json.dumps(uneven_leg(lp, torch, autotune=a.autotune)), flush=True)
+        print(json.dumps(uneven_leg(lp, torch, autotune=not a.no_autotune)), flush=True)
         return
 
     # ---- batched FP32 path -------------------------------------------------
@@ -439,7 +446,7 @@ def main():
     uneven = None
     if not a.no_uneven:
         log("uneven 96-setup plan ...")
-        uneven = uneven_leg(lp, torch, autotune=a.autotune)
+        uneven = uneven_leg(lp, torch, autotune=not a.no_autotune)
         log(f"uneven 96: {uneven['ms_per_replay_pair']:.2f} ms per forward+adjoint replay pair, "
             f"{uneven['setup_grads_per_s']:.0f} setup-gradients/s, {uneven['hbm_frac']:.3f} of HBM peak")
 
