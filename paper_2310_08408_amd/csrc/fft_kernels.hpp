@@ -696,6 +696,42 @@ hipError_t launch_rs_cols_c(cx<T>* W, int64_t bstride, int ncols, int n_valid, c
   return hipGetLastError();
 }
 
+// Untuned choice among the bit-identical lines-per-workgroup variants of a
+// non-persistent RS column pass: halve the lines (variant 1, then 2) while
+// the pass has fewer than two workgroups per CU, so that small batch-1
+// passes fill the chip.  Measured at batch 1 by the autotuner: 1024 points
+// 10.7 -> 7.4 us (8 -> 2 lines), 1536 points 18.8 -> 11.3 us (4 -> 2
+// lines).  The persistent pass keeps variant 0.
+template <typename T, class S>
+int rs_cols_fill_variant_s(int ncols, int n_valid, int batch) {
+  using CF = Cfg<T, S, true>;
+  if constexpr (!CF::fits) {
+    return 0;
+  } else {
+    constexpr int C0 = CF::C, C1 = variant_lines<S, C0>(1), C2 = variant_lines<S, C0>(2);
+    if constexpr (cols_persistent<T, S>()) {
+      if (2 * n_valid == S::n && ncols % C0 == 0) return 0;
+    }
+    const int64_t want = 2 * (int64_t)cu_count();
+    auto groups = [&](int c) { return (int64_t)((ncols + c - 1) / c) * batch; };
+    if (C1 >= C0 || groups(C0) >= want) return 0;
+    if (C2 >= C1 || groups(C1) >= want) return 1;
+    return 2;
+  }
+}
+
+template <typename T>
+int rs_cols_fill_variant(int My, int ncols, int n_valid, int batch) {
+  switch (My) {
+#define LP_CASE(N, ...) \
+  case N: return rs_cols_fill_variant_s<T, SchedOf<T, Sched<__VA_ARGS__>>>(ncols, n_valid, batch);
+    LP_LENGTHS(LP_CASE)
+#undef LP_CASE
+    default:
+      return 0;
+  }
+}
+
 template <typename T, class S>
 hipError_t launch_rs_cols_s(cx<T>* W, int64_t bstride, int ncols, int n_valid, const cx<T>* Sq, int Mx, bool conj_spec,
                             int batch, const cx<T>* tw, hipStream_t s, int variant) {

@@ -9,4 +9,5 @@ template hipError_t launch_mix2_cols<float>(int, const cx<float>*, const cx<floa
                                          const cx<float>*, int, float, const cx<float>*, int, float, bool, int, int,
                                          const cx<float>*, hipStream_t, int);
 template int col_pass_lines<float>(int, int, int);
+template int rs_cols_fill_variant<float>(int, int, int, int);
 }  // namespace lp

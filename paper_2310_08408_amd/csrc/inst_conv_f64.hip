@@ -9,4 +9,5 @@ template hipError_t launch_mix2_cols<double>(int, const cx<double>*, const cx<do
                                          const cx<double>*, int, double, const cx<double>*, int, double, bool, int, int,
                                          const cx<double>*, hipStream_t, int);
 template int col_pass_lines<double>(int, int, int);
+template int rs_cols_fill_variant<double>(int, int, int, int);
 }  // namespace lp

@@ -105,6 +105,11 @@ constexpr int kSchedVariants = 2;
 // (Bluestein rows) at length n, 0 if unsupported.
 template <typename T>
 int col_pass_lines(int kind, int n, int variant);
+// Variant of an RS column pass (length My, ncols columns of n_valid rows)
+// when nothing is tuned: bit-identical to variant 0, with fewer lines per
+// workgroup where the pass would otherwise leave CUs idle.
+template <typename T>
+int rs_cols_fill_variant(int My, int ncols, int n_valid, int batch);
 // The schedule a variant runs: 0 built-in, 1 alternative.
 inline int variant_sched(int variant) { return variant / kColVariants; }
 

@@ -521,7 +521,9 @@ static int col_variant(int dev, int kind, int n, int nlines, int n_in, int n_out
     *variant = it->second.variant;
     return PROP_OK;
   }
-  *variant = 0;
+  // untuned: the built-in variant (for RS column passes the bit-identical
+  // one that fills the chip, rs_cols_fill_variant)
+  *variant = kind == TUNE_RS_COLS ? rs_cols_fill_variant<T>(n, nlines, n_in, batch) : 0;
   if (!tune_enabled() || capturing(s)) return PROP_OK;
   TuneRecord rec;
   rec.arch = device_arch(dev);
