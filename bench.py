@@ -215,8 +215,8 @@ def cpu_baseline(reps=3):
 
 def uneven_leg(lp, torch, reps=5, autotune=True):
     """The 96-setup uneven workload as one plan of chained setups (SLM ->
-    RS(z) -> lens f -> CZT at z = f onto a 1024^2 window), one graph launch
-    per direction, by default with lines per workgroup and radix schedules
+    RS(z) -> lens f -> CZT at z = f onto a 1024^2 window), forward and
+    adjoint as one graph launch (prop_plan_step), by default with lines per workgroup and radix schedules
     picked by the library's autotuner at the plan's first execution (outside
     the timed replays): time per forward+adjoint replay pair,
     setup-gradients/s, the model bytes (per-pass algorithmic reads + writes,
@@ -250,13 +250,13 @@ def uneven_leg(lp, torch, reps=5, autotune=True):
         warnings.simplefilter("ignore")
         plan = lp.Plan(objs, graph=True, autotune=autotune)
         for _ in range(2):
-            plan.forward(); plan.adjoint()
+            plan.step()
         torch.cuda.synchronize()
         build_s = time.perf_counter() - t0
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(reps):
-            plan.forward(); plan.adjoint()
+            plan.step()
         e1.record()
         e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
@@ -270,7 +270,7 @@ def uneven_leg(lp, torch, reps=5, autotune=True):
                         "FP64 phases; forward+adjoint with SLM phase and input gradients",
             "ms_per_replay_pair": ms, "setup_grads_per_s": 96e3 / ms, "model_bytes": model,
             "hbm_gbs": model / (ms * 1e-3) / 1e9, "hbm_frac": model / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "graph_launches_per_direction": 1, "replays": reps, "plan_build_and_warmup_s": build_s,
+            "graph_launches_per_step": 1, "replays": reps, "plan_build_and_warmup_s": build_s,
             "autotuned": autotune, "tuned_shapes": tuned}
 
 

@@ -439,11 +439,17 @@ int prop_last_device_error(void);
  * vectors and twiddle tables (pinned in the cache for the plan's lifetime:
  * neither eviction nor prop_cache_clear frees them), and allocates all
  * workspace, so that
- * prop_plan_forward / prop_plan_adjoint only enqueue kernels: they neither
- * allocate nor synchronise, and may be captured into a caller's hipGraph.
- * With PROP_PLAN_GRAPH the plan captures its own forward and adjoint once
- * (setups spread over up to 4 parallel branches) and afterwards replays each
- * as a single hipGraphLaunch on the caller's stream.
+ * prop_plan_forward / prop_plan_adjoint / prop_plan_step only enqueue
+ * kernels: they neither allocate nor synchronise, and may be captured into a
+ * caller's hipGraph.  prop_plan_step is prop_plan_forward followed by
+ * prop_plan_adjoint (the same kernels in the same order, so the same bits),
+ * for callers whose output gradients gout are fixed before the step (the
+ * paper's batches evaluate forward and gradient of every setup in one
+ * step).  With PROP_PLAN_GRAPH the plan captures its own forward, adjoint
+ * and step once each, on first use (setups spread over up to 4 parallel
+ * branches; in the step every forward branch joins before the adjoint
+ * branches start), and afterwards replays each as a single hipGraphLaunch
+ * on the caller's stream.
  *
  * Per setup (one propagator call, or one RS -> lens -> CZT chain, on
  * `batch` fields), with the stage factor f = exp(i phase) exp(-i k r^2 /
@@ -474,8 +480,9 @@ int prop_last_device_error(void);
  */
 enum { PROP_OP_RS = 0, PROP_OP_CZT = 1, PROP_OP_VRS = 2, PROP_OP_VCZT = 3, PROP_OP_RS_CZT = 4 };
 #define PROP_PLAN_GRAPH 1u
-/* PROP_PLAN_AUTOTUNE: the first prop_plan_forward and the first
- * prop_plan_adjoint run eagerly with the autotuner on (see
+/* PROP_PLAN_AUTOTUNE: the first forward and the first adjoint (through
+ * prop_plan_forward, prop_plan_adjoint or prop_plan_step) run eagerly with
+ * the autotuner on (see
  * prop_autotune_report); they allocate scratch memory and synchronise the
  * stream.  Later calls (and the captured graph) use the chosen variants. */
 #define PROP_PLAN_AUTOTUNE 2u
@@ -506,6 +513,7 @@ typedef struct prop_plan prop_plan;
 int prop_plan_create(prop_dtype t, const prop_setup* setups, int32_t n, uint32_t flags, prop_plan** plan);
 int prop_plan_forward(prop_plan* plan, void* stream);
 int prop_plan_adjoint(prop_plan* plan, void* stream);
+int prop_plan_step(prop_plan* plan, void* stream);
 void prop_plan_destroy(prop_plan* plan);
 
 /* ------------------------------------------------------------- tracing --

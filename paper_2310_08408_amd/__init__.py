@@ -930,6 +930,11 @@ class Plan:
         with torch.cuda.device(self.device):
             _lib.check("prop_plan_adjoint", library().prop_plan_adjoint(self._h, self._stream()))
 
+    def step(self):
+        """forward() then adjoint(), as one graph launch for a graph plan."""
+        with torch.cuda.device(self.device):
+            _lib.check("prop_plan_step", library().prop_plan_step(self._h, self._stream()))
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             library().prop_plan_destroy(self._h)

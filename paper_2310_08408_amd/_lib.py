@@ -89,6 +89,7 @@ SIGNATURES = {
     "prop_plan_create": (c_int32, [c_int32, P, c_int32, ctypes.c_uint32, ctypes.POINTER(c_void_p)]),
     "prop_plan_forward": (c_int32, [P, P]),
     "prop_plan_adjoint": (c_int32, [P, P]),
+    "prop_plan_step": (c_int32, [P, P]),
     "prop_plan_destroy": (None, [P]),
     "prop_trace_enable": (None, [c_int32]),
     "prop_trace_read": (c_int32, [P, c_int32]),

@@ -1260,7 +1260,7 @@ struct prop_plan {
   std::vector<hipStream_t> br;  // capture streams (graph mode)
   hipEvent_t fork = nullptr;
   std::vector<hipEvent_t> join;
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};  // forward, adjoint, forward + adjoint
   bool tuned[2] = {false, false};  // PROP_PLAN_AUTOTUNE: first execution tunes
   std::vector<int> order;          // graph mode: setups by decreasing cost
   lp::Pins pins;                   // cached tables this plan's kernels address
@@ -1511,25 +1511,40 @@ static int plan_enqueue(prop_plan* p, bool adjoint, hipStream_t st, bool branche
   return PROP_OK;
 }
 
-static int plan_run(prop_plan* p, bool adjoint, hipStream_t st) {
-  if ((p->flags & PROP_PLAN_AUTOTUNE) && !p->tuned[adjoint ? 1 : 0] && !capturing(st)) {
-    // first execution runs eagerly with the autotuner on; a graph is
-    // captured afterwards with the chosen variants
-    t_tune_request = true;
-    const int r = plan_enqueue(p, adjoint, st, false);
-    t_tune_request = false;
-    LP_RET(r);
-    p->tuned[adjoint ? 1 : 0] = true;
-    return r;
+// mode 0: forward, 1: adjoint, 2: forward then adjoint (one graph with
+// PROP_PLAN_GRAPH; the adjoint's branches start once every forward branch
+// has joined, exactly as two calls in a row)
+static int plan_run(prop_plan* p, int mode, hipStream_t st) {
+  if ((p->flags & PROP_PLAN_AUTOTUNE) && !capturing(st)) {
+    // first execution of a direction runs eagerly with the autotuner on; a
+    // graph is captured afterwards with the chosen variants
+    const bool fwd_untuned = mode != 1 && !p->tuned[0], adj_untuned = mode != 0 && !p->tuned[1];
+    if (fwd_untuned || adj_untuned) {
+      for (int dir = 0; dir < 2; ++dir) {
+        if ((dir == 0 && mode == 1) || (dir == 1 && mode == 0)) continue;
+        t_tune_request = !p->tuned[dir];
+        const int r = plan_enqueue(p, dir == 1, st, false);
+        t_tune_request = false;
+        LP_RET(r);
+        p->tuned[dir] = true;
+      }
+      return PROP_OK;
+    }
   }
-  if (!(p->flags & PROP_PLAN_GRAPH)) return plan_enqueue(p, adjoint, st, false);
-  hipGraphExec_t& ex = p->gexec[adjoint ? 1 : 0];
+  if (!(p->flags & PROP_PLAN_GRAPH)) {
+    if (mode != 1) LP_RET(plan_enqueue(p, false, st, false));
+    if (mode != 0) LP_RET(plan_enqueue(p, true, st, false));
+    return PROP_OK;
+  }
+  hipGraphExec_t& ex = p->gexec[mode];
   if (!ex) {
     // capture on the first branch stream, forking to the others
     hipStream_t origin = p->br[0];
     hipGraph_t graph = nullptr;
     LP_TRY(hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal));
-    int r = plan_enqueue(p, adjoint, origin, p->nbranch > 1);
+    int r = PROP_OK;
+    if (mode != 1) r = plan_enqueue(p, false, origin, p->nbranch > 1);
+    if (r >= 0 && mode != 0) r = plan_enqueue(p, true, origin, p->nbranch > 1);
     hipError_t e = hipStreamEndCapture(origin, &graph);
     if (r < 0) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -2501,20 +2516,26 @@ int prop_plan_create(prop_dtype t, const prop_setup* setups, int32_t n, uint32_t
 int prop_plan_forward(prop_plan* plan, void* stream) {
   if (!plan) return PROP_ENULL;
   CtxLock lk;
-  return plan_run(plan, false, (hipStream_t)stream);
+  return plan_run(plan, 0, (hipStream_t)stream);
 }
 
 int prop_plan_adjoint(prop_plan* plan, void* stream) {
   if (!plan) return PROP_ENULL;
   CtxLock lk;
-  return plan_run(plan, true, (hipStream_t)stream);
+  return plan_run(plan, 1, (hipStream_t)stream);
+}
+
+int prop_plan_step(prop_plan* plan, void* stream) {
+  if (!plan) return PROP_ENULL;
+  CtxLock lk;
+  return plan_run(plan, 2, (hipStream_t)stream);
 }
 
 void prop_plan_destroy(prop_plan* plan) {
   if (!plan) return;
   CtxLock lk;
   (void)hipDeviceSynchronize();
-  for (int k = 0; k < 2; ++k)
+  for (int k = 0; k < 3; ++k)
     if (plan->gexec[k]) (void)hipGraphExecDestroy(plan->gexec[k]);
   for (auto& b : plan->work) (void)hipFree(b.p);
   for (auto& b : plan->gbuf) (void)hipFree(b.p);

@@ -1,6 +1,7 @@
 """Batched uneven setups through the plan API (one graph launch per
-direction): every setup's results equal the single calls and the FP64 oracle
-(paper: Results, batches of candidate setups evaluated per step)."""
+direction, or per forward+adjoint step): every setup's results equal the
+single calls and the FP64 oracle (paper: Results, batches of candidate
+setups evaluated per step)."""
 import math
 import warnings
 import sys
@@ -135,8 +136,8 @@ def test_uneven_rs_lens_czt_plans(lp, graph):
 def uneven96(lp):
     """The 96-setup uneven workload (N in {512..2048}, 1024^2 window) as one
     plan of chained setups -- SLM -> RS(z) -> lens f -> CZT at z = f -- with
-    one graph launch per direction; timed over replays, then every setup's
-    results copied to the host."""
+    forward and adjoint as one graph launch (prop_plan_step); timed over
+    replays, then every setup's results copied to the host."""
     import time
     import torch
     setups = _uneven(0, 96, workloads.UNEVEN_SIZES)
@@ -157,15 +158,16 @@ def uneven96(lp):
         torch.cuda.synchronize()
         say(f"  chained plan built (spectra, chirps) in {time.perf_counter() - t0:.2f} s")
         for _ in range(2):
-            plan.forward(); plan.adjoint()
+            plan.step()
         torch.cuda.synchronize()
         reps = 5
         t0 = time.perf_counter()
         for _ in range(reps):
-            plan.forward(); plan.adjoint()
+            plan.step()
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / reps
-        say(f"  96 setups forward+adjoint: {ms:.2f} ms per replay pair ({96e3 / ms:.1f} setup-gradients/s)")
+        say(f"  96 setups forward+adjoint: {ms:.2f} ms per step, one graph launch "
+            f"({96e3 / ms:.1f} setup-gradients/s)")
     h = lambda t: t.cpu().numpy()[0]
     res = [dict(w=k["w"], gy_host=k["gy_host"], y=h(c["y"]), gv=h(c["gv"]), gphi=h(c["gphi"])) for k, c in
            zip(keep, chain)]
@@ -183,6 +185,38 @@ def _oracle_chain(w, gy):
     y = oracle.czt_propagate(oracle.rs_propagate(u, g, wl, w["z"]) * _lens(g, wl, w["f"], -1), g, win, wl, w["f"])
     gu = oracle.rs_adjoint(oracle.czt_adjoint(gy, g, win, wl, w["f"]) * _lens(g, wl, w["f"], +1), g, wl, w["z"])
     return y, gu * np.exp(-1j * phi), oracle.phase_grad(gu, u)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_plan_step_equals_forward_then_adjoint(lp, graph):
+    """prop_plan_step (forward then adjoint; one graph launch for a graph
+    plan) gives the results of prop_plan_forward followed by
+    prop_plan_adjoint bit for bit, over three replays, on chained setups of
+    uneven sizes."""
+    import torch
+    setups = _uneven(5, 6, (48, 64, 96, 130))
+    rng = np.random.default_rng(5)
+    keep = []
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        for w in setups:
+            w["w0"] = 0.6e-3
+            w["window"] = win = Grid.square(40, 40 * 0.5e-6)
+            v = lp.prop_source_gaussian(w["grid"], w["w0"], w["wavelength"])
+            phi = torch.tensor(w["phase"][None], dtype=torch.float32, device="cuda")
+            gy = torch.from_numpy(workloads.random_field(rng, (1, win.ny, win.nx)).astype(np.complex64)).cuda()
+            keep.append(dict(w=w, v=v, phi=phi, gy=gy, y=torch.empty_like(gy)))
+        p1, o1 = _build_chain(lp, torch, keep, graph)
+        p2, o2 = _build_chain(lp, torch, keep, graph)
+        for rep in range(3):
+            p1.forward(); p1.adjoint()
+            p2.step()
+            torch.cuda.synchronize()
+            for a, b in zip(o1, o2):
+                for name in ("y", "gv", "gphi"):
+                    assert torch.equal(a[name], b[name]), (rep, name)
+    say(f"graph={graph}: plan step = forward + adjoint bit for bit over {len(keep)} setups, 3 replays")
+    p1.close(); p2.close()
 
 
 @pytest.mark.parametrize("part", range(4))

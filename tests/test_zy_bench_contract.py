@@ -38,4 +38,4 @@ def test_bench_prints_one_json_line_with_the_contract_fields():
     sw = d["batch_sweep"]
     assert set(sw) == {"1", "32"} and all(v["value"] > 0 and v["unit"] == "grads/s" for v in sw.values())
     u = d["uneven96"]
-    assert u["ms_per_replay_pair"] > 0 and 0 < u["hbm_frac"] < 1 and u["graph_launches_per_direction"] == 1
+    assert u["ms_per_replay_pair"] > 0 and 0 < u["hbm_frac"] < 1 and u["graph_launches_per_step"] == 1
