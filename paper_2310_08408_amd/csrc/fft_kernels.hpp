@@ -255,6 +255,49 @@ __device__ __forceinline__ cx<T> slm_adjoint_store(const Slm<T>& st, const Phase
 
 template <typename T> __device__ __forceinline__ cx<T> czero() { return mk<T>(T(0), T(0)); }
 
+// The fused SLM stage on the stores of an exact-half inverse row pass,
+// with its phase loaded when the kernel starts (as PhaseGradPre does for the
+// phase-gradient epilogue) at the indices the last stage stores (j + r n/RL,
+// r < RL/2), so that the load's HBM latency overlaps the transform.  The
+// store then forms the same products as slm_adjoint_store.  ON = false:
+// slm_adjoint_store at the store.
+template <typename T, class S, bool ON>
+struct SlmPre {
+  using HO = HalfOut<S>;
+  static constexpr int nr = HO::nr, P = ON ? HO::R : 1;
+  T ph[P];
+  __device__ __forceinline__ void load(const Slm<T>& st, const PhaseGrad<T>& pg, int b, int row, int j,
+                                       int64_t frow) {
+    if constexpr (ON) {
+      if (HO::stores(j)) {
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+          const int i = HO::index(j, r);
+          ph[r] = st.phase ? st.phase[b * st.pbs + (int64_t)row * st.nx + i] : T(0);
+        }
+      }
+    }
+  }
+  __device__ __forceinline__ void store(const Slm<T>& st, const PhaseGrad<T>& pg, cx<T>* out, int b, int row,
+                                        int i, int j, int64_t o, cx<T> g) const {
+    if constexpr (ON) {
+      const int r = (i - j) / nr;
+      cx<T> f = mk<T>(T(1), T(0));
+      if (st.phase) {
+        T sn, cs;
+        slm_sincos<T>(ph[r], &sn, &cs);
+        f = mk<T>(cs, sn);
+      }
+      if (st.lx) f = cmul(f, cmul(st.lx[i], st.ly[row]));
+      const cx<T> gv = cmulc(g, f);
+      if (out) out[o] = gv;
+      if (pg.grad) pg.put(o, gv);
+    } else {
+      slm_adjoint_store(st, pg, out, b, row, i, o, g);
+    }
+  }
+};
+
 // address of element i of line l of batch item b
 template <bool COL>
 __device__ __forceinline__ int64_t line_off(const Lines& L, int b, int l, int i) {
@@ -396,11 +439,13 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
     };
     PhaseGradPre<T, S, PG && !STAGE && pg_preload<T, S, EXACT && HALF>()> pre_pg;
     pre_pg.load(pg, j, [&](int i) { return frow + i; });
+    SlmPre<T, S, STAGE && pg_preload<T, S, EXACT && HALF>()> pre_st;
+    if constexpr (STAGE) pre_st.load(st, pg, b, y, j, frow);
     auto store = [&](int i, cx<T> v) {
       if (valid && (EXACT || i < n_io)) {
         const cx<T> g = cscale(v, scale);
         if constexpr (STAGE) {
-          slm_adjoint_store(st, pg, out, b, y, i, frow + i, g);
+          pre_st.store(st, pg, out, b, y, i, j, frow + i, g);
         } else {
           if (out) out[frow + i] = g;
           if constexpr (PG) {
