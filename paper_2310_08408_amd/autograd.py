@@ -8,7 +8,10 @@ dL/dphi = Im(g_U conj(U)) and g_V = g_U exp(-i phi).
 
 RS and CZT also accept the distance z as a 0-d float64 tensor; when it
 requires grad, backward returns dL/dz (rs_grad_z / czt_grad_z summed over
-the batch, since one z is shared by all batch items).
+the batch, since one z is shared by all batch items).  The propagators take
+z by value, so a device tensor is read back once per call; a caller that
+already holds its value passes it as the optional last argument `zv`
+(then z is not read).
 """
 from __future__ import annotations
 
@@ -27,13 +30,14 @@ def _zval(z):
 
 class RS(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, u, grid, wavelength, z):
+    def forward(ctx, u, grid, wavelength, z, zv=None):
         u = u.contiguous()
-        ctx.args = (grid, wavelength, _zval(z))
+        zv = _zval(z) if zv is None else float(zv)
+        ctx.args = (grid, wavelength, zv)
         ctx.z_tensor = isinstance(z, torch.Tensor)
         ctx.z_shape = z.shape if ctx.z_tensor else None
         ctx.save_for_backward(u)
-        return rs_propagate(u, grid, wavelength, _zval(z))
+        return rs_propagate(u, grid, wavelength, zv)
 
     @staticmethod
     def backward(ctx, g):
@@ -44,17 +48,18 @@ class RS(torch.autograd.Function):
         if ctx.z_tensor and ctx.needs_input_grad[3]:
             gz = prop_sum_items(rs_grad_z(u, g, grid, wl, z)).reshape(ctx.z_shape)
         gu = rs_adjoint(g, grid, wl, z) if ctx.needs_input_grad[0] else None
-        return gu, None, None, gz
+        return gu, None, None, gz, None
 
 
 class CZT(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, u, grid_in, window, wavelength, z):
+    def forward(ctx, u, grid_in, window, wavelength, z, zv=None):
         u = u.contiguous()
-        ctx.args = (grid_in, window, wavelength, _zval(z))
+        zv = _zval(z) if zv is None else float(zv)
+        ctx.args = (grid_in, window, wavelength, zv)
         ctx.z_tensor = isinstance(z, torch.Tensor)
         ctx.z_shape = z.shape if ctx.z_tensor else None
-        y = czt_propagate(u, grid_in, window, wavelength, _zval(z))
+        y = czt_propagate(u, grid_in, window, wavelength, zv)
         ctx.save_for_backward(u, y)
         return y
 
@@ -67,7 +72,7 @@ class CZT(torch.autograd.Function):
         if ctx.z_tensor and ctx.needs_input_grad[4]:
             gz = prop_sum_items(czt_grad_z(u, g, gi, win, wl, z, u_out=y)).reshape(ctx.z_shape)
         gu = czt_adjoint(g, gi, win, wl, z) if ctx.needs_input_grad[0] else None
-        return gu, None, None, None, gz
+        return gu, None, None, None, gz, None
 
 
 class VRS(torch.autograd.Function):

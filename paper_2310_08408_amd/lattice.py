@@ -76,8 +76,15 @@ class LatticeParams:
         return out
 
 
-def _zval(z):
-    return float(z.detach()) if isinstance(z, torch.Tensor) else float(z)
+def _host_distances(p: LatticeParams):
+    """Host values of (z1, z2) per link.  The distances may be 0-d device
+    tensors; they are read back together in one transfer, since every
+    separate read waits for the device queue to drain."""
+    zs = list(p.z1) + list(p.z2)
+    ts = [z for z in zs if isinstance(z, torch.Tensor)]
+    vals = iter(torch.stack([t.detach().to(torch.float64).reshape(()) for t in ts]).cpu().tolist() if ts else [])
+    host = [next(vals) if isinstance(z, torch.Tensor) else float(z) for z in zs]
+    return host[:len(p.z1)], host[len(p.z1):]
 
 
 class Lattice:
@@ -104,21 +111,22 @@ class Lattice:
         self.eps, self.beta_sted, self.beta_soft = eps, beta_sted, beta_soft
 
     # ------------------------------------------------------------ elements
-    def _link(self, l, fld, wl, p):
+    def _link(self, l, fld, wl, p, zh):
         if fld is None:
             return None
         ex, ey = fld
         g = self.grid
+        z1, z2 = zh[0][l], zh[1][l]
         if self.unit[l]:
             k = self.unit_index[l]
             ex = Modulate.apply(ex, p.phi[k][0])
             ey = Modulate.apply(ey, p.phi[k][1])
-            ex = RS.apply(ex, g, wl, p.z1[l])
-            ey = RS.apply(ey, g, wl, p.z1[l])
+            ex = RS.apply(ex, g, wl, p.z1[l], z1)
+            ey = RS.apply(ey, g, wl, p.z1[l], z1)
             ex, ey = WavePlates.apply(ex, ey, p.wp[k])
-        if _zval(p.z2[l]) > 0:
-            ex = RS.apply(ex, g, wl, p.z2[l])
-            ey = RS.apply(ey, g, wl, p.z2[l])
+        if z2 > 0:
+            ex = RS.apply(ex, g, wl, p.z2[l], z2)
+            ey = RS.apply(ey, g, wl, p.z2[l], z2)
         return ex, ey
 
     @staticmethod
@@ -129,21 +137,24 @@ class Lattice:
         out = BeamSplitter.apply(2, a is not None, b is not None, alpha, *planes)
         return tuple(out[:2]), tuple(out[2:])
 
-    def detector_fields(self, sources, wl, p):
+    def detector_fields(self, sources, wl, p, zh=None):
         """Transverse fields arriving at the R + C detectors for one beam;
-        sources: R + C entries (ex, ey) [B, ny, nx] or None (dark)."""
+        sources: R + C entries (ex, ey) [B, ny, nx] or None (dark); zh: the
+        host values of p's distances (read from p when not given)."""
         R, C = self.R, self.C
         if len(sources) != R + C:
             raise ValueError(f"need {R + C} sources")
+        if zh is None:
+            zh = _host_distances(p)
         h = {(r, 0): sources[r] for r in range(R)}
         v = {(0, c): sources[R + c] for c in range(C)}
         for r in range(R):
             for c in range(C):
-                a = self._link(h_link(R, C, r, c), h[(r, c)], wl, p)
-                b = self._link(v_link(R, C, r, c), v[(r, c)], wl, p)
+                a = self._link(h_link(R, C, r, c), h[(r, c)], wl, p, zh)
+                b = self._link(v_link(R, C, r, c), v[(r, c)], wl, p, zh)
                 h[(r, c + 1)], v[(r + 1, c)] = self._split(a, b, p.alpha[r * C + c])
-        det = [self._link(h_link(R, C, r, C), h[(r, C)], wl, p) for r in range(R)]
-        det += [self._link(v_link(R, C, R, c), v[(R, c)], wl, p) for c in range(C)]
+        det = [self._link(h_link(R, C, r, C), h[(r, C)], wl, p, zh) for r in range(R)]
+        det += [self._link(v_link(R, C, R, c), v[(R, c)], wl, p, zh) for c in range(C)]
         return det
 
     def forward(self, beams, p: LatticeParams):
@@ -151,9 +162,10 @@ class Lattice:
         is the STED depletion beam.  Returns (objective [B] float64,
         per-detector losses [B, R + C] float64), differentiable in p."""
         focused = []
+        zh = _host_distances(p)
         for beam in beams:
             wl = beam["wavelength"]
-            det = self.detector_fields(beam["sources"], wl, p)
+            det = self.detector_fields(beam["sources"], wl, p, zh)
             outs = []
             for k, d in enumerate(det):
                 if d is None:
