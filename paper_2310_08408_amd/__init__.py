@@ -470,9 +470,10 @@ def _items(t, npix):
     return t.numel() // npix
 
 
-def prop_waveplate_batched(ex, ey, params):
+def prop_waveplate_batched(ex, ey, params, out=None):
     """Wave plates with one (eta, theta) per batch item: params float64
-    [batch, 2] on the fields' device.  Returns (ox, oy)."""
+    [batch, 2] on the fields' device.  Returns (ox, oy), written into
+    out = (ox, oy) when given."""
     lib = library()
     ex, ey, params = ex.contiguous(), ey.contiguous(), params.contiguous()
     _field(ex, "ex")
@@ -483,7 +484,10 @@ def prop_waveplate_batched(ex, ey, params):
     _arg(params, "params", ex, dtype=torch.float64)
     if params.numel() != 2 * batch:
         raise ValueError("params must be float64 [batch, 2]")
-    ox, oy = torch.empty_like(ex), torch.empty_like(ey)
+    if out is None:
+        ox, oy = torch.empty_like(ex), torch.empty_like(ey)
+    else:
+        ox, oy = _arg(out[0], "out[0]", ex, pl, batch), _arg(out[1], "out[1]", ex, pl, batch)
     with torch.cuda.device(ex.device):
         st = lib.prop_waveplate_batched(_dtype_code(ex), _ptr(ex), _ptr(ey), _ptr(ox), _ptr(oy), _ptr(params), npix,
                                         batch, _stream(ex))
@@ -491,10 +495,11 @@ def prop_waveplate_batched(ex, ey, params):
     return ox, oy
 
 
-def prop_waveplate_batched_adjoint(gx, gy, ex, ey, params, grad=True, shared_input=False):
+def prop_waveplate_batched_adjoint(gx, gy, ex, ey, params, grad=True, shared_input=False, out=None):
     """Returns (g_ex, g_ey, dparams[batch, 2] float64 or None).  With
     shared_input (the plate was fed one field on both components) it returns
-    (g_A, None, dparams), g_A = g_ex + g_ey."""
+    (g_A, None, dparams), g_A = g_ex + g_ey.  out = (g_ex, g_ey) (g_ey None
+    with shared_input) receives the field gradients when given."""
     lib = library()
     gx, gy, params = gx.contiguous(), gy.contiguous(), params.contiguous()
     _field(gx, "gx")
@@ -505,8 +510,12 @@ def prop_waveplate_batched_adjoint(gx, gy, ex, ey, params, grad=True, shared_inp
     _arg(params, "params", gx, dtype=torch.float64)
     if params.numel() != 2 * batch:
         raise ValueError("params must be float64 [batch, 2]")
-    gex = torch.empty_like(gx)
-    gey = None if shared_input else torch.empty_like(gy)
+    if out is None:
+        gex = torch.empty_like(gx)
+        gey = None if shared_input else torch.empty_like(gy)
+    else:
+        gex = _arg(out[0], "out[0]", gx, pl, batch)
+        gey = None if shared_input else _arg(out[1], "out[1]", gx, pl, batch)
     dp = torch.empty((batch, 2), dtype=torch.float64, device=gx.device) if grad else None
     if grad:
         ex, ey = ex.contiguous(), ey.contiguous()
@@ -524,10 +533,11 @@ def _port(planes):
     return None if planes is None else [t.contiguous() for t in planes]
 
 
-def prop_beam_splitter(a, b, alpha):
+def prop_beam_splitter(a, b, alpha, out=None):
     """Beam splitter with one mixing angle per batch item (alpha float64
     [batch]): a, b are lists of component planes [batch, ny, nx] (or None:
-    dark port).  Returns (c, d) as lists of planes."""
+    dark port).  Returns (c, d) as lists of planes, written into
+    out = (c, d) when given."""
     lib = library()
     a, b = _port(a), _port(b)
     if not (a or b):
@@ -545,8 +555,15 @@ def prop_beam_splitter(a, b, alpha):
     _arg(alpha, "alpha", ref, dtype=torch.float64)
     if alpha.numel() != batch:
         raise ValueError("alpha must be float64 [batch]")
-    c = [torch.empty_like(ref) for _ in range(ncomp)]
-    d = [torch.empty_like(ref) for _ in range(ncomp)]
+    if out is None:
+        c = [torch.empty_like(ref) for _ in range(ncomp)]
+        d = [torch.empty_like(ref) for _ in range(ncomp)]
+    else:
+        c, d = list(out[0]), list(out[1])
+        if len(c) != ncomp or len(d) != ncomp:
+            raise ValueError(f"out: {ncomp} planes per output port expected")
+        for k, t in enumerate(c + d):
+            _arg(t, f"out plane {k}", ref, pl, batch)
     with torch.cuda.device(ref.device):
         st = lib.prop_beam_splitter(_dtype_code(ref), _ptr_array(a) if a else None, _ptr_array(b) if b else None,
                                     _ptr_array(c), _ptr_array(d), ncomp, _ptr(alpha), npix, batch, _stream(ref))
@@ -554,9 +571,11 @@ def prop_beam_splitter(a, b, alpha):
     return c, d
 
 
-def prop_beam_splitter_adjoint(gc, gd, a, b, alpha, want=(True, True), grad=True):
+def prop_beam_splitter_adjoint(gc, gd, a, b, alpha, want=(True, True), grad=True, out=None):
     """Returns (g_a or None, g_b or None, dalpha[batch] float64 or None);
-    a, b are the forward inputs (None: dark), needed only for dalpha."""
+    a, b are the forward inputs (None: dark), needed only for dalpha.
+    out = (g_a, g_b) (plane lists, the entry of an unwanted port ignored)
+    receives the port gradients when given."""
     lib = library()
     gc, gd = _port(gc), _port(gd)
     a, b = _port(a), _port(b)
@@ -572,8 +591,16 @@ def prop_beam_splitter_adjoint(gc, gd, a, b, alpha, want=(True, True), grad=True
     _arg(alpha, "alpha", ref, dtype=torch.float64)
     if alpha.numel() != batch:
         raise ValueError("alpha must be float64 [batch]")
-    ga = [torch.empty_like(ref) for _ in range(ncomp)] if want[0] else None
-    gb = [torch.empty_like(ref) for _ in range(ncomp)] if want[1] else None
+    if out is None:
+        ga = [torch.empty_like(ref) for _ in range(ncomp)] if want[0] else None
+        gb = [torch.empty_like(ref) for _ in range(ncomp)] if want[1] else None
+    else:
+        ga = list(out[0]) if want[0] else None
+        gb = list(out[1]) if want[1] else None
+        if (ga and len(ga) != ncomp) or (gb and len(gb) != ncomp):
+            raise ValueError(f"out: {ncomp} planes per wanted port expected")
+        for k, t in enumerate((ga or []) + (gb or [])):
+            _arg(t, f"out plane {k}", ref, pl, batch)
     da = torch.empty((batch,), dtype=torch.float64, device=ref.device) if grad else None
     with torch.cuda.device(ref.device):
         st = lib.prop_beam_splitter_adjoint(_dtype_code(ref), _ptr_array(gc), _ptr_array(gd),

@@ -204,6 +204,101 @@ class BeamSplitter(torch.autograd.Function):
         return (None, None, None, da, *outs)
 
 
+# ---------------------------------------------------------------------------
+# Elements on stacked two-component fields S = [2, batch, ny, nx] (S[0] = E_x,
+# S[1] = E_y).  A chain that keeps its fields stacked runs each scalar RS
+# propagation once over 2 * batch planes (one launch set instead of two), and
+# no element copies a component in or out of a stack: every output and every
+# input gradient is written into the halves of one new tensor.
+
+
+class ModulatePair(torch.autograd.Function):
+    """SLMs on both components: E_x exp(i phi_x), E_y exp(i phi_y)."""
+
+    @staticmethod
+    def forward(ctx, s, phi_x, phi_y):
+        s, phi_x, phi_y = s.contiguous(), phi_x.contiguous(), phi_y.contiguous()
+        u = torch.empty_like(s)
+        prop_modulate(s[0], phi_x, out=u[0])
+        prop_modulate(s[1], phi_y, out=u[1])
+        ctx.save_for_backward(u, phi_x, phi_y)
+        return u
+
+    @staticmethod
+    def backward(ctx, g):
+        u, phi_x, phi_y = ctx.saved_tensors
+        g = g.contiguous()
+        g_s = None
+        if ctx.needs_input_grad[0]:
+            g_s = torch.empty_like(g)
+            prop_modulate_adjoint(g[0], phi_x, out=g_s[0])
+            prop_modulate_adjoint(g[1], phi_y, out=g_s[1])
+        g_phi = []
+        for k, phi in enumerate((phi_x, phi_y)):
+            if not ctx.needs_input_grad[1 + k]:
+                g_phi.append(None)
+            elif phi.numel() != u[k].numel():
+                g_phi.append(prop_phase_grad_sum(g[k], u[k]).reshape(phi.shape))
+            else:
+                g_phi.append(prop_phase_grad(g[k], u[k]))
+        return g_s, g_phi[0], g_phi[1]
+
+
+class WavePlatesPair(torch.autograd.Function):
+    """Wave plates with one (eta, theta) per batch item (params float64
+    [batch, 2]) on a stacked field."""
+
+    @staticmethod
+    def forward(ctx, s, params):
+        s = s.contiguous()
+        o = torch.empty_like(s)
+        prop_waveplate_batched(s[0], s[1], params, out=(o[0], o[1]))
+        ctx.save_for_backward(s, params)
+        return o
+
+    @staticmethod
+    def backward(ctx, g):
+        s, params = ctx.saved_tensors
+        g = g.contiguous()
+        g_s = torch.empty_like(g)
+        _, _, dp = prop_waveplate_batched_adjoint(g[0], g[1], s[0], s[1], params, grad=ctx.needs_input_grad[1],
+                                                  out=(g_s[0], g_s[1]))
+        return (g_s if ctx.needs_input_grad[0] else None), (dp.reshape(params.shape) if dp is not None else None)
+
+
+class BeamSplitterPair(torch.autograd.Function):
+    """Beam splitter with one mixing angle per batch item (alpha float64
+    [batch]) on stacked ports: BeamSplitterPair.apply(alpha, S_a, S_b) ->
+    (S_c, S_d); a dark input port is None (at most one)."""
+
+    @staticmethod
+    def forward(ctx, alpha, sa, sb):
+        sa = sa.contiguous() if sa is not None else None
+        sb = sb.contiguous() if sb is not None else None
+        ref = sa if sa is not None else sb
+        sc, sd = torch.empty_like(ref), torch.empty_like(ref)
+        prop_beam_splitter([sa[0], sa[1]] if sa is not None else None, [sb[0], sb[1]] if sb is not None else None,
+                           alpha, out=([sc[0], sc[1]], [sd[0], sd[1]]))
+        ctx.save_for_backward(alpha, sa, sb)
+        return sc, sd
+
+    @staticmethod
+    def backward(ctx, gc, gd):
+        alpha, sa, sb = ctx.saved_tensors
+        ref = next(t for t in (gc, gd, sa, sb) if t is not None)
+        gc = torch.zeros_like(ref) if gc is None else gc.contiguous()
+        gd = torch.zeros_like(ref) if gd is None else gd.contiguous()
+        need = ctx.needs_input_grad
+        want = (sa is not None and need[1], sb is not None and need[2])
+        g_a = torch.empty_like(ref) if want[0] else None
+        g_b = torch.empty_like(ref) if want[1] else None
+        _, _, da = prop_beam_splitter_adjoint(
+            [gc[0], gc[1]], [gd[0], gd[1]], [sa[0], sa[1]] if sa is not None else None,
+            [sb[0], sb[1]] if sb is not None else None, alpha, want, grad=need[0],
+            out=([g_a[0], g_a[1]] if want[0] else None, [g_b[0], g_b[1]] if want[1] else None))
+        return da, g_a, g_b
+
+
 class SpotLoss(torch.autograd.Function):
     """Per-field loss sigma^2/lambda^2 + w_fz F_z on ``window`` (shape [batch])."""
 

@@ -38,7 +38,8 @@ from dataclasses import dataclass, field
 
 import torch
 
-from .autograd import CZT, RS, VCZT, BeamSplitter, DensityLoss, Modulate, SoftMin, WavePlates  # noqa: F401
+from .autograd import (CZT, RS, VCZT, BeamSplitter, BeamSplitterPair, DensityLoss, Modulate,  # noqa: F401
+                       ModulatePair, SoftMin, WavePlates, WavePlatesPair)
 
 COMPONENTS = {"ez": (2,), "radial": (0, 1), "total": (0, 1, 2)}
 
@@ -111,31 +112,30 @@ class Lattice:
         self.eps, self.beta_sted, self.beta_soft = eps, beta_sted, beta_soft
 
     # ------------------------------------------------------------ elements
-    def _link(self, l, fld, wl, p, zh):
-        if fld is None:
+    # Inside the lattice a port's field is one stacked tensor [2, B, ny, nx]
+    # (E_x, E_y): both components propagate in one RS call over 2B planes.
+    def _rs(self, s, wl, z, zv):
+        two, b, ny, nx = s.shape
+        return RS.apply(s.reshape(two * b, ny, nx), self.grid, wl, z, zv).reshape(s.shape)
+
+    def _link(self, l, s, wl, p, zh):
+        if s is None:
             return None
-        ex, ey = fld
-        g = self.grid
         z1, z2 = zh[0][l], zh[1][l]
         if self.unit[l]:
             k = self.unit_index[l]
-            ex = Modulate.apply(ex, p.phi[k][0])
-            ey = Modulate.apply(ey, p.phi[k][1])
-            ex = RS.apply(ex, g, wl, p.z1[l], z1)
-            ey = RS.apply(ey, g, wl, p.z1[l], z1)
-            ex, ey = WavePlates.apply(ex, ey, p.wp[k])
+            s = ModulatePair.apply(s, p.phi[k][0], p.phi[k][1])
+            s = self._rs(s, wl, p.z1[l], z1)
+            s = WavePlatesPair.apply(s, p.wp[k])
         if z2 > 0:
-            ex = RS.apply(ex, g, wl, p.z2[l], z2)
-            ey = RS.apply(ey, g, wl, p.z2[l], z2)
-        return ex, ey
+            s = self._rs(s, wl, p.z2[l], z2)
+        return s
 
     @staticmethod
     def _split(a, b, alpha):
         if a is None and b is None:
             return None, None
-        planes = (list(a) if a is not None else []) + (list(b) if b is not None else [])
-        out = BeamSplitter.apply(2, a is not None, b is not None, alpha, *planes)
-        return tuple(out[:2]), tuple(out[2:])
+        return BeamSplitterPair.apply(alpha, a, b)
 
     def detector_fields(self, sources, wl, p, zh=None):
         """Transverse fields arriving at the R + C detectors for one beam;
@@ -146,8 +146,9 @@ class Lattice:
             raise ValueError(f"need {R + C} sources")
         if zh is None:
             zh = _host_distances(p)
-        h = {(r, 0): sources[r] for r in range(R)}
-        v = {(0, c): sources[R + c] for c in range(C)}
+        stacked = [None if s is None else torch.stack([s[0], s[1]]) for s in sources]
+        h = {(r, 0): stacked[r] for r in range(R)}
+        v = {(0, c): stacked[R + c] for c in range(C)}
         for r in range(R):
             for c in range(C):
                 a = self._link(h_link(R, C, r, c), h[(r, c)], wl, p, zh)
@@ -155,7 +156,7 @@ class Lattice:
                 h[(r, c + 1)], v[(r + 1, c)] = self._split(a, b, p.alpha[r * C + c])
         det = [self._link(h_link(R, C, r, C), h[(r, C)], wl, p, zh) for r in range(R)]
         det += [self._link(v_link(R, C, R, c), v[(R, c)], wl, p, zh) for c in range(C)]
-        return det
+        return [None if d is None else tuple(d.unbind(0)) for d in det]
 
     def forward(self, beams, p: LatticeParams):
         """beams: list of 1 or 2 dicts {"wavelength", "sources"}; the second

@@ -59,6 +59,16 @@ def test_mismatched_arguments_raise_before_launch(lp):
                                               torch.zeros(2, dtype=torch.float64, device="cuda")),
         lambda: lp.prop_beam_splitter([u], [_c(2, 24, 32, dt=torch.complex128)], torch.zeros(2, dtype=torch.float64,
                                                                                         device="cuda")),
+        # out= planes of the element calls with the wrong shape, precision or count
+        lambda: lp.prop_waveplate_batched(u, u, torch.zeros((2, 2), dtype=torch.float64, device="cuda"),
+                                          out=(_c(2, 24, 32), _c(1, 24, 32))),
+        lambda: lp.prop_waveplate_batched_adjoint(u, u, u, u, torch.zeros((2, 2), dtype=torch.float64, device="cuda"),
+                                                  out=(_c(2, 24, 32, dt=torch.complex128), _c(2, 24, 32))),
+        lambda: lp.prop_beam_splitter([u, u], [u, u], torch.zeros(2, dtype=torch.float64, device="cuda"),
+                                      out=([_c(2, 24, 32), _c(2, 24, 32)], [_c(2, 24, 32)])),
+        lambda: lp.prop_beam_splitter_adjoint([u, u], [u, u], [u, u], None,
+                                              torch.zeros(2, dtype=torch.float64, device="cuda"), (True, False),
+                                              out=([_c(2, 24, 32), _c(2, 24, 31)], None)),
         lambda: lp.prop_spot_loss(_c(2, 16, 16), _c(2, 16, 16), _c(1, 16, 16), win, 6e-7),
         lambda: lp.prop_density_loss([_c(2, 16, 16), _c(2, 16, 15)], 0.5),
         lambda: lp.prop_scale_items([u, _c(1, 24, 32)], torch.ones(2, dtype=torch.float64, device="cuda")),

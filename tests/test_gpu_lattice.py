@@ -127,6 +127,67 @@ def test_waveplate_batched_vs_oracle(lp, kind):
 
 
 @pytest.mark.parametrize("kind", ["c64", "c128"])
+@pytest.mark.parametrize("dark", ["none", "a", "b"])
+def test_stacked_pair_elements_match_per_plane(lp, kind, dark):
+    """The elements on stacked [2, B, ny, nx] fields (SLM pair, wave plates,
+    splitter) against the per-plane elements on the same planes: outputs and
+    every gradient (fields, phases, plate parameters, splitter angles), with
+    either input port of the splitter dark or both lit."""
+    import torch
+    from paper_2310_08408_amd.autograd import (BeamSplitter, BeamSplitterPair, Modulate, ModulatePair, WavePlates,
+                                               WavePlatesPair)
+    rng = np.random.default_rng(23 + len(dark))
+    B, ny, nx = 3, 17, 23
+    rdt = torch.float32 if kind == "c64" else torch.float64
+    s_np = cast(workloads.random_field(rng, (2, B, ny, nx)), kind)
+    t_np = cast(workloads.random_field(rng, (2, B, ny, nx)), kind)
+    w = torch.tensor(rng.uniform(0.5, 1.5, (4, B, ny, nx)), dtype=rdt, device="cuda")
+    phi = rng.uniform(-math.pi, math.pi, (2, B, ny, nx))
+    wp = rng.uniform(-2, 2, (B, 2))
+    alpha = rng.uniform(-2, 2, B)
+
+    def leaves():
+        return (dev(s_np, kind).requires_grad_(), dev(t_np, kind).requires_grad_(),
+                torch.tensor(phi[0], dtype=rdt, device="cuda", requires_grad=True),
+                torch.tensor(phi[1], dtype=rdt, device="cuda", requires_grad=True),
+                torch.tensor(wp, device="cuda", requires_grad=True),
+                torch.tensor(alpha, device="cuda", requires_grad=True))
+
+    def loss(planes):
+        return sum((w[k] * (p.real ** 2 + p.imag ** 2)).sum() for k, p in enumerate(planes))
+
+    ls = leaves()
+    s, t, px, py, q, al = ls
+    p2 = WavePlatesPair.apply(ModulatePair.apply(s, px, py), q)
+    a, b = {"none": (p2, t), "a": (None, p2), "b": (p2, None)}[dark]
+    sc, sd = BeamSplitterPair.apply(al, a, b)
+    out_pair = [sc[0], sc[1], sd[0], sd[1]]
+    loss(out_pair).backward()
+
+    lp_ = leaves()
+    s1, t1, px1, py1, q1, al1 = lp_
+    ex, ey = WavePlates.apply(Modulate.apply(s1[0], px1), Modulate.apply(s1[1], py1), q1)
+    t_planes = [t1[0], t1[1]]
+    planes = {"none": [ex, ey] + t_planes, "a": [ex, ey], "b": [ex, ey]}[dark]
+    has_a, has_b = {"none": (True, True), "a": (False, True), "b": (True, False)}[dark]
+    out_plane = list(BeamSplitter.apply(2, has_a, has_b, al1, *planes))
+    loss(out_plane).backward()
+
+    tol = TOL[kind]
+    for k, (x, y) in enumerate(zip(out_pair, out_plane)):
+        assert rel_l2(host(x), host(y)) <= tol, ("output plane", k)
+    names = ["S", "T", "phi_x", "phi_y", "wave plates", "alpha"]
+    for name, x, y in zip(names, ls, lp_):
+        if name == "T" and dark != "none":
+            assert x.grad is None and y.grad is None
+            continue
+        gx_, gy_ = x.grad.detach().cpu().numpy(), y.grad.detach().cpu().numpy()
+        err = np.linalg.norm(gx_ - gy_) / np.linalg.norm(gy_)
+        say(f"pair vs per-plane {kind} dark {dark}: grad {name} rel-L2 {err:.1e}")
+        assert err <= tol, name
+
+
+@pytest.mark.parametrize("kind", ["c64", "c128"])
 def test_modulate_adjoint_and_shared_input_waveplate(lp, kind):
     """SLM adjoint g exp(-i phi), per set and shared phases; the wave-plate
     adjoint for one field fed to both components (g_A = g_ex + g_ey)."""
