@@ -192,6 +192,18 @@ int czt_adjoint_phase_grad(prop_dtype t, const void* g_out, const void* u, void*
  */
 int rs_grad_z(prop_dtype t, const void* u_in, const void* g_out, double* dz, const prop_grid* g,
               double wavelength, double z, int32_t batch, void* stream);
+/* rs_adjoint_grad_z: rs_adjoint and rs_grad_z of one RS step in one call,
+ * for a backward pass that needs both: g_in = RS^H g_out (the same passes
+ * as rs_adjoint) and dz as rs_grad_z gives it, up to rounding.  The sum is
+ * taken in the row-spectrum domain (Parseval along x), where the adjoint's
+ * first pass already holds the transformed g_out, so the distance gradient
+ * costs one row pass, one column pass and a dot product instead of a full
+ * propagation and a dot product.  u_in: the step's forward input, g_out:
+ * the output seed, both [batch][ny][nx]; g_in (same layout) and dz (device
+ * double [batch]) may not overlap the inputs or each other (PROP_EALIAS).
+ * Same limits and sampling warning as rs_propagate. */
+int rs_adjoint_grad_z(prop_dtype t, const void* g_out, const void* u_in, void* g_in, double* dz,
+                      const prop_grid* g, double wavelength, double z, int32_t batch, void* stream);
 int czt_grad_z(prop_dtype t, const void* u_in, const void* u_out, const void* g_out, double* dz,
                const prop_grid* g_in, const prop_grid* win, double wavelength, double z, int32_t batch,
                void* stream);

@@ -20,7 +20,8 @@ from ._lib import PropError, PropWarning  # noqa: F401
 
 __all__ = [
     "rs_propagate", "rs_adjoint", "czt_propagate", "czt_adjoint", "vrs_propagate", "vrs_adjoint",
-    "vczt_propagate", "vczt_adjoint", "rs_grad_z", "czt_grad_z", "rs_adjoint_phase_grad", "czt_adjoint_phase_grad",
+    "vczt_propagate", "vczt_adjoint", "rs_grad_z", "rs_adjoint_grad_z", "czt_grad_z", "rs_adjoint_phase_grad",
+    "czt_adjoint_phase_grad",
     "prop_source_gaussian", "prop_source_radial", "prop_modulate",
     "prop_phase_grad", "prop_waveplate", "prop_waveplate_adjoint", "prop_spot_loss", "prop_density_loss",
     "prop_softmin", "prop_adam_step", "Adam", "prop_track_best", "prop_sum_items", "StopRule", "prop_sampling_check",
@@ -228,6 +229,23 @@ def rs_grad_z(u, g_out, grid, wavelength, z):
                            float(wavelength), float(z), b, _stream(u))
     _lib.check("rs_grad_z", st)
     return dz
+
+
+def rs_adjoint_grad_z(g_out, u, grid, wavelength, z, out=None):
+    """rs_adjoint(g_out) and rs_grad_z(u, g_out) of one RS step in one call
+    (the distance gradient shares the adjoint's first pass).  Returns
+    (g_u, dz): g_u like u, dz float64 [batch]."""
+    lib = library()
+    _field(u)
+    b = _batch(u, grid)
+    _arg(g_out, "g_out", u, grid, b)
+    out = _like(u, grid, out)
+    dz = torch.empty((b,), dtype=torch.float64, device=u.device)
+    with torch.cuda.device(u.device):
+        st = lib.rs_adjoint_grad_z(_dtype_code(u), _ptr(g_out), _ptr(u), _ptr(out), _ptr(dz),
+                                   ctypes.byref(_lib.grid(grid)), float(wavelength), float(z), b, _stream(u))
+    _lib.check("rs_adjoint_grad_z", st)
+    return out, dz
 
 
 def czt_grad_z(u, g_out, grid_in, window, wavelength, z, u_out=None):

@@ -98,6 +98,7 @@ SIGNATURES = {
     "prop_tune_cache_path": (c_int32, [ctypes.c_char_p]),
     "prop_tune_cache_rejected": (c_int32, []),
     "rs_grad_z": (c_int32, [c_int32, P, P, P, G, c_double, c_double, c_int32, P]),
+    "rs_adjoint_grad_z": (c_int32, [c_int32, P, P, P, P, G, c_double, c_double, c_int32, P]),
     "rs_adjoint_phase_grad": (c_int32, [c_int32, P, P, P, P, c_int32, G, c_double, c_double, c_int32, P]),
     "czt_adjoint_phase_grad": (c_int32, [c_int32, P, P, P, P, c_int32, G, G, c_double, c_double, c_int32, P]),
     "czt_grad_z": (c_int32, [c_int32, P, P, P, P, G, G, c_double, c_double, c_int32, P]),

@@ -21,7 +21,7 @@ from . import (prop_sum_items, czt_adjoint, czt_grad_z, czt_propagate, prop_beam
                prop_density_loss, prop_modulate, prop_modulate_adjoint, prop_phase_grad, prop_phase_grad_sum,
                prop_scale_items, prop_softmin, prop_spot_loss, prop_waveplate,
                prop_waveplate_adjoint, prop_waveplate_batched, prop_waveplate_batched_adjoint, rs_adjoint,
-               rs_grad_z, rs_propagate, vczt_adjoint, vczt_propagate, vrs_adjoint, vrs_propagate)
+               rs_adjoint_grad_z, rs_grad_z, rs_propagate, vczt_adjoint, vczt_propagate, vrs_adjoint, vrs_propagate)
 
 
 def _zval(z):
@@ -44,10 +44,15 @@ class RS(torch.autograd.Function):
         grid, wl, z = ctx.args
         (u,) = ctx.saved_tensors
         g = g.contiguous()
-        gz = None
-        if ctx.z_tensor and ctx.needs_input_grad[3]:
+        gz = gu = None
+        want_z = ctx.z_tensor and ctx.needs_input_grad[3]
+        if want_z and ctx.needs_input_grad[0]:
+            gu, dz = rs_adjoint_grad_z(g, u, grid, wl, z)
+            gz = prop_sum_items(dz).reshape(ctx.z_shape)
+        elif want_z:
             gz = prop_sum_items(rs_grad_z(u, g, grid, wl, z)).reshape(ctx.z_shape)
-        gu = rs_adjoint(g, grid, wl, z) if ctx.needs_input_grad[0] else None
+        elif ctx.needs_input_grad[0]:
+            gu = rs_adjoint(g, grid, wl, z)
         return gu, None, None, gz, None
 
 

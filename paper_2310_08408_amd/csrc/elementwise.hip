@@ -598,20 +598,20 @@ __global__ __launch_bounds__(256) void k_redot_partial(const cx<T>* a, const cx<
   if (threadIdx.x == 0) partial[(int64_t)bi * nblk + blockIdx.x] = acc[0];
 }
 
-__global__ __launch_bounds__(256) void k_sum_partials1(const double* partial, int nblk, double* out) {
+__global__ __launch_bounds__(256) void k_sum_partials1(const double* partial, int nblk, double scale, double* out) {
   __shared__ double sh[256];
   const int b = blockIdx.x;
   double acc[1] = {0.0};
   for (int i = threadIdx.x; i < nblk; i += 256) acc[0] += partial[(int64_t)b * nblk + i];
   block_reduce<1>(acc, sh);
-  if (threadIdx.x == 0) out[b] = acc[0];
+  if (threadIdx.x == 0) out[b] = scale * acc[0];
 }
 
 template <typename T>
 hipError_t launch_redot(const cx<T>* a, const cx<T>* b, double* out, double* partial, int nblk, int64_t npix,
-                        int batch, hipStream_t s) {
+                        int batch, hipStream_t s, double scale) {
   hipLaunchKernelGGL((k_redot_partial<T>), dim3(nblk, batch), dim3(256), 0, s, a, b, partial, nblk, npix);
-  hipLaunchKernelGGL(k_sum_partials1, dim3(batch), dim3(256), 0, s, partial, nblk, out);
+  hipLaunchKernelGGL(k_sum_partials1, dim3(batch), dim3(256), 0, s, partial, nblk, scale, out);
   return hipGetLastError();
 }
 
@@ -679,7 +679,7 @@ hipError_t launch_czt_dz_reduce(const cx<T>* g, const cx<T>* U, const cx<T>* Tt,
   const int64_t pb = (int64_t)nx * ny * batch;
   hipLaunchKernelGGL((k_czt_dz_partial<T>), dim3(nblk, batch), dim3(256), 0, s, g, U, Tt, nx, ny, dX, dY, cX, cY, k,
                      z, wl, partial, nblk, pb);
-  hipLaunchKernelGGL(k_sum_partials1, dim3(batch), dim3(256), 0, s, partial, nblk, out);
+  hipLaunchKernelGGL(k_sum_partials1, dim3(batch), dim3(256), 0, s, partial, nblk, 1.0, out);
   return hipGetLastError();
 }
 
@@ -1275,7 +1275,8 @@ hipError_t launch_spot_loss(const cx<T>* ex, const cx<T>* ey, const cx<T>* ez, i
 // ------------------------------------------------------ instantiations --
 #define LP_INST(T)                                                                                                  \
   template hipError_t launch_extract_half<T>(const cx<double>*, cx<T>*, int, int, hipStream_t);                  \
-  template hipError_t launch_redot<T>(const cx<T>*, const cx<T>*, double*, double*, int, int64_t, int, hipStream_t); \
+  template hipError_t launch_redot<T>(const cx<T>*, const cx<T>*, double*, double*, int, int64_t, int, hipStream_t,   \
+                                      double);                                                                      \
   template hipError_t launch_adam<T>(T*, const T*, T*, T*, int64_t, double, double, double, double, double, int,   \
                                      hipStream_t);                                                                  \
   template hipError_t launch_density_loss<T>(const void* const*, int, const void* const*, int, double, int64_t,     \

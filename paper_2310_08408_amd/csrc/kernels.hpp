@@ -123,11 +123,12 @@ hipError_t launch_rs_kernel_wrapped(cx<double>* out, int Mx, int My, int nx, int
 // follows from its parity in ky), all columns, stored in 4-column tiles
 // like the RS workspace: (ky, kx) at (kx / 4) (My/2+1) 4 + ky 4 + kx % 4, so
 // a column pass reads its tile's spectrum as one contiguous block.
-// Distance gradients.  Re sum conj(a) b per batch item (npix elements each)
-// into out[batch] (FP64, fixed order; partial: batch * nblk doubles).
+// Distance gradients.  scale * Re sum conj(a) b per batch item (npix
+// elements each) into out[batch] (FP64, fixed order; partial: batch * nblk
+// doubles).
 template <typename T>
 hipError_t launch_redot(const cx<T>* a, const cx<T>* b, double* out, double* partial, int nblk, int64_t npix,
-                        int batch, hipStream_t s);
+                        int batch, hipStream_t s, double scale = 1.0);
 // Threshold-density detector loss of the intensity of ncomp field
 // components (optionally STED-modulated by ndep depletion components with
 // quenching efficiency beta): res[batch][4] = (Area / I_eps, Area, I_eps,

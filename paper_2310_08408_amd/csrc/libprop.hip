@@ -1028,6 +1028,77 @@ static int rs_grad_z_run(const void* u, const void* gout, double* dz, const prop
   return PROP_OK;
 }
 
+static size_t rs_adjoint_grad_z_bytes(prop_dtype t, const prop_grid* g, int batch) {
+  const int64_t plane = rs_plane_elems(g->ny, fft_len(2 * g->nx - 1));
+  return std::max(2 * rs_work_bytes(t, g, batch) + (size_t)batch * red_blocks(plane) * sizeof(double) + 256,
+                  rs_grad_z_bytes(t, g, batch));
+}
+
+// The adjoint of one RS step together with its distance gradient.  With
+// V = RS of u with the kernel dH/dz, V = scale IFFT_rows(Cu) cropped to nx
+// columns (Cu: the column pass of u's row transform with dH/dz, scale =
+// dx dy / (Mx My)), and Parseval along each row gives
+//   sum_{y, x < nx} conj(g[y, x]) V[y, x] = scale sum_{y, kx < Mx} conj(Rg[y, kx]) Cu[y, kx],
+// Rg being the row transform of the zero-padded g, which is the adjoint's
+// own first pass.  So dL/dz needs no inverse row pass: one dot product of
+// the two workspaces (same tiled layout, every element written) before the
+// adjoint's column pass overwrites Rg.  Where the workspace rows carry
+// padding columns (Mx not a multiple of the tile width, nx = 1) the two
+// computations run separately.
+template <typename T>
+static int rs_adjoint_grad_z_run(const void* gout, const void* u, void* gin, double* dz, const prop_grid* g,
+                                 double wl, double z, int batch, hipStream_t s, void* work) {
+  int dev;
+  LP_RET(cur_device(&dev));
+  const int nx = g->nx, ny = g->ny;
+  if (fft_len(2 * nx - 1) % kTile != 0) {
+    LP_RET(rs_grad_z_run<T>(u, gout, dz, g, wl, z, batch, s, work));
+    return rs_run<T>(gout, gin, g, wl, z, batch, s, true, work);
+  }
+  const cx<T>* q[4];
+  int Mx, My;
+  LP_RET(get_rs_spectra<T>(dev, g, wl, z, 1 | 8, s, q, &Mx, &My));
+  const cx<T> *twx, *twy;
+  LP_RET(get_tw<T>(dev, Mx, &twx));
+  LP_RET(get_tw<T>(dev, My, &twy));
+  const int64_t plane = rs_plane_elems(ny, Mx);
+  cx<T>* Wg = (cx<T>*)work;
+  cx<T>* Wu = Wg + plane * batch;
+  double* partial = (double*)(((uintptr_t)(Wu + plane * batch) + 255) & ~(uintptr_t)255);
+  const double scale = g->dx * g->dy / ((double)Mx * (double)My);
+  const double es = sizeof(cx<T>);
+  const double qel = (double)Mx * (My / 2 + 1);
+  LP_TRACE("rs_rows_fwd", es * batch * ny * (double)(nx + Mx), s,
+           (launch_rs_rows<T, -1>(Mx, (const cx<T>*)gout, Wg, plane, ny, nx, T(1), batch, twx, s, nullptr, nullptr,
+                                  0, nullptr)));
+  LP_TRACE("rs_rows_fwd", es * batch * ny * (double)(nx + Mx), s,
+           (launch_rs_rows<T, -1>(Mx, (const cx<T>*)u, Wu, plane, ny, nx, T(1), batch, twx, s, nullptr, nullptr, 0,
+                                  nullptr)));
+  // column passes: u with dH/dz (forward), then g with conj(H) (adjoint)
+  for (int adj = 0; adj < 2; ++adj) {
+    cx<T>* W = adj ? Wg : Wu;
+    const cx<T>* spec = adj ? q[0] : q[3];
+    int v = 0;
+    const cx<T>* twc = twy;
+    LP_RET(tuned_pass<T>(dev, TUNE_RS_COLS, My, Mx, ny, ny, batch, (size_t)plane * batch, 0, s,
+                         [&](int var, const cx<T>* tw, cx<T>* a, cx<T>*) {
+                           return launch_rs_cols<T>(My, a, plane, Mx, ny, spec, Mx, adj != 0, batch, tw, s, var);
+                         },
+                         &v, &twc));
+    if (adj) {
+      const int nblk = red_blocks(plane);
+      LP_TRACE("rs_dz_dot", 2.0 * es * batch * (double)plane, s,
+               launch_redot<T>(Wg, Wu, dz, partial, nblk, plane, batch, s, scale));
+    }
+    LP_TRACE("rs_cols", es * (2.0 * batch * ny * Mx + qel), s,
+             launch_rs_cols<T>(My, W, plane, Mx, ny, spec, Mx, adj != 0, batch, twc, s, v));
+  }
+  LP_TRACE("rs_rows_inv", es * batch * ny * (double)(Mx + nx), s,
+           (launch_rs_rows<T, 1>(Mx, Wg, (cx<T>*)gin, plane, ny, nx, (T)scale, batch, twx, s, nullptr, nullptr, 0,
+                                 nullptr)));
+  return PROP_OK;
+}
+
 static size_t czt_grad_z_bytes(prop_dtype t, const prop_grid* gi, const prop_grid* go, int batch, bool need_u) {
   const size_t ni = (size_t)gi->nx * gi->ny * batch, no = (size_t)go->nx * go->ny * batch;
   return (czt_tmp_elems(gi, go) * 3 * batch + 3 * ni + 3 * no + (need_u ? no : 0)) * esize(t) +
@@ -1707,6 +1778,29 @@ int rs_grad_z(prop_dtype t, const void* u_in, const void* g_out, double* dz, con
   LP_RET(ensure_buf(wb, rs_grad_z_bytes(t, g, batch), s));
   const int r = t == PROP_C64 ? rs_grad_z_run<float>(u_in, g_out, dz, g, wavelength, z, batch, s, wb.p)
                               : rs_grad_z_run<double>(u_in, g_out, dz, g, wavelength, z, batch, s, wb.p);
+  return r < 0 ? r : warn;
+}
+
+int rs_adjoint_grad_z(prop_dtype t, const void* g_out, const void* u_in, void* g_in, double* dz, const prop_grid* g,
+                      double wavelength, double z, int32_t batch, void* stream) {
+  LP_RET(check_common(t, batch, wavelength));
+  LP_RET(check_grid(g));
+  if (!(z > 0) || !is_finite(z)) return PROP_EPARAM;
+  if (fft_len(2 * g->nx - 1) < 0 || fft_len(2 * g->ny - 1) < 0) return PROP_ESHAPE;
+  const int warn = sampling(g, wavelength, z);
+  if (batch == 0) return warn;
+  if (!g_out || !u_in || !g_in || !dz) return PROP_ENULL;
+  const size_t bytes = (size_t)g->nx * g->ny * batch * esize(t);
+  LP_RET(check_alias({{g_out, bytes}, {u_in, bytes}}, {{g_in, bytes}, {dz, (size_t)batch * sizeof(double)}}));
+  CtxLock lk;
+  const hipStream_t s = (hipStream_t)stream;
+  int dev;
+  LP_RET(cur_device(&dev));
+  Buf& wb = ctx().work[{dev, s}];
+  LP_RET(ensure_buf(wb, rs_adjoint_grad_z_bytes(t, g, batch), s));
+  const int r = t == PROP_C64
+                    ? rs_adjoint_grad_z_run<float>(g_out, u_in, g_in, dz, g, wavelength, z, batch, s, wb.p)
+                    : rs_adjoint_grad_z_run<double>(g_out, u_in, g_in, dz, g, wavelength, z, batch, s, wb.p);
   return r < 0 ? r : warn;
 }
 

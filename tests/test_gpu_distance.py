@@ -63,6 +63,60 @@ def test_rs_grad_z(lp, kind, case):
     assert err < TOL[kind]
 
 
+FUSED_CASES = RS_CASES + [(Grid(37, 5, 3e-6, 2e-6, 0, 1e-6), 3, 600e-9, 300e-6),
+                          (Grid(1, 24, 2e-6, 2e-6), 2, 532e-9, 200e-6)]
+
+
+@pytest.mark.parametrize("kind", ["c64", "c128"])
+@pytest.mark.parametrize("case", range(len(FUSED_CASES)))
+def test_rs_adjoint_grad_z_matches_separate_calls(lp, kind, case):
+    """rs_adjoint_grad_z: its field gradient bit-identical to rs_adjoint, its
+    dz within rounding of rs_grad_z (the sum taken in the row-spectrum
+    domain) and of the oracle.  Cases: ragged grids, batch 1-3, and nx = 1
+    (padded workspace rows: the two computations run separately)."""
+    import torch
+    g, b, wl, z = FUSED_CASES[case]
+    u = cast(rnd((b, g.ny, g.nx), case + 7), kind)
+    c = cast(rnd((b, g.ny, g.nx), case + 70), kind)
+    ut, ct = dev(u, kind), dev(c, kind)
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        gu, dz = lp.rs_adjoint_grad_z(ct, ut, g, wl, z)
+        gu_ref = lp.rs_adjoint(ct, g, wl, z)
+        dz_ref = lp.rs_grad_z(ut, ct, g, wl, z).cpu().numpy()
+        with pytest.raises(lp.PropError):
+            lp.rs_adjoint_grad_z(ct, ut, g, wl, z, out=ct)
+    assert torch.equal(gu, gu_ref)
+    dz = dz.cpu().numpy()
+    ref = np.atleast_1d(oracle.rs_grad_z(u, c, g, wl, z))
+    e_sep = np.abs(dz - dz_ref).max() / np.abs(dz_ref).max()
+    e_orc = np.abs(dz - ref).max() / np.abs(ref).max()
+    say(f"rs_adjoint_grad_z case {case} {kind}: dz vs rs_grad_z {e_sep:.2e}, vs oracle {e_orc:.2e}")
+    assert e_sep < TOL[kind] and e_orc < TOL[kind]
+
+
+@pytest.mark.parametrize("kind", ["c64", "c128"])
+def test_rs_adjoint_grad_z_1024_batch4(lp, kind):
+    """The lattice's shape (1024^2 grid, 4 planes): against the separate
+    calls (the oracle at this size is covered by the 2048^2 test of
+    rs_grad_z)."""
+    import torch
+    g, wl, z = Grid.square(1024, 1024 * 4.8e-6), 532e-9, 0.03
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    dt = torch.complex64 if kind == "c64" else torch.complex128
+    u = torch.randn((4, 1024, 1024), dtype=dt, device="cuda", generator=gen)
+    c = torch.randn((4, 1024, 1024), dtype=dt, device="cuda", generator=gen)
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        gu, dz = lp.rs_adjoint_grad_z(c, u, g, wl, z)
+        gu_ref = lp.rs_adjoint(c, g, wl, z)
+        dz_ref = lp.rs_grad_z(u, c, g, wl, z)
+    assert torch.equal(gu, gu_ref)
+    err = float((dz - dz_ref).abs().max() / dz_ref.abs().max())
+    say(f"rs_adjoint_grad_z 1024^2 x4 {kind}: dz vs rs_grad_z {err:.2e}")
+    assert err < TOL[kind]
+
+
 CZT_CASES = [(Grid(40, 36, 3e-6, 3e-6, 2e-6, 0), Grid(30, 26, 0.3e-6, 0.3e-6, 1e-6, -1e-6), 2, 600e-9, 1e-3),
              (Grid(128, 96, 4e-6, 4e-6), Grid(64, 80, 0.2e-6, 0.25e-6), 1, 650e-9, 5e-3)]
 
