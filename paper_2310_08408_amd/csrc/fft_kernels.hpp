@@ -651,52 +651,99 @@ __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) vo
 // CONJ (the adjoint's conjugated spectrum) is a template parameter: as a
 // runtime flag the compiler forms both products and selects, 6% of the
 // kernel's VALU instructions.
+// One FP32 complex value through a buffer resource: vo per lane, so uniform
+// (bytes); AUX the cache policy (2: non-temporal).
+using u32x2 = __attribute__((ext_vector_type(2))) unsigned;
+template <typename T, int AUX>
+__device__ __forceinline__ cx<T> buf_load(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+  static_assert(sizeof(cx<T>) == 8, "one FP32 complex value");
+  return __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, AUX));
+}
+template <typename T, int AUX>
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, cx<T> v) {
+  static_assert(sizeof(cx<T>) == 8, "one FP32 complex value");
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, vo, so, AUX);
+}
+
 template <typename T, class S, int C, bool CONJ>
 __global__ __launch_bounds__(C * S::threads, (waves_per_eu<T, S, C, true>())) void k_rs_cols_persist(
     cx<T>* W, int64_t bstride, int n_valid, TableBox<T> Sq_, int nb, int items, int per, TableBox<T> tw_) {
+  static_assert(sizeof(cx<T>) == 8, "buffer accesses of one FP32 complex value");
   const cx<T>* Sq = Sq_.p;
   constexpr int LS = line_stride<S, C, true>();
   __shared__ cx<T> smem[C * LS];
   const cx<T>* tw = tw_.p;
   using HI = HalfIn<S>;
+  using HO = HalfOut<S>;
   constexpr int My = S::n, RIN = HI::R;
+  constexpr uint32_t ES = sizeof(cx<T>);
   const int chunk = xcd_remap(blockIdx.x, gridDim.x);
   const int first = chunk * per, last = min(first + per, items);
   const int c = threadIdx.x % C, j = threadIdx.x / C;
   cx<T>* lds = smem + c * LS;
-  auto colp = [&](int id) -> cx<T>* {
+  // A work item's columns kx = k0 + c (k0 = tile C) lie in 4-column tiles
+  // k0 / 4 .. (k0 + C - 1) / 4 of the workspace and of the spectrum table.
+  // Each is reached through a buffer resource whose base, the first of those
+  // tiles, is uniform; a lane adds a 32-bit offset, and the row offset of
+  // each register goes to the scalar offset, so no access needs 64-bit
+  // address arithmetic.
+  const int q = My / 2 + 1;
+  struct Item {
+    __amdgpu_buffer_rsrc_t w, sq;
+    uint32_t lane;  // the lane's column within the tile run, in elements
+  };
+  auto item = [&](int id) -> Item {
     const int tile = id / nb, b = id - tile * nb;
-    const int kx = tile * C + c;
-    return W + b * bstride + (int64_t)(kx >> kTileShift) * n_valid * kTile + (kx & (kTile - 1));
+    const int k0 = tile * C, ka = (k0 & 3) + c;
+    const int ntiles = ((k0 & 3) + C + 3) / 4;
+    Item it;
+    it.w = __builtin_amdgcn_make_buffer_rsrc(W + b * bstride + (int64_t)(k0 >> 2) * n_valid * kTile, 0,
+                                             (int)((uint32_t)ntiles * n_valid * kTile * ES), 0x00020000);
+    it.sq = __builtin_amdgcn_make_buffer_rsrc(const_cast<cx<T>*>(Sq) + (int64_t)(k0 >> 2) * q * 4, 0,
+                                              (int)((uint32_t)ntiles * q * 4 * ES), 0x00020000);
+    it.lane = (uint32_t)(ka >> 2);
+    it.lane = it.lane * (uint32_t)n_valid * kTile + (uint32_t)(ka & 3);
+    return it;
+  };
+  // the lane's spectrum offset: the table holds 4-column tiles of q rows
+  auto sq_lane = [&](int id) -> uint32_t {
+    const int ka = ((id / nb) * C & 3) + c;
+    return (uint32_t)(ka >> 2) * (uint32_t)q * 4 + (uint32_t)(ka & 3);
   };
   // threads j >= n/R0 exist when a later radix is smaller than the first;
   // they take no part in the first stage and load nothing
   const bool loader = HI::loads(j);
   cx<T> nxt[RIN];
   if (loader && first < last) {
-    cx<T>* col = colp(first);
+    const Item it = item(first);
+    const uint32_t vo = (it.lane + (uint32_t)j * kTile) * ES;
 #pragma unroll
-    for (int r = 0; r < RIN; ++r) nxt[r] = load_stream(&col[HI::index(j, r) * kTile]);
+    for (int r = 0; r < RIN; ++r) nxt[r] = buf_load<T, 2>(it.w, vo, (uint32_t)(HI::index(j, r) - j) * kTile * ES);
   }
   for (int id = first; id < last; ++id) {
     cx<T> cur[RIN];
 #pragma unroll
     for (int r = 0; r < RIN; ++r) cur[r] = nxt[r];
     if (loader && id + 1 < last) {
-      cx<T>* coln = colp(id + 1);
+      const Item it = item(id + 1);
+      const uint32_t vo = (it.lane + (uint32_t)j * kTile) * ES;
 #pragma unroll
-      for (int r = 0; r < RIN; ++r) nxt[r] = load_stream(&coln[HI::index(j, r) * kTile]);
+      for (int r = 0; r < RIN; ++r) nxt[r] = buf_load<T, 2>(it.w, vo, (uint32_t)(HI::index(j, r) - j) * kTile * ES);
     }
-    const int kx = (id / nb) * C + c;
-    cx<T>* col = colp(id);
-    const cx<T>* sq = Sq + (int64_t)(kx >> 2) * (My / 2 + 1) * 4 + (kx & 3);
+    const Item it = item(id);
+    const uint32_t vs = sq_lane(id) * ES;
+    const uint32_t vw = (it.lane + (uint32_t)j * kTile) * ES;
     // the first stage asks for i = HI::index(j, r): register r of cur
     auto load = [&](int i) -> cx<T> { return cur[(i - j) / HI::nr]; };
     auto mult = [&](int i, cx<T> v) -> cx<T> {
-      const cx<T> h = sq[min(i, My - i) * 4];
+      const cx<T> h = buf_load<T, 0>(it.sq, vs + (uint32_t)min(i, My - i) * 4 * ES, 0);
       return CONJ ? cmulc(v, h) : cmul(v, h);
     };
-    auto store = [&](int i, cx<T> v) { store_stream(&col[i * kTile], v); };
+    // the last stage stores i = HO::index(j, r) = j + r n / RL
+    auto store = [&](int i, cx<T> v) {
+      buf_store<T, 2>(it.w, vw, (uint32_t)(i - j) * kTile * ES, v);
+    };
+    static_assert(HO::index(1, 1) - 1 == HO::nr, "stores at j + r n / RL");
     conv_line<T, S, true, true>(lds, tw, j, load, mult, store);
   }
 }
