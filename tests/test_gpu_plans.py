@@ -340,6 +340,66 @@ def test_autotuned_plan(lp, graph, tmp_path):
     lp.prop_tune_cache_path(None)
 
 
+def _rs_plan(lp, torch, n, seed):
+    g = Grid.square(n, 4e-3)
+    rng = np.random.default_rng(seed)
+    v = torch.from_numpy(workloads.random_field(rng, (1, n, n)).astype(np.complex64)).cuda()
+    y, gi = torch.empty_like(v), torch.empty_like(v)
+    s = lp.Setup(lp.PROP_OP_RS, g, [v], [y], [y], 600e-9, 30e-3, grad_inputs=[gi])
+    return lp.Plan([s], graph=False, autotune=True), (v, y, gi), g
+
+
+@pytest.mark.parametrize("n", [512, 1024, 2048])
+def test_rs_column_variants_pinned_from_file(lp, tmp_path, n):
+    """Every candidate of the RS column pass at one shape, pinned in turn
+    through a tuning cache record (the persistent pass for these
+    exact-half FP32 lengths): the lines-per-workgroup variants of the
+    built-in schedule (0-2) give the same bits as variant 0 in the forward
+    and the adjoint, the alternative schedule's (3-5) agree to FP32
+    rounding, and variant 0 matches the oracle."""
+    import torch
+    lp.prop_cache_clear()
+    probe = tmp_path / "probe.txt"
+    lp.prop_tune_cache_path(str(probe))
+    p, t, g = _rs_plan(lp, torch, n, 5)
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        p.forward()
+    torch.cuda.synchronize()
+    p.close()
+    recs = [l.split() for l in probe.read_text().splitlines() if l.startswith("libprop-tune")]
+    rs = [r for r in recs if r[4] == "0" and r[5] == str(2 * n)]
+    assert rs, recs
+    outs = {}
+    for var in range(6):
+        f = tmp_path / f"v{var}.txt"
+        f.write_text(" ".join(rs[0][:10] + [str(var)]) + "\n")
+        lp.prop_cache_clear()
+        if lp.prop_tune_cache_path(str(f)) != 1:
+            continue  # not a candidate of this shape
+        p, t, g = _rs_plan(lp, torch, n, 5)
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore")
+            p.forward(); p.adjoint()
+        torch.cuda.synchronize()
+        line = [l for l in lp.prop_autotune_report().splitlines() if f"rs_cols n={2 * n}" in l][0]
+        assert f"variant {var}" in line and "from file" in line, line
+        outs[var] = (t[1].cpu().numpy(), t[2].cpu().numpy())
+        p.close()
+    say(f"RS columns n={2 * n}: variants pinned {sorted(outs)}")
+    assert 0 in outs, sorted(outs)
+    for var, (y, gi) in outs.items():
+        if var < 3:
+            assert np.array_equal(y, outs[0][0]) and np.array_equal(gi, outs[0][1]), var
+        else:
+            assert rel_l2(y, outs[0][0]) < 1e-5 and rel_l2(gi, outs[0][1]) < 1e-5, var
+    if n <= 1024:
+        v0 = t[0].cpu().numpy().astype(np.complex128)
+        assert rel_l2(outs[0][0], oracle.rs_propagate(v0, g, 600e-9, 30e-3)) < 1e-5
+    lp.prop_tune_cache_path(None)
+    lp.prop_cache_clear()
+
+
 def test_tuning_cache_file_is_read_and_corruption_ignored(lp, tmp_path):
     """A record in the tuning cache file fixes a shape's choice (here the
     alternative 8x16x8 schedule of the 1024-point RS column pass) without
