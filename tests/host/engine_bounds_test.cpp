@@ -15,7 +15,14 @@
 //  * the LDS twiddle tables of the FP32 row passes (TwLds) give every
 //    twiddled stage's W^{k r}: the global table entries they copy have the
 //    right exponents (one entry for the first twiddled stage, two whose
-//    exponents add up for the second), and every entry is in range.
+//    exponents add up for the second), and every entry is in range;
+//  * the buffer resources of the persistent RS column pass (the same
+//    arithmetic as k_rs_cols_persist): for every lines-per-workgroup
+//    variant, column count and work item, each lane's prefetch loads, stores
+//    and spectrum gathers (vector offset plus scalar offset) fall inside the
+//    item's resource, whose first 4-column tile and extent lie inside the
+//    workspace and the spectrum table.
+#include <algorithm>
 #include <cstdio>
 #include <vector>
 
@@ -87,6 +94,65 @@ static void launch_fits(const char* what) {
   if (LS < S::line_elems) fail("line stride below the padded line", S::n, (int)sizeof(T), C, LS);
   if ((long)C * LS * (long)sizeof(cx<T>) > kLdsBytes) fail(what, S::n, (int)sizeof(T), C, LS);
   if (C * S::threads > 1024) fail("workgroup above 1024 threads", S::n, (int)sizeof(T), C, S::threads);
+}
+
+// Buffer regions of k_rs_cols_persist<T, S, C> over ncols columns (n_valid =
+// n/2 rows kept, spectrum table of q = n/2 + 1 rows in 4-column tiles).
+template <typename T, class S, int C>
+static void col_buffers(int ncols) {
+  using HI = HalfIn<S>;
+  using HO = HalfOut<S>;
+  const long es = (long)sizeof(cx<T>);
+  const int n = S::n, n_valid = n / 2, q = n / 2 + 1;
+  const long tiles_w = (ncols + kTile - 1) / kTile;  // workspace 4-column tiles
+  for (int tile = 0; tile < ncols / C; ++tile) {
+    const int k0 = tile * C;
+    const int ntiles = ((k0 & 3) + C + 3) / 4;
+    if ((k0 >> 2) + ntiles > tiles_w) fail("column resource past the last tile", n, (int)es, C, tile);
+    const long rw = (long)ntiles * n_valid * kTile * es, rq = (long)ntiles * q * 4 * es;
+    if (rw >= (1L << 31) || rq >= (1L << 31)) fail("column resource above 2 GiB", n, (int)es, C, tile);
+    for (int c = 0; c < C; ++c) {
+      const int ka = (k0 & 3) + c;
+      const long lane = (long)(ka >> 2) * n_valid * kTile + (ka & 3);
+      const long lane_q = (long)(ka >> 2) * q * 4 + (ka & 3);
+      // the lane's column must be the one the flat layout gives
+      const int kx = k0 + c;
+      if (lane + (long)(k0 >> 2) * n_valid * kTile != (long)(kx >> kTileShift) * n_valid * kTile + (kx & (kTile - 1)))
+        fail("column lane offset", n, (int)es, C, kx);
+      for (int j = 0; j < S::threads; ++j) {
+        const long vo = (lane + (long)j * kTile) * es;
+        if (HI::loads(j))
+          for (int r = 0; r < HI::R; ++r) {
+            const long so = (long)(HI::index(j, r) - j) * kTile * es;
+            if (vo > rw || vo + so + es > rw) fail("column prefetch outside its resource", n, (int)es, C, j);
+          }
+        if (HO::stores(j))
+          for (int r = 0; r < HO::R; ++r) {
+            const long so = (long)(HO::index(j, r) - j) * kTile * es;
+            if (vo > rw || vo + so + es > rw) fail("column store outside its resource", n, (int)es, C, j);
+          }
+      }
+      for (int i = 0; i < n; ++i) {
+        const long o = (lane_q + (long)std::min(i, n - i) * 4) * es;
+        if (o + es > rq) fail("spectrum gather outside its resource", n, (int)es, C, i);
+      }
+    }
+  }
+}
+
+template <typename T, class S>
+static void check_col_buffers() {
+  if constexpr (cols_persistent<T, S>() && S::rad[0] % 2 == 0 && S::rad[S::nst - 1] % 2 == 0) {
+    using CF = Cfg<T, S, true>;
+    if constexpr (CF::fits) {
+      constexpr int C0 = CF::C, C1 = variant_lines<S, C0>(1), C2 = variant_lines<S, C0>(2);
+      for (int ncols : {16, 48, S::n, 2 * S::n}) {
+        if (ncols % C0 == 0) col_buffers<T, S, C0>(ncols);
+        if (ncols % C1 == 0) col_buffers<T, S, C1>(ncols);
+        if (ncols % C2 == 0) col_buffers<T, S, C2>(ncols);
+      }
+    }
+  }
 }
 
 template <typename T, class S>
@@ -178,12 +244,14 @@ int main() {
 #define LP_CHECK(N, ...)                                    \
   check_len<float, SchedOf<float, Sched<__VA_ARGS__>>>();   \
   check_len<double, SchedOf<double, Sched<__VA_ARGS__>>>(); \
+  check_col_buffers<float, SchedOf<float, Sched<__VA_ARGS__>>>(); \
   check_twlds<SchedOf<float, Sched<__VA_ARGS__>>>();
   LP_LENGTHS(LP_CHECK)
 #undef LP_CHECK
   // the alternative schedules the autotuner may choose (FP32)
 #define LP_CHECK_ALT(N, ...) \
   check_len<float, Sched<__VA_ARGS__>>(); \
+  check_col_buffers<float, Sched<__VA_ARGS__>>(); \
   check_twlds<Sched<__VA_ARGS__>>();
   LP_ALT_LENGTHS(LP_CHECK_ALT)
 #undef LP_CHECK_ALT
